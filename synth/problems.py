@@ -1,0 +1,122 @@
+"""Boundary conditions, loads and run presets for the synthetic workloads.
+
+Conventions (both sides follow them; neither shares code with the other):
+
+* A grid has ``nx * ny * nz`` unit hexahedral elements; node coordinates are
+  integers ``(i, j, k)`` with ``0 <= i <= nx`` etc.  Axis x is the beam's
+  length, y its width and z points up.
+* A fixed degree of freedom is ``(i, j, k, c)`` with component ``c`` in
+  {0: x, 1: y, 2: z}.  A point load is ``(i, j, k, c, value)``.
+
+The geometries follow the paper's numerical examples: the cantilever clamped
+at one end (Section 4.2.3 and the 2D cantilever of Section 4.1.1 lifted to
+3D) and the simply supported beam whose four bottom corners are fixed with a
+load at the bottom centre (Section 4.2.2).  Load layouts that exist only in
+the paper's figures are replaced by the simple layouts below.
+"""
+
+from __future__ import annotations
+
+import dataclasses
+from typing import List, Tuple
+
+import numpy as np
+
+Fixed = Tuple[int, int, int, int]
+Load = Tuple[int, int, int, int, float]
+
+
+@dataclasses.dataclass
+class Problem:
+    nx: int
+    ny: int
+    nz: int
+    fixed: List[Fixed]
+    loads: List[List[Load]]  # one list of point loads per load case
+    name: str = ""
+
+    @property
+    def n_elem(self) -> int:
+        return self.nx * self.ny * self.nz
+
+    @property
+    def n_node(self) -> int:
+        return (self.nx + 1) * (self.ny + 1) * (self.nz + 1)
+
+    @property
+    def n_case(self) -> int:
+        return len(self.loads)
+
+
+def _trapezoid(n: int) -> np.ndarray:
+    """Tributary lengths of the ``n + 1`` nodes of a unit-spaced segment."""
+    w = np.ones(n + 1)
+    if n == 0:
+        return np.ones(1)
+    w[0] = w[-1] = 0.5
+    return w / n
+
+
+def cantilever(nx: int, ny: int, nz: int) -> Problem:
+    """Clamped x=0 face; unit downward force spread over the bottom edge of
+    the x=nx face with trapezoid (tributary-length) weights summing to 1."""
+    fixed = [(0, j, k, c) for k in range(nz + 1) for j in range(ny + 1) for c in range(3)]
+    w = _trapezoid(ny)
+    loads = [[(nx, j, 0, 2, -float(w[j])) for j in range(ny + 1)]]
+    return Problem(nx, ny, nz, fixed, loads, f"cantilever{nx}x{ny}x{nz}")
+
+
+def bridge(nx: int, ny: int, nz: int) -> Problem:
+    """Simply supported beam: the four bottom-corner nodes fully fixed and a
+    unit downward point load at the bottom-centre node (nx, ny even)."""
+    corners = [(0, 0), (nx, 0), (0, ny), (nx, ny)]
+    fixed = [(i, j, 0, c) for (i, j) in corners for c in range(3)]
+    loads = [[(nx // 2, ny // 2, 0, 2, -1.0)]]
+    return Problem(nx, ny, nz, fixed, loads, f"bridge{nx}x{ny}x{nz}")
+
+
+def patch_test(nx: int, ny: int, nz: int, sigma: float = 1.0) -> Problem:
+    """Symmetry-plane rollers (u_x=0 on x=0, u_y=0 on y=0, u_z=0 on z=0) and
+    a uniform traction ``sigma`` in +x on the x=nx face, lumped to the face
+    nodes by tributary area (the consistent load of a bilinear face)."""
+    fixed = []
+    for k in range(nz + 1):
+        for j in range(ny + 1):
+            fixed.append((0, j, k, 0))
+    for k in range(nz + 1):
+        for i in range(nx + 1):
+            fixed.append((i, 0, k, 1))
+    for j in range(ny + 1):
+        for i in range(nx + 1):
+            fixed.append((i, j, 0, 2))
+    wy = _trapezoid(ny) * ny
+    wz = _trapezoid(nz) * nz
+    loads = [[(nx, j, k, 0, float(sigma * wy[j] * wz[k]))
+              for k in range(nz + 1) for j in range(ny + 1)]]
+    return Problem(nx, ny, nz, fixed, loads, f"patch{nx}x{ny}x{nz}")
+
+
+def point_loads_on_face(nx: int, ny: int, nz: int, n_case: int, seed: int) -> Problem:
+    """Clamped x=0 face; ``n_case`` load cases, each a unit downward point
+    load at a seeded node of the x=nx face."""
+    rng = np.random.default_rng(seed)
+    fixed = [(0, j, k, c) for k in range(nz + 1) for j in range(ny + 1) for c in range(3)]
+    loads = []
+    for _ in range(n_case):
+        j = int(rng.integers(0, ny + 1))
+        k = int(rng.integers(0, nz + 1))
+        loads.append([(nx, j, k, 2, -1.0)])
+    return Problem(nx, ny, nz, fixed, loads, f"pointloads{nx}x{ny}x{nz}")
+
+
+# Run presets of the synthetic workloads.  Material and method parameters are
+# the paper's (E0=1, Emin=1e-9, nu=0.3, p=3; Section 4); grid sizes, radii,
+# tolerances and level counts are the workload definitions.
+PRESETS = {
+    "cantilever24": dict(nx=24, ny=12, nz=12, rmin=1.5, levels=3, seed=1,
+                         density="uniform", lo=0.3, hi=1.0),
+    "cantilever96": dict(nx=96, ny=48, nz=48, rmin=2.0, levels=4, volfrac=0.3,
+                         cycles=50, Nm=6, Ns=2, N_on=20, ca_tol=1e-3),
+    "cantilever256": dict(nx=256, ny=128, nz=128, levels=6, seed=3,
+                          density="smoothed", sigma=8.0, lo=1e-3, hi=1.0),
+}
