@@ -1,0 +1,243 @@
+/*
+ * aarmr.h -- C ABI of the MI355X (gfx950) library for the analysis step of
+ * adaptive auxiliary reduced-model reanalysis (AARMR) topology optimisation
+ * (Yin, Wang, Li, Guo, arXiv 2205.00385).
+ *
+ * The analysis step solves the SIMP equilibrium K(rho~) u = f on a 3D grid
+ * of unit hexahedral (hex8) voxels (eqs. 1, 3, 7), by multigrid-preconditioned
+ * CG (Algorithm 2) or by the combined-approximation reduced model built on a
+ * projection auxiliary model (eqs. 15-29, Algorithm 1), and returns the
+ * compliance and its sensitivity (eqs. 3, 6, 33, 34).  Every computation runs
+ * in HIP kernels on the GPU; the host only orchestrates.
+ *
+ * Conventions shared by every entry point:
+ *   - Grid: nx * ny * nz elements, (nx+1)(ny+1)(nz+1) nodes.  Element
+ *     (i,j,k) has index e = i + nx*(j + ny*k); node (i,j,k) has index
+ *     n = i + (nx+1)*(j + (ny+1)*k) (x fastest).
+ *   - DOF vectors are structure-of-arrays: v[c * n_node + n], c in {0:x,1:y,2:z};
+ *     a DOF id is c * n_node + n.  Several load cases are stored back to back
+ *     (case l starts at l * 3 * n_node).
+ *   - All array arguments marked "device" are pointers to GPU memory of the
+ *     device current for the calling thread; "host" pointers are CPU memory.
+ *     The caller owns every buffer it passes; the library keeps no pointer to
+ *     caller memory after a call returns, except the workspace bound with
+ *     aarmr_bind_workspace, which must stay valid until aarmr_mesh_destroy.
+ *   - `stream` is a hipStream_t (NULL = the null stream).  Calls returning
+ *     host results synchronise that stream before returning; the others are
+ *     stream-ordered and asynchronous.
+ *   - Every call returns AARMR_OK (0) or an error code; aarmr_last_error()
+ *     then gives a thread-local message.  A mesh may be used by one thread
+ *     at a time; distinct meshes are independent.  Calls that overlap on one
+ *     mesh (two streams) race on its workspace.
+ *   - Operator with boundary conditions: with Df the 0/1 diagonal of free
+ *     DOFs, every solve works with A = Df K Df + (I - Df), i.e. K on free DOFs
+ *     and identity rows on fixed DOFs; loads on fixed DOFs are ignored and the
+ *     solution is zero there.
+ */
+#ifndef AARMR_H
+#define AARMR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define AARMR_OK               0
+#define AARMR_E_INVALID        1  /* bad argument: null pointer, size, range */
+#define AARMR_E_HIP            2  /* a HIP runtime call or kernel launch failed */
+#define AARMR_E_NOT_CONVERGED  3  /* CG hit cg_maxit; outputs are written anyway */
+#define AARMR_E_SINGULAR       4  /* non-positive pivot or p^T A p <= 0 */
+#define AARMR_E_NO_WORKSPACE   5  /* no (or too small a) workspace bound */
+#define AARMR_E_STATE          6  /* CA called before its PARM is complete */
+
+#define AARMR_MAX_RHS     8
+#define AARMR_MAX_LEVELS  8
+#define AARMR_MAX_BASIS   10
+
+/* ---- precision of the inner solve ------------------------------------ */
+#define AARMR_FP64         0  /* everything in FP64 */
+#define AARMR_FP32_REFINE  1  /* FP32 operator sweeps and V-cycle inside FP64
+                                 iterative refinement (FP64 residuals, dots,
+                                 reduced systems and coarsest solve) */
+
+/* ---- flags for aarmr_solve / aarmr_ca_update -------------------------- */
+#define AARMR_FILTER_INPUT  1  /* `rho` is the design density: it is filtered
+                                  first (eq. 31) and dc is returned w.r.t. the
+                                  design density through eq. (33).  Otherwise
+                                  `rho` is the physical density rho~ and dc is
+                                  dC/drho~. */
+#define AARMR_RECORD_PARM   2  /* after solving, push u/||u|| of each load case
+                                  into that case's PARM (eqs. 27-28), dropping
+                                  the oldest vector once Ns are held */
+#define AARMR_WARM_START    4  /* use the incoming u as the CG initial guess
+                                  (otherwise CG starts from zero) */
+
+/* ---- parameters -------------------------------------------------------- */
+typedef struct aarmr_params {
+  int32_t nx, ny, nz;        /* elements per axis; each divisible by
+                                2^(mg_levels-1) */
+  double E0, Emin, nu, penal;/* SIMP, eq. (1): E = Emin + (E0-Emin) rho~^p */
+  double rmin;               /* filter radius in element lengths, eq. (32);
+                                <= 0 disables aarmr_filter */
+  int32_t mg_levels;         /* grid levels including the finest (>= 2) */
+  int32_t nu_pre, nu_post;   /* damped-Jacobi sweeps (Algorithm 2) */
+  double omega;              /* Jacobi damping */
+  double cg_rtol;            /* stop when ||f - A u|| <= cg_rtol ||f|| */
+  int32_t cg_maxit;
+  int32_t precision;         /* AARMR_FP64 or AARMR_FP32_REFINE */
+  int32_t Ns;                /* PARM size s (eq. 27), <= AARMR_MAX_BASIS */
+  int32_t Nm;                /* CARM size m (eq. 20), <= AARMR_MAX_BASIS */
+  double ca_tol;             /* eps_tol of eq. (29): accept iff eps < ca_tol */
+  double gs_tau;             /* Gram-Schmidt drops a column whose remaining
+                                norm is below gs_tau times its initial norm */
+  int32_t n_rhs_max;         /* load cases per call, <= AARMR_MAX_RHS */
+} aarmr_params;
+
+/* Statistics of one aarmr_solve call (host struct written by the call). */
+typedef struct aarmr_stats {
+  int32_t iterations[AARMR_MAX_RHS];   /* CG iterations per load case */
+  double rel_residual[AARMR_MAX_RHS];  /* final ||f - A u|| / ||f|| */
+  int64_t fine_sweeps;                 /* fine-grid operator applications */
+  double setup_ms, solve_ms;           /* host wall time of the phases */
+} aarmr_stats;
+
+/* Statistics of one aarmr_ca_update call. */
+typedef struct aarmr_ca_stats {
+  double eps[AARMR_MAX_RHS];           /* eq. (29) of the reduced solution */
+  int32_t accepted[AARMR_MAX_RHS];     /* 1 if eps < ca_tol */
+  int32_t rank[AARMR_MAX_RHS];         /* columns kept by Gram-Schmidt */
+  int32_t mgcg_iterations[AARMR_MAX_RHS]; /* fallback CG iterations (0 if accepted) */
+  double rel_residual[AARMR_MAX_RHS];  /* final residual of the returned u */
+  int64_t fine_sweeps;
+} aarmr_ca_stats;
+
+typedef struct aarmr_mesh aarmr_mesh;
+
+/* Fill *p with the paper's defaults (E0=1, Emin=1e-9, nu=0.3, p=3, Section
+ * 4; rmin 2.5, Section 3.2; Ns=Nm=2, Section 4.1.1; 3 grid levels, Section
+ * 4.1.2) and solver defaults (omega 0.6, one pre- and post-sweep, rtol 1e-8,
+ * 2000 iterations, eps_tol 1e-3, tau 1e-10, one load case). */
+void aarmr_default_params(aarmr_params* p);
+
+/* Create a mesh object (host memory only; no device allocation).  Computes
+ * the hex8 element stiffness of the unit cube for nu by 2x2x2 Gauss
+ * quadrature and the filter stencil.  *out receives the handle.
+ * Errors: AARMR_E_INVALID for non-positive sizes, sizes not divisible by
+ * 2^(mg_levels-1), mg_levels outside [2, AARMR_MAX_LEVELS], Ns or Nm outside
+ * [1, AARMR_MAX_BASIS], n_rhs_max outside [1, AARMR_MAX_RHS], nu outside
+ * (-1, 0.5), or a coarsest grid above 6000 DOFs. */
+int aarmr_mesh_create(const aarmr_params* p, aarmr_mesh** out);
+
+/* Release the mesh (host memory and its pinned staging buffer).  The bound
+ * workspace belongs to the caller and is not freed. */
+void aarmr_mesh_destroy(aarmr_mesh* m);
+
+/* Exact number of device bytes the mesh needs: MG hierarchy, CG and
+ * reduced-model vectors, PARM vectors of n_rhs_max load cases, reduction
+ * scratch.  Negative on error. */
+int64_t aarmr_workspace_bytes(const aarmr_mesh* m);
+
+/* Bind caller-allocated device memory (at least aarmr_workspace_bytes,
+ * 256-byte aligned) as the mesh workspace and initialise it on `stream`
+ * (element stiffness, filter row sums); on the first bind also allocates a
+ * 32 KiB pinned host staging buffer for scalar read-backs.  Clears the PARM
+ * and the reference design.  Synchronises `stream`.  Errors:
+ * AARMR_E_NO_WORKSPACE if too small, AARMR_E_INVALID if misaligned,
+ * AARMR_E_HIP. */
+int aarmr_bind_workspace(aarmr_mesh* m, void* dev_ptr, int64_t bytes, void* stream);
+
+/* The analysis step by MGCG (Algorithm 2 as preconditioner of CG).
+ *   rho        device [n_elem]     physical density rho~ in [0,1] (design
+ *                                  density with AARMR_FILTER_INPUT)
+ *   f          device [n_rhs][3][n_node] loads (not modified)
+ *   n_rhs      1..n_rhs_max
+ *   fixed_dofs device [n_fixed]    DOF ids (c*n_node + n) held at zero
+ *   u          device [n_rhs][3][n_node] in/out: initial guess with
+ *                                  AARMR_WARM_START, solution on return
+ *   compliance host [n_rhs]        C_l = f_l^T u_l (eq. 3) or NULL
+ *   dc         device [n_elem]     sum over load cases of dC_l/drho~ (eq. 6),
+ *                                  or dC/drho (eq. 33) with
+ *                                  AARMR_FILTER_INPUT; or NULL
+ *   st         host                statistics, or NULL
+ * Also records the physical density as the reference design K0 of the next
+ * aarmr_ca_update.  Synchronises `stream`.
+ * Errors: AARMR_E_INVALID (null pointers, n_rhs, a fixed DOF id out of
+ * range, rho~ outside [0,1]), AARMR_E_NOT_CONVERGED (outputs written),
+ * AARMR_E_SINGULAR, AARMR_E_NO_WORKSPACE, AARMR_E_HIP. */
+int aarmr_solve(aarmr_mesh* m, const double* rho, const double* f, int32_t n_rhs,
+                const int64_t* fixed_dofs, int64_t n_fixed, double* u,
+                double* compliance, double* dc, int32_t flags, aarmr_stats* st,
+                void* stream);
+
+/* One reanalysis cycle of Algorithm 1 (lines 4-10) for every load case:
+ *   K0 = K(reference design of the previous aarmr_solve / aarmr_ca_update),
+ *   K_Phi = Phi^T K0 Phi (eq. 15), r_1 = u (the last solution, eq. 26),
+ *   r_i = -Phi K_Phi^-1 Phi^T (K - K0) r_(i-1) (eq. 20),
+ *   Gram-Schmidt orthonormalisation (named as an alternative to eq. 21),
+ *   (R~^T K R~) y = R~^T f, u~ = R~ y (eqs. 22-25) and
+ *   eps = ||K R~ y - f|| / ||f|| (eq. 29).
+ * If eps < ca_tol, u~ is returned; otherwise MGCG runs warm-started from u~
+ * and its normalised solution enters the PARM (Algorithm 1 lines 9-10).
+ * Arguments as for aarmr_solve; `u` must hold each case's last solution on
+ * entry.  Compliance and dc use the returned u (eq. 34 when accepted).
+ * Records the new reference design.  Synchronises `stream`.
+ * Errors: as aarmr_solve, plus AARMR_E_STATE if a case holds fewer than Ns
+ * PARM vectors or no reference design exists. */
+int aarmr_ca_update(aarmr_mesh* m, const double* rho, const double* f, int32_t n_rhs,
+                    const int64_t* fixed_dofs, int64_t n_fixed, double* u,
+                    double* compliance, double* dc, int32_t flags,
+                    aarmr_ca_stats* st, void* stream);
+
+/* Density filter (eqs. 31-32) with cone weights max(0, rmin - |x_i - x_j|)
+ * over element centres, truncated at the domain boundary and normalised by
+ * the in-domain weight sums Hs.  mode 0: out = H in / Hs (eq. 31);
+ * mode 1: out = H^T (in / Hs), the chain rule of eq. (33).
+ * in, out: device [n_elem], distinct.  Stream-ordered, asynchronous.
+ * Errors: AARMR_E_INVALID (mode, null, in == out, rmin <= 0). */
+int aarmr_filter(aarmr_mesh* m, int32_t mode, const double* in, double* out, void* stream);
+
+/* ---- building blocks (the same kernels the solvers use) --------------- */
+
+/* Set the design state used by aarmr_apply_operator and aarmr_vcycle:
+ * SIMP moduli from rho~ (device [n_elem]), the fixed-DOF mask, and the
+ * multigrid hierarchy (Jacobi diagonals, Galerkin coarse operators
+ * P^T A P per level, inverse of the coarsest operator).  Stream-ordered;
+ * rho~ is range-checked on the next synchronising call. */
+int aarmr_setup(aarmr_mesh* m, const double* rho_phys, const int64_t* fixed_dofs,
+                int64_t n_fixed, void* stream);
+
+/* y = A v on grid level `level` (0 = finest, matrix-free element-by-element
+ * product; coarser levels use the Galerkin operators of aarmr_setup).
+ * v, y: device [3][n_node(level)], distinct.  Stream-ordered. */
+int aarmr_apply_operator(aarmr_mesh* m, int32_t level, const double* v, double* y,
+                         void* stream);
+
+/* z = M^-1 r: one V-cycle of Algorithm 2 from a zero initial guess on the
+ * finest level.  r, z: device [3][n_node], distinct.  Stream-ordered. */
+int aarmr_vcycle(aarmr_mesh* m, const double* r, double* z, void* stream);
+
+/* Element energies e_e = u_e^T KE u_e of the unit-modulus element stiffness
+ * for one displacement u (device [3][n_node]) into energy (device [n_elem]).
+ * Fixed DOFs of u are treated as zero. */
+int aarmr_element_energy(aarmr_mesh* m, const double* u, double* energy, void* stream);
+
+/* Optimality-criteria update of the design density (the textbook OC rule
+ * for eq. (3)): x_new = clamp(x * (max(0,-dc)/(lambda dv))^0.5, x-move,
+ * x+move, 0, 1) with lambda found by bisection in [0, 1e9] until
+ * (l2-l1)/(l1+l2) <= 1e-3, the volume sum(rho~) of the filtered x_new
+ * compared with volfrac * n_elem.  x, dc, dv: device [n_elem]; x_new,
+ * rho_phys_new: device [n_elem].  Stream-ordered. */
+int aarmr_oc_update(aarmr_mesh* m, const double* x, const double* dc, const double* dv,
+                    double volfrac, double move, double* x_new, double* rho_phys_new,
+                    void* stream);
+
+/* Thread-local description of the last error on this thread ("" if none). */
+const char* aarmr_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AARMR_H */

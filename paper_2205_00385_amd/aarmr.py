@@ -1,0 +1,256 @@
+"""Thin ctypes binding of the AARMR HIP library (``libaarmr.so``).
+
+Argument marshalling only: every call forwards device pointers of torch
+tensors and the current HIP stream to the C ABI declared in
+``include/aarmr.h``.  There is no CPU fallback: importing this module without
+the built library raises, and every call that fails raises
+:class:`AarmrError` with the library's message.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libaarmr.so")
+
+OK, E_INVALID, E_HIP, E_NOT_CONVERGED, E_SINGULAR, E_NO_WORKSPACE, E_STATE = range(7)
+MAX_RHS, MAX_LEVELS, MAX_BASIS = 8, 8, 10
+FP64, FP32_REFINE = 0, 1
+FILTER_INPUT, RECORD_PARM, WARM_START = 1, 2, 4
+
+
+class AarmrError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"aarmr error {code}: {msg}")
+        self.code = code
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("E0", ctypes.c_double), ("Emin", ctypes.c_double), ("nu", ctypes.c_double),
+        ("penal", ctypes.c_double), ("rmin", ctypes.c_double),
+        ("mg_levels", ctypes.c_int32), ("nu_pre", ctypes.c_int32), ("nu_post", ctypes.c_int32),
+        ("omega", ctypes.c_double), ("cg_rtol", ctypes.c_double), ("cg_maxit", ctypes.c_int32),
+        ("precision", ctypes.c_int32), ("Ns", ctypes.c_int32), ("Nm", ctypes.c_int32),
+        ("ca_tol", ctypes.c_double), ("gs_tau", ctypes.c_double), ("n_rhs_max", ctypes.c_int32),
+    ]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("iterations", ctypes.c_int32 * MAX_RHS),
+        ("rel_residual", ctypes.c_double * MAX_RHS),
+        ("fine_sweeps", ctypes.c_int64),
+        ("setup_ms", ctypes.c_double), ("solve_ms", ctypes.c_double),
+    ]
+
+
+class CAStats(ctypes.Structure):
+    _fields_ = [
+        ("eps", ctypes.c_double * MAX_RHS),
+        ("accepted", ctypes.c_int32 * MAX_RHS),
+        ("rank", ctypes.c_int32 * MAX_RHS),
+        ("mgcg_iterations", ctypes.c_int32 * MAX_RHS),
+        ("rel_residual", ctypes.c_double * MAX_RHS),
+        ("fine_sweeps", ctypes.c_int64),
+    ]
+
+
+EXPORTS = [
+    "aarmr_default_params", "aarmr_mesh_create", "aarmr_mesh_destroy", "aarmr_workspace_bytes",
+    "aarmr_bind_workspace", "aarmr_solve", "aarmr_ca_update", "aarmr_filter", "aarmr_setup",
+    "aarmr_apply_operator", "aarmr_vcycle", "aarmr_element_energy", "aarmr_oc_update",
+    "aarmr_last_error",
+]
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    if not os.path.exists(path):
+        raise ImportError(
+            f"{path} is missing: build it with `python -m paper_2205_00385_amd.build` "
+            "(there is no CPU fallback)")
+    lib = ctypes.CDLL(path)
+    P, vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    lib.aarmr_default_params.argtypes = [ctypes.POINTER(Params)]
+    lib.aarmr_default_params.restype = None
+    lib.aarmr_mesh_create.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(P)]
+    lib.aarmr_mesh_destroy.argtypes = [P]
+    lib.aarmr_mesh_destroy.restype = None
+    lib.aarmr_workspace_bytes.argtypes = [P]
+    lib.aarmr_workspace_bytes.restype = i64
+    lib.aarmr_bind_workspace.argtypes = [P, vp, i64, vp]
+    lib.aarmr_solve.argtypes = [P, vp, vp, i32, vp, i64, vp, vp, vp, i32, ctypes.POINTER(Stats), vp]
+    lib.aarmr_ca_update.argtypes = [P, vp, vp, i32, vp, i64, vp, vp, vp, i32,
+                                    ctypes.POINTER(CAStats), vp]
+    lib.aarmr_filter.argtypes = [P, i32, vp, vp, vp]
+    lib.aarmr_setup.argtypes = [P, vp, vp, i64, vp]
+    lib.aarmr_apply_operator.argtypes = [P, i32, vp, vp, vp]
+    lib.aarmr_vcycle.argtypes = [P, vp, vp, vp]
+    lib.aarmr_element_energy.argtypes = [P, vp, vp, vp]
+    lib.aarmr_oc_update.argtypes = [P, vp, vp, vp, dbl, dbl, vp, vp, vp]
+    lib.aarmr_last_error.argtypes = []
+    lib.aarmr_last_error.restype = ctypes.c_char_p
+    for name in EXPORTS:
+        if name not in ("aarmr_default_params", "aarmr_mesh_destroy", "aarmr_workspace_bytes",
+                        "aarmr_last_error"):
+            getattr(lib, name).restype = i32
+    return lib
+
+
+_lib: Optional[ctypes.CDLL] = None
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is None:
+        _lib = load_library()
+    return _lib
+
+
+def _check(code: int, allow=()) -> int:
+    if code != OK and code not in allow:
+        raise AarmrError(code, lib().aarmr_last_error().decode())
+    return code
+
+
+def default_params(**kw) -> Params:
+    p = Params()
+    lib().aarmr_default_params(ctypes.byref(p))
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise KeyError(k)
+        setattr(p, k, v)
+    return p
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("tensor must live on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _f64(t: torch.Tensor, n: int, name: str) -> torch.Tensor:
+    if t.dtype != torch.float64 or t.numel() != n:
+        raise ValueError(f"{name}: expected float64 with {n} entries, got {t.dtype} {t.numel()}")
+    return t
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Mesh:
+    """A grid with its device workspace (allocated through torch)."""
+
+    def __init__(self, params: Params, device: str = "cuda"):
+        self.params = params
+        h = ctypes.c_void_p()
+        _check(lib().aarmr_mesh_create(ctypes.byref(params), ctypes.byref(h)))
+        self._h = h
+        self.nx, self.ny, self.nz = params.nx, params.ny, params.nz
+        self.n_elem = params.nx * params.ny * params.nz
+        self.n_node = (params.nx + 1) * (params.ny + 1) * (params.nz + 1)
+        nbytes = lib().aarmr_workspace_bytes(h)
+        if nbytes < 0:
+            raise AarmrError(E_INVALID, "workspace size query failed")
+        self.workspace = torch.empty(int(nbytes) + 256, dtype=torch.uint8, device=device)
+        off = (-self.workspace.data_ptr()) % 256
+        self._ws_ptr = self.workspace.data_ptr() + off
+        self.workspace_bytes = int(nbytes)
+        _check(lib().aarmr_bind_workspace(h, ctypes.c_void_p(self._ws_ptr), nbytes, _stream()))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().aarmr_mesh_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- main entry points ---------------------------------------------------
+    def solve(self, rho, f, fixed, u, compliance=True, dc=None, flags=0):
+        n3 = 3 * self.n_node
+        n_rhs = f.numel() // n3
+        _f64(rho, self.n_elem, "rho")
+        _f64(f, n_rhs * n3, "f")
+        _f64(u, n_rhs * n3, "u")
+        if dc is not None:
+            _f64(dc, self.n_elem, "dc")
+        C = (ctypes.c_double * MAX_RHS)()
+        st = Stats()
+        code = lib().aarmr_solve(self._h, _ptr(rho), _ptr(f), n_rhs, _ptr(fixed), fixed.numel(),
+                                 _ptr(u), C if compliance else None, _ptr(dc), flags,
+                                 ctypes.byref(st), _stream())
+        _check(code, allow=(E_NOT_CONVERGED,))
+        return [C[i] for i in range(n_rhs)], st, code
+
+    def ca_update(self, rho, f, fixed, u, dc=None, flags=0):
+        n3 = 3 * self.n_node
+        n_rhs = f.numel() // n3
+        _f64(rho, self.n_elem, "rho")
+        _f64(f, n_rhs * n3, "f")
+        _f64(u, n_rhs * n3, "u")
+        C = (ctypes.c_double * MAX_RHS)()
+        st = CAStats()
+        code = lib().aarmr_ca_update(self._h, _ptr(rho), _ptr(f), n_rhs, _ptr(fixed),
+                                     fixed.numel(), _ptr(u), C, _ptr(dc), flags,
+                                     ctypes.byref(st), _stream())
+        _check(code, allow=(E_NOT_CONVERGED,))
+        return [C[i] for i in range(n_rhs)], st, code
+
+    def filter(self, x, out, mode=0):
+        _check(lib().aarmr_filter(self._h, mode, _ptr(x), _ptr(out), _stream()))
+        return out
+
+    # -- building blocks -----------------------------------------------------
+    def setup(self, rho_phys, fixed):
+        _check(lib().aarmr_setup(self._h, _ptr(rho_phys), _ptr(fixed), fixed.numel(), _stream()))
+
+    def apply(self, v, y, level=0):
+        _check(lib().aarmr_apply_operator(self._h, level, _ptr(v), _ptr(y), _stream()))
+        return y
+
+    def vcycle(self, r, z):
+        _check(lib().aarmr_vcycle(self._h, _ptr(r), _ptr(z), _stream()))
+        return z
+
+    def element_energy(self, u, out):
+        _check(lib().aarmr_element_energy(self._h, _ptr(u), _ptr(out), _stream()))
+        return out
+
+    def oc_update(self, x, dc, dv, volfrac, move, x_new, rho_new):
+        _check(lib().aarmr_oc_update(self._h, _ptr(x), _ptr(dc), _ptr(dv), float(volfrac),
+                                     float(move), _ptr(x_new), _ptr(rho_new), _stream()))
+
+
+def fixed_dofs_soa(prob, n_node: int) -> list:
+    """Flatten a problem's fixed (i, j, k, c) list into SoA DOF ids c*n_node + n."""
+    nx, ny = prob.nx, prob.ny
+    ids = sorted({c * n_node + i + (nx + 1) * (j + (ny + 1) * k) for (i, j, k, c) in prob.fixed})
+    return ids
+
+
+def loads_soa(prob, n_node: int, cases: Optional[Sequence[int]] = None) -> list:
+    """Flatten a problem's point loads into SoA vectors [case][3 * n_node]."""
+    nx, ny = prob.nx, prob.ny
+    cases = range(prob.n_case) if cases is None else cases
+    out = []
+    for l in cases:
+        v = [0.0] * (3 * n_node)
+        for (i, j, k, c, val) in prob.loads[l]:
+            v[c * n_node + i + (nx + 1) * (j + (ny + 1) * k)] += val
+        out.append(v)
+    return out

@@ -1,0 +1,878 @@
+// C ABI of the AARMR analysis step: host orchestration of the HIP kernels.
+//
+// The host validates arguments, binds workspace views, issues kernels on the
+// caller's stream and reads back the few scalars that steer control flow
+// (CG convergence, Gram-Schmidt rank decisions, the eq. (29) accept/reject
+// branch).  Every arithmetic step of the method runs on the GPU.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+
+using namespace aarmr;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIP_TRY(x)                                                               \
+  do {                                                                           \
+    hipError_t e_ = (x);                                                         \
+    if (e_ != hipSuccess)                                                        \
+      return fail(AARMR_E_HIP, std::string(#x) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+#define KCHECK() HIP_TRY(hipGetLastError())
+#define TRY(x)                 \
+  do {                         \
+    int rc_ = (x);             \
+    if (rc_ != AARMR_OK) return rc_; \
+  } while (0)
+
+struct LevelBuf {
+  double* Ke = nullptr;    // levels >= 1: [ne][24][24] Galerkin element matrices
+  double* dinv = nullptr;  // [3][nn] inverse Jacobi diagonal
+  double* b = nullptr;     // levels >= 1: right-hand side
+  double* x = nullptr;     // levels >= 1: correction
+  double* t = nullptr;     // [3][nn] operator output
+};
+
+// Scalar history in device memory (indices into m->scal).
+constexpr int SC_RZ = 0;
+constexpr int SC_PQ = SC_RZ + kMaxIt + 2;
+constexpr int SC_RR = SC_PQ + kMaxIt + 2;
+constexpr int SC_MISC = SC_RR + kMaxIt + 2;  // 512 misc scalars
+constexpr int SC_TOTAL = SC_MISC + 512;
+// misc slots
+constexpr int M_FF = 0, M_RR0 = 1, M_NRM = 2, M_C = 3, M_EPS = 4, M_VOL = 5;
+constexpr int M_OC = 8;        // 4 slots: l1, l2, lmid, done
+constexpr int M_KPHI = 16;     // Ns*Ns
+constexpr int M_G = 120;       // Ns  (Phi^T dK r)
+constexpr int M_C2 = 132;      // Ns  (K_Phi^-1 g)
+constexpr int M_H = 144;       // up to 10 GS coefficients
+constexpr int M_FR = 156;      // reduced rhs
+constexpr int M_Y = 168;       // reduced solution
+constexpr int M_KR = 180;      // reduced matrix (up to 10x10, slots 180..279)
+
+constexpr int64_t kAlign = 256;
+
+inline int64_t align_up(int64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+}  // namespace
+
+struct aarmr_mesh {
+  aarmr_params p;
+  Grid lg[AARMR_MAX_LEVELS];  // lg[0] = fine grid
+  int nlev = 0;
+  int nc = 0;                 // coarsest dense order
+  double KE[576];
+  // workspace views
+  char* ws = nullptr;
+  int64_t ws_bytes = 0;
+  double* KEd = nullptr;
+  double* E = nullptr;
+  double* E_prev = nullptr;
+  double* dE = nullptr;
+  double* rho_f = nullptr;
+  double* Hs = nullptr;
+  double* ework = nullptr;
+  double* dc_tmp = nullptr;
+  double* ones_dv = nullptr;
+  uint8_t* mask = nullptr;
+  double *r = nullptr, *z = nullptr, *pv = nullptr, *q = nullptr, *t0 = nullptr, *fm = nullptr;
+  LevelBuf lv[AARMR_MAX_LEVELS];
+  double* Ainv = nullptr;
+  double *gjP = nullptr, *gjT = nullptr, *gjR = nullptr;
+  double* Phi = nullptr;   // [n_rhs_max][Ns][3nn]
+  double* R = nullptr;     // [Nm][3nn]
+  double* KR = nullptr;    // [Nm][3nn]
+  double* scal = nullptr;
+  double* partial = nullptr;
+  unsigned* ticket = nullptr;
+  unsigned* flags = nullptr;
+  // host state
+  int phi_count[AARMR_MAX_RHS] = {};
+  int phi_head[AARMR_MAX_RHS] = {};
+  bool have_prev = false;
+  bool mg_ready = false;
+  double* hpin = nullptr;  // pinned host staging
+  int64_t sweeps = 0;
+};
+
+namespace {
+
+// ---- element stiffness of the unit cube (2x2x2 Gauss) ---------------------
+void hex8_stiffness(double nu, double* KE) {
+  const double lam = nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
+  const double mu = 1.0 / (2.0 * (1.0 + nu));
+  double D[6][6] = {};
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) D[a][b] = lam;
+  for (int a = 0; a < 3; ++a) D[a][a] = lam + 2.0 * mu;
+  for (int a = 3; a < 6; ++a) D[a][a] = mu;
+  const double g[2] = {0.5 - 0.5 / std::sqrt(3.0), 0.5 + 0.5 / std::sqrt(3.0)};
+  std::memset(KE, 0, sizeof(double) * 576);
+  for (double x : g)
+    for (double y : g)
+      for (double z : g) {
+        double B[6][24] = {};
+        for (int a = 0; a < 8; ++a) {
+          const int i = a & 1, j = (a >> 1) & 1, k = a >> 2;
+          const double fx = i ? x : 1 - x, fy = j ? y : 1 - y, fz = k ? z : 1 - z;
+          const double sx = i ? 1 : -1, sy = j ? 1 : -1, sz = k ? 1 : -1;
+          const double dx = sx * fy * fz, dy = fx * sy * fz, dz = fx * fy * sz;
+          B[0][3 * a] = dx;
+          B[1][3 * a + 1] = dy;
+          B[2][3 * a + 2] = dz;
+          B[3][3 * a] = dy;
+          B[3][3 * a + 1] = dx;
+          B[4][3 * a + 1] = dz;
+          B[4][3 * a + 2] = dy;
+          B[5][3 * a] = dz;
+          B[5][3 * a + 2] = dx;
+        }
+        for (int r = 0; r < 24; ++r)
+          for (int c = 0; c < 24; ++c) {
+            double s = 0.0;
+            for (int u = 0; u < 6; ++u)
+              for (int v = 0; v < 6; ++v) s += B[u][r] * D[u][v] * B[v][c];
+            KE[r * 24 + c] += 0.125 * s;
+          }
+      }
+}
+
+// Assign workspace views; with base == nullptr only computes the size.
+int64_t layout(aarmr_mesh* m, char* base) {
+  int64_t off = 0;
+  auto take = [&](int64_t bytes) -> char* {
+    char* p = base ? base + off : nullptr;
+    off += align_up(bytes);
+    return p;
+  };
+  const Grid& g = m->lg[0];
+  const int64_t n3 = 3 * g.nn;
+  const int64_t d8 = sizeof(double);
+  m->KEd = (double*)take(576 * d8);
+  m->E = (double*)take(g.ne * d8);
+  m->E_prev = (double*)take(g.ne * d8);
+  m->dE = (double*)take(g.ne * d8);
+  m->rho_f = (double*)take(g.ne * d8);
+  m->Hs = (double*)take(g.ne * d8);
+  m->ework = (double*)take(g.ne * d8);
+  m->dc_tmp = (double*)take(g.ne * d8);
+  m->ones_dv = (double*)take(g.ne * d8);
+  m->mask = (uint8_t*)take((g.nn + 3) / 4 * 4);
+  m->r = (double*)take(n3 * d8);
+  m->z = (double*)take(n3 * d8);
+  m->pv = (double*)take(n3 * d8);
+  m->q = (double*)take(n3 * d8);
+  m->t0 = (double*)take(n3 * d8);
+  m->fm = (double*)take(n3 * d8);
+  m->lv[0] = LevelBuf();
+  m->lv[0].dinv = (double*)take(n3 * d8);
+  m->lv[0].t = m->t0;
+  for (int l = 1; l < m->nlev; ++l) {
+    const Grid& G = m->lg[l];
+    LevelBuf& L = m->lv[l];
+    L.Ke = (double*)take(G.ne * 576 * d8);
+    L.dinv = (double*)take(3 * G.nn * d8);
+    L.b = (double*)take(3 * G.nn * d8);
+    L.x = (double*)take(3 * G.nn * d8);
+    L.t = (double*)take(3 * G.nn * d8);
+  }
+  m->Ainv = (double*)take((int64_t)m->nc * m->nc * d8);
+  m->gjP = (double*)take(kGJBlock * kGJBlock * d8);
+  m->gjT = (double*)take((int64_t)m->nc * kGJBlock * d8);
+  m->gjR = (double*)take((int64_t)m->nc * kGJBlock * d8);
+  m->Phi = (double*)take((int64_t)m->p.n_rhs_max * m->p.Ns * n3 * d8);
+  m->R = (double*)take((int64_t)m->p.Nm * n3 * d8);
+  m->KR = (double*)take((int64_t)m->p.Nm * n3 * d8);
+  m->scal = (double*)take(SC_TOTAL * d8);
+  m->partial = (double*)take((int64_t)kRedSlots * kRedBlocks * d8);
+  m->ticket = (unsigned*)take(64);
+  m->flags = (unsigned*)take(64);
+  return off;
+}
+
+hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+int need_ws(const aarmr_mesh* m) {
+  if (!m) return fail(AARMR_E_INVALID, "null mesh");
+  if (!m->ws) return fail(AARMR_E_NO_WORKSPACE, "no workspace bound (aarmr_bind_workspace)");
+  return AARMR_OK;
+}
+
+RedScratch red(aarmr_mesh* m) { return RedScratch{m->partial, m->ticket}; }
+
+// Launch one multi-dot with up to kRedSlots products.
+int dots(aarmr_mesh* m, int k, const double* const* a, const double* const* b, double* const* out,
+         int64_t n, hipStream_t s) {
+  for (int base = 0; base < k; base += kRedSlots) {
+    DotSet d{};
+    d.k = std::min(kRedSlots, k - base);
+    d.n = n;
+    for (int i = 0; i < d.k; ++i) {
+      d.a[i] = a[base + i];
+      d.b[i] = b ? b[base + i] : nullptr;
+      d.out[i] = out[base + i];
+    }
+    launch_multidot(d, red(m), s);
+    KCHECK();
+  }
+  return AARMR_OK;
+}
+
+int dot1(aarmr_mesh* m, const double* a, const double* b, double* out, int64_t n, hipStream_t s) {
+  return dots(m, 1, &a, &b, &out, n, s);
+}
+
+// Copy `cnt` device scalars to the pinned staging buffer and synchronise.
+int read_scalars(aarmr_mesh* m, const double* const* src, int cnt, double* dst, hipStream_t s) {
+  for (int i = 0; i < cnt; ++i)
+    HIP_TRY(hipMemcpyAsync(m->hpin + i, src[i], sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  for (int i = 0; i < cnt; ++i) dst[i] = m->hpin[i];
+  return AARMR_OK;
+}
+
+int read_flags(aarmr_mesh* m, unsigned* out, hipStream_t s) {
+  unsigned* h = reinterpret_cast<unsigned*>(m->hpin + 64);
+  HIP_TRY(hipMemcpyAsync(h, m->flags, sizeof(unsigned), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemsetAsync(m->flags, 0, sizeof(unsigned), s));
+  HIP_TRY(hipStreamSynchronize(s));
+  *out = *h;
+  return AARMR_OK;
+}
+
+// y = A v on level l.
+int apply(aarmr_mesh* m, int l, const double* v, double* y, hipStream_t s) {
+  if (l == 0) {
+    launch_ebe_fine(m->lg[0], m->KEd, m->E, m->mask, v, y, 0, s);
+    ++m->sweeps;
+  } else {
+    launch_apply_elemmat(m->lg[l], m->lv[l].Ke, v, y, s);
+  }
+  KCHECK();
+  return AARMR_OK;
+}
+
+// One V-cycle (Algorithm 2) on level l from a zero initial guess: x = M_l^-1 b.
+int vcycle(aarmr_mesh* m, int l, const double* b, double* x, hipStream_t s) {
+  if (l == m->nlev - 1) {
+    launch_gemv(m->nc, m->Ainv, b, x, s);
+    KCHECK();
+    return AARMR_OK;
+  }
+  const Grid& G = m->lg[l];
+  const int64_t n3 = 3 * G.nn;
+  LevelBuf& L = m->lv[l];
+  LevelBuf& C = m->lv[l + 1];
+  const uint8_t* mask = (l == 0) ? m->mask : nullptr;
+  const double om = m->p.omega;
+  if (m->p.nu_pre >= 1) {
+    launch_jacobi_first(n3, b, L.dinv, om, x, s);  // line 1, first sweep from zero
+    KCHECK();
+    for (int it = 1; it < m->p.nu_pre; ++it) {
+      TRY(apply(m, l, x, L.t, s));
+      launch_jacobi_update(n3, b, L.t, L.dinv, om, x, s);
+      KCHECK();
+    }
+    TRY(apply(m, l, x, L.t, s));  // line 2: residual, restricted
+    launch_restrict(m->lg[l + 1], b, L.t, mask, C.b, s);
+  } else {
+    HIP_TRY(hipMemsetAsync(x, 0, n3 * sizeof(double), s));
+    HIP_TRY(hipMemsetAsync(L.t, 0, n3 * sizeof(double), s));
+    launch_restrict(m->lg[l + 1], b, L.t, mask, C.b, s);
+  }
+  KCHECK();
+  TRY(vcycle(m, l + 1, C.b, C.x, s));            // line 3
+  launch_prolong_add(G, C.x, mask, x, s);         // line 4
+  KCHECK();
+  for (int it = 0; it < m->p.nu_post; ++it) {     // line 5
+    TRY(apply(m, l, x, L.t, s));
+    launch_jacobi_update(n3, b, L.t, L.dinv, om, x, s);
+    KCHECK();
+  }
+  return AARMR_OK;
+}
+
+// SIMP moduli, mask and the MG hierarchy for the density rho~.
+int setup(aarmr_mesh* m, const double* rho, const int64_t* fixed, int64_t nfixed, bool build_mg,
+          hipStream_t s) {
+  const Grid& g = m->lg[0];
+  launch_build_mask(g.nn, fixed, nfixed, m->mask, m->flags, s);
+  KCHECK();
+  launch_simp(g.ne, rho, m->p.E0, m->p.Emin, m->p.penal, m->E, nullptr, m->flags, s);
+  KCHECK();
+  m->mg_ready = false;
+  if (!build_mg) return AARMR_OK;
+  launch_diag_fine(g, m->KEd, m->E, m->mask, m->lv[0].dinv, nullptr, s);
+  KCHECK();
+  for (int l = 1; l < m->nlev; ++l) {
+    if (l == 1)
+      launch_galerkin_from_fine(m->lg[1], m->KEd, m->E, m->mask, m->lv[1].Ke, s);
+    else
+      launch_galerkin_from_coarse(m->lg[l], m->lv[l - 1].Ke, m->lv[l].Ke, s);
+    KCHECK();
+    if (l < m->nlev - 1) {
+      launch_diag_elemmat(m->lg[l], m->lv[l].Ke, m->lv[l].dinv, nullptr, s);
+      KCHECK();
+    }
+  }
+  launch_assemble_dense(m->lg[m->nlev - 1], m->lv[m->nlev - 1].Ke, m->Ainv, s);
+  KCHECK();
+  launch_gj_invert(m->nc, m->Ainv, m->gjP, m->gjT, m->gjR, s);
+  KCHECK();
+  m->mg_ready = true;
+  return AARMR_OK;
+}
+
+// Preconditioned CG on A x = fm (fm already masked), x in/out (masked).
+int pcg(aarmr_mesh* m, double* x, int* iters, double* relres, hipStream_t s) {
+  const Grid& g = m->lg[0];
+  const int64_t n3 = 3 * g.nn;
+  double* sc = m->scal;
+  double* misc = sc + SC_MISC;
+  TRY(apply(m, 0, x, m->q, s));
+  launch_sub(n3, m->fm, m->q, m->r, s);
+  KCHECK();
+  {
+    const double* a[2] = {m->fm, m->r};
+    const double* b[2] = {m->fm, m->r};
+    double* o[2] = {misc + M_FF, sc + SC_RR};
+    TRY(dots(m, 2, a, b, o, n3, s));
+  }
+  double h[2];
+  {
+    const double* src[2] = {misc + M_FF, sc + SC_RR};
+    TRY(read_scalars(m, src, 2, h, s));
+  }
+  const double ff = h[0];
+  *iters = 0;
+  if (ff == 0.0) {
+    HIP_TRY(hipMemsetAsync(x, 0, n3 * sizeof(double), s));
+    *relres = 0.0;
+    return AARMR_OK;
+  }
+  const double tol2 = m->p.cg_rtol * m->p.cg_rtol * ff;
+  double rr = h[1];
+  *relres = std::sqrt(rr / ff);
+  if (rr <= tol2) return AARMR_OK;
+  TRY(vcycle(m, 0, m->r, m->z, s));
+  TRY(dot1(m, m->r, m->z, sc + SC_RZ, n3, s));
+  HIP_TRY(hipMemcpyAsync(m->pv, m->z, n3 * sizeof(double), hipMemcpyDeviceToDevice, s));
+  const int maxit = std::min(m->p.cg_maxit, kMaxIt);
+  for (int it = 0; it < maxit; ++it) {
+    TRY(apply(m, 0, m->pv, m->q, s));
+    TRY(dot1(m, m->pv, m->q, sc + SC_PQ + it, n3, s));
+    launch_cg_xr(n3, sc + SC_RZ + it, sc + SC_PQ + it, x, m->r, m->pv, m->q, s);
+    KCHECK();
+    TRY(dot1(m, m->r, m->r, sc + SC_RR + it + 1, n3, s));
+    const double* src[2] = {sc + SC_RR + it + 1, sc + SC_PQ + it};
+    TRY(read_scalars(m, src, 2, h, s));
+    *iters = it + 1;
+    rr = h[0];
+    *relres = std::sqrt(rr / ff);
+    if (!(h[1] > 0.0)) return fail(AARMR_E_SINGULAR, "CG: p^T A p <= 0");
+    if (rr <= tol2) return AARMR_OK;
+    TRY(vcycle(m, 0, m->r, m->z, s));
+    TRY(dot1(m, m->r, m->z, sc + SC_RZ + it + 1, n3, s));
+    launch_cg_p(n3, sc + SC_RZ + it + 1, sc + SC_RZ + it, m->z, m->pv, s);
+    KCHECK();
+  }
+  return fail(AARMR_E_NOT_CONVERGED, "CG reached cg_maxit before cg_rtol");
+}
+
+// phi = u / ||u|| into case l's PARM ring (eqs. 27-28, oldest dropped).
+int push_parm(aarmr_mesh* m, int l, const double* u, hipStream_t s) {
+  const int64_t n3 = 3 * m->lg[0].nn;
+  double* nrm = m->scal + SC_MISC + M_NRM;
+  TRY(dot1(m, u, u, nrm, n3, s));
+  const int slot = m->phi_head[l];
+  double* dst = m->Phi + ((int64_t)l * m->p.Ns + slot) * n3;
+  launch_scale_by_inv_sqrt(n3, u, nrm, dst, s);
+  KCHECK();
+  m->phi_head[l] = (slot + 1) % m->p.Ns;
+  m->phi_count[l] = std::min(m->phi_count[l] + 1, m->p.Ns);
+  return AARMR_OK;
+}
+
+int check_common(aarmr_mesh* m, const double* rho, const double* f, int32_t n_rhs,
+                 const int64_t* fixed, int64_t n_fixed, double* u) {
+  TRY(need_ws(m));
+  if (!rho || !f || !u) return fail(AARMR_E_INVALID, "null rho, f or u");
+  if (n_rhs < 1 || n_rhs > m->p.n_rhs_max) return fail(AARMR_E_INVALID, "n_rhs out of range");
+  if (n_fixed < 0 || (n_fixed > 0 && !fixed)) return fail(AARMR_E_INVALID, "bad fixed DOF list");
+  return AARMR_OK;
+}
+
+int finish_flags(aarmr_mesh* m, hipStream_t s) {
+  unsigned fl = 0;
+  TRY(read_flags(m, &fl, s));
+  if (fl & 1u) return fail(AARMR_E_INVALID, "density outside [0, 1]");
+  if (fl & 2u) return fail(AARMR_E_INVALID, "fixed DOF id out of range");
+  return AARMR_OK;
+}
+
+// compliance, energy and dc contribution of case l.
+int post_case(aarmr_mesh* m, int l, const double* rho_phys, const double* ul, double* compliance,
+              bool want_dc, hipStream_t s) {
+  const Grid& g = m->lg[0];
+  const int64_t n3 = 3 * g.nn;
+  if (compliance) {
+    double* c = m->scal + SC_MISC + M_C;
+    TRY(dot1(m, m->fm, ul, c, n3, s));
+    double h;
+    TRY(read_scalars(m, (const double* const*)&c, 1, &h, s));
+    compliance[l] = h;
+  }
+  if (want_dc) {
+    launch_energy(g, m->KEd, m->mask, ul, m->ework, s);
+    KCHECK();
+    launch_dc_accum(g.ne, rho_phys, m->ework, m->p.E0, m->p.Emin, m->p.penal, m->dc_tmp, l == 0,
+                    s);
+    KCHECK();
+  }
+  return AARMR_OK;
+}
+
+int finish_dc(aarmr_mesh* m, double* dc, int32_t flags, hipStream_t s) {
+  const Grid& g = m->lg[0];
+  if (!dc) return AARMR_OK;
+  if (flags & AARMR_FILTER_INPUT) {
+    launch_filter(g, m->p.rmin, 1, m->Hs, m->dc_tmp, dc, s);
+  } else {
+    HIP_TRY(hipMemcpyAsync(dc, m->dc_tmp, g.ne * sizeof(double), hipMemcpyDeviceToDevice, s));
+  }
+  KCHECK();
+  return AARMR_OK;
+}
+
+double ms_since(std::chrono::steady_clock::time_point t0) {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+}  // namespace
+
+extern "C" {
+
+void aarmr_default_params(aarmr_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->nx = p->ny = p->nz = 8;
+  p->E0 = 1.0;
+  p->Emin = 1e-9;
+  p->nu = 0.3;
+  p->penal = 3.0;
+  p->rmin = 2.5;
+  p->mg_levels = 3;
+  p->nu_pre = 1;
+  p->nu_post = 1;
+  p->omega = 0.6;
+  p->cg_rtol = 1e-8;
+  p->cg_maxit = 2000;
+  p->precision = AARMR_FP64;
+  p->Ns = 2;
+  p->Nm = 2;
+  p->ca_tol = 1e-3;
+  p->gs_tau = 1e-10;
+  p->n_rhs_max = 1;
+}
+
+int aarmr_mesh_create(const aarmr_params* p, aarmr_mesh** out) {
+  if (!p || !out) return fail(AARMR_E_INVALID, "null argument");
+  *out = nullptr;
+  if (p->nx < 1 || p->ny < 1 || p->nz < 1) return fail(AARMR_E_INVALID, "grid sizes must be >= 1");
+  if (p->mg_levels < 2 || p->mg_levels > AARMR_MAX_LEVELS)
+    return fail(AARMR_E_INVALID, "mg_levels outside [2, 8]");
+  const int f = 1 << (p->mg_levels - 1);
+  if (p->nx % f || p->ny % f || p->nz % f)
+    return fail(AARMR_E_INVALID, "grid sizes not divisible by 2^(mg_levels-1)");
+  if (p->Ns < 1 || p->Ns > AARMR_MAX_BASIS || p->Nm < 1 || p->Nm > AARMR_MAX_BASIS)
+    return fail(AARMR_E_INVALID, "Ns/Nm outside [1, 10]");
+  if (p->n_rhs_max < 1 || p->n_rhs_max > AARMR_MAX_RHS)
+    return fail(AARMR_E_INVALID, "n_rhs_max outside [1, 8]");
+  if (!(p->nu > -1.0 && p->nu < 0.5)) return fail(AARMR_E_INVALID, "nu outside (-1, 0.5)");
+  if (!(p->E0 > p->Emin && p->Emin > 0.0)) return fail(AARMR_E_INVALID, "need E0 > Emin > 0");
+  if (p->cg_maxit < 1 || p->cg_maxit > kMaxIt) return fail(AARMR_E_INVALID, "cg_maxit outside [1, 4096]");
+  if (p->precision != AARMR_FP64 && p->precision != AARMR_FP32_REFINE)
+    return fail(AARMR_E_INVALID, "unknown precision");
+  if (p->nu_pre < 0 || p->nu_post < 0 || !(p->omega > 0.0))
+    return fail(AARMR_E_INVALID, "bad smoother parameters");
+  aarmr_mesh* m = new aarmr_mesh();
+  m->p = *p;
+  m->nlev = p->mg_levels;
+  for (int l = 0; l < m->nlev; ++l) m->lg[l] = make_grid(p->nx >> l, p->ny >> l, p->nz >> l);
+  m->nc = (int)(3 * m->lg[m->nlev - 1].nn);
+  if (m->nc > 6000) {
+    delete m;
+    return fail(AARMR_E_INVALID, "coarsest grid above 6000 DOFs: use more levels");
+  }
+  hex8_stiffness(p->nu, m->KE);  // unit modulus; E0 enters through SIMP
+  *out = m;
+  return AARMR_OK;
+}
+
+void aarmr_mesh_destroy(aarmr_mesh* m) {
+  if (!m) return;
+  if (m->hpin) (void)hipHostFree(m->hpin);
+  delete m;
+}
+
+int64_t aarmr_workspace_bytes(const aarmr_mesh* m) {
+  if (!m) return -1;
+  aarmr_mesh tmp = *m;
+  tmp.hpin = nullptr;
+  return layout(&tmp, nullptr);
+}
+
+int aarmr_bind_workspace(aarmr_mesh* m, void* dev_ptr, int64_t bytes, void* stream) {
+  if (!m || !dev_ptr) return fail(AARMR_E_INVALID, "null argument");
+  if (reinterpret_cast<uintptr_t>(dev_ptr) % kAlign) return fail(AARMR_E_INVALID, "workspace not 256-byte aligned");
+  const int64_t need = layout(m, nullptr);
+  if (bytes < need) return fail(AARMR_E_NO_WORKSPACE, "workspace too small");
+  if (!m->hpin) HIP_TRY(hipHostMalloc((void**)&m->hpin, 4096 * sizeof(double), hipHostMallocDefault));
+  m->ws = static_cast<char*>(dev_ptr);
+  m->ws_bytes = bytes;
+  layout(m, m->ws);
+  hipStream_t s = S(stream);
+  HIP_TRY(hipMemcpyAsync(m->KEd, m->KE, 576 * sizeof(double), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemsetAsync(m->ticket, 0, 64, s));
+  HIP_TRY(hipMemsetAsync(m->flags, 0, 64, s));
+  HIP_TRY(hipMemsetAsync(m->mask, 0, (m->lg[0].nn + 3) / 4 * 4, s));
+  if (m->p.rmin > 0.0) {
+    launch_filter_rowsum(m->lg[0], m->p.rmin, m->Hs, s);
+    KCHECK();
+  }
+  HIP_TRY(hipStreamSynchronize(s));
+  for (int l = 0; l < AARMR_MAX_RHS; ++l) m->phi_count[l] = m->phi_head[l] = 0;
+  m->have_prev = false;
+  m->mg_ready = false;
+  return AARMR_OK;
+}
+
+int aarmr_setup(aarmr_mesh* m, const double* rho_phys, const int64_t* fixed_dofs, int64_t n_fixed,
+                void* stream) {
+  TRY(need_ws(m));
+  if (!rho_phys) return fail(AARMR_E_INVALID, "null rho");
+  if (n_fixed < 0 || (n_fixed > 0 && !fixed_dofs)) return fail(AARMR_E_INVALID, "bad fixed DOF list");
+  return setup(m, rho_phys, fixed_dofs, n_fixed, true, S(stream));
+}
+
+int aarmr_apply_operator(aarmr_mesh* m, int32_t level, const double* v, double* y, void* stream) {
+  TRY(need_ws(m));
+  if (!v || !y || v == y) return fail(AARMR_E_INVALID, "v, y must be distinct non-null");
+  if (level < 0 || level >= m->nlev) return fail(AARMR_E_INVALID, "level out of range");
+  if (level > 0 && !m->mg_ready) return fail(AARMR_E_STATE, "no hierarchy: call aarmr_setup");
+  return apply(m, level, v, y, S(stream));
+}
+
+int aarmr_vcycle(aarmr_mesh* m, const double* r, double* z, void* stream) {
+  TRY(need_ws(m));
+  if (!r || !z || r == z) return fail(AARMR_E_INVALID, "r, z must be distinct non-null");
+  if (!m->mg_ready) return fail(AARMR_E_STATE, "no hierarchy: call aarmr_setup");
+  return vcycle(m, 0, r, z, S(stream));
+}
+
+int aarmr_element_energy(aarmr_mesh* m, const double* u, double* energy, void* stream) {
+  TRY(need_ws(m));
+  if (!u || !energy) return fail(AARMR_E_INVALID, "null argument");
+  launch_energy(m->lg[0], m->KEd, m->mask, u, energy, S(stream));
+  KCHECK();
+  return AARMR_OK;
+}
+
+int aarmr_filter(aarmr_mesh* m, int32_t mode, const double* in, double* out, void* stream) {
+  TRY(need_ws(m));
+  if (!in || !out || in == out) return fail(AARMR_E_INVALID, "in, out must be distinct non-null");
+  if (mode != 0 && mode != 1) return fail(AARMR_E_INVALID, "mode must be 0 or 1");
+  if (!(m->p.rmin > 0.0)) return fail(AARMR_E_INVALID, "filter disabled (rmin <= 0)");
+  launch_filter(m->lg[0], m->p.rmin, mode, m->Hs, in, out, S(stream));
+  KCHECK();
+  return AARMR_OK;
+}
+
+int aarmr_solve(aarmr_mesh* m, const double* rho, const double* f, int32_t n_rhs,
+                const int64_t* fixed_dofs, int64_t n_fixed, double* u, double* compliance,
+                double* dc, int32_t flags, aarmr_stats* st, void* stream) {
+  TRY(check_common(m, rho, f, n_rhs, fixed_dofs, n_fixed, u));
+  if ((flags & AARMR_FILTER_INPUT) && !(m->p.rmin > 0.0))
+    return fail(AARMR_E_INVALID, "AARMR_FILTER_INPUT needs rmin > 0");
+  hipStream_t s = S(stream);
+  const Grid& g = m->lg[0];
+  const int64_t n3 = 3 * g.nn;
+  auto t0 = std::chrono::steady_clock::now();
+  const int64_t sw0 = m->sweeps;
+  const double* rho_phys = rho;
+  if (flags & AARMR_FILTER_INPUT) {
+    launch_filter(g, m->p.rmin, 0, m->Hs, rho, m->rho_f, s);
+    KCHECK();
+    rho_phys = m->rho_f;
+  }
+  TRY(setup(m, rho_phys, fixed_dofs, n_fixed, true, s));
+  TRY(finish_flags(m, s));
+  if (st) {
+    std::memset(st, 0, sizeof(*st));
+    st->setup_ms = ms_since(t0);
+  }
+  auto t1 = std::chrono::steady_clock::now();
+  int status = AARMR_OK;
+  for (int l = 0; l < n_rhs; ++l) {
+    double* ul = u + l * n3;
+    launch_copy_masked(g, f + l * n3, m->mask, m->fm, s);
+    KCHECK();
+    if (flags & AARMR_WARM_START) {
+      launch_copy_masked(g, ul, m->mask, ul, s);
+      KCHECK();
+    } else {
+      HIP_TRY(hipMemsetAsync(ul, 0, n3 * sizeof(double), s));
+    }
+    int its = 0;
+    double rel = 0.0;
+    int rc = pcg(m, ul, &its, &rel, s);
+    if (rc != AARMR_OK && rc != AARMR_E_NOT_CONVERGED) return rc;
+    if (rc == AARMR_E_NOT_CONVERGED) status = rc;
+    if (st) {
+      st->iterations[l] = its;
+      st->rel_residual[l] = rel;
+    }
+    TRY(post_case(m, l, rho_phys, ul, compliance, dc != nullptr, s));
+    if (flags & AARMR_RECORD_PARM) TRY(push_parm(m, l, ul, s));
+  }
+  TRY(finish_dc(m, dc, flags, s));
+  HIP_TRY(hipMemcpyAsync(m->E_prev, m->E, g.ne * sizeof(double), hipMemcpyDeviceToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  m->have_prev = true;
+  if (st) {
+    st->solve_ms = ms_since(t1);
+    st->fine_sweeps = m->sweeps - sw0;
+  }
+  if (status != AARMR_OK) return fail(status, "CG reached cg_maxit before cg_rtol");
+  return AARMR_OK;
+}
+
+int aarmr_ca_update(aarmr_mesh* m, const double* rho, const double* f, int32_t n_rhs,
+                    const int64_t* fixed_dofs, int64_t n_fixed, double* u, double* compliance,
+                    double* dc, int32_t flags, aarmr_ca_stats* st, void* stream) {
+  TRY(check_common(m, rho, f, n_rhs, fixed_dofs, n_fixed, u));
+  if ((flags & AARMR_FILTER_INPUT) && !(m->p.rmin > 0.0))
+    return fail(AARMR_E_INVALID, "AARMR_FILTER_INPUT needs rmin > 0");
+  if (!m->have_prev) return fail(AARMR_E_STATE, "no reference design: run aarmr_solve first");
+  for (int l = 0; l < n_rhs; ++l)
+    if (m->phi_count[l] < m->p.Ns) return fail(AARMR_E_STATE, "PARM of a load case is not complete");
+  hipStream_t s = S(stream);
+  const Grid& g = m->lg[0];
+  const int64_t n3 = 3 * g.nn;
+  const int Ns = m->p.Ns, Nm = m->p.Nm;
+  const int64_t sw0 = m->sweeps;
+  if (st) std::memset(st, 0, sizeof(*st));
+  const double* rho_phys = rho;
+  if (flags & AARMR_FILTER_INPUT) {
+    launch_filter(g, m->p.rmin, 0, m->Hs, rho, m->rho_f, s);
+    KCHECK();
+    rho_phys = m->rho_f;
+  }
+  TRY(setup(m, rho_phys, fixed_dofs, n_fixed, false, s));
+  TRY(finish_flags(m, s));
+  launch_diff(g.ne, m->E, m->E_prev, m->dE, s);  // weights of dK = K - K0
+  KCHECK();
+  double* misc = m->scal + SC_MISC;
+  int status = AARMR_OK;
+  for (int l = 0; l < n_rhs; ++l) {
+    double* ul = u + l * n3;
+    const double* PhiL = m->Phi + (int64_t)l * Ns * n3;
+    launch_copy_masked(g, f + l * n3, m->mask, m->fm, s);
+    KCHECK();
+    launch_copy_masked(g, ul, m->mask, ul, s);
+    KCHECK();
+    // eq. (15): K_Phi = Phi^T K0 Phi, K0 = K(previous design)
+    for (int j = 0; j < Ns; ++j) {
+      launch_ebe_fine(g, m->KEd, m->E_prev, m->mask, PhiL + j * n3, m->t0, 0, s);
+      ++m->sweeps;
+      KCHECK();
+      std::vector<const double*> a(Ns), b(Ns);
+      std::vector<double*> o(Ns);
+      for (int i = 0; i < Ns; ++i) {
+        a[i] = PhiL + i * n3;
+        b[i] = m->t0;
+        o[i] = misc + M_KPHI + i * Ns + j;
+      }
+      TRY(dots(m, Ns, a.data(), b.data(), o.data(), n3, s));
+    }
+    // eq. (20)/(26): r_1 = u_last, r_i = -Phi K_Phi^-1 Phi^T dK r_(i-1)
+    HIP_TRY(hipMemcpyAsync(m->R, ul, n3 * sizeof(double), hipMemcpyDeviceToDevice, s));
+    bool ca_ok = true;
+    for (int i = 1; i < Nm; ++i) {
+      launch_ebe_fine(g, m->KEd, m->dE, m->mask, m->R + (i - 1) * n3, m->t0, 1, s);
+      ++m->sweeps;
+      KCHECK();
+      std::vector<const double*> a(Ns), b(Ns);
+      std::vector<double*> o(Ns);
+      for (int j = 0; j < Ns; ++j) {
+        a[j] = PhiL + j * n3;
+        b[j] = m->t0;
+        o[j] = misc + M_G + j;
+      }
+      TRY(dots(m, Ns, a.data(), b.data(), o.data(), n3, s));
+      launch_small_spd_solve(Ns, Ns, misc + M_KPHI, misc + M_G, misc + M_C2, m->flags, s);
+      KCHECK();
+      std::vector<const double*> V(Ns);
+      for (int j = 0; j < Ns; ++j) V[j] = PhiL + j * n3;
+      launch_lincomb(n3, Ns, V.data(), misc + M_C2, -1.0, nullptr, m->R + i * n3, s);
+      KCHECK();
+    }
+    {
+      unsigned fl = 0;
+      TRY(read_flags(m, &fl, s));
+      if (fl & 4u) ca_ok = false;  // K_Phi not positive definite: reject CA
+    }
+    // Gram-Schmidt (two passes, classical) with rank drop
+    int kept = 0;
+    if (ca_ok) {
+      for (int i = 0; i < Nm; ++i) {
+        double* v = m->R + i * n3;
+        double n0;
+        double* nrm = misc + M_NRM;
+        TRY(dot1(m, v, v, nrm, n3, s));
+        TRY(read_scalars(m, (const double* const*)&nrm, 1, &n0, s));
+        if (!(n0 > 0.0)) continue;
+        for (int pass = 0; pass < 2 && kept > 0; ++pass) {
+          std::vector<const double*> a(kept), b(kept);
+          std::vector<double*> o(kept);
+          for (int j = 0; j < kept; ++j) {
+            a[j] = m->R + j * n3;
+            b[j] = v;
+            o[j] = misc + M_H + j;
+          }
+          TRY(dots(m, kept, a.data(), b.data(), o.data(), n3, s));
+          launch_lincomb(n3, kept, a.data(), misc + M_H, -1.0, v, v, s);
+          KCHECK();
+        }
+        double n1;
+        TRY(dot1(m, v, v, nrm, n3, s));
+        TRY(read_scalars(m, (const double* const*)&nrm, 1, &n1, s));
+        if (!(std::sqrt(n1) > m->p.gs_tau * std::sqrt(n0))) continue;  // dependent column
+        launch_scale_by_inv_sqrt(n3, v, nrm, m->R + kept * n3, s);
+        KCHECK();
+        ++kept;
+      }
+    }
+    double eps = 1.0;
+    if (kept > 0) {
+      // eqs. (22)-(25): K_R~ = R~^T K R~, f_R~ = R~^T f, y, u~ = R~ y
+      for (int j = 0; j < kept; ++j) {
+        launch_ebe_fine(g, m->KEd, m->E, m->mask, m->R + j * n3, m->KR + j * n3, 0, s);
+        ++m->sweeps;
+        KCHECK();
+      }
+      std::vector<const double*> a, b;
+      std::vector<double*> o;
+      for (int i = 0; i < kept; ++i)
+        for (int j = 0; j < kept; ++j) {
+          a.push_back(m->R + i * n3);
+          b.push_back(m->KR + j * n3);
+          o.push_back(misc + M_KR + i * kept + j);
+        }
+      for (int i = 0; i < kept; ++i) {
+        a.push_back(m->R + i * n3);
+        b.push_back(m->fm);
+        o.push_back(misc + M_FR + i);
+      }
+      a.push_back(m->fm);
+      b.push_back(m->fm);
+      o.push_back(misc + M_FF);
+      TRY(dots(m, (int)a.size(), a.data(), b.data(), o.data(), n3, s));
+      launch_small_spd_solve(kept, kept, misc + M_KR, misc + M_FR, misc + M_Y, m->flags, s);
+      KCHECK();
+      std::vector<const double*> Q(kept), KQ(kept);
+      for (int j = 0; j < kept; ++j) {
+        Q[j] = m->R + j * n3;
+        KQ[j] = m->KR + j * n3;
+      }
+      launch_lincomb(n3, kept, Q.data(), misc + M_Y, 1.0, nullptr, ul, s);
+      KCHECK();
+      // eq. (29) from the stored K R~ columns: f - sum_j y_j K r~_j
+      launch_lincomb(n3, kept, KQ.data(), misc + M_Y, -1.0, m->fm, m->t0, s);
+      KCHECK();
+      TRY(dot1(m, m->t0, m->t0, misc + M_EPS, n3, s));
+      double h[2];
+      const double* src[2] = {misc + M_EPS, misc + M_FF};
+      TRY(read_scalars(m, src, 2, h, s));
+      unsigned fl = 0;
+      TRY(read_flags(m, &fl, s));
+      eps = (h[1] > 0.0 && !(fl & 4u)) ? std::sqrt(h[0] / h[1]) : 1.0;
+      if (h[1] == 0.0) eps = 0.0;
+    }
+    const bool accept = kept > 0 && eps < m->p.ca_tol;
+    if (st) {
+      st->eps[l] = eps;
+      st->accepted[l] = accept ? 1 : 0;
+      st->rank[l] = kept;
+      st->rel_residual[l] = eps;
+    }
+    if (!accept) {
+      // Algorithm 1 lines 9-10: MGCG warm-started from u~, then PARM update
+      if (kept == 0) HIP_TRY(hipMemsetAsync(ul, 0, n3 * sizeof(double), s));
+      if (!m->mg_ready) TRY(setup(m, rho_phys, fixed_dofs, n_fixed, true, s));
+      int its = 0;
+      double rel = 0.0;
+      int rc = pcg(m, ul, &its, &rel, s);
+      if (rc != AARMR_OK && rc != AARMR_E_NOT_CONVERGED) return rc;
+      if (rc == AARMR_E_NOT_CONVERGED) status = rc;
+      if (st) {
+        st->mgcg_iterations[l] = its;
+        st->rel_residual[l] = rel;
+      }
+      TRY(push_parm(m, l, ul, s));
+    }
+    TRY(post_case(m, l, rho_phys, ul, compliance, dc != nullptr, s));
+  }
+  TRY(finish_dc(m, dc, flags, s));
+  HIP_TRY(hipMemcpyAsync(m->E_prev, m->E, g.ne * sizeof(double), hipMemcpyDeviceToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (st) st->fine_sweeps = m->sweeps - sw0;
+  if (status != AARMR_OK) return fail(status, "fallback CG reached cg_maxit before cg_rtol");
+  return AARMR_OK;
+}
+
+int aarmr_oc_update(aarmr_mesh* m, const double* x, const double* dc, const double* dv,
+                    double volfrac, double move, double* x_new, double* rho_phys_new,
+                    void* stream) {
+  TRY(need_ws(m));
+  if (!x || !dc || !dv || !x_new || !rho_phys_new) return fail(AARMR_E_INVALID, "null argument");
+  if (!(m->p.rmin > 0.0)) return fail(AARMR_E_INVALID, "OC needs the filter (rmin > 0)");
+  hipStream_t s = S(stream);
+  const Grid& g = m->lg[0];
+  double* lam = m->scal + SC_MISC + M_OC;
+  double* vol = m->scal + SC_MISC + M_VOL;
+  const double target = volfrac * (double)g.ne;
+  launch_oc_init(lam, s);
+  KCHECK();
+  for (int it = 0; it < 200; ++it) {
+    launch_oc_step(g.ne, x, dc, dv, move, lam, x_new, s);
+    launch_filter(g, m->p.rmin, 0, m->Hs, x_new, rho_phys_new, s);
+    KCHECK();
+    const double* a = rho_phys_new;
+    TRY(dots(m, 1, &a, nullptr, &vol, g.ne, s));
+    launch_oc_bisect(lam, vol, target, s);
+    KCHECK();
+    if ((it & 15) == 15) {
+      double done;
+      const double* src = lam + 3;
+      TRY(read_scalars(m, &src, 1, &done, s));
+      if (done != 0.0) break;
+    }
+  }
+  return AARMR_OK;
+}
+
+const char* aarmr_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,228 @@
+// Fine-grid kernels: SIMP moduli (eq. 1), fixed-DOF mask, the
+// element-by-element stiffness product y = A v (eq. 7 operator), its
+// diagonal (Jacobi smoother of Algorithm 2) and element energies (eq. 6).
+#include "internal.hpp"
+
+namespace aarmr {
+
+namespace {
+
+__device__ inline int64_t node_of(int nx, int ny, int i, int j, int k) {
+  return (int64_t)i + (int64_t)(nx + 1) * ((int64_t)j + (int64_t)(ny + 1) * k);
+}
+
+// eq. (1): E = Emin + (E0 - Emin) rho~^p; flags rho~ outside [0, 1].
+__global__ void k_simp(int64_t ne, const double* __restrict__ rho, double E0, double Emin,
+                       double p, double* __restrict__ E, float* __restrict__ E32,
+                       unsigned* __restrict__ bad) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ne) return;
+  double r = rho[e];
+  if (!(r >= 0.0 && r <= 1.0)) {  // also catches NaN
+    atomicOr(bad, 1u);
+    r = fmin(fmax(r, 0.0), 1.0);
+    if (r != r) r = 0.0;
+  }
+  double v = Emin + (E0 - Emin) * pow(r, p);
+  E[e] = v;
+  if (E32) E32[e] = (float)v;
+}
+
+__global__ void k_diff(int64_t n, const double* __restrict__ a, const double* __restrict__ b,
+                       double* __restrict__ out) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = a[i] - b[i];
+}
+
+__global__ void k_mask_clear(int64_t nn, uint32_t* mask_words) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < (nn + 3) / 4) mask_words[i] = 0u;
+}
+
+__global__ void k_mask_set(int64_t nn, const int64_t* __restrict__ fixed, int64_t nf,
+                           uint32_t* mask_words, unsigned* bad) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nf) return;
+  int64_t d = fixed[t];
+  if (d < 0 || d >= 3 * nn) {
+    atomicOr(bad, 2u);
+    return;
+  }
+  int64_t node = d % nn;
+  int c = (int)(d / nn);
+  uint32_t bit = (1u << c) << (8 * (node & 3));
+  atomicOr(&mask_words[node >> 2], bit);
+}
+
+// y = A v, thread per node, gathering the 3 rows of each adjacent element's
+// stiffness (owner computes: no atomics, fixed summation order).
+__global__ void __launch_bounds__(256) k_ebe_gather(int nx, int ny, int nz,
+                                                    const double* __restrict__ KE,
+                                                    const double* __restrict__ E,
+                                                    const uint8_t* __restrict__ mask,
+                                                    const double* __restrict__ v,
+                                                    double* __restrict__ y, int mode) {
+  const int64_t nn = (int64_t)(nx + 1) * (ny + 1) * (nz + 1);
+  int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= nn) return;
+  int i = (int)(n % (nx + 1));
+  int64_t rest = n / (nx + 1);
+  int j = (int)(rest % (ny + 1));
+  int k = (int)(rest / (ny + 1));
+  double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
+  for (int ez = k - 1; ez <= k; ++ez) {
+    if (ez < 0 || ez >= nz) continue;
+    for (int ey = j - 1; ey <= j; ++ey) {
+      if (ey < 0 || ey >= ny) continue;
+      for (int ex = i - 1; ex <= i; ++ex) {
+        if (ex < 0 || ex >= nx) continue;
+        const int a = (i - ex) + 2 * (j - ey) + 4 * (k - ez);
+        const double w = E[(int64_t)ex + (int64_t)nx * ((int64_t)ey + (int64_t)ny * ez)];
+        const double* row = KE + (3 * a) * 24;
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+          const int64_t nb = node_of(nx, ny, ex + (b & 1), ey + ((b >> 1) & 1), ez + (b >> 2));
+          const uint8_t mb = mask[nb];
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            const double vb = ((mb >> c) & 1) ? 0.0 : v[c * nn + nb];
+            s0 = fma(row[3 * b + c], vb, s0);
+            s1 = fma(row[24 + 3 * b + c], vb, s1);
+            s2 = fma(row[48 + 3 * b + c], vb, s2);
+          }
+        }
+        acc0 = fma(w, s0, acc0);
+        acc1 = fma(w, s1, acc1);
+        acc2 = fma(w, s2, acc2);
+      }
+    }
+  }
+  const uint8_t m = mask[n];
+  const double acc[3] = {acc0, acc1, acc2};
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    double out = acc[c];
+    if ((m >> c) & 1) out = (mode == 0) ? v[c * nn + n] : 0.0;
+    y[c * nn + n] = out;
+  }
+}
+
+// Jacobi diagonal of A: sum over adjacent elements of E_e * KE_(aa) per
+// component; identity on fixed DOFs.  Stores the inverse.
+__global__ void k_diag_fine(int nx, int ny, int nz, const double* __restrict__ KE,
+                            const double* __restrict__ E, const uint8_t* __restrict__ mask,
+                            double* __restrict__ dinv, float* __restrict__ dinv32) {
+  const int64_t nn = (int64_t)(nx + 1) * (ny + 1) * (nz + 1);
+  int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= nn) return;
+  int i = (int)(n % (nx + 1));
+  int64_t rest = n / (nx + 1);
+  int j = (int)(rest % (ny + 1));
+  int k = (int)(rest / (ny + 1));
+  double d[3] = {0.0, 0.0, 0.0};
+  for (int ez = k - 1; ez <= k; ++ez) {
+    if (ez < 0 || ez >= nz) continue;
+    for (int ey = j - 1; ey <= j; ++ey) {
+      if (ey < 0 || ey >= ny) continue;
+      for (int ex = i - 1; ex <= i; ++ex) {
+        if (ex < 0 || ex >= nx) continue;
+        const int a = (i - ex) + 2 * (j - ey) + 4 * (k - ez);
+        const double w = E[(int64_t)ex + (int64_t)nx * ((int64_t)ey + (int64_t)ny * ez)];
+        for (int c = 0; c < 3; ++c) d[c] += w * KE[(3 * a + c) * 25];
+      }
+    }
+  }
+  const uint8_t m = mask[n];
+  for (int c = 0; c < 3; ++c) {
+    double di = (((m >> c) & 1) || d[c] == 0.0) ? 1.0 : 1.0 / d[c];
+    dinv[c * nn + n] = di;
+    if (dinv32) dinv32[c * nn + n] = (float)di;
+  }
+}
+
+// e_e = u_e^T KE u_e with fixed DOFs of u read as zero.
+__global__ void __launch_bounds__(256) k_energy(int nx, int ny, int nz,
+                                                const double* __restrict__ KE,
+                                                const uint8_t* __restrict__ mask,
+                                                const double* __restrict__ u,
+                                                double* __restrict__ energy) {
+  const int64_t nn = (int64_t)(nx + 1) * (ny + 1) * (nz + 1);
+  const int64_t ne = (int64_t)nx * ny * nz;
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ne) return;
+  int ex = (int)(e % nx);
+  int64_t rest = e / nx;
+  int ey = (int)(rest % ny);
+  int ez = (int)(rest / ny);
+  double ue[24];
+#pragma unroll
+  for (int b = 0; b < 8; ++b) {
+    const int64_t nb = node_of(nx, ny, ex + (b & 1), ey + ((b >> 1) & 1), ez + (b >> 2));
+    const uint8_t mb = mask[nb];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) ue[3 * b + c] = ((mb >> c) & 1) ? 0.0 : u[c * nn + nb];
+  }
+  double s = 0.0;
+#pragma unroll
+  for (int r = 0; r < 24; ++r) {
+    double t = 0.0;
+#pragma unroll
+    for (int c = 0; c < 24; ++c) t = fma(KE[r * 24 + c], ue[c], t);
+    s = fma(ue[r], t, s);
+  }
+  energy[e] = s;
+}
+
+// dc (+)= -p rho~^(p-1) (E0 - Emin) e_e  (eq. 6 with eq. 1).
+__global__ void k_dc_accum(int64_t ne, const double* __restrict__ rho,
+                           const double* __restrict__ energy, double E0, double Emin, double p,
+                           double* __restrict__ dc, int first) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ne) return;
+  double r = fmin(fmax(rho[e], 0.0), 1.0);
+  double v = -p * pow(r, p - 1.0) * (E0 - Emin) * energy[e];
+  dc[e] = first ? v : dc[e] + v;
+}
+
+inline unsigned nblk(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+}  // namespace
+
+void launch_simp(int64_t ne, const double* rho, double E0, double Emin, double p, double* E,
+                 float* E32, unsigned* bad, hipStream_t s) {
+  k_simp<<<nblk(ne, 256), 256, 0, s>>>(ne, rho, E0, Emin, p, E, E32, bad);
+}
+
+void launch_diff(int64_t n, const double* a, const double* b, double* out, hipStream_t s) {
+  k_diff<<<nblk(n, 256), 256, 0, s>>>(n, a, b, out);
+}
+
+void launch_build_mask(int64_t nn, const int64_t* fixed, int64_t nfixed, uint8_t* mask,
+                       unsigned* bad, hipStream_t s) {
+  uint32_t* w = reinterpret_cast<uint32_t*>(mask);
+  k_mask_clear<<<nblk((nn + 3) / 4, 256), 256, 0, s>>>(nn, w);
+  if (nfixed > 0) k_mask_set<<<nblk(nfixed, 256), 256, 0, s>>>(nn, fixed, nfixed, w, bad);
+}
+
+void launch_ebe_fine(const Grid& g, const double* KE, const double* E, const uint8_t* mask,
+                     const double* v, double* y, int mode, hipStream_t s) {
+  k_ebe_gather<<<nblk(g.nn, 256), 256, 0, s>>>(g.nx, g.ny, g.nz, KE, E, mask, v, y, mode);
+}
+
+void launch_diag_fine(const Grid& g, const double* KE, const double* E, const uint8_t* mask,
+                      double* dinv, float* dinv32, hipStream_t s) {
+  k_diag_fine<<<nblk(g.nn, 256), 256, 0, s>>>(g.nx, g.ny, g.nz, KE, E, mask, dinv, dinv32);
+}
+
+void launch_energy(const Grid& g, const double* KE, const uint8_t* mask, const double* u,
+                   double* energy, hipStream_t s) {
+  k_energy<<<nblk(g.ne, 256), 256, 0, s>>>(g.nx, g.ny, g.nz, KE, mask, u, energy);
+}
+
+void launch_dc_accum(int64_t ne, const double* rho, const double* energy, double E0, double Emin,
+                     double p, double* dc, int first, hipStream_t s) {
+  k_dc_accum<<<nblk(ne, 256), 256, 0, s>>>(ne, rho, energy, E0, Emin, p, dc, first);
+}
+
+}  // namespace aarmr

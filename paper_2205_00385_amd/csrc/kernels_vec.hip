@@ -1,0 +1,211 @@
+// Vector kernels of CG and of the reduced model: deterministic FP64 dot
+// products (wavefront shuffles, fixed-order block partials, last block
+// finishes), CG updates whose scalars stay in device memory, linear
+// combinations with device coefficients and small dense SPD solves.
+#include "internal.hpp"
+
+namespace aarmr {
+
+namespace {
+
+inline unsigned nblk(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+// Block (256 threads) sum in a fixed order; result valid in thread 0.
+__device__ inline double block_sum(double v, double* sh) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0) r = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+  __syncthreads();
+  return r;
+}
+
+// k dot products over n entries; grid of nb <= kRedBlocks blocks; each block
+// strides over the vector in a fixed pattern and writes one partial per
+// product; the last block to finish sums the partials in index order.
+__global__ void __launch_bounds__(256) k_multidot(DotSet d, double* __restrict__ partial,
+                                                  unsigned* __restrict__ ticket) {
+  __shared__ double sh[4];
+  __shared__ bool last;
+  const int nb = gridDim.x;
+  const int64_t stride = (int64_t)nb * 256;
+  for (int k = 0; k < d.k; ++k) {
+    const double* a = d.a[k];
+    const double* b = d.b[k];
+    double s = 0.0;
+    if (b) {
+      for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < d.n; i += stride)
+        s = fma(a[i], b[i], s);
+    } else {  // plain sum
+      for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < d.n; i += stride) s += a[i];
+    }
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) partial[k * kRedBlocks + blockIdx.x] = s;
+  }
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned t = atomicAdd(ticket, 1u);
+    last = (t == (unsigned)nb - 1);
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  for (int k = 0; k < d.k; ++k) {
+    double s = 0.0;
+    for (int i = threadIdx.x; i < nb; i += 256)
+      s += __hip_atomic_load(&partial[k * kRedBlocks + i], __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) *d.out[k] = s;
+  }
+  if (threadIdx.x == 0) __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ void k_copy_masked(int64_t nn, const double* __restrict__ src,
+                              const uint8_t* __restrict__ mask, double* __restrict__ dst) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 3 * nn) return;
+  const int c = (int)(i / nn);
+  const int64_t n = i - c * nn;
+  dst[i] = ((mask[n] >> c) & 1) ? 0.0 : src[i];
+}
+
+__global__ void k_sub(int64_t n, const double* __restrict__ a, const double* __restrict__ b,
+                      double* __restrict__ out) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = a[i] - b[i];
+}
+
+// alpha = rz / pq; x += alpha p; r -= alpha q.
+__global__ void k_cg_xr(int64_t n, const double* __restrict__ rz, const double* __restrict__ pq,
+                        double* __restrict__ x, double* __restrict__ r,
+                        const double* __restrict__ p, const double* __restrict__ q) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double alpha = *rz / *pq;
+  x[i] = fma(alpha, p[i], x[i]);
+  r[i] = fma(-alpha, q[i], r[i]);
+}
+
+// beta = rz_new / rz_old; p = z + beta p.
+__global__ void k_cg_p(int64_t n, const double* __restrict__ rz_new,
+                       const double* __restrict__ rz_old, const double* __restrict__ z,
+                       double* __restrict__ p) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double beta = *rz_new / *rz_old;
+  p[i] = fma(beta, p[i], z[i]);
+}
+
+__global__ void k_scale_inv_sqrt(int64_t n, const double* __restrict__ src,
+                                 const double* __restrict__ nrm2, double* __restrict__ dst) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double s = 1.0 / sqrt(*nrm2);
+  dst[i] = src[i] * s;
+}
+
+struct VecList {
+  const double* v[2 * AARMR_MAX_BASIS];
+};
+
+// out = add + sign * sum_j coef[j] V_j   (add may be null)
+__global__ void k_lincomb(int64_t n, int k, VecList V, const double* __restrict__ coef,
+                          double sign, const double* __restrict__ add, double* __restrict__ out) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = 0.0;
+  for (int j = 0; j < k; ++j) s = fma(coef[j], V.v[j][i], s);
+  out[i] = add ? fma(sign, s, add[i]) : sign * s;
+}
+
+// Solve A x = b for a small SPD matrix (row-major, leading dimension lda) by
+// Cholesky in one thread; flags a non-positive pivot.
+__global__ void k_small_spd_solve(int n, int lda, const double* __restrict__ A,
+                                  const double* __restrict__ b, double* __restrict__ x,
+                                  unsigned* bad) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double L[2 * AARMR_MAX_BASIS][2 * AARMR_MAX_BASIS];
+  double y[2 * AARMR_MAX_BASIS];
+  for (int i = 0; i < n; ++i) {
+    for (int j = 0; j <= i; ++j) {
+      double s = 0.5 * (A[i * lda + j] + A[j * lda + i]);
+      for (int k = 0; k < j; ++k) s -= L[i][k] * L[j][k];
+      if (i == j) {
+        if (!(s > 0.0)) {
+          atomicOr(bad, 4u);
+          for (int t = 0; t < n; ++t) x[t] = 0.0;
+          return;
+        }
+        L[i][i] = sqrt(s);
+      } else {
+        L[i][j] = s / L[j][j];
+      }
+    }
+  }
+  for (int i = 0; i < n; ++i) {
+    double s = b[i];
+    for (int k = 0; k < i; ++k) s -= L[i][k] * y[k];
+    y[i] = s / L[i][i];
+  }
+  for (int i = n - 1; i >= 0; --i) {
+    double s = y[i];
+    for (int k = i + 1; k < n; ++k) s -= L[k][i] * x[k];
+    x[i] = s / L[i][i];
+  }
+}
+
+}  // namespace
+
+void launch_multidot(const DotSet& d, const RedScratch& rs, hipStream_t s) {
+  int64_t want = (d.n + 255) / 256;
+  int nb = (int)(want < kRedBlocks ? (want < 1 ? 1 : want) : kRedBlocks);
+  k_multidot<<<nb, 256, 0, s>>>(d, rs.partial, rs.ticket);
+}
+
+void launch_copy_masked(const Grid& g, const double* src, const uint8_t* mask, double* dst,
+                        hipStream_t s) {
+  k_copy_masked<<<nblk(3 * g.nn, 256), 256, 0, s>>>(g.nn, src, mask, dst);
+}
+
+void launch_sub(int64_t n, const double* a, const double* b, double* out, hipStream_t s) {
+  k_sub<<<nblk(n, 256), 256, 0, s>>>(n, a, b, out);
+}
+
+void launch_cg_xr(int64_t n, const double* rz, const double* pq, double* x, double* r,
+                  const double* p, const double* q, hipStream_t s) {
+  k_cg_xr<<<nblk(n, 256), 256, 0, s>>>(n, rz, pq, x, r, p, q);
+}
+
+void launch_cg_p(int64_t n, const double* rz_new, const double* rz_old, const double* z,
+                 double* p, hipStream_t s) {
+  k_cg_p<<<nblk(n, 256), 256, 0, s>>>(n, rz_new, rz_old, z, p);
+}
+
+void launch_scale_by_inv_sqrt(int64_t n, const double* src, const double* nrm2, double* dst,
+                              hipStream_t s) {
+  k_scale_inv_sqrt<<<nblk(n, 256), 256, 0, s>>>(n, src, nrm2, dst);
+}
+
+void launch_lincomb(int64_t n, int k, const double* const* V, const double* coef, double sign,
+                    const double* add, double* out, hipStream_t s) {
+  VecList L;
+  for (int j = 0; j < 2 * AARMR_MAX_BASIS; ++j) L.v[j] = j < k ? V[j] : nullptr;
+  k_lincomb<<<nblk(n, 256), 256, 0, s>>>(n, k, L, coef, sign, add, out);
+}
+
+void launch_small_spd_solve(int n, int lda, const double* A, const double* b, double* x,
+                            unsigned* bad, hipStream_t s) {
+  k_small_spd_solve<<<1, 64, 0, s>>>(n, lda, A, b, x, bad);
+}
+
+}  // namespace aarmr

@@ -1,0 +1,261 @@
+"""GPU parity of every kernel family and of the full analysis step against
+the CPU FP64 oracle, through the C ABI.  Tolerances: building blocks to
+1e-12 relative (FP64, different summation order); converged solves to the
+1e-6 compliance / displacement / sensitivity bar."""
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import ca as oca
+from oracle import fem, filt, mg, oc, sens, solve
+
+from gpu_util import aos, fixed_tensor, loads_tensor, log, mesh_for, rel, soa, t64
+
+pytestmark = pytest.mark.gpu
+
+SIZES = [(2, 2, 2, 2), (8, 4, 4, 3), (18, 10, 6, 2), (24, 12, 12, 3), (36, 20, 12, 3)]
+
+
+def _density(prob, seed, lo=0.3, hi=1.0):
+    return synth.uniform_iid(prob.nx, prob.ny, prob.nz, lo, hi, seed).ravel()
+
+
+@pytest.mark.parametrize("nx,ny,nz,lev", SIZES)
+def test_operator_apply_matches_assembled(nx, ny, nz, lev):
+    log(f"operator apply {nx}x{ny}x{nz}")
+    prob = synth.cantilever(nx, ny, nz)
+    rho = _density(prob, 11)
+    m = mesh_for(prob, mg_levels=lev)
+    fixed = fixed_tensor(prob, m)
+    m.setup(t64(rho), fixed)
+    v = np.random.default_rng(12).standard_normal(3 * m.n_node)
+    y = torch.zeros(3 * m.n_node, dtype=torch.float64, device="cuda")
+    m.apply(t64(v), y)
+    K = fem.assemble(nx, ny, nz, fem.simp(rho), fem.hex8_ke())
+    A = fem.operator_with_bc(K, fem.fixed_dofs_aos(prob))
+    want = soa(A @ aos(v))
+    assert rel(y.cpu().numpy(), want) < 1e-13
+
+
+def test_operator_apply_is_deterministic():
+    prob = synth.cantilever(24, 12, 12)
+    m = mesh_for(prob)
+    m.setup(t64(_density(prob, 1)), fixed_tensor(prob, m))
+    v = t64(np.random.default_rng(0).standard_normal(3 * m.n_node))
+    y1 = torch.empty_like(v)
+    y2 = torch.empty_like(v)
+    m.apply(v, y1)
+    m.apply(v, y2)
+    assert torch.equal(y1, y2)
+
+
+@pytest.mark.parametrize("nx,ny,nz,lev", [(8, 4, 4, 3), (24, 12, 12, 3), (16, 8, 8, 4)])
+def test_coarse_operators_and_vcycle(nx, ny, nz, lev):
+    log(f"coarse ops / vcycle {nx}x{ny}x{nz} levels={lev}")
+    prob = synth.cantilever(nx, ny, nz)
+    rho = _density(prob, 21)
+    m = mesh_for(prob, mg_levels=lev)
+    m.setup(t64(rho), fixed_tensor(prob, m))
+    K = fem.assemble(nx, ny, nz, fem.simp(rho), fem.hex8_ke())
+    H = mg.Hierarchy(K, fem.fixed_dofs_aos(prob), (nx, ny, nz), lev)
+    rng = np.random.default_rng(22)
+    for l in range(1, lev):
+        nn = (nx // 2 ** l + 1) * (ny // 2 ** l + 1) * (nz // 2 ** l + 1)
+        v = rng.standard_normal(3 * nn)
+        y = torch.zeros(3 * nn, dtype=torch.float64, device="cuda")
+        m.apply(t64(v), y, level=l)
+        want = soa(H.A[l] @ aos(v))
+        assert rel(y.cpu().numpy(), want) < 1e-12, f"level {l}"
+    free = fem.free_mask(K.shape[0], fem.fixed_dofs_aos(prob))
+    r = rng.standard_normal(K.shape[0]) * free
+    z = torch.zeros(K.shape[0], dtype=torch.float64, device="cuda")
+    m.vcycle(t64(soa(r)), z)
+    want = soa(H.vcycle(r, omega=0.6, nu1=1, nu2=1))
+    assert rel(z.cpu().numpy(), want) < 1e-9
+
+
+def test_energy_matches_oracle():
+    prob = synth.cantilever(18, 10, 6)
+    m = mesh_for(prob, mg_levels=2)
+    m.setup(t64(_density(prob, 3)), fixed_tensor(prob, m))
+    u = np.random.default_rng(4).standard_normal(3 * m.n_node)
+    e = torch.zeros(m.n_elem, dtype=torch.float64, device="cuda")
+    m.element_energy(t64(u), e)
+    ua = aos(u)
+    ua[fem.fixed_dofs_aos(prob)] = 0.0
+    want = sens.element_energy(ua, fem.element_dofs(18, 10, 6), fem.hex8_ke())
+    assert rel(e.cpu().numpy(), want) < 1e-13
+
+
+@pytest.mark.parametrize("r", [1.5, 2.0, 2.5])
+@pytest.mark.parametrize("dims", [(6, 4, 2), (18, 10, 6)])
+def test_filter_matches_oracle(r, dims):
+    nx, ny, nz = dims
+    prob = synth.cantilever(nx, ny, nz)
+    m = mesh_for(prob, mg_levels=2, rmin=r)
+    x = np.random.default_rng(5).uniform(0, 1, m.n_elem)
+    H, Hs = filt.filter_matrix(nx, ny, nz, r)
+    out = torch.zeros(m.n_elem, dtype=torch.float64, device="cuda")
+    m.filter(t64(x), out, mode=0)
+    assert rel(out.cpu().numpy(), filt.forward(H, Hs, x)) < 1e-14
+    m.filter(t64(x), out, mode=1)
+    assert rel(out.cpu().numpy(), filt.adjoint(H, Hs, x)) < 1e-14
+
+
+def test_solve_cantilever24_matches_direct():
+    """The 24x12x12 cantilever: design density U[0.3,1] (seed 1), filter
+    r=1.5, 3 levels; u, C and dC/drho against the direct solve."""
+    nx, ny, nz = 24, 12, 12
+    log("solve cantilever24")
+    prob = synth.cantilever(nx, ny, nz)
+    x = synth.uniform_iid(nx, ny, nz, 0.3, 1.0, seed=1).ravel()
+    from paper_2205_00385_amd import aarmr
+
+    m = mesh_for(prob, mg_levels=3, rmin=1.5, cg_rtol=1e-10)
+    fixed = fixed_tensor(prob, m)
+    f = loads_tensor(prob, m)
+    u = torch.zeros_like(f)
+    dc = torch.zeros(m.n_elem, dtype=torch.float64, device="cuda")
+    C, st, code = m.solve(t64(x), f, fixed, u, dc=dc, flags=aarmr.FILTER_INPUT)
+    H, Hs = filt.filter_matrix(nx, ny, nz, 1.5)
+    xphys = filt.forward(H, Hs, x)
+    us, Cs, dcp = sens.analyse(prob, xphys)
+    log(f"  its={st.iterations[0]} rel={st.rel_residual[0]:.2e} C={C[0]:.12g} ref={Cs[0]:.12g}")
+    assert code == aarmr.OK and st.rel_residual[0] <= 1e-10
+    assert abs(C[0] - Cs[0]) <= 1e-6 * abs(Cs[0])
+    assert rel(u.cpu().numpy(), soa(us[0])) <= 1e-6
+    assert rel(dc.cpu().numpy(), filt.adjoint(H, Hs, dcp)) <= 1e-6
+
+
+def test_solve_multi_case_and_warm_start():
+    prob = synth.point_loads_on_face(16, 8, 8, n_case=3, seed=7)
+    from paper_2205_00385_amd import aarmr
+
+    m = mesh_for(prob, mg_levels=3, cg_rtol=1e-10, n_rhs_max=4)
+    rho = synth.smoothed_field(16, 8, 8, 2.0, 1e-3, 1.0, seed=8).ravel()
+    fixed = fixed_tensor(prob, m)
+    f = loads_tensor(prob, m)
+    u = torch.zeros_like(f)
+    dc = torch.zeros(m.n_elem, dtype=torch.float64, device="cuda")
+    C, st, code = m.solve(t64(rho), f, fixed, u, dc=dc)
+    us, Cs, dcs = sens.analyse(prob, rho)
+    n3 = 3 * m.n_node
+    for l in range(3):
+        assert abs(C[l] - Cs[l]) <= 1e-6 * abs(Cs[l])
+        assert rel(u[l * n3:(l + 1) * n3].cpu().numpy(), soa(us[l])) <= 1e-6
+    assert rel(dc.cpu().numpy(), dcs) <= 1e-6
+    # warm start from the converged solution: no iteration needed
+    C2, st2, _ = m.solve(t64(rho), f, fixed, u, flags=aarmr.WARM_START)
+    assert all(st2.iterations[l] <= 1 for l in range(3))
+
+
+def test_solve_bridge_high_contrast():
+    """Simply supported beam (four bottom corners fixed, centre load) on a
+    thresholded field {1e-3, 1}: MGCG must still reach the oracle."""
+    prob = synth.bridge(16, 8, 8)
+    m = mesh_for(prob, mg_levels=3, cg_rtol=1e-10)
+    rho = synth.thresholded_field(16, 8, 8, 2.0, 1e-3, 1.0, seed=9).ravel()
+    f = loads_tensor(prob, m)
+    u = torch.zeros_like(f)
+    C, st, code = m.solve(t64(rho), f, fixed_tensor(prob, m), u)
+    us, Cs, _ = sens.analyse(prob, rho)
+    log(f"  bridge its={st.iterations[0]} C={C[0]:.10g} ref={Cs[0]:.10g}")
+    assert abs(C[0] - Cs[0]) <= 1e-6 * abs(Cs[0])
+    assert rel(u.cpu().numpy(), soa(us[0])) <= 1e-6
+
+
+def test_invalid_inputs_rejected():
+    from paper_2205_00385_amd import aarmr
+
+    prob = synth.cantilever(8, 4, 4)
+    m = mesh_for(prob, mg_levels=2)
+    fixed = fixed_tensor(prob, m)
+    f = loads_tensor(prob, m)
+    u = torch.zeros_like(f)
+    bad = t64(np.full(m.n_elem, 1.5))
+    with pytest.raises(aarmr.AarmrError) as ei:
+        m.solve(bad, f, fixed, u)
+    assert ei.value.code == aarmr.E_INVALID
+    badfix = torch.tensor([3 * m.n_node + 5], dtype=torch.int64, device="cuda")
+    with pytest.raises(aarmr.AarmrError) as ei:
+        m.solve(t64(np.full(m.n_elem, 0.5)), f, badfix, u)
+    assert ei.value.code == aarmr.E_INVALID
+    with pytest.raises(aarmr.AarmrError) as ei:
+        m.ca_update(t64(np.full(m.n_elem, 0.5)), f, fixed, u)
+    assert ei.value.code == aarmr.E_STATE
+
+
+def test_not_converged_reports_and_writes():
+    from paper_2205_00385_amd import aarmr
+
+    prob = synth.cantilever(16, 8, 8)
+    m = mesh_for(prob, mg_levels=3, cg_maxit=2)
+    f = loads_tensor(prob, m)
+    u = torch.zeros_like(f)
+    C, st, code = m.solve(t64(np.full(m.n_elem, 0.7)), f, fixed_tensor(prob, m), u)
+    assert code == aarmr.E_NOT_CONVERGED
+    assert st.iterations[0] == 2 and st.rel_residual[0] > 1e-8
+    assert torch.isfinite(u).all() and float(u.abs().max()) > 0
+
+
+def test_ca_sequence_matches_oracle_algorithm1():
+    """Algorithm 1 on both sides over the same density sequence: N_on exact
+    (oracle) / converged MGCG (GPU) cycles build the PARM, then CA cycles.
+    The accept/reject path, u, C and dc must agree."""
+    from paper_2205_00385_amd import aarmr
+
+    prob = synth.cantilever(16, 8, 8)
+    Ns, Nm, N_on, tol = 2, 3, 3, 0.05
+    alg = oca.AARMR(prob, Ns=Ns, Nm=Nm, N_on=N_on, eps_tol=tol)
+    m = mesh_for(prob, mg_levels=3, cg_rtol=1e-11, Ns=Ns, Nm=Nm, ca_tol=tol)
+    fixed = fixed_tensor(prob, m)
+    f = loads_tensor(prob, m)
+    u = torch.zeros_like(f)
+    dc = torch.zeros(m.n_elem, dtype=torch.float64, device="cuda")
+    base = synth.smoothed_field(16, 8, 8, 2.0, 0.2, 1.0, seed=30).ravel()
+    d = synth.smoothed_field(16, 8, 8, 3.0, -1.0, 1.0, seed=32).ravel()
+    edof = fem.element_dofs(16, 8, 8)
+    KE = fem.hex8_ke()
+    paths = []
+    for loop in range(1, 10):
+        # a smooth drift whose step grows: both CA acceptance and fallback occur
+        rho = np.clip(base + 0.02 * loop * d + 4e-4 * loop ** 2 * np.roll(d, 7), 0.05, 1.0)
+        (u_ref, path, eps_ref, rank_ref), = alg.cycle(loop, rho)
+        if loop <= N_on:
+            flags = aarmr.WARM_START | (aarmr.RECORD_PARM if loop > N_on - Ns else 0)
+            C, st, _ = m.solve(t64(rho), f, fixed, u, dc=dc, flags=flags)
+            gpath = "mgcg"
+        else:
+            C, st, _ = m.ca_update(t64(rho), f, fixed, u, dc=dc)
+            gpath = "ca" if st.accepted[0] else "fallback"
+            log(f"  loop {loop}: eps gpu={st.eps[0]:.6e} oracle={eps_ref:.6e} rank {st.rank[0]}/{rank_ref}")
+            if abs(st.eps[0] - tol) > 1e-6 * tol:
+                assert gpath == path
+            assert abs(st.eps[0] - eps_ref) <= 1e-6 * max(eps_ref, 1e-12) + 1e-9
+        paths.append(gpath)
+        assert rel(u.cpu().numpy(), soa(u_ref)) <= 1e-6
+        Cref = float(alg.f[0] @ u_ref)
+        assert abs(C[0] - Cref) <= 1e-6 * abs(Cref)
+        dref = sens.dc_drho_phys(rho, sens.element_energy(u_ref, edof, KE))
+        assert rel(dc.cpu().numpy(), dref) <= 1e-6
+    log(f"  paths {paths}")
+    assert "ca" in paths and "fallback" in paths
+
+
+def test_oc_update_matches_oracle():
+    nx, ny, nz = 12, 8, 6
+    prob = synth.cantilever(nx, ny, nz)
+    m = mesh_for(prob, mg_levels=2, rmin=2.0)
+    H, Hs = filt.filter_matrix(nx, ny, nz, 2.0)
+    rng = np.random.default_rng(41)
+    x = rng.uniform(0.1, 0.9, m.n_elem)
+    dc = -rng.uniform(0.01, 3.0, m.n_elem)
+    dv = filt.adjoint(H, Hs, np.ones(m.n_elem))
+    xn, xp, lam = oc.oc_update(x, dc, dv, H, Hs, 0.3)
+    gx = torch.zeros(m.n_elem, dtype=torch.float64, device="cuda")
+    gp = torch.zeros_like(gx)
+    m.oc_update(t64(x), t64(dc), t64(dv), 0.3, 0.2, gx, gp)
+    assert rel(gx.cpu().numpy(), xn) < 1e-9
+    assert rel(gp.cpu().numpy(), xp) < 1e-9
