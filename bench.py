@@ -1,0 +1,279 @@
+#!/usr/bin/env python3
+"""Benchmark of the AARMR analysis step on one MI355X.
+
+Workload (one "step"): the complete 50-cycle topology-optimisation run of the
+96x48x48 hex8 cantilever (clamped x=0 face, unit load spread over the bottom
+edge of the x=96 face), volume fraction 0.3, SIMP p=3, density filter r=2,
+OC update, starting from a uniform design of 0.3.  Analyses follow
+Algorithm 1: MGCG (4 grid levels, damped Jacobi, rel. residual 1e-8) for
+cycles 1..20 while the last Ns=2 solutions build the PARM, then the
+combined-approximation reduced model (Nm=6) with the eq. (29) criterion
+eps < 1e-3 and the MGCG fallback.  Every step starts from the same state, so
+steps are identical work.
+
+Printed: one JSON line.  ``value`` is analyses (design-cycle equilibrium
+solves with compliance and sensitivities) per second over the timed steps.
+``roofline`` is the fine-grid element-by-element K.v kernel, timed with HIP
+events on the library's stream; ``cpu_baseline`` is the CPU FP64 oracle on a
+bounded sample of the workload.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "EbE K·v GDOF/s; solves/s at 1e-6 rel. compliance; p50/p99 latency vs plain"
+HBM_PEAK_GBS = 8000.0
+
+NX, NY, NZ = 96, 48, 48
+CYCLES, N_ON, NS, NM = 50, 20, 2, 6
+VOLFRAC, RMIN, MOVE, CA_TOL = 0.3, 2.0, 0.2, 1e-3
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-large", action="store_true", help="skip the 256x128x128 K.v roofline")
+    ap.add_argument("--plain", action="store_true", help="also time plain MGCG every cycle")
+    ap.add_argument("--kv-launches", type=int, default=200)
+    return ap.parse_args()
+
+
+def make_loop_state(torch, aarmr, synth):
+    prob = synth.cantilever(NX, NY, NZ)
+    p = aarmr.default_params(nx=NX, ny=NY, nz=NZ, rmin=RMIN, mg_levels=4, cg_rtol=1e-8,
+                             cg_maxit=2000, Ns=NS, Nm=NM, ca_tol=CA_TOL)
+    mesh = aarmr.Mesh(p)
+    dev = torch.device("cuda")
+    fixed = torch.tensor(aarmr.fixed_dofs_soa(prob, mesh.n_node), dtype=torch.int64, device=dev)
+    f = torch.tensor(aarmr.loads_soa(prob, mesh.n_node)[0], dtype=torch.float64, device=dev)
+    ones = torch.ones(mesh.n_elem, dtype=torch.float64, device=dev)
+    dv = torch.empty_like(ones)
+    mesh.filter(ones, dv, mode=1)  # d(volume)/d(design) through eq. (33)
+    return mesh, fixed, f, dv
+
+
+def run_loop(torch, aarmr, mesh, fixed, f, dv, plain=False, record=None):
+    """One full optimisation run; returns per-cycle wall times (ms) and paths."""
+    dev = f.device
+    x = torch.full((mesh.n_elem,), VOLFRAC, dtype=torch.float64, device=dev)
+    xn = torch.empty_like(x)
+    rp = torch.empty_like(x)
+    u = torch.zeros_like(f)
+    dc = torch.empty_like(x)
+    lat, paths, comp = [], [], []
+    fl = aarmr.FILTER_INPUT
+    for loop in range(1, CYCLES + 1):
+        t0 = time.perf_counter()
+        if plain or loop <= N_ON:
+            flags = fl | aarmr.WARM_START
+            if not plain and loop > N_ON - NS:
+                flags |= aarmr.RECORD_PARM
+            C, st, code = mesh.solve(x, f, fixed, u, dc=dc, flags=flags)
+            paths.append("mgcg")
+            if record is not None:
+                record.append(("mgcg", st.iterations[0], st.fine_sweeps))
+        else:
+            C, st, code = mesh.ca_update(x, f, fixed, u, dc=dc, flags=fl)
+            paths.append("ca" if st.accepted[0] else "fallback")
+            if record is not None:
+                record.append((paths[-1], st.mgcg_iterations[0], st.fine_sweeps, st.eps[0]))
+        t1 = time.perf_counter()
+        mesh.oc_update(x, dc, dv, VOLFRAC, MOVE, xn, rp)
+        x, xn = xn, x
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        lat.append(((t1 - t0) * 1e3, (t2 - t0) * 1e3))
+        comp.append(C[0])
+    return lat, paths, comp
+
+
+def kv_event_timing(torch, mesh, n_launch, sets):
+    """Average duration of the fine-grid K.v kernel, HIP events on the
+    stream the library launches on (torch's current stream).  `sets` is a
+    list of (mesh, v, y) rotated between launches."""
+    s = torch.cuda.current_stream()
+    for (m, v, y) in sets:
+        m.apply(v, y)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for i in range(n_launch):
+        m, v, y = sets[i % len(sets)]
+        m.apply(v, y)
+    e1.record(s)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / n_launch  # ms per launch
+
+
+def ebe_bytes(nx, ny, nz):
+    """Algorithmic HBM bytes of one FP64 K.v sweep: read v and write y
+    (3 x 8 B per node each), the node's fixed-DOF mask byte, and one
+    modulus (8 B) per element."""
+    nn = (nx + 1) * (ny + 1) * (nz + 1)
+    ne = nx * ny * nz
+    return 49 * nn + 8 * ne, nn
+
+
+def cpu_baseline():
+    """The oracle's analysis (assembly, banded Cholesky, compliance,
+    sensitivities, filter and its adjoint) on the 48x24x24 sub-grid of the
+    workload: the full 96x48x48 direct solve needs ~41 GB and ~3.7e13 flop."""
+    import numpy as np
+
+    import synth
+    from oracle import filt, sens
+
+    nx, ny, nz = NX // 2, NY // 2, NZ // 2
+    prob = synth.cantilever(nx, ny, nz)
+    reps = 3
+    t0 = time.perf_counter()
+    for r in range(reps):
+        x = np.full(prob.n_elem, VOLFRAC) + 0.01 * r
+        H, Hs = filt.filter_matrix(nx, ny, nz, RMIN)
+        xp = filt.forward(H, Hs, x)
+        _, Cs, dcp = sens.analyse(prob, xp)
+        filt.adjoint(H, Hs, dcp)
+    dt = time.perf_counter() - t0
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return {"value": round(reps / dt, 4), "unit": "solves/s", "cores": cores, "kind": "oracle",
+            "sample": f"{reps} analyses of the {nx}x{ny}x{nz} sub-grid (1/8 of the elements): "
+                      f"filter, assembly, banded Cholesky, C, dC/drho; {dt:.1f} s total"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2205_00385_amd import aarmr
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(2)
+    torch.cuda.set_device(0)
+    mesh, fixed, f, dv = make_loop_state(torch, aarmr, synth)
+    print(f"[bench] mesh {NX}x{NY}x{NZ}, workspace {mesh.workspace_bytes / 2**20:.0f} MiB",
+          file=sys.stderr, flush=True)
+    for w in range(args.warmup):
+        run_loop(torch, aarmr, mesh, fixed, f, dv)
+        print(f"[bench] warmup step {w + 1} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    lat_all, paths_all, comp_last = [], [], None
+    record = []
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        lat, paths, comp = run_loop(torch, aarmr, mesh, fixed, f, dv,
+                                    record=record if k == 0 else None)
+        lat_all += lat
+        paths_all += paths
+        comp_last = comp
+        print(f"[bench] step {k + 1}/{args.steps} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    T = time.perf_counter() - t0
+    n_analyses = CYCLES * args.steps
+    ms_per_step = T * 1e3 / args.steps
+
+    # K.v roofline at the loop size (design of the last cycle is set up)
+    dev = torch.device("cuda")
+    n3 = 3 * mesh.n_node
+    sets = [(mesh, torch.randn(n3, dtype=torch.float64, device=dev),
+             torch.empty(n3, dtype=torch.float64, device=dev)) for _ in range(3)]
+    ms_kv = kv_event_timing(torch, mesh, args.kv_launches, sets)
+    bytes_kv, nn = ebe_bytes(NX, NY, NZ)
+    gbs = bytes_kv / (ms_kv * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "k_ebe (fine-grid K.v, FP64)", "grid": f"{NX}x{NY}x{NZ}",
+                "ms_per_launch": round(ms_kv, 5), "bytes_per_launch": bytes_kv,
+                "gdof_s": round(3 * nn / (ms_kv * 1e-3) / 1e9, 2)}
+    extra = {}
+    if not args.no_large:
+        L = (256, 128, 128)
+        prob = synth.cantilever(*L)
+        big = []
+        for seed in (3, 4):
+            p = aarmr.default_params(nx=L[0], ny=L[1], nz=L[2], mg_levels=6)
+            m = aarmr.Mesh(p)
+            rho = synth.smoothed_field(*L, 8.0, 1e-3, 1.0, seed=seed).ravel()
+            fx = torch.tensor(aarmr.fixed_dofs_soa(prob, m.n_node), dtype=torch.int64, device=dev)
+            m.setup(torch.tensor(rho, dtype=torch.float64, device=dev), fx)
+            nb = 3 * m.n_node
+            big.append((m, torch.randn(nb, dtype=torch.float64, device=dev),
+                        torch.empty(nb, dtype=torch.float64, device=dev)))
+        ms_big = kv_event_timing(torch, None, args.kv_launches, big)
+        bb, nnb = ebe_bytes(*L)
+        gb = bb / (ms_big * 1e-3) / 1e9
+        extra["roofline_kv_256x128x128"] = {
+            "bound": "hbm", "achieved": round(gb, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(gb / HBM_PEAK_GBS, 4), "traffic": None,
+            "ms_per_launch": round(ms_big, 5), "bytes_per_launch": bb,
+            "gdof_s": round(3 * nnb / (ms_big * 1e-3) / 1e9, 2),
+            "note": "two independent meshes (v, y, E, mask) alternate so the working set "
+                    "exceeds the 256 MB Infinity Cache"}
+        del big
+
+    lat_solve = np.array([a for a, _ in lat_all])
+    lat_cycle = np.array([b for _, b in lat_all])
+    out = {
+        "metric": METRIC,
+        "value": round(n_analyses / T, 3),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "AARMR topology-optimisation loop, 96x48x48 hex8 cantilever, "
+                               "50 cycles (N_on=20, Ns=2, Nm=6, eps_tol=1e-3), MGCG 4 levels "
+                               "rtol 1e-8, filter r=2, OC volfrac 0.3",
+                   "elements": NX * NY * NZ, "dofs": 3 * mesh.n_node,
+                   "parallelism": "single GPU"},
+        "latency_ms": {"analysis_p50": round(float(np.percentile(lat_solve, 50)), 3),
+                       "analysis_p99": round(float(np.percentile(lat_solve, 99)), 3),
+                       "cycle_p50": round(float(np.percentile(lat_cycle, 50)), 3),
+                       "cycle_p99": round(float(np.percentile(lat_cycle, 99)), 3)},
+        "paths": {p: paths_all.count(p) // args.steps for p in ("mgcg", "ca", "fallback")},
+        "final_compliance": comp_last[-1],
+        "roofline": roofline,
+    }
+    out.update(extra)
+    if args.plain:
+        mesh2, fixed2, f2, dv2 = mesh, fixed, f, dv
+        tp = time.perf_counter()
+        latp, _, compp = run_loop(torch, aarmr, mesh2, fixed2, f2, dv2, plain=True)
+        Tp = time.perf_counter() - tp
+        out["plain_mgcg"] = {"solves_s": round(CYCLES / Tp, 3),
+                             "analysis_p50_ms": round(float(np.median([a for a, _ in latp])), 3),
+                             "final_compliance": compp[-1],
+                             "aarmr_speedup_eq35": round(
+                                 sum(a for a, _ in latp) /
+                                 (sum(a for a, _ in lat_all) / args.steps), 3)}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+    if os.environ.get("AARMR_BENCH_TRACE"):
+        print(json.dumps({"trace_first_step": record}), file=sys.stderr)
+
+
+if __name__ == "__main__":
+    main()
