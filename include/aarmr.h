@@ -127,7 +127,7 @@ void aarmr_default_params(aarmr_params* p);
  * Errors: AARMR_E_INVALID for non-positive sizes, sizes not divisible by
  * 2^(mg_levels-1), mg_levels outside [2, AARMR_MAX_LEVELS], Ns or Nm outside
  * [1, AARMR_MAX_BASIS], n_rhs_max outside [1, AARMR_MAX_RHS], nu outside
- * (-1, 0.5), or a coarsest grid above 6000 DOFs. */
+ * (-1, 0.5), a coarsest grid above 6000 DOFs, or 3 * n_node >= 2^31. */
 int aarmr_mesh_create(const aarmr_params* p, aarmr_mesh** out);
 
 /* Release the mesh (host memory and its pinned staging buffer).  The bound

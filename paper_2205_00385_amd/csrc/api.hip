@@ -4,6 +4,7 @@
 // caller's stream and reads back the few scalars that steer control flow
 // (CG convergence, Gram-Schmidt rank decisions, the eq. (29) accept/reject
 // branch).  Every arithmetic step of the method runs on the GPU.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -37,7 +38,7 @@ int fail(int code, const std::string& msg) {
   } while (0)
 
 struct LevelBuf {
-  double* Ke = nullptr;    // levels >= 1: [ne][24][24] Galerkin element matrices
+  double* Ke = nullptr;    // levels >= 1: packed Galerkin element matrices [300][ne]
   double* dinv = nullptr;  // [3][nn] inverse Jacobi diagonal
   double* b = nullptr;     // levels >= 1: right-hand side
   double* x = nullptr;     // levels >= 1: correction
@@ -73,10 +74,13 @@ struct aarmr_mesh {
   int nlev = 0;
   int nc = 0;                 // coarsest dense order
   double KE[576];
+  WalshConsts wk;             // reflection-blocked form of KE
+  double Mc[8 * kSymEntries]; // P_c^T KE P_c per child position, packed
   // workspace views
   char* ws = nullptr;
   int64_t ws_bytes = 0;
   double* KEd = nullptr;
+  double* Mcd = nullptr;      // P_c^T KE P_c of the 8 children, packed
   double* E = nullptr;
   double* E_prev = nullptr;
   double* dE = nullptr;
@@ -95,7 +99,6 @@ struct aarmr_mesh {
   double* KR = nullptr;    // [Nm][3nn]
   double* scal = nullptr;
   double* partial = nullptr;
-  unsigned* ticket = nullptr;
   unsigned* flags = nullptr;
   // host state
   int phi_count[AARMR_MAX_RHS] = {};
@@ -148,6 +151,66 @@ void hex8_stiffness(double nu, double* KE) {
       }
 }
 
+// Constants of the reflection-blocked form B = W KE W^T / 64 and a check
+// that walsh_blocks() (the exact formula the kernels evaluate) reproduces
+// every column of B.  Returns false if KE lacks that structure.
+bool walsh_form(const double* KE, WalshConsts* K) {
+  auto chi = [](int k, int a) { return (__builtin_popcount(k & a) & 1) ? -1.0 : 1.0; };
+  static double B[24][24];
+  double bmax = 0.0;
+  for (int k = 0; k < 8; ++k)
+    for (int c = 0; c < 3; ++c)
+      for (int k2 = 0; k2 < 8; ++k2)
+        for (int c2 = 0; c2 < 3; ++c2) {
+          double s = 0.0;
+          for (int a = 0; a < 8; ++a)
+            for (int b = 0; b < 8; ++b) s += chi(k, a) * KE[(3 * a + c) * 24 + 3 * b + c2] * chi(k2, b);
+          B[3 * k + c][3 * k2 + c2] = s / 64.0;
+          bmax = std::max(bmax, std::fabs(s / 64.0));
+        }
+  auto at = [&](int k, int c, int k2, int c2) { return B[3 * k + c][3 * k2 + c2]; };
+  K->a1mb1 = at(1, 0, 1, 0) - at(1, 0, 2, 1);
+  K->b1 = at(1, 0, 2, 1);
+  K->g = at(1, 1, 2, 0);
+  K->d = at(3, 0, 3, 0);
+  K->e = at(3, 0, 6, 2);
+  K->a4mb4 = at(3, 2, 3, 2) - at(3, 2, 5, 1);
+  K->b4 = at(3, 2, 5, 1);
+  K->h = at(7, 0, 7, 0);
+  double err = 0.0;
+  for (int col = 0; col < 24; ++col) {
+    double hv[8][3] = {}, z[8][3];
+    hv[col / 3][col % 3] = 1.0;
+    walsh_blocks<double>(*K, 1.0, hv, z);
+    for (int row = 0; row < 24; ++row)
+      err = std::max(err, std::fabs(z[row / 3][row % 3] - B[row][col]));
+  }
+  return err <= 1e-12 * bmax;
+}
+
+// M_c = P_c^T KE P_c for the 8 child positions c of a 2:1 refined parent,
+// P_c the trilinear map from the parent's corners to child c's corners
+// (per component), packed with sym_index.
+void child_galerkin(const double* KE, double* Mc) {
+  auto phi = [](int pos, int A) { return pos == 1 ? 0.5 : ((pos >> 1) == A ? 1.0 : 0.0); };
+  for (int c = 0; c < 8; ++c) {
+    const int dx = c & 1, dy = (c >> 1) & 1, dz = c >> 2;
+    double P[8][8];  // P[b][A]
+    for (int b = 0; b < 8; ++b)
+      for (int A = 0; A < 8; ++A)
+        P[b][A] = phi(dx + (b & 1), A & 1) * phi(dy + ((b >> 1) & 1), (A >> 1) & 1) *
+                  phi(dz + (b >> 2), A >> 2);
+    for (int I = 0; I < 24; ++I)
+      for (int J = I; J < 24; ++J) {
+        double acc = 0.0;
+        for (int b = 0; b < 8; ++b)
+          for (int b2 = 0; b2 < 8; ++b2)
+            acc += P[b][I / 3] * KE[(3 * b + I % 3) * 24 + 3 * b2 + J % 3] * P[b2][J / 3];
+        Mc[c * kSymEntries + sym_index(I, J)] = acc;
+      }
+  }
+}
+
 // Assign workspace views; with base == nullptr only computes the size.
 int64_t layout(aarmr_mesh* m, char* base) {
   int64_t off = 0;
@@ -160,6 +223,7 @@ int64_t layout(aarmr_mesh* m, char* base) {
   const int64_t n3 = 3 * g.nn;
   const int64_t d8 = sizeof(double);
   m->KEd = (double*)take(576 * d8);
+  m->Mcd = (double*)take(8 * kSymEntries * d8);
   m->E = (double*)take(g.ne * d8);
   m->E_prev = (double*)take(g.ne * d8);
   m->dE = (double*)take(g.ne * d8);
@@ -181,7 +245,7 @@ int64_t layout(aarmr_mesh* m, char* base) {
   for (int l = 1; l < m->nlev; ++l) {
     const Grid& G = m->lg[l];
     LevelBuf& L = m->lv[l];
-    L.Ke = (double*)take(G.ne * 576 * d8);
+    L.Ke = (double*)take(G.ne * kSymEntries * d8);
     L.dinv = (double*)take(3 * G.nn * d8);
     L.b = (double*)take(3 * G.nn * d8);
     L.x = (double*)take(3 * G.nn * d8);
@@ -196,7 +260,6 @@ int64_t layout(aarmr_mesh* m, char* base) {
   m->KR = (double*)take((int64_t)m->p.Nm * n3 * d8);
   m->scal = (double*)take(SC_TOTAL * d8);
   m->partial = (double*)take((int64_t)kRedSlots * kRedBlocks * d8);
-  m->ticket = (unsigned*)take(64);
   m->flags = (unsigned*)take(64);
   return off;
 }
@@ -209,7 +272,7 @@ int need_ws(const aarmr_mesh* m) {
   return AARMR_OK;
 }
 
-RedScratch red(aarmr_mesh* m) { return RedScratch{m->partial, m->ticket}; }
+RedScratch red(aarmr_mesh* m) { return RedScratch{m->partial}; }
 
 // Launch one multi-dot with up to kRedSlots products.
 int dots(aarmr_mesh* m, int k, const double* const* a, const double* const* b, double* const* out,
@@ -254,7 +317,7 @@ int read_flags(aarmr_mesh* m, unsigned* out, hipStream_t s) {
 // y = A v on level l.
 int apply(aarmr_mesh* m, int l, const double* v, double* y, hipStream_t s) {
   if (l == 0) {
-    launch_ebe_fine(m->lg[0], m->KEd, m->E, m->mask, v, y, 0, s);
+    launch_ebe(m->lg[0], m->wk, m->E, m->mask, v, y, 0, s);
     ++m->sweeps;
   } else {
     launch_apply_elemmat(m->lg[l], m->lv[l].Ke, v, y, s);
@@ -317,7 +380,7 @@ int setup(aarmr_mesh* m, const double* rho, const int64_t* fixed, int64_t nfixed
   KCHECK();
   for (int l = 1; l < m->nlev; ++l) {
     if (l == 1)
-      launch_galerkin_from_fine(m->lg[1], m->KEd, m->E, m->mask, m->lv[1].Ke, s);
+      launch_galerkin_from_fine(m->lg[1], m->KEd, m->Mcd, m->E, m->mask, m->lv[1].Ke, s);
     else
       launch_galerkin_from_coarse(m->lg[l], m->lv[l - 1].Ke, m->lv[l].Ke, s);
     KCHECK();
@@ -434,7 +497,7 @@ int post_case(aarmr_mesh* m, int l, const double* rho_phys, const double* ul, do
     compliance[l] = h;
   }
   if (want_dc) {
-    launch_energy(g, m->KEd, m->mask, ul, m->ework, s);
+    launch_energy_walsh(g, m->wk, m->mask, ul, m->ework, s);
     KCHECK();
     launch_dc_accum(g.ne, rho_phys, m->ework, m->p.E0, m->p.Emin, m->p.penal, m->dc_tmp, l == 0,
                     s);
@@ -506,6 +569,8 @@ int aarmr_mesh_create(const aarmr_params* p, aarmr_mesh** out) {
     return fail(AARMR_E_INVALID, "unknown precision");
   if (p->nu_pre < 0 || p->nu_post < 0 || !(p->omega > 0.0))
     return fail(AARMR_E_INVALID, "bad smoother parameters");
+  if (3 * (int64_t)(p->nx + 1) * (p->ny + 1) * (p->nz + 1) >= (int64_t(1) << 31))
+    return fail(AARMR_E_INVALID, "grid too large: 3 * n_node must stay below 2^31");
   aarmr_mesh* m = new aarmr_mesh();
   m->p = *p;
   m->nlev = p->mg_levels;
@@ -516,6 +581,11 @@ int aarmr_mesh_create(const aarmr_params* p, aarmr_mesh** out) {
     return fail(AARMR_E_INVALID, "coarsest grid above 6000 DOFs: use more levels");
   }
   hex8_stiffness(p->nu, m->KE);  // unit modulus; E0 enters through SIMP
+  child_galerkin(m->KE, m->Mc);
+  if (!walsh_form(m->KE, &m->wk)) {
+    delete m;
+    return fail(AARMR_E_INVALID, "element stiffness lacks the reflection-blocked structure");
+  }
   *out = m;
   return AARMR_OK;
 }
@@ -544,7 +614,7 @@ int aarmr_bind_workspace(aarmr_mesh* m, void* dev_ptr, int64_t bytes, void* stre
   layout(m, m->ws);
   hipStream_t s = S(stream);
   HIP_TRY(hipMemcpyAsync(m->KEd, m->KE, 576 * sizeof(double), hipMemcpyHostToDevice, s));
-  HIP_TRY(hipMemsetAsync(m->ticket, 0, 64, s));
+  HIP_TRY(hipMemcpyAsync(m->Mcd, m->Mc, 8 * kSymEntries * sizeof(double), hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemsetAsync(m->flags, 0, 64, s));
   HIP_TRY(hipMemsetAsync(m->mask, 0, (m->lg[0].nn + 3) / 4 * 4, s));
   if (m->p.rmin > 0.0) {
@@ -584,7 +654,7 @@ int aarmr_vcycle(aarmr_mesh* m, const double* r, double* z, void* stream) {
 int aarmr_element_energy(aarmr_mesh* m, const double* u, double* energy, void* stream) {
   TRY(need_ws(m));
   if (!u || !energy) return fail(AARMR_E_INVALID, "null argument");
-  launch_energy(m->lg[0], m->KEd, m->mask, u, energy, S(stream));
+  launch_energy_walsh(m->lg[0], m->wk, m->mask, u, energy, S(stream));
   KCHECK();
   return AARMR_OK;
 }
@@ -694,7 +764,7 @@ int aarmr_ca_update(aarmr_mesh* m, const double* rho, const double* f, int32_t n
     KCHECK();
     // eq. (15): K_Phi = Phi^T K0 Phi, K0 = K(previous design)
     for (int j = 0; j < Ns; ++j) {
-      launch_ebe_fine(g, m->KEd, m->E_prev, m->mask, PhiL + j * n3, m->t0, 0, s);
+      launch_ebe(g, m->wk, m->E_prev, m->mask, PhiL + j * n3, m->t0, 0, s);
       ++m->sweeps;
       KCHECK();
       std::vector<const double*> a(Ns), b(Ns);
@@ -710,7 +780,7 @@ int aarmr_ca_update(aarmr_mesh* m, const double* rho, const double* f, int32_t n
     HIP_TRY(hipMemcpyAsync(m->R, ul, n3 * sizeof(double), hipMemcpyDeviceToDevice, s));
     bool ca_ok = true;
     for (int i = 1; i < Nm; ++i) {
-      launch_ebe_fine(g, m->KEd, m->dE, m->mask, m->R + (i - 1) * n3, m->t0, 1, s);
+      launch_ebe(g, m->wk, m->dE, m->mask, m->R + (i - 1) * n3, m->t0, 1, s);
       ++m->sweeps;
       KCHECK();
       std::vector<const double*> a(Ns), b(Ns);
@@ -768,7 +838,7 @@ int aarmr_ca_update(aarmr_mesh* m, const double* rho, const double* f, int32_t n
     if (kept > 0) {
       // eqs. (22)-(25): K_R~ = R~^T K R~, f_R~ = R~^T f, y, u~ = R~ y
       for (int j = 0; j < kept; ++j) {
-        launch_ebe_fine(g, m->KEd, m->E, m->mask, m->R + j * n3, m->KR + j * n3, 0, s);
+        launch_ebe(g, m->wk, m->E, m->mask, m->R + j * n3, m->KR + j * n3, 0, s);
         ++m->sweeps;
         KCHECK();
       }

@@ -11,6 +11,7 @@
 #include <string>
 
 #include "aarmr.h"
+#include "walsh.hpp"
 
 namespace aarmr {
 
@@ -32,11 +33,9 @@ inline Grid make_grid(int nx, int ny, int nz) {
   return g;
 }
 
-// Reduction scratch: per-slot partials, a ticket counter for the
-// last-block-finishes pattern, and the output scalars.
+// Reduction scratch: per-slot block partials.
 struct RedScratch {
   double* partial;     // [kRedSlots][kRedBlocks]
-  unsigned* ticket;    // [1]
 };
 
 struct DotSet {
@@ -47,12 +46,14 @@ struct DotSet {
   int64_t n;           // length
 };
 
-// ---- fine-level operator (element-by-element) ---------------------------
+// ---- fine-level operator (element-by-element, reflection-blocked) --------
 // mode 0: y = A v with identity rows on fixed DOFs; mode 1: y = Df K Df v.
-void launch_ebe_fine(const Grid& g, const double* KE, const double* E, const uint8_t* mask,
-                     const double* v, double* y, int mode, hipStream_t s);
-void launch_ebe_fine_f32(const Grid& g, const float* ke32, const float* E, const uint8_t* mask,
-                         const float* v, float* y, hipStream_t s);
+void launch_ebe(const Grid& g, const WalshConsts& K, const double* E, const uint8_t* mask,
+                const double* v, double* y, int mode, hipStream_t s);
+void launch_ebe_f32(const Grid& g, const WalshConsts& K, const float* E, const uint8_t* mask,
+                    const float* v, float* y, int mode, hipStream_t s);
+void launch_energy_walsh(const Grid& g, const WalshConsts& K, const uint8_t* mask,
+                         const double* u, double* energy, hipStream_t s);
 void launch_simp(int64_t ne, const double* rho, double E0, double Emin, double p, double* E,
                  float* E32, unsigned* bad, hipStream_t s);
 void launch_diff(int64_t n, const double* a, const double* b, double* out, hipStream_t s);
@@ -60,14 +61,20 @@ void launch_build_mask(int64_t nn, const int64_t* fixed, int64_t nfixed, uint8_t
                        unsigned* bad, hipStream_t s);
 void launch_diag_fine(const Grid& g, const double* KE, const double* E, const uint8_t* mask,
                       double* dinv, float* dinv32, hipStream_t s);
-void launch_energy(const Grid& g, const double* KE, const uint8_t* mask, const double* u,
-                   double* energy, hipStream_t s);
 void launch_dc_accum(int64_t ne, const double* rho, const double* energy, double E0, double Emin,
                      double p, double* dc, int first, hipStream_t s);
 
 // ---- multigrid ------------------------------------------------------------
-void launch_galerkin_from_fine(const Grid& coarse, const double* KE, const double* E,
-                               const uint8_t* mask, double* Kc, hipStream_t s);
+// Coarse element matrices are symmetric 24x24 and stored packed (upper
+// triangle, row-major: 300 entries) and entry-major, Ke[sym_index(r,c) *
+// n_elem + e], so that threads on consecutive elements read consecutive
+// addresses.
+constexpr int kSymEntries = 300;
+__host__ __device__ constexpr int sym_index(int r, int c) {
+  return r <= c ? r * 24 - (r * (r - 1)) / 2 + (c - r) : c * 24 - (c * (c - 1)) / 2 + (r - c);
+}
+void launch_galerkin_from_fine(const Grid& coarse, const double* KE, const double* Mc,
+                               const double* E, const uint8_t* mask, double* Kc, hipStream_t s);
 void launch_galerkin_from_coarse(const Grid& coarse, const double* Kf, double* Kc, hipStream_t s);
 void launch_apply_elemmat(const Grid& g, const double* Ke, const double* v, double* y,
                           hipStream_t s);
@@ -101,7 +108,6 @@ void launch_lincomb(int64_t n, int k, const double* const* V, const double* coef
                     const double* add, double* out, hipStream_t s);
 void launch_small_spd_solve(int n, int lda, const double* A, const double* b, double* x,
                             unsigned* bad, hipStream_t s);
-void launch_gs_step(int64_t n, int j, double* const* Q, const double* h, double* v, hipStream_t s);
 
 // ---- filter, OC --------------------------------------------------------------
 void launch_filter_rowsum(const Grid& g, double r, double* Hs, hipStream_t s);
@@ -111,21 +117,5 @@ void launch_oc_step(int64_t ne, const double* x, const double* dc, const double*
                     double move, double* lam, double* xnew, hipStream_t s);
 void launch_oc_bisect(double* lam, const double* vol, double target, hipStream_t s);
 void launch_oc_init(double* lam, hipStream_t s);
-
-// ---- FP32 refinement form -----------------------------------------------------
-void launch_to_f32(int64_t n, const double* a, float* b, hipStream_t s);
-void launch_add_f32_to_f64(int64_t n, const float* a, double* b, hipStream_t s);
-void launch_jacobi_first_f32(int64_t n3, const float* b, const float* dinv, float omega, float* x,
-                             hipStream_t s);
-void launch_jacobi_update_f32(int64_t n3, const float* b, const float* t, const float* dinv,
-                              float omega, float* x, hipStream_t s);
-void launch_restrict_f32(const Grid& coarse, const float* bf, const float* tf,
-                         const uint8_t* mask, float* bc, hipStream_t s);
-void launch_prolong_add_f32(const Grid& fine, const float* xc, const uint8_t* mask, float* xf,
-                            hipStream_t s);
-void launch_apply_elemmat_f32(const Grid& g, const float* Ke, const float* v, float* y,
-                              hipStream_t s);
-void launch_convert_f32(int64_t n, const double* a, float* b, hipStream_t s);
-void launch_gemv_f32in(int n, const double* A, const float* x, float* y, hipStream_t s);
 
 }  // namespace aarmr

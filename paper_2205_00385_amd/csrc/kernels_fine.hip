@@ -1,6 +1,6 @@
-// Fine-grid kernels: SIMP moduli (eq. 1), fixed-DOF mask, the
-// element-by-element stiffness product y = A v (eq. 7 operator), its
-// diagonal (Jacobi smoother of Algorithm 2) and element energies (eq. 6).
+// Fine-grid kernels: SIMP moduli (eq. 1), fixed-DOF mask, the diagonal of
+// the stiffness operator (Jacobi smoother of Algorithm 2) and the
+// sensitivity of eq. (6) from element energies.
 #include "internal.hpp"
 
 namespace aarmr {
@@ -54,60 +54,6 @@ __global__ void k_mask_set(int64_t nn, const int64_t* __restrict__ fixed, int64_
   atomicOr(&mask_words[node >> 2], bit);
 }
 
-// y = A v, thread per node, gathering the 3 rows of each adjacent element's
-// stiffness (owner computes: no atomics, fixed summation order).
-__global__ void __launch_bounds__(256) k_ebe_gather(int nx, int ny, int nz,
-                                                    const double* __restrict__ KE,
-                                                    const double* __restrict__ E,
-                                                    const uint8_t* __restrict__ mask,
-                                                    const double* __restrict__ v,
-                                                    double* __restrict__ y, int mode) {
-  const int64_t nn = (int64_t)(nx + 1) * (ny + 1) * (nz + 1);
-  int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= nn) return;
-  int i = (int)(n % (nx + 1));
-  int64_t rest = n / (nx + 1);
-  int j = (int)(rest % (ny + 1));
-  int k = (int)(rest / (ny + 1));
-  double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
-  for (int ez = k - 1; ez <= k; ++ez) {
-    if (ez < 0 || ez >= nz) continue;
-    for (int ey = j - 1; ey <= j; ++ey) {
-      if (ey < 0 || ey >= ny) continue;
-      for (int ex = i - 1; ex <= i; ++ex) {
-        if (ex < 0 || ex >= nx) continue;
-        const int a = (i - ex) + 2 * (j - ey) + 4 * (k - ez);
-        const double w = E[(int64_t)ex + (int64_t)nx * ((int64_t)ey + (int64_t)ny * ez)];
-        const double* row = KE + (3 * a) * 24;
-        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-#pragma unroll
-        for (int b = 0; b < 8; ++b) {
-          const int64_t nb = node_of(nx, ny, ex + (b & 1), ey + ((b >> 1) & 1), ez + (b >> 2));
-          const uint8_t mb = mask[nb];
-#pragma unroll
-          for (int c = 0; c < 3; ++c) {
-            const double vb = ((mb >> c) & 1) ? 0.0 : v[c * nn + nb];
-            s0 = fma(row[3 * b + c], vb, s0);
-            s1 = fma(row[24 + 3 * b + c], vb, s1);
-            s2 = fma(row[48 + 3 * b + c], vb, s2);
-          }
-        }
-        acc0 = fma(w, s0, acc0);
-        acc1 = fma(w, s1, acc1);
-        acc2 = fma(w, s2, acc2);
-      }
-    }
-  }
-  const uint8_t m = mask[n];
-  const double acc[3] = {acc0, acc1, acc2};
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    double out = acc[c];
-    if ((m >> c) & 1) out = (mode == 0) ? v[c * nn + n] : 0.0;
-    y[c * nn + n] = out;
-  }
-}
-
 // Jacobi diagonal of A: sum over adjacent elements of E_e * KE_(aa) per
 // component; identity on fixed DOFs.  Stores the inverse.
 __global__ void k_diag_fine(int nx, int ny, int nz, const double* __restrict__ KE,
@@ -141,39 +87,6 @@ __global__ void k_diag_fine(int nx, int ny, int nz, const double* __restrict__ K
   }
 }
 
-// e_e = u_e^T KE u_e with fixed DOFs of u read as zero.
-__global__ void __launch_bounds__(256) k_energy(int nx, int ny, int nz,
-                                                const double* __restrict__ KE,
-                                                const uint8_t* __restrict__ mask,
-                                                const double* __restrict__ u,
-                                                double* __restrict__ energy) {
-  const int64_t nn = (int64_t)(nx + 1) * (ny + 1) * (nz + 1);
-  const int64_t ne = (int64_t)nx * ny * nz;
-  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= ne) return;
-  int ex = (int)(e % nx);
-  int64_t rest = e / nx;
-  int ey = (int)(rest % ny);
-  int ez = (int)(rest / ny);
-  double ue[24];
-#pragma unroll
-  for (int b = 0; b < 8; ++b) {
-    const int64_t nb = node_of(nx, ny, ex + (b & 1), ey + ((b >> 1) & 1), ez + (b >> 2));
-    const uint8_t mb = mask[nb];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) ue[3 * b + c] = ((mb >> c) & 1) ? 0.0 : u[c * nn + nb];
-  }
-  double s = 0.0;
-#pragma unroll
-  for (int r = 0; r < 24; ++r) {
-    double t = 0.0;
-#pragma unroll
-    for (int c = 0; c < 24; ++c) t = fma(KE[r * 24 + c], ue[c], t);
-    s = fma(ue[r], t, s);
-  }
-  energy[e] = s;
-}
-
 // dc (+)= -p rho~^(p-1) (E0 - Emin) e_e  (eq. 6 with eq. 1).
 __global__ void k_dc_accum(int64_t ne, const double* __restrict__ rho,
                            const double* __restrict__ energy, double E0, double Emin, double p,
@@ -205,19 +118,9 @@ void launch_build_mask(int64_t nn, const int64_t* fixed, int64_t nfixed, uint8_t
   if (nfixed > 0) k_mask_set<<<nblk(nfixed, 256), 256, 0, s>>>(nn, fixed, nfixed, w, bad);
 }
 
-void launch_ebe_fine(const Grid& g, const double* KE, const double* E, const uint8_t* mask,
-                     const double* v, double* y, int mode, hipStream_t s) {
-  k_ebe_gather<<<nblk(g.nn, 256), 256, 0, s>>>(g.nx, g.ny, g.nz, KE, E, mask, v, y, mode);
-}
-
 void launch_diag_fine(const Grid& g, const double* KE, const double* E, const uint8_t* mask,
                       double* dinv, float* dinv32, hipStream_t s) {
   k_diag_fine<<<nblk(g.nn, 256), 256, 0, s>>>(g.nx, g.ny, g.nz, KE, E, mask, dinv, dinv32);
-}
-
-void launch_energy(const Grid& g, const double* KE, const uint8_t* mask, const double* u,
-                   double* energy, hipStream_t s) {
-  k_energy<<<nblk(g.ne, 256), 256, 0, s>>>(g.nx, g.ny, g.nz, KE, mask, u, energy);
 }
 
 void launch_dc_accum(int64_t ne, const double* rho, const double* energy, double E0, double Emin,

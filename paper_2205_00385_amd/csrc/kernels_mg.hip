@@ -1,5 +1,5 @@
 // Multigrid kernels of the V-cycle (Algorithm 2): Galerkin coarse operators
-// P^T A P stored as one 24x24 matrix per coarse element, their products and
+// P^T A P stored as one packed symmetric 24x24 matrix per coarse element, their products and
 // diagonals, restriction P^T and interpolation P (trilinear, 2:1 per axis),
 // damped-Jacobi smoothing, and the exact coarsest solve through an explicit
 // inverse computed by blocked Gauss-Jordan elimination.
@@ -21,110 +21,166 @@ __device__ inline double phi1(int pos, int A) {
   return pos == 1 ? 0.5 : ((pos >> 1) == A ? 1.0 : 0.0);
 }
 
-// Kc(E) = sum over the 8 children c of P_c^T Kchild_c P_c, where P_c maps the
-// parent's 8 corners to child c's 8 corners.  Children are fine elements
-// (from_fine: Kchild = E_c Df KE Df with the fine fixed-DOF mask) or coarse
-// element matrices of the previous level.  One block per coarse element.
-template <bool FROM_FINE>
-__global__ void __launch_bounds__(256) k_galerkin(int cnx, int cny, int cnz,
-                                                  const double* __restrict__ KE,
-                                                  const double* __restrict__ E,
-                                                  const uint8_t* __restrict__ mask,
-                                                  const double* __restrict__ Kf,
-                                                  double* __restrict__ Kc) {
-  __shared__ double sK[FROM_FINE ? 576 : 8 * 576];
-  __shared__ double sw[8];
-  __shared__ uint8_t sm[27];
-  const int64_t E_id = blockIdx.x;
-  const int cx = (int)(E_id % cnx);
-  const int64_t rest = E_id / cnx;
-  const int cy = (int)(rest % cny);
-  const int cz = (int)(rest / cny);
+constexpr int kSym = kSymEntries;
+__host__ __device__ constexpr int sidx(int r, int c) { return sym_index(r, c); }
+
+// Level-1 Galerkin matrices, fast path: Kc = sum_c E_c M_c with
+// M_c = P_c^T KE P_c precomputed (P_c the trilinear map from the parent's
+// corners to child c's corners).  Exact for parents whose 27 fine nodes are
+// all free; k_galerkin_lds then overwrites the parents that touch a fixed
+// DOF.  Block: 64 parents (lanes) x 4 waves; wave w writes the packed
+// entries w, w+4, ...
+__global__ void __launch_bounds__(256) k_galerkin_fast(int cnx, int cny, int cnz,
+                                                       const double* __restrict__ Mc,
+                                                       const double* __restrict__ E,
+                                                       double* __restrict__ Kc) {
+  const int64_t cne = (int64_t)cnx * cny * cnz;
+  const int64_t eid = (int64_t)blockIdx.x * 64 + (threadIdx.x & 63);
+  const int wave = threadIdx.x >> 6;
+  if (eid >= cne) return;
+  const int cx = (int)(eid % cnx);
+  const int64_t rest = eid / cnx;
+  const int cy = (int)(rest % cny), cz = (int)(rest / cny);
   const int fnx = 2 * cnx, fny = 2 * cny;
+  double w[8];
+#pragma unroll
+  for (int c = 0; c < 8; ++c)
+    w[c] = E[(int64_t)(2 * cx + (c & 1)) +
+             (int64_t)fnx * ((2 * cy + ((c >> 1) & 1)) + (int64_t)fny * (2 * cz + (c >> 2)))];
+  for (int sx = wave; sx < kSym; sx += 4) {
+    double acc = 0.0;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) acc = fma(w[c], Mc[c * kSym + sx], acc);
+    Kc[(int64_t)sx * cne + eid] = acc;
+  }
+}
+
+// Galerkin matrix of one parent per block: the 8 child matrices are staged
+// in LDS, T_c = K_c P_c is formed by a column pass and sum_c P_c^T T_c by a
+// row pass.  FROM_FINE: children are E_c Df KE Df with the fine fixed-DOF
+// mask, and only parents touching a fixed DOF are written.  Otherwise the
+// children are the previous level's packed matrices.
+template <bool FROM_FINE>
+__global__ void __launch_bounds__(256) k_galerkin_lds(int cnx, int cny, int cnz,
+                                                      const double* __restrict__ KE,
+                                                      const double* __restrict__ E,
+                                                      const uint8_t* __restrict__ mask,
+                                                      const double* __restrict__ Kf,
+                                                      double* __restrict__ Kc) {
+  __shared__ double sK[8][24][25];
+  __shared__ uint8_t sm[27];
+  __shared__ double sw[8];
+  __shared__ int any_fixed;
+  const int64_t cne = (int64_t)cnx * cny * cnz;
+  const int64_t eid = blockIdx.x;
+  const int cx = (int)(eid % cnx);
+  const int64_t rest = eid / cnx;
+  const int cy = (int)(rest % cny), cz = (int)(rest / cny);
+  const int fnx = 2 * cnx, fny = 2 * cny;
+  const int64_t fne = cne * 8;
   const int tid = threadIdx.x;
   if (FROM_FINE) {
-    for (int t = tid; t < 576; t += 256) sK[t] = KE[t];
-    if (tid < 8) {
-      int dx = tid & 1, dy = (tid >> 1) & 1, dz = tid >> 2;
-      int64_t fe = (int64_t)(2 * cx + dx) + (int64_t)fnx * ((2 * cy + dy) + (int64_t)fny * (2 * cz + dz));
-      sw[tid] = E[fe];
-    }
+    if (tid == 0) any_fixed = 0;
+    __syncthreads();
     if (tid < 27) {
-      int px = tid % 3, py = (tid / 3) % 3, pz = tid / 9;
+      const int px = tid % 3, py = (tid / 3) % 3, pz = tid / 9;
       sm[tid] = mask[node_of(fnx, fny, 2 * cx + px, 2 * cy + py, 2 * cz + pz)];
+      if (sm[tid]) atomicOr(&any_fixed, 1);
     }
-  } else {
-    for (int t = tid; t < 8 * 576; t += 256) {
-      int c = t / 576, o = t % 576;
-      int dx = c & 1, dy = (c >> 1) & 1, dz = c >> 2;
-      int64_t fe = (int64_t)(2 * cx + dx) + (int64_t)fnx * ((2 * cy + dy) + (int64_t)fny * (2 * cz + dz));
-      sK[t] = Kf[fe * 576 + o];
+    if (tid < 8)
+      sw[tid] = E[(int64_t)(2 * cx + (tid & 1)) +
+                  (int64_t)fnx * ((2 * cy + ((tid >> 1) & 1)) + (int64_t)fny * (2 * cz + (tid >> 2)))];
+    __syncthreads();
+    if (!any_fixed) return;  // block-uniform: the fast path already wrote it
+  }
+  for (int t = tid; t < 8 * 576; t += 256) {
+    const int c = t / 576, r = (t % 576) / 24, q = t % 24;
+    const int dx = c & 1, dy = (c >> 1) & 1, dz = c >> 2;
+    double v;
+    if (FROM_FINE) {
+      const int br = r / 3, bq = q / 3;
+      const int pr = (dx + (br & 1)) + 3 * (dy + ((br >> 1) & 1)) + 9 * (dz + (br >> 2));
+      const int pq = (dx + (bq & 1)) + 3 * (dy + ((bq >> 1) & 1)) + 9 * (dz + (bq >> 2));
+      const bool fx = ((sm[pr] >> (r % 3)) & 1) || ((sm[pq] >> (q % 3)) & 1);
+      v = fx ? 0.0 : sw[c] * KE[r * 24 + q];
+    } else {
+      const int64_t fe = (int64_t)(2 * cx + dx) + (int64_t)fnx * ((2 * cy + dy) + (int64_t)fny * (2 * cz + dz));
+      v = Kf[(int64_t)sidx(r, q) * fne + fe];
     }
+    sK[c][r][q] = v;
   }
   __syncthreads();
-  for (int idx = tid; idx < 576; idx += 256) {
-    const int I = idx / 24, J = idx % 24;
-    const int A = I / 3, i = I % 3, B = J / 3, j = J % 3;
-    const int Ax = A & 1, Ay = (A >> 1) & 1, Az = A >> 2;
-    const int Bx = B & 1, By = (B >> 1) & 1, Bz = B >> 2;
+  // column pass: T_c[r][3B+j] = sum_b P_c[b][B] K_c[r][3b+j]
+  double tv[18];
+#pragma unroll
+  for (int u = 0; u < 18; ++u) {
+    const int t = tid + 256 * u;
+    const int c = t / 576, r = (t % 576) / 24, J = t % 24;
+    const int B = J / 3, j = J % 3;
+    const int dx = c & 1, dy = (c >> 1) & 1, dz = c >> 2;
+    double acc = 0.0;
+    for (int b = 0; b < 8; ++b) {
+      const double pb = phi1(dx + (b & 1), B & 1) * phi1(dy + ((b >> 1) & 1), (B >> 1) & 1) *
+                        phi1(dz + (b >> 2), B >> 2);
+      acc = fma(pb, sK[c][r][3 * b + j], acc);
+    }
+    tv[u] = acc;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < 18; ++u) {
+    const int t = tid + 256 * u;
+    sK[t / 576][(t % 576) / 24][t % 24] = tv[u];
+  }
+  __syncthreads();
+  // row pass over packed entries (I <= J): sum_c sum_b P_c[b][A] T_c[3b+i][J]
+  for (int sx = tid; sx < kSym; sx += 256) {
+    int I = 0;
+    while (sidx(I, 23) < sx) ++I;  // row of packed entry sx
+    const int J = I + (sx - sidx(I, I));
+    const int A = I / 3, i = I % 3;
     double acc = 0.0;
     for (int c = 0; c < 8; ++c) {
       const int dx = c & 1, dy = (c >> 1) & 1, dz = c >> 2;
       for (int b = 0; b < 8; ++b) {
-        const int px = dx + (b & 1), py = dy + ((b >> 1) & 1), pz = dz + (b >> 2);
-        const double pa = phi1(px, Ax) * phi1(py, Ay) * phi1(pz, Az);
-        if (pa == 0.0) continue;
-        if (FROM_FINE && ((sm[px + 3 * py + 9 * pz] >> i) & 1)) continue;
-        double inner = 0.0;
-        for (int b2 = 0; b2 < 8; ++b2) {
-          const int qx = dx + (b2 & 1), qy = dy + ((b2 >> 1) & 1), qz = dz + (b2 >> 2);
-          const double pb = phi1(qx, Bx) * phi1(qy, By) * phi1(qz, Bz);
-          if (pb == 0.0) continue;
-          if (FROM_FINE && ((sm[qx + 3 * qy + 9 * qz] >> j) & 1)) continue;
-          const double kv = FROM_FINE ? sK[(3 * b + i) * 24 + 3 * b2 + j]
-                                      : sK[c * 576 + (3 * b + i) * 24 + 3 * b2 + j];
-          inner = fma(pb, kv, inner);
-        }
-        acc = fma(pa * (FROM_FINE ? sw[c] : 1.0), inner, acc);
+        const double pa = phi1(dx + (b & 1), A & 1) * phi1(dy + ((b >> 1) & 1), (A >> 1) & 1) *
+                          phi1(dz + (b >> 2), A >> 2);
+        acc = fma(pa, sK[c][3 * b + i][J], acc);
       }
     }
-    Kc[E_id * 576 + idx] = acc;
+    Kc[(int64_t)sx * cne + eid] = acc;
   }
 }
 
-// y = sum_e L_e^T Ke_e L_e v for per-element matrices; thread per node.
+// y = sum_e L_e^T Ke_e L_e v for packed element matrices; thread per node.
+template <typename T>
 __global__ void __launch_bounds__(256) k_apply_elemmat(int nx, int ny, int nz,
-                                                       const double* __restrict__ Ke,
-                                                       const double* __restrict__ v,
-                                                       double* __restrict__ y) {
+                                                       const T* __restrict__ Ke,
+                                                       const T* __restrict__ v,
+                                                       T* __restrict__ y) {
   const int64_t nn = (int64_t)(nx + 1) * (ny + 1) * (nz + 1);
+  const int64_t ne = (int64_t)nx * ny * nz;
   int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= nn) return;
-  int i = (int)(n % (nx + 1));
-  int64_t rest = n / (nx + 1);
-  int j = (int)(rest % (ny + 1));
-  int k = (int)(rest / (ny + 1));
-  double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
-  for (int ez = k - 1; ez <= k; ++ez) {
-    if (ez < 0 || ez >= nz) continue;
-    for (int ey = j - 1; ey <= j; ++ey) {
-      if (ey < 0 || ey >= ny) continue;
-      for (int ex = i - 1; ex <= i; ++ex) {
-        if (ex < 0 || ex >= nx) continue;
-        const int a = (i - ex) + 2 * (j - ey) + 4 * (k - ez);
-        const int64_t e = (int64_t)ex + (int64_t)nx * ((int64_t)ey + (int64_t)ny * ez);
-        const double* row = Ke + e * 576 + (3 * a) * 24;
+  const int i = (int)(n % (nx + 1));
+  const int64_t rest = n / (nx + 1);
+  const int j = (int)(rest % (ny + 1));
+  const int k = (int)(rest / (ny + 1));
+  T acc0 = 0, acc1 = 0, acc2 = 0;
 #pragma unroll
-        for (int b = 0; b < 8; ++b) {
-          const int64_t nb = node_of(nx, ny, ex + (b & 1), ey + ((b >> 1) & 1), ez + (b >> 2));
+  for (int a = 0; a < 8; ++a) {  // the node is local corner a of element (i,j,k) - offset(a)
+    const int ex = i - (a & 1), ey = j - ((a >> 1) & 1), ez = k - (a >> 2);
+    if (ex < 0 || ex >= nx || ey < 0 || ey >= ny || ez < 0 || ez >= nz) continue;
+    const int64_t e = (int64_t)ex + (int64_t)nx * ((int64_t)ey + (int64_t)ny * ez);
 #pragma unroll
-          for (int c = 0; c < 3; ++c) {
-            const double vb = v[c * nn + nb];
-            acc0 = fma(row[3 * b + c], vb, acc0);
-            acc1 = fma(row[24 + 3 * b + c], vb, acc1);
-            acc2 = fma(row[48 + 3 * b + c], vb, acc2);
-          }
-        }
+    for (int b = 0; b < 8; ++b) {
+      const int64_t nb = node_of(nx, ny, ex + (b & 1), ey + ((b >> 1) & 1), ez + (b >> 2));
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const T vb = v[c * nn + nb];
+        acc0 = fma(Ke[(int64_t)sidx(3 * a + 0, 3 * b + c) * ne + e], vb, acc0);
+        acc1 = fma(Ke[(int64_t)sidx(3 * a + 1, 3 * b + c) * ne + e], vb, acc1);
+        acc2 = fma(Ke[(int64_t)sidx(3 * a + 2, 3 * b + c) * ne + e], vb, acc2);
       }
     }
   }
@@ -136,24 +192,21 @@ __global__ void __launch_bounds__(256) k_apply_elemmat(int nx, int ny, int nz,
 __global__ void k_diag_elemmat(int nx, int ny, int nz, const double* __restrict__ Ke,
                                double* __restrict__ dinv, float* __restrict__ dinv32) {
   const int64_t nn = (int64_t)(nx + 1) * (ny + 1) * (nz + 1);
+  const int64_t ne = (int64_t)nx * ny * nz;
   int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= nn) return;
-  int i = (int)(n % (nx + 1));
-  int64_t rest = n / (nx + 1);
-  int j = (int)(rest % (ny + 1));
-  int k = (int)(rest / (ny + 1));
+  const int i = (int)(n % (nx + 1));
+  const int64_t rest = n / (nx + 1);
+  const int j = (int)(rest % (ny + 1));
+  const int k = (int)(rest / (ny + 1));
   double d[3] = {0.0, 0.0, 0.0};
-  for (int ez = k - 1; ez <= k; ++ez) {
-    if (ez < 0 || ez >= nz) continue;
-    for (int ey = j - 1; ey <= j; ++ey) {
-      if (ey < 0 || ey >= ny) continue;
-      for (int ex = i - 1; ex <= i; ++ex) {
-        if (ex < 0 || ex >= nx) continue;
-        const int a = (i - ex) + 2 * (j - ey) + 4 * (k - ez);
-        const int64_t e = (int64_t)ex + (int64_t)nx * ((int64_t)ey + (int64_t)ny * ez);
-        for (int c = 0; c < 3; ++c) d[c] += Ke[e * 576 + (3 * a + c) * 25];
-      }
-    }
+#pragma unroll
+  for (int a = 0; a < 8; ++a) {
+    const int ex = i - (a & 1), ey = j - ((a >> 1) & 1), ez = k - (a >> 2);
+    if (ex < 0 || ex >= nx || ey < 0 || ey >= ny || ez < 0 || ez >= nz) continue;
+    const int64_t e = (int64_t)ex + (int64_t)nx * ((int64_t)ey + (int64_t)ny * ez);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) d[c] += Ke[(int64_t)sidx(3 * a + c, 3 * a + c) * ne + e];
   }
   for (int c = 0; c < 3; ++c) {
     double di = d[c] == 0.0 ? 1.0 : 1.0 / d[c];  // dead coarse DOF: identity row
@@ -258,6 +311,7 @@ __global__ void k_jacobi_update(int64_t n3, const T* __restrict__ b, const T* __
 __global__ void k_assemble_dense(int nx, int ny, int nz, const double* __restrict__ Ke,
                                  double* __restrict__ A) {
   const int64_t nn = (int64_t)(nx + 1) * (ny + 1) * (nz + 1);
+  const int64_t ne = (int64_t)nx * ny * nz;
   const int64_t nd = 3 * nn;
   int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (row >= nd) return;
@@ -265,24 +319,17 @@ __global__ void k_assemble_dense(int nx, int ny, int nz, const double* __restric
   const int64_t n = row % nn;
   double* Ar = A + row * nd;
   for (int64_t t = 0; t < nd; ++t) Ar[t] = 0.0;
-  int i = (int)(n % (nx + 1));
-  int64_t rest = n / (nx + 1);
-  int j = (int)(rest % (ny + 1));
-  int k = (int)(rest / (ny + 1));
-  for (int ez = k - 1; ez <= k; ++ez) {
-    if (ez < 0 || ez >= nz) continue;
-    for (int ey = j - 1; ey <= j; ++ey) {
-      if (ey < 0 || ey >= ny) continue;
-      for (int ex = i - 1; ex <= i; ++ex) {
-        if (ex < 0 || ex >= nx) continue;
-        const int a = (i - ex) + 2 * (j - ey) + 4 * (k - ez);
-        const int64_t e = (int64_t)ex + (int64_t)nx * ((int64_t)ey + (int64_t)ny * ez);
-        const double* r = Ke + e * 576 + (3 * a + c) * 24;
-        for (int b = 0; b < 8; ++b) {
-          const int64_t nb = node_of(nx, ny, ex + (b & 1), ey + ((b >> 1) & 1), ez + (b >> 2));
-          for (int cc = 0; cc < 3; ++cc) Ar[cc * nn + nb] += r[3 * b + cc];
-        }
-      }
+  const int i = (int)(n % (nx + 1));
+  const int64_t rest = n / (nx + 1);
+  const int j = (int)(rest % (ny + 1));
+  const int k = (int)(rest / (ny + 1));
+  for (int a = 0; a < 8; ++a) {
+    const int ex = i - (a & 1), ey = j - ((a >> 1) & 1), ez = k - (a >> 2);
+    if (ex < 0 || ex >= nx || ey < 0 || ey >= ny || ez < 0 || ez >= nz) continue;
+    const int64_t e = (int64_t)ex + (int64_t)nx * ((int64_t)ey + (int64_t)ny * ez);
+    for (int b = 0; b < 8; ++b) {
+      const int64_t nb = node_of(nx, ny, ex + (b & 1), ey + ((b >> 1) & 1), ez + (b >> 2));
+      for (int cc = 0; cc < 3; ++cc) Ar[cc * nn + nb] += Ke[(int64_t)sidx(3 * a + c, 3 * b + cc) * ne + e];
     }
   }
   if (Ar[row] == 0.0) Ar[row] = 1.0;  // dead coarse DOF: identity row
@@ -293,35 +340,42 @@ __global__ void k_assemble_dense(int nx, int ny, int nz, const double* __restric
 //   P = A_KK^-1, T = A_:K P, A_IJ -= T_I A_KJ (I, J outside K),
 //   A_KJ = P A_KJ, A_IK = -T_I, A_KK = P.
 
-// Invert the kb x kb pivot block in LDS (unblocked Gauss-Jordan).
-__global__ void __launch_bounds__(256) k_gj_pivot(int n, int k0, int kb,
-                                                  const double* __restrict__ A,
-                                                  double* __restrict__ P) {
-  __shared__ double s[kGJBlock * kGJBlock];
-  __shared__ double rowk[kGJBlock], colk[kGJBlock];
-  const int tid = threadIdx.x;
-  for (int t = tid; t < kb * kb; t += 256) {
-    int r = t / kb, c = t % kb;
-    s[t] = A[(int64_t)(k0 + r) * n + (k0 + c)];
-  }
-  __syncthreads();
-  for (int k = 0; k < kb; ++k) {
-    if (tid < kb) {
-      rowk[tid] = s[k * kb + tid];
-      colk[tid] = s[tid * kb + k];
+// Invert the kb x kb pivot block (unblocked Gauss-Jordan) in one wavefront:
+// lane c holds column c in registers; the pivot column is broadcast with
+// readlane.  Rows/columns beyond kb are padded with the identity.
+__device__ inline double lane_bcast(double x, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(x), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(x), lane);
+  return __hiloint2double(hi, lo);
+}
+
+__global__ void __launch_bounds__(64) k_gj_pivot(int n, int k0, int kb,
+                                                 const double* __restrict__ A,
+                                                 double* __restrict__ P) {
+  const int c = threadIdx.x;
+  double col[kGJBlock];
+#pragma unroll
+  for (int r = 0; r < kGJBlock; ++r)
+    col[r] = (r < kb && c < kb) ? A[(int64_t)(k0 + r) * n + (k0 + c)] : (r == c ? 1.0 : 0.0);
+  // the step index k is a runtime value; col[] is only ever indexed by the
+  // unrolled r, so it stays in registers (row k is picked out by selects)
+  for (int k = 0; k < kGJBlock; ++k) {
+    double rk = 0.0;
+#pragma unroll
+    for (int r = 0; r < kGJBlock; ++r) rk = (r == k) ? col[r] : rk;
+    const double piv = 1.0 / lane_bcast(rk, k);
+    const bool pc = (c == k);
+#pragma unroll
+    for (int r = 0; r < kGJBlock; ++r) {
+      const double crk = lane_bcast(col[r], k);
+      const double upd = pc ? -crk * piv : fma(-crk * piv, rk, col[r]);
+      const double kr = pc ? piv : rk * piv;
+      col[r] = (r == k) ? kr : upd;
     }
-    __syncthreads();
-    const double piv = 1.0 / colk[k];
-    for (int t = tid; t < kb * kb; t += 256) {
-      int r = t / kb, c = t % kb;
-      if (r == k && c == k) s[t] = piv;
-      else if (r == k) s[t] = rowk[c] * piv;
-      else if (c == k) s[t] = -colk[r] * piv;
-      else s[t] -= colk[r] * rowk[c] * piv;
-    }
-    __syncthreads();
   }
-  for (int t = tid; t < kb * kb; t += 256) P[t] = s[t];
+#pragma unroll
+  for (int r = 0; r < kGJBlock; ++r)
+    if (r < kb && c < kb) P[r * kb + c] = col[r];
 }
 
 // T[i][p] = sum_q A[i][k0+q] P[q][p] (all rows i); Rw[p][j] = A[k0+p][j].
@@ -338,39 +392,47 @@ __global__ void k_gj_panels(int n, int k0, int kb, const double* __restrict__ A,
   Rw[t] = A[(int64_t)(k0 + pr) * n + j];
 }
 
-// A_IJ -= T_I Rw_J for I, J outside the pivot block (32x64 LDS tiles; each
-// of the 256 threads computes 2 rows x 4 columns).
+// A_IJ -= T_I Rw_J for I, J outside the pivot block: 64x64 output tiles, each
+// of the 256 threads accumulates a 4x4 sub-tile; the rank-kb product is
+// staged through LDS in chunks of 16.
 __global__ void __launch_bounds__(256) k_gj_update(int n, int k0, int kb,
                                                    double* __restrict__ A,
                                                    const double* __restrict__ T,
                                                    const double* __restrict__ Rw) {
-  __shared__ double sT[32][kGJBlock + 1];
-  __shared__ double sR[kGJBlock][64 + 1];
-  const int bi = blockIdx.y * 32, bj = blockIdx.x * 64;
+  __shared__ double sT[16][64 + 1];
+  __shared__ double sR[16][64 + 1];
+  const int bi = blockIdx.y * 64, bj = blockIdx.x * 64;
   const int tid = threadIdx.x;
-  for (int t = tid; t < 32 * kb; t += 256) {
-    int r = t / kb, p = t % kb;
-    int i = bi + r;
-    sT[r][p] = (i < n) ? T[(int64_t)i * kb + p] : 0.0;
-  }
-  for (int t = tid; t < kb * 64; t += 256) {
-    int p = t / 64, c = t % 64;
-    int j = bj + c;
-    sR[p][c] = (j < n) ? Rw[(int64_t)p * n + j] : 0.0;
-  }
-  __syncthreads();
   const int tr = tid / 16, tc = tid % 16;
-  double acc[2][4] = {};
-  for (int p = 0; p < kb; ++p) {
-    double a[2], b[4];
-    for (int u = 0; u < 2; ++u) a[u] = sT[tr * 2 + u][p];
-    for (int w = 0; w < 4; ++w) b[w] = sR[p][tc + 16 * w];
-    for (int u = 0; u < 2; ++u)
-      for (int w = 0; w < 4; ++w) acc[u][w] = fma(a[u], b[w], acc[u][w]);
+  double acc[4][4] = {};
+  for (int p0 = 0; p0 < kb; p0 += 16) {
+    for (int t = tid; t < 16 * 64; t += 256) {
+      const int q = t / 64, rr = t % 64;
+      const int p = p0 + q;
+      const int i = bi + rr, j = bj + rr;
+      sT[q][rr] = (p < kb && i < n) ? T[(int64_t)i * kb + p] : 0.0;
+      sR[q][rr] = (p < kb && j < n) ? Rw[(int64_t)p * n + j] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      double a[4], b[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) a[u] = sT[q][tr + 16 * u];
+#pragma unroll
+      for (int w = 0; w < 4; ++w) b[w] = sR[q][tc + 16 * w];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int w = 0; w < 4; ++w) acc[u][w] = fma(a[u], b[w], acc[u][w]);
+    }
+    __syncthreads();
   }
-  for (int u = 0; u < 2; ++u) {
-    const int i = bi + tr * 2 + u;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int i = bi + tr + 16 * u;
     if (i >= n || (i >= k0 && i < k0 + kb)) continue;
+#pragma unroll
     for (int w = 0; w < 4; ++w) {
       const int j = bj + tc + 16 * w;
       if (j >= n || (j >= k0 && j < k0 + kb)) continue;
@@ -417,20 +479,21 @@ __global__ void __launch_bounds__(256) k_gemv(int n, const double* __restrict__ 
 
 }  // namespace
 
-void launch_galerkin_from_fine(const Grid& coarse, const double* KE, const double* E,
-                               const uint8_t* mask, double* Kc, hipStream_t s) {
-  k_galerkin<true><<<(unsigned)coarse.ne, 256, 0, s>>>(coarse.nx, coarse.ny, coarse.nz, KE, E,
-                                                       mask, nullptr, Kc);
+void launch_galerkin_from_fine(const Grid& coarse, const double* KE, const double* Mc,
+                               const double* E, const uint8_t* mask, double* Kc, hipStream_t s) {
+  k_galerkin_fast<<<nblk(coarse.ne, 64), 256, 0, s>>>(coarse.nx, coarse.ny, coarse.nz, Mc, E, Kc);
+  k_galerkin_lds<true><<<(unsigned)coarse.ne, 256, 0, s>>>(coarse.nx, coarse.ny, coarse.nz, KE, E,
+                                                          mask, nullptr, Kc);
 }
 
 void launch_galerkin_from_coarse(const Grid& coarse, const double* Kf, double* Kc, hipStream_t s) {
-  k_galerkin<false><<<(unsigned)coarse.ne, 256, 0, s>>>(coarse.nx, coarse.ny, coarse.nz, nullptr,
-                                                        nullptr, nullptr, Kf, Kc);
+  k_galerkin_lds<false><<<(unsigned)coarse.ne, 256, 0, s>>>(coarse.nx, coarse.ny, coarse.nz,
+                                                           nullptr, nullptr, nullptr, Kf, Kc);
 }
 
 void launch_apply_elemmat(const Grid& g, const double* Ke, const double* v, double* y,
                           hipStream_t s) {
-  k_apply_elemmat<<<nblk(g.nn, 256), 256, 0, s>>>(g.nx, g.ny, g.nz, Ke, v, y);
+  k_apply_elemmat<double><<<nblk(g.nn, 256), 256, 0, s>>>(g.nx, g.ny, g.nz, Ke, v, y);
 }
 
 void launch_diag_elemmat(const Grid& g, const double* Ke, double* dinv, float* dinv32,
@@ -467,10 +530,10 @@ void launch_assemble_dense(const Grid& g, const double* Ke, double* A, hipStream
 void launch_gj_invert(int n, double* A, double* P, double* T, double* Rw, hipStream_t s) {
   for (int k0 = 0; k0 < n; k0 += kGJBlock) {
     const int kb = (n - k0 < kGJBlock) ? (n - k0) : kGJBlock;
-    k_gj_pivot<<<1, 256, 0, s>>>(n, k0, kb, A, P);
+    k_gj_pivot<<<1, 64, 0, s>>>(n, k0, kb, A, P);
     const int64_t nk = (int64_t)n * kb;
     k_gj_panels<<<nblk(nk, 256), 256, 0, s>>>(n, k0, kb, A, P, T, Rw);
-    dim3 grid((n + 63) / 64, (n + 31) / 32);
+    dim3 grid((n + 63) / 64, (n + 63) / 64);
     k_gj_update<<<grid, 256, 0, s>>>(n, k0, kb, A, T, Rw);
     k_gj_finish<<<nblk(nk, 256), 256, 0, s>>>(n, k0, kb, A, P, T, Rw);
   }

@@ -1,6 +1,6 @@
 // Vector kernels of CG and of the reduced model: deterministic FP64 dot
-// products (wavefront shuffles, fixed-order block partials, last block
-// finishes), CG updates whose scalars stay in device memory, linear
+// products (wavefront shuffles, fixed-order block partials, a one-block
+// finishing pass), CG updates whose scalars stay in device memory, linear
 // combinations with device coefficients and small dense SPD solves.
 #include "internal.hpp"
 
@@ -28,13 +28,14 @@ __device__ inline double block_sum(double v, double* sh) {
   return r;
 }
 
-// k dot products over n entries; grid of nb <= kRedBlocks blocks; each block
-// strides over the vector in a fixed pattern and writes one partial per
-// product; the last block to finish sums the partials in index order.
-__global__ void __launch_bounds__(256) k_multidot(DotSet d, double* __restrict__ partial,
-                                                  unsigned* __restrict__ ticket) {
+// k dot products over n entries.  Pass 1: a grid of nb <= kRedBlocks blocks,
+// each striding over the vectors in a fixed pattern, writes one partial per
+// product.  Pass 2 (one block) sums the partials in index order.  Both
+// passes have a fixed summation order, so results are bitwise reproducible;
+// the kernel boundary orders the partial stores before their reads without
+// any device-scope fence (each of which would write back an XCD's L2).
+__global__ void __launch_bounds__(256) k_multidot(DotSet d, double* __restrict__ partial) {
   __shared__ double sh[4];
-  __shared__ bool last;
   const int nb = gridDim.x;
   const int64_t stride = (int64_t)nb * 256;
   for (int k = 0; k < d.k; ++k) {
@@ -50,24 +51,17 @@ __global__ void __launch_bounds__(256) k_multidot(DotSet d, double* __restrict__
     s = block_sum(s, sh);
     if (threadIdx.x == 0) partial[k * kRedBlocks + blockIdx.x] = s;
   }
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned t = atomicAdd(ticket, 1u);
-    last = (t == (unsigned)nb - 1);
-  }
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
+}
+
+__global__ void __launch_bounds__(256) k_multidot_finish(DotSet d, int nb,
+                                                         const double* __restrict__ partial) {
+  __shared__ double sh[4];
   for (int k = 0; k < d.k; ++k) {
     double s = 0.0;
-    for (int i = threadIdx.x; i < nb; i += 256)
-      s += __hip_atomic_load(&partial[k * kRedBlocks + i], __ATOMIC_RELAXED,
-                             __HIP_MEMORY_SCOPE_AGENT);
+    for (int i = threadIdx.x; i < nb; i += 256) s += partial[k * kRedBlocks + i];
     s = block_sum(s, sh);
     if (threadIdx.x == 0) *d.out[k] = s;
   }
-  if (threadIdx.x == 0) __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __global__ void k_copy_masked(int64_t nn, const double* __restrict__ src,
@@ -169,7 +163,8 @@ __global__ void k_small_spd_solve(int n, int lda, const double* __restrict__ A,
 void launch_multidot(const DotSet& d, const RedScratch& rs, hipStream_t s) {
   int64_t want = (d.n + 255) / 256;
   int nb = (int)(want < kRedBlocks ? (want < 1 ? 1 : want) : kRedBlocks);
-  k_multidot<<<nb, 256, 0, s>>>(d, rs.partial, rs.ticket);
+  k_multidot<<<nb, 256, 0, s>>>(d, rs.partial);
+  k_multidot_finish<<<1, 256, 0, s>>>(d, nb, rs.partial);
 }
 
 void launch_copy_masked(const Grid& g, const double* src, const uint8_t* mask, double* dst,
