@@ -73,6 +73,10 @@ extern "C" {
                                   the oldest vector once Ns are held */
 #define AARMR_WARM_START    4  /* use the incoming u as the CG initial guess
                                   (otherwise CG starts from zero) */
+#define AARMR_INPUT_MASKED  8  /* aarmr_apply_operator: the caller guarantees
+                                  that v is zero on fixed DOFs, so the product
+                                  skips masking its input (the form every
+                                  solver-internal product uses) */
 
 /* ---- parameters -------------------------------------------------------- */
 typedef struct aarmr_params {
@@ -209,10 +213,12 @@ int aarmr_setup(aarmr_mesh* m, const double* rho_phys, const int64_t* fixed_dofs
                 int64_t n_fixed, void* stream);
 
 /* y = A v on grid level `level` (0 = finest, matrix-free element-by-element
- * product; coarser levels use the Galerkin operators of aarmr_setup).
- * v, y: device [3][n_node(level)], distinct.  Stream-ordered. */
+ * product of eq. (7)'s stiffness; coarser levels use the Galerkin operators
+ * of aarmr_setup).  v, y: device [3][n_node(level)], distinct.  flags:
+ * AARMR_INPUT_MASKED (level 0 only) promises v is zero on fixed DOFs; the
+ * result is then the same and cheaper to compute.  Stream-ordered. */
 int aarmr_apply_operator(aarmr_mesh* m, int32_t level, const double* v, double* y,
-                         void* stream);
+                         int32_t flags, void* stream);
 
 /* z = M^-1 r: one V-cycle of Algorithm 2 from a zero initial guess on the
  * finest level.  r, z: device [3][n_node], distinct.  Stream-ordered. */

@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(_PKG, "libaarmr.so")
 OK, E_INVALID, E_HIP, E_NOT_CONVERGED, E_SINGULAR, E_NO_WORKSPACE, E_STATE = range(7)
 MAX_RHS, MAX_LEVELS, MAX_BASIS = 8, 8, 10
 FP64, FP32_REFINE = 0, 1
-FILTER_INPUT, RECORD_PARM, WARM_START = 1, 2, 4
+FILTER_INPUT, RECORD_PARM, WARM_START, INPUT_MASKED = 1, 2, 4, 8
 
 
 class AarmrError(RuntimeError):
@@ -90,7 +90,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                     ctypes.POINTER(CAStats), vp]
     lib.aarmr_filter.argtypes = [P, i32, vp, vp, vp]
     lib.aarmr_setup.argtypes = [P, vp, vp, i64, vp]
-    lib.aarmr_apply_operator.argtypes = [P, i32, vp, vp, vp]
+    lib.aarmr_apply_operator.argtypes = [P, i32, vp, vp, i32, vp]
     lib.aarmr_vcycle.argtypes = [P, vp, vp, vp]
     lib.aarmr_element_energy.argtypes = [P, vp, vp, vp]
     lib.aarmr_oc_update.argtypes = [P, vp, vp, vp, dbl, dbl, vp, vp, vp]
@@ -219,8 +219,8 @@ class Mesh:
     def setup(self, rho_phys, fixed):
         _check(lib().aarmr_setup(self._h, _ptr(rho_phys), _ptr(fixed), fixed.numel(), _stream()))
 
-    def apply(self, v, y, level=0):
-        _check(lib().aarmr_apply_operator(self._h, level, _ptr(v), _ptr(y), _stream()))
+    def apply(self, v, y, level=0, flags=0):
+        _check(lib().aarmr_apply_operator(self._h, level, _ptr(v), _ptr(y), flags, _stream()))
         return y
 
     def vcycle(self, r, z):

@@ -314,10 +314,14 @@ int read_flags(aarmr_mesh* m, unsigned* out, hipStream_t s) {
   return AARMR_OK;
 }
 
-// y = A v on level l.
-int apply(aarmr_mesh* m, int l, const double* v, double* y, hipStream_t s) {
+// y = A v on level l.  Inside the solvers every vector is zero on fixed
+// DOFs (loads and initial guesses are masked, and A, the smoother and the
+// masked transfer operators preserve that), so the fine product skips input
+// masking (mode 2); `any_input` selects the general form.
+int apply(aarmr_mesh* m, int l, const double* v, double* y, hipStream_t s,
+          bool any_input = false) {
   if (l == 0) {
-    launch_ebe(m->lg[0], m->wk, m->E, m->mask, v, y, 0, s);
+    launch_ebe(m->lg[0], m->wk, m->E, m->mask, v, y, any_input ? 0 : 2, s);
     ++m->sweeps;
   } else {
     launch_apply_elemmat(m->lg[l], m->lv[l].Ke, v, y, s);
@@ -636,12 +640,13 @@ int aarmr_setup(aarmr_mesh* m, const double* rho_phys, const int64_t* fixed_dofs
   return setup(m, rho_phys, fixed_dofs, n_fixed, true, S(stream));
 }
 
-int aarmr_apply_operator(aarmr_mesh* m, int32_t level, const double* v, double* y, void* stream) {
+int aarmr_apply_operator(aarmr_mesh* m, int32_t level, const double* v, double* y, int32_t flags,
+                         void* stream) {
   TRY(need_ws(m));
   if (!v || !y || v == y) return fail(AARMR_E_INVALID, "v, y must be distinct non-null");
   if (level < 0 || level >= m->nlev) return fail(AARMR_E_INVALID, "level out of range");
   if (level > 0 && !m->mg_ready) return fail(AARMR_E_STATE, "no hierarchy: call aarmr_setup");
-  return apply(m, level, v, y, S(stream));
+  return apply(m, level, v, y, S(stream), !(flags & AARMR_INPUT_MASKED));
 }
 
 int aarmr_vcycle(aarmr_mesh* m, const double* r, double* z, void* stream) {
@@ -764,7 +769,7 @@ int aarmr_ca_update(aarmr_mesh* m, const double* rho, const double* f, int32_t n
     KCHECK();
     // eq. (15): K_Phi = Phi^T K0 Phi, K0 = K(previous design)
     for (int j = 0; j < Ns; ++j) {
-      launch_ebe(g, m->wk, m->E_prev, m->mask, PhiL + j * n3, m->t0, 0, s);
+      launch_ebe(g, m->wk, m->E_prev, m->mask, PhiL + j * n3, m->t0, 2, s);
       ++m->sweeps;
       KCHECK();
       std::vector<const double*> a(Ns), b(Ns);
@@ -780,7 +785,7 @@ int aarmr_ca_update(aarmr_mesh* m, const double* rho, const double* f, int32_t n
     HIP_TRY(hipMemcpyAsync(m->R, ul, n3 * sizeof(double), hipMemcpyDeviceToDevice, s));
     bool ca_ok = true;
     for (int i = 1; i < Nm; ++i) {
-      launch_ebe(g, m->wk, m->dE, m->mask, m->R + (i - 1) * n3, m->t0, 1, s);
+      launch_ebe(g, m->wk, m->dE, m->mask, m->R + (i - 1) * n3, m->t0, 2, s);
       ++m->sweeps;
       KCHECK();
       std::vector<const double*> a(Ns), b(Ns);
@@ -838,7 +843,7 @@ int aarmr_ca_update(aarmr_mesh* m, const double* rho, const double* f, int32_t n
     if (kept > 0) {
       // eqs. (22)-(25): K_R~ = R~^T K R~, f_R~ = R~^T f, y, u~ = R~ y
       for (int j = 0; j < kept; ++j) {
-        launch_ebe(g, m->wk, m->E, m->mask, m->R + j * n3, m->KR + j * n3, 0, s);
+        launch_ebe(g, m->wk, m->E, m->mask, m->R + j * n3, m->KR + j * n3, 2, s);
         ++m->sweeps;
         KCHECK();
       }

@@ -47,7 +47,9 @@ struct DotSet {
 };
 
 // ---- fine-level operator (element-by-element, reflection-blocked) --------
-// mode 0: y = A v with identity rows on fixed DOFs; mode 1: y = Df K Df v.
+// mode 0: y = A v = Df K Df v + (I - Df) v for any v; mode 1: y = Df K Df v;
+// mode 2: y = Df K v for a v that is zero on fixed DOFs (then equal to both
+// A v and Df K Df v), the form every solver-internal product uses.
 void launch_ebe(const Grid& g, const WalshConsts& K, const double* E, const uint8_t* mask,
                 const double* v, double* y, int mode, hipStream_t s);
 void launch_ebe_f32(const Grid& g, const WalshConsts& K, const float* E, const uint8_t* mask,

@@ -10,14 +10,15 @@
 // mesh is created).  So KE v = W^T B (W v) / 8 costs two 8-point Walsh
 // transforms per component plus ~40 multiply-adds instead of 576.
 //
-// Data flow.  A workgroup of 16 x 16 threads owns 15 x 15 node columns;
-// thread (tx, ty) owns the element column (i, j) = (15 bx - 1 + tx,
-// 15 by - 1 + ty) and marches along z over a chunk of node planes.  The x-y
+// Data flow.  A workgroup of 16 x 16 threads (four 16-lane x-rows per
+// wavefront) owns 14 x 15 node columns; thread (tx, ty) handles the element
+// column (i, j) = (14 bx - 1 + tx, 15 by - 1 + ty) (the last lane of a row
+// only supplies node values) and marches along z over a chunk of node planes.  The x-y
 // Walsh transform of a node plane is computed once and reused by the two
 // element layers that share the plane; the dz = 1 outputs of layer k-1 stay
 // in registers and are added to the dz = 0 outputs of layer k.  The four
 // element columns around a node are combined in a fixed order: x neighbours
-// through DPP row shifts inside 16-lane rows, y neighbours through one
+// through DPP wavefront shifts, y neighbours through one
 // double-buffered LDS exchange per layer.  The next node plane is loaded
 // while the current one is processed.  No atomics: every node is
 // written once by its owner, so results are deterministic.
@@ -30,9 +31,11 @@ namespace {
 
 inline unsigned nblk(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
-// Lane i of each 16-lane row takes the value of lane i+1 (row_shl:1) or
-// lane i-1 (row_shr:1) through DPP; lanes whose source lies outside the row
-// keep their own value.
+// Lane i of a wavefront takes the value of lane i+1 (wave_shl:1) or lane
+// i-1 (wave_shr:1) through DPP; the end lanes keep their own value.  Across
+// the boundary of two 16-lane x-rows this moves a value between the last
+// lane of a row (which only supplies node values) and the first lane of
+// the next (a halo lane that owns nothing), so both results are unused.
 template <int CTRL>
 __device__ inline double dpp(double x) {
   const int lo = __builtin_amdgcn_update_dpp(__double2loint(x), __double2loint(x), CTRL, 0xF, 0xF, false);
@@ -44,12 +47,12 @@ __device__ inline float dpp(float x) {
   const int v = __float_as_int(x);
   return __int_as_float(__builtin_amdgcn_update_dpp(v, v, CTRL, 0xF, 0xF, false));
 }
-constexpr int kRowShl1 = 0x101;
-constexpr int kRowShr1 = 0x111;
+constexpr int kWaveShl1 = 0x130;  // lane i <- lane i+1 across the wavefront
+constexpr int kWaveShr1 = 0x138;  // lane i <- lane i-1
 template <typename T>
-__device__ inline T from_next_lane(T v) { return dpp<kRowShl1>(v); }
+__device__ inline T from_next_lane(T v) { return dpp<kWaveShl1>(v); }
 template <typename T>
-__device__ inline T from_prev_lane(T v) { return dpp<kRowShr1>(v); }
+__device__ inline T from_prev_lane(T v) { return dpp<kWaveShr1>(v); }
 
 // 2D Walsh transform of a 2x2 quad q[cxy] (cxy = dx + 2 dy), in place.
 template <typename T>
@@ -69,6 +72,11 @@ __device__ inline void walsh4(T& q0, T& q1, T& q2, T& q3) {
 // compiler can count outstanding memory operations statically and never has
 // to drain the prefetched plane.
 constexpr uint32_t kOutside = 0x80000000u;
+constexpr int kLanes = 16;           // element columns per x-row
+constexpr int kRows = 16;            // x-rows per workgroup (4 per wavefront)
+constexpr int kTileX = kLanes - 2;   // node columns owned per row
+constexpr int kTileY = kRows - 1;    // node rows owned per workgroup
+constexpr int kThreads = kLanes * kRows;
 constexpr int kBufferWord3 = 0x00020000;  // raw buffer, 32-bit dwords (gfx9)
 
 __device__ inline __amdgpu_buffer_rsrc_t make_rsrc(const void* p, uint32_t bytes) {
@@ -94,25 +102,41 @@ __device__ inline uint32_t ld_u8(__amdgpu_buffer_rsrc_t r, uint32_t off) {
 }
 
 // Raw node values and fixed-DOF masks of one plane as seen by a thread: its
-// own nodes (i, j) and (i, j+1), and for the last lane of a row also
-// (i+1, j), (i+1, j+1) (the other lanes get those from the next lane).
+// nodes (i, j) and (i, j+1); the (i+1) corners come from the next lane.
 template <typename T>
 struct PlaneRaw {
-  T q0[3], q2[3], q1[3], q3[3];
-  uint32_t m0, m2, m1, m3;
+  T q0[3], q2[3];
+  uint32_t m0, m2;
 };
 
-template <typename T, int TZ>
-__global__ void __launch_bounds__(256) k_ebe_z(int nx, int ny, int nz, WalshConsts K,
-                                               const T* __restrict__ E,
-                                               const uint8_t* __restrict__ mask,
-                                               const T* __restrict__ v, T* __restrict__ y,
-                                               int mode) {
-  __shared__ T xs[2][3][16][16];
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  const int i = (int)blockIdx.x * 15 - 1 + tx;
-  const int j = (int)blockIdx.y * 15 - 1 + ty;
-  const int kz0 = (int)blockIdx.z * TZ;
+// y = Df K Df v (zero on fixed DOFs).  MASK_IN: zero the fixed DOFs of v on
+// load; without it the caller guarantees that v is already zero there (true
+// of every vector inside the solvers), which saves the loads and selects.
+// PF: prefetch distance in node planes (1 or 2).
+template <typename T, bool MASK_IN, int PF>
+__global__ void __launch_bounds__(kThreads) k_ebe_z(int nx, int ny, int nz, int gx, int gy, int TZ,
+                                                    WalshConsts K, const T* __restrict__ E,
+                                                    const uint8_t* __restrict__ mask,
+                                                    const T* __restrict__ v, T* __restrict__ y) {
+  __shared__ T xs[2][3][kRows][kLanes];
+  const int tx = threadIdx.x & (kLanes - 1), ty = threadIdx.x / kLanes;
+  // XCD-aware tile order: workgroups are dispatched round-robin over the 8
+  // XCDs, so workgroup w is given tile (w % 8) * (count / 8) + w / 8 and
+  // every XCD walks a contiguous range of tiles.  Tiles that share cache
+  // lines (x neighbours) or halo rows (y neighbours) then meet in one L2.
+  int bx, by, bz;
+  {
+    const int total = gridDim.x;
+    const int w = blockIdx.x;
+    const int xcd = w & 7, pos = w >> 3, q = total >> 3, r = total & 7;
+    const int t = (xcd < r) ? xcd * (q + 1) + pos : r * (q + 1) + (xcd - r) * q + pos;
+    bx = t % gx;
+    by = (t / gx) % gy;
+    bz = t / (gx * gy);
+  }
+  const int i = bx * kTileX - 1 + tx;
+  const int j = by * kTileY - 1 + ty;
+  const int kz0 = bz * TZ;
   const int kz1 = min(kz0 + TZ, nz + 1);
   // 32-bit offsets: the host guarantees 3 * n_node * 8 < 2^31
   const int nxp = nx + 1, nyp = ny + 1;
@@ -122,40 +146,35 @@ __global__ void __launch_bounds__(256) k_ebe_z(int nx, int ny, int nz, WalshCons
   const auto ry = make_rsrc(y, 3u * nn * TS);
   const auto rE = make_rsrc(E, (uint32_t)eplane * nz * TS);
   const auto rm = make_rsrc(mask, (uint32_t)nn);
-  const bool col_ok = i >= 0 && i < nx && j >= 0 && j < ny;
-  const bool xi_ok = i >= 0 && i <= nx, xi1_ok = i + 1 >= 0 && i + 1 <= nx;
+  // the last lane of a row only supplies node values to its left neighbour:
+  // it computes no element and owns no node
+  const bool col_ok = tx < kLanes - 1 && i >= 0 && i < nx && j >= 0 && j < ny;
+  const bool xi_ok = i >= 0 && i <= nx;
   const bool yj_ok = j >= 0 && j <= ny, yj1_ok = j + 1 >= 0 && j + 1 <= ny;
-  const bool own = tx >= 1 && ty >= 1 && i <= nx && j <= ny;
-  const bool last = tx == 15;
+  const bool own = tx >= 1 && tx < kLanes - 1 && ty >= 1 && i <= nx && j <= ny;
   const int off00 = i + nxp * j;
 
   // One select per node: kOutside + c * 3 n_node * sizeof(T) stays out of
   // range (below 2^32, above every buffer size), so components need none.
   const uint32_t cstride = (uint32_t)nn * TS;
-  auto load_node = [&](bool ok, int node, T (&q)[3], uint32_t& m) {
+  auto load_node = [&](bool ok, int node, T (&q)[3], uint32_t& m, bool want_mask) {
     const uint32_t o = ok ? (uint32_t)node * TS : kOutside;
-    m = ld_u8(rm, ok ? (uint32_t)node : kOutside);
+    m = want_mask ? ld_u8(rm, ok ? (uint32_t)node : kOutside) : 0u;
 #pragma unroll
     for (int c = 0; c < 3; ++c) q[c] = ld(rv, o + (uint32_t)c * cstride, T());
   };
   auto load_plane = [&](int k, PlaneRaw<T>& R) {
     const bool kin = k >= 0 && k <= nz;
     const int base = k * plane + off00;
-    load_node(kin && xi_ok && yj_ok, base, R.q0, R.m0);
-    load_node(kin && xi_ok && yj1_ok, base + nxp, R.q2, R.m2);
-    load_node(last && kin && xi1_ok && yj_ok, base + 1, R.q1, R.m1);
-    load_node(last && kin && xi1_ok && yj1_ok, base + nxp + 1, R.q3, R.m3);
+    load_node(kin && xi_ok && yj_ok, base, R.q0, R.m0, true);  // m0 also masks the output
+    load_node(kin && xi_ok && yj1_ok, base + nxp, R.q2, R.m2, MASK_IN);
   };
-  auto masked = [](T x, uint32_t m, int c) { return ((m >> c) & 1u) ? (T)0 : x; };
+  auto masked = [](T x, uint32_t m, int c) { return (MASK_IN && ((m >> c) & 1u)) ? (T)0 : x; };
   auto transform = [&](const PlaneRaw<T>& R, T (&P)[4][3]) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       T a0 = masked(R.q0[c], R.m0, c), a2 = masked(R.q2[c], R.m2, c);
       T a1 = from_next_lane(a0), a3 = from_next_lane(a2);
-      if (last) {
-        a1 = masked(R.q1[c], R.m1, c);
-        a3 = masked(R.q3[c], R.m3, c);
-      }
       walsh4(a0, a1, a2, a3);
       P[0][c] = a0;
       P[1][c] = a1;
@@ -168,35 +187,39 @@ __global__ void __launch_bounds__(256) k_ebe_z(int nx, int ny, int nz, WalshCons
     return ld(rE, ok ? (uint32_t)(i + nx * j + eplane * k) * TS : kOutside, T());
   };
 
-  T Pb[4][3], carry[4][3];
+  T P0[4][3], P1[4][3], carry[4][3];
   {
     PlaneRaw<T> r0;
     load_plane(kz0 - 1, r0);
-    transform(r0, Pb);
+    transform(r0, P0);
   }
-  PlaneRaw<T> R;
-  load_plane(kz0, R);
-  T W = load_w(kz0 - 1);
-  T own_v[3] = {(T)0, (T)0, (T)0};  // raw v and mask of node (i, j) on the plane written next
-  uint32_t own_m = 7u;
+  // PF planes in flight: a plane's loads have PF element layers of work to
+  // arrive in.  The loop is unrolled by two: the two plane transforms swap
+  // the roles of bottom and top instead of being copied, and with PF = 2 the
+  // two raw-plane buffers alternate.
+  PlaneRaw<T> RA, RB;
+  load_plane(kz0, RA);
+  T WA = load_w(kz0 - 1), WB = (T)0;
+  if (PF == 2) {
+    load_plane(kz0 + 1, RB);
+    WB = load_w(kz0);
+  }
+  uint32_t own_m = 7u;  // fixed-DOF mask of node (i, j) on the plane written next
 #pragma unroll
   for (int q = 0; q < 4; ++q)
 #pragma unroll
     for (int c = 0; c < 3; ++c) carry[q][c] = (T)0;
   int buf = 0;
 
-  // Element layer k: node planes k (Pb) and k+1 (R); writes plane k.  The
-  // first layer of a chunk only primes the carry (its stores go outside).
-  for (int k = kz0 - 1; k < kz1; ++k) {
-    T Pt[4][3];
+  // Element layer k: node planes k (Pb) and k+1 (R, transformed into Pt);
+  // writes plane k and refills R with plane k+1+PF.  The first layer of a
+  // chunk only primes the carry (its stores go outside).
+  auto step = [&](int k, PlaneRaw<T>& R, T& W, const T (&Pb)[4][3], T (&Pt)[4][3]) {
     transform(R, Pt);
     const T w = W;
-    T v_next[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) v_next[c] = R.q0[c];
     const uint32_t m_next = R.m0;
-    load_plane(k + 2 <= kz1 ? k + 2 : -2, R);  // prefetch plane k+2
-    W = load_w(k + 1 < kz1 ? k + 1 : -1);
+    load_plane(k + 1 + PF <= kz1 ? k + 1 + PF : -2, R);
+    W = load_w(k + PF < kz1 ? k + PF : -1);
     T h[8][3], z[8][3];
 #pragma unroll
     for (int q = 0; q < 4; ++q)
@@ -206,7 +229,8 @@ __global__ void __launch_bounds__(256) k_ebe_z(int nx, int ny, int nz, WalshCons
         h[q + 4][c] = Pb[q][c] - Pt[q][c];
       }
     walsh_blocks<T>(K, w, h, z);
-    // plane k: carry (dz=1 of layer k-1) + dz=0 of layer k, back to corners
+    // plane k: carry (dz=1 of layer k-1) + dz=0 of layer k, back to corners;
+    // the carry is then replaced by the dz=1 part of layer k
     T cor[4][3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -214,6 +238,10 @@ __global__ void __launch_bounds__(256) k_ebe_z(int nx, int ny, int nz, WalshCons
       T a1 = carry[1][c] + (z[1][c] + z[5][c]);
       T a2 = carry[2][c] + (z[2][c] + z[6][c]);
       T a3 = carry[3][c] + (z[3][c] + z[7][c]);
+      carry[0][c] = z[0][c] - z[4][c];
+      carry[1][c] = z[1][c] - z[5][c];
+      carry[2][c] = z[2][c] - z[6][c];
+      carry[3][c] = z[3][c] - z[7][c];
       walsh4(a0, a1, a2, a3);
       cor[0][c] = a0;
       cor[1][c] = a1;
@@ -232,23 +260,18 @@ __global__ void __launch_bounds__(256) k_ebe_z(int nx, int ny, int nz, WalshCons
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       T out = X0[c] + xs[buf][c][ty > 0 ? ty - 1 : 0][tx];
-      if ((own_m >> c) & 1u) out = mode == 0 ? own_v[c] : (T)0;
+      if ((own_m >> c) & 1u) out = (T)0;
       st(ry, oy + (uint32_t)c * cstride, out);
     }
     buf ^= 1;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      carry[0][c] = z[0][c] - z[4][c];
-      carry[1][c] = z[1][c] - z[5][c];
-      carry[2][c] = z[2][c] - z[6][c];
-      carry[3][c] = z[3][c] - z[7][c];
-      own_v[c] = v_next[c];
-    }
     own_m = m_next;
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-#pragma unroll
-      for (int c = 0; c < 3; ++c) Pb[q][c] = Pt[q][c];
+  };
+  for (int k = kz0 - 1; k < kz1; k += 2) {
+    step(k, RA, WA, P0, P1);
+    if (k + 1 < kz1) {
+      if (PF == 2) step(k + 1, RB, WB, P1, P0);
+      else step(k + 1, RA, WA, P1, P0);
+    }
   }
 }
 
@@ -301,30 +324,69 @@ __global__ void __launch_bounds__(256) k_energy_walsh(int nx, int ny, int nz, Wa
 
 }  // namespace
 
-// z-chunk of node planes per workgroup: the longest chunk that still gives
-// at least four workgroups per compute unit (256 CUs), 4 at the least.
+// y[fixed] = v[fixed]: the identity rows of A on fixed DOFs.
 template <typename T>
+__global__ void k_identity_rows(int64_t nn, const uint8_t* __restrict__ mask,
+                                const T* __restrict__ v, T* __restrict__ y) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= nn) return;
+  const uint32_t m = mask[n];
+  if (!m) return;
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+    if ((m >> c) & 1u) y[c * nn + n] = v[c * nn + n];
+}
+
+// z-chunk of node planes per workgroup.  A chunk costs one extra element
+// layer (the carry is primed from the layer below it), so chunks are made
+// as long as possible while the grid still fills every resident workgroup
+// slot of the device in a single round; at least 4 planes per chunk.
+#ifndef AARMR_EBE_PF
+#define AARMR_EBE_PF 1
+#endif
+
+template <typename T, bool MASK_IN>
 static void launch_ebe_t(const Grid& g, const WalshConsts& K, const T* E, const uint8_t* mask,
-                         const T* v, T* y, int mode, hipStream_t s) {
-  const unsigned gx = (unsigned)((g.nx + 1 + 14) / 15), gy = (unsigned)((g.ny + 1 + 14) / 15);
+                         const T* v, T* y, hipStream_t s) {
+  static int slots = 0;  // resident workgroups of this kernel on the device
+  if (slots == 0) {
+    int dev = 0, cus = 0, per_cu = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_ebe_z<T, MASK_IN, AARMR_EBE_PF>,
+                                                       kThreads, 0);
+    slots = (cus > 0 && per_cu > 0) ? cus * per_cu : 512;
+  }
+  const int gx = (g.nx + 1 + kTileX - 1) / kTileX;
+  const int gy = (g.ny + 1 + kTileY - 1) / kTileY;
   const int planes = g.nz + 1;
-  auto gz = [&](int tz) { return (unsigned)((planes + tz - 1) / tz); };
-  if ((int64_t)gx * gy * gz(16) >= 1024)
-    k_ebe_z<T, 16><<<dim3(gx, gy, gz(16)), 256, 0, s>>>(g.nx, g.ny, g.nz, K, E, mask, v, y, mode);
-  else if ((int64_t)gx * gy * gz(8) >= 1024)
-    k_ebe_z<T, 8><<<dim3(gx, gy, gz(8)), 256, 0, s>>>(g.nx, g.ny, g.nz, K, E, mask, v, y, mode);
-  else
-    k_ebe_z<T, 4><<<dim3(gx, gy, gz(4)), 256, 0, s>>>(g.nx, g.ny, g.nz, K, E, mask, v, y, mode);
+  int gz = slots / (gx * gy);
+  gz = gz < 1 ? 1 : (gz > planes ? planes : gz);
+  int tz = (planes + gz - 1) / gz;
+  if (tz < 4) tz = 4;
+  gz = (planes + tz - 1) / tz;
+  k_ebe_z<T, MASK_IN, AARMR_EBE_PF><<<(unsigned)(gx * gy * gz), kThreads, 0, s>>>(g.nx, g.ny, g.nz, gx, gy, tz, K,
+                                                                     E, mask, v, y);
 }
 
 void launch_ebe(const Grid& g, const WalshConsts& K, const double* E, const uint8_t* mask,
                 const double* v, double* y, int mode, hipStream_t s) {
-  launch_ebe_t<double>(g, K, E, mask, v, y, mode, s);
+  if (mode == 2) {
+    launch_ebe_t<double, false>(g, K, E, mask, v, y, s);
+    return;
+  }
+  launch_ebe_t<double, true>(g, K, E, mask, v, y, s);
+  if (mode == 0) k_identity_rows<double><<<nblk(g.nn, 256), 256, 0, s>>>(g.nn, mask, v, y);
 }
 
 void launch_ebe_f32(const Grid& g, const WalshConsts& K, const float* E, const uint8_t* mask,
                     const float* v, float* y, int mode, hipStream_t s) {
-  launch_ebe_t<float>(g, K, E, mask, v, y, mode, s);
+  if (mode == 2) {
+    launch_ebe_t<float, false>(g, K, E, mask, v, y, s);
+    return;
+  }
+  launch_ebe_t<float, true>(g, K, E, mask, v, y, s);
+  if (mode == 0) k_identity_rows<float><<<nblk(g.nn, 256), 256, 0, s>>>(g.nn, mask, v, y);
 }
 
 void launch_energy_walsh(const Grid& g, const WalshConsts& K, const uint8_t* mask,

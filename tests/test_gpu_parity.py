@@ -37,6 +37,13 @@ def test_operator_apply_matches_assembled(nx, ny, nz, lev):
     A = fem.operator_with_bc(K, fem.fixed_dofs_aos(prob))
     want = soa(A @ aos(v))
     assert rel(y.cpu().numpy(), want) < 1e-13
+    # the solver-internal form: input zero on fixed DOFs, no masking on load
+    from paper_2205_00385_amd import aarmr
+
+    vm = aos(v)
+    vm[fem.fixed_dofs_aos(prob)] = 0.0
+    m.apply(t64(soa(vm)), y, flags=aarmr.INPUT_MASKED)
+    assert rel(y.cpu().numpy(), soa(A @ vm)) < 1e-13
 
 
 def test_operator_apply_is_deterministic():
