@@ -76,11 +76,16 @@ struct aarmr_mesh {
   double KE[576];
   WalshConsts wk;             // reflection-blocked form of KE
   double Mc[8 * kSymEntries]; // P_c^T KE P_c per child position, packed
+  double Mf[8 * 72];          // child 0's, row blocks: [a][col][r] = M_0[3a + r][col]
   // workspace views
   char* ws = nullptr;
   int64_t ws_bytes = 0;
   double* KEd = nullptr;
   double* Mcd = nullptr;      // P_c^T KE P_c of the 8 children, packed
+  double* Mfd = nullptr;      // the same as row blocks (Mf)
+  uint8_t* eflag1 = nullptr;  // level-1 parents touching a fixed DOF
+  int* list1 = nullptr;       // their indices
+  int* count1 = nullptr;
   double* E = nullptr;
   double* E_prev = nullptr;
   double* dE = nullptr;
@@ -93,7 +98,7 @@ struct aarmr_mesh {
   double *r = nullptr, *z = nullptr, *pv = nullptr, *q = nullptr, *t0 = nullptr, *fm = nullptr;
   LevelBuf lv[AARMR_MAX_LEVELS];
   double* Ainv = nullptr;
-  double *gjP = nullptr, *gjT = nullptr, *gjR = nullptr;
+  double *gjP = nullptr, *gjT = nullptr, *gjC = nullptr;
   double* Phi = nullptr;   // [n_rhs_max][Ns][3nn]
   double* R = nullptr;     // [Nm][3nn]
   double* KR = nullptr;    // [Nm][3nn]
@@ -211,6 +216,22 @@ void child_galerkin(const double* KE, double* Mc) {
   }
 }
 
+// Check M_c = R_c M_0 R_c for every child c, where R_c mirrors the parent in
+// the axes set in c: (R_c v)[3b + s] = (-1)^(bit s of c) v[3(b ^ c) + s].
+bool mirror_children(const double* Mc) {
+  double scale = 0.0;
+  for (int x = 0; x < kSymEntries; ++x) scale = std::max(scale, std::fabs(Mc[x]));
+  for (int c = 1; c < 8; ++c)
+    for (int I = 0; I < 24; ++I)
+      for (int J = I; J < 24; ++J) {
+        const int a = I / 3, r = I % 3, b = J / 3, q = J % 3;
+        const double sg = (((c >> r) ^ (c >> q)) & 1) ? -1.0 : 1.0;
+        const double ref = sg * Mc[sym_index(3 * (a ^ c) + r, 3 * (b ^ c) + q)];
+        if (std::fabs(Mc[c * kSymEntries + sym_index(I, J)] - ref) > 1e-12 * scale) return false;
+      }
+  return true;
+}
+
 // Assign workspace views; with base == nullptr only computes the size.
 int64_t layout(aarmr_mesh* m, char* base) {
   int64_t off = 0;
@@ -224,6 +245,10 @@ int64_t layout(aarmr_mesh* m, char* base) {
   const int64_t d8 = sizeof(double);
   m->KEd = (double*)take(576 * d8);
   m->Mcd = (double*)take(8 * kSymEntries * d8);
+  m->Mfd = (double*)take(8 * 72 * d8);
+  m->eflag1 = (uint8_t*)take(m->lg[1].ne);
+  m->list1 = (int*)take(m->lg[1].ne * 4);
+  m->count1 = (int*)take(4);
   m->E = (double*)take(g.ne * d8);
   m->E_prev = (double*)take(g.ne * d8);
   m->dE = (double*)take(g.ne * d8);
@@ -254,7 +279,7 @@ int64_t layout(aarmr_mesh* m, char* base) {
   m->Ainv = (double*)take((int64_t)m->nc * m->nc * d8);
   m->gjP = (double*)take(kGJBlock * kGJBlock * d8);
   m->gjT = (double*)take((int64_t)m->nc * kGJBlock * d8);
-  m->gjR = (double*)take((int64_t)m->nc * kGJBlock * d8);
+  m->gjC = (double*)take((int64_t)m->nc * kGJBlock * d8);
   m->Phi = (double*)take((int64_t)m->p.n_rhs_max * m->p.Ns * n3 * d8);
   m->R = (double*)take((int64_t)m->p.Nm * n3 * d8);
   m->KR = (double*)take((int64_t)m->p.Nm * n3 * d8);
@@ -323,6 +348,8 @@ int apply(aarmr_mesh* m, int l, const double* v, double* y, hipStream_t s,
   if (l == 0) {
     launch_ebe(m->lg[0], m->wk, m->E, m->mask, v, y, any_input ? 0 : 2, s);
     ++m->sweeps;
+  } else if (l == 1) {
+    launch_apply_elemmat_mf(m->lg[1], m->lv[1].Ke, m->Mfd, m->E, m->eflag1, v, y, s);
   } else {
     launch_apply_elemmat(m->lg[l], m->lv[l].Ke, v, y, s);
   }
@@ -384,7 +411,8 @@ int setup(aarmr_mesh* m, const double* rho, const int64_t* fixed, int64_t nfixed
   KCHECK();
   for (int l = 1; l < m->nlev; ++l) {
     if (l == 1)
-      launch_galerkin_from_fine(m->lg[1], m->KEd, m->Mcd, m->E, m->mask, m->lv[1].Ke, s);
+      launch_galerkin_from_fine(m->lg[1], m->KEd, m->Mcd, m->E, m->mask, m->eflag1, m->list1,
+                                m->count1, m->lv[1].Ke, s);
     else
       launch_galerkin_from_coarse(m->lg[l], m->lv[l - 1].Ke, m->lv[l].Ke, s);
     KCHECK();
@@ -395,7 +423,7 @@ int setup(aarmr_mesh* m, const double* rho, const int64_t* fixed, int64_t nfixed
   }
   launch_assemble_dense(m->lg[m->nlev - 1], m->lv[m->nlev - 1].Ke, m->Ainv, s);
   KCHECK();
-  launch_gj_invert(m->nc, m->Ainv, m->gjP, m->gjT, m->gjR, s);
+  launch_gj_invert(m->nc, m->Ainv, m->gjP, m->gjT, m->gjC, s);
   KCHECK();
   m->mg_ready = true;
   return AARMR_OK;
@@ -586,6 +614,14 @@ int aarmr_mesh_create(const aarmr_params* p, aarmr_mesh** out) {
   }
   hex8_stiffness(p->nu, m->KE);  // unit modulus; E0 enters through SIMP
   child_galerkin(m->KE, m->Mc);
+  for (int a = 0; a < 8; ++a)
+    for (int q = 0; q < 24; ++q)
+      for (int r = 0; r < 3; ++r)
+        m->Mf[(a * 24 + q) * 3 + r] = m->Mc[sym_index(3 * a + r, q)];
+  if (!mirror_children(m->Mc)) {
+    delete m;
+    return fail(AARMR_E_INVALID, "child Galerkin matrices are not mirror images of child 0's");
+  }
   if (!walsh_form(m->KE, &m->wk)) {
     delete m;
     return fail(AARMR_E_INVALID, "element stiffness lacks the reflection-blocked structure");
@@ -619,6 +655,7 @@ int aarmr_bind_workspace(aarmr_mesh* m, void* dev_ptr, int64_t bytes, void* stre
   hipStream_t s = S(stream);
   HIP_TRY(hipMemcpyAsync(m->KEd, m->KE, 576 * sizeof(double), hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(m->Mcd, m->Mc, 8 * kSymEntries * sizeof(double), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(m->Mfd, m->Mf, 8 * 72 * sizeof(double), hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemsetAsync(m->flags, 0, 64, s));
   HIP_TRY(hipMemsetAsync(m->mask, 0, (m->lg[0].nn + 3) / 4 * 4, s));
   if (m->p.rmin > 0.0) {

@@ -75,11 +75,20 @@ constexpr int kSymEntries = 300;
 __host__ __device__ constexpr int sym_index(int r, int c) {
   return r <= c ? r * 24 - (r * (r - 1)) / 2 + (c - r) : c * 24 - (c * (c - 1)) / 2 + (r - c);
 }
+// Level-1 operators from the fine moduli: fast path for every parent, exact
+// masked product for the parents flagged in eflag (1 = touches a fixed DOF),
+// whose indices are listed in list[0..*count).
 void launch_galerkin_from_fine(const Grid& coarse, const double* KE, const double* Mc,
-                               const double* E, const uint8_t* mask, double* Kc, hipStream_t s);
+                               const double* E, const uint8_t* mask, uint8_t* eflag, int* list,
+                               int* count, double* Kc, hipStream_t s);
 void launch_galerkin_from_coarse(const Grid& coarse, const double* Kf, double* Kc, hipStream_t s);
 void launch_apply_elemmat(const Grid& g, const double* Ke, const double* v, double* y,
                           hipStream_t s);
+// Level-1 product: unflagged parents from the fine moduli Ef and child 0's
+// matrix as row blocks, Mf[a][col][r] = (P_0^T KE P_0)[3a + r][col] (the
+// other children are its mirror images); flagged parents from Ke.
+void launch_apply_elemmat_mf(const Grid& g, const double* Ke, const double* Mf, const double* Ef,
+                             const uint8_t* eflag, const double* v, double* y, hipStream_t s);
 void launch_diag_elemmat(const Grid& g, const double* Ke, double* dinv, float* dinv32,
                          hipStream_t s);
 void launch_restrict(const Grid& coarse, const double* bf, const double* tf, const uint8_t* mask,
@@ -91,7 +100,7 @@ void launch_jacobi_first(int64_t n3, const double* b, const double* dinv, double
 void launch_jacobi_update(int64_t n3, const double* b, const double* t, const double* dinv,
                           double omega, double* x, hipStream_t s);
 void launch_assemble_dense(const Grid& g, const double* Ke, double* A, hipStream_t s);
-void launch_gj_invert(int n, double* A, double* P, double* T, double* Rw, hipStream_t s);
+void launch_gj_invert(int n, double* A, double* P, double* T, double* C, hipStream_t s);
 void launch_gemv(int n, const double* A, const double* x, double* y, hipStream_t s);
 
 // ---- vector kernels and reductions ----------------------------------------

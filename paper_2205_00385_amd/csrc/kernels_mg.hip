@@ -3,6 +3,8 @@
 // diagonals, restriction P^T and interpolation P (trilinear, 2:1 per axis),
 // damped-Jacobi smoothing, and the exact coarsest solve through an explicit
 // inverse computed by blocked Gauss-Jordan elimination.
+#include <algorithm>
+
 #include "internal.hpp"
 
 namespace aarmr {
@@ -55,43 +57,65 @@ __global__ void __launch_bounds__(256) k_galerkin_fast(int cnx, int cny, int cnz
   }
 }
 
-// Galerkin matrix of one parent per block: the 8 child matrices are staged
-// in LDS, T_c = K_c P_c is formed by a column pass and sum_c P_c^T T_c by a
-// row pass.  FROM_FINE: children are E_c Df KE Df with the fine fixed-DOF
-// mask, and only parents touching a fixed DOF are written.  Otherwise the
-// children are the previous level's packed matrices.
+// Level-1 parents touching a fixed DOF: eflag[e] = 1 (else 0) and the
+// indices of the flagged parents appended to list (in no particular order;
+// every entry is processed independently).  *count must be zero on entry.
+__global__ void k_parent_flags(int cnx, int cny, int cnz, const uint8_t* __restrict__ mask,
+                               uint8_t* __restrict__ eflag, int* __restrict__ list,
+                               int* __restrict__ count) {
+  const int64_t cne = (int64_t)cnx * cny * cnz;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= cne) return;
+  const int cx = (int)(e % cnx);
+  const int64_t rest = e / cnx;
+  const int cy = (int)(rest % cny), cz = (int)(rest / cny);
+  const int fnx = 2 * cnx, fny = 2 * cny;
+  unsigned any = 0;
+  for (int t = 0; t < 27; ++t)
+    any |= mask[node_of(fnx, fny, 2 * cx + t % 3, 2 * cy + (t / 3) % 3, 2 * cz + t / 9)];
+  eflag[e] = any ? 1 : 0;
+  if (any) list[atomicAdd(count, 1)] = (int)e;
+}
+
+__global__ void k_zero_int(int* p) { *p = 0; }
+
+// Galerkin matrix of one parent per block iteration: the 8 child matrices
+// are staged in LDS, T_c = K_c P_c is formed by a column pass and
+// sum_c P_c^T T_c by a row pass.  FROM_FINE: children are E_c Df KE Df with
+// the fine fixed-DOF mask, for the parents listed by k_parent_flags (the
+// others are exact from the fast path).  Otherwise every parent, with the
+// previous level's packed matrices as children.
 template <bool FROM_FINE>
 __global__ void __launch_bounds__(256) k_galerkin_lds(int cnx, int cny, int cnz,
                                                       const double* __restrict__ KE,
                                                       const double* __restrict__ E,
                                                       const uint8_t* __restrict__ mask,
+                                                      const int* __restrict__ list,
+                                                      const int* __restrict__ count,
                                                       const double* __restrict__ Kf,
                                                       double* __restrict__ Kc) {
   __shared__ double sK[8][24][25];
   __shared__ uint8_t sm[27];
   __shared__ double sw[8];
-  __shared__ int any_fixed;
   const int64_t cne = (int64_t)cnx * cny * cnz;
-  const int64_t eid = blockIdx.x;
-  const int cx = (int)(eid % cnx);
-  const int64_t rest = eid / cnx;
-  const int cy = (int)(rest % cny), cz = (int)(rest / cny);
   const int fnx = 2 * cnx, fny = 2 * cny;
   const int64_t fne = cne * 8;
   const int tid = threadIdx.x;
+  const int64_t nwork = FROM_FINE ? (int64_t)*count : cne;
+  for (int64_t w = blockIdx.x; w < nwork; w += gridDim.x) {
+  const int64_t eid = FROM_FINE ? (int64_t)list[w] : w;
+  const int cx = (int)(eid % cnx);
+  const int64_t rest = eid / cnx;
+  const int cy = (int)(rest % cny), cz = (int)(rest / cny);
   if (FROM_FINE) {
-    if (tid == 0) any_fixed = 0;
-    __syncthreads();
     if (tid < 27) {
       const int px = tid % 3, py = (tid / 3) % 3, pz = tid / 9;
       sm[tid] = mask[node_of(fnx, fny, 2 * cx + px, 2 * cy + py, 2 * cz + pz)];
-      if (sm[tid]) atomicOr(&any_fixed, 1);
     }
     if (tid < 8)
       sw[tid] = E[(int64_t)(2 * cx + (tid & 1)) +
                   (int64_t)fnx * ((2 * cy + ((tid >> 1) & 1)) + (int64_t)fny * (2 * cz + (tid >> 2)))];
     __syncthreads();
-    if (!any_fixed) return;  // block-uniform: the fast path already wrote it
   }
   for (int t = tid; t < 8 * 576; t += 256) {
     const int c = t / 576, r = (t % 576) / 24, q = t % 24;
@@ -150,43 +174,91 @@ __global__ void __launch_bounds__(256) k_galerkin_lds(int cnx, int cny, int cnz,
     }
     Kc[(int64_t)sx * cne + eid] = acc;
   }
+  __syncthreads();  // sK, sm, sw are reused by the next parent
+  }
 }
 
-// y = sum_e L_e^T Ke_e L_e v for packed element matrices; thread per node.
-template <typename T>
-__global__ void __launch_bounds__(256) k_apply_elemmat(int nx, int ny, int nz,
-                                                       const T* __restrict__ Ke,
-                                                       const T* __restrict__ v,
-                                                       T* __restrict__ y) {
+// y = sum_e L_e^T Ke_e L_e v on a coarse level.  Block: 64 consecutive nodes
+// x 8 waves; wave a takes each node as local corner a of the element
+// e = node - offset(a) and forms rows 3a..3a+2 of Ke_e v_e; the 8 partial
+// rows are summed in LDS in a fixed order.  MATFREE (level 1): elements with
+// eflag 0 (no fixed DOF among their 27 fine nodes) use
+// Ke_e = sum_c E_child(c) M_c, the Galerkin product of their 8 unmasked
+// children.  Child c is the mirror image of child 0 in the axes set in c, so
+// M_c = R_c M_0 R_c with (R_c v)[3b + s] = (-1)^(bit s of c) v[3(b ^ c) + s],
+// and only M_0 (row blocks Mf[a][col][r] = M_0[3a + r][col]) is read, as
+// wave-uniform (scalar) operands.  The other elements use the stored matrix.
+template <bool MATFREE>
+__global__ void __launch_bounds__(512) k_apply_elemmat(int nx, int ny, int nz,
+                                                       const double* __restrict__ Ke,
+                                                       const double* __restrict__ Mf,
+                                                       const double* __restrict__ Ef,
+                                                       const uint8_t* __restrict__ eflag,
+                                                       const double* __restrict__ v,
+                                                       double* __restrict__ y) {
+  __shared__ double red[8][3][64];
+  const int a = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int lane = threadIdx.x & 63;
   const int64_t nn = (int64_t)(nx + 1) * (ny + 1) * (nz + 1);
   const int64_t ne = (int64_t)nx * ny * nz;
-  int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= nn) return;
-  const int i = (int)(n % (nx + 1));
-  const int64_t rest = n / (nx + 1);
-  const int j = (int)(rest % (ny + 1));
-  const int k = (int)(rest / (ny + 1));
-  T acc0 = 0, acc1 = 0, acc2 = 0;
-#pragma unroll
-  for (int a = 0; a < 8; ++a) {  // the node is local corner a of element (i,j,k) - offset(a)
+  const int64_t n = (int64_t)blockIdx.x * 64 + lane;
+  double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
+  if (n < nn) {
+    const int i = (int)(n % (nx + 1));
+    const int64_t rest = n / (nx + 1);
+    const int j = (int)(rest % (ny + 1));
+    const int k = (int)(rest / (ny + 1));
     const int ex = i - (a & 1), ey = j - ((a >> 1) & 1), ez = k - (a >> 2);
-    if (ex < 0 || ex >= nx || ey < 0 || ey >= ny || ez < 0 || ez >= nz) continue;
-    const int64_t e = (int64_t)ex + (int64_t)nx * ((int64_t)ey + (int64_t)ny * ez);
+    if (ex >= 0 && ex < nx && ey >= 0 && ey < ny && ez >= 0 && ez < nz) {
+      const int64_t e = (int64_t)ex + (int64_t)nx * ((int64_t)ey + (int64_t)ny * ez);
+      double ve[24];
 #pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      const int64_t nb = node_of(nx, ny, ex + (b & 1), ey + ((b >> 1) & 1), ez + (b >> 2));
+      for (int b = 0; b < 8; ++b) {
+        const int64_t nb = node_of(nx, ny, ex + (b & 1), ey + ((b >> 1) & 1), ez + (b >> 2));
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const T vb = v[c * nn + nb];
-        acc0 = fma(Ke[(int64_t)sidx(3 * a + 0, 3 * b + c) * ne + e], vb, acc0);
-        acc1 = fma(Ke[(int64_t)sidx(3 * a + 1, 3 * b + c) * ne + e], vb, acc1);
-        acc2 = fma(Ke[(int64_t)sidx(3 * a + 2, 3 * b + c) * ne + e], vb, acc2);
+        for (int c = 0; c < 3; ++c) ve[3 * b + c] = v[c * nn + nb];
+      }
+      if (MATFREE && eflag[e] == 0) {
+        const int fnx = 2 * nx, fny = 2 * ny;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+          const double Ec = Ef[(int64_t)(2 * ex + (c & 1)) +
+                               (int64_t)fnx * ((2 * ey + ((c >> 1) & 1)) +
+                                               (int64_t)fny * (2 * ez + (c >> 2)))];
+          const double* M = Mf + (a ^ c) * 72;
+          double t0 = 0.0, t1 = 0.0, t2 = 0.0;
+#pragma unroll
+          for (int q = 0; q < 24; ++q) {
+            const int b = q / 3, sc = q % 3;
+            const double w = ((c >> sc) & 1) ? -ve[3 * (b ^ c) + sc] : ve[3 * (b ^ c) + sc];
+            t0 = fma(M[3 * q + 0], w, t0);
+            t1 = fma(M[3 * q + 1], w, t1);
+            t2 = fma(M[3 * q + 2], w, t2);
+          }
+          acc0 = fma((c & 1) ? -Ec : Ec, t0, acc0);
+          acc1 = fma((c & 2) ? -Ec : Ec, t1, acc1);
+          acc2 = fma((c & 4) ? -Ec : Ec, t2, acc2);
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < 24; ++q) {
+          acc0 = fma(Ke[(int64_t)sidx(3 * a + 0, q) * ne + e], ve[q], acc0);
+          acc1 = fma(Ke[(int64_t)sidx(3 * a + 1, q) * ne + e], ve[q], acc1);
+          acc2 = fma(Ke[(int64_t)sidx(3 * a + 2, q) * ne + e], ve[q], acc2);
+        }
       }
     }
   }
-  y[n] = acc0;
-  y[nn + n] = acc1;
-  y[2 * nn + n] = acc2;
+  red[a][0][lane] = acc0;
+  red[a][1][lane] = acc1;
+  red[a][2][lane] = acc2;
+  __syncthreads();
+  if (a < 3 && n < nn) {
+    double sum = red[0][a][lane];
+#pragma unroll
+    for (int q = 1; q < 8; ++q) sum += red[q][a][lane];
+    y[a * nn + n] = sum;
+  }
 }
 
 __global__ void k_diag_elemmat(int nx, int ny, int nz, const double* __restrict__ Ke,
@@ -215,81 +287,93 @@ __global__ void k_diag_elemmat(int nx, int ny, int nz, const double* __restrict_
   }
 }
 
-// bc = P^T Df (bf - tf): thread per coarse node, 27-point gather with
-// weights (1/2, 1, 1/2) per axis.  mask == nullptr: no fine fixed DOFs.
+// bc = P^T Df (bf - tf) (tf == nullptr: bf alone), weights (1/2, 1, 1/2)
+// per axis.  One thread per (coarse node, fine z-offset) and component
+// (grid.y); the three z-planes of a coarse node are summed in LDS.
+// mask == nullptr: no fine fixed DOFs.
 template <typename T>
-__global__ void k_restrict(int cnx, int cny, int cnz, const T* __restrict__ bf,
-                           const T* __restrict__ tf, const uint8_t* __restrict__ mask,
-                           T* __restrict__ bc) {
+__global__ void __launch_bounds__(192) k_restrict(int cnx, int cny, int cnz,
+                                                  const T* __restrict__ bf,
+                                                  const T* __restrict__ tf,
+                                                  const uint8_t* __restrict__ mask,
+                                                  T* __restrict__ bc) {
+  __shared__ T part[3][64];
+  const int lane = threadIdx.x & 63, dzi = threadIdx.x >> 6;
+  const int c = blockIdx.y;
   const int64_t cnn = (int64_t)(cnx + 1) * (cny + 1) * (cnz + 1);
-  int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= cnn) return;
+  const int64_t n = (int64_t)blockIdx.x * 64 + lane;
   const int fnx = 2 * cnx, fny = 2 * cny, fnz = 2 * cnz;
   const int64_t fnn = (int64_t)(fnx + 1) * (fny + 1) * (fnz + 1);
-  int I = (int)(n % (cnx + 1));
-  int64_t rest = n / (cnx + 1);
-  int J = (int)(rest % (cny + 1));
-  int K = (int)(rest / (cny + 1));
-  T acc[3] = {0, 0, 0};
-  for (int dz = -1; dz <= 1; ++dz) {
-    int fk = 2 * K + dz;
-    if (fk < 0 || fk > fnz) continue;
-    for (int dy = -1; dy <= 1; ++dy) {
-      int fj = 2 * J + dy;
-      if (fj < 0 || fj > fny) continue;
-      for (int dx = -1; dx <= 1; ++dx) {
-        int fi = 2 * I + dx;
-        if (fi < 0 || fi > fnx) continue;
-        const T w = (dx ? T(0.5) : T(1)) * (dy ? T(0.5) : T(1)) * (dz ? T(0.5) : T(1));
-        const int64_t fnode = node_of(fnx, fny, fi, fj, fk);
-        const uint8_t m = mask ? mask[fnode] : 0;
+  T acc = 0;
+  if (n < cnn) {
+    const int I = (int)(n % (cnx + 1));
+    const int64_t rest = n / (cnx + 1);
+    const int J = (int)(rest % (cny + 1));
+    const int K = (int)(rest / (cny + 1));
+    const int fk = 2 * K + dzi - 1;
+    if (fk >= 0 && fk <= fnz) {
+      const T wz = dzi == 1 ? T(1) : T(0.5);
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          if ((m >> c) & 1) continue;
-          acc[c] += w * (bf[c * fnn + fnode] - tf[c * fnn + fnode]);
+      for (int dy = -1; dy <= 1; ++dy) {
+        const int fj = 2 * J + dy;
+        if (fj < 0 || fj > fny) continue;
+        const T wyz = (dy ? T(0.5) : T(1)) * wz;
+#pragma unroll
+        for (int dx = -1; dx <= 1; ++dx) {
+          const int fi = 2 * I + dx;
+          if (fi < 0 || fi > fnx) continue;
+          const T w = (dx ? T(0.5) : T(1)) * wyz;
+          const int64_t f = node_of(fnx, fny, fi, fj, fk);
+          const bool fixed = mask && ((mask[f] >> c) & 1);
+          const T val = tf ? bf[c * fnn + f] - tf[c * fnn + f] : bf[c * fnn + f];
+          if (!fixed) acc = fma(w, val, acc);
         }
       }
     }
   }
-  bc[n] = acc[0];
-  bc[cnn + n] = acc[1];
-  bc[2 * cnn + n] = acc[2];
+  part[dzi][lane] = acc;
+  __syncthreads();
+  if (dzi == 0 && n < cnn) bc[c * cnn + n] = part[0][lane] + part[1][lane] + part[2][lane];
 }
 
-// xf += Df P xc: thread per fine node.
+// xf += Df P xc: thread per fine node, branch-free over the (up to) 8
+// parent nodes: along an axis an even fine index takes its parent with
+// weight 1, an odd one both neighbours with weight 1/2.
 template <typename T>
-__global__ void k_prolong_add(int fnx, int fny, int fnz, const T* __restrict__ xc,
-                              const uint8_t* __restrict__ mask, T* __restrict__ xf) {
+__global__ void __launch_bounds__(256) k_prolong_add(int fnx, int fny, int fnz,
+                                                     const T* __restrict__ xc,
+                                                     const uint8_t* __restrict__ mask,
+                                                     T* __restrict__ xf) {
   const int64_t fnn = (int64_t)(fnx + 1) * (fny + 1) * (fnz + 1);
-  int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= fnn) return;
   const int cnx = fnx / 2, cny = fny / 2, cnz = fnz / 2;
   const int64_t cnn = (int64_t)(cnx + 1) * (cny + 1) * (cnz + 1);
-  int fi = (int)(n % (fnx + 1));
-  int64_t rest = n / (fnx + 1);
-  int fj = (int)(rest % (fny + 1));
-  int fk = (int)(rest / (fny + 1));
+  const int fi = (int)(n % (fnx + 1));
+  const int64_t rest = n / (fnx + 1);
+  const int fj = (int)(rest % (fny + 1));
+  const int fk = (int)(rest / (fny + 1));
+  const int ix[2] = {fi >> 1, (fi + 1) >> 1};
+  const int iy[2] = {fj >> 1, (fj + 1) >> 1};
+  const int iz[2] = {fk >> 1, (fk + 1) >> 1};
+  const T wx[2] = {(fi & 1) ? T(0.5) : T(1), (fi & 1) ? T(0.5) : T(0)};
+  const T wy[2] = {(fj & 1) ? T(0.5) : T(1), (fj & 1) ? T(0.5) : T(0)};
+  const T wz[2] = {(fk & 1) ? T(0.5) : T(1), (fk & 1) ? T(0.5) : T(0)};
+  int64_t id[8];
+  T w[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    id[q] = node_of(cnx, cny, ix[q & 1], iy[(q >> 1) & 1], iz[q >> 2]);
+    w[q] = wx[q & 1] * wy[(q >> 1) & 1] * wz[q >> 2];
+  }
   const uint8_t m = mask ? mask[n] : 0;
-  int ix0 = fi >> 1, ix1 = (fi + 1) >> 1;
-  int iy0 = fj >> 1, iy1 = (fj + 1) >> 1;
-  int iz0 = fk >> 1, iz1 = (fk + 1) >> 1;
-  const T wx = (fi & 1) ? T(0.5) : T(1), wy = (fj & 1) ? T(0.5) : T(1), wz = (fk & 1) ? T(0.5) : T(1);
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    if ((m >> c) & 1) continue;
     const T* x = xc + c * cnn;
-    T s;
-    if (!(fi & 1) && !(fj & 1) && !(fk & 1)) {
-      s = x[node_of(cnx, cny, ix0, iy0, iz0)];
-    } else {
-      s = 0;
-      for (int z = 0; z < ((fk & 1) ? 2 : 1); ++z)
-        for (int y = 0; y < ((fj & 1) ? 2 : 1); ++y)
-          for (int xx = 0; xx < ((fi & 1) ? 2 : 1); ++xx)
-            s += x[node_of(cnx, cny, xx ? ix1 : ix0, y ? iy1 : iy0, z ? iz1 : iz0)];
-      s *= wx * wy * wz;
-    }
-    xf[c * fnn + n] += s;
+    T s = 0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) s = fma(w[q], x[id[q]], s);
+    if (!((m >> c) & 1)) xf[c * fnn + n] += s;
   }
 }
 
@@ -336,91 +420,167 @@ __global__ void k_assemble_dense(int nx, int ny, int nz, const double* __restric
 }
 
 // ---- blocked Gauss-Jordan inversion of an SPD matrix (sweep operator) -----
-// One block step with pivot block K = [k0, k0+kb):
-//   P = A_KK^-1, T = A_:K P, A_IJ -= T_I A_KJ (I, J outside K),
-//   A_KJ = P A_KJ, A_IK = -T_I, A_KK = P.
+// One block step with pivot block K = [k0, k0+kb) maps
+//   A_KK -> P = A_KK^-1,  A_IK -> -A_IK P,  A_KJ -> P A_KJ,
+//   A_IJ -> A_IJ - A_IK P A_KJ            (I, J outside K).
+// For symmetric A the matrix stays symmetric up to sign: after the blocks
+// before k0 are done, A_ij = A_ji when i and j are both below k0 or both at
+// or above it, and A_ij = -A_ji otherwise.  Only tiles on or above the
+// diagonal are therefore kept: with c_i = A_iK (read from the stored upper
+// triangle as A_iK for i < k0, as A_Ki for i beyond K) and T_i = P c_i,
+//   A_ij -= s_j T_i . c_j  (s_j = -1 for j < k0, +1 beyond K),
+//   A_iK  = -T_i (i < k0),  A_Kj = T_j (j beyond K).
+// After the last block the stored upper triangle is A^-1 and the lower
+// triangle is filled by transposition.
 
-// Invert the kb x kb pivot block (unblocked Gauss-Jordan) in one wavefront:
-// lane c holds column c in registers; the pivot column is broadcast with
-// readlane.  Rows/columns beyond kb are padded with the identity.
-__device__ inline double lane_bcast(double x, int lane) {
-  const int lo = __builtin_amdgcn_readlane(__double2loint(x), lane);
-  const int hi = __builtin_amdgcn_readlane(__double2hiint(x), lane);
-  return __hiloint2double(hi, lo);
-}
+typedef double f64x4 __attribute__((ext_vector_type(4)));
 
-__global__ void __launch_bounds__(64) k_gj_pivot(int n, int k0, int kb,
-                                                 const double* __restrict__ A,
-                                                 double* __restrict__ P) {
-  const int c = threadIdx.x;
-  double col[kGJBlock];
+// In-place Gauss-Jordan inversion of a 16x16 block of LDS (row stride ld) by
+// one wavefront in registers: lane l holds rows 4(l/16)..4(l/16)+3 of column
+// l%16; pivot row and column are exchanged with lane shuffles.
+__device__ __forceinline__ void gj16_wave(double* S, int ld) {
+  const int l = threadIdx.x & 63, c = l & 15, r4 = l >> 4;
+  double x[4];
 #pragma unroll
-  for (int r = 0; r < kGJBlock; ++r)
-    col[r] = (r < kb && c < kb) ? A[(int64_t)(k0 + r) * n + (k0 + c)] : (r == c ? 1.0 : 0.0);
-  // the step index k is a runtime value; col[] is only ever indexed by the
-  // unrolled r, so it stays in registers (row k is picked out by selects)
-  for (int k = 0; k < kGJBlock; ++k) {
-    double rk = 0.0;
+  for (int q = 0; q < 4; ++q) x[q] = S[(4 * r4 + q) * ld + c];
 #pragma unroll
-    for (int r = 0; r < kGJBlock; ++r) rk = (r == k) ? col[r] : rk;
-    const double piv = 1.0 / lane_bcast(rk, k);
+  for (int k = 0; k < 16; ++k) {
+    const int kq = k & 3, kr = k >> 2;
+    const double rk = __shfl(x[kq], kr * 16 + c, 64);   // S[k][c]
+    const double piv = 1.0 / __shfl(x[kq], kr * 16 + k, 64);
     const bool pc = (c == k);
 #pragma unroll
-    for (int r = 0; r < kGJBlock; ++r) {
-      const double crk = lane_bcast(col[r], k);
-      const double upd = pc ? -crk * piv : fma(-crk * piv, rk, col[r]);
-      const double kr = pc ? piv : rk * piv;
-      col[r] = (r == k) ? kr : upd;
+    for (int q = 0; q < 4; ++q) {
+      const double ck = __shfl(x[q], r4 * 16 + k, 64);  // S[4 r4 + q][k]
+      const double upd = pc ? -ck * piv : fma(-ck * piv, rk, x[q]);
+      x[q] = (4 * r4 + q == k) ? (pc ? piv : rk * piv) : upd;
     }
   }
 #pragma unroll
-  for (int r = 0; r < kGJBlock; ++r)
-    if (r < kb && c < kb) P[r * kb + c] = col[r];
+  for (int q = 0; q < 4; ++q) S[(4 * r4 + q) * ld + c] = x[q];
 }
 
-// T[i][p] = sum_q A[i][k0+q] P[q][p] (all rows i); Rw[p][j] = A[k0+p][j].
-__global__ void k_gj_panels(int n, int k0, int kb, const double* __restrict__ A,
-                            const double* __restrict__ P, double* __restrict__ T,
-                            double* __restrict__ Rw) {
-  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (int64_t)n * kb) return;
-  const int i = (int)(t / kb), p = (int)(t % kb);
-  double acc = 0.0;
-  for (int q = 0; q < kb; ++q) acc = fma(A[(int64_t)i * n + k0 + q], P[q * kb + p], acc);
-  T[t] = acc;
-  const int pr = (int)(t / n), j = (int)(t % n);
-  Rw[t] = A[(int64_t)(k0 + pr) * n + j];
-}
-
-// A_IJ -= T_I Rw_J for I, J outside the pivot block: 64x64 output tiles, each
-// of the 256 threads accumulates a 4x4 sub-tile; the rank-kb product is
-// staged through LDS in chunks of 16.
-__global__ void __launch_bounds__(256) k_gj_update(int n, int k0, int kb,
-                                                   double* __restrict__ A,
-                                                   const double* __restrict__ T,
-                                                   const double* __restrict__ Rw) {
-  __shared__ double sT[16][64 + 1];
-  __shared__ double sR[16][64 + 1];
-  const int bi = blockIdx.y * 64, bj = blockIdx.x * 64;
-  const int tid = threadIdx.x;
-  const int tr = tid / 16, tc = tid % 16;
-  double acc[4][4] = {};
-  for (int p0 = 0; p0 < kb; p0 += 16) {
-    for (int t = tid; t < 16 * 64; t += 256) {
-      const int q = t / 64, rr = t % 64;
-      const int p = p0 + q;
-      const int i = bi + rr, j = bj + rr;
-      sT[q][rr] = (p < kb && i < n) ? T[(int64_t)i * kb + p] : 0.0;
-      sR[q][rr] = (p < kb && j < n) ? Rw[(int64_t)p * n + j] : 0.0;
+// In-place Gauss-Jordan inversion of the 64x64 block sS (padded with the
+// identity beyond the pivot block size) by 256 threads, in four 16-wide
+// sub-steps J: Q = S_JJ^-1 (one wavefront), then S_Jk <- Q S_Jk,
+// S_ik <- S_ik - S_iJ (Q S_Jk), S_iJ <- -S_iJ Q for i, k outside J.
+__device__ __forceinline__ void gj64_block(double (*sS)[kGJBlock + 1], double (*sT)[17]) {
+  const int t = threadIdx.x;
+  const int lo = t & 15, hi = t >> 4;  // 16 x 16 thread grid
+  for (int j = 0; j < 4; ++j) {
+    const int J0 = 16 * j;
+    if (t < 64) gj16_wave(&sS[J0][J0], kGJBlock + 1);
+    __syncthreads();
+    double Tv[3], Rv[3];
+#pragma unroll
+    for (int u = 0; u < 3; ++u) {
+      const int ii = hi + 16 * u, i = ii < J0 ? ii : ii + 16;
+      double acc = 0.0;
+#pragma unroll
+      for (int p = 0; p < 16; ++p) acc = fma(sS[i][J0 + p], sS[J0 + p][J0 + lo], acc);
+      Tv[u] = acc;  // (S_iJ Q)[i][lo]
+      const int kk = lo + 16 * u, k = kk < J0 ? kk : kk + 16;
+      double r = 0.0;
+#pragma unroll
+      for (int q = 0; q < 16; ++q) r = fma(sS[J0 + hi][J0 + q], sS[J0 + q][k], r);
+      Rv[u] = r;  // (Q S_Jk)[hi][k]
     }
     __syncthreads();
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
+    for (int u = 0; u < 3; ++u) {
+      sT[hi + 16 * u][lo] = Tv[u];
+      const int kk = lo + 16 * u, k = kk < J0 ? kk : kk + 16;
+      sS[J0 + hi][k] = Rv[u];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 3; ++u) {
+      const int ii = hi + 16 * u, i = ii < J0 ? ii : ii + 16;
+      double sij[16];
+#pragma unroll
+      for (int p = 0; p < 16; ++p) sij[p] = sS[i][J0 + p];
+      // each thread reads and writes only its own (i, k) of the updated block
+#pragma unroll
+      for (int w = 0; w < 3; ++w) {
+        const int kk = lo + 16 * w, k = kk < J0 ? kk : kk + 16;
+        double acc = sS[i][k];
+#pragma unroll
+        for (int p = 0; p < 16; ++p) acc = fma(-sij[p], sS[J0 + p][k], acc);
+        sS[i][k] = acc;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 3; ++u) {
+      const int ii = hi + 16 * u, i = ii < J0 ? ii : ii + 16;
+      sS[i][J0 + lo] = -sT[ii][lo];
+    }
+    __syncthreads();
+  }
+}
+
+// Pivot inverse of the first block: Pb = A_00^-1 (kb x kb).
+__global__ void __launch_bounds__(256) k_gj_pivot_first(int n, int kb,
+                                                        const double* __restrict__ A,
+                                                        double* __restrict__ Pb) {
+  __shared__ double sS[kGJBlock][kGJBlock + 1];
+  __shared__ double sT[48][17];
+  for (int x = threadIdx.x; x < kGJBlock * kGJBlock; x += 256) {
+    const int r = x / 64, c = x % 64;
+    sS[r][c] = (r < kb && c < kb) ? A[(int64_t)r * n + c] : (r == c ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  gj64_block(sS, sT);
+  for (int x = threadIdx.x; x < kb * kb; x += 256) Pb[x] = sS[x / kb][x % kb];
+}
+
+// One block per 64-row block I != K: c_I gathered from the stored upper
+// triangle, T_I = c_I P with P = Pb; writes Cb, Tb ([kb][n], index-fastest)
+// and the new cross entries of A.  Block K writes A_KK = P.
+__global__ void __launch_bounds__(256) k_gj_cross(int n, int k0, int kb,
+                                                  double* __restrict__ A,
+                                                  const double* __restrict__ Pb,
+                                                  double* __restrict__ Tb,
+                                                  double* __restrict__ Cb) {
+  __shared__ double sP[kGJBlock][kGJBlock];
+  __shared__ double sX[kGJBlock][33];
+  const int tid = threadIdx.x;
+  const int i0 = blockIdx.x * kGJBlock;
+  const int rows = (n - i0 < kGJBlock) ? (n - i0) : kGJBlock;
+  if (i0 == k0) {
+    for (int x = tid; x < kb * kb; x += 256)
+      A[(int64_t)(k0 + x / kb) * n + k0 + x % kb] = Pb[x];
+    return;
+  }
+  for (int x = tid; x < kGJBlock * kGJBlock; x += 256) {
+    const int r = x / 64, c = x % 64;
+    sP[r][c] = (r < kb && c < kb) ? Pb[r * kb + c] : 0.0;
+  }
+  const bool below = i0 < k0;  // rows already pivoted
+  const int tr = tid / 16, tc = tid % 16;
+  double acc[4][4] = {};
+  for (int h = 0; h < 2; ++h) {  // c columns [32h, 32h + 32)
+    for (int t = tid; t < kGJBlock * 32; t += 256) {
+      int r, q;
+      if (below) { r = t / 32; q = t % 32; } else { q = t / 64; r = t % 64; }
+      const int p = 32 * h + q;
+      double v = 0.0;
+      if (r < rows && p < kb)
+        v = below ? A[(int64_t)(i0 + r) * n + (k0 + p)] : A[(int64_t)(k0 + p) * n + (i0 + r)];
+      sX[r][q] = v;
+    }
+    __syncthreads();
+    for (int t = tid; t < kGJBlock * 32; t += 256) {
+      const int q = t / 64, r = t % 64, p = 32 * h + q;
+      if (r < rows && p < kb) Cb[(int64_t)p * n + i0 + r] = sX[r][q];
+    }
+#pragma unroll 4
+    for (int q = 0; q < 32; ++q) {
       double a[4], b[4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) a[u] = sT[q][tr + 16 * u];
+      for (int u = 0; u < 4; ++u) a[u] = sX[tr + 16 * u][q];
 #pragma unroll
-      for (int w = 0; w < 4; ++w) b[w] = sR[q][tc + 16 * w];
+      for (int w = 0; w < 4; ++w) b[w] = sP[32 * h + q][tc + 16 * w];
 #pragma unroll
       for (int u = 0; u < 4; ++u)
 #pragma unroll
@@ -428,38 +588,124 @@ __global__ void __launch_bounds__(256) k_gj_update(int n, int k0, int kb,
     }
     __syncthreads();
   }
+  // acc[u][w] = T[row tr + 16u][col tc + 16w]; stage each half through sX
+  for (int h = 0; h < 2; ++h) {
 #pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int i = bi + tr + 16 * u;
-    if (i >= n || (i >= k0 && i < k0 + kb)) continue;
+    for (int u = 0; u < 4; ++u)
 #pragma unroll
-    for (int w = 0; w < 4; ++w) {
-      const int j = bj + tc + 16 * w;
-      if (j >= n || (j >= k0 && j < k0 + kb)) continue;
-      A[(int64_t)i * n + j] -= acc[u][w];
+      for (int w = 0; w < 2; ++w) sX[tr + 16 * u][tc + 16 * w] = acc[u][2 * h + w];
+    __syncthreads();
+    // columns held in this half: tc + 16 * (2h + w), w in {0, 1}
+    for (int t = tid; t < kGJBlock * 32; t += 256) {
+      const int q = t / 64, r = t % 64;
+      const int p = (q % 16) + 16 * (2 * h + q / 16);
+      if (r < rows && p < kb) Tb[(int64_t)p * n + i0 + r] = sX[r][q];
     }
+    for (int t = tid; t < kGJBlock * 32; t += 256) {
+      int r, q;
+      if (below) { r = t / 32; q = t % 32; } else { q = t / 64; r = t % 64; }
+      const int p = (q % 16) + 16 * (2 * h + q / 16);
+      if (r < rows && p < kb) {
+        if (below) A[(int64_t)(i0 + r) * n + (k0 + p)] = -sX[r][q];
+        else A[(int64_t)(k0 + p) * n + (i0 + r)] = sX[r][q];
+      }
+    }
+    __syncthreads();
   }
 }
 
-// A_KJ = P Rw_J, A_IK = -T_I, A_KK = P.
-__global__ void k_gj_finish(int n, int k0, int kb, double* __restrict__ A,
-                            const double* __restrict__ P, const double* __restrict__ T,
-                            const double* __restrict__ Rw) {
-  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (int64_t)n * kb) return;
-  {  // row panel entry (p, j)
-    const int p = (int)(t / n), j = (int)(t % n);
-    if (j >= k0 && j < k0 + kb) {
-      A[(int64_t)(k0 + p) * n + j] = P[p * kb + (j - k0)];
-    } else {
-      double acc = 0.0;
-      for (int q = 0; q < kb; ++q) acc = fma(P[p * kb + q], Rw[(int64_t)q * n + j], acc);
-      A[(int64_t)(k0 + p) * n + j] = acc;
+// Upper tiles (bi <= bj) outside K: A_IJ -= s_J T_I C_J^T on 64x64 tiles with
+// FP64 MFMA (wave w: rows 16w..16w+15, four 16x16 accumulators), operands
+// read straight from Tb and Cb.  Block 0 takes the next diagonal tile
+// (K+1, K+1) and then inverts it into Pb, the pivot of the next step.
+__global__ void __launch_bounds__(256) k_gj_update(int n, int k0, int kb, int nb,
+                                                   double* __restrict__ A,
+                                                   double* __restrict__ Pb,
+                                                   const double* __restrict__ Tb,
+                                                   const double* __restrict__ Cb) {
+  __shared__ double sS[kGJBlock][kGJBlock + 1];
+  __shared__ double sT[48][17];
+  const int kblk = k0 / kGJBlock;
+  const bool has_next = kblk + 1 < nb;
+  int bi, bj;
+  if (blockIdx.x == 0) {
+    if (!has_next) return;
+    bi = bj = kblk + 1;
+  } else {
+    // linear index over the upper triangle, row-major, skipping (K+1, K+1)
+    int t = blockIdx.x - 1;
+    if (has_next) {
+      const int nxt = (kblk + 1) * nb - ((kblk + 1) * kblk) / 2;  // index of (K+1, K+1)
+      if (t >= nxt) ++t;
+    }
+    bi = 0;
+    while (t >= nb - bi) { t -= nb - bi; ++bi; }
+    bj = bi + t;
+    if (bi == kblk || bj == kblk) return;
+  }
+  const int I0 = bi * kGJBlock, J0 = bj * kGJBlock;
+  const double sgn = (J0 < k0) ? -1.0 : 1.0;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int row = I0 + 16 * w + li;
+  f64x4 acc[4];
+#pragma unroll
+  for (int jb = 0; jb < 4; ++jb) acc[jb] = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+  for (int p = 0; p < kb; p += 4) {
+    const int pk = p + lk;
+    const bool pin = pk < kb;
+    const double av = (pin && row < n) ? Tb[(int64_t)pk * n + row] : 0.0;
+#pragma unroll
+    for (int jb = 0; jb < 4; ++jb) {
+      const int col = J0 + 16 * jb + li;
+      const double bv = (pin && col < n) ? Cb[(int64_t)pk * n + col] : 0.0;
+      acc[jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[jb], 0, 0, 0);
     }
   }
-  {  // column panel entry (i, p)
-    const int i = (int)(t / kb), p = (int)(t % kb);
-    if (!(i >= k0 && i < k0 + kb)) A[(int64_t)i * n + k0 + p] = -T[t];
+  // accumulator layout: lane l, element v -> row l/16 + 4v, column l%16 of
+  // the 16x16 block (operands: A[l%16][l/16], B[l/16][l%16])
+  const bool diag_next = (blockIdx.x == 0);
+#pragma unroll
+  for (int jb = 0; jb < 4; ++jb) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int ti = 16 * w + lk + 4 * v, tj = 16 * jb + li;
+      const int i = I0 + ti, j = J0 + tj;
+      double val = 0.0;
+      if (i < n && j < n) {
+        val = fma(-sgn, acc[jb][v], A[(int64_t)i * n + j]);
+        A[(int64_t)i * n + j] = val;
+      }
+      if (diag_next) sS[ti][tj] = val;
+    }
+  }
+  if (!diag_next) return;
+  const int kbn = (n - I0 < kGJBlock) ? (n - I0) : kGJBlock;
+  __syncthreads();
+  for (int x = threadIdx.x; x < kGJBlock * kGJBlock; x += 256) {
+    const int r = x / 64, c = x % 64;
+    if (r >= kbn || c >= kbn) sS[r][c] = (r == c) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  gj64_block(sS, sT);
+  for (int x = threadIdx.x; x < kbn * kbn; x += 256) Pb[x] = sS[x / kbn][x % kbn];
+}
+
+// Lower tiles (bi > bj) <- transpose of the upper tiles.
+__global__ void __launch_bounds__(256) k_gj_mirror(int n, double* __restrict__ A) {
+  __shared__ double sX[kGJBlock][kGJBlock + 1];
+  const int bi = blockIdx.y, bj = blockIdx.x;
+  if (bi <= bj) return;
+  const int I0 = bi * kGJBlock, J0 = bj * kGJBlock, tid = threadIdx.x;
+  for (int x = tid; x < kGJBlock * kGJBlock; x += 256) {  // read A[J0 + r][I0 + c]
+    const int r = x / 64, c = x % 64;
+    if (J0 + r < n && I0 + c < n) sX[r][c] = A[(int64_t)(J0 + r) * n + I0 + c];
+  }
+  __syncthreads();
+  for (int x = tid; x < kGJBlock * kGJBlock; x += 256) {  // write A[I0 + r][J0 + c]
+    const int r = x / 64, c = x % 64;
+    if (I0 + r < n && J0 + c < n) A[(int64_t)(I0 + r) * n + J0 + c] = sX[c][r];
   }
 }
 
@@ -480,20 +726,32 @@ __global__ void __launch_bounds__(256) k_gemv(int n, const double* __restrict__ 
 }  // namespace
 
 void launch_galerkin_from_fine(const Grid& coarse, const double* KE, const double* Mc,
-                               const double* E, const uint8_t* mask, double* Kc, hipStream_t s) {
+                               const double* E, const uint8_t* mask, uint8_t* eflag, int* list,
+                               int* count, double* Kc, hipStream_t s) {
   k_galerkin_fast<<<nblk(coarse.ne, 64), 256, 0, s>>>(coarse.nx, coarse.ny, coarse.nz, Mc, E, Kc);
-  k_galerkin_lds<true><<<(unsigned)coarse.ne, 256, 0, s>>>(coarse.nx, coarse.ny, coarse.nz, KE, E,
-                                                          mask, nullptr, Kc);
+  k_zero_int<<<1, 1, 0, s>>>(count);
+  k_parent_flags<<<nblk(coarse.ne, 256), 256, 0, s>>>(coarse.nx, coarse.ny, coarse.nz, mask, eflag,
+                                                       list, count);
+  const unsigned grid = (unsigned)std::min<int64_t>(coarse.ne, 2048);
+  k_galerkin_lds<true><<<grid, 256, 0, s>>>(coarse.nx, coarse.ny, coarse.nz, KE, E, mask, list,
+                                            count, nullptr, Kc);
 }
 
 void launch_galerkin_from_coarse(const Grid& coarse, const double* Kf, double* Kc, hipStream_t s) {
-  k_galerkin_lds<false><<<(unsigned)coarse.ne, 256, 0, s>>>(coarse.nx, coarse.ny, coarse.nz,
-                                                           nullptr, nullptr, nullptr, Kf, Kc);
+  const unsigned grid = (unsigned)std::min<int64_t>(coarse.ne, 4096);
+  k_galerkin_lds<false><<<grid, 256, 0, s>>>(coarse.nx, coarse.ny, coarse.nz, nullptr, nullptr,
+                                             nullptr, nullptr, nullptr, Kf, Kc);
 }
 
 void launch_apply_elemmat(const Grid& g, const double* Ke, const double* v, double* y,
                           hipStream_t s) {
-  k_apply_elemmat<double><<<nblk(g.nn, 256), 256, 0, s>>>(g.nx, g.ny, g.nz, Ke, v, y);
+  k_apply_elemmat<false><<<nblk(g.nn, 64), 512, 0, s>>>(g.nx, g.ny, g.nz, Ke, nullptr, nullptr,
+                                                        nullptr, v, y);
+}
+
+void launch_apply_elemmat_mf(const Grid& g, const double* Ke, const double* Mf, const double* Ef,
+                             const uint8_t* eflag, const double* v, double* y, hipStream_t s) {
+  k_apply_elemmat<true><<<nblk(g.nn, 64), 512, 0, s>>>(g.nx, g.ny, g.nz, Ke, Mf, Ef, eflag, v, y);
 }
 
 void launch_diag_elemmat(const Grid& g, const double* Ke, double* dinv, float* dinv32,
@@ -503,8 +761,8 @@ void launch_diag_elemmat(const Grid& g, const double* Ke, double* dinv, float* d
 
 void launch_restrict(const Grid& coarse, const double* bf, const double* tf, const uint8_t* mask,
                      double* bc, hipStream_t s) {
-  k_restrict<double><<<nblk(coarse.nn, 256), 256, 0, s>>>(coarse.nx, coarse.ny, coarse.nz, bf, tf,
-                                                          mask, bc);
+  k_restrict<double><<<dim3(nblk(coarse.nn, 64), 3), 192, 0, s>>>(coarse.nx, coarse.ny, coarse.nz,
+                                                                  bf, tf, mask, bc);
 }
 
 void launch_prolong_add(const Grid& fine, const double* xc, const uint8_t* mask, double* xf,
@@ -527,16 +785,16 @@ void launch_assemble_dense(const Grid& g, const double* Ke, double* A, hipStream
   k_assemble_dense<<<nblk(3 * g.nn, 64), 64, 0, s>>>(g.nx, g.ny, g.nz, Ke, A);
 }
 
-void launch_gj_invert(int n, double* A, double* P, double* T, double* Rw, hipStream_t s) {
+void launch_gj_invert(int n, double* A, double* P, double* T, double* C, hipStream_t s) {
+  const int nb = (n + kGJBlock - 1) / kGJBlock;
+  const unsigned n_upper = (unsigned)(nb * (nb + 1) / 2);
+  k_gj_pivot_first<<<1, 256, 0, s>>>(n, std::min(n, kGJBlock), A, P);
   for (int k0 = 0; k0 < n; k0 += kGJBlock) {
-    const int kb = (n - k0 < kGJBlock) ? (n - k0) : kGJBlock;
-    k_gj_pivot<<<1, 64, 0, s>>>(n, k0, kb, A, P);
-    const int64_t nk = (int64_t)n * kb;
-    k_gj_panels<<<nblk(nk, 256), 256, 0, s>>>(n, k0, kb, A, P, T, Rw);
-    dim3 grid((n + 63) / 64, (n + 63) / 64);
-    k_gj_update<<<grid, 256, 0, s>>>(n, k0, kb, A, T, Rw);
-    k_gj_finish<<<nblk(nk, 256), 256, 0, s>>>(n, k0, kb, A, P, T, Rw);
+    const int kb = std::min(kGJBlock, n - k0);
+    k_gj_cross<<<nb, 256, 0, s>>>(n, k0, kb, A, P, T, C);
+    k_gj_update<<<n_upper, 256, 0, s>>>(n, k0, kb, nb, A, P, T, C);
   }
+  k_gj_mirror<<<dim3(nb, nb), 256, 0, s>>>(n, A);
 }
 
 void launch_gemv(int n, const double* A, const double* x, double* y, hipStream_t s) {
