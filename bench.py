@@ -46,6 +46,10 @@ def parse():
     ap.add_argument("--no-large", action="store_true", help="skip the 256x128x128 K.v roofline")
     ap.add_argument("--plain", action="store_true", help="also time plain MGCG every cycle")
     ap.add_argument("--kv-launches", type=int, default=200)
+    ap.add_argument("--no-precision", action="store_true",
+                    help="skip the 256x128x128 FP64 vs refinement-form solve")
+    ap.add_argument("--precision-only", action="store_true",
+                    help="only the 256x128x128 FP64 vs refinement-form solve")
     ap.add_argument("--kv-only", action="store_true",
                     help="only the 256x128x128 K.v timing (for hardware-counter runs)")
     return ap.parse_args()
@@ -159,6 +163,61 @@ def large_kv(torch, aarmr, synth, n_launch):
                     "exceeds the 256 MB Infinity Cache"}
 
 
+def precision_form(torch, aarmr, synth, reps=3):
+    """One analysis (setup + MGCG to rel. residual 1e-8, compliance) of the
+    256x128x128 cantilever on a smoothed random field (correlation length 8
+    voxels, seed 3, mapped to [1e-3, 1]), 5 grid levels, in FP64 and in the
+    refinement form (FP32 operator sweeps, V-cycle and inner CG; FP64
+    residuals, dot accumulation and updates of u).  Median of `reps` timed
+    solves after one warm-up solve, each from u = 0."""
+    import numpy as np
+
+    dev = torch.device("cuda")
+    L = (256, 128, 128)
+    prob = synth.cantilever(*L)
+    rho = torch.tensor(synth.smoothed_field(*L, 8.0, 1e-3, 1.0, seed=3).ravel(),
+                       dtype=torch.float64, device=dev)
+    res = {}
+    for prec in (aarmr.FP64, aarmr.FP32_REFINE):
+        p = aarmr.default_params(nx=L[0], ny=L[1], nz=L[2], mg_levels=5, cg_rtol=1e-8,
+                                 cg_maxit=2000, precision=prec)
+        m = aarmr.Mesh(p)
+        fixed = torch.tensor(aarmr.fixed_dofs_soa(prob, m.n_node), dtype=torch.int64, device=dev)
+        f = torch.tensor(np.asarray(aarmr.loads_soa(prob, m.n_node)[0]), dtype=torch.float64,
+                         device=dev)
+        u = torch.zeros_like(f)
+        times = []
+        for r in range(reps + 1):
+            u.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            C, st, code = m.solve(rho, f, fixed, u)
+            dt = time.perf_counter() - t0
+            if r > 0:
+                times.append(dt)
+        res[prec] = {"ms": float(np.median(times)) * 1e3, "C": C[0], "u": u.clone(),
+                     "its": int(st.iterations[0]), "rel": float(st.rel_residual[0]),
+                     "code": int(code)}
+        print(f"[bench] precision form {prec}: {res[prec]['ms']:.2f} ms, "
+              f"{res[prec]['its']} its", file=sys.stderr, flush=True)
+        m.close()
+        del m, u
+    a, b = res[aarmr.FP64], res[aarmr.FP32_REFINE]
+    du = float(torch.linalg.norm(b["u"] - a["u"]) / torch.linalg.norm(a["u"]))
+    return {"workload": "256x128x128 hex8 cantilever, smoothed random field [1e-3, 1], "
+                        "5 levels, rel. residual 1e-8, one load case",
+            "dofs": 3 * (L[0] + 1) * (L[1] + 1) * (L[2] + 1),
+            "fp64": {"ms_per_solve": round(a["ms"], 3), "solves_s": round(1e3 / a["ms"], 3),
+                     "iterations": a["its"], "rel_residual": a["rel"]},
+            "fp32_refine": {"ms_per_solve": round(b["ms"], 3), "solves_s": round(1e3 / b["ms"], 3),
+                            "iterations": b["its"], "rel_residual": b["rel"]},
+            "speedup": round(a["ms"] / b["ms"], 3),
+            "compliance_rel_diff": abs(b["C"] - a["C"]) / abs(a["C"]),
+            "u_rel_l2_diff": du,
+            "within_1e-6": bool(abs(b["C"] - a["C"]) <= 1e-6 * abs(a["C"]) and du <= 1e-6
+                                and a["code"] == 0 and b["code"] == 0)}
+
+
 def cpu_baseline():
     """The oracle's analysis (assembly, banded Cholesky, compliance,
     sensitivities, filter and its adjoint) on the 48x24x24 sub-grid of the
@@ -210,6 +269,9 @@ def main():
         del a, b
         print(json.dumps({"roofline_kv_256x128x128": large_kv(torch, aarmr, synth, args.kv_launches)}))
         return
+    if args.precision_only:
+        print(json.dumps({"precision_form_256x128x128": precision_form(torch, aarmr, synth)}))
+        return
     mesh, fixed, f, dv = make_loop_state(torch, aarmr, synth)
     print(f"[bench] mesh {NX}x{NY}x{NZ}, workspace {mesh.workspace_bytes / 2**20:.0f} MiB",
           file=sys.stderr, flush=True)
@@ -251,6 +313,10 @@ def main():
     extra = {}
     if not args.no_large:
         extra["roofline_kv_256x128x128"] = large_kv(torch, aarmr, synth, args.kv_launches)
+        torch.cuda.empty_cache()
+    if not args.no_precision:
+        extra["precision_form_256x128x128"] = precision_form(torch, aarmr, synth)
+        torch.cuda.empty_cache()
 
     lat_solve = np.array([a for a, _ in lat_all])
     lat_cycle = np.array([b for _, b in lat_all])

@@ -43,6 +43,11 @@ struct LevelBuf {
   double* b = nullptr;     // levels >= 1: right-hand side
   double* x = nullptr;     // levels >= 1: correction
   double* t = nullptr;     // [3][nn] operator output
+  // FP32 copies for the refinement form's V-cycle (same roles)
+  float* dinv32 = nullptr;
+  float* b32 = nullptr;
+  float* x32 = nullptr;
+  float* t32 = nullptr;
 };
 
 // Scalar history in device memory (indices into m->scal).
@@ -53,6 +58,7 @@ constexpr int SC_MISC = SC_RR + kMaxIt + 2;  // 512 misc scalars
 constexpr int SC_TOTAL = SC_MISC + 512;
 // misc slots
 constexpr int M_FF = 0, M_RR0 = 1, M_NRM = 2, M_C = 3, M_EPS = 4, M_VOL = 5;
+constexpr int M_RR64 = 6;      // FP64 residual norm^2 of a refinement step
 constexpr int M_OC = 8;        // 4 slots: l1, l2, lmid, done
 constexpr int M_KPHI = 16;     // Ns*Ns
 constexpr int M_G = 120;       // Ns  (Phi^T dK r)
@@ -77,12 +83,17 @@ struct aarmr_mesh {
   WalshConsts wk;             // reflection-blocked form of KE
   double Mc[8 * kSymEntries]; // P_c^T KE P_c per child position, packed
   double Mf[8 * 72];          // child 0's, row blocks: [a][col][r] = M_0[3a + r][col]
+  float Mf32[8 * 72];         // the same in FP32
+  bool fp32 = false;          // precision == AARMR_FP32_REFINE
   // workspace views
   char* ws = nullptr;
   int64_t ws_bytes = 0;
   double* KEd = nullptr;
   double* Mcd = nullptr;      // P_c^T KE P_c of the 8 children, packed
   double* Mfd = nullptr;      // the same as row blocks (Mf)
+  float* Mf32d = nullptr;     // FP32 copy (refinement form)
+  float* E32 = nullptr;       // FP32 moduli (refinement form)
+  float *r32 = nullptr, *z32 = nullptr, *p32 = nullptr, *q32 = nullptr, *d32 = nullptr;
   uint8_t* eflag1 = nullptr;  // level-1 parents touching a fixed DOF
   int* list1 = nullptr;       // their indices
   int* count1 = nullptr;
@@ -93,7 +104,10 @@ struct aarmr_mesh {
   double* Hs = nullptr;
   double* ework = nullptr;
   double* dc_tmp = nullptr;
-  double* ones_dv = nullptr;
+  double* ones_dv = nullptr;  // all ones [ne]
+  double* Wf = nullptr;       // filter weights of the offsets
+  double* cw = nullptr;       // H^T (1 / Hs): volume weights of a filtered field
+  std::vector<double> Wh;     // host copy of the filter weights
   uint8_t* mask = nullptr;
   double *r = nullptr, *z = nullptr, *pv = nullptr, *q = nullptr, *t0 = nullptr, *fm = nullptr;
   LevelBuf lv[AARMR_MAX_LEVELS];
@@ -257,6 +271,8 @@ int64_t layout(aarmr_mesh* m, char* base) {
   m->ework = (double*)take(g.ne * d8);
   m->dc_tmp = (double*)take(g.ne * d8);
   m->ones_dv = (double*)take(g.ne * d8);
+  m->Wf = (double*)take((m->p.rmin > 0.0 ? filter_taps(m->p.rmin) : 1) * d8);
+  m->cw = (double*)take(g.ne * d8);
   m->mask = (uint8_t*)take((g.nn + 3) / 4 * 4);
   m->r = (double*)take(n3 * d8);
   m->z = (double*)take(n3 * d8);
@@ -275,6 +291,26 @@ int64_t layout(aarmr_mesh* m, char* base) {
     L.b = (double*)take(3 * G.nn * d8);
     L.x = (double*)take(3 * G.nn * d8);
     L.t = (double*)take(3 * G.nn * d8);
+  }
+  if (m->fp32) {
+    const int64_t f4 = sizeof(float);
+    m->Mf32d = (float*)take(8 * 72 * f4);
+    m->E32 = (float*)take(g.ne * f4);
+    m->r32 = (float*)take(n3 * f4);
+    m->z32 = (float*)take(n3 * f4);
+    m->p32 = (float*)take(n3 * f4);
+    m->q32 = (float*)take(n3 * f4);
+    m->d32 = (float*)take(n3 * f4);
+    for (int l = 0; l < m->nlev; ++l) {
+      const int64_t m3 = 3 * m->lg[l].nn;
+      LevelBuf& L = m->lv[l];
+      L.dinv32 = (float*)take(m3 * f4);
+      L.t32 = (float*)take(m3 * f4);
+      if (l >= 1) {
+        L.b32 = (float*)take(m3 * f4);
+        L.x32 = (float*)take(m3 * f4);
+      }
+    }
   }
   m->Ainv = (double*)take((int64_t)m->nc * m->nc * d8);
   m->gjP = (double*)take(kGJBlock * kGJBlock * d8);
@@ -403,11 +439,12 @@ int setup(aarmr_mesh* m, const double* rho, const int64_t* fixed, int64_t nfixed
   const Grid& g = m->lg[0];
   launch_build_mask(g.nn, fixed, nfixed, m->mask, m->flags, s);
   KCHECK();
-  launch_simp(g.ne, rho, m->p.E0, m->p.Emin, m->p.penal, m->E, nullptr, m->flags, s);
+  launch_simp(g.ne, rho, m->p.E0, m->p.Emin, m->p.penal, m->E, m->fp32 ? m->E32 : nullptr,
+              m->flags, s);
   KCHECK();
   m->mg_ready = false;
   if (!build_mg) return AARMR_OK;
-  launch_diag_fine(g, m->KEd, m->E, m->mask, m->lv[0].dinv, nullptr, s);
+  launch_diag_fine(g, m->KEd, m->E, m->mask, m->lv[0].dinv, m->lv[0].dinv32, s);
   KCHECK();
   for (int l = 1; l < m->nlev; ++l) {
     if (l == 1)
@@ -417,7 +454,7 @@ int setup(aarmr_mesh* m, const double* rho, const int64_t* fixed, int64_t nfixed
       launch_galerkin_from_coarse(m->lg[l], m->lv[l - 1].Ke, m->lv[l].Ke, s);
     KCHECK();
     if (l < m->nlev - 1) {
-      launch_diag_elemmat(m->lg[l], m->lv[l].Ke, m->lv[l].dinv, nullptr, s);
+      launch_diag_elemmat(m->lg[l], m->lv[l].Ke, m->lv[l].dinv, m->lv[l].dinv32, s);
       KCHECK();
     }
   }
@@ -429,8 +466,219 @@ int setup(aarmr_mesh* m, const double* rho, const int64_t* fixed, int64_t nfixed
   return AARMR_OK;
 }
 
-// Preconditioned CG on A x = fm (fm already masked), x in/out (masked).
+// ---- refinement form: FP32 inner solve ------------------------------------
+// y = A v on level l with FP32 vectors (v zero on fixed DOFs).
+int apply32(aarmr_mesh* m, int l, const float* v, float* y, hipStream_t s) {
+  if (l == 0) {
+    launch_ebe_f32(m->lg[0], m->wk, m->E32, m->mask, v, y, 2, s);
+    ++m->sweeps;
+  } else if (l == 1) {
+    launch_apply_elemmat_mf_f32(m->lg[1], m->lv[1].Ke, m->Mf32d, m->E32, m->eflag1, v, y, s);
+  } else {
+    launch_apply_elemmat_f32(m->lg[l], m->lv[l].Ke, v, y, s);
+  }
+  KCHECK();
+  return AARMR_OK;
+}
+
+// The V-cycle of vcycle() with FP32 vectors and smoothing; the coarsest
+// inverse is the FP64 one.
+int vcycle32(aarmr_mesh* m, int l, const float* b, float* x, hipStream_t s) {
+  if (l == m->nlev - 1) {
+    launch_gemv_f32(m->nc, m->Ainv, b, x, s);
+    KCHECK();
+    return AARMR_OK;
+  }
+  const Grid& G = m->lg[l];
+  const int64_t n3 = 3 * G.nn;
+  LevelBuf& L = m->lv[l];
+  LevelBuf& C = m->lv[l + 1];
+  const uint8_t* mask = (l == 0) ? m->mask : nullptr;
+  const float om = (float)m->p.omega;
+  if (m->p.nu_pre >= 1) {
+    launch_jacobi_first_f32(n3, b, L.dinv32, om, x, s);
+    KCHECK();
+    for (int it = 1; it < m->p.nu_pre; ++it) {
+      TRY(apply32(m, l, x, L.t32, s));
+      launch_jacobi_update_f32(n3, b, L.t32, L.dinv32, om, x, s);
+      KCHECK();
+    }
+    TRY(apply32(m, l, x, L.t32, s));
+    launch_restrict_f32(m->lg[l + 1], b, L.t32, mask, C.b32, s);
+  } else {
+    HIP_TRY(hipMemsetAsync(x, 0, n3 * sizeof(float), s));
+    launch_restrict_f32(m->lg[l + 1], b, nullptr, mask, C.b32, s);
+  }
+  KCHECK();
+  TRY(vcycle32(m, l + 1, C.b32, C.x32, s));
+  launch_prolong_add_f32(G, C.x32, mask, x, s);
+  KCHECK();
+  for (int it = 0; it < m->p.nu_post; ++it) {
+    TRY(apply32(m, l, x, L.t32, s));
+    launch_jacobi_update_f32(n3, b, L.t32, L.dinv32, om, x, s);
+    KCHECK();
+  }
+  return AARMR_OK;
+}
+
+int dot32(aarmr_mesh* m, const float* a, const float* b, double* out, int64_t n, hipStream_t s) {
+  DotSetT<float> d{};
+  d.k = 1;
+  d.n = n;
+  d.a[0] = a;
+  d.b[0] = b;
+  d.out[0] = out;
+  launch_multidot_f32(d, red(m), s);
+  KCHECK();
+  return AARMR_OK;
+}
+
+// FP32 PCG on A d = r32 (r32 of unit norm, zero on fixed DOFs) from d = 0,
+// until ||r|| <= rtol (recurrence residual, FP64 dots) or maxit iterations.
+// r32 is overwritten.  *stalled is set when r^T z or p^T A p stops being
+// positive, the sign that FP32 can make no further progress.
+int pcg32(aarmr_mesh* m, double rtol, int maxit, int* iters, double* relres, bool* stalled,
+          hipStream_t s) {
+  const Grid& g = m->lg[0];
+  const int64_t n3 = 3 * g.nn;
+  double* sc = m->scal;
+  HIP_TRY(hipMemsetAsync(m->d32, 0, n3 * sizeof(float), s));
+  *iters = 0;
+  *relres = 1.0;
+  *stalled = false;
+  const double tol2 = rtol * rtol;
+  TRY(vcycle32(m, 0, m->r32, m->z32, s));
+  TRY(dot32(m, m->r32, m->z32, sc + SC_RZ, n3, s));
+  launch_copy_f32(n3, m->z32, m->p32, s);
+  KCHECK();
+  double h[3];
+  for (int it = 0; it < maxit; ++it) {
+    TRY(apply32(m, 0, m->p32, m->q32, s));
+    TRY(dot32(m, m->p32, m->q32, sc + SC_PQ + it, n3, s));
+    launch_cg_xr_f32(n3, sc + SC_RZ + it, sc + SC_PQ + it, m->d32, m->r32, m->p32, m->q32, s);
+    KCHECK();
+    TRY(dot32(m, m->r32, m->r32, sc + SC_RR + it + 1, n3, s));
+    const double* src[3] = {sc + SC_RR + it + 1, sc + SC_PQ + it, sc + SC_RZ + it};
+    TRY(read_scalars(m, src, 3, h, s));
+    *iters = it + 1;
+    *relres = std::sqrt(h[0]);
+    if (!(h[1] > 0.0) || !(h[2] > 0.0)) {
+      *stalled = true;
+      return AARMR_OK;
+    }
+    if (h[0] <= tol2) return AARMR_OK;
+    TRY(vcycle32(m, 0, m->r32, m->z32, s));
+    TRY(dot32(m, m->r32, m->z32, sc + SC_RZ + it + 1, n3, s));
+    launch_cg_p_f32(n3, sc + SC_RZ + it + 1, sc + SC_RZ + it, m->z32, m->p32, s);
+    KCHECK();
+  }
+  return AARMR_OK;
+}
+
+// Iterative refinement: r = fm - A x in FP64, the FP32 PCG solves A d = r/||r||
+// to a relative accuracy chosen so that the next FP64 residual lands near
+// cg_rtol, and x += ||r|| d in FP64; repeated until the FP64 residual meets
+// cg_rtol.  *iters counts the inner iterations.  When FP32 stops making
+// progress (a non-positive p^T A p or r^T z in the inner CG, or an outer step
+// that does not halve the residual) *fallback is set and x holds the latest
+// iterate: the caller continues from it with FP64 CG and the FP32 V-cycle as
+// preconditioner.
+int refine(aarmr_mesh* m, double* x, int* iters, double* relres, bool* fallback,
+           hipStream_t s) {
+  const Grid& g = m->lg[0];
+  const int64_t n3 = 3 * g.nn;
+  double* misc = m->scal + SC_MISC;
+  const double rtol = m->p.cg_rtol;
+  const int budget = std::min(m->p.cg_maxit, kMaxIt);
+  constexpr double kInnerFloor = 2e-5;  // attainable FP32 reduction per step
+  *iters = 0;
+  *fallback = false;
+  double ff = -1.0, prev_rel = 0.0;
+  for (int outer = 0; outer < 64; ++outer) {
+    TRY(apply(m, 0, x, m->q, s));
+    launch_sub(n3, m->fm, m->q, m->r, s);
+    KCHECK();
+    double h[2];
+    if (ff < 0.0) {
+      const double* a[2] = {m->fm, m->r};
+      double* o[2] = {misc + M_FF, misc + M_RR64};
+      TRY(dots(m, 2, a, a, o, n3, s));
+      const double* src[2] = {misc + M_FF, misc + M_RR64};
+      TRY(read_scalars(m, src, 2, h, s));
+      ff = h[0];
+      if (ff == 0.0) {
+        HIP_TRY(hipMemsetAsync(x, 0, n3 * sizeof(double), s));
+        *relres = 0.0;
+        return AARMR_OK;
+      }
+    } else {
+      TRY(dot1(m, m->r, m->r, misc + M_RR64, n3, s));
+      const double* src = misc + M_RR64;
+      TRY(read_scalars(m, &src, 1, h + 1, s));
+    }
+    const double rel = std::sqrt(h[1] / ff);
+    *relres = rel;
+    if (rel <= rtol) return AARMR_OK;
+    if (*iters >= budget) break;
+    const double inner = std::min(0.1, std::max(kInnerFloor, 0.5 * rtol / rel));
+    launch_to_f32_scaled(n3, m->r, misc + M_RR64, m->r32, s);
+    KCHECK();
+    if (outer > 0 && rel > 0.5 * prev_rel) {  // the FP32 step no longer pays
+      *fallback = true;
+      return AARMR_OK;
+    }
+    prev_rel = rel;
+    int its = 0;
+    double rin = 1.0;
+    bool stalled = false;
+    TRY(pcg32(m, inner, budget - *iters, &its, &rin, &stalled, s));
+    *iters += its;
+    if (stalled) {  // FP32 cannot resolve p^T A p here (e.g. extreme contrast)
+      *fallback = true;
+      return AARMR_OK;
+    }
+    launch_add_scaled_f32(n3, m->d32, misc + M_RR64, x, s);
+    KCHECK();
+  }
+  return fail(AARMR_E_NOT_CONVERGED, "refinement reached cg_maxit before cg_rtol");
+}
+
+int pcg64(aarmr_mesh* m, double* x, int* iters, double* relres, int maxit_in, hipStream_t s);
+
+// z = M^-1 r: the FP64 V-cycle, or in the refinement form the FP32 V-cycle
+// on r converted to FP32 (scaled to unit norm; rr = ||r||^2 on the device).
+int precond(aarmr_mesh* m, const double* r, const double* rr, double* z, hipStream_t s) {
+  if (!m->fp32) return vcycle(m, 0, r, z, s);
+  const int64_t n3 = 3 * m->lg[0].nn;
+  launch_to_f32_scaled(n3, r, rr, m->r32, s);
+  KCHECK();
+  TRY(vcycle32(m, 0, m->r32, m->z32, s));
+  HIP_TRY(hipMemsetAsync(z, 0, n3 * sizeof(double), s));
+  launch_add_scaled_f32(n3, m->z32, rr, z, s);
+  KCHECK();
+  return AARMR_OK;
+}
+
+// Preconditioned CG on A x = fm (fm already masked), x in/out (masked).  In
+// the refinement form the FP32 refinement runs first; if it hands over, CG
+// continues from its iterate with the FP32 V-cycle as preconditioner.
 int pcg(aarmr_mesh* m, double* x, int* iters, double* relres, hipStream_t s) {
+  int it0 = 0;
+  if (m->fp32) {
+    bool fallback = false;
+    const int rc = refine(m, x, &it0, relres, &fallback, s);
+    if (rc != AARMR_OK || !fallback) {
+      *iters = it0;
+      return rc;
+    }
+  }
+  const int rc = pcg64(m, x, iters, relres, std::min(m->p.cg_maxit, kMaxIt) - it0, s);
+  *iters += it0;
+  return rc;
+}
+
+// CG with the V-cycle preconditioner (precond) for at most maxit iterations.
+int pcg64(aarmr_mesh* m, double* x, int* iters, double* relres, int maxit_in, hipStream_t s) {
   const Grid& g = m->lg[0];
   const int64_t n3 = 3 * g.nn;
   double* sc = m->scal;
@@ -460,10 +708,10 @@ int pcg(aarmr_mesh* m, double* x, int* iters, double* relres, hipStream_t s) {
   double rr = h[1];
   *relres = std::sqrt(rr / ff);
   if (rr <= tol2) return AARMR_OK;
-  TRY(vcycle(m, 0, m->r, m->z, s));
+  TRY(precond(m, m->r, sc + SC_RR, m->z, s));
   TRY(dot1(m, m->r, m->z, sc + SC_RZ, n3, s));
   HIP_TRY(hipMemcpyAsync(m->pv, m->z, n3 * sizeof(double), hipMemcpyDeviceToDevice, s));
-  const int maxit = std::min(m->p.cg_maxit, kMaxIt);
+  const int maxit = std::max(0, maxit_in);
   for (int it = 0; it < maxit; ++it) {
     TRY(apply(m, 0, m->pv, m->q, s));
     TRY(dot1(m, m->pv, m->q, sc + SC_PQ + it, n3, s));
@@ -477,7 +725,7 @@ int pcg(aarmr_mesh* m, double* x, int* iters, double* relres, hipStream_t s) {
     *relres = std::sqrt(rr / ff);
     if (!(h[1] > 0.0)) return fail(AARMR_E_SINGULAR, "CG: p^T A p <= 0");
     if (rr <= tol2) return AARMR_OK;
-    TRY(vcycle(m, 0, m->r, m->z, s));
+    TRY(precond(m, m->r, sc + SC_RR + it + 1, m->z, s));
     TRY(dot1(m, m->r, m->z, sc + SC_RZ + it + 1, n3, s));
     launch_cg_p(n3, sc + SC_RZ + it + 1, sc + SC_RZ + it, m->z, m->pv, s);
     KCHECK();
@@ -542,7 +790,7 @@ int finish_dc(aarmr_mesh* m, double* dc, int32_t flags, hipStream_t s) {
   const Grid& g = m->lg[0];
   if (!dc) return AARMR_OK;
   if (flags & AARMR_FILTER_INPUT) {
-    launch_filter(g, m->p.rmin, 1, m->Hs, m->dc_tmp, dc, s);
+    launch_filter(g, m->p.rmin, m->Wf, 1, m->Hs, m->dc_tmp, dc, s);
   } else {
     HIP_TRY(hipMemcpyAsync(dc, m->dc_tmp, g.ne * sizeof(double), hipMemcpyDeviceToDevice, s));
   }
@@ -618,6 +866,8 @@ int aarmr_mesh_create(const aarmr_params* p, aarmr_mesh** out) {
     for (int q = 0; q < 24; ++q)
       for (int r = 0; r < 3; ++r)
         m->Mf[(a * 24 + q) * 3 + r] = m->Mc[sym_index(3 * a + r, q)];
+  for (int x = 0; x < 8 * 72; ++x) m->Mf32[x] = (float)m->Mf[x];
+  m->fp32 = (p->precision == AARMR_FP32_REFINE);
   if (!mirror_children(m->Mc)) {
     delete m;
     return fail(AARMR_E_INVALID, "child Galerkin matrices are not mirror images of child 0's");
@@ -656,10 +906,20 @@ int aarmr_bind_workspace(aarmr_mesh* m, void* dev_ptr, int64_t bytes, void* stre
   HIP_TRY(hipMemcpyAsync(m->KEd, m->KE, 576 * sizeof(double), hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(m->Mcd, m->Mc, 8 * kSymEntries * sizeof(double), hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(m->Mfd, m->Mf, 8 * 72 * sizeof(double), hipMemcpyHostToDevice, s));
+  if (m->fp32)
+    HIP_TRY(hipMemcpyAsync(m->Mf32d, m->Mf32, 8 * 72 * sizeof(float), hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemsetAsync(m->flags, 0, 64, s));
   HIP_TRY(hipMemsetAsync(m->mask, 0, (m->lg[0].nn + 3) / 4 * 4, s));
+  launch_fill(m->lg[0].ne, 1.0, m->ones_dv, s);
+  KCHECK();
   if (m->p.rmin > 0.0) {
+    m->Wh.assign(filter_taps(m->p.rmin), 0.0);
+    filter_weights(m->p.rmin, m->Wh.data());
+    HIP_TRY(hipMemcpyAsync(m->Wf, m->Wh.data(), m->Wh.size() * sizeof(double),
+                           hipMemcpyHostToDevice, s));
     launch_filter_rowsum(m->lg[0], m->p.rmin, m->Hs, s);
+    KCHECK();
+    launch_filter(m->lg[0], m->p.rmin, m->Wf, 1, m->Hs, m->ones_dv, m->cw, s);
     KCHECK();
   }
   HIP_TRY(hipStreamSynchronize(s));
@@ -706,7 +966,7 @@ int aarmr_filter(aarmr_mesh* m, int32_t mode, const double* in, double* out, voi
   if (!in || !out || in == out) return fail(AARMR_E_INVALID, "in, out must be distinct non-null");
   if (mode != 0 && mode != 1) return fail(AARMR_E_INVALID, "mode must be 0 or 1");
   if (!(m->p.rmin > 0.0)) return fail(AARMR_E_INVALID, "filter disabled (rmin <= 0)");
-  launch_filter(m->lg[0], m->p.rmin, mode, m->Hs, in, out, S(stream));
+  launch_filter(m->lg[0], m->p.rmin, m->Wf, mode, m->Hs, in, out, S(stream));
   KCHECK();
   return AARMR_OK;
 }
@@ -724,7 +984,7 @@ int aarmr_solve(aarmr_mesh* m, const double* rho, const double* f, int32_t n_rhs
   const int64_t sw0 = m->sweeps;
   const double* rho_phys = rho;
   if (flags & AARMR_FILTER_INPUT) {
-    launch_filter(g, m->p.rmin, 0, m->Hs, rho, m->rho_f, s);
+    launch_filter(g, m->p.rmin, m->Wf, 0, m->Hs, rho, m->rho_f, s);
     KCHECK();
     rho_phys = m->rho_f;
   }
@@ -787,7 +1047,7 @@ int aarmr_ca_update(aarmr_mesh* m, const double* rho, const double* f, int32_t n
   if (st) std::memset(st, 0, sizeof(*st));
   const double* rho_phys = rho;
   if (flags & AARMR_FILTER_INPUT) {
-    launch_filter(g, m->p.rmin, 0, m->Hs, rho, m->rho_f, s);
+    launch_filter(g, m->p.rmin, m->Wf, 0, m->Hs, rho, m->rho_f, s);
     KCHECK();
     rho_phys = m->rho_f;
   }
@@ -963,17 +1223,15 @@ int aarmr_oc_update(aarmr_mesh* m, const double* x, const double* dc, const doub
   hipStream_t s = S(stream);
   const Grid& g = m->lg[0];
   double* lam = m->scal + SC_MISC + M_OC;
-  double* vol = m->scal + SC_MISC + M_VOL;
+  // the volume of the filtered trial density, sum_e (H x / Hs)_e, is the
+  // weighted sum sum_j cw_j x_j: no filter inside the bisection
   const double target = volfrac * (double)g.ne;
+  const int nparts = kRedBlocks;
   launch_oc_init(lam, s);
   KCHECK();
   for (int it = 0; it < 200; ++it) {
-    launch_oc_step(g.ne, x, dc, dv, move, lam, x_new, s);
-    launch_filter(g, m->p.rmin, 0, m->Hs, x_new, rho_phys_new, s);
-    KCHECK();
-    const double* a = rho_phys_new;
-    TRY(dots(m, 1, &a, nullptr, &vol, g.ne, s));
-    launch_oc_bisect(lam, vol, target, s);
+    launch_oc_step(g.ne, x, dc, dv, m->cw, move, lam, x_new, m->partial, nparts, s);
+    launch_oc_bisect(lam, m->partial, nparts, target, s);
     KCHECK();
     if ((it & 15) == 15) {
       double done;
@@ -982,6 +1240,8 @@ int aarmr_oc_update(aarmr_mesh* m, const double* x, const double* dc, const doub
       if (done != 0.0) break;
     }
   }
+  launch_filter(g, m->p.rmin, m->Wf, 0, m->Hs, x_new, rho_phys_new, s);
+  KCHECK();
   return AARMR_OK;
 }
 

@@ -38,13 +38,17 @@ struct RedScratch {
   double* partial;     // [kRedSlots][kRedBlocks]
 };
 
-struct DotSet {
-  const double* a[kRedSlots];
-  const double* b[kRedSlots];
+// k dot products a_i . b_i (b_i == nullptr: plain sum of a_i) of vectors of
+// element type T, accumulated and returned in FP64.
+template <typename T>
+struct DotSetT {
+  const T* a[kRedSlots];
+  const T* b[kRedSlots];
   double* out[kRedSlots];
   int k;               // number of products
   int64_t n;           // length
 };
+using DotSet = DotSetT<double>;
 
 // ---- fine-level operator (element-by-element, reflection-blocked) --------
 // mode 0: y = A v = Df K Df v + (I - Df) v for any v; mode 1: y = Df K Df v;
@@ -102,9 +106,38 @@ void launch_jacobi_update(int64_t n3, const double* b, const double* t, const do
 void launch_assemble_dense(const Grid& g, const double* Ke, double* A, hipStream_t s);
 void launch_gj_invert(int n, double* A, double* P, double* T, double* C, hipStream_t s);
 void launch_gemv(int n, const double* A, const double* x, double* y, hipStream_t s);
+// FP32 V-cycle pieces (vectors FP32; element matrices and the coarsest
+// inverse stay FP64 and are applied with FP32 vectors).
+void launch_apply_elemmat_f32(const Grid& g, const double* Ke, const float* v, float* y,
+                              hipStream_t s);
+void launch_apply_elemmat_mf_f32(const Grid& g, const double* Ke, const float* Mf,
+                                 const float* Ef, const uint8_t* eflag, const float* v, float* y,
+                                 hipStream_t s);
+void launch_restrict_f32(const Grid& coarse, const float* bf, const float* tf,
+                         const uint8_t* mask, float* bc, hipStream_t s);
+void launch_prolong_add_f32(const Grid& fine, const float* xc, const uint8_t* mask, float* xf,
+                            hipStream_t s);
+void launch_jacobi_first_f32(int64_t n3, const float* b, const float* dinv, float omega, float* x,
+                             hipStream_t s);
+void launch_jacobi_update_f32(int64_t n3, const float* b, const float* t, const float* dinv,
+                              float omega, float* x, hipStream_t s);
+void launch_gemv_f32(int n, const double* A, const float* x, float* y, hipStream_t s);
 
 // ---- vector kernels and reductions ----------------------------------------
 void launch_multidot(const DotSet& d, const RedScratch& rs, hipStream_t s);
+void launch_multidot_f32(const DotSetT<float>& d, const RedScratch& rs, hipStream_t s);
+// FP32 CG updates; the scalars stay FP64 in device memory and the updates are
+// formed in FP64 before rounding to FP32.
+void launch_cg_xr_f32(int64_t n, const double* rz, const double* pq, float* x, float* r,
+                      const float* p, const float* q, hipStream_t s);
+void launch_cg_p_f32(int64_t n, const double* rz_new, const double* rz_old, const float* z,
+                     float* p, hipStream_t s);
+// Refinement transfers: dst32 = src64 / sqrt(*nrm2);  x64 += sqrt(*nrm2) d32.
+void launch_to_f32_scaled(int64_t n, const double* src, const double* nrm2, float* dst,
+                          hipStream_t s);
+void launch_add_scaled_f32(int64_t n, const float* d, const double* nrm2, double* x,
+                           hipStream_t s);
+void launch_copy_f32(int64_t n, const float* src, float* dst, hipStream_t s);
 void launch_copy_masked(const Grid& g, const double* src, const uint8_t* mask, double* dst,
                         hipStream_t s);
 void launch_sub(int64_t n, const double* a, const double* b, double* out, hipStream_t s);
@@ -121,12 +154,21 @@ void launch_small_spd_solve(int n, int lda, const double* A, const double* b, do
                             unsigned* bad, hipStream_t s);
 
 // ---- filter, OC --------------------------------------------------------------
+// Cone weights max(0, r - |d|) of the filter offsets, (2R+1)^3 with
+// R = ceil(r) - 1, offset (dk, dj, di) at ((dk + R)(2R+1) + dj + R)(2R+1) + di + R.
+void filter_weights(double r, double* W);
+int filter_taps(double r);
 void launch_filter_rowsum(const Grid& g, double r, double* Hs, hipStream_t s);
-void launch_filter(const Grid& g, double r, int mode, const double* Hs, const double* in,
-                   double* out, hipStream_t s);
+void launch_filter(const Grid& g, double r, const double* W, int mode, const double* Hs,
+                   const double* in, double* out, hipStream_t s);
+void launch_fill(int64_t n, double v, double* out, hipStream_t s);
+// One OC trial: x_new at the bisection midpoint and block partials of
+// sum_j cw_j x_new_j (nparts blocks); then the bisection step on lam.
 void launch_oc_step(int64_t ne, const double* x, const double* dc, const double* dv,
-                    double move, double* lam, double* xnew, hipStream_t s);
-void launch_oc_bisect(double* lam, const double* vol, double target, hipStream_t s);
+                    const double* cw, double move, double* lam, double* xnew, double* partial,
+                    int nparts, hipStream_t s);
+void launch_oc_bisect(double* lam, const double* partial, int nparts, double target,
+                      hipStream_t s);
 void launch_oc_init(double* lam, hipStream_t s);
 
 }  // namespace aarmr

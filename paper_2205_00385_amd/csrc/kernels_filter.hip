@@ -1,5 +1,7 @@
 // Density filter (eqs. 31-32), its adjoint (eq. 33) and the device-side
 // bisection of the optimality-criteria update.
+#include <cmath>
+
 #include "internal.hpp"
 
 namespace aarmr {
@@ -32,30 +34,49 @@ __global__ void k_filter_rowsum(int nx, int ny, int nz, double r, int R, double*
 }
 
 // mode 0: out_e = sum_j w_ej in_j / Hs_e;  mode 1: out_e = sum_i w_ie in_i / Hs_i.
-__global__ void __launch_bounds__(256) k_filter(int nx, int ny, int nz, double r, int R, int mode,
+// W holds the cone weights max(0, r - |d|) of the (2R+1)^3 offsets
+// (dk, dj, di), di fastest; zero weights are summed too (adding +0 changes
+// nothing).  RC > 0 fixes R at compile time; elements whose neighbourhood
+// lies inside the grid take an unrolled path without bounds checks.
+template <int RC>
+__global__ void __launch_bounds__(256) k_filter(int nx, int ny, int nz, int Rrt, int mode,
+                                                const double* __restrict__ W,
                                                 const double* __restrict__ Hs,
                                                 const double* __restrict__ in,
                                                 double* __restrict__ out) {
+  const int R = RC > 0 ? RC : Rrt;
+  const int D = 2 * R + 1;
   const int64_t ne = (int64_t)nx * ny * nz;
-  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= ne) return;
   const int i = (int)(e % nx);
   const int64_t rest = e / nx;
   const int j = (int)(rest % ny), k = (int)(rest / ny);
+  const int64_t sy = nx, sz = (int64_t)nx * ny;
   double s = 0.0;
-  for (int dk = -R; dk <= R; ++dk) {
-    const int kk = k + dk;
-    if (kk < 0 || kk >= nz) continue;
-    for (int dj = -R; dj <= R; ++dj) {
-      const int jj = j + dj;
-      if (jj < 0 || jj >= ny) continue;
-      for (int di = -R; di <= R; ++di) {
-        const int ii = i + di;
-        if (ii < 0 || ii >= nx) continue;
-        const double w = r - sqrt((double)(di * di + dj * dj + dk * dk));
-        if (!(w > 0.0)) continue;
-        const int64_t nb = (int64_t)ii + (int64_t)nx * ((int64_t)jj + (int64_t)ny * kk);
-        s += mode == 0 ? w * in[nb] : w * in[nb] / Hs[nb];
+  const bool inside = i >= R && i < nx - R && j >= R && j < ny - R && k >= R && k < nz - R;
+  if (RC > 0 && inside && mode == 0) {
+#pragma unroll
+    for (int dk = -RC; dk <= RC; ++dk)
+#pragma unroll
+      for (int dj = -RC; dj <= RC; ++dj)
+#pragma unroll
+        for (int di = -RC; di <= RC; ++di)
+          s = fma(W[((dk + RC) * D + (dj + RC)) * D + (di + RC)], in[e + di + sy * dj + sz * dk], s);
+  } else {
+    for (int dk = -R; dk <= R; ++dk) {
+      const int kk = k + dk;
+      if (kk < 0 || kk >= nz) continue;
+      for (int dj = -R; dj <= R; ++dj) {
+        const int jj = j + dj;
+        if (jj < 0 || jj >= ny) continue;
+        for (int di = -R; di <= R; ++di) {
+          const int ii = i + di;
+          if (ii < 0 || ii >= nx) continue;
+          const double w = W[((dk + R) * D + (dj + R)) * D + (di + R)];
+          const int64_t nb = e + di + sy * dj + sz * dk;
+          s = mode == 0 ? fma(w, in[nb], s) : fma(w, in[nb] / Hs[nb], s);
+        }
       }
     }
   }
@@ -72,52 +93,109 @@ __global__ void k_oc_init(double* lam) {
   }
 }
 
-__global__ void k_oc_step(int64_t ne, const double* __restrict__ x, const double* __restrict__ dc,
-                          const double* __restrict__ dv, double move,
-                          const double* __restrict__ lam, double* __restrict__ xnew) {
-  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= ne || lam[3] != 0.0) return;
+// x_new for the midpoint of lam and block partials of sum_j c_j x_new_j,
+// the volume of the filtered x_new (c = H^T (1 / Hs), the column weights of
+// the normalised filter).
+__global__ void __launch_bounds__(256) k_oc_step(int64_t ne, const double* __restrict__ x,
+                                                 const double* __restrict__ dc,
+                                                 const double* __restrict__ dv,
+                                                 const double* __restrict__ cw, double move,
+                                                 const double* __restrict__ lam,
+                                                 double* __restrict__ xnew,
+                                                 double* __restrict__ partial) {
+  __shared__ double red[4];
+  if (lam[3] != 0.0) return;  // block-uniform
   const double lmid = 0.5 * (lam[0] + lam[1]);
-  const double B = fmax(0.0, -dc[e]) / dv[e];
-  const double xe = x[e];
-  double v = xe * sqrt(B / lmid);
-  v = fmin(v, fmin(1.0, xe + move));
-  v = fmax(v, fmax(0.0, xe - move));
-  xnew[e] = v;
+  double acc = 0.0;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < ne;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const double B = fmax(0.0, -dc[e]) / dv[e];
+    const double xe = x[e];
+    double v = xe * sqrt(B / lmid);
+    v = fmin(v, fmin(1.0, xe + move));
+    v = fmax(v, fmax(0.0, xe - move));
+    xnew[e] = v;
+    acc = fma(cw[e], v, acc);
+  }
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) partial[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
-__global__ void k_oc_bisect(double* lam, const double* __restrict__ vol, double target) {
-  if (threadIdx.x != 0 || blockIdx.x != 0 || lam[3] != 0.0) return;
+// Sum the nparts partials in a fixed order, then one bisection step on lam.
+__global__ void __launch_bounds__(256) k_oc_bisect(double* lam, const double* __restrict__ partial,
+                                                   int nparts, double target) {
+  __shared__ double red[4];
+  if (lam[3] != 0.0) return;
+  double acc = 0.0;
+  for (int b = threadIdx.x; b < nparts; b += 256) acc += partial[b];
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  const double vol = (red[0] + red[1]) + (red[2] + red[3]);
   const double lmid = 0.5 * (lam[0] + lam[1]);
   lam[2] = lmid;
-  if (*vol > target) lam[0] = lmid;
+  if (vol > target) lam[0] = lmid;
   else lam[1] = lmid;
   if ((lam[1] - lam[0]) / (lam[0] + lam[1]) <= 1e-3) lam[3] = 1.0;
+}
+
+__global__ void k_fill(int64_t n, double v, double* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = v;
 }
 
 }  // namespace
 
 static int filter_reach(double r) { return (int)ceil(r) - 1; }
 
+void filter_weights(double r, double* W) {
+  const int R = filter_reach(r), D = 2 * R + 1;
+  for (int dk = -R; dk <= R; ++dk)
+    for (int dj = -R; dj <= R; ++dj)
+      for (int di = -R; di <= R; ++di) {
+        const double w = r - std::sqrt((double)(di * di + dj * dj + dk * dk));
+        W[((dk + R) * D + (dj + R)) * D + (di + R)] = w > 0.0 ? w : 0.0;
+      }
+}
+
+int filter_taps(double r) {
+  const int D = 2 * filter_reach(r) + 1;
+  return D * D * D;
+}
+
 void launch_filter_rowsum(const Grid& g, double r, double* Hs, hipStream_t s) {
   k_filter_rowsum<<<nblk(g.ne, 256), 256, 0, s>>>(g.nx, g.ny, g.nz, r, filter_reach(r), Hs);
 }
 
-void launch_filter(const Grid& g, double r, int mode, const double* Hs, const double* in,
-                   double* out, hipStream_t s) {
-  k_filter<<<nblk(g.ne, 256), 256, 0, s>>>(g.nx, g.ny, g.nz, r, filter_reach(r), mode, Hs, in,
-                                           out);
+void launch_filter(const Grid& g, double r, const double* W, int mode, const double* Hs,
+                   const double* in, double* out, hipStream_t s) {
+  const int R = filter_reach(r);
+  const unsigned nb = nblk(g.ne, 256);
+  switch (R) {
+    case 1: k_filter<1><<<nb, 256, 0, s>>>(g.nx, g.ny, g.nz, R, mode, W, Hs, in, out); break;
+    case 2: k_filter<2><<<nb, 256, 0, s>>>(g.nx, g.ny, g.nz, R, mode, W, Hs, in, out); break;
+    default: k_filter<0><<<nb, 256, 0, s>>>(g.nx, g.ny, g.nz, R, mode, W, Hs, in, out); break;
+  }
+}
+
+void launch_fill(int64_t n, double v, double* out, hipStream_t s) {
+  k_fill<<<nblk(n, 256), 256, 0, s>>>(n, v, out);
 }
 
 void launch_oc_init(double* lam, hipStream_t s) { k_oc_init<<<1, 64, 0, s>>>(lam); }
 
-void launch_oc_step(int64_t ne, const double* x, const double* dc, const double* dv, double move,
-                    double* lam, double* xnew, hipStream_t s) {
-  k_oc_step<<<nblk(ne, 256), 256, 0, s>>>(ne, x, dc, dv, move, lam, xnew);
+void launch_oc_step(int64_t ne, const double* x, const double* dc, const double* dv,
+                    const double* cw, double move, double* lam, double* xnew, double* partial,
+                    int nparts, hipStream_t s) {
+  k_oc_step<<<nparts, 256, 0, s>>>(ne, x, dc, dv, cw, move, lam, xnew, partial);
 }
 
-void launch_oc_bisect(double* lam, const double* vol, double target, hipStream_t s) {
-  k_oc_bisect<<<1, 64, 0, s>>>(lam, vol, target);
+void launch_oc_bisect(double* lam, const double* partial, int nparts, double target,
+                      hipStream_t s) {
+  k_oc_bisect<<<1, 256, 0, s>>>(lam, partial, nparts, target);
 }
 
 }  // namespace aarmr

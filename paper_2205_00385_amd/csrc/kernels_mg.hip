@@ -188,21 +188,21 @@ __global__ void __launch_bounds__(256) k_galerkin_lds(int cnx, int cny, int cnz,
 // M_c = R_c M_0 R_c with (R_c v)[3b + s] = (-1)^(bit s of c) v[3(b ^ c) + s],
 // and only M_0 (row blocks Mf[a][col][r] = M_0[3a + r][col]) is read, as
 // wave-uniform (scalar) operands.  The other elements use the stored matrix.
-template <bool MATFREE>
+template <bool MATFREE, typename T>
 __global__ void __launch_bounds__(512) k_apply_elemmat(int nx, int ny, int nz,
                                                        const double* __restrict__ Ke,
-                                                       const double* __restrict__ Mf,
-                                                       const double* __restrict__ Ef,
+                                                       const T* __restrict__ Mf,
+                                                       const T* __restrict__ Ef,
                                                        const uint8_t* __restrict__ eflag,
-                                                       const double* __restrict__ v,
-                                                       double* __restrict__ y) {
-  __shared__ double red[8][3][64];
+                                                       const T* __restrict__ v,
+                                                       T* __restrict__ y) {
+  __shared__ T red[8][3][64];
   const int a = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int lane = threadIdx.x & 63;
   const int64_t nn = (int64_t)(nx + 1) * (ny + 1) * (nz + 1);
   const int64_t ne = (int64_t)nx * ny * nz;
   const int64_t n = (int64_t)blockIdx.x * 64 + lane;
-  double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
+  T acc0 = 0, acc1 = 0, acc2 = 0;
   if (n < nn) {
     const int i = (int)(n % (nx + 1));
     const int64_t rest = n / (nx + 1);
@@ -211,7 +211,7 @@ __global__ void __launch_bounds__(512) k_apply_elemmat(int nx, int ny, int nz,
     const int ex = i - (a & 1), ey = j - ((a >> 1) & 1), ez = k - (a >> 2);
     if (ex >= 0 && ex < nx && ey >= 0 && ey < ny && ez >= 0 && ez < nz) {
       const int64_t e = (int64_t)ex + (int64_t)nx * ((int64_t)ey + (int64_t)ny * ez);
-      double ve[24];
+      T ve[24];
 #pragma unroll
       for (int b = 0; b < 8; ++b) {
         const int64_t nb = node_of(nx, ny, ex + (b & 1), ey + ((b >> 1) & 1), ez + (b >> 2));
@@ -222,15 +222,15 @@ __global__ void __launch_bounds__(512) k_apply_elemmat(int nx, int ny, int nz,
         const int fnx = 2 * nx, fny = 2 * ny;
 #pragma unroll
         for (int c = 0; c < 8; ++c) {
-          const double Ec = Ef[(int64_t)(2 * ex + (c & 1)) +
+          const T Ec = Ef[(int64_t)(2 * ex + (c & 1)) +
                                (int64_t)fnx * ((2 * ey + ((c >> 1) & 1)) +
                                                (int64_t)fny * (2 * ez + (c >> 2)))];
-          const double* M = Mf + (a ^ c) * 72;
-          double t0 = 0.0, t1 = 0.0, t2 = 0.0;
+          const T* M = Mf + (a ^ c) * 72;
+          T t0 = 0, t1 = 0, t2 = 0;
 #pragma unroll
           for (int q = 0; q < 24; ++q) {
             const int b = q / 3, sc = q % 3;
-            const double w = ((c >> sc) & 1) ? -ve[3 * (b ^ c) + sc] : ve[3 * (b ^ c) + sc];
+            const T w = ((c >> sc) & 1) ? -ve[3 * (b ^ c) + sc] : ve[3 * (b ^ c) + sc];
             t0 = fma(M[3 * q + 0], w, t0);
             t1 = fma(M[3 * q + 1], w, t1);
             t2 = fma(M[3 * q + 2], w, t2);
@@ -242,9 +242,9 @@ __global__ void __launch_bounds__(512) k_apply_elemmat(int nx, int ny, int nz,
       } else {
 #pragma unroll
         for (int q = 0; q < 24; ++q) {
-          acc0 = fma(Ke[(int64_t)sidx(3 * a + 0, q) * ne + e], ve[q], acc0);
-          acc1 = fma(Ke[(int64_t)sidx(3 * a + 1, q) * ne + e], ve[q], acc1);
-          acc2 = fma(Ke[(int64_t)sidx(3 * a + 2, q) * ne + e], ve[q], acc2);
+          acc0 = fma((T)Ke[(int64_t)sidx(3 * a + 0, q) * ne + e], ve[q], acc0);
+          acc1 = fma((T)Ke[(int64_t)sidx(3 * a + 1, q) * ne + e], ve[q], acc1);
+          acc2 = fma((T)Ke[(int64_t)sidx(3 * a + 2, q) * ne + e], ve[q], acc2);
         }
       }
     }
@@ -254,7 +254,7 @@ __global__ void __launch_bounds__(512) k_apply_elemmat(int nx, int ny, int nz,
   red[a][2][lane] = acc2;
   __syncthreads();
   if (a < 3 && n < nn) {
-    double sum = red[0][a][lane];
+    T sum = red[0][a][lane];
 #pragma unroll
     for (int q = 1; q < 8; ++q) sum += red[q][a][lane];
     y[a * nn + n] = sum;
@@ -745,13 +745,52 @@ void launch_galerkin_from_coarse(const Grid& coarse, const double* Kf, double* K
 
 void launch_apply_elemmat(const Grid& g, const double* Ke, const double* v, double* y,
                           hipStream_t s) {
-  k_apply_elemmat<false><<<nblk(g.nn, 64), 512, 0, s>>>(g.nx, g.ny, g.nz, Ke, nullptr, nullptr,
-                                                        nullptr, v, y);
+  k_apply_elemmat<false, double><<<nblk(g.nn, 64), 512, 0, s>>>(g.nx, g.ny, g.nz, Ke, nullptr,
+                                                                nullptr, nullptr, v, y);
 }
 
 void launch_apply_elemmat_mf(const Grid& g, const double* Ke, const double* Mf, const double* Ef,
                              const uint8_t* eflag, const double* v, double* y, hipStream_t s) {
-  k_apply_elemmat<true><<<nblk(g.nn, 64), 512, 0, s>>>(g.nx, g.ny, g.nz, Ke, Mf, Ef, eflag, v, y);
+  k_apply_elemmat<true, double><<<nblk(g.nn, 64), 512, 0, s>>>(g.nx, g.ny, g.nz, Ke, Mf, Ef, eflag,
+                                                               v, y);
+}
+
+void launch_apply_elemmat_f32(const Grid& g, const double* Ke, const float* v, float* y,
+                              hipStream_t s) {
+  k_apply_elemmat<false, float><<<nblk(g.nn, 64), 512, 0, s>>>(g.nx, g.ny, g.nz, Ke, nullptr,
+                                                               nullptr, nullptr, v, y);
+}
+
+void launch_apply_elemmat_mf_f32(const Grid& g, const double* Ke, const float* Mf,
+                                 const float* Ef, const uint8_t* eflag, const float* v, float* y,
+                                 hipStream_t s) {
+  k_apply_elemmat<true, float><<<nblk(g.nn, 64), 512, 0, s>>>(g.nx, g.ny, g.nz, Ke, Mf, Ef, eflag,
+                                                              v, y);
+}
+
+void launch_restrict_f32(const Grid& coarse, const float* bf, const float* tf,
+                         const uint8_t* mask, float* bc, hipStream_t s) {
+  k_restrict<float><<<dim3(nblk(coarse.nn, 64), 3), 192, 0, s>>>(coarse.nx, coarse.ny, coarse.nz,
+                                                                 bf, tf, mask, bc);
+}
+
+void launch_prolong_add_f32(const Grid& fine, const float* xc, const uint8_t* mask, float* xf,
+                            hipStream_t s) {
+  k_prolong_add<float><<<nblk(fine.nn, 256), 256, 0, s>>>(fine.nx, fine.ny, fine.nz, xc, mask, xf);
+}
+
+void launch_jacobi_first_f32(int64_t n3, const float* b, const float* dinv, float omega, float* x,
+                             hipStream_t s) {
+  k_jacobi_first<float><<<nblk(n3, 256), 256, 0, s>>>(n3, b, dinv, omega, x);
+}
+
+void launch_jacobi_update_f32(int64_t n3, const float* b, const float* t, const float* dinv,
+                              float omega, float* x, hipStream_t s) {
+  k_jacobi_update<float><<<nblk(n3, 256), 256, 0, s>>>(n3, b, t, dinv, omega, x);
+}
+
+void launch_gemv_f32(int n, const double* A, const float* x, float* y, hipStream_t s) {
+  k_gemv<float, float><<<nblk(n, 4), 256, 0, s>>>(n, A, x, y);
 }
 
 void launch_diag_elemmat(const Grid& g, const double* Ke, double* dinv, float* dinv32,

@@ -34,26 +34,29 @@ __device__ inline double block_sum(double v, double* sh) {
 // passes have a fixed summation order, so results are bitwise reproducible;
 // the kernel boundary orders the partial stores before their reads without
 // any device-scope fence (each of which would write back an XCD's L2).
-__global__ void __launch_bounds__(256) k_multidot(DotSet d, double* __restrict__ partial) {
+template <typename T>
+__global__ void __launch_bounds__(256) k_multidot(DotSetT<T> d, double* __restrict__ partial) {
   __shared__ double sh[4];
   const int nb = gridDim.x;
   const int64_t stride = (int64_t)nb * 256;
   for (int k = 0; k < d.k; ++k) {
-    const double* a = d.a[k];
-    const double* b = d.b[k];
+    const T* a = d.a[k];
+    const T* b = d.b[k];
     double s = 0.0;
     if (b) {
       for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < d.n; i += stride)
-        s = fma(a[i], b[i], s);
+        s = fma((double)a[i], (double)b[i], s);
     } else {  // plain sum
-      for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < d.n; i += stride) s += a[i];
+      for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < d.n; i += stride)
+        s += (double)a[i];
     }
     s = block_sum(s, sh);
     if (threadIdx.x == 0) partial[k * kRedBlocks + blockIdx.x] = s;
   }
 }
 
-__global__ void __launch_bounds__(256) k_multidot_finish(DotSet d, int nb,
+template <typename T>
+__global__ void __launch_bounds__(256) k_multidot_finish(DotSetT<T> d, int nb,
                                                          const double* __restrict__ partial) {
   __shared__ double sh[4];
   for (int k = 0; k < d.k; ++k) {
@@ -108,6 +111,45 @@ __global__ void k_scale_inv_sqrt(int64_t n, const double* __restrict__ src,
   dst[i] = src[i] * s;
 }
 
+__global__ void k_cg_xr_f32(int64_t n, const double* __restrict__ rz,
+                            const double* __restrict__ pq, float* __restrict__ x,
+                            float* __restrict__ r, const float* __restrict__ p,
+                            const float* __restrict__ q) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double alpha = *rz / *pq;
+  x[i] = (float)fma(alpha, (double)p[i], (double)x[i]);
+  r[i] = (float)fma(-alpha, (double)q[i], (double)r[i]);
+}
+
+__global__ void k_cg_p_f32(int64_t n, const double* __restrict__ rz_new,
+                           const double* __restrict__ rz_old, const float* __restrict__ z,
+                           float* __restrict__ p) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double beta = *rz_new / *rz_old;
+  p[i] = (float)fma(beta, (double)p[i], (double)z[i]);
+}
+
+__global__ void k_to_f32_scaled(int64_t n, const double* __restrict__ src,
+                                const double* __restrict__ nrm2, float* __restrict__ dst) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  dst[i] = (float)(src[i] / sqrt(*nrm2));
+}
+
+__global__ void k_add_scaled_f32(int64_t n, const float* __restrict__ d,
+                                 const double* __restrict__ nrm2, double* __restrict__ x) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  x[i] = fma(sqrt(*nrm2), (double)d[i], x[i]);
+}
+
+__global__ void k_copy_f32(int64_t n, const float* __restrict__ src, float* __restrict__ dst) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+
 struct VecList {
   const double* v[2 * AARMR_MAX_BASIS];
 };
@@ -160,11 +202,44 @@ __global__ void k_small_spd_solve(int n, int lda, const double* __restrict__ A,
 
 }  // namespace
 
-void launch_multidot(const DotSet& d, const RedScratch& rs, hipStream_t s) {
+template <typename T>
+void multidot_t(const DotSetT<T>& d, const RedScratch& rs, hipStream_t s) {
   int64_t want = (d.n + 255) / 256;
   int nb = (int)(want < kRedBlocks ? (want < 1 ? 1 : want) : kRedBlocks);
-  k_multidot<<<nb, 256, 0, s>>>(d, rs.partial);
-  k_multidot_finish<<<1, 256, 0, s>>>(d, nb, rs.partial);
+  k_multidot<T><<<nb, 256, 0, s>>>(d, rs.partial);
+  k_multidot_finish<T><<<1, 256, 0, s>>>(d, nb, rs.partial);
+}
+
+void launch_multidot(const DotSet& d, const RedScratch& rs, hipStream_t s) {
+  multidot_t<double>(d, rs, s);
+}
+
+void launch_multidot_f32(const DotSetT<float>& d, const RedScratch& rs, hipStream_t s) {
+  multidot_t<float>(d, rs, s);
+}
+
+void launch_cg_xr_f32(int64_t n, const double* rz, const double* pq, float* x, float* r,
+                      const float* p, const float* q, hipStream_t s) {
+  k_cg_xr_f32<<<nblk(n, 256), 256, 0, s>>>(n, rz, pq, x, r, p, q);
+}
+
+void launch_cg_p_f32(int64_t n, const double* rz_new, const double* rz_old, const float* z,
+                     float* p, hipStream_t s) {
+  k_cg_p_f32<<<nblk(n, 256), 256, 0, s>>>(n, rz_new, rz_old, z, p);
+}
+
+void launch_to_f32_scaled(int64_t n, const double* src, const double* nrm2, float* dst,
+                          hipStream_t s) {
+  k_to_f32_scaled<<<nblk(n, 256), 256, 0, s>>>(n, src, nrm2, dst);
+}
+
+void launch_add_scaled_f32(int64_t n, const float* d, const double* nrm2, double* x,
+                           hipStream_t s) {
+  k_add_scaled_f32<<<nblk(n, 256), 256, 0, s>>>(n, d, nrm2, x);
+}
+
+void launch_copy_f32(int64_t n, const float* src, float* dst, hipStream_t s) {
+  k_copy_f32<<<nblk(n, 256), 256, 0, s>>>(n, src, dst);
 }
 
 void launch_copy_masked(const Grid& g, const double* src, const uint8_t* mask, double* dst,
