@@ -82,16 +82,20 @@ struct aarmr_mesh {
   double KE[576];
   WalshConsts wk;             // reflection-blocked form of KE
   double Mc[8 * kSymEntries]; // P_c^T KE P_c per child position, packed
-  double Mf[8 * 72];          // child 0's, row blocks: [a][col][r] = M_0[3a + r][col]
-  float Mf32[8 * 72];         // the same in FP32
+  double Bw[576];             // W M_0 W / 64 in the Walsh x component basis
+  float Bw32[576];
   bool fp32 = false;          // precision == AARMR_FP32_REFINE
   // workspace views
   char* ws = nullptr;
   int64_t ws_bytes = 0;
   double* KEd = nullptr;
   double* Mcd = nullptr;      // P_c^T KE P_c of the 8 children, packed
-  double* Mfd = nullptr;      // the same as row blocks (Mf)
-  float* Mf32d = nullptr;     // FP32 copy (refinement form)
+  double* Bwd = nullptr;      // Bw on the device
+  float* Bw32d = nullptr;
+  double* Y1 = nullptr;       // level-1 element products [24][ne1]
+  double* Kcomp1 = nullptr;   // compact copy of the flagged parents' matrices
+  int cap1 = 0;               // its capacity (parents)
+  float* Y1f = nullptr;
   float* E32 = nullptr;       // FP32 moduli (refinement form)
   float *r32 = nullptr, *z32 = nullptr, *p32 = nullptr, *q32 = nullptr, *d32 = nullptr;
   uint8_t* eflag1 = nullptr;  // level-1 parents touching a fixed DOF
@@ -246,6 +250,54 @@ bool mirror_children(const double* Mc) {
   return true;
 }
 
+// Bw = W M_0 W / 64: child 0's Galerkin matrix in the Walsh x component
+// basis, W[3k + s][3a + s] = (-1)^popcount(k & a).
+void walsh_child(const double* Mc, double* Bw) {
+  auto pc = [](int x) { return __builtin_popcount((unsigned)x); };
+  for (int ka = 0; ka < 24; ++ka)
+    for (int la = 0; la < 24; ++la) {
+      const int k = ka / 3, sk = ka % 3, l = la / 3, sl = la % 3;
+      double acc = 0.0;
+      for (int a = 0; a < 8; ++a)
+        for (int b = 0; b < 8; ++b) {
+          const double sg = ((pc(k & a) + pc(l & b)) & 1) ? -1.0 : 1.0;
+          acc += sg * Mc[sym_index(3 * a + sk, 3 * b + sl)];
+        }
+      Bw[ka * 24 + la] = acc / 64.0;
+    }
+}
+
+// For moduli E_c = 1 + c / 8: W (B' o Ehat(mu ^ mu)) W == sum_c E_c M_c, the
+// identity the level-1 kernel evaluates.
+bool walsh_parent_check(const double* Mc, const double* Bw) {
+  auto pc = [](int x) { return __builtin_popcount((unsigned)x); };
+  double E[8], Eh[8], G[576], scale = 0.0;
+  for (int c = 0; c < 8; ++c) E[c] = 1.0 + c / 8.0;
+  for (int k = 0; k < 8; ++k) {
+    Eh[k] = 0.0;
+    for (int c = 0; c < 8; ++c) Eh[k] += (pc(k & c) & 1) ? -E[c] : E[c];
+  }
+  for (int ka = 0; ka < 24; ++ka)
+    for (int la = 0; la < 24; ++la) {
+      const int mk = (ka / 3) ^ (1 << (ka % 3)), ml = (la / 3) ^ (1 << (la % 3));
+      G[ka * 24 + la] = Bw[ka * 24 + la] * Eh[mk ^ ml];
+    }
+  for (int x = 0; x < 8 * kSymEntries; ++x) scale = std::max(scale, std::fabs(Mc[x]));
+  for (int I = 0; I < 24; ++I)
+    for (int J = 0; J < 24; ++J) {
+      double want = 0.0, got = 0.0;
+      for (int c = 0; c < 8; ++c) want += E[c] * Mc[c * kSymEntries + sym_index(I, J)];
+      const int a = I / 3, s = I % 3, b = J / 3, t = J % 3;
+      for (int k = 0; k < 8; ++k)
+        for (int l = 0; l < 8; ++l) {
+          const double sg = ((pc(k & a) + pc(l & b)) & 1) ? -1.0 : 1.0;
+          got += sg * G[(3 * k + s) * 24 + 3 * l + t];
+        }
+      if (std::fabs(got - want) > 1e-11 * scale) return false;
+    }
+  return true;
+}
+
 // Assign workspace views; with base == nullptr only computes the size.
 int64_t layout(aarmr_mesh* m, char* base) {
   int64_t off = 0;
@@ -259,10 +311,13 @@ int64_t layout(aarmr_mesh* m, char* base) {
   const int64_t d8 = sizeof(double);
   m->KEd = (double*)take(576 * d8);
   m->Mcd = (double*)take(8 * kSymEntries * d8);
-  m->Mfd = (double*)take(8 * 72 * d8);
   m->eflag1 = (uint8_t*)take(m->lg[1].ne);
   m->list1 = (int*)take(m->lg[1].ne * 4);
   m->count1 = (int*)take(4);
+  m->Bwd = (double*)take(576 * d8);
+  m->Y1 = (double*)take(24 * m->lg[1].ne * d8);
+  m->cap1 = (int)std::min<int64_t>(m->lg[1].ne, std::max<int64_t>(m->lg[1].ne / 8, 1024));
+  m->Kcomp1 = (double*)take((int64_t)kSymEntries * m->cap1 * d8);
   m->E = (double*)take(g.ne * d8);
   m->E_prev = (double*)take(g.ne * d8);
   m->dE = (double*)take(g.ne * d8);
@@ -294,7 +349,8 @@ int64_t layout(aarmr_mesh* m, char* base) {
   }
   if (m->fp32) {
     const int64_t f4 = sizeof(float);
-    m->Mf32d = (float*)take(8 * 72 * f4);
+    m->Bw32d = (float*)take(576 * f4);
+    m->Y1f = (float*)take(24 * m->lg[1].ne * f4);
     m->E32 = (float*)take(g.ne * f4);
     m->r32 = (float*)take(n3 * f4);
     m->z32 = (float*)take(n3 * f4);
@@ -385,7 +441,8 @@ int apply(aarmr_mesh* m, int l, const double* v, double* y, hipStream_t s,
     launch_ebe(m->lg[0], m->wk, m->E, m->mask, v, y, any_input ? 0 : 2, s);
     ++m->sweeps;
   } else if (l == 1) {
-    launch_apply_elemmat_mf(m->lg[1], m->lv[1].Ke, m->Mfd, m->E, m->eflag1, v, y, s);
+    launch_apply_l1(m->lg[1], m->lv[1].Ke, m->Kcomp1, m->cap1, m->Bwd, m->E, m->eflag1,
+                    m->list1, m->count1, v, m->Y1, y, s);
   } else {
     launch_apply_elemmat(m->lg[l], m->lv[l].Ke, v, y, s);
   }
@@ -449,7 +506,7 @@ int setup(aarmr_mesh* m, const double* rho, const int64_t* fixed, int64_t nfixed
   for (int l = 1; l < m->nlev; ++l) {
     if (l == 1)
       launch_galerkin_from_fine(m->lg[1], m->KEd, m->Mcd, m->E, m->mask, m->eflag1, m->list1,
-                                m->count1, m->lv[1].Ke, s);
+                                m->count1, m->lv[1].Ke, m->Kcomp1, m->cap1, s);
     else
       launch_galerkin_from_coarse(m->lg[l], m->lv[l - 1].Ke, m->lv[l].Ke, s);
     KCHECK();
@@ -473,7 +530,8 @@ int apply32(aarmr_mesh* m, int l, const float* v, float* y, hipStream_t s) {
     launch_ebe_f32(m->lg[0], m->wk, m->E32, m->mask, v, y, 2, s);
     ++m->sweeps;
   } else if (l == 1) {
-    launch_apply_elemmat_mf_f32(m->lg[1], m->lv[1].Ke, m->Mf32d, m->E32, m->eflag1, v, y, s);
+    launch_apply_l1_f32(m->lg[1], m->lv[1].Ke, m->Kcomp1, m->cap1, m->Bw32d, m->E32,
+                        m->eflag1, m->list1, m->count1, v, m->Y1f, y, s);
   } else {
     launch_apply_elemmat_f32(m->lg[l], m->lv[l].Ke, v, y, s);
   }
@@ -862,11 +920,12 @@ int aarmr_mesh_create(const aarmr_params* p, aarmr_mesh** out) {
   }
   hex8_stiffness(p->nu, m->KE);  // unit modulus; E0 enters through SIMP
   child_galerkin(m->KE, m->Mc);
-  for (int a = 0; a < 8; ++a)
-    for (int q = 0; q < 24; ++q)
-      for (int r = 0; r < 3; ++r)
-        m->Mf[(a * 24 + q) * 3 + r] = m->Mc[sym_index(3 * a + r, q)];
-  for (int x = 0; x < 8 * 72; ++x) m->Mf32[x] = (float)m->Mf[x];
+  walsh_child(m->Mc, m->Bw);
+  for (int x = 0; x < 576; ++x) m->Bw32[x] = (float)m->Bw[x];
+  if (!walsh_parent_check(m->Mc, m->Bw)) {
+    delete m;
+    return fail(AARMR_E_INVALID, "Walsh form of the level-1 operator does not reproduce it");
+  }
   m->fp32 = (p->precision == AARMR_FP32_REFINE);
   if (!mirror_children(m->Mc)) {
     delete m;
@@ -905,9 +964,10 @@ int aarmr_bind_workspace(aarmr_mesh* m, void* dev_ptr, int64_t bytes, void* stre
   hipStream_t s = S(stream);
   HIP_TRY(hipMemcpyAsync(m->KEd, m->KE, 576 * sizeof(double), hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(m->Mcd, m->Mc, 8 * kSymEntries * sizeof(double), hipMemcpyHostToDevice, s));
-  HIP_TRY(hipMemcpyAsync(m->Mfd, m->Mf, 8 * 72 * sizeof(double), hipMemcpyHostToDevice, s));
-  if (m->fp32)
-    HIP_TRY(hipMemcpyAsync(m->Mf32d, m->Mf32, 8 * 72 * sizeof(float), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(m->Bwd, m->Bw, 576 * sizeof(double), hipMemcpyHostToDevice, s));
+  if (m->fp32) {
+    HIP_TRY(hipMemcpyAsync(m->Bw32d, m->Bw32, 576 * sizeof(float), hipMemcpyHostToDevice, s));
+  }
   HIP_TRY(hipMemsetAsync(m->flags, 0, 64, s));
   HIP_TRY(hipMemsetAsync(m->mask, 0, (m->lg[0].nn + 3) / 4 * 4, s));
   launch_fill(m->lg[0].ne, 1.0, m->ones_dv, s);

@@ -81,18 +81,24 @@ __host__ __device__ constexpr int sym_index(int r, int c) {
 }
 // Level-1 operators from the fine moduli: fast path for every parent, exact
 // masked product for the parents flagged in eflag (1 = touches a fixed DOF),
-// whose indices are listed in list[0..*count).
+// whose indices are listed in list[0..*count); list entries w < cap are also
+// stored compactly, Kcomp[entry][w].
 void launch_galerkin_from_fine(const Grid& coarse, const double* KE, const double* Mc,
                                const double* E, const uint8_t* mask, uint8_t* eflag, int* list,
-                               int* count, double* Kc, hipStream_t s);
+                               int* count, double* Kc, double* Kcomp, int cap, hipStream_t s);
 void launch_galerkin_from_coarse(const Grid& coarse, const double* Kf, double* Kc, hipStream_t s);
 void launch_apply_elemmat(const Grid& g, const double* Ke, const double* v, double* y,
                           hipStream_t s);
-// Level-1 product: unflagged parents from the fine moduli Ef and child 0's
-// matrix as row blocks, Mf[a][col][r] = (P_0^T KE P_0)[3a + r][col] (the
-// other children are its mirror images); flagged parents from Ke.
-void launch_apply_elemmat_mf(const Grid& g, const double* Ke, const double* Mf, const double* Ef,
-                             const uint8_t* eflag, const double* v, double* y, hipStream_t s);
+// Level-1 product through the Walsh form of the child matrices:
+// Bw = W M_0 W / 64 (24 x 24, Walsh x component basis, index 3k + s), Y a
+// [24][ne] element-product buffer.  Flagged parents (eflag 1, indices in
+// list[0..*count)) use their stored Ke.
+void launch_apply_l1(const Grid& g, const double* Ke, const double* Kcomp, int cap,
+                     const double* Bw, const double* Ef, const uint8_t* eflag, const int* list,
+                     const int* count, const double* v, double* Y, double* y, hipStream_t s);
+void launch_apply_l1_f32(const Grid& g, const double* Ke, const double* Kcomp, int cap,
+                         const float* Bw, const float* Ef, const uint8_t* eflag, const int* list,
+                         const int* count, const float* v, float* Y, float* y, hipStream_t s);
 void launch_diag_elemmat(const Grid& g, const double* Ke, double* dinv, float* dinv32,
                          hipStream_t s);
 void launch_restrict(const Grid& coarse, const double* bf, const double* tf, const uint8_t* mask,
@@ -110,9 +116,6 @@ void launch_gemv(int n, const double* A, const double* x, double* y, hipStream_t
 // inverse stay FP64 and are applied with FP32 vectors).
 void launch_apply_elemmat_f32(const Grid& g, const double* Ke, const float* v, float* y,
                               hipStream_t s);
-void launch_apply_elemmat_mf_f32(const Grid& g, const double* Ke, const float* Mf,
-                                 const float* Ef, const uint8_t* eflag, const float* v, float* y,
-                                 hipStream_t s);
 void launch_restrict_f32(const Grid& coarse, const float* bf, const float* tf,
                          const uint8_t* mask, float* bc, hipStream_t s);
 void launch_prolong_add_f32(const Grid& fine, const float* xc, const uint8_t* mask, float* xf,

@@ -83,7 +83,8 @@ __global__ void k_zero_int(int* p) { *p = 0; }
 // are staged in LDS, T_c = K_c P_c is formed by a column pass and
 // sum_c P_c^T T_c by a row pass.  FROM_FINE: children are E_c Df KE Df with
 // the fine fixed-DOF mask, for the parents listed by k_parent_flags (the
-// others are exact from the fast path).  Otherwise every parent, with the
+// others are exact from the fast path); list entry w < cap is also written to
+// the compact copy Kcomp[entry][w].  Otherwise every parent, with the
 // previous level's packed matrices as children.
 template <bool FROM_FINE>
 __global__ void __launch_bounds__(256) k_galerkin_lds(int cnx, int cny, int cnz,
@@ -93,7 +94,8 @@ __global__ void __launch_bounds__(256) k_galerkin_lds(int cnx, int cny, int cnz,
                                                       const int* __restrict__ list,
                                                       const int* __restrict__ count,
                                                       const double* __restrict__ Kf,
-                                                      double* __restrict__ Kc) {
+                                                      double* __restrict__ Kc,
+                                                      double* __restrict__ Kcomp, int cap) {
   __shared__ double sK[8][24][25];
   __shared__ uint8_t sm[27];
   __shared__ double sw[8];
@@ -173,27 +175,20 @@ __global__ void __launch_bounds__(256) k_galerkin_lds(int cnx, int cny, int cnz,
       }
     }
     Kc[(int64_t)sx * cne + eid] = acc;
+    if (FROM_FINE && w < cap) Kcomp[(int64_t)sx * cap + w] = acc;
   }
   __syncthreads();  // sK, sm, sw are reused by the next parent
   }
 }
 
-// y = sum_e L_e^T Ke_e L_e v on a coarse level.  Block: 64 consecutive nodes
-// x 8 waves; wave a takes each node as local corner a of the element
-// e = node - offset(a) and forms rows 3a..3a+2 of Ke_e v_e; the 8 partial
-// rows are summed in LDS in a fixed order.  MATFREE (level 1): elements with
-// eflag 0 (no fixed DOF among their 27 fine nodes) use
-// Ke_e = sum_c E_child(c) M_c, the Galerkin product of their 8 unmasked
-// children.  Child c is the mirror image of child 0 in the axes set in c, so
-// M_c = R_c M_0 R_c with (R_c v)[3b + s] = (-1)^(bit s of c) v[3(b ^ c) + s],
-// and only M_0 (row blocks Mf[a][col][r] = M_0[3a + r][col]) is read, as
-// wave-uniform (scalar) operands.  The other elements use the stored matrix.
-template <bool MATFREE, typename T>
+// y = sum_e L_e^T Ke_e L_e v on a coarse level (levels >= 2) from the stored
+// packed element matrices.  Block: 64 consecutive nodes x 8 waves; wave a
+// takes each node as local corner a of the element e = node - offset(a) and
+// forms rows 3a..3a+2 of Ke_e v_e; the 8 partial rows are summed in LDS in a
+// fixed order.  Vectors of type T, matrices FP64.
+template <typename T>
 __global__ void __launch_bounds__(512) k_apply_elemmat(int nx, int ny, int nz,
                                                        const double* __restrict__ Ke,
-                                                       const T* __restrict__ Mf,
-                                                       const T* __restrict__ Ef,
-                                                       const uint8_t* __restrict__ eflag,
                                                        const T* __restrict__ v,
                                                        T* __restrict__ y) {
   __shared__ T red[8][3][64];
@@ -218,34 +213,11 @@ __global__ void __launch_bounds__(512) k_apply_elemmat(int nx, int ny, int nz,
 #pragma unroll
         for (int c = 0; c < 3; ++c) ve[3 * b + c] = v[c * nn + nb];
       }
-      if (MATFREE && eflag[e] == 0) {
-        const int fnx = 2 * nx, fny = 2 * ny;
 #pragma unroll
-        for (int c = 0; c < 8; ++c) {
-          const T Ec = Ef[(int64_t)(2 * ex + (c & 1)) +
-                               (int64_t)fnx * ((2 * ey + ((c >> 1) & 1)) +
-                                               (int64_t)fny * (2 * ez + (c >> 2)))];
-          const T* M = Mf + (a ^ c) * 72;
-          T t0 = 0, t1 = 0, t2 = 0;
-#pragma unroll
-          for (int q = 0; q < 24; ++q) {
-            const int b = q / 3, sc = q % 3;
-            const T w = ((c >> sc) & 1) ? -ve[3 * (b ^ c) + sc] : ve[3 * (b ^ c) + sc];
-            t0 = fma(M[3 * q + 0], w, t0);
-            t1 = fma(M[3 * q + 1], w, t1);
-            t2 = fma(M[3 * q + 2], w, t2);
-          }
-          acc0 = fma((c & 1) ? -Ec : Ec, t0, acc0);
-          acc1 = fma((c & 2) ? -Ec : Ec, t1, acc1);
-          acc2 = fma((c & 4) ? -Ec : Ec, t2, acc2);
-        }
-      } else {
-#pragma unroll
-        for (int q = 0; q < 24; ++q) {
-          acc0 = fma((T)Ke[(int64_t)sidx(3 * a + 0, q) * ne + e], ve[q], acc0);
-          acc1 = fma((T)Ke[(int64_t)sidx(3 * a + 1, q) * ne + e], ve[q], acc1);
-          acc2 = fma((T)Ke[(int64_t)sidx(3 * a + 2, q) * ne + e], ve[q], acc2);
-        }
+      for (int q = 0; q < 24; ++q) {
+        acc0 = fma((T)Ke[(int64_t)sidx(3 * a + 0, q) * ne + e], ve[q], acc0);
+        acc1 = fma((T)Ke[(int64_t)sidx(3 * a + 1, q) * ne + e], ve[q], acc1);
+        acc2 = fma((T)Ke[(int64_t)sidx(3 * a + 2, q) * ne + e], ve[q], acc2);
       }
     }
   }
@@ -259,6 +231,174 @@ __global__ void __launch_bounds__(512) k_apply_elemmat(int nx, int ny, int nz,
     for (int q = 1; q < 8; ++q) sum += red[q][a][lane];
     y[a * nn + n] = sum;
   }
+}
+
+// 8-point Walsh-Hadamard transform x[k] <- sum_a (-1)^popcount(k & a) x[a]
+// of the entries 3a + s (one component s) of a 24-vector.
+template <typename T>
+__device__ __forceinline__ void wht8(T* x, int s) {
+#pragma unroll
+  for (int bit = 1; bit < 8; bit <<= 1)
+#pragma unroll
+    for (int a = 0; a < 8; ++a)
+      if (!(a & bit)) {
+        const T p = x[3 * a + s], q = x[3 * (a | bit) + s];
+        x[3 * a + s] = p + q;
+        x[3 * (a | bit) + s] = p - q;
+      }
+}
+
+// Level-1 element products, pass 1: Y[q][e] = (Ke_e v_e)[q], one thread per
+// parent element e and output component s (grid.y), which writes the entries
+// q = 3a + s.  Parents without a fixed DOF among their fine nodes have
+// Ke_e = sum_c E_c M_c with M_c = R_c M_0 R_c (R_c the mirror map of child c).
+// In the Walsh basis over the 8 corners (index 3k + s), R_c is the diagonal
+// sign (-1)^popcount(c & mu), mu(k, s) = k ^ (1 << s), so
+//   W Ke_e W / 64 = B'[kappa][lambda] * Ehat[mu(kappa) ^ mu(lambda)]
+// with B' = W M_0 W / 64 and Ehat the Walsh transform of the 8 child moduli:
+// y = W ((B' o Ehat) (W v)), about 256 FMA per thread.  Parents with eflag 1
+// are left to k_l1_masked, so no wave carries both paths.
+template <typename T, int so>
+__device__ __forceinline__ void l1_elem(int nx, int ny, int nz, const double* __restrict__ Ke,
+                                        const T* __restrict__ Bw, const T* __restrict__ Ef,
+                                        const uint8_t* __restrict__ eflag,
+                                        const T* __restrict__ v, T* __restrict__ Y) {
+  const int64_t nn = (int64_t)(nx + 1) * (ny + 1) * (nz + 1);
+  const int64_t ne = (int64_t)nx * ny * nz;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ne || eflag[e]) return;  // flagged parents: k_l1_masked
+  const int ex = (int)(e % nx);
+  const int64_t rest = e / nx;
+  const int ey = (int)(rest % ny), ez = (int)(rest / ny);
+  T x[24];
+#pragma unroll
+  for (int b = 0; b < 8; ++b) {
+    const int64_t nb = node_of(nx, ny, ex + (b & 1), ey + ((b >> 1) & 1), ez + (b >> 2));
+#pragma unroll
+    for (int c = 0; c < 3; ++c) x[3 * b + c] = v[c * nn + nb];
+  }
+  T y[8];  // entries 3a + so
+  {
+    T Eh[8];
+    const int fnx = 2 * nx, fny = 2 * ny;
+#pragma unroll
+    for (int c = 0; c < 8; ++c)
+      Eh[c] = Ef[(int64_t)(2 * ex + (c & 1)) +
+                 (int64_t)fnx * ((2 * ey + ((c >> 1) & 1)) + (int64_t)fny * (2 * ez + (c >> 2)))];
+#pragma unroll
+    for (int bit = 1; bit < 8; bit <<= 1)
+#pragma unroll
+      for (int c = 0; c < 8; ++c)
+        if (!(c & bit)) {
+          const T p = Eh[c], q = Eh[c | bit];
+          Eh[c] = p + q;
+          Eh[c | bit] = p - q;
+        }
+#pragma unroll
+    for (int s = 0; s < 3; ++s) wht8(x, s);
+    const T* B = Bw + so * 24;  // row kappa = 3k + so starts at B + 72k
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int muk = k ^ (1 << so);
+      T acc = 0;
+#pragma unroll
+      for (int mm = 0; mm < 8; ++mm) {
+        T t = 0;
+#pragma unroll
+        for (int s2 = 0; s2 < 3; ++s2) {
+          const int la = 3 * (muk ^ mm ^ (1 << s2)) + s2;
+          t = fma(B[72 * k + la], x[la], t);
+        }
+        acc = fma(Eh[mm], t, acc);
+      }
+      y[k] = acc;
+    }
+#pragma unroll
+    for (int bit = 1; bit < 8; bit <<= 1)
+#pragma unroll
+      for (int a = 0; a < 8; ++a)
+        if (!(a & bit)) {
+          const T p = y[a], q = y[a | bit];
+          y[a] = p + q;
+          y[a | bit] = p - q;
+        }
+  }
+#pragma unroll
+  for (int a = 0; a < 8; ++a) Y[(int64_t)(3 * a + so) * ne + e] = y[a];
+}
+
+// Level-1 element products of the flagged parents (list[0..*count)) from their
+// stored Galerkin matrices: one thread per (listed parent, row r).
+// Rows come from the compact copy Kcomp[entry][w] (coalesced over list entries
+// w) while the list fits its capacity, else from Ke.  Thread (w, r): lanes run
+// over w, the row r is uniform per wave.
+template <typename T>
+__global__ void __launch_bounds__(256) k_l1_masked(int nx, int ny, int nz,
+                                                   const double* __restrict__ Ke,
+                                                   const double* __restrict__ Kcomp, int cap,
+                                                   const int* __restrict__ list,
+                                                   const int* __restrict__ count,
+                                                   const T* __restrict__ v, T* __restrict__ Y) {
+  const int64_t nn = (int64_t)(nx + 1) * (ny + 1) * (nz + 1);
+  const int64_t ne = (int64_t)nx * ny * nz;
+  const int64_t cnt = *count;
+  const bool compact = cnt <= cap;
+  const int64_t stride = (int64_t)gridDim.x * 64;
+  const int r = blockIdx.y * 4 + (threadIdx.x >> 6);  // 6 x 4 waves: rows 0..23
+  for (int64_t w = (int64_t)blockIdx.x * 64 + (threadIdx.x & 63); w < cnt; w += stride) {
+    const int64_t e = list[w];
+    const int ex = (int)(e % nx);
+    const int64_t rest = e / nx;
+    const int ey = (int)(rest % ny), ez = (int)(rest / ny);
+    T acc = 0;
+#pragma unroll
+    for (int q = 0; q < 24; ++q) {
+      const int b = q / 3, c = q % 3;
+      const int64_t nb = node_of(nx, ny, ex + (b & 1), ey + ((b >> 1) & 1), ez + (b >> 2));
+      const double k = compact ? Kcomp[(int64_t)sidx(r, q) * cap + w] : Ke[(int64_t)sidx(r, q) * ne + e];
+      acc = fma((T)k, v[c * nn + nb], acc);
+    }
+    Y[(int64_t)r * ne + e] = acc;
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_l1_elem(int nx, int ny, int nz,
+                                                 const double* __restrict__ Ke,
+                                                 const T* __restrict__ Bw,
+                                                 const T* __restrict__ Ef,
+                                                 const uint8_t* __restrict__ eflag,
+                                                 const T* __restrict__ v, T* __restrict__ Y) {
+  switch (blockIdx.y) {  // output component
+    case 0: l1_elem<T, 0>(nx, ny, nz, Ke, Bw, Ef, eflag, v, Y); break;
+    case 1: l1_elem<T, 1>(nx, ny, nz, Ke, Bw, Ef, eflag, v, Y); break;
+    default: l1_elem<T, 2>(nx, ny, nz, Ke, Bw, Ef, eflag, v, Y); break;
+  }
+}
+
+// Pass 2: y[c][n] = sum over the (up to 8) elements around node n, taken in
+// corner order a = 0..7, of Y[3a + c][e(n, a)].
+template <typename T>
+__global__ void __launch_bounds__(256) k_l1_gather(int nx, int ny, int nz,
+                                                   const T* __restrict__ Y, T* __restrict__ y) {
+  const int64_t nn = (int64_t)(nx + 1) * (ny + 1) * (nz + 1);
+  const int64_t ne = (int64_t)nx * ny * nz;
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= nn) return;
+  const int i = (int)(n % (nx + 1));
+  const int64_t rest = n / (nx + 1);
+  const int j = (int)(rest % (ny + 1)), k = (int)(rest / (ny + 1));
+  T acc[3] = {0, 0, 0};
+#pragma unroll
+  for (int a = 0; a < 8; ++a) {
+    const int ex = i - (a & 1), ey = j - ((a >> 1) & 1), ez = k - (a >> 2);
+    if (ex < 0 || ex >= nx || ey < 0 || ey >= ny || ez < 0 || ez >= nz) continue;
+    const int64_t e = (int64_t)ex + (int64_t)nx * ((int64_t)ey + (int64_t)ny * ez);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) acc[c] += Y[(int64_t)(3 * a + c) * ne + e];
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) y[c * nn + n] = acc[c];
 }
 
 __global__ void k_diag_elemmat(int nx, int ny, int nz, const double* __restrict__ Ke,
@@ -727,45 +867,52 @@ __global__ void __launch_bounds__(256) k_gemv(int n, const double* __restrict__ 
 
 void launch_galerkin_from_fine(const Grid& coarse, const double* KE, const double* Mc,
                                const double* E, const uint8_t* mask, uint8_t* eflag, int* list,
-                               int* count, double* Kc, hipStream_t s) {
+                               int* count, double* Kc, double* Kcomp, int cap, hipStream_t s) {
   k_galerkin_fast<<<nblk(coarse.ne, 64), 256, 0, s>>>(coarse.nx, coarse.ny, coarse.nz, Mc, E, Kc);
   k_zero_int<<<1, 1, 0, s>>>(count);
   k_parent_flags<<<nblk(coarse.ne, 256), 256, 0, s>>>(coarse.nx, coarse.ny, coarse.nz, mask, eflag,
                                                        list, count);
   const unsigned grid = (unsigned)std::min<int64_t>(coarse.ne, 2048);
   k_galerkin_lds<true><<<grid, 256, 0, s>>>(coarse.nx, coarse.ny, coarse.nz, KE, E, mask, list,
-                                            count, nullptr, Kc);
+                                            count, nullptr, Kc, Kcomp, cap);
 }
 
 void launch_galerkin_from_coarse(const Grid& coarse, const double* Kf, double* Kc, hipStream_t s) {
   const unsigned grid = (unsigned)std::min<int64_t>(coarse.ne, 4096);
   k_galerkin_lds<false><<<grid, 256, 0, s>>>(coarse.nx, coarse.ny, coarse.nz, nullptr, nullptr,
-                                             nullptr, nullptr, nullptr, Kf, Kc);
+                                             nullptr, nullptr, nullptr, Kf, Kc, nullptr, 0);
 }
 
 void launch_apply_elemmat(const Grid& g, const double* Ke, const double* v, double* y,
                           hipStream_t s) {
-  k_apply_elemmat<false, double><<<nblk(g.nn, 64), 512, 0, s>>>(g.nx, g.ny, g.nz, Ke, nullptr,
-                                                                nullptr, nullptr, v, y);
-}
-
-void launch_apply_elemmat_mf(const Grid& g, const double* Ke, const double* Mf, const double* Ef,
-                             const uint8_t* eflag, const double* v, double* y, hipStream_t s) {
-  k_apply_elemmat<true, double><<<nblk(g.nn, 64), 512, 0, s>>>(g.nx, g.ny, g.nz, Ke, Mf, Ef, eflag,
-                                                               v, y);
+  k_apply_elemmat<double><<<nblk(g.nn, 64), 512, 0, s>>>(g.nx, g.ny, g.nz, Ke, v, y);
 }
 
 void launch_apply_elemmat_f32(const Grid& g, const double* Ke, const float* v, float* y,
                               hipStream_t s) {
-  k_apply_elemmat<false, float><<<nblk(g.nn, 64), 512, 0, s>>>(g.nx, g.ny, g.nz, Ke, nullptr,
-                                                               nullptr, nullptr, v, y);
+  k_apply_elemmat<float><<<nblk(g.nn, 64), 512, 0, s>>>(g.nx, g.ny, g.nz, Ke, v, y);
 }
 
-void launch_apply_elemmat_mf_f32(const Grid& g, const double* Ke, const float* Mf,
-                                 const float* Ef, const uint8_t* eflag, const float* v, float* y,
-                                 hipStream_t s) {
-  k_apply_elemmat<true, float><<<nblk(g.nn, 64), 512, 0, s>>>(g.nx, g.ny, g.nz, Ke, Mf, Ef, eflag,
-                                                              v, y);
+template <typename T>
+void l1_apply(const Grid& g, const double* Ke, const double* Kcomp, int cap, const T* Bw,
+              const T* Ef, const uint8_t* eflag, const int* list, const int* count, const T* v,
+              T* Y, T* y, hipStream_t s) {
+  k_l1_elem<T><<<dim3(nblk(g.ne, 256), 3), 256, 0, s>>>(g.nx, g.ny, g.nz, Ke, Bw, Ef, eflag, v, Y);
+  const unsigned mb = (unsigned)std::min<int64_t>(nblk(g.ne, 64), 256);
+  k_l1_masked<T><<<dim3(mb, 6), 256, 0, s>>>(g.nx, g.ny, g.nz, Ke, Kcomp, cap, list, count, v, Y);
+  k_l1_gather<T><<<nblk(g.nn, 256), 256, 0, s>>>(g.nx, g.ny, g.nz, Y, y);
+}
+
+void launch_apply_l1(const Grid& g, const double* Ke, const double* Kcomp, int cap,
+                     const double* Bw, const double* Ef, const uint8_t* eflag, const int* list,
+                     const int* count, const double* v, double* Y, double* y, hipStream_t s) {
+  l1_apply<double>(g, Ke, Kcomp, cap, Bw, Ef, eflag, list, count, v, Y, y, s);
+}
+
+void launch_apply_l1_f32(const Grid& g, const double* Ke, const double* Kcomp, int cap,
+                         const float* Bw, const float* Ef, const uint8_t* eflag, const int* list,
+                         const int* count, const float* v, float* Y, float* y, hipStream_t s) {
+  l1_apply<float>(g, Ke, Kcomp, cap, Bw, Ef, eflag, list, count, v, Y, y, s);
 }
 
 void launch_restrict_f32(const Grid& coarse, const float* bf, const float* tf,

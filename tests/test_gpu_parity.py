@@ -266,3 +266,41 @@ def test_oc_update_matches_oracle():
     m.oc_update(t64(x), t64(dc), t64(dv), 0.3, 0.2, gx, gp)
     assert rel(gx.cpu().numpy(), xn) < 1e-9
     assert rel(gp.cpu().numpy(), xp) < 1e-9
+
+
+def test_level1_many_fixed_parents_strided_path():
+    """Three fully fixed faces on a 64x32x32 grid flag more level-1 parents
+    than the compact copy holds (1024), so the level-1 product reads the
+    flagged parents' matrices in place; level 1 and the V-cycle against the
+    oracle's sparse Galerkin hierarchy."""
+    nx, ny, nz, lev = 64, 32, 32, 3
+    base = synth.cantilever(nx, ny, nz)
+    fixed = set()
+    for i in range(nx + 1):
+        for j in range(ny + 1):
+            for c in range(3):
+                fixed.add((i, j, 0, c))
+    for j in range(ny + 1):
+        for k in range(nz + 1):
+            for c in range(3):
+                fixed.add((0, j, k, c))
+    for i in range(nx + 1):
+        for k in range(nz + 1):
+            fixed.add((i, 0, k, 1))
+    prob = synth.problems.Problem(nx, ny, nz, sorted(fixed), base.loads, "three faces")
+    rho = _density(prob, 31)
+    m = mesh_for(prob, mg_levels=lev)
+    m.setup(t64(rho), fixed_tensor(prob, m))
+    K = fem.assemble(nx, ny, nz, fem.simp(rho), fem.hex8_ke())
+    H = mg.Hierarchy(K, fem.fixed_dofs_aos(prob), (nx, ny, nz), lev)
+    rng = np.random.default_rng(32)
+    nn1 = (nx // 2 + 1) * (ny // 2 + 1) * (nz // 2 + 1)
+    v = rng.standard_normal(3 * nn1)
+    y = torch.zeros(3 * nn1, dtype=torch.float64, device="cuda")
+    m.apply(t64(v), y, level=1)
+    assert rel(y.cpu().numpy(), soa(H.A[1] @ aos(v))) < 1e-12
+    free = fem.free_mask(K.shape[0], fem.fixed_dofs_aos(prob))
+    r = rng.standard_normal(K.shape[0]) * free
+    z = torch.zeros(K.shape[0], dtype=torch.float64, device="cuda")
+    m.vcycle(t64(soa(r)), z)
+    assert rel(z.cpu().numpy(), soa(H.vcycle(r, omega=0.6, nu1=1, nu2=1))) < 1e-9
