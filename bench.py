@@ -125,6 +125,28 @@ def kv_event_timing(torch, aarmr, n_launch, sets):
     return e0.elapsed_time(e1) / n_launch  # ms per launch
 
 
+def pmc_traffic(grid):
+    """HBM bytes per launch of the fine-grid K.v kernel on `grid` ("AxBxC")
+    from the committed FETCH_SIZE / WRITE_SIZE counter summary (calibrated by
+    a 1 GiB copy), or None when the kernel source has changed since the
+    counters were taken or no summary exists."""
+    import hashlib
+    import re
+
+    path = os.path.join(ROOT, "profiles", "ebe_kv_pmc_traffic.txt")
+    src = os.path.join(ROOT, "paper_2205_00385_amd", "csrc", "kernels_ebe.hip")
+    try:
+        text = open(path).read()
+        h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    except OSError:
+        return None
+    m = re.search(r"sha256\[:16\]=([0-9a-f]{16})", text)
+    if not m or m.group(1) != h:
+        return None
+    m = re.search(r"kv grid=%s .*traffic_bytes=(\d+)" % re.escape(grid), text)
+    return int(m.group(1)) if m else None
+
+
 def ebe_bytes(nx, ny, nz):
     """Algorithmic HBM bytes of one FP64 K.v sweep: read v and write y
     (3 x 8 B per node each), the node's fixed-DOF mask byte, and one
@@ -156,7 +178,7 @@ def large_kv(torch, aarmr, synth, n_launch):
     bb, nnb = ebe_bytes(*L)
     gb = bb / (ms_big * 1e-3) / 1e9
     return {"bound": "hbm", "achieved": round(gb, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(gb / HBM_PEAK_GBS, 4), "traffic": None,
+            "frac": round(gb / HBM_PEAK_GBS, 4), "traffic": pmc_traffic("256x128x128"),
             "ms_per_launch": round(ms_big, 5), "bytes_per_launch": bb,
             "gdof_s": round(3 * nnb / (ms_big * 1e-3) / 1e9, 2),
             "note": "two independent meshes (v, y, E, mask) alternate so the working set "
@@ -260,14 +282,23 @@ def main():
         sys.exit(2)
     torch.cuda.set_device(0)
     if args.kv_only:
-        # a plain copy of known size (256 MiB read + 256 MiB written) first, to
-        # calibrate the FETCH_SIZE / WRITE_SIZE counters of a counter run
-        a = torch.ones(2 ** 25, dtype=torch.float64, device="cuda")
+        # a plain copy of known size (1 GiB read + 1 GiB written, four times the
+        # Infinity Cache) first, to calibrate the FETCH_SIZE / WRITE_SIZE
+        # counters of a counter run
+        a = torch.ones(2 ** 27, dtype=torch.float64, device="cuda")
         b = torch.empty_like(a)
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
-        print(json.dumps({"roofline_kv_256x128x128": large_kv(torch, aarmr, synth, args.kv_launches)}))
+        mesh, fixed, _, _ = make_loop_state(torch, aarmr, synth)
+        mesh.setup(torch.full((NX * NY * NZ,), VOLFRAC, dtype=torch.float64, device="cuda"), fixed)
+        n3 = 3 * mesh.n_node
+        vr = torch.randn(n3, dtype=torch.float64, device="cuda")
+        vr[fixed] = 0.0
+        ms_loop = kv_event_timing(torch, aarmr, args.kv_launches,
+                                  [(mesh, vr, torch.empty_like(vr))])
+        print(json.dumps({"kv_96x48x48_ms": ms_loop,
+                          "roofline_kv_256x128x128": large_kv(torch, aarmr, synth, args.kv_launches)}))
         return
     if args.precision_only:
         print(json.dumps({"precision_form_256x128x128": precision_form(torch, aarmr, synth)}))
@@ -306,7 +337,7 @@ def main():
     bytes_kv, nn = ebe_bytes(NX, NY, NZ)
     gbs = bytes_kv / (ms_kv * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": pmc_traffic(f"{NX}x{NY}x{NZ}"),
                 "kernel": "k_ebe (fine-grid K.v, FP64)", "grid": f"{NX}x{NY}x{NZ}",
                 "ms_per_launch": round(ms_kv, 5), "bytes_per_launch": bytes_kv,
                 "gdof_s": round(3 * nn / (ms_kv * 1e-3) / 1e9, 2)}
