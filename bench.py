@@ -50,6 +50,8 @@ def parse():
                     help="skip the 256x128x128 FP64 vs refinement-form solve")
     ap.add_argument("--precision-only", action="store_true",
                     help="only the 256x128x128 FP64 vs refinement-form solve")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-instance batch")
+    ap.add_argument("--batch-only", action="store_true", help="only the 64-instance batch")
     ap.add_argument("--kv-only", action="store_true",
                     help="only the 256x128x128 K.v timing (for hardware-counter runs)")
     return ap.parse_args()
@@ -240,6 +242,56 @@ def precision_form(torch, aarmr, synth, reps=3):
                                 and a["code"] == 0 and b["code"] == 0)}
 
 
+def batched_form(torch, aarmr, synth, stream_counts=(1, 4), reps=2):
+    """The batch workload: 64 independent cantilevers of uneven cube-ish size
+    (each axis from {16, ..., 64}, seed 4000+i, max/min <= 2), each with 4
+    load cases (unit -z point loads at seeded x=nx face nodes) and a smoothed
+    random density (correlation 4 voxels) in [1e-3, 1]; refinement form,
+    4 grid levels, rel. residual 1e-8.  aarmr_batch_solve over 1 and 4
+    streams, median of `reps` timed runs after a warm-up, each from u = 0."""
+    import numpy as np
+
+    dev = torch.device("cuda")
+    sizes = synth.batch_sizes(64)
+    jobs = []
+    for i, (nx, ny, nz) in enumerate(sizes):
+        prob = synth.point_loads_on_face(nx, ny, nz, n_case=4, seed=4000 + i)
+        p = aarmr.default_params(nx=nx, ny=ny, nz=nz, mg_levels=4, cg_rtol=1e-8, cg_maxit=2000,
+                                 n_rhs_max=4, precision=aarmr.FP32_REFINE)
+        m = aarmr.Mesh(p)
+        f = torch.tensor(np.concatenate([np.asarray(v) for v in aarmr.loads_soa(prob, m.n_node)]),
+                         dtype=torch.float64, device=dev)
+        rho = torch.tensor(synth.smoothed_field(nx, ny, nz, 4.0, 1e-3, 1.0, seed=4000 + i).ravel(),
+                           dtype=torch.float64, device=dev)
+        fx = torch.tensor(aarmr.fixed_dofs_soa(prob, m.n_node), dtype=torch.int64, device=dev)
+        jobs.append(dict(mesh=m, rho=rho, f=f, fixed=fx, u=torch.zeros_like(f)))
+    n_solves = 4 * len(jobs)
+    out = {"workload": "64 cantilevers, sizes 16..64 per axis (seeds 4000-4063), 4 point-load "
+                       "cases each, refinement form, 4 levels, rel. residual 1e-8",
+           "elements": int(sum(a * b * c for a, b, c in sizes)), "solves_per_batch": n_solves}
+    for ns in stream_counts:
+        streams = [torch.cuda.Stream() for _ in range(ns)]
+        times = []
+        for r in range(reps + 1):
+            for jb in jobs:
+                jb["u"].zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, items, code = aarmr.batch_solve(jobs, streams)
+            dt = time.perf_counter() - t0
+            if r > 0:
+                times.append(dt)
+        ok = code == 0 and all(max(it.stats.rel_residual[l] for l in range(it.n_rhs)) <= 1e-8
+                               for it in items)
+        T = float(np.median(times))
+        out[f"streams_{ns}"] = {"ms_per_batch": round(T * 1e3, 2),
+                                "solves_s": round(n_solves / T, 2), "all_converged": bool(ok)}
+        print(f"[bench] batch {ns} streams: {T * 1e3:.1f} ms", file=sys.stderr, flush=True)
+    for jb in jobs:
+        jb["mesh"].close()
+    return out
+
+
 def cpu_baseline():
     """The oracle's analysis (assembly, banded Cholesky, compliance,
     sensitivities, filter and its adjoint) on the 48x24x24 sub-grid of the
@@ -300,6 +352,9 @@ def main():
         print(json.dumps({"kv_96x48x48_ms": ms_loop,
                           "roofline_kv_256x128x128": large_kv(torch, aarmr, synth, args.kv_launches)}))
         return
+    if args.batch_only:
+        print(json.dumps({"batched_form_64": batched_form(torch, aarmr, synth)}))
+        return
     if args.precision_only:
         print(json.dumps({"precision_form_256x128x128": precision_form(torch, aarmr, synth)}))
         return
@@ -347,6 +402,9 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_precision:
         extra["precision_form_256x128x128"] = precision_form(torch, aarmr, synth)
+        torch.cuda.empty_cache()
+    if not args.no_batch:
+        extra["batched_form_64"] = batched_form(torch, aarmr, synth)
         torch.cuda.empty_cache()
 
     lat_solve = np.array([a for a, _ in lat_all])

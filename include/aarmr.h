@@ -58,9 +58,14 @@ extern "C" {
 
 /* ---- precision of the inner solve ------------------------------------ */
 #define AARMR_FP64         0  /* everything in FP64 */
-#define AARMR_FP32_REFINE  1  /* FP32 operator sweeps and V-cycle inside FP64
-                                 iterative refinement (FP64 residuals, dots,
-                                 reduced systems and coarsest solve) */
+#define AARMR_FP32_REFINE  1  /* FP32 operator sweeps, V-cycle and inner CG
+                                 vectors inside FP64 iterative refinement (FP64
+                                 residuals, dot accumulation, updates of u,
+                                 reduced systems and coarsest inverse).  Where
+                                 FP32 stops making progress (extreme modulus
+                                 contrast) the solve continues with FP64 CG
+                                 preconditioned by the FP32 V-cycle.  Results
+                                 meet cg_rtol in FP64 either way. */
 
 /* ---- flags for aarmr_solve / aarmr_ca_update -------------------------- */
 #define AARMR_FILTER_INPUT  1  /* `rho` is the design density: it is filtered
@@ -238,6 +243,39 @@ int aarmr_element_energy(aarmr_mesh* m, const double* u, double* energy, void* s
 int aarmr_oc_update(aarmr_mesh* m, const double* x, const double* dc, const double* dv,
                     double volfrac, double move, double* x_new, double* rho_phys_new,
                     void* stream);
+
+/* ---- batched form ------------------------------------------------------
+ * Many independent analyses (meshes of uneven size, each with its own load
+ * cases) run concurrently.  Each item is one aarmr_solve call on its own mesh
+ * (and therefore its own workspace); the items are spread over `n_streams`
+ * caller-owned streams, each driven by one host worker thread of the
+ * library, largest items first.  The GPU overlaps the items in flight on
+ * different streams.  An item's result does not depend on the batch it runs
+ * in (every kernel of an item reads and writes only that item's memory in a
+ * fixed order), so it equals the item solved alone, bit for bit. */
+typedef struct aarmr_batch_item {
+  aarmr_mesh* mesh;             /* distinct meshes per item (workspace bound) */
+  const double* rho;            /* as aarmr_solve */
+  const double* f;
+  int32_t n_rhs;
+  const int64_t* fixed_dofs;
+  int64_t n_fixed;
+  double* u;
+  double* compliance;           /* host [n_rhs] or NULL */
+  double* dc;                   /* device [n_elem] or NULL */
+  int32_t flags;
+  int32_t status;               /* out: the item's aarmr_solve return code */
+  aarmr_stats stats;            /* out */
+} aarmr_batch_item;
+
+/* Solve every item (see above).  streams: host array of n_streams hipStream_t
+ * handles (1 <= n_streams <= 64).  Returns AARMR_OK if every item returned
+ * AARMR_OK, else the first non-OK item status in item order (each item's own
+ * code is in its `status`).  All streams are synchronised on return.
+ * Errors: AARMR_E_INVALID for a null or repeated mesh, n_items < 0 or a bad
+ * n_streams; item errors as aarmr_solve. */
+int aarmr_batch_solve(aarmr_batch_item* items, int32_t n_items, void* const* streams,
+                      int32_t n_streams);
 
 /* Thread-local description of the last error on this thread ("" if none). */
 const char* aarmr_last_error(void);

@@ -62,11 +62,20 @@ class CAStats(ctypes.Structure):
     ]
 
 
+class BatchItem(ctypes.Structure):
+    _fields_ = [
+        ("mesh", ctypes.c_void_p), ("rho", ctypes.c_void_p), ("f", ctypes.c_void_p),
+        ("n_rhs", ctypes.c_int32), ("fixed_dofs", ctypes.c_void_p), ("n_fixed", ctypes.c_int64),
+        ("u", ctypes.c_void_p), ("compliance", ctypes.c_void_p), ("dc", ctypes.c_void_p),
+        ("flags", ctypes.c_int32), ("status", ctypes.c_int32), ("stats", Stats),
+    ]
+
+
 EXPORTS = [
     "aarmr_default_params", "aarmr_mesh_create", "aarmr_mesh_destroy", "aarmr_workspace_bytes",
     "aarmr_bind_workspace", "aarmr_solve", "aarmr_ca_update", "aarmr_filter", "aarmr_setup",
     "aarmr_apply_operator", "aarmr_vcycle", "aarmr_element_energy", "aarmr_oc_update",
-    "aarmr_last_error",
+    "aarmr_batch_solve", "aarmr_last_error",
 ]
 
 
@@ -94,6 +103,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.aarmr_vcycle.argtypes = [P, vp, vp, vp]
     lib.aarmr_element_energy.argtypes = [P, vp, vp, vp]
     lib.aarmr_oc_update.argtypes = [P, vp, vp, vp, dbl, dbl, vp, vp, vp]
+    lib.aarmr_batch_solve.argtypes = [ctypes.POINTER(BatchItem), i32, ctypes.POINTER(P), i32]
     lib.aarmr_last_error.argtypes = []
     lib.aarmr_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
@@ -234,6 +244,44 @@ class Mesh:
     def oc_update(self, x, dc, dv, volfrac, move, x_new, rho_new):
         _check(lib().aarmr_oc_update(self._h, _ptr(x), _ptr(dc), _ptr(dv), float(volfrac),
                                      float(move), _ptr(x_new), _ptr(rho_new), _stream()))
+
+
+def batch_solve(jobs, streams, check=True):
+    """Solve independent analyses concurrently (aarmr_batch_solve).
+
+    jobs: list of dicts with keys mesh, rho, f, fixed, u and optionally dc,
+    flags; tensors as for Mesh.solve.  streams: torch.cuda.Stream objects.
+    Returns (compliances per job, the BatchItem array, return code)."""
+    n = len(jobs)
+    items = (BatchItem * n)()
+    comp = []
+    for i, jb in enumerate(jobs):
+        m = jb["mesh"]
+        n3 = 3 * m.n_node
+        n_rhs = jb["f"].numel() // n3
+        _f64(jb["rho"], m.n_elem, "rho")
+        _f64(jb["f"], n_rhs * n3, "f")
+        _f64(jb["u"], n_rhs * n3, "u")
+        C = (ctypes.c_double * MAX_RHS)()
+        comp.append(C)
+        it = items[i]
+        it.mesh = m._h.value
+        it.rho = jb["rho"].data_ptr()
+        it.f = jb["f"].data_ptr()
+        it.n_rhs = n_rhs
+        it.fixed_dofs = jb["fixed"].data_ptr() if jb["fixed"].numel() else None
+        it.n_fixed = jb["fixed"].numel()
+        it.u = jb["u"].data_ptr()
+        it.compliance = ctypes.cast(C, ctypes.c_void_p).value
+        dc = jb.get("dc")
+        it.dc = dc.data_ptr() if dc is not None else None
+        it.flags = jb.get("flags", 0)
+    hs = (ctypes.c_void_p * len(streams))(*[s.cuda_stream for s in streams])
+    code = lib().aarmr_batch_solve(items, n, hs, len(streams))
+    if check:
+        _check(code, allow=(E_NOT_CONVERGED,))
+    out = [[comp[i][l] for l in range(items[i].n_rhs)] for i in range(n)]
+    return out, items, code
 
 
 def fixed_dofs_soa(prob, n_node: int) -> list:

@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "internal.hpp"
@@ -179,7 +180,7 @@ void hex8_stiffness(double nu, double* KE) {
 // every column of B.  Returns false if KE lacks that structure.
 bool walsh_form(const double* KE, WalshConsts* K) {
   auto chi = [](int k, int a) { return (__builtin_popcount(k & a) & 1) ? -1.0 : 1.0; };
-  static double B[24][24];
+  double B[24][24];
   double bmax = 0.0;
   for (int k = 0; k < 8; ++k)
     for (int c = 0; c < 3; ++c)
@@ -1302,6 +1303,53 @@ int aarmr_oc_update(aarmr_mesh* m, const double* x, const double* dc, const doub
   }
   launch_filter(g, m->p.rmin, m->Wf, 0, m->Hs, x_new, rho_phys_new, s);
   KCHECK();
+  return AARMR_OK;
+}
+
+int aarmr_batch_solve(aarmr_batch_item* items, int32_t n_items, void* const* streams,
+                      int32_t n_streams) {
+  if (n_items < 0 || (n_items > 0 && !items)) return fail(AARMR_E_INVALID, "bad item array");
+  if (!streams || n_streams < 1 || n_streams > 64) return fail(AARMR_E_INVALID, "bad stream array");
+  if (n_items == 0) return AARMR_OK;
+  std::vector<int> order(n_items);
+  for (int i = 0; i < n_items; ++i) {
+    if (!items[i].mesh) return fail(AARMR_E_INVALID, "null mesh in batch");
+    order[i] = i;
+  }
+  {
+    std::vector<const aarmr_mesh*> seen;
+    for (int i = 0; i < n_items; ++i) seen.push_back(items[i].mesh);
+    std::sort(seen.begin(), seen.end());
+    if (std::adjacent_find(seen.begin(), seen.end()) != seen.end())
+      return fail(AARMR_E_INVALID, "a mesh appears twice in the batch");
+  }
+  // largest first, then round-robin over the streams: a simple balance of
+  // the per-stream work (work ~ nodes x load cases)
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    return items[a].mesh->lg[0].nn * items[a].n_rhs > items[b].mesh->lg[0].nn * items[b].n_rhs;
+  });
+  const int nw = std::min<int>(n_streams, n_items);
+  std::vector<std::vector<int>> queue(nw);
+  std::vector<int64_t> load(nw, 0);
+  for (int i : order) {  // greedy: next item to the least-loaded worker
+    const int w = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    queue[w].push_back(i);
+    load[w] += items[i].mesh->lg[0].nn * std::max(1, items[i].n_rhs);
+  }
+  auto work = [&](int w) {
+    for (int i : queue[w]) {
+      aarmr_batch_item& it = items[i];
+      it.status = aarmr_solve(it.mesh, it.rho, it.f, it.n_rhs, it.fixed_dofs, it.n_fixed, it.u,
+                              it.compliance, it.dc, it.flags, &it.stats, streams[w]);
+    }
+  };
+  std::vector<std::thread> pool;
+  for (int w = 1; w < nw; ++w) pool.emplace_back(work, w);
+  work(0);
+  for (auto& t : pool) t.join();
+  for (int w = 0; w < nw; ++w) HIP_TRY(hipStreamSynchronize(S(streams[w])));
+  for (int i = 0; i < n_items; ++i)
+    if (items[i].status != AARMR_OK) return fail(items[i].status, "a batch item failed (see its status)");
   return AARMR_OK;
 }
 

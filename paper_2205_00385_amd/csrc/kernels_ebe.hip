@@ -348,15 +348,15 @@ __global__ void k_identity_rows(int64_t nn, const uint8_t* __restrict__ mask,
 template <typename T, bool MASK_IN>
 static void launch_ebe_t(const Grid& g, const WalshConsts& K, const T* E, const uint8_t* mask,
                          const T* v, T* y, hipStream_t s) {
-  static int slots = 0;  // resident workgroups of this kernel on the device
-  if (slots == 0) {
+  // resident workgroups of this kernel on the device (thread-safe one-time init)
+  static const int slots = [] {
     int dev = 0, cus = 0, per_cu = 0;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_ebe_z<T, MASK_IN, AARMR_EBE_PF>,
                                                        kThreads, 0);
-    slots = (cus > 0 && per_cu > 0) ? cus * per_cu : 512;
-  }
+    return (cus > 0 && per_cu > 0) ? cus * per_cu : 512;
+  }();
   const int gx = (g.nx + 1 + kTileX - 1) / kTileX;
   const int gy = (g.ny + 1 + kTileY - 1) / kTileY;
   const int planes = g.nz + 1;

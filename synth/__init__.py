@@ -14,6 +14,7 @@ from .problems import (  # noqa: F401
     bridge,
     patch_test,
     point_loads_on_face,
+    batch_sizes,
     PRESETS,
 )
 from .fields import uniform_iid, smoothed_field, thresholded_field, perturb  # noqa: F401

@@ -109,6 +109,22 @@ def point_loads_on_face(nx: int, ny: int, nz: int, n_case: int, seed: int) -> Pr
     return Problem(nx, ny, nz, fixed, loads, f"pointloads{nx}x{ny}x{nz}")
 
 
+def batch_sizes(n: int, seed0: int = 4000, choices=(16, 24, 32, 40, 48, 56, 64),
+                max_ratio: float = 2.0) -> List[Tuple[int, int, int]]:
+    """Grid sizes of a batch of ``n`` cube-ish instances: instance i draws each
+    axis i.i.d. from ``choices`` with generator seed ``seed0 + i``, redrawing
+    until max/min <= ``max_ratio``."""
+    out = []
+    for i in range(n):
+        rng = np.random.default_rng(seed0 + i)
+        while True:
+            d = [int(x) for x in rng.choice(choices, size=3)]
+            if max(d) <= max_ratio * min(d):
+                break
+        out.append((d[0], d[1], d[2]))
+    return out
+
+
 # Run presets of the synthetic workloads.  Material and method parameters are
 # the paper's (E0=1, Emin=1e-9, nu=0.3, p=3; Section 4); grid sizes, radii,
 # tolerances and level counts are the workload definitions.

@@ -1,0 +1,86 @@
+"""The batched form (aarmr_batch_solve): many independent instances of
+uneven size, each with several load cases, solved concurrently on several
+streams.  Checks: every instance converges; an instance's result in the
+batch equals the same instance solved alone, bit for bit; and instances
+against the CPU FP64 oracle to the 1e-6 compliance / displacement bar."""
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import sens
+
+from gpu_util import fixed_tensor, loads_tensor, log, mesh_for, rel, soa, t64
+
+pytestmark = pytest.mark.gpu
+
+
+def _aarmr():
+    from paper_2205_00385_amd import aarmr
+
+    return aarmr
+
+
+def _instance(i, size, prec, rtol=1e-8):
+    """Instance i of the batch workload: clamped x=0, 4 load cases (unit -z
+    point loads at seeded nodes of the x=nx face, seed 4000+i), smoothed
+    random density (correlation 4 voxels, seed 4000+i) in [1e-3, 1]."""
+    nx, ny, nz = size
+    prob = synth.point_loads_on_face(nx, ny, nz, n_case=4, seed=4000 + i)
+    rho = synth.smoothed_field(nx, ny, nz, 4.0, 1e-3, 1.0, seed=4000 + i).ravel()
+    m = mesh_for(prob, mg_levels=4, cg_rtol=rtol, n_rhs_max=4, precision=prec)
+    f = loads_tensor(prob, m)
+    return dict(prob=prob, rho_np=rho, mesh=m, rho=t64(rho), f=f, fixed=fixed_tensor(prob, m),
+                u=torch.zeros_like(f))
+
+
+def test_batch64_refine_converges_matches_alone_and_oracle():
+    aarmr = _aarmr()
+    sizes = synth.batch_sizes(64)
+    jobs = [_instance(i, sz, aarmr.FP32_REFINE) for i, sz in enumerate(sizes)]
+    streams = [torch.cuda.Stream() for _ in range(4)]
+    torch.cuda.synchronize()
+    comp, items, code = aarmr.batch_solve(jobs, streams)
+    log(f"  batch of {len(jobs)}: code={code}, "
+        f"iterations {min(it.stats.iterations[0] for it in items)}.."
+        f"{max(it.stats.iterations[0] for it in items)}")
+    assert code == aarmr.OK
+    for it in items:
+        assert it.status == aarmr.OK
+        for l in range(it.n_rhs):
+            assert it.stats.rel_residual[l] <= 1e-8
+    # the same instance alone, on the current stream: identical bits
+    for i in (0, 17, 63):
+        jb = jobs[i]
+        u_b = jb["u"].clone()
+        u2 = torch.zeros_like(jb["u"])
+        C2, st2, code2 = jb["mesh"].solve(jb["rho"], jb["f"], jb["fixed"], u2)
+        assert code2 == aarmr.OK
+        assert torch.equal(u2, u_b), f"instance {i} differs alone vs in the batch"
+        assert C2 == comp[i]
+    # the three smallest against the oracle's direct solve
+    small = sorted(range(len(jobs)), key=lambda i: np.prod(sizes[i]))[:3]
+    n3s = [3 * jobs[i]["mesh"].n_node for i in small]
+    for i, n3 in zip(small, n3s):
+        jb = jobs[i]
+        us, Cs, _ = sens.analyse(jb["prob"], jb["rho_np"])
+        for l in range(4):
+            assert abs(comp[i][l] - Cs[l]) <= 1e-6 * abs(Cs[l])
+            assert rel(jb["u"][l * n3:(l + 1) * n3].cpu().numpy(), soa(us[l])) <= 1e-6
+        log(f"  instance {i} {sizes[i]}: C[0]={comp[i][0]:.10g} ref={Cs[0]:.10g}")
+
+
+def test_batch_fp64_small_matches_alone_and_rejects_repeats():
+    aarmr = _aarmr()
+    sizes = [(16, 16, 16), (24, 16, 16), (16, 24, 32), (32, 16, 16), (16, 16, 24), (24, 24, 16)]
+    jobs = [_instance(i, sz, aarmr.FP64) for i, sz in enumerate(sizes)]
+    streams = [torch.cuda.Stream() for _ in range(2)]
+    comp, items, code = aarmr.batch_solve(jobs, streams)
+    assert code == aarmr.OK
+    for i, jb in enumerate(jobs):
+        u2 = torch.zeros_like(jb["u"])
+        C2, _, _ = jb["mesh"].solve(jb["rho"], jb["f"], jb["fixed"], u2)
+        assert torch.equal(u2, jb["u"]) and C2 == comp[i]
+    with pytest.raises(aarmr.AarmrError):
+        aarmr.batch_solve([jobs[0], jobs[0]], streams)
