@@ -52,6 +52,8 @@ def parse():
                     help="only the 256x128x128 FP64 vs refinement-form solve")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-instance batch")
     ap.add_argument("--batch-only", action="store_true", help="only the 64-instance batch")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving workload")
+    ap.add_argument("--serve-only", action="store_true", help="only the serving workload")
     ap.add_argument("--kv-only", action="store_true",
                     help="only the 256x128x128 K.v timing (for hardware-counter runs)")
     return ap.parse_args()
@@ -292,6 +294,53 @@ def batched_form(torch, aarmr, synth, stream_counts=(1, 4), reps=2):
     return out
 
 
+def served_form(torch, aarmr, synth, n_requests=40):
+    """The serving workload: a Poisson stream (seed 5) of analysis requests on
+    grids drawn from {32^3, 48^3, 64^3, 96x48x48, 128^3}, 1-8 load cases each,
+    half of them repeats of an earlier design perturbed by w <= 5% (eq. 30).
+    Served form: 4 workers, refinement form, resident families with the CA
+    reanalysis, HBM budget 80% of free memory.  Plain: one request at a time,
+    FP64, same residency and CA.  First both at saturation (every request at
+    t = 0), then the served form at 0.5x, 0.8x and 1.0x of its saturation
+    rate with real-time arrivals.  Every served compliance is compared with
+    the plain FP64 result of the same request."""
+    from paper_2205_00385_amd import serve
+
+    free, _ = torch.cuda.mem_get_info()
+    budget = int(0.8 * free)
+    trace = synth.serve_trace(n_requests, 0.0, seed=5)
+
+    def one(workers, prec, reqs, realtime):
+        srv = serve.AnalysisServer(budget, n_workers=workers, precision=prec)
+        res = srv.run(reqs, realtime=realtime)
+        ev = srv.evictions
+        srv.close()
+        torch.cuda.empty_cache()
+        return res, ev
+
+    plain, _ = one(1, aarmr.FP64, trace, False)
+    sat, ev = one(4, aarmr.FP32_REFINE, trace, False)
+    worst = max(abs(a - b) / abs(b) for ra, rb in zip(sat, plain)
+                for a, b in zip(ra.compliance, rb.compliance))
+    ok = sum(all(abs(a - b) <= 1e-6 * abs(b) for a, b in zip(ra.compliance, rb.compliance))
+             for ra, rb in zip(sat, plain))
+    out = {"workload": f"{n_requests} requests (seed 5), grids 32^3/48^3/64^3/96x48x48/128^3, "
+                       "1-8 load cases, 50% perturbed repeats (w <= 5%)",
+           "plain_fp64_one_at_a_time": serve.summarize(plain),
+           "served_saturation": dict(serve.summarize(sat), evictions=ev),
+           "compliance_max_rel_diff_vs_plain": worst,
+           "requests_within_1e-6": f"{ok}/{len(sat)}"}
+    print(f"[bench] serve saturation: {out['served_saturation']}", file=sys.stderr, flush=True)
+    sat_qps = out["served_saturation"]["requests_s"]
+    for frac in (0.5, 0.8, 1.0):
+        tr = synth.serve_trace(n_requests, frac * sat_qps, seed=5)
+        res, ev = one(4, aarmr.FP32_REFINE, tr, True)
+        out[f"served_qps_{frac}x"] = dict(serve.summarize(res), qps=round(frac * sat_qps, 3),
+                                          evictions=ev)
+        print(f"[bench] serve {frac}x: {out[f'served_qps_{frac}x']}", file=sys.stderr, flush=True)
+    return out
+
+
 def cpu_baseline():
     """The oracle's analysis (assembly, banded Cholesky, compliance,
     sensitivities, filter and its adjoint) on the 48x24x24 sub-grid of the
@@ -352,6 +401,9 @@ def main():
         print(json.dumps({"kv_96x48x48_ms": ms_loop,
                           "roofline_kv_256x128x128": large_kv(torch, aarmr, synth, args.kv_launches)}))
         return
+    if args.serve_only:
+        print(json.dumps({"served_form": served_form(torch, aarmr, synth)}))
+        return
     if args.batch_only:
         print(json.dumps({"batched_form_64": batched_form(torch, aarmr, synth)}))
         return
@@ -405,6 +457,9 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_batch:
         extra["batched_form_64"] = batched_form(torch, aarmr, synth)
+        torch.cuda.empty_cache()
+    if not args.no_serve:
+        extra["served_form"] = served_form(torch, aarmr, synth)
         torch.cuda.empty_cache()
 
     lat_solve = np.array([a for a, _ in lat_all])

@@ -77,7 +77,9 @@ extern "C" {
                                   into that case's PARM (eqs. 27-28), dropping
                                   the oldest vector once Ns are held */
 #define AARMR_WARM_START    4  /* use the incoming u as the CG initial guess
-                                  (otherwise CG starts from zero) */
+                                  (otherwise CG starts from zero); a guess
+                                  whose residual exceeds ||f|| is replaced by
+                                  zero */
 #define AARMR_INPUT_MASKED  8  /* aarmr_apply_operator: the caller guarantees
                                   that v is zero on fixed DOFs, so the product
                                   skips masking its input (the form every

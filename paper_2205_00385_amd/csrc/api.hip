@@ -639,9 +639,8 @@ int pcg32(aarmr_mesh* m, double rtol, int maxit, int* iters, double* relres, boo
 // cg_rtol, and x += ||r|| d in FP64; repeated until the FP64 residual meets
 // cg_rtol.  *iters counts the inner iterations.  When FP32 stops making
 // progress (a non-positive p^T A p or r^T z in the inner CG, or an outer step
-// that does not halve the residual) *fallback is set and x holds the latest
-// iterate: the caller continues from it with FP64 CG and the FP32 V-cycle as
-// preconditioner.
+// that reduces the FP64 residual less than 5x) *fallback is set and x holds the latest
+// iterate: the caller continues from it with FP64 CG and the FP64 V-cycle.
 int refine(aarmr_mesh* m, double* x, int* iters, double* relres, bool* fallback,
            hipStream_t s) {
   const Grid& g = m->lg[0];
@@ -670,6 +669,13 @@ int refine(aarmr_mesh* m, double* x, int* iters, double* relres, bool* fallback,
         *relres = 0.0;
         return AARMR_OK;
       }
+      if (h[1] > ff) {  // the initial guess is worse than zero: start from zero
+        HIP_TRY(hipMemsetAsync(x, 0, n3 * sizeof(double), s));
+        HIP_TRY(hipMemcpyAsync(m->r, m->fm, n3 * sizeof(double), hipMemcpyDeviceToDevice, s));
+        HIP_TRY(hipMemcpyAsync(misc + M_RR64, misc + M_FF, sizeof(double),
+                               hipMemcpyDeviceToDevice, s));
+        h[1] = ff;
+      }
     } else {
       TRY(dot1(m, m->r, m->r, misc + M_RR64, n3, s));
       const double* src = misc + M_RR64;
@@ -682,7 +688,9 @@ int refine(aarmr_mesh* m, double* x, int* iters, double* relres, bool* fallback,
     const double inner = std::min(0.1, std::max(kInnerFloor, 0.5 * rtol / rel));
     launch_to_f32_scaled(n3, m->r, misc + M_RR64, m->r32, s);
     KCHECK();
-    if (outer > 0 && rel > 0.5 * prev_rel) {  // the FP32 step no longer pays
+    // every step targets a reduction of at least 10x; one that delivers less
+    // than 5x shows that FP32 cannot resolve this operator well enough
+    if (outer > 0 && rel > 0.2 * prev_rel) {
       *fallback = true;
       return AARMR_OK;
     }
@@ -702,12 +710,14 @@ int refine(aarmr_mesh* m, double* x, int* iters, double* relres, bool* fallback,
   return fail(AARMR_E_NOT_CONVERGED, "refinement reached cg_maxit before cg_rtol");
 }
 
-int pcg64(aarmr_mesh* m, double* x, int* iters, double* relres, int maxit_in, hipStream_t s);
+int pcg64(aarmr_mesh* m, double* x, int* iters, double* relres, int maxit_in, bool use32,
+          hipStream_t s);
 
-// z = M^-1 r: the FP64 V-cycle, or in the refinement form the FP32 V-cycle
-// on r converted to FP32 (scaled to unit norm; rr = ||r||^2 on the device).
-int precond(aarmr_mesh* m, const double* r, const double* rr, double* z, hipStream_t s) {
-  if (!m->fp32) return vcycle(m, 0, r, z, s);
+// z = M^-1 r: the FP64 V-cycle, or (use32) the FP32 V-cycle on r converted to
+// FP32 (scaled to unit norm; rr = ||r||^2 on the device).
+int precond(aarmr_mesh* m, const double* r, const double* rr, double* z, bool use32,
+            hipStream_t s) {
+  if (!use32) return vcycle(m, 0, r, z, s);
   const int64_t n3 = 3 * m->lg[0].nn;
   launch_to_f32_scaled(n3, r, rr, m->r32, s);
   KCHECK();
@@ -719,8 +729,8 @@ int precond(aarmr_mesh* m, const double* r, const double* rr, double* z, hipStre
 }
 
 // Preconditioned CG on A x = fm (fm already masked), x in/out (masked).  In
-// the refinement form the FP32 refinement runs first; if it hands over, CG
-// continues from its iterate with the FP32 V-cycle as preconditioner.
+// the refinement form the FP32 refinement runs first; if it hands over, FP64
+// CG with the FP64 V-cycle continues from its iterate.
 int pcg(aarmr_mesh* m, double* x, int* iters, double* relres, hipStream_t s) {
   int it0 = 0;
   if (m->fp32) {
@@ -731,13 +741,14 @@ int pcg(aarmr_mesh* m, double* x, int* iters, double* relres, hipStream_t s) {
       return rc;
     }
   }
-  const int rc = pcg64(m, x, iters, relres, std::min(m->p.cg_maxit, kMaxIt) - it0, s);
+  const int rc = pcg64(m, x, iters, relres, std::min(m->p.cg_maxit, kMaxIt) - it0, false, s);
   *iters += it0;
   return rc;
 }
 
 // CG with the V-cycle preconditioner (precond) for at most maxit iterations.
-int pcg64(aarmr_mesh* m, double* x, int* iters, double* relres, int maxit_in, hipStream_t s) {
+int pcg64(aarmr_mesh* m, double* x, int* iters, double* relres, int maxit_in, bool use32,
+          hipStream_t s) {
   const Grid& g = m->lg[0];
   const int64_t n3 = 3 * g.nn;
   double* sc = m->scal;
@@ -765,9 +776,15 @@ int pcg64(aarmr_mesh* m, double* x, int* iters, double* relres, int maxit_in, hi
   }
   const double tol2 = m->p.cg_rtol * m->p.cg_rtol * ff;
   double rr = h[1];
+  if (rr > ff) {  // the initial guess is worse than zero: start from zero
+    HIP_TRY(hipMemsetAsync(x, 0, n3 * sizeof(double), s));
+    HIP_TRY(hipMemcpyAsync(m->r, m->fm, n3 * sizeof(double), hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipMemcpyAsync(sc + SC_RR, misc + M_FF, sizeof(double), hipMemcpyDeviceToDevice, s));
+    rr = ff;
+  }
   *relres = std::sqrt(rr / ff);
   if (rr <= tol2) return AARMR_OK;
-  TRY(precond(m, m->r, sc + SC_RR, m->z, s));
+  TRY(precond(m, m->r, sc + SC_RR, m->z, use32, s));
   TRY(dot1(m, m->r, m->z, sc + SC_RZ, n3, s));
   HIP_TRY(hipMemcpyAsync(m->pv, m->z, n3 * sizeof(double), hipMemcpyDeviceToDevice, s));
   const int maxit = std::max(0, maxit_in);
@@ -784,7 +801,7 @@ int pcg64(aarmr_mesh* m, double* x, int* iters, double* relres, int maxit_in, hi
     *relres = std::sqrt(rr / ff);
     if (!(h[1] > 0.0)) return fail(AARMR_E_SINGULAR, "CG: p^T A p <= 0");
     if (rr <= tol2) return AARMR_OK;
-    TRY(precond(m, m->r, sc + SC_RR + it + 1, m->z, s));
+    TRY(precond(m, m->r, sc + SC_RR + it + 1, m->z, use32, s));
     TRY(dot1(m, m->r, m->z, sc + SC_RZ + it + 1, n3, s));
     launch_cg_p(n3, sc + SC_RZ + it + 1, sc + SC_RZ + it, m->z, m->pv, s);
     KCHECK();

@@ -1,0 +1,295 @@
+"""Serving form: a request loop with continuous batching on one GPU.
+
+A request asks for the analysis (displacements, compliance per load case) of
+one density field on a grid with its load cases.  Requests of the same
+*design family* (same grid, supports and loads; densities that drift, as
+between the cycles of one optimisation) share a resident mesh: its MG
+workspace, its PARM (eqs. 27-28) and its last solution stay in HBM, so a
+repeat design is reanalysed by the combined-approximation step of
+Algorithm 1 (lines 4-10, `aarmr_ca_update`): accepted when eq. (29)'s force
+residual is below ca_tol, otherwise MGCG warm-started from the reduced
+solution.  The first Ns requests of a family run MGCG and fill its PARM.
+
+Scheduling:
+- Admission by HBM budget: a new family is admitted when its exact
+  workspace (`aarmr_workspace_bytes`) fits next to the resident ones; idle
+  families are evicted least-recently-used to make room.  A request that
+  does not fit yet waits while later ones that fit go ahead.
+- Workers are host threads, each with its own HIP stream.  Every worker
+  takes the first admissible request in arrival order (its family not busy,
+  its memory admitted) as soon as it is free, so requests that arrive while
+  others are on the GPU start as slots free up, and their kernels overlap on
+  the device.  The library calls release the GIL.
+- The requests of one family run one at a time in arrival order, so each
+  result depends only on its family's request sequence, not on the other
+  requests in flight: with no eviction in between, it is bit for bit the
+  result of serving the requests alone.
+"""
+
+from __future__ import annotations
+
+import dataclasses
+import threading
+import time
+from typing import Dict, List, Optional
+
+import numpy as np
+import torch
+
+from . import aarmr
+
+
+def levels_for(grid, max_coarse_dofs: int = 2500) -> int:
+    """Fewest grid levels whose coarsest grid has at most ``max_coarse_dofs``
+    DOFs (sizes must stay divisible by 2^(levels-1))."""
+    nx, ny, nz = grid
+    for L in range(2, aarmr.MAX_LEVELS + 1):
+        f = 1 << (L - 1)
+        if nx % f or ny % f or nz % f:
+            break
+        if 3 * (nx // f + 1) * (ny // f + 1) * (nz // f + 1) <= max_coarse_dofs:
+            return L
+    L = 2
+    while L < aarmr.MAX_LEVELS and all(d % (1 << L) == 0 for d in grid):
+        L += 1
+    return L
+
+
+def family_problem(req):
+    """Supports and loads of a request's family: clamped x=0, one unit -z
+    point load per load case at a seeded node of the x=nx face."""
+    import synth
+
+    nx, ny, nz = req["grid"]
+    return synth.point_loads_on_face(nx, ny, nz, n_case=req["n_case"], seed=req["load_seed"])
+
+
+@dataclasses.dataclass
+class Result:
+    rid: int
+    family: int
+    compliance: List[float]
+    path: str                  # "mgcg", "ca" or "fallback"
+    iterations: int            # CG iterations summed over load cases
+    rel_residual: float        # largest final residual over load cases
+    arrival: float             # seconds after the start of the run
+    start: float
+    end: float
+    worker: int
+    u: Optional[np.ndarray] = None
+
+    @property
+    def latency(self) -> float:
+        return self.end - self.arrival
+
+
+class _Family:
+    def __init__(self, fid: int, nbytes: int):
+        self.fid = fid
+        self.nbytes = nbytes
+        self.mesh = None
+        self.f = None
+        self.fixed = None
+        self.u = None
+        self.records = 0
+        self.busy = False
+        self.last_used = 0.0
+
+
+class AnalysisServer:
+    """Continuous-batching analysis server (see the module docstring).
+
+    hbm_budget: bytes of workspace the resident families may hold.
+    precision: aarmr.FP64 or aarmr.FP32_REFINE for every solve."""
+
+    def __init__(self, hbm_budget: int, n_workers: int = 4, precision: int = aarmr.FP32_REFINE,
+                 ca_tol: float = 1e-4, Ns: int = 2, Nm: int = 4, cg_rtol: float = 1e-8,
+                 keep_u: bool = False):
+        self.budget = int(hbm_budget)
+        self.n_workers = n_workers
+        self.precision = precision
+        self.ca_tol, self.Ns, self.Nm, self.cg_rtol = ca_tol, Ns, Nm, cg_rtol
+        self.keep_u = keep_u
+        self.families: Dict[int, _Family] = {}
+        self.used = 0
+        self.evictions = 0
+        self._bytes_cache: Dict[tuple, int] = {}
+        self._cv = threading.Condition()
+        self._queue: List[dict] = []
+        self._closed = False
+        self._results: List[Result] = []
+        self._t0 = 0.0
+        self._error: Optional[BaseException] = None
+
+    # -- sizing ------------------------------------------------------------
+    def params(self, req):
+        nx, ny, nz = req["grid"]
+        return aarmr.default_params(nx=nx, ny=ny, nz=nz, mg_levels=levels_for(req["grid"]),
+                                    cg_rtol=self.cg_rtol, cg_maxit=2000, Ns=self.Ns, Nm=self.Nm,
+                                    ca_tol=self.ca_tol, n_rhs_max=req["n_case"],
+                                    precision=self.precision)
+
+    def workspace_bytes(self, req) -> int:
+        key = (tuple(req["grid"]), req["n_case"])
+        if key not in self._bytes_cache:
+            import ctypes
+
+            p = self.params(req)
+            h = ctypes.c_void_p()
+            aarmr._check(aarmr.lib().aarmr_mesh_create(ctypes.byref(p), ctypes.byref(h)))
+            self._bytes_cache[key] = int(aarmr.lib().aarmr_workspace_bytes(h)) + 256
+            aarmr.lib().aarmr_mesh_destroy(h)
+        return self._bytes_cache[key]
+
+    # -- scheduling (called with the condition held) -----------------------
+    def _pick(self):
+        for qi, req in enumerate(self._queue):
+            fam = self.families.get(req["family"])
+            if fam is not None:
+                if fam.busy:
+                    continue
+            else:
+                need = self.workspace_bytes(req)
+                if need > self.budget:
+                    raise RuntimeError(f"request {req['rid']} needs {need} B > budget {self.budget} B")
+                if self.used + need > self.budget:
+                    idle = sorted((f for f in self.families.values() if not f.busy),
+                                  key=lambda f: f.last_used)
+                    freeable = sum(f.nbytes for f in idle)
+                    if self.used - freeable + need > self.budget:
+                        continue  # wait for a busy family to finish
+                    for f in idle:
+                        if self.used + need <= self.budget:
+                            break
+                        self._evict(f)
+                fam = _Family(req["family"], need)
+                self.families[req["family"]] = fam
+                self.used += need
+            fam.busy = True
+            del self._queue[qi]
+            return req, fam
+        return None
+
+    def _evict(self, fam: _Family):
+        del self.families[fam.fid]
+        self.used -= fam.nbytes
+        self.evictions += 1
+        if fam.mesh is not None:
+            fam.mesh.close()
+        fam.mesh = fam.f = fam.fixed = fam.u = None
+
+    # -- work --------------------------------------------------------------
+    def _serve(self, req, fam: _Family, wid: int) -> Result:
+        start = time.perf_counter() - self._t0
+        dev = torch.device("cuda")
+        if fam.mesh is None:
+            prob = family_problem(req)
+            fam.mesh = aarmr.Mesh(self.params(req))
+            n_node = fam.mesh.n_node
+            fam.f = torch.tensor(np.concatenate([np.asarray(v) for v in aarmr.loads_soa(prob, n_node)]),
+                                 dtype=torch.float64, device=dev)
+            fam.fixed = torch.tensor(aarmr.fixed_dofs_soa(prob, n_node), dtype=torch.int64, device=dev)
+            fam.u = torch.zeros_like(fam.f)
+        rho = torch.tensor(np.asarray(req["rho"], dtype=np.float64).ravel(), device=dev)
+        m = fam.mesh
+        if fam.records >= self.Ns:
+            C, st, code = m.ca_update(rho, fam.f, fam.fixed, fam.u)
+            acc = [st.accepted[l] for l in range(req["n_case"])]
+            path = "ca" if all(acc) else "fallback"
+            its = sum(st.mgcg_iterations[l] for l in range(req["n_case"]))
+            res = max(st.rel_residual[l] for l in range(req["n_case"]))
+        else:
+            flags = aarmr.RECORD_PARM | (aarmr.WARM_START if fam.records > 0 else 0)
+            C, st, code = m.solve(rho, fam.f, fam.fixed, fam.u, flags=flags)
+            fam.records += 1
+            path = "mgcg"
+            its = sum(st.iterations[l] for l in range(req["n_case"]))
+            res = max(st.rel_residual[l] for l in range(req["n_case"]))
+        if code != aarmr.OK:
+            raise aarmr.AarmrError(code, f"request {req['rid']} did not converge")
+        u = fam.u.cpu().numpy().copy() if self.keep_u else None
+        end = time.perf_counter() - self._t0
+        return Result(req["rid"], req["family"], list(C), path, int(its), float(res),
+                      req["arrival"], start, end, wid, u)
+
+    def _worker(self, wid: int):
+        stream = torch.cuda.Stream()
+        with torch.cuda.stream(stream):
+            while True:
+                with self._cv:
+                    job = None
+                    while job is None:
+                        if self._error is not None:
+                            return
+                        job = self._pick()
+                        if job is None:
+                            if self._closed and not self._queue:
+                                return
+                            self._cv.wait()
+                req, fam = job
+                try:
+                    r = self._serve(req, fam, wid)
+                except BaseException as exc:  # surfaced by run()
+                    with self._cv:
+                        self._error = exc
+                        fam.busy = False
+                        self._cv.notify_all()
+                    return
+                with self._cv:
+                    fam.busy = False
+                    fam.last_used = r.end
+                    self._results.append(r)
+                    self._cv.notify_all()
+
+    def run(self, requests: List[dict], realtime: bool = True) -> List[Result]:
+        """Serve `requests` (dicts as made by synth.serve_trace).  realtime:
+        each request is submitted at its arrival time; otherwise all are
+        submitted at once (saturation).  Returns the results in request order;
+        resident families persist across calls."""
+        self._results = []
+        self._closed = False
+        self._error = None
+        torch.cuda.synchronize()
+        self._t0 = time.perf_counter()
+        workers = [threading.Thread(target=self._worker, args=(w,), daemon=True)
+                   for w in range(self.n_workers)]
+        for t in workers:
+            t.start()
+        reqs = sorted(requests, key=lambda r: (r["arrival"], r["rid"]))
+        for req in reqs:
+            if realtime:
+                wait = req["arrival"] - (time.perf_counter() - self._t0)
+                if wait > 0:
+                    time.sleep(wait)
+                req = dict(req)
+            else:
+                req = dict(req, arrival=0.0)
+            with self._cv:
+                self._queue.append(req)
+                self._cv.notify_all()
+        with self._cv:
+            self._closed = True
+            self._cv.notify_all()
+        for t in workers:
+            t.join()
+        if self._error is not None:
+            raise self._error
+        return sorted(self._results, key=lambda r: r.rid)
+
+    def close(self):
+        for fam in list(self.families.values()):
+            self._evict(fam)
+
+
+def summarize(results: List[Result]) -> dict:
+    """p50/p99 latency, throughput (analyses and load-case solves per second
+    of the run's span) and the path mix."""
+    lat = np.array([r.latency for r in results])
+    span = max(r.end for r in results) - min(r.arrival for r in results)
+    n_solves = sum(len(r.compliance) for r in results)
+    paths = {p: sum(1 for r in results if r.path == p) for p in ("mgcg", "ca", "fallback")}
+    return {"requests": len(results), "solves": n_solves,
+            "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 2),
+            "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 2),
+            "requests_s": round(len(results) / span, 3),
+            "solves_s": round(n_solves / span, 3), "paths": paths}

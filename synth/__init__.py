@@ -15,6 +15,8 @@ from .problems import (  # noqa: F401
     patch_test,
     point_loads_on_face,
     batch_sizes,
+    serve_trace,
     PRESETS,
 )
-from .fields import uniform_iid, smoothed_field, thresholded_field, perturb  # noqa: F401
+from .fields import (  # noqa: F401
+    uniform_iid, smoothed_field, thresholded_field, perturb, smooth_perturb)

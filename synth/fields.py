@@ -44,3 +44,16 @@ def perturb(field: np.ndarray, amount: float, seed: int, lo: float = 1e-3,
     rng = np.random.default_rng(seed)
     d = rng.uniform(-2.0 * amount, 2.0 * amount, size=field.shape)
     return np.clip(field + d, lo, hi)
+
+
+def smooth_perturb(field: np.ndarray, amount: float, seed: int, sigma: float = 2.0,
+                   lo: float = 1e-3, hi: float = 1.0) -> np.ndarray:
+    """Add a seeded smoothed perturbation (standard normal noise, Gaussian-
+    smoothed with ``sigma`` voxels, periodic wrap) scaled to mean absolute
+    size ``amount`` (in density units) and clip to [lo, hi]."""
+    from scipy.ndimage import gaussian_filter
+
+    rng = np.random.default_rng(seed)
+    d = gaussian_filter(rng.standard_normal(field.shape), sigma, mode="wrap")
+    d *= amount / max(float(np.mean(np.abs(d))), 1e-300)
+    return np.clip(field + d, lo, hi)

@@ -125,6 +125,52 @@ def batch_sizes(n: int, seed0: int = 4000, choices=(16, 24, 32, 40, 48, 56, 64),
     return out
 
 
+def serve_trace(n: int, qps: float, seed: int = 5,
+                sizes=((32, 32, 32), (48, 48, 48), (64, 64, 64), (96, 48, 48), (128, 128, 128)),
+                repeat_frac: float = 0.5, w_max: float = 0.05, max_case: int = 8,
+                sigma: float = 4.0) -> List[dict]:
+    """A seeded stream of ``n`` analysis requests with Poisson arrivals at rate
+    ``qps`` (exponential gaps from a generator of their own, so the requests
+    are the same at every rate; ``qps`` <= 0: all at t = 0).
+
+    A new design draws its grid uniformly from ``sizes``, 1..``max_case``
+    load cases (clamped x=0, unit -z point loads at seeded x=nx face nodes)
+    and a smoothed random density (correlation ``sigma`` voxels, [1e-3, 1]).
+    With probability ``repeat_frac`` a request instead repeats an earlier
+    design (its family: same grid and loads), perturbed by smoothed noise
+    (correlation 2 voxels, like a filtered design update) of mean absolute
+    density change w drawn uniformly from (0, ``w_max``] (the change measure
+    of eq. 30).  Each request is a dict: rid, arrival [s], family, grid,
+    n_case, load_seed, rho (float64, (nz, ny, nx))."""
+    from .fields import smooth_perturb, smoothed_field
+
+    rng = np.random.default_rng(seed)
+    arr = np.random.default_rng([seed, 1])  # arrivals apart: same requests at any rate
+    t = 0.0
+    reqs: List[dict] = []
+    families: List[dict] = []
+    for rid in range(n):
+        if qps > 0:
+            t += float(arr.exponential(1.0 / qps))
+        if families and rng.random() < repeat_frac:
+            fam = families[int(rng.integers(0, len(families)))]
+            w = float(rng.uniform(0.0, w_max)) or w_max
+            rho = smooth_perturb(fam["rho"], w, seed=int(rng.integers(0, 2 ** 31)))
+            fam["rho"] = rho
+        else:
+            nx, ny, nz = sizes[int(rng.integers(0, len(sizes)))]
+            fam = dict(family=len(families), grid=(nx, ny, nz),
+                       n_case=int(rng.integers(1, max_case + 1)),
+                       load_seed=int(rng.integers(0, 2 ** 31)))
+            fam["rho"] = smoothed_field(nx, ny, nz, sigma, 1e-3, 1.0,
+                                        seed=int(rng.integers(0, 2 ** 31)))
+            families.append(fam)
+            rho = fam["rho"]
+        reqs.append(dict(rid=rid, arrival=t, family=fam["family"], grid=fam["grid"],
+                         n_case=fam["n_case"], load_seed=fam["load_seed"], rho=rho))
+    return reqs
+
+
 # Run presets of the synthetic workloads.  Material and method parameters are
 # the paper's (E0=1, Emin=1e-9, nu=0.3, p=3; Section 4); grid sizes, radii,
 # tolerances and level counts are the workload definitions.
