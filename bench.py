@@ -249,8 +249,9 @@ def batched_form(torch, aarmr, synth, stream_counts=(1, 4), reps=2):
     (each axis from {16, ..., 64}, seed 4000+i, max/min <= 2), each with 4
     load cases (unit -z point loads at seeded x=nx face nodes) and a smoothed
     random density (correlation 4 voxels) in [1e-3, 1]; refinement form,
-    4 grid levels, rel. residual 1e-8.  aarmr_batch_solve over 1 and 4
-    streams, median of `reps` timed runs after a warm-up, each from u = 0."""
+    4 grid levels, rel. residual 1e-8; each mesh's operator launch shape is
+    chosen once by aarmr_autotune.  aarmr_batch_solve over 1 and 4 streams,
+    median of `reps` timed runs after a warm-up, each from u = 0."""
     import numpy as np
 
     dev = torch.device("cuda")
@@ -267,10 +268,15 @@ def batched_form(torch, aarmr, synth, stream_counts=(1, 4), reps=2):
                            dtype=torch.float64, device=dev)
         fx = torch.tensor(aarmr.fixed_dofs_soa(prob, m.n_node), dtype=torch.int64, device=dev)
         jobs.append(dict(mesh=m, rho=rho, f=f, fixed=fx, u=torch.zeros_like(f)))
+    t_tune = time.perf_counter()
+    for jb in jobs:  # launch shapes chosen by the autotuner, once per mesh
+        jb["mesh"].autotune()
+    t_tune = time.perf_counter() - t_tune
     n_solves = 4 * len(jobs)
     out = {"workload": "64 cantilevers, sizes 16..64 per axis (seeds 4000-4063), 4 point-load "
                        "cases each, refinement form, 4 levels, rel. residual 1e-8",
-           "elements": int(sum(a * b * c for a, b, c in sizes)), "solves_per_batch": n_solves}
+           "elements": int(sum(a * b * c for a, b, c in sizes)), "solves_per_batch": n_solves,
+           "autotune_s": round(t_tune, 3)}
     for ns in stream_counts:
         streams = [torch.cuda.Stream() for _ in range(ns)]
         times = []

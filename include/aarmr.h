@@ -246,6 +246,17 @@ int aarmr_oc_update(aarmr_mesh* m, const double* x, const double* dc, const doub
                     double volfrac, double move, double* x_new, double* rho_phys_new,
                     void* stream);
 
+/* Autotuner of the fine-grid operator's launch shape: the z-marching kernel
+ * runs 14 x 15-node tiles of the x-y plane, each marching over a chunk of
+ * node planes; times the residency-sized default chunk length and candidate
+ * lengths 4..n_z+1 on this mesh's grid (scratch operands: the solver state is
+ * untouched), 3 launches each after a warm-up, and keeps the fastest for the
+ * mesh's later products (FP64 and, in the refinement form, FP32).
+ * tz_out: host [2] or NULL, receives the chosen lengths (0 = the default).
+ * The result of every product is the same for every chunk length.
+ * Synchronises `stream`.  Errors: AARMR_E_NO_WORKSPACE, AARMR_E_HIP. */
+int aarmr_autotune(aarmr_mesh* m, int32_t* tz_out, void* stream);
+
 /* ---- batched form ------------------------------------------------------
  * Many independent analyses (meshes of uneven size, each with its own load
  * cases) run concurrently.  Each item is one aarmr_solve call on its own mesh

@@ -75,7 +75,7 @@ EXPORTS = [
     "aarmr_default_params", "aarmr_mesh_create", "aarmr_mesh_destroy", "aarmr_workspace_bytes",
     "aarmr_bind_workspace", "aarmr_solve", "aarmr_ca_update", "aarmr_filter", "aarmr_setup",
     "aarmr_apply_operator", "aarmr_vcycle", "aarmr_element_energy", "aarmr_oc_update",
-    "aarmr_batch_solve", "aarmr_last_error",
+    "aarmr_autotune", "aarmr_batch_solve", "aarmr_last_error",
 ]
 
 
@@ -104,6 +104,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.aarmr_element_energy.argtypes = [P, vp, vp, vp]
     lib.aarmr_oc_update.argtypes = [P, vp, vp, vp, dbl, dbl, vp, vp, vp]
     lib.aarmr_batch_solve.argtypes = [ctypes.POINTER(BatchItem), i32, ctypes.POINTER(P), i32]
+    lib.aarmr_autotune.argtypes = [P, ctypes.POINTER(i32), vp]
     lib.aarmr_last_error.argtypes = []
     lib.aarmr_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
@@ -240,6 +241,13 @@ class Mesh:
     def element_energy(self, u, out):
         _check(lib().aarmr_element_energy(self._h, _ptr(u), _ptr(out), _stream()))
         return out
+
+    def autotune(self):
+        """Pick the fine-grid operator's z-chunk length by timing; returns the
+        chosen (FP64, FP32) lengths (0 = the default)."""
+        out = (ctypes.c_int32 * 2)()
+        _check(lib().aarmr_autotune(self._h, out, _stream()))
+        return out[0], out[1]
 
     def oc_update(self, x, dc, dv, volfrac, move, x_new, rho_new):
         _check(lib().aarmr_oc_update(self._h, _ptr(x), _ptr(dc), _ptr(dv), float(volfrac),

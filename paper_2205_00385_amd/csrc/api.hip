@@ -86,6 +86,7 @@ struct aarmr_mesh {
   double Bw[576];             // W M_0 W / 64 in the Walsh x component basis
   float Bw32[576];
   bool fp32 = false;          // precision == AARMR_FP32_REFINE
+  int tz64 = 0, tz32 = 0;     // tuned EbE z-chunk lengths (0: default)
   // workspace views
   char* ws = nullptr;
   int64_t ws_bytes = 0;
@@ -439,7 +440,7 @@ int read_flags(aarmr_mesh* m, unsigned* out, hipStream_t s) {
 int apply(aarmr_mesh* m, int l, const double* v, double* y, hipStream_t s,
           bool any_input = false) {
   if (l == 0) {
-    launch_ebe(m->lg[0], m->wk, m->E, m->mask, v, y, any_input ? 0 : 2, s);
+    launch_ebe(m->lg[0], m->wk, m->E, m->mask, v, y, any_input ? 0 : 2, s, m->tz64);
     ++m->sweeps;
   } else if (l == 1) {
     launch_apply_l1(m->lg[1], m->lv[1].Ke, m->Kcomp1, m->cap1, m->Bwd, m->E, m->eflag1,
@@ -528,7 +529,7 @@ int setup(aarmr_mesh* m, const double* rho, const int64_t* fixed, int64_t nfixed
 // y = A v on level l with FP32 vectors (v zero on fixed DOFs).
 int apply32(aarmr_mesh* m, int l, const float* v, float* y, hipStream_t s) {
   if (l == 0) {
-    launch_ebe_f32(m->lg[0], m->wk, m->E32, m->mask, v, y, 2, s);
+    launch_ebe_f32(m->lg[0], m->wk, m->E32, m->mask, v, y, 2, s, m->tz32);
     ++m->sweeps;
   } else if (l == 1) {
     launch_apply_l1_f32(m->lg[1], m->lv[1].Ke, m->Kcomp1, m->cap1, m->Bw32d, m->E32,
@@ -1320,6 +1321,68 @@ int aarmr_oc_update(aarmr_mesh* m, const double* x, const double* dc, const doub
   }
   launch_filter(g, m->p.rmin, m->Wf, 0, m->Hs, x_new, rho_phys_new, s);
   KCHECK();
+  return AARMR_OK;
+}
+
+int aarmr_autotune(aarmr_mesh* m, int32_t* tz_out, void* stream) {
+  TRY(need_ws(m));
+  hipStream_t s = S(stream);
+  const Grid& g = m->lg[0];
+  const int planes = g.nz + 1;
+  const int64_t n3 = 3 * g.nn;
+  std::vector<int> cand{0};  // 0: the residency-sized default
+  for (int t : {4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512})
+    if (t <= planes) cand.push_back(t);
+  if (planes > 4) cand.push_back(planes);
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  auto time_one = [&](auto launch) -> float {
+    launch();  // warm-up
+    (void)hipEventRecord(e0, s);
+    for (int r = 0; r < 3; ++r) launch();
+    (void)hipEventRecord(e1, s);
+    (void)hipEventSynchronize(e1);
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    return ms;
+  };
+  // scratch operands: moduli 1, input 1 (the timing does not depend on values)
+  launch_fill(g.ne, 1.0, m->ework, s);
+  launch_fill(n3, 1.0, m->q, s);
+  KCHECK();
+  float best = 1e30f;
+  int best_tz = 0;
+  for (int tz : cand) {
+    const float ms = time_one([&] {
+      launch_ebe(g, m->wk, m->ework, m->mask, m->q, m->t0, 2, s, tz);
+    });
+    if (ms < best) { best = ms; best_tz = tz; }
+  }
+  m->tz64 = best_tz;
+  if (m->fp32) {
+    // FP32 scratch: moduli in d32 (3 n_node >= n_elem floats), input in q32
+    launch_fill_f32(g.ne, 1.0f, m->d32, s);
+    launch_fill_f32(n3, 1.0f, m->q32, s);
+    KCHECK();
+    best = 1e30f;
+    best_tz = 0;
+    for (int tz : cand) {
+      const float ms = time_one([&] {
+        launch_ebe_f32(g, m->wk, m->d32, m->mask, m->q32, m->p32, 2, s, tz);
+      });
+      if (ms < best) { best = ms; best_tz = tz; }
+    }
+    m->tz32 = best_tz;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  KCHECK();
+  HIP_TRY(hipStreamSynchronize(s));
+  if (tz_out) {
+    tz_out[0] = m->tz64;
+    tz_out[1] = m->tz32;
+  }
   return AARMR_OK;
 }
 

@@ -54,10 +54,12 @@ using DotSet = DotSetT<double>;
 // mode 0: y = A v = Df K Df v + (I - Df) v for any v; mode 1: y = Df K Df v;
 // mode 2: y = Df K v for a v that is zero on fixed DOFs (then equal to both
 // A v and Df K Df v), the form every solver-internal product uses.
+// tz: z-chunk length (node planes per workgroup); <= 0 takes the default
+// sized from the kernel's residency (one round of workgroups fills the GPU).
 void launch_ebe(const Grid& g, const WalshConsts& K, const double* E, const uint8_t* mask,
-                const double* v, double* y, int mode, hipStream_t s);
+                const double* v, double* y, int mode, hipStream_t s, int tz = 0);
 void launch_ebe_f32(const Grid& g, const WalshConsts& K, const float* E, const uint8_t* mask,
-                    const float* v, float* y, int mode, hipStream_t s);
+                    const float* v, float* y, int mode, hipStream_t s, int tz = 0);
 void launch_energy_walsh(const Grid& g, const WalshConsts& K, const uint8_t* mask,
                          const double* u, double* energy, hipStream_t s);
 void launch_simp(int64_t ne, const double* rho, double E0, double Emin, double p, double* E,
@@ -165,6 +167,7 @@ void launch_filter_rowsum(const Grid& g, double r, double* Hs, hipStream_t s);
 void launch_filter(const Grid& g, double r, const double* W, int mode, const double* Hs,
                    const double* in, double* out, hipStream_t s);
 void launch_fill(int64_t n, double v, double* out, hipStream_t s);
+void launch_fill_f32(int64_t n, float v, float* out, hipStream_t s);
 // One OC trial: x_new at the bisection midpoint and block partials of
 // sum_j cw_j x_new_j (nparts blocks); then the bisection step on lam.
 void launch_oc_step(int64_t ne, const double* x, const double* dc, const double* dv,

@@ -347,7 +347,7 @@ __global__ void k_identity_rows(int64_t nn, const uint8_t* __restrict__ mask,
 
 template <typename T, bool MASK_IN>
 static void launch_ebe_t(const Grid& g, const WalshConsts& K, const T* E, const uint8_t* mask,
-                         const T* v, T* y, hipStream_t s) {
+                         const T* v, T* y, int tz_req, hipStream_t s) {
   // resident workgroups of this kernel on the device (thread-safe one-time init)
   static const int slots = [] {
     int dev = 0, cus = 0, per_cu = 0;
@@ -363,6 +363,7 @@ static void launch_ebe_t(const Grid& g, const WalshConsts& K, const T* E, const 
   int gz = slots / (gx * gy);
   gz = gz < 1 ? 1 : (gz > planes ? planes : gz);
   int tz = (planes + gz - 1) / gz;
+  if (tz_req > 0) tz = tz_req < planes ? tz_req : planes;  // tuned z-chunk length
   if (tz < 4) tz = 4;
   gz = (planes + tz - 1) / tz;
   k_ebe_z<T, MASK_IN, AARMR_EBE_PF><<<(unsigned)(gx * gy * gz), kThreads, 0, s>>>(g.nx, g.ny, g.nz, gx, gy, tz, K,
@@ -370,22 +371,22 @@ static void launch_ebe_t(const Grid& g, const WalshConsts& K, const T* E, const 
 }
 
 void launch_ebe(const Grid& g, const WalshConsts& K, const double* E, const uint8_t* mask,
-                const double* v, double* y, int mode, hipStream_t s) {
+                const double* v, double* y, int mode, hipStream_t s, int tz) {
   if (mode == 2) {
-    launch_ebe_t<double, false>(g, K, E, mask, v, y, s);
+    launch_ebe_t<double, false>(g, K, E, mask, v, y, tz, s);
     return;
   }
-  launch_ebe_t<double, true>(g, K, E, mask, v, y, s);
+  launch_ebe_t<double, true>(g, K, E, mask, v, y, tz, s);
   if (mode == 0) k_identity_rows<double><<<nblk(g.nn, 256), 256, 0, s>>>(g.nn, mask, v, y);
 }
 
 void launch_ebe_f32(const Grid& g, const WalshConsts& K, const float* E, const uint8_t* mask,
-                    const float* v, float* y, int mode, hipStream_t s) {
+                    const float* v, float* y, int mode, hipStream_t s, int tz) {
   if (mode == 2) {
-    launch_ebe_t<float, false>(g, K, E, mask, v, y, s);
+    launch_ebe_t<float, false>(g, K, E, mask, v, y, tz, s);
     return;
   }
-  launch_ebe_t<float, true>(g, K, E, mask, v, y, s);
+  launch_ebe_t<float, true>(g, K, E, mask, v, y, tz, s);
   if (mode == 0) k_identity_rows<float><<<nblk(g.nn, 256), 256, 0, s>>>(g.nn, mask, v, y);
 }
 

@@ -142,7 +142,8 @@ __global__ void __launch_bounds__(256) k_oc_bisect(double* lam, const double* __
   if ((lam[1] - lam[0]) / (lam[0] + lam[1]) <= 1e-3) lam[3] = 1.0;
 }
 
-__global__ void k_fill(int64_t n, double v, double* __restrict__ out) {
+template <typename T>
+__global__ void k_fill(int64_t n, T v, T* __restrict__ out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) out[i] = v;
 }
@@ -182,7 +183,11 @@ void launch_filter(const Grid& g, double r, const double* W, int mode, const dou
 }
 
 void launch_fill(int64_t n, double v, double* out, hipStream_t s) {
-  k_fill<<<nblk(n, 256), 256, 0, s>>>(n, v, out);
+  k_fill<double><<<nblk(n, 256), 256, 0, s>>>(n, v, out);
+}
+
+void launch_fill_f32(int64_t n, float v, float* out, hipStream_t s) {
+  k_fill<float><<<nblk(n, 256), 256, 0, s>>>(n, v, out);
 }
 
 void launch_oc_init(double* lam, hipStream_t s) { k_oc_init<<<1, 64, 0, s>>>(lam); }

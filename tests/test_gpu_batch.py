@@ -39,6 +39,8 @@ def test_batch64_refine_converges_matches_alone_and_oracle():
     aarmr = _aarmr()
     sizes = synth.batch_sizes(64)
     jobs = [_instance(i, sz, aarmr.FP32_REFINE) for i, sz in enumerate(sizes)]
+    tuned = [jb["mesh"].autotune() for jb in jobs]  # launch shapes by the autotuner
+    log(f"  tuned z-chunk lengths (fp64, fp32) of the first 8: {tuned[:8]}")
     streams = [torch.cuda.Stream() for _ in range(4)]
     torch.cuda.synchronize()
     comp, items, code = aarmr.batch_solve(jobs, streams)

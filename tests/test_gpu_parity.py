@@ -304,3 +304,30 @@ def test_level1_many_fixed_parents_strided_path():
     z = torch.zeros(K.shape[0], dtype=torch.float64, device="cuda")
     m.vcycle(t64(soa(r)), z)
     assert rel(z.cpu().numpy(), soa(H.vcycle(r, omega=0.6, nu1=1, nu2=1))) < 1e-9
+
+
+@pytest.mark.parametrize("dims", [(24, 12, 12), (36, 20, 40)])
+def test_autotune_keeps_products_bitwise(dims):
+    """The autotuner only changes the z-chunk length of the fine-grid
+    operator; every chunk length gives the same bits."""
+    from paper_2205_00385_amd import aarmr
+
+    prob = synth.cantilever(*dims)
+    for prec in (aarmr.FP64, aarmr.FP32_REFINE):
+        m = mesh_for(prob, mg_levels=3, precision=prec)
+        fixed = fixed_tensor(prob, m)
+        m.setup(t64(_density(prob, 41)), fixed)
+        v = np.random.default_rng(42).standard_normal(3 * m.n_node)
+        y0 = torch.empty(3 * m.n_node, dtype=torch.float64, device="cuda")
+        y1 = torch.empty_like(y0)
+        m.apply(t64(v), y0)
+        f = loads_tensor(prob, m)
+        u0 = torch.zeros_like(f)
+        m.solve(t64(_density(prob, 41)), f, fixed, u0)
+        tz = m.autotune()
+        log(f"  {dims} precision {prec}: chunk lengths {tz}")
+        m.apply(t64(v), y1)
+        assert torch.equal(y0, y1)
+        u1 = torch.zeros_like(f)
+        m.solve(t64(_density(prob, 41)), f, fixed, u1)
+        assert torch.equal(u0, u1)
