@@ -97,6 +97,7 @@ struct aarmr_mesh {
   double* Y1 = nullptr;       // level-1 element products [24][ne1]
   double* Kcomp1 = nullptr;   // compact copy of the flagged parents' matrices
   int cap1 = 0;               // its capacity (parents)
+  int nflag1 = 0;             // flagged level-1 parents of the current hierarchy
   float* Y1f = nullptr;
   float* E32 = nullptr;       // FP32 moduli (refinement form)
   float *r32 = nullptr, *z32 = nullptr, *p32 = nullptr, *q32 = nullptr, *d32 = nullptr;
@@ -433,6 +434,16 @@ int read_flags(aarmr_mesh* m, unsigned* out, hipStream_t s) {
   return AARMR_OK;
 }
 
+// The flagged level-1 parent count of the current hierarchy, copied by setup
+// into the pinned staging area (doubles 72.., after the scalar read-backs at
+// 0..3 and the flag word at 64); the first call after a setup synchronises.
+int flagged_count(aarmr_mesh* m, hipStream_t s) {
+  if (m->nflag1 >= 0) return AARMR_OK;
+  HIP_TRY(hipStreamSynchronize(s));
+  m->nflag1 = *reinterpret_cast<const int*>(m->hpin + 72);
+  return AARMR_OK;
+}
+
 // y = A v on level l.  Inside the solvers every vector is zero on fixed
 // DOFs (loads and initial guesses are masked, and A, the smoother and the
 // masked transfer operators preserve that), so the fine product skips input
@@ -443,8 +454,9 @@ int apply(aarmr_mesh* m, int l, const double* v, double* y, hipStream_t s,
     launch_ebe(m->lg[0], m->wk, m->E, m->mask, v, y, any_input ? 0 : 2, s, m->tz64);
     ++m->sweeps;
   } else if (l == 1) {
+    TRY(flagged_count(m, s));
     launch_apply_l1(m->lg[1], m->lv[1].Ke, m->Kcomp1, m->cap1, m->Bwd, m->E, m->eflag1,
-                    m->list1, m->count1, v, m->Y1, y, s);
+                    m->list1, m->count1, m->nflag1, v, m->Y1, y, s);
   } else {
     launch_apply_elemmat(m->lg[l], m->lv[l].Ke, v, y, s);
   }
@@ -506,10 +518,15 @@ int setup(aarmr_mesh* m, const double* rho, const int64_t* fixed, int64_t nfixed
   launch_diag_fine(g, m->KEd, m->E, m->mask, m->lv[0].dinv, m->lv[0].dinv32, s);
   KCHECK();
   for (int l = 1; l < m->nlev; ++l) {
-    if (l == 1)
+    if (l == 1) {
       launch_galerkin_from_fine(m->lg[1], m->KEd, m->Mcd, m->E, m->mask, m->eflag1, m->list1,
                                 m->count1, m->lv[1].Ke, m->Kcomp1, m->cap1, s);
-    else
+      KCHECK();
+      // the flagged count sizes the level-1 launches: fetched without a
+      // stall, read at the first level-1 product (nflag1 < 0 until then)
+      HIP_TRY(hipMemcpyAsync(m->hpin + 72, m->count1, sizeof(int), hipMemcpyDeviceToHost, s));
+      m->nflag1 = -1;
+    } else
       launch_galerkin_from_coarse(m->lg[l], m->lv[l - 1].Ke, m->lv[l].Ke, s);
     KCHECK();
     if (l < m->nlev - 1) {
@@ -532,8 +549,9 @@ int apply32(aarmr_mesh* m, int l, const float* v, float* y, hipStream_t s) {
     launch_ebe_f32(m->lg[0], m->wk, m->E32, m->mask, v, y, 2, s, m->tz32);
     ++m->sweeps;
   } else if (l == 1) {
+    TRY(flagged_count(m, s));
     launch_apply_l1_f32(m->lg[1], m->lv[1].Ke, m->Kcomp1, m->cap1, m->Bw32d, m->E32,
-                        m->eflag1, m->list1, m->count1, v, m->Y1f, y, s);
+                        m->eflag1, m->list1, m->count1, m->nflag1, v, m->Y1f, y, s);
   } else {
     launch_apply_elemmat_f32(m->lg[l], m->lv[l].Ke, v, y, s);
   }

@@ -94,13 +94,15 @@ void launch_apply_elemmat(const Grid& g, const double* Ke, const double* v, doub
 // Level-1 product through the Walsh form of the child matrices:
 // Bw = W M_0 W / 64 (24 x 24, Walsh x component basis, index 3k + s), Y a
 // [24][ne] element-product buffer.  Flagged parents (eflag 1, indices in
-// list[0..*count)) use their stored Ke.
+// list[0..*count), nflag = *count as read back by the host) use their stored Ke.
 void launch_apply_l1(const Grid& g, const double* Ke, const double* Kcomp, int cap,
                      const double* Bw, const double* Ef, const uint8_t* eflag, const int* list,
-                     const int* count, const double* v, double* Y, double* y, hipStream_t s);
+                     const int* count, int nflag, const double* v, double* Y, double* y,
+                     hipStream_t s);
 void launch_apply_l1_f32(const Grid& g, const double* Ke, const double* Kcomp, int cap,
                          const float* Bw, const float* Ef, const uint8_t* eflag, const int* list,
-                         const int* count, const float* v, float* Y, float* y, hipStream_t s);
+                         const int* count, int nflag, const float* v, float* Y, float* y,
+                         hipStream_t s);
 void launch_diag_elemmat(const Grid& g, const double* Ke, double* dinv, float* dinv32,
                          hipStream_t s);
 void launch_restrict(const Grid& coarse, const double* bf, const double* tf, const uint8_t* mask,

@@ -575,6 +575,42 @@ __global__ void k_assemble_dense(int nx, int ny, int nz, const double* __restric
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
+// 1/x from the hardware reciprocal estimate and two Newton steps.
+__device__ __forceinline__ double recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return fma(r, fma(-x, r, 1.0), r);
+}
+
+// 16x16 FP64 MFMA tiles over LDS (row stride ld).  Operand lane layout of
+// v_mfma_f64_16x16x4f64: A[l%16][l/16], B[l/16][l%16]; accumulator element
+// v of lane l is row l/16 + 4v, column l%16.
+__device__ __forceinline__ f64x4 mma16(const double* A, int lda, const double* B, int ldb,
+                                       f64x4 acc, double sgn_a) {
+  const int l = threadIdx.x & 63, li = l & 15, lk = l >> 4;
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) {
+    const double a = sgn_a * A[li * lda + 4 * kk + lk];
+    const double b = B[(4 * kk + lk) * ldb + li];
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+  }
+  return acc;
+}
+
+__device__ __forceinline__ f64x4 ld16(const double* C, int ldc) {
+  const int l = threadIdx.x & 63, li = l & 15, lk = l >> 4;
+  f64x4 x;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) x[v] = C[(lk + 4 * v) * ldc + li];
+  return x;
+}
+
+__device__ __forceinline__ void st16(double* C, int ldc, f64x4 x, double sgn) {
+  const int l = threadIdx.x & 63, li = l & 15, lk = l >> 4;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) C[(lk + 4 * v) * ldc + li] = sgn * x[v];
+}
+
 // In-place Gauss-Jordan inversion of a 16x16 block of LDS (row stride ld) by
 // one wavefront in registers: lane l holds rows 4(l/16)..4(l/16)+3 of column
 // l%16; pivot row and column are exchanged with lane shuffles.
@@ -587,7 +623,7 @@ __device__ __forceinline__ void gj16_wave(double* S, int ld) {
   for (int k = 0; k < 16; ++k) {
     const int kq = k & 3, kr = k >> 2;
     const double rk = __shfl(x[kq], kr * 16 + c, 64);   // S[k][c]
-    const double piv = 1.0 / __shfl(x[kq], kr * 16 + k, 64);
+    const double piv = recip(__shfl(x[kq], kr * 16 + k, 64));
     const bool pc = (c == k);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -602,59 +638,35 @@ __device__ __forceinline__ void gj16_wave(double* S, int ld) {
 
 // In-place Gauss-Jordan inversion of the 64x64 block sS (padded with the
 // identity beyond the pivot block size) by 256 threads, in four 16-wide
-// sub-steps J: Q = S_JJ^-1 (one wavefront), then S_Jk <- Q S_Jk,
-// S_ik <- S_ik - S_iJ (Q S_Jk), S_iJ <- -S_iJ Q for i, k outside J.
-__device__ __forceinline__ void gj64_block(double (*sS)[kGJBlock + 1], double (*sT)[17]) {
-  const int t = threadIdx.x;
-  const int lo = t & 15, hi = t >> 4;  // 16 x 16 thread grid
+// sub-steps J over the 4 x 4 grid of 16x16 blocks: Q = S_JJ^-1 (one
+// wavefront), then for the other blocks o, o': R_o = Q S_Jo, T_o = S_oJ Q,
+// S_oo' -= S_oJ R_o', S_Jo = R_o, S_oJ = -T_o, all on FP64 MFMA.
+__device__ __forceinline__ void gj64_block(double (*sS)[kGJBlock + 1]) {
+  constexpr int ld = kGJBlock + 1;
+  const int w = threadIdx.x >> 6;
+  const f64x4 zero = {0.0, 0.0, 0.0, 0.0};
   for (int j = 0; j < 4; ++j) {
     const int J0 = 16 * j;
-    if (t < 64) gj16_wave(&sS[J0][J0], kGJBlock + 1);
+    if (w == 0) gj16_wave(&sS[J0][J0], ld);
     __syncthreads();
-    double Tv[3], Rv[3];
-#pragma unroll
-    for (int u = 0; u < 3; ++u) {
-      const int ii = hi + 16 * u, i = ii < J0 ? ii : ii + 16;
-      double acc = 0.0;
-#pragma unroll
-      for (int p = 0; p < 16; ++p) acc = fma(sS[i][J0 + p], sS[J0 + p][J0 + lo], acc);
-      Tv[u] = acc;  // (S_iJ Q)[i][lo]
-      const int kk = lo + 16 * u, k = kk < J0 ? kk : kk + 16;
-      double r = 0.0;
-#pragma unroll
-      for (int q = 0; q < 16; ++q) r = fma(sS[J0 + hi][J0 + q], sS[J0 + q][k], r);
-      Rv[u] = r;  // (Q S_Jk)[hi][k]
+    const int ob = 16 * (w < j ? w : w + 1);  // wave w < 3: the w-th other block
+    f64x4 T = zero, R = zero;
+    if (w < 3) {
+      T = mma16(&sS[ob][J0], ld, &sS[J0][J0], ld, zero, 1.0);
+      R = mma16(&sS[J0][J0], ld, &sS[J0][ob], ld, zero, 1.0);
     }
     __syncthreads();
-#pragma unroll
-    for (int u = 0; u < 3; ++u) {
-      sT[hi + 16 * u][lo] = Tv[u];
-      const int kk = lo + 16 * u, k = kk < J0 ? kk : kk + 16;
-      sS[J0 + hi][k] = Rv[u];
+    if (w < 3) st16(&sS[J0][ob], ld, R, 1.0);
+    __syncthreads();
+    for (int t = w; t < 9; t += 4) {
+      const int q1 = t / 3, q2 = t % 3;
+      const int o1 = 16 * (q1 < j ? q1 : q1 + 1), o2 = 16 * (q2 < j ? q2 : q2 + 1);
+      f64x4 c = ld16(&sS[o1][o2], ld);
+      c = mma16(&sS[o1][J0], ld, &sS[J0][o2], ld, c, -1.0);
+      st16(&sS[o1][o2], ld, c, 1.0);
     }
     __syncthreads();
-#pragma unroll
-    for (int u = 0; u < 3; ++u) {
-      const int ii = hi + 16 * u, i = ii < J0 ? ii : ii + 16;
-      double sij[16];
-#pragma unroll
-      for (int p = 0; p < 16; ++p) sij[p] = sS[i][J0 + p];
-      // each thread reads and writes only its own (i, k) of the updated block
-#pragma unroll
-      for (int w = 0; w < 3; ++w) {
-        const int kk = lo + 16 * w, k = kk < J0 ? kk : kk + 16;
-        double acc = sS[i][k];
-#pragma unroll
-        for (int p = 0; p < 16; ++p) acc = fma(-sij[p], sS[J0 + p][k], acc);
-        sS[i][k] = acc;
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int u = 0; u < 3; ++u) {
-      const int ii = hi + 16 * u, i = ii < J0 ? ii : ii + 16;
-      sS[i][J0 + lo] = -sT[ii][lo];
-    }
+    if (w < 3) st16(&sS[ob][J0], ld, T, -1.0);
     __syncthreads();
   }
 }
@@ -664,13 +676,12 @@ __global__ void __launch_bounds__(256) k_gj_pivot_first(int n, int kb,
                                                         const double* __restrict__ A,
                                                         double* __restrict__ Pb) {
   __shared__ double sS[kGJBlock][kGJBlock + 1];
-  __shared__ double sT[48][17];
   for (int x = threadIdx.x; x < kGJBlock * kGJBlock; x += 256) {
     const int r = x / 64, c = x % 64;
     sS[r][c] = (r < kb && c < kb) ? A[(int64_t)r * n + c] : (r == c ? 1.0 : 0.0);
   }
   __syncthreads();
-  gj64_block(sS, sT);
+  gj64_block(sS);
   for (int x = threadIdx.x; x < kb * kb; x += 256) Pb[x] = sS[x / kb][x % kb];
 }
 
@@ -697,8 +708,10 @@ __global__ void __launch_bounds__(256) k_gj_cross(int n, int k0, int kb,
     sP[r][c] = (r < kb && c < kb) ? Pb[r * kb + c] : 0.0;
   }
   const bool below = i0 < k0;  // rows already pivoted
-  const int tr = tid / 16, tc = tid % 16;
-  double acc[4][4] = {};
+  const int w = tid >> 6, l = tid & 63, li = l & 15, lk = l >> 4;
+  f64x4 acc[4];
+#pragma unroll
+  for (int jb = 0; jb < 4; ++jb) acc[jb] = f64x4{0.0, 0.0, 0.0, 0.0};
   for (int h = 0; h < 2; ++h) {  // c columns [32h, 32h + 32)
     for (int t = tid; t < kGJBlock * 32; t += 256) {
       int r, q;
@@ -714,37 +727,33 @@ __global__ void __launch_bounds__(256) k_gj_cross(int n, int k0, int kb,
       const int q = t / 64, r = t % 64, p = 32 * h + q;
       if (r < rows && p < kb) Cb[(int64_t)p * n + i0 + r] = sX[r][q];
     }
-#pragma unroll 4
-    for (int q = 0; q < 32; ++q) {
-      double a[4], b[4];
+    // T[16w + i][16jb + j] += sum_q c[16w + i][32h + q] P[32h + q][16jb + j]
 #pragma unroll
-      for (int u = 0; u < 4; ++u) a[u] = sX[tr + 16 * u][q];
+    for (int kk = 0; kk < 8; ++kk) {
+      const double a = sX[16 * w + li][4 * kk + lk];
 #pragma unroll
-      for (int w = 0; w < 4; ++w) b[w] = sP[32 * h + q][tc + 16 * w];
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int w = 0; w < 4; ++w) acc[u][w] = fma(a[u], b[w], acc[u][w]);
+      for (int jb = 0; jb < 4; ++jb) {
+        const double b = sP[32 * h + 4 * kk + lk][16 * jb + li];
+        acc[jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[jb], 0, 0, 0);
+      }
     }
     __syncthreads();
   }
-  // acc[u][w] = T[row tr + 16u][col tc + 16w]; stage each half through sX
+  // acc[jb][v] = T[16w + lk + 4v][16jb + li]; stage 32 columns at a time
   for (int h = 0; h < 2; ++h) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int jj = 0; jj < 2; ++jj)
 #pragma unroll
-      for (int w = 0; w < 2; ++w) sX[tr + 16 * u][tc + 16 * w] = acc[u][2 * h + w];
+      for (int v = 0; v < 4; ++v) sX[16 * w + lk + 4 * v][16 * jj + li] = acc[2 * h + jj][v];
     __syncthreads();
-    // columns held in this half: tc + 16 * (2h + w), w in {0, 1}
     for (int t = tid; t < kGJBlock * 32; t += 256) {
-      const int q = t / 64, r = t % 64;
-      const int p = (q % 16) + 16 * (2 * h + q / 16);
+      const int q = t / 64, r = t % 64, p = 32 * h + q;
       if (r < rows && p < kb) Tb[(int64_t)p * n + i0 + r] = sX[r][q];
     }
     for (int t = tid; t < kGJBlock * 32; t += 256) {
       int r, q;
       if (below) { r = t / 32; q = t % 32; } else { q = t / 64; r = t % 64; }
-      const int p = (q % 16) + 16 * (2 * h + q / 16);
+      const int p = 32 * h + q;
       if (r < rows && p < kb) {
         if (below) A[(int64_t)(i0 + r) * n + (k0 + p)] = -sX[r][q];
         else A[(int64_t)(k0 + p) * n + (i0 + r)] = sX[r][q];
@@ -764,7 +773,6 @@ __global__ void __launch_bounds__(256) k_gj_update(int n, int k0, int kb, int nb
                                                    const double* __restrict__ Tb,
                                                    const double* __restrict__ Cb) {
   __shared__ double sS[kGJBlock][kGJBlock + 1];
-  __shared__ double sT[48][17];
   const int kblk = k0 / kGJBlock;
   const bool has_next = kblk + 1 < nb;
   int bi, bj;
@@ -828,7 +836,7 @@ __global__ void __launch_bounds__(256) k_gj_update(int n, int k0, int kb, int nb
     if (r >= kbn || c >= kbn) sS[r][c] = (r == c) ? 1.0 : 0.0;
   }
   __syncthreads();
-  gj64_block(sS, sT);
+  gj64_block(sS);
   for (int x = threadIdx.x; x < kbn * kbn; x += 256) Pb[x] = sS[x / kbn][x % kbn];
 }
 
@@ -895,24 +903,28 @@ void launch_apply_elemmat_f32(const Grid& g, const double* Ke, const float* v, f
 
 template <typename T>
 void l1_apply(const Grid& g, const double* Ke, const double* Kcomp, int cap, const T* Bw,
-              const T* Ef, const uint8_t* eflag, const int* list, const int* count, const T* v,
-              T* Y, T* y, hipStream_t s) {
+              const T* Ef, const uint8_t* eflag, const int* list, const int* count, int nflag,
+              const T* v, T* Y, T* y, hipStream_t s) {
   k_l1_elem<T><<<dim3(nblk(g.ne, 256), 3), 256, 0, s>>>(g.nx, g.ny, g.nz, Ke, Bw, Ef, eflag, v, Y);
-  const unsigned mb = (unsigned)std::min<int64_t>(nblk(g.ne, 64), 256);
-  k_l1_masked<T><<<dim3(mb, 6), 256, 0, s>>>(g.nx, g.ny, g.nz, Ke, Kcomp, cap, list, count, v, Y);
+  if (nflag > 0) {  // nflag: the flagged-parent count, known to the host after setup
+    const unsigned mb = (unsigned)std::min<int64_t>(nblk(nflag, 64), 256);
+    k_l1_masked<T><<<dim3(mb, 6), 256, 0, s>>>(g.nx, g.ny, g.nz, Ke, Kcomp, cap, list, count, v, Y);
+  }
   k_l1_gather<T><<<nblk(g.nn, 256), 256, 0, s>>>(g.nx, g.ny, g.nz, Y, y);
 }
 
 void launch_apply_l1(const Grid& g, const double* Ke, const double* Kcomp, int cap,
                      const double* Bw, const double* Ef, const uint8_t* eflag, const int* list,
-                     const int* count, const double* v, double* Y, double* y, hipStream_t s) {
-  l1_apply<double>(g, Ke, Kcomp, cap, Bw, Ef, eflag, list, count, v, Y, y, s);
+                     const int* count, int nflag, const double* v, double* Y, double* y,
+                     hipStream_t s) {
+  l1_apply<double>(g, Ke, Kcomp, cap, Bw, Ef, eflag, list, count, nflag, v, Y, y, s);
 }
 
 void launch_apply_l1_f32(const Grid& g, const double* Ke, const double* Kcomp, int cap,
                          const float* Bw, const float* Ef, const uint8_t* eflag, const int* list,
-                         const int* count, const float* v, float* Y, float* y, hipStream_t s) {
-  l1_apply<float>(g, Ke, Kcomp, cap, Bw, Ef, eflag, list, count, v, Y, y, s);
+                         const int* count, int nflag, const float* v, float* Y, float* y,
+                         hipStream_t s) {
+  l1_apply<float>(g, Ke, Kcomp, cap, Bw, Ef, eflag, list, count, nflag, v, Y, y, s);
 }
 
 void launch_restrict_f32(const Grid& coarse, const float* bf, const float* tf,
