@@ -54,6 +54,8 @@ def parse():
     ap.add_argument("--batch-only", action="store_true", help="only the 64-instance batch")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving workload")
     ap.add_argument("--serve-only", action="store_true", help="only the serving workload")
+    ap.add_argument("--study", choices=["nsnm", "bridge"],
+                    help="run a parameter study instead of the benchmark")
     ap.add_argument("--kv-only", action="store_true",
                     help="only the 256x128x128 K.v timing (for hardware-counter runs)")
     return ap.parse_args()
@@ -106,6 +108,101 @@ def run_loop(torch, aarmr, mesh, fixed, f, dv, plain=False, record=None):
         lat.append(((t1 - t0) * 1e3, (t2 - t0) * 1e3))
         comp.append(C[0])
     return lat, paths, comp
+
+
+def run_opt(torch, aarmr, synth, prob, cycles, volfrac, rmin, levels, n_on=20, ns=2, nm=2,
+            ca_tol=1e-3, orth=0, cg_rtol=1e-8, cg_maxit=2000, plain=False, move=0.2):
+    """A full optimisation of `prob` (Algorithm 1 unless `plain`: MGCG every
+    cycle) from a uniform design; returns the summed analysis time [ms],
+    the path of each cycle and the compliance history."""
+    dev = torch.device("cuda")
+    p = aarmr.default_params(nx=prob.nx, ny=prob.ny, nz=prob.nz, rmin=rmin, mg_levels=levels,
+                             cg_rtol=cg_rtol, cg_maxit=cg_maxit, Ns=ns, Nm=nm, ca_tol=ca_tol,
+                             orth=orth)
+    mesh = aarmr.Mesh(p)
+    fixed = torch.tensor(aarmr.fixed_dofs_soa(prob, mesh.n_node), dtype=torch.int64, device=dev)
+    f = torch.tensor(aarmr.loads_soa(prob, mesh.n_node)[0], dtype=torch.float64, device=dev)
+    ones = torch.ones(mesh.n_elem, dtype=torch.float64, device=dev)
+    dv = torch.empty_like(ones)
+    mesh.filter(ones, dv, mode=1)
+    x = torch.full((mesh.n_elem,), volfrac, dtype=torch.float64, device=dev)
+    xn, rp = torch.empty_like(x), torch.empty_like(x)
+    u = torch.zeros_like(f)
+    dc = torch.empty_like(x)
+    t_an, paths, comp, its = 0.0, [], [], 0
+    fl = aarmr.FILTER_INPUT
+    for loop in range(1, cycles + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if plain or loop <= n_on:
+            flags = fl | aarmr.WARM_START | (aarmr.RECORD_PARM if not plain and loop > n_on - ns else 0)
+            C, st, code = mesh.solve(x, f, fixed, u, dc=dc, flags=flags)
+            paths.append("mgcg")
+            its += st.iterations[0]
+        else:
+            C, st, code = mesh.ca_update(x, f, fixed, u, dc=dc, flags=fl)
+            paths.append("ca" if st.accepted[0] else "fallback")
+            its += st.mgcg_iterations[0]
+        t_an += time.perf_counter() - t0
+        mesh.oc_update(x, dc, dv, volfrac, move, xn, rp)
+        x, xn = xn, x
+        comp.append(C[0])
+    torch.cuda.synchronize()
+    mesh.close()
+    return {"analysis_ms": t_an * 1e3, "paths": paths, "compliance": comp, "cg_iterations": its}
+
+
+def study_ns_nm(torch, aarmr, synth):
+    """Section 4.1.1's Ns/Nm design on a 3D grid: the 48x24x24 cantilever,
+    60 cycles, volfrac 0.3, r = 2, N_on = 20, eps_tol = 1e-2, SVD basis (eq. 21),
+    Ns, Nm in {1, 2, 3, 4, 6}, against MGCG every cycle."""
+    prob = synth.cantilever(48, 24, 24)
+    kw = dict(cycles=60, volfrac=0.3, rmin=2.0, levels=3)
+    ref = run_opt(torch, aarmr, synth, prob, plain=True, **kw)
+    c_ref = ref["compliance"][-1]
+    rows = []
+    for ns in (1, 2, 3, 4, 6):
+        for nm in (1, 2, 3, 4, 6):
+            r = run_opt(torch, aarmr, synth, prob, ns=ns, nm=nm, ca_tol=1e-2, orth=1, **kw)
+            rows.append({"Ns": ns, "Nm": nm, "analysis_ms": round(r["analysis_ms"], 1),
+                         "speedup": round(ref["analysis_ms"] / r["analysis_ms"], 3),
+                         "mgcg_calls": sum(p != "ca" for p in r["paths"]),
+                         "ca_accepted": r["paths"].count("ca"),
+                         "end_compliance": r["compliance"][-1],
+                         "end_rel_diff": (r["compliance"][-1] - c_ref) / c_ref})
+            print(f"[study] Ns={ns} Nm={nm}: {rows[-1]}", file=sys.stderr, flush=True)
+    return {"grid": "48x24x24 cantilever", "cycles": 60, "eps_tol": 1e-2,
+            "mgcg_every_cycle": {"analysis_ms": round(ref["analysis_ms"], 1),
+                                 "end_compliance": c_ref},
+            "cases": rows}
+
+
+def study_bridge(torch, aarmr, synth):
+    """Section 4.2.2: the simply supported beam (four bottom corners fixed,
+    unit load at the bottom centre) on the paper's four grids, volfrac 0.2,
+    N_on = 20, Ns = Nm = 2, MGCG to rel. residual 1e-6 with at most 50
+    iterations (the paper's settings), 80 cycles, r = 2; AARMR with eps_tol
+    0.5%, 1% and 5% against MGCG every cycle.  Grid levels: 4 where the sizes
+    allow (3 for 84x28x56), the paper's 3 would leave a dense coarsest
+    operator above 8192 DOFs on the larger grids."""
+    out = []
+    for dims, lev in (((72, 24, 48), 4), ((84, 28, 56), 3), ((96, 32, 64), 4),
+                      ((120, 40, 80), 4)):
+        prob = synth.bridge(*dims)
+        kw = dict(cycles=80, volfrac=0.2, rmin=2.0, levels=lev, cg_rtol=1e-6, cg_maxit=50)
+        ref = run_opt(torch, aarmr, synth, prob, plain=True, **kw)
+        row = {"grid": "x".join(map(str, dims)), "levels": lev,
+               "mgcg_ms": round(ref["analysis_ms"], 1), "mgcg_end_compliance": ref["compliance"][-1]}
+        for tol in (0.005, 0.01, 0.05):
+            r = run_opt(torch, aarmr, synth, prob, ns=2, nm=2, ca_tol=tol, **kw)
+            row[f"eps_{tol}"] = {"analysis_ms": round(r["analysis_ms"], 1),
+                                 "speedup": round(ref["analysis_ms"] / r["analysis_ms"], 3),
+                                 "mgcg_calls": sum(p != "ca" for p in r["paths"]),
+                                 "end_rel_diff": (r["compliance"][-1] - ref["compliance"][-1])
+                                 / ref["compliance"][-1]}
+        print(f"[study] bridge {row}", file=sys.stderr, flush=True)
+        out.append(row)
+    return {"cycles": 80, "Ns": 2, "Nm": 2, "N_on": 20, "rows": out}
 
 
 def kv_event_timing(torch, aarmr, n_launch, sets):
@@ -406,6 +503,10 @@ def main():
                                   [(mesh, vr, torch.empty_like(vr))])
         print(json.dumps({"kv_96x48x48_ms": ms_loop,
                           "roofline_kv_256x128x128": large_kv(torch, aarmr, synth, args.kv_launches)}))
+        return
+    if args.study:
+        fn = {"nsnm": study_ns_nm, "bridge": study_bridge}[args.study]
+        print(json.dumps({f"study_{args.study}": fn(torch, aarmr, synth)}))
         return
     if args.serve_only:
         print(json.dumps({"served_form": served_form(torch, aarmr, synth)}))

@@ -67,6 +67,15 @@ extern "C" {
                                  preconditioned by the FP32 V-cycle.  Results
                                  meet cg_rtol in FP64 either way. */
 
+/* ---- orthogonalisation of the CARM basis (Section 2.2) ---------------- */
+#define AARMR_ORTH_GS   0  /* two-pass classical Gram-Schmidt with rank drop (named
+                              beside eq. 21 as equally valid) */
+#define AARMR_ORTH_SVD  1  /* PCA by the SVD of eq. (21), R = R~ Sigma V^T, on the
+                              column-normalised basis: R~ = left singular vectors
+                              with sigma > gs_tau sigma_1, computed as R = Q T
+                              (Gram-Schmidt without drop) and T = U Sigma V^T
+                              (one-sided Jacobi on the device), R~ = Q U */
+
 /* ---- flags for aarmr_solve / aarmr_ca_update -------------------------- */
 #define AARMR_FILTER_INPUT  1  /* `rho` is the design density: it is filtered
                                   first (eq. 31) and dc is returned w.r.t. the
@@ -102,8 +111,12 @@ typedef struct aarmr_params {
   int32_t Nm;                /* CARM size m (eq. 20), <= AARMR_MAX_BASIS */
   double ca_tol;             /* eps_tol of eq. (29): accept iff eps < ca_tol */
   double gs_tau;             /* Gram-Schmidt drops a column whose remaining
-                                norm is below gs_tau times its initial norm */
+                                norm is below gs_tau times its initial norm;
+                                with AARMR_ORTH_SVD, singular values below
+                                gs_tau times the largest are dropped */
   int32_t n_rhs_max;         /* load cases per call, <= AARMR_MAX_RHS */
+  int32_t orth;              /* CARM orthogonalisation: AARMR_ORTH_GS or
+                                AARMR_ORTH_SVD */
 } aarmr_params;
 
 /* Statistics of one aarmr_solve call (host struct written by the call). */
@@ -138,7 +151,7 @@ void aarmr_default_params(aarmr_params* p);
  * Errors: AARMR_E_INVALID for non-positive sizes, sizes not divisible by
  * 2^(mg_levels-1), mg_levels outside [2, AARMR_MAX_LEVELS], Ns or Nm outside
  * [1, AARMR_MAX_BASIS], n_rhs_max outside [1, AARMR_MAX_RHS], nu outside
- * (-1, 0.5), a coarsest grid above 6000 DOFs, or 3 * n_node >= 2^31. */
+ * (-1, 0.5), a coarsest grid above 8192 DOFs, or 3 * n_node >= 2^31. */
 int aarmr_mesh_create(const aarmr_params* p, aarmr_mesh** out);
 
 /* Release the mesh (host memory and its pinned staging buffer).  The bound

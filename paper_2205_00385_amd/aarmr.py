@@ -22,6 +22,7 @@ OK, E_INVALID, E_HIP, E_NOT_CONVERGED, E_SINGULAR, E_NO_WORKSPACE, E_STATE = ran
 MAX_RHS, MAX_LEVELS, MAX_BASIS = 8, 8, 10
 FP64, FP32_REFINE = 0, 1
 FILTER_INPUT, RECORD_PARM, WARM_START, INPUT_MASKED = 1, 2, 4, 8
+ORTH_GS, ORTH_SVD = 0, 1
 
 
 class AarmrError(RuntimeError):
@@ -39,6 +40,7 @@ class Params(ctypes.Structure):
         ("omega", ctypes.c_double), ("cg_rtol", ctypes.c_double), ("cg_maxit", ctypes.c_int32),
         ("precision", ctypes.c_int32), ("Ns", ctypes.c_int32), ("Nm", ctypes.c_int32),
         ("ca_tol", ctypes.c_double), ("gs_tau", ctypes.c_double), ("n_rhs_max", ctypes.c_int32),
+        ("orth", ctypes.c_int32),
     ]
 
 

@@ -68,6 +68,8 @@ constexpr int M_H = 144;       // up to 10 GS coefficients
 constexpr int M_FR = 156;      // reduced rhs
 constexpr int M_Y = 168;       // reduced solution
 constexpr int M_KR = 180;      // reduced matrix (up to 10x10, slots 180..279)
+constexpr int M_SVC = 300;     // SVD basis coefficients (up to 10x10, slots 300..399)
+constexpr int M_SVK = 400;     // SVD: number of kept singular vectors
 
 constexpr int64_t kAlign = 256;
 
@@ -431,6 +433,69 @@ int read_flags(aarmr_mesh* m, unsigned* out, hipStream_t s) {
   HIP_TRY(hipMemsetAsync(m->flags, 0, sizeof(unsigned), s));
   HIP_TRY(hipStreamSynchronize(s));
   *out = *h;
+  return AARMR_OK;
+}
+
+// eq. (21): R = R~ Sigma V^T on the column-normalised CARM basis in m->R
+// (Nm columns).  R = Q T by two-pass Gram-Schmidt without drop (Q in place,
+// the normalised columns kept in m->KR), T = Q^T R by dot products, the thin
+// SVD of the small T on the device (left singular vectors U of sigma >
+// gs_tau sigma_1) and R~ = Q U written back into m->R.  *kept: number of
+// basis vectors.
+int orth_svd(aarmr_mesh* m, int Nm, int* kept, hipStream_t s) {
+  const int64_t n3 = 3 * m->lg[0].nn;
+  double* misc = m->scal + SC_MISC;
+  double* R = m->R;
+  double* KR = m->KR;
+  for (int i = 0; i < Nm; ++i) {
+    TRY(dot1(m, R + i * n3, R + i * n3, misc + M_H + i, n3, s));
+    launch_scale_by_inv_sqrt(n3, R + i * n3, misc + M_H + i, R + i * n3, s);
+    KCHECK();
+    HIP_TRY(hipMemcpyAsync(KR + i * n3, R + i * n3, n3 * sizeof(double), hipMemcpyDeviceToDevice, s));
+  }
+  for (int i = 0; i < Nm; ++i) {
+    double* v = R + i * n3;
+    for (int pass = 0; pass < 2 && i > 0; ++pass) {
+      std::vector<const double*> a(i), b(i);
+      std::vector<double*> o(i);
+      for (int j = 0; j < i; ++j) {
+        a[j] = R + j * n3;
+        b[j] = v;
+        o[j] = misc + M_H + j;
+      }
+      TRY(dots(m, i, a.data(), b.data(), o.data(), n3, s));
+      launch_lincomb(n3, i, a.data(), misc + M_H, -1.0, v, v, s);
+      KCHECK();
+    }
+    TRY(dot1(m, v, v, misc + M_NRM, n3, s));
+    launch_scale_by_inv_sqrt(n3, v, misc + M_NRM, v, s);
+    KCHECK();
+  }
+  {
+    std::vector<const double*> a, b;
+    std::vector<double*> o;
+    for (int j = 0; j < Nm; ++j)
+      for (int i = 0; i < Nm; ++i) {
+        a.push_back(R + j * n3);
+        b.push_back(KR + i * n3);
+        o.push_back(misc + M_KR + j * Nm + i);
+      }
+    TRY(dots(m, (int)a.size(), a.data(), b.data(), o.data(), n3, s));
+  }
+  launch_small_svd(Nm, misc + M_KR, m->p.gs_tau, misc + M_SVC, misc + M_SVK, s);
+  KCHECK();
+  double hk = 0.0;
+  const double* src = misc + M_SVK;
+  TRY(read_scalars(m, &src, 1, &hk, s));
+  *kept = (int)hk;
+  std::vector<const double*> Q(Nm);
+  for (int i = 0; i < Nm; ++i) Q[i] = R + i * n3;
+  for (int j = 0; j < *kept; ++j) {
+    launch_lincomb(n3, Nm, Q.data(), misc + M_SVC + j * Nm, 1.0, nullptr, KR + j * n3, s);
+    KCHECK();
+  }
+  for (int j = 0; j < *kept; ++j)
+    HIP_TRY(hipMemcpyAsync(R + j * n3, KR + j * n3, n3 * sizeof(double), hipMemcpyDeviceToDevice, s));
   return AARMR_OK;
 }
 
@@ -922,6 +987,7 @@ void aarmr_default_params(aarmr_params* p) {
   p->ca_tol = 1e-3;
   p->gs_tau = 1e-10;
   p->n_rhs_max = 1;
+  p->orth = AARMR_ORTH_GS;
 }
 
 int aarmr_mesh_create(const aarmr_params* p, aarmr_mesh** out) {
@@ -937,6 +1003,8 @@ int aarmr_mesh_create(const aarmr_params* p, aarmr_mesh** out) {
     return fail(AARMR_E_INVALID, "Ns/Nm outside [1, 10]");
   if (p->n_rhs_max < 1 || p->n_rhs_max > AARMR_MAX_RHS)
     return fail(AARMR_E_INVALID, "n_rhs_max outside [1, 8]");
+  if (p->orth != AARMR_ORTH_GS && p->orth != AARMR_ORTH_SVD)
+    return fail(AARMR_E_INVALID, "unknown orthogonalisation");
   if (!(p->nu > -1.0 && p->nu < 0.5)) return fail(AARMR_E_INVALID, "nu outside (-1, 0.5)");
   if (!(p->E0 > p->Emin && p->Emin > 0.0)) return fail(AARMR_E_INVALID, "need E0 > Emin > 0");
   if (p->cg_maxit < 1 || p->cg_maxit > kMaxIt) return fail(AARMR_E_INVALID, "cg_maxit outside [1, 4096]");
@@ -951,9 +1019,9 @@ int aarmr_mesh_create(const aarmr_params* p, aarmr_mesh** out) {
   m->nlev = p->mg_levels;
   for (int l = 0; l < m->nlev; ++l) m->lg[l] = make_grid(p->nx >> l, p->ny >> l, p->nz >> l);
   m->nc = (int)(3 * m->lg[m->nlev - 1].nn);
-  if (m->nc > 6000) {
+  if (m->nc > 8192) {
     delete m;
-    return fail(AARMR_E_INVALID, "coarsest grid above 6000 DOFs: use more levels");
+    return fail(AARMR_E_INVALID, "coarsest grid above 8192 DOFs: use more levels");
   }
   hex8_stiffness(p->nu, m->KE);  // unit modulus; E0 enters through SIMP
   child_galerkin(m->KE, m->Mc);
@@ -1202,9 +1270,11 @@ int aarmr_ca_update(aarmr_mesh* m, const double* rho, const double* f, int32_t n
       TRY(read_flags(m, &fl, s));
       if (fl & 4u) ca_ok = false;  // K_Phi not positive definite: reject CA
     }
-    // Gram-Schmidt (two passes, classical) with rank drop
+    // Gram-Schmidt (two passes, classical) with rank drop, or the SVD of eq. 21
     int kept = 0;
-    if (ca_ok) {
+    if (ca_ok && m->p.orth == AARMR_ORTH_SVD) {
+      TRY(orth_svd(m, Nm, &kept, s));
+    } else if (ca_ok) {
       for (int i = 0; i < Nm; ++i) {
         double* v = m->R + i * n3;
         double n0;

@@ -159,6 +159,11 @@ void launch_lincomb(int64_t n, int k, const double* const* V, const double* coef
                     const double* add, double* out, hipStream_t s);
 void launch_small_spd_solve(int n, int lda, const double* A, const double* b, double* x,
                             unsigned* bad, hipStream_t s);
+// Thin SVD of the small n x n matrix T (row-major): left singular vectors of
+// sigma > tau sigma_1, decreasing, column by column into coef[j * n + i];
+// their count (as a double) into *kept.
+void launch_small_svd(int n, const double* T, double tau, double* coef, double* kept,
+                      hipStream_t s);
 
 // ---- filter, OC --------------------------------------------------------------
 // Cone weights max(0, r - |d|) of the filter offsets, (2R+1)^3 with

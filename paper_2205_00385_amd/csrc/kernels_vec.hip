@@ -107,7 +107,7 @@ __global__ void k_scale_inv_sqrt(int64_t n, const double* __restrict__ src,
                                  const double* __restrict__ nrm2, double* __restrict__ dst) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const double s = 1.0 / sqrt(*nrm2);
+  const double s = *nrm2 > 0.0 ? 1.0 / sqrt(*nrm2) : 0.0;  // a zero vector stays zero
   dst[i] = src[i] * s;
 }
 
@@ -148,6 +148,68 @@ __global__ void k_add_scaled_f32(int64_t n, const float* __restrict__ d,
 __global__ void k_copy_f32(int64_t n, const float* __restrict__ src, float* __restrict__ dst) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) dst[i] = src[i];
+}
+
+// Thin SVD T = U Sigma V^T of a small n x n matrix (row-major T[i * n + j],
+// n <= 2 * AARMR_MAX_BASIS) by one-sided Jacobi in one thread: rotate column
+// pairs of A = T (and V) until their inner products vanish, then
+// sigma_j = |A_j|, U_j = A_j / sigma_j, sorted by decreasing sigma.
+// Writes U_j for sigma_j > tau sigma_1 column by column (coef[j * n + i] =
+// U[i][j]) and their count (as a double) to *kept.
+__global__ void k_small_svd(int n, const double* __restrict__ T, double tau,
+                            double* __restrict__ coef, double* __restrict__ kept) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  constexpr int N = 2 * AARMR_MAX_BASIS;
+  double A[N][N];
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) A[i][j] = T[i * n + j];
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    bool rotated = false;
+    for (int p = 0; p < n - 1; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        double a = 0.0, b = 0.0, g = 0.0;
+        for (int i = 0; i < n; ++i) {
+          a += A[i][p] * A[i][p];
+          b += A[i][q] * A[i][q];
+          g += A[i][p] * A[i][q];
+        }
+        if (!(fabs(g) > 1e-15 * sqrt(a * b)) || g == 0.0) continue;
+        rotated = true;
+        const double zeta = (b - a) / (2.0 * g);
+        const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        const double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
+        for (int i = 0; i < n; ++i) {
+          const double x = A[i][p], y = A[i][q];
+          A[i][p] = c * x - sn * y;
+          A[i][q] = sn * x + c * y;
+        }
+      }
+    if (!rotated) break;
+  }
+  double sig[N];
+  int ord[N];
+  for (int j = 0; j < n; ++j) {
+    double s2 = 0.0;
+    for (int i = 0; i < n; ++i) s2 += A[i][j] * A[i][j];
+    sig[j] = sqrt(s2);
+    ord[j] = j;
+  }
+  for (int a = 0; a < n; ++a)  // selection sort, decreasing sigma
+    for (int b = a + 1; b < n; ++b)
+      if (sig[ord[b]] > sig[ord[a]]) {
+        const int t = ord[a];
+        ord[a] = ord[b];
+        ord[b] = t;
+      }
+  int k = 0;
+  const double s1 = n > 0 ? sig[ord[0]] : 0.0;
+  for (int j = 0; j < n; ++j) {
+    const int c = ord[j];
+    if (!(sig[c] > tau * s1) || sig[c] == 0.0) break;
+    for (int i = 0; i < n; ++i) coef[k * n + i] = A[i][c] / sig[c];
+    ++k;
+  }
+  *kept = (double)k;
 }
 
 struct VecList {
@@ -271,6 +333,11 @@ void launch_lincomb(int64_t n, int k, const double* const* V, const double* coef
   VecList L;
   for (int j = 0; j < 2 * AARMR_MAX_BASIS; ++j) L.v[j] = j < k ? V[j] : nullptr;
   k_lincomb<<<nblk(n, 256), 256, 0, s>>>(n, k, L, coef, sign, add, out);
+}
+
+void launch_small_svd(int n, const double* T, double tau, double* coef, double* kept,
+                      hipStream_t s) {
+  k_small_svd<<<1, 64, 0, s>>>(n, T, tau, coef, kept);
 }
 
 void launch_small_spd_solve(int n, int lda, const double* A, const double* b, double* x,

@@ -207,16 +207,20 @@ def test_not_converged_reports_and_writes():
     assert torch.isfinite(u).all() and float(u.abs().max()) > 0
 
 
-def test_ca_sequence_matches_oracle_algorithm1():
+@pytest.mark.parametrize("orth", ["gs", "svd"])
+def test_ca_sequence_matches_oracle_algorithm1(orth):
     """Algorithm 1 on both sides over the same density sequence: N_on exact
     (oracle) / converged MGCG (GPU) cycles build the PARM, then CA cycles.
-    The accept/reject path, u, C and dc must agree."""
+    The accept/reject path, u, C and dc must agree.  The oracle
+    orthogonalises by eq. 21's SVD; the GPU by Gram-Schmidt or by the same
+    SVD (rank of the kept basis compared too)."""
     from paper_2205_00385_amd import aarmr
 
     prob = synth.cantilever(16, 8, 8)
     Ns, Nm, N_on, tol = 2, 3, 3, 0.05
     alg = oca.AARMR(prob, Ns=Ns, Nm=Nm, N_on=N_on, eps_tol=tol)
-    m = mesh_for(prob, mg_levels=3, cg_rtol=1e-11, Ns=Ns, Nm=Nm, ca_tol=tol)
+    m = mesh_for(prob, mg_levels=3, cg_rtol=1e-11, Ns=Ns, Nm=Nm, ca_tol=tol,
+                 orth=aarmr.ORTH_SVD if orth == "svd" else aarmr.ORTH_GS)
     fixed = fixed_tensor(prob, m)
     f = loads_tensor(prob, m)
     u = torch.zeros_like(f)
@@ -241,6 +245,8 @@ def test_ca_sequence_matches_oracle_algorithm1():
             if abs(st.eps[0] - tol) > 1e-6 * tol:
                 assert gpath == path
             assert abs(st.eps[0] - eps_ref) <= 1e-6 * max(eps_ref, 1e-12) + 1e-9
+            if orth == "svd":
+                assert st.rank[0] == rank_ref
         paths.append(gpath)
         assert rel(u.cpu().numpy(), soa(u_ref)) <= 1e-6
         Cref = float(alg.f[0] @ u_ref)
@@ -331,3 +337,29 @@ def test_autotune_keeps_products_bitwise(dims):
         u1 = torch.zeros_like(f)
         m.solve(t64(_density(prob, 41)), f, fixed, u1)
         assert torch.equal(u0, u1)
+
+
+def test_ca_svd_and_gs_bases_give_same_reduced_solution():
+    """Nm > Ns + 1 (dependent CARM columns): the SVD and the Gram-Schmidt
+    bases span the same space, so the reduced solution and eps agree."""
+    from paper_2205_00385_amd import aarmr
+
+    prob = synth.cantilever(16, 8, 8)
+    out = {}
+    for orth in (aarmr.ORTH_GS, aarmr.ORTH_SVD):
+        m = mesh_for(prob, mg_levels=3, cg_rtol=1e-11, Ns=2, Nm=6, ca_tol=1.0, orth=orth)
+        fixed = fixed_tensor(prob, m)
+        f = loads_tensor(prob, m)
+        u = torch.zeros_like(f)
+        base = synth.smoothed_field(16, 8, 8, 2.0, 0.2, 1.0, seed=50).ravel()
+        for k in range(2):
+            m.solve(t64(np.clip(base + 0.01 * k, 0, 1)), f, fixed, u,
+                    flags=aarmr.RECORD_PARM | aarmr.WARM_START)
+        C, st, _ = m.ca_update(t64(np.clip(base + 0.03, 0, 1)), f, fixed, u)
+        assert st.accepted[0] == 1
+        out[orth] = (u.cpu().numpy(), st.eps[0], st.rank[0])
+        log(f"  orth {orth}: eps {st.eps[0]:.6e} rank {st.rank[0]}")
+    (ug, eg, rg), (us, es, rs) = out[aarmr.ORTH_GS], out[aarmr.ORTH_SVD]
+    assert rg == rs
+    assert rel(us, ug) <= 1e-9
+    assert abs(es - eg) <= 1e-9 * max(eg, 1e-12) + 1e-12
