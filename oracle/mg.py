@@ -52,6 +52,30 @@ def prolongation(ncx: int, ncy: int, ncz: int) -> sp.csr_matrix:
     return sp.csr_matrix((vals, (rows, cols)), shape=(nf, nc))
 
 
+def prolongation2(ncx: int, ncy: int) -> sp.csr_matrix:
+    """Bilinear interpolation from the coarse 2D grid (ncx x ncy elements) to
+    the 2:1 refined grid, AoS with 2 components per node."""
+    nfx, nfy = 2 * ncx, 2 * ncy
+
+    def axis(f):
+        return [(f // 2, 1.0)] if f % 2 == 0 else [((f - 1) // 2, 0.5), ((f + 1) // 2, 0.5)]
+
+    rows, cols, vals = [], [], []
+    for fj in range(nfy + 1):
+        for fi in range(nfx + 1):
+            fn = fi + (nfx + 1) * fj
+            for ci, wi in axis(fi):
+                for cj, wj in axis(fj):
+                    cn = ci + (ncx + 1) * cj
+                    for c in range(2):
+                        rows.append(2 * fn + c)
+                        cols.append(2 * cn + c)
+                        vals.append(wi * wj)
+    nf = 2 * (nfx + 1) * (nfy + 1)
+    nc = 2 * (ncx + 1) * (ncy + 1)
+    return sp.csr_matrix((vals, (rows, cols)), shape=(nf, nc))
+
+
 def _fix_empty_rows(A: sp.csr_matrix) -> sp.csr_matrix:
     d = A.diagonal()
     dead = (d == 0.0).astype(np.float64)
@@ -62,11 +86,13 @@ class Hierarchy:
     """Galerkin hierarchy A_0 .. A_{L-1} with per-level Jacobi diagonals."""
 
     def __init__(self, K: sp.spmatrix, fixed: np.ndarray, dims, levels: int):
-        nx, ny, nz = dims
+        """dims: (nx, ny, nz) elements, or (nx, ny) for the 2D plane-stress grid."""
+        two_d = len(dims) == 2
+        nx, ny, nz = (dims[0], dims[1], 1) if two_d else dims
         if levels < 2:
             raise ValueError("need at least two levels")
         s = 2 ** (levels - 1)
-        if nx % s or ny % s or nz % s:
+        if nx % s or ny % s or (not two_d and nz % s):
             raise ValueError("grid not divisible by 2^(levels-1)")
         n = K.shape[0]
         df = fem.free_mask(n, fixed).astype(np.float64)
@@ -74,7 +100,7 @@ class Hierarchy:
         self.P = []
         for l in range(levels - 1):
             f = 2 ** (l + 1)
-            P = prolongation(nx // f, ny // f, nz // f)
+            P = prolongation2(nx // f, ny // f) if two_d else prolongation(nx // f, ny // f, nz // f)
             if l == 0:
                 P = (sp.diags(df) @ P).tocsr()
             self.P.append(P)

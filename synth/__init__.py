@@ -14,6 +14,9 @@ from .problems import (  # noqa: F401
     bridge,
     patch_test,
     point_loads_on_face,
+    Problem2D,
+    cantilever2d,
+    half_wheel,
     batch_sizes,
     serve_trace,
     PRESETS,

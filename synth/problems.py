@@ -109,6 +109,46 @@ def point_loads_on_face(nx: int, ny: int, nz: int, n_case: int, seed: int) -> Pr
     return Problem(nx, ny, nz, fixed, loads, f"pointloads{nx}x{ny}x{nz}")
 
 
+@dataclasses.dataclass
+class Problem2D:
+    """A plane-stress problem on an nx x ny grid of unit squares: nodes (i, j),
+    fixed DOFs (i, j, c), point loads (i, j, c, value) per load case, and
+    linear springs (i, j, c, stiffness) on single DOFs."""
+    nx: int
+    ny: int
+    fixed: List[Tuple[int, int, int]]
+    loads: List[List[Tuple[int, int, int, float]]]
+    name: str = ""
+    springs: List[Tuple[int, int, int, float]] = dataclasses.field(default_factory=list)
+
+    @property
+    def n_elem(self) -> int:
+        return self.nx * self.ny
+
+    @property
+    def n_node(self) -> int:
+        return (self.nx + 1) * (self.ny + 1)
+
+    @property
+    def n_case(self) -> int:
+        return len(self.loads)
+
+
+def cantilever2d(nx: int, ny: int) -> Problem2D:
+    """Section 4.1.1: the whole left side fully restrained, a unit downward
+    point load at the midpoint of the right end (ny even)."""
+    fixed = [(0, j, c) for j in range(ny + 1) for c in range(2)]
+    return Problem2D(nx, ny, fixed, [[(nx, ny // 2, 1, -1.0)]], f"cantilever2d{nx}x{ny}")
+
+
+def half_wheel(nx: int, ny: int) -> Problem2D:
+    """Section 4.2.1: the lower-left corner fully constrained, the load-direction
+    DOF of the lower-right corner constrained, a unit downward point load at
+    the midpoint of the bottom edge (nx even)."""
+    fixed = [(0, 0, 0), (0, 0, 1), (nx, 0, 1)]
+    return Problem2D(nx, ny, fixed, [[(nx // 2, 0, 1, -1.0)]], f"halfwheel{nx}x{ny}")
+
+
 def batch_sizes(n: int, seed0: int = 4000, choices=(16, 24, 32, 40, 48, 56, 64),
                 max_ratio: float = 2.0) -> List[Tuple[int, int, int]]:
     """Grid sizes of a batch of ``n`` cube-ish instances: instance i draws each

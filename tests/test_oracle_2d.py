@@ -1,0 +1,92 @@
+"""Pins of the 2D plane-stress oracle (Q4, Sections 4.1, 4.2.1, 4.3) against
+closed forms and independent computations."""
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import fem, fem2d, mg, solve
+
+
+def test_q4_ke_closed_forms():
+    nu = 0.3
+    KE = fem2d.q4_ke(1.0, nu)
+    assert np.allclose(KE, KE.T, atol=1e-15)
+    # diagonal: E/(1-nu^2) * (1/3 + (1-nu)/2 * 1/3) = (3 - nu) / (6 (1 - nu^2))
+    assert np.allclose(np.diag(KE), (3.0 - nu) / (6.0 * (1.0 - nu * nu)), rtol=0, atol=1e-15)
+    w, V = np.linalg.eigh(KE)
+    assert np.sum(np.abs(w) < 1e-12) == 3 and w.min() > -1e-13
+    # rigid modes: two translations and the in-plane rotation
+    xy = np.array([[a & 1, a >> 1] for a in range(4)], dtype=float)
+    modes = [np.tile([1.0, 0.0], 4), np.tile([0.0, 1.0], 4),
+             np.column_stack([-xy[:, 1], xy[:, 0]]).ravel()]
+    for r in modes:
+        assert np.abs(KE @ r).max() < 1e-14
+
+
+@pytest.mark.parametrize("strain", [(1, 0, 0), (0, 1, 0), (0, 0, 1), (0.3, -0.7, 0.2)])
+def test_q4_constant_strain_energy(strain):
+    """u = (exx x + gxy/2 y, eyy y + gxy/2 x): energy u^T KE u = eps^T D eps (unit area)."""
+    nu = 0.3
+    exx, eyy, gxy = strain
+    xy = np.array([[a & 1, a >> 1] for a in range(4)], dtype=float)
+    u = np.column_stack([exx * xy[:, 0] + 0.5 * gxy * xy[:, 1],
+                         eyy * xy[:, 1] + 0.5 * gxy * xy[:, 0]]).ravel()
+    eps = np.array([exx, eyy, gxy])
+    D = np.array([[1, nu, 0], [nu, 1, 0], [0, 0, (1 - nu) / 2]]) / (1 - nu * nu)
+    assert abs(u @ fem2d.q4_ke(1.0, nu) @ u - eps @ D @ eps) < 1e-14
+
+
+def test_patch_test_plane_stress():
+    """Symmetry rollers (u_x = 0 on x = 0, u_y = 0 on y = 0), uniform traction
+    sigma on x = nx with consistent nodal forces: u_x = sigma x / E,
+    u_y = -nu sigma y / E exactly, C = sigma^2 V / E."""
+    nx, ny, sigma, nu = 6, 4, 2.0, 0.3
+    fixed = [(0, j, 0) for j in range(ny + 1)] + [(i, 0, 1) for i in range(nx + 1)]
+    w = np.ones(ny + 1) / ny
+    w[0] = w[-1] = 0.5 / ny
+    loads = [[(nx, j, 0, sigma * ny * w[j]) for j in range(ny + 1)]]
+    prob = synth.Problem2D(nx, ny, fixed, loads, "patch2d")
+    us, Cs, _ = fem2d.analyse2(prob, np.ones(prob.n_elem), Emin=0.0)
+    u = us[0].reshape(-1, 2)
+    for j in range(ny + 1):
+        for i in range(nx + 1):
+            n = fem2d.node_id2(nx, i, j)
+            assert abs(u[n, 0] - sigma * i) < 1e-12
+            assert abs(u[n, 1] + nu * sigma * j) < 1e-12
+    assert abs(Cs[0] - sigma ** 2 * nx * ny) < 1e-10
+
+
+def test_sensitivity_complex_step_2d():
+    prob = synth.cantilever2d(4, 2)
+    rho = np.random.default_rng(5).uniform(0.3, 1.0, prob.n_elem)
+    _, Cs, dc = fem2d.analyse2(prob, rho)
+    KE = fem2d.q4_ke()
+    fixed = fem2d.fixed_dofs_aos2(prob)
+    free = fem.free_mask(2 * prob.n_node, fixed)
+    f = fem2d.dof_vector_aos2(prob) * free
+    h = 1e-30
+    for e in range(prob.n_elem):
+        r = rho.astype(complex)
+        r[e] += 1j * h
+        K = fem2d.assemble2(prob.nx, prob.ny, fem.simp(r), KE).toarray()
+        idx = np.nonzero(free)[0]
+        u = np.zeros(2 * prob.n_node, dtype=complex)
+        u[idx] = np.linalg.solve(K[np.ix_(idx, idx)], f[idx])
+        assert abs((f @ u).imag / h - dc[e]) <= 1e-12 * abs(dc[e])
+
+
+def test_multigrid_2d_symmetric_and_mgcg_matches_direct():
+    prob = synth.cantilever2d(16, 8)
+    rho = np.random.default_rng(6).uniform(0.2, 1.0, prob.n_elem)
+    K = fem2d.assemble2(16, 8, fem.simp(rho), fem2d.q4_ke())
+    fixed = fem2d.fixed_dofs_aos2(prob)
+    H = mg.Hierarchy(K, fixed, (16, 8), 3)
+    rng = np.random.default_rng(7)
+    free = fem.free_mask(K.shape[0], fixed)
+    x, y = rng.standard_normal(K.shape[0]) * free, rng.standard_normal(K.shape[0]) * free
+    assert abs(H.vcycle(x) @ y - x @ H.vcycle(y)) < 1e-11 * np.linalg.norm(x) * np.linalg.norm(y)
+    f = fem2d.dof_vector_aos2(prob)
+    u, its, rel = mg.mgcg(K, f, fixed, (16, 8), 3, rtol=1e-12)
+    ud = solve.solve_direct(K, f * free, fixed)
+    assert rel <= 1e-12 and np.linalg.norm(u - ud) <= 1e-9 * np.linalg.norm(ud)
