@@ -171,8 +171,11 @@ class Mesh:
         _check(lib().aarmr_mesh_create(ctypes.byref(params), ctypes.byref(h)))
         self._h = h
         self.nx, self.ny, self.nz = params.nx, params.ny, params.nz
-        self.n_elem = params.nx * params.ny * params.nz
+        # nz == 0: the plane-stress grid of unit squares, 2 DOFs per node
+        self.dim = 2 if params.nz == 0 else 3
+        self.n_elem = params.nx * params.ny * max(params.nz, 1)
         self.n_node = (params.nx + 1) * (params.ny + 1) * (params.nz + 1)
+        self.n_dof = self.dim * self.n_node
         nbytes = lib().aarmr_workspace_bytes(h)
         if nbytes < 0:
             raise AarmrError(E_INVALID, "workspace size query failed")
@@ -195,7 +198,7 @@ class Mesh:
 
     # -- main entry points ---------------------------------------------------
     def solve(self, rho, f, fixed, u, compliance=True, dc=None, flags=0):
-        n3 = 3 * self.n_node
+        n3 = self.n_dof
         n_rhs = f.numel() // n3
         _f64(rho, self.n_elem, "rho")
         _f64(f, n_rhs * n3, "f")
@@ -211,7 +214,7 @@ class Mesh:
         return [C[i] for i in range(n_rhs)], st, code
 
     def ca_update(self, rho, f, fixed, u, dc=None, flags=0):
-        n3 = 3 * self.n_node
+        n3 = self.n_dof
         n_rhs = f.numel() // n3
         _f64(rho, self.n_elem, "rho")
         _f64(f, n_rhs * n3, "f")
@@ -267,7 +270,7 @@ def batch_solve(jobs, streams, check=True):
     comp = []
     for i, jb in enumerate(jobs):
         m = jb["mesh"]
-        n3 = 3 * m.n_node
+        n3 = m.n_dof
         n_rhs = jb["f"].numel() // n3
         _f64(jb["rho"], m.n_elem, "rho")
         _f64(jb["f"], n_rhs * n3, "f")
@@ -295,20 +298,30 @@ def batch_solve(jobs, streams, check=True):
 
 
 def fixed_dofs_soa(prob, n_node: int) -> list:
-    """Flatten a problem's fixed (i, j, k, c) list into SoA DOF ids c*n_node + n."""
+    """Flatten a problem's fixed (i, j, k, c) list, or (i, j, c) for a
+    plane-stress problem, into SoA DOF ids c*n_node + n."""
     nx, ny = prob.nx, prob.ny
+    if not hasattr(prob, "nz"):
+        return sorted({c * n_node + i + (nx + 1) * j for (i, j, c) in prob.fixed})
     ids = sorted({c * n_node + i + (nx + 1) * (j + (ny + 1) * k) for (i, j, k, c) in prob.fixed})
     return ids
 
 
 def loads_soa(prob, n_node: int, cases: Optional[Sequence[int]] = None) -> list:
-    """Flatten a problem's point loads into SoA vectors [case][3 * n_node]."""
+    """Flatten a problem's point loads into SoA vectors [case][dim * n_node]
+    (dim = 2 for a plane-stress problem, whose loads are (i, j, c, value))."""
     nx, ny = prob.nx, prob.ny
+    plane = not hasattr(prob, "nz")
     cases = range(prob.n_case) if cases is None else cases
     out = []
     for l in cases:
-        v = [0.0] * (3 * n_node)
-        for (i, j, k, c, val) in prob.loads[l]:
-            v[c * n_node + i + (nx + 1) * (j + (ny + 1) * k)] += val
+        v = [0.0] * ((2 if plane else 3) * n_node)
+        for ld in prob.loads[l]:
+            if plane:
+                i, j, c, val = ld
+                v[c * n_node + i + (nx + 1) * j] += val
+            else:
+                i, j, k, c, val = ld
+                v[c * n_node + i + (nx + 1) * (j + (ny + 1) * k)] += val
         out.append(v)
     return out

@@ -80,10 +80,12 @@ inline int64_t align_up(int64_t x) { return (x + kAlign - 1) / kAlign * kAlign; 
 struct aarmr_mesh {
   aarmr_params p;
   Grid lg[AARMR_MAX_LEVELS];  // lg[0] = fine grid
+  Grid fg;                    // element grid of the filter (nz >= 1)
+  int dim = 3;                // 3: hex8 solid; 2: plane-stress Q4 (nz == 0)
   int nlev = 0;
   int nc = 0;                 // coarsest dense order
-  double KE[576];
-  WalshConsts wk;             // reflection-blocked form of KE
+  double KE[576];             // 24x24 (3D) or 8x8 (2D) row-major
+  WalshConsts wk;             // reflection-blocked form of KE (3D)
   double Mc[8 * kSymEntries]; // P_c^T KE P_c per child position, packed
   double Bw[576];             // W M_0 W / 64 in the Walsh x component basis
   float Bw32[576];
@@ -177,6 +179,35 @@ void hex8_stiffness(double nu, double* KE) {
             KE[r * 24 + c] += 0.125 * s;
           }
       }
+}
+
+// Plane-stress element stiffness of the unit square (unit thickness and
+// modulus), 2x2 Gauss; DOF 2a + c of corner a = dx + 2 dy.
+void q4_stiffness(double nu, double* KE) {
+  const double c0 = 1.0 / (1.0 - nu * nu);
+  const double D[3][3] = {{c0, c0 * nu, 0.0}, {c0 * nu, c0, 0.0}, {0.0, 0.0, c0 * 0.5 * (1.0 - nu)}};
+  const double g[2] = {0.5 - 0.5 / std::sqrt(3.0), 0.5 + 0.5 / std::sqrt(3.0)};
+  std::memset(KE, 0, sizeof(double) * 64);
+  for (double x : g)
+    for (double y : g) {
+      double B[3][8] = {};
+      for (int a = 0; a < 4; ++a) {
+        const int i = a & 1, j = a >> 1;
+        const double dx = (i ? 1.0 : -1.0) * (j ? y : 1 - y);
+        const double dy = (i ? x : 1 - x) * (j ? 1.0 : -1.0);
+        B[0][2 * a] = dx;
+        B[1][2 * a + 1] = dy;
+        B[2][2 * a] = dy;
+        B[2][2 * a + 1] = dx;
+      }
+      for (int r = 0; r < 8; ++r)
+        for (int c = 0; c < 8; ++c) {
+          double s = 0.0;
+          for (int u = 0; u < 3; ++u)
+            for (int v = 0; v < 3; ++v) s += B[u][r] * D[u][v] * B[v][c];
+          KE[r * 8 + c] += 0.25 * s;
+        }
+    }
 }
 
 // Constants of the reflection-blocked form B = W KE W^T / 64 and a check
@@ -303,6 +334,9 @@ bool walsh_parent_check(const double* Mc, const double* Bw) {
   return true;
 }
 
+// DOFs of level l (dim per node).
+inline int64_t ndof(const aarmr_mesh* m, int l) { return m->dim * m->lg[l].nn; }
+
 // Assign workspace views; with base == nullptr only computes the size.
 int64_t layout(aarmr_mesh* m, char* base) {
   int64_t off = 0;
@@ -312,17 +346,21 @@ int64_t layout(aarmr_mesh* m, char* base) {
     return p;
   };
   const Grid& g = m->lg[0];
-  const int64_t n3 = 3 * g.nn;
+  const int64_t n3 = ndof(m, 0);
   const int64_t d8 = sizeof(double);
+  const bool solid = m->dim == 3;
+  const int64_t nsym = solid ? kSymEntries : kSymEntries2;
   m->KEd = (double*)take(576 * d8);
-  m->Mcd = (double*)take(8 * kSymEntries * d8);
-  m->eflag1 = (uint8_t*)take(m->lg[1].ne);
-  m->list1 = (int*)take(m->lg[1].ne * 4);
-  m->count1 = (int*)take(4);
-  m->Bwd = (double*)take(576 * d8);
-  m->Y1 = (double*)take(24 * m->lg[1].ne * d8);
-  m->cap1 = (int)std::min<int64_t>(m->lg[1].ne, std::max<int64_t>(m->lg[1].ne / 8, 1024));
-  m->Kcomp1 = (double*)take((int64_t)kSymEntries * m->cap1 * d8);
+  if (solid) {  // level-1 Walsh product (3D only)
+    m->Mcd = (double*)take(8 * kSymEntries * d8);
+    m->eflag1 = (uint8_t*)take(m->lg[1].ne);
+    m->list1 = (int*)take(m->lg[1].ne * 4);
+    m->count1 = (int*)take(4);
+    m->Bwd = (double*)take(576 * d8);
+    m->Y1 = (double*)take(24 * m->lg[1].ne * d8);
+    m->cap1 = (int)std::min<int64_t>(m->lg[1].ne, std::max<int64_t>(m->lg[1].ne / 8, 1024));
+    m->Kcomp1 = (double*)take((int64_t)kSymEntries * m->cap1 * d8);
+  }
   m->E = (double*)take(g.ne * d8);
   m->E_prev = (double*)take(g.ne * d8);
   m->dE = (double*)take(g.ne * d8);
@@ -346,11 +384,12 @@ int64_t layout(aarmr_mesh* m, char* base) {
   for (int l = 1; l < m->nlev; ++l) {
     const Grid& G = m->lg[l];
     LevelBuf& L = m->lv[l];
-    L.Ke = (double*)take(G.ne * kSymEntries * d8);
-    L.dinv = (double*)take(3 * G.nn * d8);
-    L.b = (double*)take(3 * G.nn * d8);
-    L.x = (double*)take(3 * G.nn * d8);
-    L.t = (double*)take(3 * G.nn * d8);
+    const int64_t nl = ndof(m, l);
+    L.Ke = (double*)take(G.ne * nsym * d8);
+    L.dinv = (double*)take(nl * d8);
+    L.b = (double*)take(nl * d8);
+    L.x = (double*)take(nl * d8);
+    L.t = (double*)take(nl * d8);
   }
   if (m->fp32) {
     const int64_t f4 = sizeof(float);
@@ -363,7 +402,7 @@ int64_t layout(aarmr_mesh* m, char* base) {
     m->q32 = (float*)take(n3 * f4);
     m->d32 = (float*)take(n3 * f4);
     for (int l = 0; l < m->nlev; ++l) {
-      const int64_t m3 = 3 * m->lg[l].nn;
+      const int64_t m3 = ndof(m, l);
       LevelBuf& L = m->lv[l];
       L.dinv32 = (float*)take(m3 * f4);
       L.t32 = (float*)take(m3 * f4);
@@ -443,7 +482,7 @@ int read_flags(aarmr_mesh* m, unsigned* out, hipStream_t s) {
 // gs_tau sigma_1) and R~ = Q U written back into m->R.  *kept: number of
 // basis vectors.
 int orth_svd(aarmr_mesh* m, int Nm, int* kept, hipStream_t s) {
-  const int64_t n3 = 3 * m->lg[0].nn;
+  const int64_t n3 = ndof(m, 0);
   double* misc = m->scal + SC_MISC;
   double* R = m->R;
   double* KR = m->KR;
@@ -513,8 +552,30 @@ int flagged_count(aarmr_mesh* m, hipStream_t s) {
 // DOFs (loads and initial guesses are masked, and A, the smoother and the
 // masked transfer operators preserve that), so the fine product skips input
 // masking (mode 2); `any_input` selects the general form.
+// Fine product with moduli E (the current design's, the reference design's
+// or their difference): y = Df K(E) v for a v zero on fixed DOFs.
+int fine_product(aarmr_mesh* m, const double* E, const double* v, double* y, hipStream_t s) {
+  if (m->dim == 2)
+    launch_q4_apply(m->lg[0], m->KEd, E, m->mask, v, y, 2, s);
+  else
+    launch_ebe(m->lg[0], m->wk, E, m->mask, v, y, 2, s);
+  ++m->sweeps;
+  KCHECK();
+  return AARMR_OK;
+}
+
 int apply(aarmr_mesh* m, int l, const double* v, double* y, hipStream_t s,
           bool any_input = false) {
+  if (m->dim == 2) {
+    if (l == 0) {
+      launch_q4_apply(m->lg[0], m->KEd, m->E, m->mask, v, y, any_input ? 0 : 2, s);
+      ++m->sweeps;
+    } else {
+      launch_q4_apply_elemmat(m->lg[l], m->lv[l].Ke, v, y, s);
+    }
+    KCHECK();
+    return AARMR_OK;
+  }
   if (l == 0) {
     launch_ebe(m->lg[0], m->wk, m->E, m->mask, v, y, any_input ? 0 : 2, s, m->tz64);
     ++m->sweeps;
@@ -537,7 +598,7 @@ int vcycle(aarmr_mesh* m, int l, const double* b, double* x, hipStream_t s) {
     return AARMR_OK;
   }
   const Grid& G = m->lg[l];
-  const int64_t n3 = 3 * G.nn;
+  const int64_t n3 = ndof(m, l);
   LevelBuf& L = m->lv[l];
   LevelBuf& C = m->lv[l + 1];
   const uint8_t* mask = (l == 0) ? m->mask : nullptr;
@@ -551,15 +612,15 @@ int vcycle(aarmr_mesh* m, int l, const double* b, double* x, hipStream_t s) {
       KCHECK();
     }
     TRY(apply(m, l, x, L.t, s));  // line 2: residual, restricted
-    launch_restrict(m->lg[l + 1], b, L.t, mask, C.b, s);
+    launch_restrict(m->lg[l + 1], b, L.t, mask, C.b, s, m->dim);
   } else {
     HIP_TRY(hipMemsetAsync(x, 0, n3 * sizeof(double), s));
     HIP_TRY(hipMemsetAsync(L.t, 0, n3 * sizeof(double), s));
-    launch_restrict(m->lg[l + 1], b, L.t, mask, C.b, s);
+    launch_restrict(m->lg[l + 1], b, L.t, mask, C.b, s, m->dim);
   }
   KCHECK();
   TRY(vcycle(m, l + 1, C.b, C.x, s));            // line 3
-  launch_prolong_add(G, C.x, mask, x, s);         // line 4
+  launch_prolong_add(G, C.x, mask, x, s, m->dim); // line 4
   KCHECK();
   for (int it = 0; it < m->p.nu_post; ++it) {     // line 5
     TRY(apply(m, l, x, L.t, s));
@@ -573,13 +634,34 @@ int vcycle(aarmr_mesh* m, int l, const double* b, double* x, hipStream_t s) {
 int setup(aarmr_mesh* m, const double* rho, const int64_t* fixed, int64_t nfixed, bool build_mg,
           hipStream_t s) {
   const Grid& g = m->lg[0];
-  launch_build_mask(g.nn, fixed, nfixed, m->mask, m->flags, s);
+  launch_build_mask(g.nn, fixed, nfixed, m->mask, m->flags, s, m->dim);
   KCHECK();
   launch_simp(g.ne, rho, m->p.E0, m->p.Emin, m->p.penal, m->E, m->fp32 ? m->E32 : nullptr,
               m->flags, s);
   KCHECK();
   m->mg_ready = false;
   if (!build_mg) return AARMR_OK;
+  if (m->dim == 2) {
+    launch_q4_diag(g, m->KEd, m->E, m->mask, m->lv[0].dinv, s);
+    KCHECK();
+    for (int l = 1; l < m->nlev; ++l) {
+      if (l == 1)
+        launch_q4_galerkin_from_fine(m->lg[1], m->KEd, m->E, m->mask, m->lv[1].Ke, s);
+      else
+        launch_q4_galerkin_from_coarse(m->lg[l], m->lv[l - 1].Ke, m->lv[l].Ke, s);
+      KCHECK();
+      if (l < m->nlev - 1) {
+        launch_q4_diag_elemmat(m->lg[l], m->lv[l].Ke, m->lv[l].dinv, s);
+        KCHECK();
+      }
+    }
+    launch_q4_assemble_dense(m->lg[m->nlev - 1], m->lv[m->nlev - 1].Ke, m->Ainv, s);
+    KCHECK();
+    launch_gj_invert(m->nc, m->Ainv, m->gjP, m->gjT, m->gjC, s);
+    KCHECK();
+    m->mg_ready = true;
+    return AARMR_OK;
+  }
   launch_diag_fine(g, m->KEd, m->E, m->mask, m->lv[0].dinv, m->lv[0].dinv32, s);
   KCHECK();
   for (int l = 1; l < m->nlev; ++l) {
@@ -633,7 +715,7 @@ int vcycle32(aarmr_mesh* m, int l, const float* b, float* x, hipStream_t s) {
     return AARMR_OK;
   }
   const Grid& G = m->lg[l];
-  const int64_t n3 = 3 * G.nn;
+  const int64_t n3 = ndof(m, l);
   LevelBuf& L = m->lv[l];
   LevelBuf& C = m->lv[l + 1];
   const uint8_t* mask = (l == 0) ? m->mask : nullptr;
@@ -683,7 +765,7 @@ int dot32(aarmr_mesh* m, const float* a, const float* b, double* out, int64_t n,
 int pcg32(aarmr_mesh* m, double rtol, int maxit, int* iters, double* relres, bool* stalled,
           hipStream_t s) {
   const Grid& g = m->lg[0];
-  const int64_t n3 = 3 * g.nn;
+  const int64_t n3 = ndof(m, 0);
   double* sc = m->scal;
   HIP_TRY(hipMemsetAsync(m->d32, 0, n3 * sizeof(float), s));
   *iters = 0;
@@ -728,7 +810,7 @@ int pcg32(aarmr_mesh* m, double rtol, int maxit, int* iters, double* relres, boo
 int refine(aarmr_mesh* m, double* x, int* iters, double* relres, bool* fallback,
            hipStream_t s) {
   const Grid& g = m->lg[0];
-  const int64_t n3 = 3 * g.nn;
+  const int64_t n3 = ndof(m, 0);
   double* misc = m->scal + SC_MISC;
   const double rtol = m->p.cg_rtol;
   const int budget = std::min(m->p.cg_maxit, kMaxIt);
@@ -802,7 +884,7 @@ int pcg64(aarmr_mesh* m, double* x, int* iters, double* relres, int maxit_in, bo
 int precond(aarmr_mesh* m, const double* r, const double* rr, double* z, bool use32,
             hipStream_t s) {
   if (!use32) return vcycle(m, 0, r, z, s);
-  const int64_t n3 = 3 * m->lg[0].nn;
+  const int64_t n3 = ndof(m, 0);
   launch_to_f32_scaled(n3, r, rr, m->r32, s);
   KCHECK();
   TRY(vcycle32(m, 0, m->r32, m->z32, s));
@@ -834,7 +916,7 @@ int pcg(aarmr_mesh* m, double* x, int* iters, double* relres, hipStream_t s) {
 int pcg64(aarmr_mesh* m, double* x, int* iters, double* relres, int maxit_in, bool use32,
           hipStream_t s) {
   const Grid& g = m->lg[0];
-  const int64_t n3 = 3 * g.nn;
+  const int64_t n3 = ndof(m, 0);
   double* sc = m->scal;
   double* misc = sc + SC_MISC;
   TRY(apply(m, 0, x, m->q, s));
@@ -895,7 +977,7 @@ int pcg64(aarmr_mesh* m, double* x, int* iters, double* relres, int maxit_in, bo
 
 // phi = u / ||u|| into case l's PARM ring (eqs. 27-28, oldest dropped).
 int push_parm(aarmr_mesh* m, int l, const double* u, hipStream_t s) {
-  const int64_t n3 = 3 * m->lg[0].nn;
+  const int64_t n3 = ndof(m, 0);
   double* nrm = m->scal + SC_MISC + M_NRM;
   TRY(dot1(m, u, u, nrm, n3, s));
   const int slot = m->phi_head[l];
@@ -928,7 +1010,7 @@ int finish_flags(aarmr_mesh* m, hipStream_t s) {
 int post_case(aarmr_mesh* m, int l, const double* rho_phys, const double* ul, double* compliance,
               bool want_dc, hipStream_t s) {
   const Grid& g = m->lg[0];
-  const int64_t n3 = 3 * g.nn;
+  const int64_t n3 = ndof(m, 0);
   if (compliance) {
     double* c = m->scal + SC_MISC + M_C;
     TRY(dot1(m, m->fm, ul, c, n3, s));
@@ -937,7 +1019,10 @@ int post_case(aarmr_mesh* m, int l, const double* rho_phys, const double* ul, do
     compliance[l] = h;
   }
   if (want_dc) {
-    launch_energy_walsh(g, m->wk, m->mask, ul, m->ework, s);
+    if (m->dim == 2)
+      launch_q4_energy(g, m->KEd, m->mask, ul, m->ework, s);
+    else
+      launch_energy_walsh(g, m->wk, m->mask, ul, m->ework, s);
     KCHECK();
     launch_dc_accum(g.ne, rho_phys, m->ework, m->p.E0, m->p.Emin, m->p.penal, m->dc_tmp, l == 0,
                     s);
@@ -950,7 +1035,7 @@ int finish_dc(aarmr_mesh* m, double* dc, int32_t flags, hipStream_t s) {
   const Grid& g = m->lg[0];
   if (!dc) return AARMR_OK;
   if (flags & AARMR_FILTER_INPUT) {
-    launch_filter(g, m->p.rmin, m->Wf, 1, m->Hs, m->dc_tmp, dc, s);
+    launch_filter(m->fg, m->p.rmin, m->Wf, 1, m->Hs, m->dc_tmp, dc, s);
   } else {
     HIP_TRY(hipMemcpyAsync(dc, m->dc_tmp, g.ne * sizeof(double), hipMemcpyDeviceToDevice, s));
   }
@@ -993,7 +1078,11 @@ void aarmr_default_params(aarmr_params* p) {
 int aarmr_mesh_create(const aarmr_params* p, aarmr_mesh** out) {
   if (!p || !out) return fail(AARMR_E_INVALID, "null argument");
   *out = nullptr;
-  if (p->nx < 1 || p->ny < 1 || p->nz < 1) return fail(AARMR_E_INVALID, "grid sizes must be >= 1");
+  if (p->nx < 1 || p->ny < 1 || p->nz < 0)
+    return fail(AARMR_E_INVALID, "grid sizes must be >= 1 (nz = 0: plane stress)");
+  const int dim = p->nz == 0 ? 2 : 3;
+  if (dim == 2 && p->precision != AARMR_FP64)
+    return fail(AARMR_E_INVALID, "the plane-stress grid supports AARMR_FP64 only");
   if (p->mg_levels < 2 || p->mg_levels > AARMR_MAX_LEVELS)
     return fail(AARMR_E_INVALID, "mg_levels outside [2, 8]");
   const int f = 1 << (p->mg_levels - 1);
@@ -1012,16 +1101,23 @@ int aarmr_mesh_create(const aarmr_params* p, aarmr_mesh** out) {
     return fail(AARMR_E_INVALID, "unknown precision");
   if (p->nu_pre < 0 || p->nu_post < 0 || !(p->omega > 0.0))
     return fail(AARMR_E_INVALID, "bad smoother parameters");
-  if (3 * (int64_t)(p->nx + 1) * (p->ny + 1) * (p->nz + 1) >= (int64_t(1) << 31))
-    return fail(AARMR_E_INVALID, "grid too large: 3 * n_node must stay below 2^31");
+  if (dim * (int64_t)(p->nx + 1) * (p->ny + 1) * (p->nz + 1) >= (int64_t(1) << 31))
+    return fail(AARMR_E_INVALID, "grid too large: DOF count must stay below 2^31");
   aarmr_mesh* m = new aarmr_mesh();
   m->p = *p;
+  m->dim = dim;
   m->nlev = p->mg_levels;
   for (int l = 0; l < m->nlev; ++l) m->lg[l] = make_grid(p->nx >> l, p->ny >> l, p->nz >> l);
-  m->nc = (int)(3 * m->lg[m->nlev - 1].nn);
+  m->fg = make_grid(p->nx, p->ny, std::max(p->nz, 1));
+  m->nc = (int)(dim * m->lg[m->nlev - 1].nn);
   if (m->nc > 8192) {
     delete m;
     return fail(AARMR_E_INVALID, "coarsest grid above 8192 DOFs: use more levels");
+  }
+  if (dim == 2) {
+    q4_stiffness(p->nu, m->KE);  // unit modulus and thickness
+    *out = m;
+    return AARMR_OK;
   }
   hex8_stiffness(p->nu, m->KE);  // unit modulus; E0 enters through SIMP
   child_galerkin(m->KE, m->Mc);
@@ -1068,8 +1164,10 @@ int aarmr_bind_workspace(aarmr_mesh* m, void* dev_ptr, int64_t bytes, void* stre
   layout(m, m->ws);
   hipStream_t s = S(stream);
   HIP_TRY(hipMemcpyAsync(m->KEd, m->KE, 576 * sizeof(double), hipMemcpyHostToDevice, s));
-  HIP_TRY(hipMemcpyAsync(m->Mcd, m->Mc, 8 * kSymEntries * sizeof(double), hipMemcpyHostToDevice, s));
-  HIP_TRY(hipMemcpyAsync(m->Bwd, m->Bw, 576 * sizeof(double), hipMemcpyHostToDevice, s));
+  if (m->dim == 3) {
+    HIP_TRY(hipMemcpyAsync(m->Mcd, m->Mc, 8 * kSymEntries * sizeof(double), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(m->Bwd, m->Bw, 576 * sizeof(double), hipMemcpyHostToDevice, s));
+  }
   if (m->fp32) {
     HIP_TRY(hipMemcpyAsync(m->Bw32d, m->Bw32, 576 * sizeof(float), hipMemcpyHostToDevice, s));
   }
@@ -1082,9 +1180,9 @@ int aarmr_bind_workspace(aarmr_mesh* m, void* dev_ptr, int64_t bytes, void* stre
     filter_weights(m->p.rmin, m->Wh.data());
     HIP_TRY(hipMemcpyAsync(m->Wf, m->Wh.data(), m->Wh.size() * sizeof(double),
                            hipMemcpyHostToDevice, s));
-    launch_filter_rowsum(m->lg[0], m->p.rmin, m->Hs, s);
+    launch_filter_rowsum(m->fg, m->p.rmin, m->Hs, s);
     KCHECK();
-    launch_filter(m->lg[0], m->p.rmin, m->Wf, 1, m->Hs, m->ones_dv, m->cw, s);
+    launch_filter(m->fg, m->p.rmin, m->Wf, 1, m->Hs, m->ones_dv, m->cw, s);
     KCHECK();
   }
   HIP_TRY(hipStreamSynchronize(s));
@@ -1121,7 +1219,10 @@ int aarmr_vcycle(aarmr_mesh* m, const double* r, double* z, void* stream) {
 int aarmr_element_energy(aarmr_mesh* m, const double* u, double* energy, void* stream) {
   TRY(need_ws(m));
   if (!u || !energy) return fail(AARMR_E_INVALID, "null argument");
-  launch_energy_walsh(m->lg[0], m->wk, m->mask, u, energy, S(stream));
+  if (m->dim == 2)
+    launch_q4_energy(m->lg[0], m->KEd, m->mask, u, energy, S(stream));
+  else
+    launch_energy_walsh(m->lg[0], m->wk, m->mask, u, energy, S(stream));
   KCHECK();
   return AARMR_OK;
 }
@@ -1131,7 +1232,7 @@ int aarmr_filter(aarmr_mesh* m, int32_t mode, const double* in, double* out, voi
   if (!in || !out || in == out) return fail(AARMR_E_INVALID, "in, out must be distinct non-null");
   if (mode != 0 && mode != 1) return fail(AARMR_E_INVALID, "mode must be 0 or 1");
   if (!(m->p.rmin > 0.0)) return fail(AARMR_E_INVALID, "filter disabled (rmin <= 0)");
-  launch_filter(m->lg[0], m->p.rmin, m->Wf, mode, m->Hs, in, out, S(stream));
+  launch_filter(m->fg, m->p.rmin, m->Wf, mode, m->Hs, in, out, S(stream));
   KCHECK();
   return AARMR_OK;
 }
@@ -1144,12 +1245,12 @@ int aarmr_solve(aarmr_mesh* m, const double* rho, const double* f, int32_t n_rhs
     return fail(AARMR_E_INVALID, "AARMR_FILTER_INPUT needs rmin > 0");
   hipStream_t s = S(stream);
   const Grid& g = m->lg[0];
-  const int64_t n3 = 3 * g.nn;
+  const int64_t n3 = ndof(m, 0);
   auto t0 = std::chrono::steady_clock::now();
   const int64_t sw0 = m->sweeps;
   const double* rho_phys = rho;
   if (flags & AARMR_FILTER_INPUT) {
-    launch_filter(g, m->p.rmin, m->Wf, 0, m->Hs, rho, m->rho_f, s);
+    launch_filter(m->fg, m->p.rmin, m->Wf, 0, m->Hs, rho, m->rho_f, s);
     KCHECK();
     rho_phys = m->rho_f;
   }
@@ -1163,10 +1264,10 @@ int aarmr_solve(aarmr_mesh* m, const double* rho, const double* f, int32_t n_rhs
   int status = AARMR_OK;
   for (int l = 0; l < n_rhs; ++l) {
     double* ul = u + l * n3;
-    launch_copy_masked(g, f + l * n3, m->mask, m->fm, s);
+    launch_copy_masked(g, f + l * n3, m->mask, m->fm, s, m->dim);
     KCHECK();
     if (flags & AARMR_WARM_START) {
-      launch_copy_masked(g, ul, m->mask, ul, s);
+      launch_copy_masked(g, ul, m->mask, ul, s, m->dim);
       KCHECK();
     } else {
       HIP_TRY(hipMemsetAsync(ul, 0, n3 * sizeof(double), s));
@@ -1206,13 +1307,13 @@ int aarmr_ca_update(aarmr_mesh* m, const double* rho, const double* f, int32_t n
     if (m->phi_count[l] < m->p.Ns) return fail(AARMR_E_STATE, "PARM of a load case is not complete");
   hipStream_t s = S(stream);
   const Grid& g = m->lg[0];
-  const int64_t n3 = 3 * g.nn;
+  const int64_t n3 = ndof(m, 0);
   const int Ns = m->p.Ns, Nm = m->p.Nm;
   const int64_t sw0 = m->sweeps;
   if (st) std::memset(st, 0, sizeof(*st));
   const double* rho_phys = rho;
   if (flags & AARMR_FILTER_INPUT) {
-    launch_filter(g, m->p.rmin, m->Wf, 0, m->Hs, rho, m->rho_f, s);
+    launch_filter(m->fg, m->p.rmin, m->Wf, 0, m->Hs, rho, m->rho_f, s);
     KCHECK();
     rho_phys = m->rho_f;
   }
@@ -1225,15 +1326,13 @@ int aarmr_ca_update(aarmr_mesh* m, const double* rho, const double* f, int32_t n
   for (int l = 0; l < n_rhs; ++l) {
     double* ul = u + l * n3;
     const double* PhiL = m->Phi + (int64_t)l * Ns * n3;
-    launch_copy_masked(g, f + l * n3, m->mask, m->fm, s);
+    launch_copy_masked(g, f + l * n3, m->mask, m->fm, s, m->dim);
     KCHECK();
-    launch_copy_masked(g, ul, m->mask, ul, s);
+    launch_copy_masked(g, ul, m->mask, ul, s, m->dim);
     KCHECK();
     // eq. (15): K_Phi = Phi^T K0 Phi, K0 = K(previous design)
     for (int j = 0; j < Ns; ++j) {
-      launch_ebe(g, m->wk, m->E_prev, m->mask, PhiL + j * n3, m->t0, 2, s);
-      ++m->sweeps;
-      KCHECK();
+      TRY(fine_product(m, m->E_prev, PhiL + j * n3, m->t0, s));
       std::vector<const double*> a(Ns), b(Ns);
       std::vector<double*> o(Ns);
       for (int i = 0; i < Ns; ++i) {
@@ -1247,9 +1346,7 @@ int aarmr_ca_update(aarmr_mesh* m, const double* rho, const double* f, int32_t n
     HIP_TRY(hipMemcpyAsync(m->R, ul, n3 * sizeof(double), hipMemcpyDeviceToDevice, s));
     bool ca_ok = true;
     for (int i = 1; i < Nm; ++i) {
-      launch_ebe(g, m->wk, m->dE, m->mask, m->R + (i - 1) * n3, m->t0, 2, s);
-      ++m->sweeps;
-      KCHECK();
+      TRY(fine_product(m, m->dE, m->R + (i - 1) * n3, m->t0, s));
       std::vector<const double*> a(Ns), b(Ns);
       std::vector<double*> o(Ns);
       for (int j = 0; j < Ns; ++j) {
@@ -1307,9 +1404,7 @@ int aarmr_ca_update(aarmr_mesh* m, const double* rho, const double* f, int32_t n
     if (kept > 0) {
       // eqs. (22)-(25): K_R~ = R~^T K R~, f_R~ = R~^T f, y, u~ = R~ y
       for (int j = 0; j < kept; ++j) {
-        launch_ebe(g, m->wk, m->E, m->mask, m->R + j * n3, m->KR + j * n3, 2, s);
-        ++m->sweeps;
-        KCHECK();
+        TRY(fine_product(m, m->E, m->R + j * n3, m->KR + j * n3, s));
       }
       std::vector<const double*> a, b;
       std::vector<double*> o;
@@ -1407,17 +1502,21 @@ int aarmr_oc_update(aarmr_mesh* m, const double* x, const double* dc, const doub
       if (done != 0.0) break;
     }
   }
-  launch_filter(g, m->p.rmin, m->Wf, 0, m->Hs, x_new, rho_phys_new, s);
+  launch_filter(m->fg, m->p.rmin, m->Wf, 0, m->Hs, x_new, rho_phys_new, s);
   KCHECK();
   return AARMR_OK;
 }
 
 int aarmr_autotune(aarmr_mesh* m, int32_t* tz_out, void* stream) {
   TRY(need_ws(m));
+  if (m->dim == 2) {  // the plane-stress product has no tunable chunk
+    if (tz_out) tz_out[0] = tz_out[1] = 0;
+    return AARMR_OK;
+  }
   hipStream_t s = S(stream);
   const Grid& g = m->lg[0];
   const int planes = g.nz + 1;
-  const int64_t n3 = 3 * g.nn;
+  const int64_t n3 = ndof(m, 0);
   std::vector<int> cand{0};  // 0: the residency-sized default
   for (int t : {4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512})
     if (t <= planes) cand.push_back(t);

@@ -20,6 +20,8 @@ constexpr int kRedSlots = 24;      // dot products one reduction launch can hold
 constexpr int kMaxIt = 4096;       // bound of cg_maxit (scalar history length)
 constexpr int kGJBlock = 64;       // block size of the coarsest inversion
 
+// nz == 0 is the plane-stress grid: nx * ny unit squares, (nx+1)(ny+1)
+// nodes with 2 DOFs each.
 struct Grid {
   int nx, ny, nz;          // elements
   int64_t ne, nn;          // elements, nodes
@@ -28,7 +30,7 @@ struct Grid {
 inline Grid make_grid(int nx, int ny, int nz) {
   Grid g;
   g.nx = nx; g.ny = ny; g.nz = nz;
-  g.ne = (int64_t)nx * ny * nz;
+  g.ne = (int64_t)nx * ny * (nz > 0 ? nz : 1);
   g.nn = (int64_t)(nx + 1) * (ny + 1) * (nz + 1);
   return g;
 }
@@ -65,8 +67,9 @@ void launch_energy_walsh(const Grid& g, const WalshConsts& K, const uint8_t* mas
 void launch_simp(int64_t ne, const double* rho, double E0, double Emin, double p, double* E,
                  float* E32, unsigned* bad, hipStream_t s);
 void launch_diff(int64_t n, const double* a, const double* b, double* out, hipStream_t s);
+// ncomp: DOFs per node (3, or 2 on the plane-stress grid)
 void launch_build_mask(int64_t nn, const int64_t* fixed, int64_t nfixed, uint8_t* mask,
-                       unsigned* bad, hipStream_t s);
+                       unsigned* bad, hipStream_t s, int ncomp = 3);
 void launch_diag_fine(const Grid& g, const double* KE, const double* E, const uint8_t* mask,
                       double* dinv, float* dinv32, hipStream_t s);
 void launch_dc_accum(int64_t ne, const double* rho, const double* energy, double E0, double Emin,
@@ -105,10 +108,11 @@ void launch_apply_l1_f32(const Grid& g, const double* Ke, const double* Kcomp, i
                          hipStream_t s);
 void launch_diag_elemmat(const Grid& g, const double* Ke, double* dinv, float* dinv32,
                          hipStream_t s);
+// Transfers act per component; ncomp = 2 on the plane-stress grid (nz = 0).
 void launch_restrict(const Grid& coarse, const double* bf, const double* tf, const uint8_t* mask,
-                     double* bc, hipStream_t s);
+                     double* bc, hipStream_t s, int ncomp = 3);
 void launch_prolong_add(const Grid& fine, const double* xc, const uint8_t* mask, double* xf,
-                        hipStream_t s);
+                        hipStream_t s, int ncomp = 3);
 void launch_jacobi_first(int64_t n3, const double* b, const double* dinv, double omega, double* x,
                          hipStream_t s);
 void launch_jacobi_update(int64_t n3, const double* b, const double* t, const double* dinv,
@@ -146,7 +150,7 @@ void launch_add_scaled_f32(int64_t n, const float* d, const double* nrm2, double
                            hipStream_t s);
 void launch_copy_f32(int64_t n, const float* src, float* dst, hipStream_t s);
 void launch_copy_masked(const Grid& g, const double* src, const uint8_t* mask, double* dst,
-                        hipStream_t s);
+                        hipStream_t s, int ncomp = 3);
 void launch_sub(int64_t n, const double* a, const double* b, double* out, hipStream_t s);
 void launch_cg_xr(int64_t n, const double* rz, const double* pq, double* x, double* r,
                   const double* p, const double* q, hipStream_t s);
@@ -164,6 +168,31 @@ void launch_small_spd_solve(int n, int lda, const double* A, const double* b, do
 // their count (as a double) into *kept.
 void launch_small_svd(int n, const double* T, double tau, double* coef, double* kept,
                       hipStream_t s);
+
+// ---- plane stress (bilinear quadrilaterals, grids with nz = 0) -------------
+// Coarse element matrices are symmetric 8x8, packed (upper triangle,
+// row-major: 36 entries) and entry-major like the 3D ones.  KE: the 8x8
+// unit-modulus element stiffness, row-major, DOF 2a + c of corner a = dx + 2dy.
+constexpr int kSymEntries2 = 36;
+__host__ __device__ constexpr int sym_index2(int r, int c) {
+  return r <= c ? r * 8 - (r * (r - 1)) / 2 + (c - r) : c * 8 - (c * (c - 1)) / 2 + (r - c);
+}
+// mode as for launch_ebe
+void launch_q4_apply(const Grid& g, const double* KE, const double* E, const uint8_t* mask,
+                     const double* v, double* y, int mode, hipStream_t s);
+void launch_q4_energy(const Grid& g, const double* KE, const uint8_t* mask, const double* u,
+                      double* energy, hipStream_t s);
+void launch_q4_diag(const Grid& g, const double* KE, const double* E, const uint8_t* mask,
+                    double* dinv, hipStream_t s);
+// Level 1: (Df P)^T K (Df P) per parent from the fine moduli and mask.
+void launch_q4_galerkin_from_fine(const Grid& coarse, const double* KE, const double* E,
+                                  const uint8_t* mask, double* Kc, hipStream_t s);
+void launch_q4_galerkin_from_coarse(const Grid& coarse, const double* Kf, double* Kc,
+                                    hipStream_t s);
+void launch_q4_apply_elemmat(const Grid& g, const double* Ke, const double* v, double* y,
+                             hipStream_t s);
+void launch_q4_diag_elemmat(const Grid& g, const double* Ke, double* dinv, hipStream_t s);
+void launch_q4_assemble_dense(const Grid& g, const double* Ke, double* A, hipStream_t s);
 
 // ---- filter, OC --------------------------------------------------------------
 // Cone weights max(0, r - |d|) of the filter offsets, (2R+1)^3 with

@@ -39,12 +39,12 @@ __global__ void k_mask_clear(int64_t nn, uint32_t* mask_words) {
   if (i < (nn + 3) / 4) mask_words[i] = 0u;
 }
 
-__global__ void k_mask_set(int64_t nn, const int64_t* __restrict__ fixed, int64_t nf,
+__global__ void k_mask_set(int64_t nn, int ncomp, const int64_t* __restrict__ fixed, int64_t nf,
                            uint32_t* mask_words, unsigned* bad) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= nf) return;
   int64_t d = fixed[t];
-  if (d < 0 || d >= 3 * nn) {
+  if (d < 0 || d >= ncomp * nn) {
     atomicOr(bad, 2u);
     return;
   }
@@ -112,10 +112,10 @@ void launch_diff(int64_t n, const double* a, const double* b, double* out, hipSt
 }
 
 void launch_build_mask(int64_t nn, const int64_t* fixed, int64_t nfixed, uint8_t* mask,
-                       unsigned* bad, hipStream_t s) {
+                       unsigned* bad, hipStream_t s, int ncomp) {
   uint32_t* w = reinterpret_cast<uint32_t*>(mask);
   k_mask_clear<<<nblk((nn + 3) / 4, 256), 256, 0, s>>>(nn, w);
-  if (nfixed > 0) k_mask_set<<<nblk(nfixed, 256), 256, 0, s>>>(nn, fixed, nfixed, w, bad);
+  if (nfixed > 0) k_mask_set<<<nblk(nfixed, 256), 256, 0, s>>>(nn, ncomp, fixed, nfixed, w, bad);
 }
 
 void launch_diag_fine(const Grid& g, const double* KE, const double* E, const uint8_t* mask,

@@ -429,7 +429,8 @@ __global__ void k_diag_elemmat(int nx, int ny, int nz, const double* __restrict_
 
 // bc = P^T Df (bf - tf) (tf == nullptr: bf alone), weights (1/2, 1, 1/2)
 // per axis.  One thread per (coarse node, fine z-offset) and component
-// (grid.y); the three z-planes of a coarse node are summed in LDS.
+// (grid.y); the three z-planes of a coarse node are summed in LDS.  On the
+// plane grid (cnz = 0) only the middle offset lies in the grid.
 // mask == nullptr: no fine fixed DOFs.
 template <typename T>
 __global__ void __launch_bounds__(192) k_restrict(int cnx, int cny, int cnz,
@@ -478,12 +479,13 @@ __global__ void __launch_bounds__(192) k_restrict(int cnx, int cny, int cnz,
 
 // xf += Df P xc: thread per fine node, branch-free over the (up to) 8
 // parent nodes: along an axis an even fine index takes its parent with
-// weight 1, an odd one both neighbours with weight 1/2.
+// weight 1, an odd one both neighbours with weight 1/2.  On the plane grid
+// (fnz = 0) the z pair is (0, 0) with weights (1, 0) and ncomp = 2.
 template <typename T>
 __global__ void __launch_bounds__(256) k_prolong_add(int fnx, int fny, int fnz,
                                                      const T* __restrict__ xc,
                                                      const uint8_t* __restrict__ mask,
-                                                     T* __restrict__ xf) {
+                                                     T* __restrict__ xf, int ncomp) {
   const int64_t fnn = (int64_t)(fnx + 1) * (fny + 1) * (fnz + 1);
   const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= fnn) return;
@@ -509,6 +511,7 @@ __global__ void __launch_bounds__(256) k_prolong_add(int fnx, int fny, int fnz,
   const uint8_t m = mask ? mask[n] : 0;
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
+    if (c >= ncomp) break;
     const T* x = xc + c * cnn;
     T s = 0;
 #pragma unroll
@@ -935,7 +938,8 @@ void launch_restrict_f32(const Grid& coarse, const float* bf, const float* tf,
 
 void launch_prolong_add_f32(const Grid& fine, const float* xc, const uint8_t* mask, float* xf,
                             hipStream_t s) {
-  k_prolong_add<float><<<nblk(fine.nn, 256), 256, 0, s>>>(fine.nx, fine.ny, fine.nz, xc, mask, xf);
+  k_prolong_add<float><<<nblk(fine.nn, 256), 256, 0, s>>>(fine.nx, fine.ny, fine.nz, xc, mask, xf,
+                                                          3);
 }
 
 void launch_jacobi_first_f32(int64_t n3, const float* b, const float* dinv, float omega, float* x,
@@ -958,15 +962,15 @@ void launch_diag_elemmat(const Grid& g, const double* Ke, double* dinv, float* d
 }
 
 void launch_restrict(const Grid& coarse, const double* bf, const double* tf, const uint8_t* mask,
-                     double* bc, hipStream_t s) {
-  k_restrict<double><<<dim3(nblk(coarse.nn, 64), 3), 192, 0, s>>>(coarse.nx, coarse.ny, coarse.nz,
+                     double* bc, hipStream_t s, int ncomp) {
+  k_restrict<double><<<dim3(nblk(coarse.nn, 64), ncomp), 192, 0, s>>>(coarse.nx, coarse.ny, coarse.nz,
                                                                   bf, tf, mask, bc);
 }
 
 void launch_prolong_add(const Grid& fine, const double* xc, const uint8_t* mask, double* xf,
-                        hipStream_t s) {
+                        hipStream_t s, int ncomp) {
   k_prolong_add<double><<<nblk(fine.nn, 256), 256, 0, s>>>(fine.nx, fine.ny, fine.nz, xc, mask,
-                                                           xf);
+                                                           xf, ncomp);
 }
 
 void launch_jacobi_first(int64_t n3, const double* b, const double* dinv, double omega, double* x,

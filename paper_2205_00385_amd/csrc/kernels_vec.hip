@@ -67,10 +67,10 @@ __global__ void __launch_bounds__(256) k_multidot_finish(DotSetT<T> d, int nb,
   }
 }
 
-__global__ void k_copy_masked(int64_t nn, const double* __restrict__ src,
+__global__ void k_copy_masked(int64_t nn, int ncomp, const double* __restrict__ src,
                               const uint8_t* __restrict__ mask, double* __restrict__ dst) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= 3 * nn) return;
+  if (i >= ncomp * nn) return;
   const int c = (int)(i / nn);
   const int64_t n = i - c * nn;
   dst[i] = ((mask[n] >> c) & 1) ? 0.0 : src[i];
@@ -305,8 +305,8 @@ void launch_copy_f32(int64_t n, const float* src, float* dst, hipStream_t s) {
 }
 
 void launch_copy_masked(const Grid& g, const double* src, const uint8_t* mask, double* dst,
-                        hipStream_t s) {
-  k_copy_masked<<<nblk(3 * g.nn, 256), 256, 0, s>>>(g.nn, src, mask, dst);
+                        hipStream_t s, int ncomp) {
+  k_copy_masked<<<nblk(ncomp * g.nn, 256), 256, 0, s>>>(g.nn, ncomp, src, mask, dst);
 }
 
 void launch_sub(int64_t n, const double* a, const double* b, double* out, hipStream_t s) {
