@@ -87,6 +87,16 @@ def assemble2(nx: int, ny: int, Ee: np.ndarray, KE: np.ndarray) -> sp.csr_matrix
     return K
 
 
+def spring_matrix2(prob) -> sp.csr_matrix:
+    """Diagonal matrix of the problem's linear springs to ground: k on the
+    DOF (i, j, c) of each spring (Section 4.3's k_in, k_out)."""
+    n = 2 * prob.n_node
+    d = np.zeros(n)
+    for (i, j, c, k) in getattr(prob, "springs", []):
+        d[2 * node_id2(prob.nx, i, j) + c] += k
+    return sp.diags(d).tocsr()
+
+
 def dof_vector_aos2(prob, case: int = 0) -> np.ndarray:
     f = np.zeros(2 * prob.n_node)
     for (i, j, c, v) in prob.loads[case]:
@@ -110,7 +120,8 @@ def soa_to_aos2(v: np.ndarray) -> np.ndarray:
 
 def analyse2(prob, rho_phys, KE=None, E0=1.0, Emin=1e-9, p=3.0):
     """Plain definition of the 2D analysis for every load case: direct solve
-    on the free DOFs, C_l = f_l^T u_l (eq. 3), summed dC/drho~ (eq. 6).
+    on the free DOFs of K + springs, C_l = f_l^T u_l (eq. 3), summed
+    dC/drho~ (eq. 6; the springs do not depend on rho~).
     Returns (u_list AoS, C_list, dc_phys)."""
     from . import fem, sens, solve
 
@@ -118,7 +129,7 @@ def analyse2(prob, rho_phys, KE=None, E0=1.0, Emin=1e-9, p=3.0):
         KE = q4_ke(1.0, 0.3)
     rho = np.asarray(rho_phys).ravel()
     Ee = fem.simp(rho, E0, Emin, p)
-    K = assemble2(prob.nx, prob.ny, Ee, KE)
+    K = (assemble2(prob.nx, prob.ny, Ee, KE) + spring_matrix2(prob)).tocsr()
     fixed = fixed_dofs_aos2(prob)
     ds = solve.DirectSolver(K, fixed)
     edof = element_dofs2(prob.nx, prob.ny)
@@ -132,3 +143,31 @@ def analyse2(prob, rho_phys, KE=None, E0=1.0, Emin=1e-9, p=3.0):
         Cs.append(sens.compliance(f, u))
         dc += sens.dc_drho_phys(rho, sens.element_energy(u, edof, KE), E0, Emin, p)
     return us, Cs, dc
+
+
+def mutual_energy(u: np.ndarray, w: np.ndarray, edof: np.ndarray, KE: np.ndarray) -> np.ndarray:
+    """Per-element u_e^T KE w_e."""
+    return np.einsum("ei,ij,ej->e", u[edof], KE, w[edof])
+
+
+def mechanism2(prob, rho_phys, KE=None, E0=1.0, Emin=1e-9, p=3.0):
+    """The non-self-adjoint analysis of Section 4.3: load case 0 (input force)
+    and case 1 (unit dummy load at the output DOF) solved with the springs;
+    the output displacement u_out = f_1^T u_0 and its sensitivity by the
+    adjoint method: d u_out / d rho~_e = -dE_e/drho~_e u1_e^T KE u0_e (K
+    symmetric, so case 1's solution is the adjoint).  Evaluated with the
+    approximate displacements of the reduced model in place of u0, u1 this
+    is the paper's approximate sensitivity (eq. 34's form).
+    Returns (u0, u1 AoS, u_out, dout_phys)."""
+    from . import fem
+
+    if KE is None:
+        KE = q4_ke(1.0, 0.3)
+    us, _, _ = analyse2(prob, rho_phys, KE, E0, Emin, p)
+    u0, u1 = us[0], us[1]
+    free = fem.free_mask(2 * prob.n_node, fixed_dofs_aos2(prob))
+    f1 = dof_vector_aos2(prob, 1) * free
+    rho = np.asarray(rho_phys).ravel()
+    dE = p * (E0 - Emin) * rho ** (p - 1)
+    mut = mutual_energy(u0, u1, element_dofs2(prob.nx, prob.ny), KE)
+    return u0, u1, float(f1 @ u0), -dE * mut

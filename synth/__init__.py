@@ -17,6 +17,7 @@ from .problems import (  # noqa: F401
     Problem2D,
     cantilever2d,
     half_wheel,
+    inverter2d,
     batch_sizes,
     serve_trace,
     PRESETS,

@@ -149,6 +149,21 @@ def half_wheel(nx: int, ny: int) -> Problem2D:
     return Problem2D(nx, ny, fixed, [[(nx // 2, 0, 1, -1.0)]], f"halfwheel{nx}x{ny}")
 
 
+def inverter2d(nx: int, ny: int, k_in: float = 1.0, k_out: float = 0.1) -> Problem2D:
+    """Section 4.3's displacement inverter on the half domain below its axis of
+    symmetry, taken as the bottom edge j = 0: the y DOFs of that edge fixed
+    (symmetry), both DOFs of the two top nodes of the left side fixed
+    (support), input point A = (0, 0) and output point B = (nx, 0) on the
+    axis.  Load case 0 is the unit input force +x at A; load case 1 the unit
+    dummy load +x at B, whose solution gives the output displacement's
+    sensitivity.  Springs k_in at A and k_out at B, both in x."""
+    fixed = [(i, 0, 1) for i in range(nx + 1)]
+    fixed += [(0, ny, 0), (0, ny, 1), (0, ny - 1, 0), (0, ny - 1, 1)]
+    loads = [[(0, 0, 0, 1.0)], [(nx, 0, 0, 1.0)]]
+    springs = [(0, 0, 0, k_in), (nx, 0, 0, k_out)]
+    return Problem2D(nx, ny, fixed, loads, f"inverter{nx}x{ny}", springs)
+
+
 def batch_sizes(n: int, seed0: int = 4000, choices=(16, 24, 32, 40, 48, 56, 64),
                 max_ratio: float = 2.0) -> List[Tuple[int, int, int]]:
     """Grid sizes of a batch of ``n`` cube-ish instances: instance i draws each

@@ -90,3 +90,77 @@ def test_multigrid_2d_symmetric_and_mgcg_matches_direct():
     u, its, rel = mg.mgcg(K, f, fixed, (16, 8), 3, rtol=1e-12)
     ud = solve.solve_direct(K, f * free, fixed)
     assert rel <= 1e-12 and np.linalg.norm(u - ud) <= 1e-9 * np.linalg.norm(ud)
+
+
+def test_springs_proportional_to_traction_give_uniform_strain():
+    """A strip on rollers (u_x = 0 on x = 0, u_y = 0 on y = 0) pulled by the
+    consistent nodal forces of a uniform traction sigma on x = nx, with
+    grounded springs kappa * ny * w_j proportional to the same weights:
+    the uniform strain state u_x = eps x, u_y = -nu eps y is exact with
+    eps = sigma / (E + kappa nx), and C = sigma ny eps nx."""
+    nx, ny, sigma, kappa, nu = 6, 4, 2.0, 0.05, 0.3
+    fixed = [(0, j, 0) for j in range(ny + 1)] + [(i, 0, 1) for i in range(nx + 1)]
+    w = np.ones(ny + 1) / ny
+    w[0] = w[-1] = 0.5 / ny
+    loads = [[(nx, j, 0, sigma * ny * w[j]) for j in range(ny + 1)]]
+    springs = [(nx, j, 0, kappa * ny * w[j]) for j in range(ny + 1)]
+    prob = synth.Problem2D(nx, ny, fixed, loads, "spring_strip", springs)
+    us, Cs, _ = fem2d.analyse2(prob, np.ones(prob.n_elem), Emin=0.0)
+    eps = sigma / (1.0 + kappa * nx)
+    u = us[0].reshape(-1, 2)
+    for j in range(ny + 1):
+        for i in range(nx + 1):
+            n = fem2d.node_id2(nx, i, j)
+            assert abs(u[n, 0] - eps * i) < 1e-12
+            assert abs(u[n, 1] + nu * eps * j) < 1e-12
+    assert abs(Cs[0] - sigma * ny * eps * nx) < 1e-10
+
+
+def test_mechanism_sensitivity_complex_step():
+    """The inverter's output displacement f_1^T u_0 (springs included)
+    differentiated by a complex step in each element's modulus equals the
+    adjoint sensitivity, and Maxwell-Betti reciprocity f_1^T u_0 = f_0^T u_1
+    holds."""
+    prob = synth.inverter2d(6, 4)
+    rho = np.random.default_rng(8).uniform(0.3, 1.0, prob.n_elem)
+    u0, u1, uout, dout = fem2d.mechanism2(prob, rho)
+    fixed = fem2d.fixed_dofs_aos2(prob)
+    free = fem.free_mask(2 * prob.n_node, fixed)
+    f0 = fem2d.dof_vector_aos2(prob, 0) * free
+    f1 = fem2d.dof_vector_aos2(prob, 1) * free
+    assert abs(f1 @ u0 - f0 @ u1) <= 1e-12 * abs(uout)
+    assert abs(f1 @ u0 - uout) == 0.0
+    KE = fem2d.q4_ke()
+    S = fem2d.spring_matrix2(prob).toarray()
+    idx = np.nonzero(free)[0]
+    h = 1e-30
+    for e in range(prob.n_elem):
+        r = rho.astype(complex)
+        r[e] += 1j * h
+        K = fem2d.assemble2(prob.nx, prob.ny, fem.simp(r), KE).toarray() + S
+        u = np.zeros(2 * prob.n_node, dtype=complex)
+        u[idx] = np.linalg.solve(K[np.ix_(idx, idx)], f0[idx])
+        assert abs((f1 @ u).imag / h - dout[e]) <= 1e-10 * np.abs(dout).max()
+
+
+def test_mechanism_springs_enter_the_objective():
+    """Raising k_out stiffens the output: |u_out| falls; with both springs
+    zero the objective is the spring-free analysis."""
+    rho = np.full(8 * 4, 0.6)
+    outs = [fem2d.mechanism2(synth.inverter2d(8, 4, 1.0, k), rho)[2] for k in (0.0, 0.1, 10.0)]
+    assert abs(outs[0]) > abs(outs[1]) > abs(outs[2])
+    bare = synth.inverter2d(8, 4, 0.0, 0.0)
+    us, _, _ = fem2d.analyse2(synth.Problem2D(8, 4, bare.fixed, bare.loads), rho)
+    assert abs(fem2d.mechanism2(bare, rho)[2] - us[0][2 * fem2d.node_id2(8, 8, 0)]) < 1e-15
+
+
+def test_mutual_sensitivity_reduces_to_compliance():
+    """With the dummy load equal to the input load, the mutual-energy
+    sensitivity is the (pinned) compliance sensitivity."""
+    base = synth.inverter2d(6, 4)
+    prob = synth.Problem2D(6, 4, base.fixed, [base.loads[0], base.loads[0]], "same", base.springs)
+    rho = np.random.default_rng(9).uniform(0.3, 1.0, prob.n_elem)
+    _, _, uout, dout = fem2d.mechanism2(prob, rho)
+    _, Cs, dc = fem2d.analyse2(synth.Problem2D(6, 4, base.fixed, [base.loads[0]], "c", base.springs), rho)
+    assert abs(uout - Cs[0]) <= 1e-13 * Cs[0]
+    assert np.abs(dout - dc).max() <= 1e-12 * np.abs(dc).max()
