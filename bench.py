@@ -54,7 +54,7 @@ def parse():
     ap.add_argument("--batch-only", action="store_true", help="only the 64-instance batch")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving workload")
     ap.add_argument("--serve-only", action="store_true", help="only the serving workload")
-    ap.add_argument("--study", choices=["nsnm", "bridge", "nsnm2d", "halfwheel"],
+    ap.add_argument("--study", choices=["nsnm", "bridge", "nsnm2d", "halfwheel", "inverter"],
                     help="run a parameter study instead of the benchmark")
     ap.add_argument("--kv-only", action="store_true",
                     help="only the 256x128x128 K.v timing (for hardware-counter runs)")
@@ -264,6 +264,88 @@ def study_half_wheel(torch, aarmr, synth, cycles=100):
         print(f"[study] half-wheel {row}", file=sys.stderr, flush=True)
         out.append(row)
     return {"cycles": cycles, "Ns": 2, "Nm": 2, "N_on": 20, "rows": out}
+
+
+def run_mechanism(torch, aarmr, synth, prob, cycles, levels, plain, ca_tol=1e-3, volfrac=0.3,
+                  rmin=2.5, move=0.05, n_on=20, ns=2, nm=2):
+    """A full displacement-inverter optimisation (Section 4.3): load cases
+    input and dummy output, springs, the output displacement's sensitivity
+    (AARMR_MUTUAL_SENS; from the reduced model when CA is accepted), OC
+    with eta 0.3.  Returns the summed analysis time, paths, the u_out history
+    and CG iterations per MGCG call."""
+    dev = torch.device("cuda")
+    p = aarmr.default_params(nx=prob.nx, ny=prob.ny, nz=0, rmin=rmin, mg_levels=levels,
+                             cg_rtol=1e-6, cg_maxit=200, Ns=ns, Nm=nm, ca_tol=ca_tol,
+                             n_rhs_max=2, oc_eta=0.3)
+    mesh = aarmr.Mesh(p)
+    mesh.set_springs(*aarmr.springs_soa(prob, mesh.n_node))
+    fixed = torch.tensor(aarmr.fixed_dofs_soa(prob, mesh.n_node), dtype=torch.int64, device=dev)
+    f = torch.tensor([v for c in aarmr.loads_soa(prob, mesh.n_node) for v in c],
+                     dtype=torch.float64, device=dev)
+    ones = torch.ones(mesh.n_elem, dtype=torch.float64, device=dev)
+    dv = torch.empty_like(ones)
+    mesh.filter(ones, dv, mode=1)
+    x = torch.full((mesh.n_elem,), volfrac, dtype=torch.float64, device=dev)
+    xn, rp = torch.empty_like(x), torch.empty_like(x)
+    u = torch.zeros_like(f)
+    dc = torch.empty_like(x)
+    out_dof = prob.nx  # x DOF of the output node (nx, 0)
+    t_an, paths, uout, its, calls = 0.0, [], [], 0, 0
+    fl = aarmr.FILTER_INPUT | aarmr.MUTUAL_SENS
+    for loop in range(1, cycles + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if plain or loop <= n_on:
+            flags = fl | aarmr.WARM_START | (aarmr.RECORD_PARM if not plain and loop > n_on - ns else 0)
+            C, st, code = mesh.solve(x, f, fixed, u, dc=dc, flags=flags)
+            paths.append("mgcg")
+            its += st.iterations[0] + st.iterations[1]
+            calls += 2
+        else:
+            C, st, code = mesh.ca_update(x, f, fixed, u, dc=dc, flags=fl)
+            acc = st.accepted[0] and st.accepted[1]
+            paths.append("ca" if acc else "fallback")
+            for l in range(2):
+                if not st.accepted[l]:
+                    its += st.mgcg_iterations[l]
+                    calls += 1
+        t_an += time.perf_counter() - t0
+        uout.append(float(u[out_dof]))
+        mesh.oc_update(x, dc, dv, volfrac, move, xn, rp)
+        x, xn = xn, x
+    torch.cuda.synchronize()
+    mesh.close()
+    return {"analysis_ms": t_an * 1e3, "paths": paths, "u_out": uout,
+            "avg_cg_iterations": its / max(calls, 1), "mgcg_solves": calls}
+
+
+def study_inverter(torch, aarmr, synth, cycles=200):
+    """Section 4.3 / Table 1: the displacement inverter on the L-grid 320x160
+    and the H-grid 640x320, 200 cycles, volfrac 0.3, N_on = 20, Ns = Nm = 2,
+    MGCG to rel. residual 1e-6 with at most 200 iterations, k_in = 1,
+    k_out = 0.1; AARMR with eps_tol 0.01% and 0.1% against MGCG every cycle.
+    Levels: 4 and 5 (coarsest 1722 DOFs); OC move 0.05, eta 0.3."""
+    rows = []
+    for dims, lev in (((320, 160), 4), ((640, 320), 5)):
+        prob = synth.inverter2d(*dims)
+        ref = run_mechanism(torch, aarmr, synth, prob, cycles, lev, plain=True)
+        row = {"grid": "x".join(map(str, dims)), "levels": lev,
+               "mgcg": {"analysis_ms": round(ref["analysis_ms"], 1),
+                        "avg_cg_iterations": round(ref["avg_cg_iterations"], 3),
+                        "u_out_end": ref["u_out"][-1]}}
+        for tol in (1e-4, 1e-3):
+            r = run_mechanism(torch, aarmr, synth, prob, cycles, lev, plain=False, ca_tol=tol)
+            row[f"eps_{tol}"] = {"analysis_ms": round(r["analysis_ms"], 1),
+                                 "speedup": round(ref["analysis_ms"] / r["analysis_ms"], 3),
+                                 "avg_cg_iterations": round(r["avg_cg_iterations"], 3),
+                                 "mgcg_solves": r["mgcg_solves"],
+                                 "ca_accepted": r["paths"].count("ca"),
+                                 "u_out_end": r["u_out"][-1],
+                                 "diff_pct": 100.0 * (r["u_out"][-1] - ref["u_out"][-1])
+                                 / abs(ref["u_out"][-1])}
+        print(f"[study] inverter {row}", file=sys.stderr, flush=True)
+        rows.append(row)
+    return {"cycles": cycles, "Ns": 2, "Nm": 2, "N_on": 20, "rows": rows}
 
 
 def kv_event_timing(torch, aarmr, n_launch, sets):
@@ -567,7 +649,7 @@ def main():
         return
     if args.study:
         fn = {"nsnm": study_ns_nm, "bridge": study_bridge, "nsnm2d": study_ns_nm_2d,
-              "halfwheel": study_half_wheel}[args.study]
+              "halfwheel": study_half_wheel, "inverter": study_inverter}[args.study]
         print(json.dumps({f"study_{args.study}": fn(torch, aarmr, synth)}))
         return
     if args.serve_only:

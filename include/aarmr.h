@@ -17,6 +17,11 @@
  *   - DOF vectors are structure-of-arrays: v[c * n_node + n], c in {0:x,1:y,2:z};
  *     a DOF id is c * n_node + n.  Several load cases are stored back to back
  *     (case l starts at l * 3 * n_node).
+ *   - Plane stress (the paper's 2D examples, Sections 4.1, 4.2.1, 4.3):
+ *     nz = 0 selects a grid of nx * ny unit squares (bilinear Q4 elements,
+ *     unit thickness), (nx+1)(ny+1) nodes, element e = i + nx*j, node
+ *     n = i + (nx+1)*j, two DOFs per node: every "[3][n_node]" below reads
+ *     "[2][n_node]" and every 3 * n_node reads 2 * n_node.
  *   - All array arguments marked "device" are pointers to GPU memory of the
  *     device current for the calling thread; "host" pointers are CPU memory.
  *     The caller owns every buffer it passes; the library keeps no pointer to
@@ -55,6 +60,7 @@ extern "C" {
 #define AARMR_MAX_RHS     8
 #define AARMR_MAX_LEVELS  8
 #define AARMR_MAX_BASIS   10
+#define AARMR_MAX_SPRINGS 8
 
 /* ---- precision of the inner solve ------------------------------------ */
 #define AARMR_FP64         0  /* everything in FP64 */
@@ -93,11 +99,22 @@ extern "C" {
                                   that v is zero on fixed DOFs, so the product
                                   skips masking its input (the form every
                                   solver-internal product uses) */
+#define AARMR_MUTUAL_SENS  16  /* the non-self-adjoint objective of Section
+                                  4.3: with n_rhs = 2, dc is the sensitivity
+                                  of f_1^T u_0 (load case 1 is the unit dummy
+                                  load on the output DOF, so this is the
+                                  output displacement under load case 0):
+                                  -dE_e/drho~_e u1_e^T KE u0_e, load case 1's
+                                  solution serving as the adjoint.  In
+                                  aarmr_ca_update both come from the reduced
+                                  model when accepted: the approximate
+                                  sensitivity of eq. (34)'s form.  Plane-stress
+                                  grid only. */
 
 /* ---- parameters -------------------------------------------------------- */
 typedef struct aarmr_params {
   int32_t nx, ny, nz;        /* elements per axis; each divisible by
-                                2^(mg_levels-1) */
+                                2^(mg_levels-1); nz = 0: plane stress */
   double E0, Emin, nu, penal;/* SIMP, eq. (1): E = Emin + (E0-Emin) rho~^p */
   double rmin;               /* filter radius in element lengths, eq. (32);
                                 <= 0 disables aarmr_filter */
@@ -117,6 +134,9 @@ typedef struct aarmr_params {
   int32_t n_rhs_max;         /* load cases per call, <= AARMR_MAX_RHS */
   int32_t orth;              /* CARM orthogonalisation: AARMR_ORTH_GS or
                                 AARMR_ORTH_SVD */
+  double oc_eta;             /* OC damping exponent in (0, 1]: 0.5 for
+                                compliance, 0.3 for the mechanism of Section
+                                4.3 */
 } aarmr_params;
 
 /* Statistics of one aarmr_solve call (host struct written by the call). */
@@ -147,11 +167,14 @@ void aarmr_default_params(aarmr_params* p);
 
 /* Create a mesh object (host memory only; no device allocation).  Computes
  * the hex8 element stiffness of the unit cube for nu by 2x2x2 Gauss
- * quadrature and the filter stencil.  *out receives the handle.
+ * quadrature (nz = 0: the plane-stress Q4 stiffness of the unit square,
+ * 2x2 Gauss) and the filter stencil.  *out receives the handle.  The
+ * plane-stress grid supports precision AARMR_FP64 only.
  * Errors: AARMR_E_INVALID for non-positive sizes, sizes not divisible by
  * 2^(mg_levels-1), mg_levels outside [2, AARMR_MAX_LEVELS], Ns or Nm outside
  * [1, AARMR_MAX_BASIS], n_rhs_max outside [1, AARMR_MAX_RHS], nu outside
- * (-1, 0.5), a coarsest grid above 8192 DOFs, or 3 * n_node >= 2^31. */
+ * (-1, 0.5), a coarsest grid above 8192 DOFs, the DOF count >= 2^31, or
+ * AARMR_FP32_REFINE with nz = 0. */
 int aarmr_mesh_create(const aarmr_params* p, aarmr_mesh** out);
 
 /* Release the mesh (host memory and its pinned staging buffer).  The bound
@@ -249,11 +272,23 @@ int aarmr_vcycle(aarmr_mesh* m, const double* r, double* z, void* stream);
  * Fixed DOFs of u are treated as zero. */
 int aarmr_element_energy(aarmr_mesh* m, const double* u, double* energy, void* stream);
 
+/* Linear springs to ground on single DOFs (Section 4.3's k_in at the input
+ * and k_out at the output of the displacement inverter): the stiffness is
+ * K(rho~) + sum_s k_s e_s e_s^T in every solve, V-cycle and operator product
+ * after the call (the hierarchy includes them from the next aarmr_setup,
+ * aarmr_solve or aarmr_ca_update), and the change K - K0 of the CA step
+ * (eqs. 20, 26) does not contain them.  dofs: host [n] DOF ids
+ * (c * n_node + n), repeated ids add up; k: host [n], >= 0; 0 <= n <=
+ * AARMR_MAX_SPRINGS; n = 0 removes all springs.  Springs on fixed DOFs have
+ * no effect.  Plane-stress grid only.  The arrays are copied.
+ * Errors: AARMR_E_INVALID (3D mesh, n or an id out of range, k < 0). */
+int aarmr_set_springs(aarmr_mesh* m, const int64_t* dofs, const double* k, int32_t n);
+
 /* Optimality-criteria update of the design density (the textbook OC rule
- * for eq. (3)): x_new = clamp(x * (max(0,-dc)/(lambda dv))^0.5, x-move,
+ * for eq. (3)): x_new = clamp(x * (max(0,-dc)/(lambda dv))^eta, x-move,
  * x+move, 0, 1) with lambda found by bisection in [0, 1e9] until
  * (l2-l1)/(l1+l2) <= 1e-3, the volume sum(rho~) of the filtered x_new
- * compared with volfrac * n_elem.  x, dc, dv: device [n_elem]; x_new,
+ * compared with volfrac * n_elem; eta = params.oc_eta.  x, dc, dv: device [n_elem]; x_new,
  * rho_phys_new: device [n_elem].  Stream-ordered. */
 int aarmr_oc_update(aarmr_mesh* m, const double* x, const double* dc, const double* dv,
                     double volfrac, double move, double* x_new, double* rho_phys_new,
@@ -266,7 +301,8 @@ int aarmr_oc_update(aarmr_mesh* m, const double* x, const double* dc, const doub
  * untouched), 3 launches each after a warm-up, and keeps the fastest for the
  * mesh's later products (FP64 and, in the refinement form, FP32).
  * tz_out: host [2] or NULL, receives the chosen lengths (0 = the default).
- * The result of every product is the same for every chunk length.
+ * The result of every product is the same for every chunk length.  On the
+ * plane-stress grid there is nothing to tune: tz_out receives 0, 0.
  * Synchronises `stream`.  Errors: AARMR_E_NO_WORKSPACE, AARMR_E_HIP. */
 int aarmr_autotune(aarmr_mesh* m, int32_t* tz_out, void* stream);
 

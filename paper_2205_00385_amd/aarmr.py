@@ -19,9 +19,9 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libaarmr.so")
 
 OK, E_INVALID, E_HIP, E_NOT_CONVERGED, E_SINGULAR, E_NO_WORKSPACE, E_STATE = range(7)
-MAX_RHS, MAX_LEVELS, MAX_BASIS = 8, 8, 10
+MAX_RHS, MAX_LEVELS, MAX_BASIS, MAX_SPRINGS = 8, 8, 10, 8
 FP64, FP32_REFINE = 0, 1
-FILTER_INPUT, RECORD_PARM, WARM_START, INPUT_MASKED = 1, 2, 4, 8
+FILTER_INPUT, RECORD_PARM, WARM_START, INPUT_MASKED, MUTUAL_SENS = 1, 2, 4, 8, 16
 ORTH_GS, ORTH_SVD = 0, 1
 
 
@@ -40,7 +40,7 @@ class Params(ctypes.Structure):
         ("omega", ctypes.c_double), ("cg_rtol", ctypes.c_double), ("cg_maxit", ctypes.c_int32),
         ("precision", ctypes.c_int32), ("Ns", ctypes.c_int32), ("Nm", ctypes.c_int32),
         ("ca_tol", ctypes.c_double), ("gs_tau", ctypes.c_double), ("n_rhs_max", ctypes.c_int32),
-        ("orth", ctypes.c_int32),
+        ("orth", ctypes.c_int32), ("oc_eta", ctypes.c_double),
     ]
 
 
@@ -77,7 +77,7 @@ EXPORTS = [
     "aarmr_default_params", "aarmr_mesh_create", "aarmr_mesh_destroy", "aarmr_workspace_bytes",
     "aarmr_bind_workspace", "aarmr_solve", "aarmr_ca_update", "aarmr_filter", "aarmr_setup",
     "aarmr_apply_operator", "aarmr_vcycle", "aarmr_element_energy", "aarmr_oc_update",
-    "aarmr_autotune", "aarmr_batch_solve", "aarmr_last_error",
+    "aarmr_autotune", "aarmr_batch_solve", "aarmr_set_springs", "aarmr_last_error",
 ]
 
 
@@ -107,6 +107,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.aarmr_oc_update.argtypes = [P, vp, vp, vp, dbl, dbl, vp, vp, vp]
     lib.aarmr_batch_solve.argtypes = [ctypes.POINTER(BatchItem), i32, ctypes.POINTER(P), i32]
     lib.aarmr_autotune.argtypes = [P, ctypes.POINTER(i32), vp]
+    lib.aarmr_set_springs.argtypes = [P, ctypes.POINTER(i64), ctypes.POINTER(dbl), i32]
     lib.aarmr_last_error.argtypes = []
     lib.aarmr_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
@@ -254,6 +255,13 @@ class Mesh:
         _check(lib().aarmr_autotune(self._h, out, _stream()))
         return out[0], out[1]
 
+    def set_springs(self, dofs, k):
+        """Grounded springs (host sequences of SoA DOF ids and stiffnesses)."""
+        n = len(dofs)
+        d = (ctypes.c_int64 * max(n, 1))(*[int(x) for x in dofs])
+        kk = (ctypes.c_double * max(n, 1))(*[float(x) for x in k])
+        _check(lib().aarmr_set_springs(self._h, d, kk, n))
+
     def oc_update(self, x, dc, dv, volfrac, move, x_new, rho_new):
         _check(lib().aarmr_oc_update(self._h, _ptr(x), _ptr(dc), _ptr(dv), float(volfrac),
                                      float(move), _ptr(x_new), _ptr(rho_new), _stream()))
@@ -305,6 +313,13 @@ def fixed_dofs_soa(prob, n_node: int) -> list:
         return sorted({c * n_node + i + (nx + 1) * j for (i, j, c) in prob.fixed})
     ids = sorted({c * n_node + i + (nx + 1) * (j + (ny + 1) * k) for (i, j, k, c) in prob.fixed})
     return ids
+
+
+def springs_soa(prob, n_node: int):
+    """A plane-stress problem's springs (i, j, c, k) as (SoA DOF ids, k)."""
+    nx = prob.nx
+    sp = getattr(prob, "springs", [])
+    return [c * n_node + i + (nx + 1) * j for (i, j, c, _) in sp], [k for (*_, k) in sp]
 
 
 def loads_soa(prob, n_node: int, cases: Optional[Sequence[int]] = None) -> list:

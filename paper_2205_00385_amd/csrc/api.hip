@@ -91,6 +91,7 @@ struct aarmr_mesh {
   float Bw32[576];
   bool fp32 = false;          // precision == AARMR_FP32_REFINE
   int tz64 = 0, tz32 = 0;     // tuned EbE z-chunk lengths (0: default)
+  SpringSet springs{};        // grounded springs (plane stress)
   // workspace views
   char* ws = nullptr;
   int64_t ws_bytes = 0;
@@ -553,11 +554,14 @@ int flagged_count(aarmr_mesh* m, hipStream_t s) {
 // masked transfer operators preserve that), so the fine product skips input
 // masking (mode 2); `any_input` selects the general form.
 // Fine product with moduli E (the current design's, the reference design's
-// or their difference): y = Df K(E) v for a v zero on fixed DOFs.
-int fine_product(aarmr_mesh* m, const double* E, const double* v, double* y, hipStream_t s) {
-  if (m->dim == 2)
+// or their difference): y = Df K(E) v for a v zero on fixed DOFs, plus the
+// springs unless the product is the change K - K0 (with_springs false).
+int fine_product(aarmr_mesh* m, const double* E, const double* v, double* y, hipStream_t s,
+                 bool with_springs = true) {
+  if (m->dim == 2) {
     launch_q4_apply(m->lg[0], m->KEd, E, m->mask, v, y, 2, s);
-  else
+    if (with_springs) launch_springs_add(m->springs, m->lg[0], m->mask, v, y, s);
+  } else
     launch_ebe(m->lg[0], m->wk, E, m->mask, v, y, 2, s);
   ++m->sweeps;
   KCHECK();
@@ -569,6 +573,7 @@ int apply(aarmr_mesh* m, int l, const double* v, double* y, hipStream_t s,
   if (m->dim == 2) {
     if (l == 0) {
       launch_q4_apply(m->lg[0], m->KEd, m->E, m->mask, v, y, any_input ? 0 : 2, s);
+      launch_springs_add(m->springs, m->lg[0], m->mask, v, y, s);
       ++m->sweeps;
     } else {
       launch_q4_apply_elemmat(m->lg[l], m->lv[l].Ke, v, y, s);
@@ -643,11 +648,13 @@ int setup(aarmr_mesh* m, const double* rho, const int64_t* fixed, int64_t nfixed
   if (!build_mg) return AARMR_OK;
   if (m->dim == 2) {
     launch_q4_diag(g, m->KEd, m->E, m->mask, m->lv[0].dinv, s);
+    launch_springs_diag(m->springs, g, m->mask, m->lv[0].dinv, s);
     KCHECK();
     for (int l = 1; l < m->nlev; ++l) {
-      if (l == 1)
+      if (l == 1) {
         launch_q4_galerkin_from_fine(m->lg[1], m->KEd, m->E, m->mask, m->lv[1].Ke, s);
-      else
+        launch_springs_galerkin(m->springs, m->lg[1], m->mask, m->lv[1].Ke, s);
+      } else
         launch_q4_galerkin_from_coarse(m->lg[l], m->lv[l - 1].Ke, m->lv[l].Ke, s);
       KCHECK();
       if (l < m->nlev - 1) {
@@ -1020,7 +1027,7 @@ int post_case(aarmr_mesh* m, int l, const double* rho_phys, const double* ul, do
   }
   if (want_dc) {
     if (m->dim == 2)
-      launch_q4_energy(g, m->KEd, m->mask, ul, m->ework, s);
+      launch_q4_energy(g, m->KEd, m->mask, ul, ul, m->ework, s);
     else
       launch_energy_walsh(g, m->wk, m->mask, ul, m->ework, s);
     KCHECK();
@@ -1028,6 +1035,25 @@ int post_case(aarmr_mesh* m, int l, const double* rho_phys, const double* ul, do
                     s);
     KCHECK();
   }
+  return AARMR_OK;
+}
+
+// AARMR_MUTUAL_SENS: dc = -dE/drho~ u1_e^T KE u0_e (the sensitivity of
+// f_1^T u_0 with case 1's solution as the adjoint).
+int mutual_dc(aarmr_mesh* m, const double* rho_phys, const double* u, hipStream_t s) {
+  const Grid& g = m->lg[0];
+  const int64_t n3 = ndof(m, 0);
+  launch_q4_energy(g, m->KEd, m->mask, u + n3, u, m->ework, s);
+  KCHECK();
+  launch_dc_accum(g.ne, rho_phys, m->ework, m->p.E0, m->p.Emin, m->p.penal, m->dc_tmp, 1, s);
+  KCHECK();
+  return AARMR_OK;
+}
+
+int check_mutual(const aarmr_mesh* m, int32_t n_rhs, int32_t flags) {
+  if (!(flags & AARMR_MUTUAL_SENS)) return AARMR_OK;
+  if (m->dim != 2) return fail(AARMR_E_INVALID, "AARMR_MUTUAL_SENS needs the plane-stress grid");
+  if (n_rhs != 2) return fail(AARMR_E_INVALID, "AARMR_MUTUAL_SENS needs n_rhs = 2");
   return AARMR_OK;
 }
 
@@ -1073,6 +1099,7 @@ void aarmr_default_params(aarmr_params* p) {
   p->gs_tau = 1e-10;
   p->n_rhs_max = 1;
   p->orth = AARMR_ORTH_GS;
+  p->oc_eta = 0.5;
 }
 
 int aarmr_mesh_create(const aarmr_params* p, aarmr_mesh** out) {
@@ -1094,6 +1121,7 @@ int aarmr_mesh_create(const aarmr_params* p, aarmr_mesh** out) {
     return fail(AARMR_E_INVALID, "n_rhs_max outside [1, 8]");
   if (p->orth != AARMR_ORTH_GS && p->orth != AARMR_ORTH_SVD)
     return fail(AARMR_E_INVALID, "unknown orthogonalisation");
+  if (!(p->oc_eta > 0.0 && p->oc_eta <= 1.0)) return fail(AARMR_E_INVALID, "oc_eta outside (0, 1]");
   if (!(p->nu > -1.0 && p->nu < 0.5)) return fail(AARMR_E_INVALID, "nu outside (-1, 0.5)");
   if (!(p->E0 > p->Emin && p->Emin > 0.0)) return fail(AARMR_E_INVALID, "need E0 > Emin > 0");
   if (p->cg_maxit < 1 || p->cg_maxit > kMaxIt) return fail(AARMR_E_INVALID, "cg_maxit outside [1, 4096]");
@@ -1220,7 +1248,7 @@ int aarmr_element_energy(aarmr_mesh* m, const double* u, double* energy, void* s
   TRY(need_ws(m));
   if (!u || !energy) return fail(AARMR_E_INVALID, "null argument");
   if (m->dim == 2)
-    launch_q4_energy(m->lg[0], m->KEd, m->mask, u, energy, S(stream));
+    launch_q4_energy(m->lg[0], m->KEd, m->mask, u, u, energy, S(stream));
   else
     launch_energy_walsh(m->lg[0], m->wk, m->mask, u, energy, S(stream));
   KCHECK();
@@ -1243,6 +1271,8 @@ int aarmr_solve(aarmr_mesh* m, const double* rho, const double* f, int32_t n_rhs
   TRY(check_common(m, rho, f, n_rhs, fixed_dofs, n_fixed, u));
   if ((flags & AARMR_FILTER_INPUT) && !(m->p.rmin > 0.0))
     return fail(AARMR_E_INVALID, "AARMR_FILTER_INPUT needs rmin > 0");
+  TRY(check_mutual(m, n_rhs, flags));
+  const bool mutual = (flags & AARMR_MUTUAL_SENS) != 0;
   hipStream_t s = S(stream);
   const Grid& g = m->lg[0];
   const int64_t n3 = ndof(m, 0);
@@ -1281,9 +1311,10 @@ int aarmr_solve(aarmr_mesh* m, const double* rho, const double* f, int32_t n_rhs
       st->iterations[l] = its;
       st->rel_residual[l] = rel;
     }
-    TRY(post_case(m, l, rho_phys, ul, compliance, dc != nullptr, s));
+    TRY(post_case(m, l, rho_phys, ul, compliance, dc != nullptr && !mutual, s));
     if (flags & AARMR_RECORD_PARM) TRY(push_parm(m, l, ul, s));
   }
+  if (dc && mutual) TRY(mutual_dc(m, rho_phys, u, s));
   TRY(finish_dc(m, dc, flags, s));
   HIP_TRY(hipMemcpyAsync(m->E_prev, m->E, g.ne * sizeof(double), hipMemcpyDeviceToDevice, s));
   HIP_TRY(hipStreamSynchronize(s));
@@ -1302,6 +1333,8 @@ int aarmr_ca_update(aarmr_mesh* m, const double* rho, const double* f, int32_t n
   TRY(check_common(m, rho, f, n_rhs, fixed_dofs, n_fixed, u));
   if ((flags & AARMR_FILTER_INPUT) && !(m->p.rmin > 0.0))
     return fail(AARMR_E_INVALID, "AARMR_FILTER_INPUT needs rmin > 0");
+  TRY(check_mutual(m, n_rhs, flags));
+  const bool mutual = (flags & AARMR_MUTUAL_SENS) != 0;
   if (!m->have_prev) return fail(AARMR_E_STATE, "no reference design: run aarmr_solve first");
   for (int l = 0; l < n_rhs; ++l)
     if (m->phi_count[l] < m->p.Ns) return fail(AARMR_E_STATE, "PARM of a load case is not complete");
@@ -1346,7 +1379,7 @@ int aarmr_ca_update(aarmr_mesh* m, const double* rho, const double* f, int32_t n
     HIP_TRY(hipMemcpyAsync(m->R, ul, n3 * sizeof(double), hipMemcpyDeviceToDevice, s));
     bool ca_ok = true;
     for (int i = 1; i < Nm; ++i) {
-      TRY(fine_product(m, m->dE, m->R + (i - 1) * n3, m->t0, s));
+      TRY(fine_product(m, m->dE, m->R + (i - 1) * n3, m->t0, s, false));
       std::vector<const double*> a(Ns), b(Ns);
       std::vector<double*> o(Ns);
       for (int j = 0; j < Ns; ++j) {
@@ -1466,13 +1499,37 @@ int aarmr_ca_update(aarmr_mesh* m, const double* rho, const double* f, int32_t n
       }
       TRY(push_parm(m, l, ul, s));
     }
-    TRY(post_case(m, l, rho_phys, ul, compliance, dc != nullptr, s));
+    TRY(post_case(m, l, rho_phys, ul, compliance, dc != nullptr && !mutual, s));
   }
+  if (dc && mutual) TRY(mutual_dc(m, rho_phys, u, s));
   TRY(finish_dc(m, dc, flags, s));
   HIP_TRY(hipMemcpyAsync(m->E_prev, m->E, g.ne * sizeof(double), hipMemcpyDeviceToDevice, s));
   HIP_TRY(hipStreamSynchronize(s));
   if (st) st->fine_sweeps = m->sweeps - sw0;
   if (status != AARMR_OK) return fail(status, "fallback CG reached cg_maxit before cg_rtol");
+  return AARMR_OK;
+}
+
+int aarmr_set_springs(aarmr_mesh* m, const int64_t* dofs, const double* k, int32_t n) {
+  if (!m) return fail(AARMR_E_INVALID, "null mesh");
+  if (m->dim != 2) return fail(AARMR_E_INVALID, "springs need the plane-stress grid");
+  if (n < 0 || n > AARMR_MAX_SPRINGS) return fail(AARMR_E_INVALID, "spring count outside [0, 8]");
+  if (n > 0 && (!dofs || !k)) return fail(AARMR_E_INVALID, "null spring arrays");
+  SpringSet S{};
+  const int64_t nd = ndof(m, 0);
+  for (int i = 0; i < n; ++i) {
+    if (dofs[i] < 0 || dofs[i] >= nd) return fail(AARMR_E_INVALID, "spring DOF id out of range");
+    if (!(k[i] >= 0.0)) return fail(AARMR_E_INVALID, "spring stiffness must be >= 0");
+    int j = 0;
+    while (j < S.n && S.dof[j] != dofs[i]) ++j;  // repeated ids add up
+    if (j == S.n) {
+      S.dof[S.n] = dofs[i];
+      S.k[S.n++] = 0.0;
+    }
+    S.k[j] += k[i];
+  }
+  m->springs = S;
+  m->mg_ready = false;
   return AARMR_OK;
 }
 
@@ -1492,7 +1549,7 @@ int aarmr_oc_update(aarmr_mesh* m, const double* x, const double* dc, const doub
   launch_oc_init(lam, s);
   KCHECK();
   for (int it = 0; it < 200; ++it) {
-    launch_oc_step(g.ne, x, dc, dv, m->cw, move, lam, x_new, m->partial, nparts, s);
+    launch_oc_step(g.ne, x, dc, dv, m->cw, move, m->p.oc_eta, lam, x_new, m->partial, nparts, s);
     launch_oc_bisect(lam, m->partial, nparts, target, s);
     KCHECK();
     if ((it & 15) == 15) {

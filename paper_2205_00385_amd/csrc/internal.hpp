@@ -180,8 +180,22 @@ __host__ __device__ constexpr int sym_index2(int r, int c) {
 // mode as for launch_ebe
 void launch_q4_apply(const Grid& g, const double* KE, const double* E, const uint8_t* mask,
                      const double* v, double* y, int mode, hipStream_t s);
+// energy_e = u_e^T KE w_e (w = u: strain energy)
 void launch_q4_energy(const Grid& g, const double* KE, const uint8_t* mask, const double* u,
-                      double* energy, hipStream_t s);
+                      const double* w, double* energy, hipStream_t s);
+// Grounded springs on single DOFs (passed by value to the kernels).
+struct SpringSet {
+  int n;
+  int64_t dof[AARMR_MAX_SPRINGS];
+  double k[AARMR_MAX_SPRINGS];
+};
+void launch_springs_add(const SpringSet& S, const Grid& g, const uint8_t* mask, const double* v,
+                        double* y, hipStream_t s);
+void launch_springs_diag(const SpringSet& S, const Grid& g, const uint8_t* mask, double* dinv,
+                         hipStream_t s);
+// level-1 contribution (Df P)^T S (Df P); coarse = the level-1 grid
+void launch_springs_galerkin(const SpringSet& S, const Grid& coarse, const uint8_t* mask,
+                             double* Kc, hipStream_t s);
 void launch_q4_diag(const Grid& g, const double* KE, const double* E, const uint8_t* mask,
                     double* dinv, hipStream_t s);
 // Level 1: (Df P)^T K (Df P) per parent from the fine moduli and mask.
@@ -207,8 +221,8 @@ void launch_fill_f32(int64_t n, float v, float* out, hipStream_t s);
 // One OC trial: x_new at the bisection midpoint and block partials of
 // sum_j cw_j x_new_j (nparts blocks); then the bisection step on lam.
 void launch_oc_step(int64_t ne, const double* x, const double* dc, const double* dv,
-                    const double* cw, double move, double* lam, double* xnew, double* partial,
-                    int nparts, hipStream_t s);
+                    const double* cw, double move, double eta, double* lam, double* xnew,
+                    double* partial, int nparts, hipStream_t s);
 void launch_oc_bisect(double* lam, const double* partial, int nparts, double target,
                       hipStream_t s);
 void launch_oc_init(double* lam, hipStream_t s);

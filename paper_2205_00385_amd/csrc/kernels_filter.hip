@@ -100,7 +100,7 @@ __global__ void __launch_bounds__(256) k_oc_step(int64_t ne, const double* __res
                                                  const double* __restrict__ dc,
                                                  const double* __restrict__ dv,
                                                  const double* __restrict__ cw, double move,
-                                                 const double* __restrict__ lam,
+                                                 double eta, const double* __restrict__ lam,
                                                  double* __restrict__ xnew,
                                                  double* __restrict__ partial) {
   __shared__ double red[4];
@@ -111,7 +111,7 @@ __global__ void __launch_bounds__(256) k_oc_step(int64_t ne, const double* __res
        e += (int64_t)gridDim.x * blockDim.x) {
     const double B = fmax(0.0, -dc[e]) / dv[e];
     const double xe = x[e];
-    double v = xe * sqrt(B / lmid);
+    double v = xe * (eta == 0.5 ? sqrt(B / lmid) : pow(B / lmid, eta));
     v = fmin(v, fmin(1.0, xe + move));
     v = fmax(v, fmax(0.0, xe - move));
     xnew[e] = v;
@@ -193,9 +193,9 @@ void launch_fill_f32(int64_t n, float v, float* out, hipStream_t s) {
 void launch_oc_init(double* lam, hipStream_t s) { k_oc_init<<<1, 64, 0, s>>>(lam); }
 
 void launch_oc_step(int64_t ne, const double* x, const double* dc, const double* dv,
-                    const double* cw, double move, double* lam, double* xnew, double* partial,
-                    int nparts, hipStream_t s) {
-  k_oc_step<<<nparts, 256, 0, s>>>(ne, x, dc, dv, cw, move, lam, xnew, partial);
+                    const double* cw, double move, double eta, double* lam, double* xnew,
+                    double* partial, int nparts, hipStream_t s) {
+  k_oc_step<<<nparts, 256, 0, s>>>(ne, x, dc, dv, cw, move, eta, lam, xnew, partial);
 }
 
 void launch_oc_bisect(double* lam, const double* partial, int nparts, double target,

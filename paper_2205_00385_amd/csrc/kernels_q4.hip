@@ -59,28 +59,31 @@ __global__ void __launch_bounds__(256) k_q4_apply(int nx, int ny, const double* 
   }
 }
 
-// energy_e = u_e^T KE u_e (unit modulus), fixed DOFs of u read as zero.
+// energy_e = u_e^T KE w_e (unit modulus; w = u: the strain energy), fixed
+// DOFs read as zero.
 __global__ void k_q4_energy(int nx, int ny, const double* __restrict__ KE,
                             const uint8_t* __restrict__ mask, const double* __restrict__ u,
-                            double* __restrict__ energy) {
+                            const double* __restrict__ w, double* __restrict__ energy) {
   const int64_t nn = (int64_t)(nx + 1) * (ny + 1);
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (int64_t)nx * ny) return;
   const int ex = (int)(e % nx), ey = (int)(e / nx);
-  double ue[8];
+  double ue[8], we[8];
 #pragma unroll
   for (int b = 0; b < 4; ++b) {
     const int64_t nb = (int64_t)(ex + (b & 1)) + (int64_t)(nx + 1) * (ey + (b >> 1));
     const uint8_t mb = mask[nb];
     ue[2 * b] = (mb & 1) ? 0.0 : u[nb];
     ue[2 * b + 1] = (mb & 2) ? 0.0 : u[nn + nb];
+    we[2 * b] = (mb & 1) ? 0.0 : w[nb];
+    we[2 * b + 1] = (mb & 2) ? 0.0 : w[nn + nb];
   }
   double s = 0.0;
 #pragma unroll
   for (int r = 0; r < 8; ++r) {
     double t = 0.0;
 #pragma unroll
-    for (int q = 0; q < 8; ++q) t = fma(KE[r * 8 + q], ue[q], t);
+    for (int q = 0; q < 8; ++q) t = fma(KE[r * 8 + q], we[q], t);
     s = fma(ue[r], t, s);
   }
   energy[e] = s;
@@ -204,6 +207,61 @@ __global__ void k_q4_diag_elemmat(int nx, int ny, const double* __restrict__ Ke,
   for (int c = 0; c < 2; ++c) dinv[c * nn + n] = d[c] == 0.0 ? 1.0 : 1.0 / d[c];
 }
 
+// Grounded springs (one thread each; the host merges repeated DOFs, so no
+// two threads touch one DOF).  y += k v on free spring DOFs.
+__global__ void k_springs_add(SpringSet S, int64_t nn, const uint8_t* __restrict__ mask,
+                              const double* __restrict__ v, double* __restrict__ y) {
+  const int t = threadIdx.x;
+  if (t >= S.n) return;
+  const int64_t d = S.dof[t];
+  const int64_t node = d % nn;
+  if ((mask[node] >> (int)(d / nn)) & 1) return;
+  y[d] = fma(S.k[t], v[d], y[d]);
+}
+
+// The inverse Jacobi diagonal with the spring stiffness added.
+__global__ void k_springs_diag(SpringSet S, int64_t nn, const uint8_t* __restrict__ mask,
+                               double* __restrict__ dinv) {
+  const int t = threadIdx.x;
+  if (t >= S.n) return;
+  const int64_t d = S.dof[t];
+  const int64_t node = d % nn;
+  if ((mask[node] >> (int)(d / nn)) & 1) return;
+  dinv[d] = 1.0 / (1.0 / dinv[d] + S.k[t]);
+}
+
+// (Df P)^T S (Df P) for the springs S of the fine grid, added to the level-1
+// matrices: the fine DOF of a spring interpolates from the corners of one
+// parent (any parent containing it), so k w w^T lands in that parent's
+// matrix.  One thread walks the springs in order (two may share a parent).
+__global__ void k_springs_galerkin(SpringSet S, int cnx, int cny, const uint8_t* __restrict__ mask,
+                                   double* __restrict__ Kc) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const int fnx = 2 * cnx;
+  const int64_t fnn = (int64_t)(fnx + 1) * (2 * cny + 1);
+  const int64_t cne = (int64_t)cnx * cny;
+  for (int t = 0; t < S.n; ++t) {
+    const int64_t d = S.dof[t];
+    const int64_t node = d % fnn;
+    const int c = (int)(d / fnn);
+    if ((mask[node] >> c) & 1) continue;
+    const int fi = (int)(node % (fnx + 1)), fj = (int)(node / (fnx + 1));
+    const int px = min(fi >> 1, cnx - 1), py = min(fj >> 1, cny - 1);
+    const int lx = fi - 2 * px, ly = fj - 2 * py;
+    const int64_t e = (int64_t)px + (int64_t)cnx * py;
+    for (int A = 0; A < 4; ++A) {
+      const double wa = phi1q(lx, A & 1) * phi1q(ly, A >> 1);
+      if (wa == 0.0) continue;
+      for (int B = A; B < 4; ++B) {
+        const double wb = phi1q(lx, B & 1) * phi1q(ly, B >> 1);
+        if (wb == 0.0) continue;
+        double& k = Kc[(int64_t)s2(2 * A + c, 2 * B + c) * cne + e];
+        k = fma(S.k[t] * wa, wb, k);
+      }
+    }
+  }
+}
+
 // Dense coarsest operator in SoA DOF order (c * nn + node); thread per row.
 __global__ void k_q4_assemble_dense(int nx, int ny, const double* __restrict__ Ke,
                                     double* __restrict__ A) {
@@ -236,8 +294,23 @@ void launch_q4_apply(const Grid& g, const double* KE, const double* E, const uin
 }
 
 void launch_q4_energy(const Grid& g, const double* KE, const uint8_t* mask, const double* u,
-                      double* energy, hipStream_t s) {
-  k_q4_energy<<<nblk(g.ne, 256), 256, 0, s>>>(g.nx, g.ny, KE, mask, u, energy);
+                      const double* w, double* energy, hipStream_t s) {
+  k_q4_energy<<<nblk(g.ne, 256), 256, 0, s>>>(g.nx, g.ny, KE, mask, u, w, energy);
+}
+
+void launch_springs_add(const SpringSet& S, const Grid& g, const uint8_t* mask, const double* v,
+                        double* y, hipStream_t s) {
+  if (S.n > 0) k_springs_add<<<1, 64, 0, s>>>(S, g.nn, mask, v, y);
+}
+
+void launch_springs_diag(const SpringSet& S, const Grid& g, const uint8_t* mask, double* dinv,
+                         hipStream_t s) {
+  if (S.n > 0) k_springs_diag<<<1, 64, 0, s>>>(S, g.nn, mask, dinv);
+}
+
+void launch_springs_galerkin(const SpringSet& S, const Grid& coarse, const uint8_t* mask,
+                             double* Kc, hipStream_t s) {
+  if (S.n > 0) k_springs_galerkin<<<1, 64, 0, s>>>(S, coarse.nx, coarse.ny, mask, Kc);
 }
 
 void launch_q4_diag(const Grid& g, const double* KE, const double* E, const uint8_t* mask,
