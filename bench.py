@@ -66,6 +66,7 @@ def make_loop_state(torch, aarmr, synth):
     p = aarmr.default_params(nx=NX, ny=NY, nz=NZ, rmin=RMIN, mg_levels=4, cg_rtol=1e-8,
                              cg_maxit=2000, Ns=NS, Nm=NM, ca_tol=CA_TOL)
     mesh = aarmr.Mesh(p)
+    mesh.autotune()  # launch shape of the fine-grid operator, chosen once per mesh
     dev = torch.device("cuda")
     fixed = torch.tensor(aarmr.fixed_dofs_soa(prob, mesh.n_node), dtype=torch.int64, device=dev)
     f = torch.tensor(aarmr.loads_soa(prob, mesh.n_node)[0], dtype=torch.float64, device=dev)

@@ -327,7 +327,7 @@ __device__ __forceinline__ void l1_elem(int nx, int ny, int nz, const double* __
   for (int a = 0; a < 8; ++a) Y[(int64_t)(3 * a + so) * ne + e] = y[a];
 }
 
-// Level-1 element products of the flagged parents (list[0..*count)) from their
+// Level-1 element products of the flagged parents (list[0..cnt)) from their
 // stored Galerkin matrices: one thread per (listed parent, row r).
 // Rows come from the compact copy Kcomp[entry][w] (coalesced over list entries
 // w) while the list fits its capacity, else from Ke.  Thread (w, r): lanes run
@@ -336,12 +336,10 @@ template <typename T>
 __global__ void __launch_bounds__(256) k_l1_masked(int nx, int ny, int nz,
                                                    const double* __restrict__ Ke,
                                                    const double* __restrict__ Kcomp, int cap,
-                                                   const int* __restrict__ list,
-                                                   const int* __restrict__ count,
+                                                   const int* __restrict__ list, int cnt,
                                                    const T* __restrict__ v, T* __restrict__ Y) {
   const int64_t nn = (int64_t)(nx + 1) * (ny + 1) * (nz + 1);
   const int64_t ne = (int64_t)nx * ny * nz;
-  const int64_t cnt = *count;
   const bool compact = cnt <= cap;
   const int64_t stride = (int64_t)gridDim.x * 64;
   const int r = blockIdx.y * 4 + (threadIdx.x >> 6);  // 6 x 4 waves: rows 0..23
@@ -688,16 +686,26 @@ __global__ void __launch_bounds__(256) k_gj_pivot_first(int n, int kb,
   for (int x = threadIdx.x; x < kb * kb; x += 256) Pb[x] = sS[x / kb][x % kb];
 }
 
+// 64x64 FP64 tile in LDS, row p, column i at p * 64 + (i ^ 8 (p & 3)).  An
+// MFMA operand read (lanes l: row 4kk + l/16, 16 consecutive columns) then
+// spreads its four 16-lane groups over both bank halves, two groups each:
+// two passes, the minimum for 64 doubles, without padding (two tiles fill
+// the 64 KB a workgroup may hold).
+__device__ __forceinline__ int swz(int p, int i) { return p * 64 + (i ^ ((p & 3) << 3)); }
+
 // One block per 64-row block I != K: c_I gathered from the stored upper
 // triangle, T_I = c_I P with P = Pb; writes Cb, Tb ([kb][n], index-fastest)
-// and the new cross entries of A.  Block K writes A_KK = P.
+// and the new cross entries of A.  Block K writes A_KK = P.  Every global
+// load of P and c_I is issued before the first LDS store, so the block
+// waits for memory once.
 __global__ void __launch_bounds__(256) k_gj_cross(int n, int k0, int kb,
                                                   double* __restrict__ A,
                                                   const double* __restrict__ Pb,
                                                   double* __restrict__ Tb,
                                                   double* __restrict__ Cb) {
-  __shared__ double sP[kGJBlock][kGJBlock];
-  __shared__ double sX[kGJBlock][33];
+  __shared__ double sm[2 * kGJBlock * kGJBlock];
+  double* sP = sm;                      // P[p][q]
+  double* sX = sm + kGJBlock * kGJBlock;  // c as [p][r], later T as [q][r]
   const int tid = threadIdx.x;
   const int i0 = blockIdx.x * kGJBlock;
   const int rows = (n - i0 < kGJBlock) ? (n - i0) : kGJBlock;
@@ -706,76 +714,82 @@ __global__ void __launch_bounds__(256) k_gj_cross(int n, int k0, int kb,
       A[(int64_t)(k0 + x / kb) * n + k0 + x % kb] = Pb[x];
     return;
   }
-  for (int x = tid; x < kGJBlock * kGJBlock; x += 256) {
-    const int r = x / 64, c = x % 64;
-    sP[r][c] = (r < kb && c < kb) ? Pb[r * kb + c] : 0.0;
-  }
   const bool below = i0 < k0;  // rows already pivoted
+  double pv[16], xv[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int x = tid + 256 * r, a = x >> 6, b = x & 63;
+    pv[r] = (a < kb && b < kb) ? Pb[a * kb + b] : 0.0;
+    // c(row, p): below, A[i0 + row][k0 + p] (row = a, p = b); above,
+    // A[k0 + p][i0 + row] (p = a, row = b): coalesced either way
+    if (below)
+      xv[r] = (a < rows && b < kb) ? A[(int64_t)(i0 + a) * n + k0 + b] : 0.0;
+    else
+      xv[r] = (a < kb && b < rows) ? A[(int64_t)(k0 + a) * n + i0 + b] : 0.0;
+  }
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int x = tid + 256 * r, a = x >> 6, b = x & 63;
+    sP[swz(a, b)] = pv[r];
+    sX[below ? swz(b, a) : swz(a, b)] = xv[r];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int x = tid + 256 * r, p = x >> 6, row = x & 63;
+    if (p < kb && row < rows) Cb[(int64_t)p * n + i0 + row] = sX[swz(p, row)];
+  }
+  // T[16w + i][16jb + j] = sum_p c[16w + i][p] P[p][16jb + j]
   const int w = tid >> 6, l = tid & 63, li = l & 15, lk = l >> 4;
   f64x4 acc[4];
 #pragma unroll
   for (int jb = 0; jb < 4; ++jb) acc[jb] = f64x4{0.0, 0.0, 0.0, 0.0};
-  for (int h = 0; h < 2; ++h) {  // c columns [32h, 32h + 32)
-    for (int t = tid; t < kGJBlock * 32; t += 256) {
-      int r, q;
-      if (below) { r = t / 32; q = t % 32; } else { q = t / 64; r = t % 64; }
-      const int p = 32 * h + q;
-      double v = 0.0;
-      if (r < rows && p < kb)
-        v = below ? A[(int64_t)(i0 + r) * n + (k0 + p)] : A[(int64_t)(k0 + p) * n + (i0 + r)];
-      sX[r][q] = v;
-    }
-    __syncthreads();
-    for (int t = tid; t < kGJBlock * 32; t += 256) {
-      const int q = t / 64, r = t % 64, p = 32 * h + q;
-      if (r < rows && p < kb) Cb[(int64_t)p * n + i0 + r] = sX[r][q];
-    }
-    // T[16w + i][16jb + j] += sum_q c[16w + i][32h + q] P[32h + q][16jb + j]
 #pragma unroll
-    for (int kk = 0; kk < 8; ++kk) {
-      const double a = sX[16 * w + li][4 * kk + lk];
+  for (int kk = 0; kk < 16; ++kk) {
+    const int p = 4 * kk + lk;
+    const double a = sX[swz(p, 16 * w + li)];
 #pragma unroll
-      for (int jb = 0; jb < 4; ++jb) {
-        const double b = sP[32 * h + 4 * kk + lk][16 * jb + li];
-        acc[jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[jb], 0, 0, 0);
-      }
-    }
-    __syncthreads();
+    for (int jb = 0; jb < 4; ++jb)
+      acc[jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, sP[swz(p, 16 * jb + li)], acc[jb], 0, 0, 0);
   }
-  // acc[jb][v] = T[16w + lk + 4v][16jb + li]; stage 32 columns at a time
-  for (int h = 0; h < 2; ++h) {
+  __syncthreads();
+  // acc[jb][v] = T[16w + lk + 4v][16jb + li]; stage as [q][row]
 #pragma unroll
-    for (int jj = 0; jj < 2; ++jj)
+  for (int jb = 0; jb < 4; ++jb)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) sX[16 * w + lk + 4 * v][16 * jj + li] = acc[2 * h + jj][v];
-    __syncthreads();
-    for (int t = tid; t < kGJBlock * 32; t += 256) {
-      const int q = t / 64, r = t % 64, p = 32 * h + q;
-      if (r < rows && p < kb) Tb[(int64_t)p * n + i0 + r] = sX[r][q];
+    for (int v = 0; v < 4; ++v) sX[swz(16 * jb + li, 16 * w + lk + 4 * v)] = acc[jb][v];
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int x = tid + 256 * r, q = x >> 6, row = x & 63;
+    if (q < kb && row < rows) {
+      const double t = sX[swz(q, row)];
+      Tb[(int64_t)q * n + i0 + row] = t;
+      if (!below) A[(int64_t)(k0 + q) * n + i0 + row] = t;
     }
-    for (int t = tid; t < kGJBlock * 32; t += 256) {
-      int r, q;
-      if (below) { r = t / 32; q = t % 32; } else { q = t / 64; r = t % 64; }
-      const int p = 32 * h + q;
-      if (r < rows && p < kb) {
-        if (below) A[(int64_t)(i0 + r) * n + (k0 + p)] = -sX[r][q];
-        else A[(int64_t)(k0 + p) * n + (i0 + r)] = sX[r][q];
-      }
+  }
+  if (below) {  // A[i0 + row][k0 + q] = -T[row][q], coalesced along q
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int x = tid + 256 * r, row = x >> 6, q = x & 63;
+      if (q < kb && row < rows) A[(int64_t)(i0 + row) * n + k0 + q] = -sX[swz(q, row)];
     }
-    __syncthreads();
   }
 }
 
 // Upper tiles (bi <= bj) outside K: A_IJ -= s_J T_I C_J^T on 64x64 tiles with
-// FP64 MFMA (wave w: rows 16w..16w+15, four 16x16 accumulators), operands
-// read straight from Tb and Cb.  Block 0 takes the next diagonal tile
-// (K+1, K+1) and then inverts it into Pb, the pivot of the next step.
+// FP64 MFMA (wave w: rows 16w..16w+15, four 16x16 accumulators that start
+// from A_IJ).  T_I and C_J are staged in LDS with all loads in flight at
+// once.  Block 0 takes the next diagonal tile (K+1, K+1) and then inverts it
+// into Pb, the pivot of the next step.
 __global__ void __launch_bounds__(256) k_gj_update(int n, int k0, int kb, int nb,
                                                    double* __restrict__ A,
                                                    double* __restrict__ Pb,
                                                    const double* __restrict__ Tb,
                                                    const double* __restrict__ Cb) {
-  __shared__ double sS[kGJBlock][kGJBlock + 1];
+  __shared__ double sm[2 * kGJBlock * kGJBlock];
+  double* sT = sm;
+  double* sC = sm + kGJBlock * kGJBlock;
   const int kblk = k0 / kGJBlock;
   const bool has_next = kblk + 1 < nb;
   int bi, bj;
@@ -795,49 +809,60 @@ __global__ void __launch_bounds__(256) k_gj_update(int n, int k0, int kb, int nb
     if (bi == kblk || bj == kblk) return;
   }
   const int I0 = bi * kGJBlock, J0 = bj * kGJBlock;
-  const double sgn = (J0 < k0) ? -1.0 : 1.0;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   const int li = lane & 15, lk = lane >> 4;
-  const int row = I0 + 16 * w + li;
-  f64x4 acc[4];
+  double tv[16], cv[16];
 #pragma unroll
-  for (int jb = 0; jb < 4; ++jb) acc[jb] = f64x4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll 4
-  for (int p = 0; p < kb; p += 4) {
-    const int pk = p + lk;
-    const bool pin = pk < kb;
-    const double av = (pin && row < n) ? Tb[(int64_t)pk * n + row] : 0.0;
-#pragma unroll
-    for (int jb = 0; jb < 4; ++jb) {
-      const int col = J0 + 16 * jb + li;
-      const double bv = (pin && col < n) ? Cb[(int64_t)pk * n + col] : 0.0;
-      acc[jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[jb], 0, 0, 0);
-    }
+  for (int r = 0; r < 16; ++r) {
+    const int x = tid + 256 * r, p = x >> 6, i = x & 63;
+    tv[r] = (p < kb && I0 + i < n) ? Tb[(int64_t)p * n + I0 + i] : 0.0;
+    cv[r] = (p < kb && J0 + i < n) ? Cb[(int64_t)p * n + J0 + i] : 0.0;
   }
   // accumulator layout: lane l, element v -> row l/16 + 4v, column l%16 of
   // the 16x16 block (operands: A[l%16][l/16], B[l/16][l%16])
-  const bool diag_next = (blockIdx.x == 0);
+  f64x4 acc[4];
 #pragma unroll
-  for (int jb = 0; jb < 4; ++jb) {
+  for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = I0 + 16 * w + lk + 4 * v, j = J0 + 16 * jb + li;
+      acc[jb][v] = (i < n && j < n) ? A[(int64_t)i * n + j] : 0.0;
+    }
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int x = tid + 256 * r, p = x >> 6, i = x & 63;
+    sT[swz(p, i)] = tv[r];
+    sC[swz(p, i)] = cv[r];
+  }
+  __syncthreads();
+  const double ns = (J0 < k0) ? 1.0 : -1.0;  // -s_J
+#pragma unroll
+  for (int kk = 0; kk < 16; ++kk) {
+    const int p = 4 * kk + lk;
+    const double a = ns * sT[swz(p, 16 * w + li)];
+#pragma unroll
+    for (int jb = 0; jb < 4; ++jb)
+      acc[jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, sC[swz(p, 16 * jb + li)], acc[jb], 0, 0, 0);
+  }
+#pragma unroll
+  for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = I0 + 16 * w + lk + 4 * v, j = J0 + 16 * jb + li;
+      if (i < n && j < n) A[(int64_t)i * n + j] = acc[jb][v];
+    }
+  if (blockIdx.x != 0) return;
+  // next pivot block: the tile just updated, identity beyond the matrix
+  double (*sS)[kGJBlock + 1] = reinterpret_cast<double (*)[kGJBlock + 1]>(sm);
+  const int kbn = (n - I0 < kGJBlock) ? (n - I0) : kGJBlock;
+  __syncthreads();
+#pragma unroll
+  for (int jb = 0; jb < 4; ++jb)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int ti = 16 * w + lk + 4 * v, tj = 16 * jb + li;
-      const int i = I0 + ti, j = J0 + tj;
-      double val = 0.0;
-      if (i < n && j < n) {
-        val = fma(-sgn, acc[jb][v], A[(int64_t)i * n + j]);
-        A[(int64_t)i * n + j] = val;
-      }
-      if (diag_next) sS[ti][tj] = val;
+      sS[ti][tj] = (ti < kbn && tj < kbn) ? acc[jb][v] : (ti == tj ? 1.0 : 0.0);
     }
-  }
-  if (!diag_next) return;
-  const int kbn = (n - I0 < kGJBlock) ? (n - I0) : kGJBlock;
-  __syncthreads();
-  for (int x = threadIdx.x; x < kGJBlock * kGJBlock; x += 256) {
-    const int r = x / 64, c = x % 64;
-    if (r >= kbn || c >= kbn) sS[r][c] = (r == c) ? 1.0 : 0.0;
-  }
   __syncthreads();
   gj64_block(sS);
   for (int x = threadIdx.x; x < kbn * kbn; x += 256) Pb[x] = sS[x / kbn][x % kbn];
@@ -911,7 +936,7 @@ void l1_apply(const Grid& g, const double* Ke, const double* Kcomp, int cap, con
   k_l1_elem<T><<<dim3(nblk(g.ne, 256), 3), 256, 0, s>>>(g.nx, g.ny, g.nz, Ke, Bw, Ef, eflag, v, Y);
   if (nflag > 0) {  // nflag: the flagged-parent count, known to the host after setup
     const unsigned mb = (unsigned)std::min<int64_t>(nblk(nflag, 64), 256);
-    k_l1_masked<T><<<dim3(mb, 6), 256, 0, s>>>(g.nx, g.ny, g.nz, Ke, Kcomp, cap, list, count, v, Y);
+    k_l1_masked<T><<<dim3(mb, 6), 256, 0, s>>>(g.nx, g.ny, g.nz, Ke, Kcomp, cap, list, nflag, v, Y);
   }
   k_l1_gather<T><<<nblk(g.nn, 256), 256, 0, s>>>(g.nx, g.ny, g.nz, Y, y);
 }
