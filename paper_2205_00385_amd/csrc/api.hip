@@ -60,7 +60,7 @@ constexpr int SC_TOTAL = SC_MISC + 512;
 // misc slots
 constexpr int M_FF = 0, M_RR0 = 1, M_NRM = 2, M_C = 3, M_EPS = 4, M_VOL = 5;
 constexpr int M_RR64 = 6;      // FP64 residual norm^2 of a refinement step
-constexpr int M_OC = 8;        // 4 slots: l1, l2, lmid, done
+constexpr int M_OC = 8;        // 5 slots: l1, l2, lmid, done, steps
 constexpr int M_KPHI = 16;     // Ns*Ns
 constexpr int M_G = 120;       // Ns  (Phi^T dK r)
 constexpr int M_C2 = 132;      // Ns  (K_Phi^-1 g)
@@ -137,6 +137,7 @@ struct aarmr_mesh {
   bool have_prev = false;
   bool mg_ready = false;
   double* hpin = nullptr;  // pinned host staging
+  hipEvent_t ev_cg = nullptr;  // marks a CG iteration's scalar read-back
   int64_t sweeps = 0;
 };
 
@@ -596,7 +597,14 @@ int apply(aarmr_mesh* m, int l, const double* v, double* y, hipStream_t s,
 }
 
 // One V-cycle (Algorithm 2) on level l from a zero initial guess: x = M_l^-1 b.
-int vcycle(aarmr_mesh* m, int l, const double* b, double* x, hipStream_t s) {
+// x_init: x already holds the first pre-smoothing sweep omega D^-1 b (formed
+// by the kernel that produced b).  On the 3D hierarchy the sweeps are fused
+// into neighbouring kernels: the restriction forms the coarse level's first
+// sweep, and below the finest level the last post-smoothing sweep is the
+// epilogue of its operator product.  On levels >= 2 that product writes into
+// L.t and the level's x and t buffers swap roles, so there x must be L.x.
+int vcycle(aarmr_mesh* m, int l, const double* b, double* x, hipStream_t s,
+           bool x_init = false) {
   if (l == m->nlev - 1) {
     launch_gemv(m->nc, m->Ainv, b, x, s);
     KCHECK();
@@ -608,26 +616,46 @@ int vcycle(aarmr_mesh* m, int l, const double* b, double* x, hipStream_t s) {
   LevelBuf& C = m->lv[l + 1];
   const uint8_t* mask = (l == 0) ? m->mask : nullptr;
   const double om = m->p.omega;
+  const bool fuse = m->dim == 3;
+  const bool child_first = fuse && m->p.nu_pre >= 1 && l + 1 < m->nlev - 1;
   if (m->p.nu_pre >= 1) {
-    launch_jacobi_first(n3, b, L.dinv, om, x, s);  // line 1, first sweep from zero
-    KCHECK();
+    if (!x_init) {
+      launch_jacobi_first(n3, b, L.dinv, om, x, s);  // line 1, first sweep from zero
+      KCHECK();
+    }
     for (int it = 1; it < m->p.nu_pre; ++it) {
       TRY(apply(m, l, x, L.t, s));
       launch_jacobi_update(n3, b, L.t, L.dinv, om, x, s);
       KCHECK();
     }
     TRY(apply(m, l, x, L.t, s));  // line 2: residual, restricted
-    launch_restrict(m->lg[l + 1], b, L.t, mask, C.b, s, m->dim);
+    if (child_first)
+      launch_restrict_jacobi(m->lg[l + 1], b, L.t, mask, C.b, C.dinv, om, C.x, s);
+    else
+      launch_restrict(m->lg[l + 1], b, L.t, mask, C.b, s, m->dim);
   } else {
     HIP_TRY(hipMemsetAsync(x, 0, n3 * sizeof(double), s));
     HIP_TRY(hipMemsetAsync(L.t, 0, n3 * sizeof(double), s));
     launch_restrict(m->lg[l + 1], b, L.t, mask, C.b, s, m->dim);
   }
   KCHECK();
-  TRY(vcycle(m, l + 1, C.b, C.x, s));            // line 3
-  launch_prolong_add(G, C.x, mask, x, s, m->dim); // line 4
+  TRY(vcycle(m, l + 1, C.b, C.x, s, child_first));  // line 3
+  launch_prolong_add(G, C.x, mask, x, s, m->dim);    // line 4
   KCHECK();
-  for (int it = 0; it < m->p.nu_post; ++it) {     // line 5
+  for (int it = 0; it < m->p.nu_post; ++it) {        // line 5
+    if (fuse && l >= 1 && it == m->p.nu_post - 1) {
+      if (l == 1) {
+        TRY(flagged_count(m, s));
+        launch_apply_l1_jacobi(m->lg[1], L.Ke, m->Kcomp1, m->cap1, m->Bwd, m->E, m->eflag1,
+                               m->list1, m->count1, m->nflag1, x, m->Y1, b, L.dinv, om, s);
+      } else {
+        if (x != L.x) return fail(AARMR_E_STATE, "V-cycle iterate is not the level's buffer");
+        launch_apply_elemmat_jacobi(G, L.Ke, x, b, L.dinv, om, L.t, s);
+        std::swap(L.x, L.t);
+      }
+      KCHECK();
+      continue;
+    }
     TRY(apply(m, l, x, L.t, s));
     launch_jacobi_update(n3, b, L.t, L.dinv, om, x, s);
     KCHECK();
@@ -961,6 +989,45 @@ int pcg64(aarmr_mesh* m, double* x, int* iters, double* relres, int maxit_in, bo
   TRY(dot1(m, m->r, m->z, sc + SC_RZ, n3, s));
   HIP_TRY(hipMemcpyAsync(m->pv, m->z, n3 * sizeof(double), hipMemcpyDeviceToDevice, s));
   const int maxit = std::max(0, maxit_in);
+  if (!use32) {
+    // reductions folded into the updates: p^T q finished by the x/r update,
+    // r^T r summed on the host from its block partials, r^T z finished by the
+    // p update; the update also forms the V-cycle's first sweep.  While the
+    // host waits for r^T r, the GPU already runs the next preconditioner and
+    // direction update: they read r and write only z and p, so when the
+    // iteration turns out to be the last, x and r are final and that work is
+    // simply unused.
+    double* part_pq = m->partial;
+    double* part_rz = m->partial + kRedBlocks;
+    double* part_rr = m->partial + 2 * kRedBlocks;
+    const int nb = dot_blocks(n3);
+    const bool z0 = m->p.nu_pre >= 1;
+    double* hrr = m->hpin + 1024;
+    for (int it = 0; it < maxit; ++it) {
+      TRY(apply(m, 0, m->pv, m->q, s));
+      launch_dot_partials(n3, m->pv, m->q, part_pq, s);
+      launch_cg_xr_fused(n3, sc + SC_RZ + it, part_pq, sc + SC_PQ + it, x, m->r, m->pv, m->q,
+                         part_rr, m->lv[0].dinv, m->p.omega, z0 ? m->z : nullptr, s);
+      KCHECK();
+      HIP_TRY(hipMemcpyAsync(m->hpin + 1, sc + SC_PQ + it, sizeof(double), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipMemcpyAsync(hrr, part_rr, nb * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipEventRecord(m->ev_cg, s));
+      if (it + 1 < maxit) {
+        TRY(vcycle(m, 0, m->r, m->z, s, z0));
+        launch_dot_partials(n3, m->r, m->z, part_rz, s);
+        launch_cg_p_fused(n3, part_rz, sc + SC_RZ + it + 1, sc + SC_RZ + it, m->z, m->pv, s);
+        KCHECK();
+      }
+      HIP_TRY(hipEventSynchronize(m->ev_cg));
+      rr = 0.0;
+      for (int b = 0; b < nb; ++b) rr += hrr[b];
+      *iters = it + 1;
+      *relres = std::sqrt(rr / ff);
+      if (!(m->hpin[1] > 0.0)) return fail(AARMR_E_SINGULAR, "CG: p^T A p <= 0");
+      if (rr <= tol2) return AARMR_OK;
+    }
+    return fail(AARMR_E_NOT_CONVERGED, "CG reached cg_maxit before cg_rtol");
+  }
   for (int it = 0; it < maxit; ++it) {
     TRY(apply(m, 0, m->pv, m->q, s));
     TRY(dot1(m, m->pv, m->q, sc + SC_PQ + it, n3, s));
@@ -1171,6 +1238,7 @@ int aarmr_mesh_create(const aarmr_params* p, aarmr_mesh** out) {
 void aarmr_mesh_destroy(aarmr_mesh* m) {
   if (!m) return;
   if (m->hpin) (void)hipHostFree(m->hpin);
+  if (m->ev_cg) (void)hipEventDestroy(m->ev_cg);
   delete m;
 }
 
@@ -1178,6 +1246,7 @@ int64_t aarmr_workspace_bytes(const aarmr_mesh* m) {
   if (!m) return -1;
   aarmr_mesh tmp = *m;
   tmp.hpin = nullptr;
+  tmp.ev_cg = nullptr;
   return layout(&tmp, nullptr);
 }
 
@@ -1187,6 +1256,7 @@ int aarmr_bind_workspace(aarmr_mesh* m, void* dev_ptr, int64_t bytes, void* stre
   const int64_t need = layout(m, nullptr);
   if (bytes < need) return fail(AARMR_E_NO_WORKSPACE, "workspace too small");
   if (!m->hpin) HIP_TRY(hipHostMalloc((void**)&m->hpin, 4096 * sizeof(double), hipHostMallocDefault));
+  if (!m->ev_cg) HIP_TRY(hipEventCreateWithFlags(&m->ev_cg, hipEventDisableTiming));
   m->ws = static_cast<char*>(dev_ptr);
   m->ws_bytes = bytes;
   layout(m, m->ws);
@@ -1548,17 +1618,21 @@ int aarmr_oc_update(aarmr_mesh* m, const double* x, const double* dc, const doub
   const int nparts = kRedBlocks;
   launch_oc_init(lam, s);
   KCHECK();
-  for (int it = 0; it < 200; ++it) {
-    launch_oc_step(g.ne, x, dc, dv, m->cw, move, m->p.oc_eta, lam, x_new, m->partial, nparts, s);
-    launch_oc_bisect(lam, m->partial, nparts, target, s);
+  // three bisection steps per launch pair, 200 at most (the kernels count
+  // them); the done flag is read every 12 steps
+  for (int it = 0; it < 67; ++it) {
+    launch_oc_step3(g.ne, x, dc, dv, m->cw, move, m->p.oc_eta, lam, m->partial, nparts, s);
+    launch_oc_bisect3(lam, m->partial, nparts, target, s);
     KCHECK();
-    if ((it & 15) == 15) {
+    if ((it & 3) == 3) {
       double done;
       const double* src = lam + 3;
       TRY(read_scalars(m, &src, 1, &done, s));
       if (done != 0.0) break;
     }
   }
+  launch_oc_final(g.ne, x, dc, dv, move, m->p.oc_eta, lam, x_new, s);
+  KCHECK();
   launch_filter(m->fg, m->p.rmin, m->Wf, 0, m->Hs, x_new, rho_phys_new, s);
   KCHECK();
   return AARMR_OK;

@@ -115,6 +115,19 @@ void launch_prolong_add(const Grid& fine, const double* xc, const uint8_t* mask,
                         hipStream_t s, int ncomp = 3);
 void launch_jacobi_first(int64_t n3, const double* b, const double* dinv, double omega, double* x,
                          hipStream_t s);
+// Fused damped-Jacobi sweeps (3D hierarchy): restriction that also forms the
+// coarse level's first sweep xc = omega dinv_c bc; the level-1 product that
+// ends in x += omega dinv (b - A x) in place; the stored-matrix product that
+// writes out = v + omega dinv (b - A v) (out distinct from v).
+void launch_restrict_jacobi(const Grid& coarse, const double* bf, const double* tf,
+                            const uint8_t* mask, double* bc, const double* dinv_c, double omega,
+                            double* xc, hipStream_t s);
+void launch_apply_l1_jacobi(const Grid& g, const double* Ke, const double* Kcomp, int cap,
+                            const double* Bw, const double* Ef, const uint8_t* eflag,
+                            const int* list, const int* count, int nflag, double* x, double* Y,
+                            const double* b, const double* dinv, double omega, hipStream_t s);
+void launch_apply_elemmat_jacobi(const Grid& g, const double* Ke, const double* v, const double* b,
+                                 const double* dinv, double omega, double* out, hipStream_t s);
 void launch_jacobi_update(int64_t n3, const double* b, const double* t, const double* dinv,
                           double omega, double* x, hipStream_t s);
 void launch_assemble_dense(const Grid& g, const double* Ke, double* A, hipStream_t s);
@@ -156,6 +169,21 @@ void launch_cg_xr(int64_t n, const double* rz, const double* pq, double* x, doub
                   const double* p, const double* q, hipStream_t s);
 void launch_cg_p(int64_t n, const double* rz_new, const double* rz_old, const double* z,
                  double* p, hipStream_t s);
+// CG with folded reductions.  dot_blocks(n): the block count of one dot's
+// partials (and of the fused updates that finish them); launch_dot_partials
+// writes a^T b's partials to part[0..dot_blocks(n)).
+int dot_blocks(int64_t n);
+void launch_dot_partials(int64_t n, const double* a, const double* b, double* part,
+                         hipStream_t s);
+// pq finished from pq_part (stored to *pq); x += alpha p, r -= alpha q with
+// alpha = *rz / pq; rr_part[0..dot_blocks(n)) = partials of r^T r;
+// z0 = omega dinv r unless z0 is null.
+void launch_cg_xr_fused(int64_t n, const double* rz, const double* pq_part, double* pq, double* x,
+                        double* r, const double* p, const double* q, double* rr_part,
+                        const double* dinv, double omega, double* z0, hipStream_t s);
+// rz_new finished from rz_part (stored to *rz_new); p = z + (rz_new / *rz_old) p.
+void launch_cg_p_fused(int64_t n, const double* rz_part, double* rz_new, const double* rz_old,
+                       const double* z, double* p, hipStream_t s);
 void launch_scale_by_inv_sqrt(int64_t n, const double* src, const double* nrm2, double* dst,
                               hipStream_t s);
 // out = sum_j coef[j] * V_j (+ add) with coefficients read from device memory
@@ -218,13 +246,17 @@ void launch_filter(const Grid& g, double r, const double* W, int mode, const dou
                    const double* in, double* out, hipStream_t s);
 void launch_fill(int64_t n, double v, double* out, hipStream_t s);
 void launch_fill_f32(int64_t n, float v, float* out, hipStream_t s);
-// One OC trial: x_new at the bisection midpoint and block partials of
-// sum_j cw_j x_new_j (nparts blocks); then the bisection step on lam.
-void launch_oc_step(int64_t ne, const double* x, const double* dc, const double* dv,
-                    const double* cw, double move, double eta, double* lam, double* xnew,
-                    double* partial, int nparts, hipStream_t s);
-void launch_oc_bisect(double* lam, const double* partial, int nparts, double target,
-                      hipStream_t s);
+// OC bisection, three levels per launch pair: block partials of the volume
+// sum_j cw_j x_new_j for the seven multipliers three levels can visit
+// (nparts blocks), then the bisection steps on lam; x_new at the last
+// multiplier evaluated.
+void launch_oc_step3(int64_t ne, const double* x, const double* dc, const double* dv,
+                     const double* cw, double move, double eta, const double* lam,
+                     double* partial, int nparts, hipStream_t s);
+void launch_oc_bisect3(double* lam, const double* partial, int nparts, double target,
+                       hipStream_t s);
+void launch_oc_final(int64_t ne, const double* x, const double* dc, const double* dv, double move,
+                     double eta, const double* lam, double* xnew, hipStream_t s);
 void launch_oc_init(double* lam, hipStream_t s);
 
 }  // namespace aarmr

@@ -83,63 +83,113 @@ __global__ void __launch_bounds__(256) k_filter(int nx, int ny, int nz, int Rrt,
   out[e] = mode == 0 ? s / Hs[e] : s;
 }
 
-// lam[0] = l1, lam[1] = l2, lam[2] = current midpoint, lam[3] = done flag.
+// lam[0] = l1, lam[1] = l2, lam[2] = current midpoint, lam[3] = done flag,
+// lam[4] = bisection steps taken (at most 200).
 __global__ void k_oc_init(double* lam) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     lam[0] = 0.0;
     lam[1] = 1e9;
     lam[2] = 0.5e9;
     lam[3] = 0.0;
+    lam[4] = 0.0;
   }
 }
 
-// x_new for the midpoint of lam and block partials of sum_j c_j x_new_j,
-// the volume of the filtered x_new (c = H^T (1 / Hs), the column weights of
-// the normalised filter).
-__global__ void __launch_bounds__(256) k_oc_step(int64_t ne, const double* __restrict__ x,
-                                                 const double* __restrict__ dc,
-                                                 const double* __restrict__ dv,
-                                                 const double* __restrict__ cw, double move,
-                                                 double eta, const double* __restrict__ lam,
-                                                 double* __restrict__ xnew,
-                                                 double* __restrict__ partial) {
-  __shared__ double red[4];
+// The OC update of one element at multiplier lmid.
+__device__ inline double oc_x(double xe, double B, double lmid, double move, double eta) {
+  double v = xe * (eta == 0.5 ? sqrt(B / lmid) : pow(B / lmid, eta));
+  v = fmin(v, fmin(1.0, xe + move));
+  return fmax(v, fmax(0.0, xe - move));
+}
+
+// Three bisection levels per launch.  The seven multipliers a three-level
+// bisection of [lam[0], lam[1]] can visit, in heap order (t: midpoint;
+// 2t + 1: its left half's midpoint, 2t + 2: its right half's), computed with
+// the same expressions the one-level steps would use; for each, block
+// partials of sum_j c_j x_new_j, the volume of the filtered x_new (c =
+// H^T (1 / Hs), the column weights of the normalised filter), in the
+// summation order of a one-level step, so every decision is bitwise the one
+// the one-level bisection takes.
+__global__ void __launch_bounds__(256) k_oc_step3(int64_t ne, const double* __restrict__ x,
+                                                  const double* __restrict__ dc,
+                                                  const double* __restrict__ dv,
+                                                  const double* __restrict__ cw, double move,
+                                                  double eta, const double* __restrict__ lam,
+                                                  double* __restrict__ partial) {
+  __shared__ double red[7][4];
   if (lam[3] != 0.0) return;  // block-uniform
-  const double lmid = 0.5 * (lam[0] + lam[1]);
-  double acc = 0.0;
+  const double l1 = lam[0], l2 = lam[1];
+  double lm[7];
+  lm[0] = 0.5 * (l1 + l2);
+  lm[1] = 0.5 * (l1 + lm[0]);
+  lm[2] = 0.5 * (lm[0] + l2);
+  lm[3] = 0.5 * (l1 + lm[1]);
+  lm[4] = 0.5 * (lm[1] + lm[0]);
+  lm[5] = 0.5 * (lm[0] + lm[2]);
+  lm[6] = 0.5 * (lm[2] + l2);
+  double acc[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < ne;
        e += (int64_t)gridDim.x * blockDim.x) {
     const double B = fmax(0.0, -dc[e]) / dv[e];
-    const double xe = x[e];
-    double v = xe * (eta == 0.5 ? sqrt(B / lmid) : pow(B / lmid, eta));
-    v = fmin(v, fmin(1.0, xe + move));
-    v = fmax(v, fmax(0.0, xe - move));
-    xnew[e] = v;
-    acc = fma(cw[e], v, acc);
+    const double xe = x[e], c = cw[e];
+#pragma unroll
+    for (int t = 0; t < 7; ++t) acc[t] = fma(c, oc_x(xe, B, lm[t], move, eta), acc[t]);
   }
-  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+#pragma unroll
+  for (int t = 0; t < 7; ++t) {
+    double a = acc[t];
+    for (int off = 32; off > 0; off >>= 1) a += __shfl_down(a, off, 64);
+    if ((threadIdx.x & 63) == 0) red[t][threadIdx.x >> 6] = a;
+  }
   __syncthreads();
-  if (threadIdx.x == 0) partial[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+  if (threadIdx.x < 7) {
+    const int t = threadIdx.x;
+    partial[t * kRedBlocks + blockIdx.x] = (red[t][0] + red[t][1]) + (red[t][2] + red[t][3]);
+  }
 }
 
-// Sum the nparts partials in a fixed order, then one bisection step on lam.
-__global__ void __launch_bounds__(256) k_oc_bisect(double* lam, const double* __restrict__ partial,
-                                                   int nparts, double target) {
+// The volumes of the seven multipliers (partials summed in a fixed order),
+// then up to three bisection steps along the path the decisions take; lam[2]
+// records the last multiplier evaluated, lam[3] = 1 once (l2-l1)/(l1+l2) <= 1e-3
+// or after the 200th step.
+__global__ void __launch_bounds__(256) k_oc_bisect3(double* lam, const double* __restrict__ partial,
+                                                    int nparts, double target) {
   __shared__ double red[4];
+  __shared__ double vol[7];
   if (lam[3] != 0.0) return;
-  double acc = 0.0;
-  for (int b = threadIdx.x; b < nparts; b += 256) acc += partial[b];
-  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
-  __syncthreads();
+  for (int t = 0; t < 7; ++t) {
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < nparts; b += 256) acc += partial[t * kRedBlocks + b];
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) vol[t] = (red[0] + red[1]) + (red[2] + red[3]);
+    __syncthreads();
+  }
   if (threadIdx.x != 0) return;
-  const double vol = (red[0] + red[1]) + (red[2] + red[3]);
-  const double lmid = 0.5 * (lam[0] + lam[1]);
-  lam[2] = lmid;
-  if (vol > target) lam[0] = lmid;
-  else lam[1] = lmid;
-  if ((lam[1] - lam[0]) / (lam[0] + lam[1]) <= 1e-3) lam[3] = 1.0;
+  int t = 0;
+  for (int level = 0; level < 3 && lam[3] == 0.0; ++level) {
+    const double lmid = 0.5 * (lam[0] + lam[1]);
+    lam[2] = lmid;
+    if (vol[t] > target) {
+      lam[0] = lmid;
+      t = 2 * t + 2;
+    } else {
+      lam[1] = lmid;
+      t = 2 * t + 1;
+    }
+    lam[4] += 1.0;
+    if ((lam[1] - lam[0]) / (lam[0] + lam[1]) <= 1e-3 || lam[4] >= 200.0) lam[3] = 1.0;
+  }
+}
+
+// x_new at the last multiplier the bisection evaluated.
+__global__ void k_oc_final(int64_t ne, const double* __restrict__ x, const double* __restrict__ dc,
+                           const double* __restrict__ dv, double move, double eta,
+                           const double* __restrict__ lam, double* __restrict__ xnew) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ne) return;
+  xnew[e] = oc_x(x[e], fmax(0.0, -dc[e]) / dv[e], lam[2], move, eta);
 }
 
 template <typename T>
@@ -192,15 +242,20 @@ void launch_fill_f32(int64_t n, float v, float* out, hipStream_t s) {
 
 void launch_oc_init(double* lam, hipStream_t s) { k_oc_init<<<1, 64, 0, s>>>(lam); }
 
-void launch_oc_step(int64_t ne, const double* x, const double* dc, const double* dv,
-                    const double* cw, double move, double eta, double* lam, double* xnew,
-                    double* partial, int nparts, hipStream_t s) {
-  k_oc_step<<<nparts, 256, 0, s>>>(ne, x, dc, dv, cw, move, eta, lam, xnew, partial);
+void launch_oc_step3(int64_t ne, const double* x, const double* dc, const double* dv,
+                     const double* cw, double move, double eta, const double* lam,
+                     double* partial, int nparts, hipStream_t s) {
+  k_oc_step3<<<nparts, 256, 0, s>>>(ne, x, dc, dv, cw, move, eta, lam, partial);
 }
 
-void launch_oc_bisect(double* lam, const double* partial, int nparts, double target,
-                      hipStream_t s) {
-  k_oc_bisect<<<1, 256, 0, s>>>(lam, partial, nparts, target);
+void launch_oc_bisect3(double* lam, const double* partial, int nparts, double target,
+                       hipStream_t s) {
+  k_oc_bisect3<<<1, 256, 0, s>>>(lam, partial, nparts, target);
+}
+
+void launch_oc_final(int64_t ne, const double* x, const double* dc, const double* dv, double move,
+                     double eta, const double* lam, double* xnew, hipStream_t s) {
+  k_oc_final<<<nblk(ne, 256), 256, 0, s>>>(ne, x, dc, dv, move, eta, lam, xnew);
 }
 
 }  // namespace aarmr

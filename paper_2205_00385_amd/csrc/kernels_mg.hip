@@ -186,11 +186,15 @@ __global__ void __launch_bounds__(256) k_galerkin_lds(int cnx, int cny, int cnz,
 // takes each node as local corner a of the element e = node - offset(a) and
 // forms rows 3a..3a+2 of Ke_e v_e; the 8 partial rows are summed in LDS in a
 // fixed order.  Vectors of type T, matrices FP64.
+// With jb non-null the product feeds a damped-Jacobi sweep instead:
+// y = v + omega jd (jb - A v) (y distinct from v).
 template <typename T>
 __global__ void __launch_bounds__(512) k_apply_elemmat(int nx, int ny, int nz,
                                                        const double* __restrict__ Ke,
                                                        const T* __restrict__ v,
-                                                       T* __restrict__ y) {
+                                                       T* __restrict__ y,
+                                                       const T* __restrict__ jb,
+                                                       const T* __restrict__ jd, T omega) {
   __shared__ T red[8][3][64];
   const int a = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int lane = threadIdx.x & 63;
@@ -229,7 +233,8 @@ __global__ void __launch_bounds__(512) k_apply_elemmat(int nx, int ny, int nz,
     T sum = red[0][a][lane];
 #pragma unroll
     for (int q = 1; q < 8; ++q) sum += red[q][a][lane];
-    y[a * nn + n] = sum;
+    const int64_t d = a * nn + n;
+    y[d] = jb ? v[d] + omega * jd[d] * (jb[d] - sum) : sum;
   }
 }
 
@@ -376,9 +381,13 @@ __global__ void __launch_bounds__(256) k_l1_elem(int nx, int ny, int nz,
 
 // Pass 2: y[c][n] = sum over the (up to 8) elements around node n, taken in
 // corner order a = 0..7, of Y[3a + c][e(n, a)].
+// With jb non-null: y += omega jd (jb - (A v)) in place (y is the product's
+// input v, read only here), the damped-Jacobi sweep on the product.
 template <typename T>
 __global__ void __launch_bounds__(256) k_l1_gather(int nx, int ny, int nz,
-                                                   const T* __restrict__ Y, T* __restrict__ y) {
+                                                   const T* __restrict__ Y, T* __restrict__ y,
+                                                   const T* __restrict__ jb,
+                                                   const T* __restrict__ jd, T omega) {
   const int64_t nn = (int64_t)(nx + 1) * (ny + 1) * (nz + 1);
   const int64_t ne = (int64_t)nx * ny * nz;
   const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -396,7 +405,11 @@ __global__ void __launch_bounds__(256) k_l1_gather(int nx, int ny, int nz,
     for (int c = 0; c < 3; ++c) acc[c] += Y[(int64_t)(3 * a + c) * ne + e];
   }
 #pragma unroll
-  for (int c = 0; c < 3; ++c) y[c * nn + n] = acc[c];
+  for (int c = 0; c < 3; ++c) {
+    const int64_t d = c * nn + n;
+    if (jb) y[d] = y[d] + omega * jd[d] * (jb[d] - acc[c]);
+    else y[d] = acc[c];
+  }
 }
 
 __global__ void k_diag_elemmat(int nx, int ny, int nz, const double* __restrict__ Ke,
@@ -430,12 +443,16 @@ __global__ void k_diag_elemmat(int nx, int ny, int nz, const double* __restrict_
 // (grid.y); the three z-planes of a coarse node are summed in LDS.  On the
 // plane grid (cnz = 0) only the middle offset lies in the grid.
 // mask == nullptr: no fine fixed DOFs.
+// With xc non-null also the coarse level's first Jacobi sweep from zero,
+// xc = omega dc bc.
 template <typename T>
 __global__ void __launch_bounds__(192) k_restrict(int cnx, int cny, int cnz,
                                                   const T* __restrict__ bf,
                                                   const T* __restrict__ tf,
                                                   const uint8_t* __restrict__ mask,
-                                                  T* __restrict__ bc) {
+                                                  T* __restrict__ bc,
+                                                  const T* __restrict__ dc, T omega,
+                                                  T* __restrict__ xc) {
   __shared__ T part[3][64];
   const int lane = threadIdx.x & 63, dzi = threadIdx.x >> 6;
   const int c = blockIdx.y;
@@ -472,7 +489,11 @@ __global__ void __launch_bounds__(192) k_restrict(int cnx, int cny, int cnz,
   }
   part[dzi][lane] = acc;
   __syncthreads();
-  if (dzi == 0 && n < cnn) bc[c * cnn + n] = part[0][lane] + part[1][lane] + part[2][lane];
+  if (dzi == 0 && n < cnn) {
+    const T v = part[0][lane] + part[1][lane] + part[2][lane];
+    bc[c * cnn + n] = v;
+    if (xc) xc[c * cnn + n] = omega * dc[c * cnn + n] * v;
+  }
 }
 
 // xf += Df P xc: thread per fine node, branch-free over the (up to) 8
@@ -921,24 +942,41 @@ void launch_galerkin_from_coarse(const Grid& coarse, const double* Kf, double* K
 
 void launch_apply_elemmat(const Grid& g, const double* Ke, const double* v, double* y,
                           hipStream_t s) {
-  k_apply_elemmat<double><<<nblk(g.nn, 64), 512, 0, s>>>(g.nx, g.ny, g.nz, Ke, v, y);
+  k_apply_elemmat<double><<<nblk(g.nn, 64), 512, 0, s>>>(g.nx, g.ny, g.nz, Ke, v, y, nullptr,
+                                                         nullptr, 0.0);
+}
+
+void launch_apply_elemmat_jacobi(const Grid& g, const double* Ke, const double* v, const double* b,
+                                 const double* dinv, double omega, double* out, hipStream_t s) {
+  k_apply_elemmat<double><<<nblk(g.nn, 64), 512, 0, s>>>(g.nx, g.ny, g.nz, Ke, v, out, b, dinv,
+                                                         omega);
 }
 
 void launch_apply_elemmat_f32(const Grid& g, const double* Ke, const float* v, float* y,
                               hipStream_t s) {
-  k_apply_elemmat<float><<<nblk(g.nn, 64), 512, 0, s>>>(g.nx, g.ny, g.nz, Ke, v, y);
+  k_apply_elemmat<float><<<nblk(g.nn, 64), 512, 0, s>>>(g.nx, g.ny, g.nz, Ke, v, y, nullptr,
+                                                        nullptr, 0.0f);
 }
 
 template <typename T>
 void l1_apply(const Grid& g, const double* Ke, const double* Kcomp, int cap, const T* Bw,
               const T* Ef, const uint8_t* eflag, const int* list, const int* count, int nflag,
-              const T* v, T* Y, T* y, hipStream_t s) {
+              const T* v, T* Y, T* y, hipStream_t s, const T* jb = nullptr,
+              const T* jd = nullptr, T omega = 0) {
   k_l1_elem<T><<<dim3(nblk(g.ne, 256), 3), 256, 0, s>>>(g.nx, g.ny, g.nz, Ke, Bw, Ef, eflag, v, Y);
   if (nflag > 0) {  // nflag: the flagged-parent count, known to the host after setup
     const unsigned mb = (unsigned)std::min<int64_t>(nblk(nflag, 64), 256);
     k_l1_masked<T><<<dim3(mb, 6), 256, 0, s>>>(g.nx, g.ny, g.nz, Ke, Kcomp, cap, list, nflag, v, Y);
   }
-  k_l1_gather<T><<<nblk(g.nn, 256), 256, 0, s>>>(g.nx, g.ny, g.nz, Y, y);
+  k_l1_gather<T><<<nblk(g.nn, 256), 256, 0, s>>>(g.nx, g.ny, g.nz, Y, y, jb, jd, omega);
+}
+
+void launch_apply_l1_jacobi(const Grid& g, const double* Ke, const double* Kcomp, int cap,
+                            const double* Bw, const double* Ef, const uint8_t* eflag,
+                            const int* list, const int* count, int nflag, double* x, double* Y,
+                            const double* b, const double* dinv, double omega, hipStream_t s) {
+  l1_apply<double>(g, Ke, Kcomp, cap, Bw, Ef, eflag, list, count, nflag, x, Y, x, s, b, dinv,
+                   omega);
 }
 
 void launch_apply_l1(const Grid& g, const double* Ke, const double* Kcomp, int cap,
@@ -958,7 +996,8 @@ void launch_apply_l1_f32(const Grid& g, const double* Ke, const double* Kcomp, i
 void launch_restrict_f32(const Grid& coarse, const float* bf, const float* tf,
                          const uint8_t* mask, float* bc, hipStream_t s) {
   k_restrict<float><<<dim3(nblk(coarse.nn, 64), 3), 192, 0, s>>>(coarse.nx, coarse.ny, coarse.nz,
-                                                                 bf, tf, mask, bc);
+                                                                 bf, tf, mask, bc, nullptr, 0.0f,
+                                                                 nullptr);
 }
 
 void launch_prolong_add_f32(const Grid& fine, const float* xc, const uint8_t* mask, float* xf,
@@ -989,7 +1028,16 @@ void launch_diag_elemmat(const Grid& g, const double* Ke, double* dinv, float* d
 void launch_restrict(const Grid& coarse, const double* bf, const double* tf, const uint8_t* mask,
                      double* bc, hipStream_t s, int ncomp) {
   k_restrict<double><<<dim3(nblk(coarse.nn, 64), ncomp), 192, 0, s>>>(coarse.nx, coarse.ny, coarse.nz,
-                                                                  bf, tf, mask, bc);
+                                                                  bf, tf, mask, bc, nullptr, 0.0,
+                                                                  nullptr);
+}
+
+void launch_restrict_jacobi(const Grid& coarse, const double* bf, const double* tf,
+                            const uint8_t* mask, double* bc, const double* dinv_c, double omega,
+                            double* xc, hipStream_t s) {
+  k_restrict<double><<<dim3(nblk(coarse.nn, 64), 3), 192, 0, s>>>(coarse.nx, coarse.ny, coarse.nz,
+                                                                  bf, tf, mask, bc, dinv_c, omega,
+                                                                  xc);
 }
 
 void launch_prolong_add(const Grid& fine, const double* xc, const uint8_t* mask, double* xf,

@@ -67,6 +67,67 @@ __global__ void __launch_bounds__(256) k_multidot_finish(DotSetT<T> d, int nb,
   }
 }
 
+// The finished sum of nb block partials, in the order of k_multidot_finish
+// (so bitwise the value that kernel writes); returned to every thread.
+__device__ inline double finish_partials(const double* __restrict__ part, int nb, double* sh) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nb; i += 256) s += part[i];
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) sh[4] = s;
+  __syncthreads();
+  s = sh[4];
+  __syncthreads();
+  return s;
+}
+
+// CG step with its reductions folded in (grid-stride, nb blocks): p^T q is
+// finished from the nb partials of k_multidot (block 0 stores it in *pq),
+// alpha = *rz / p^T q, x += alpha p, r -= alpha q; the block partials of
+// r^T r go to rr_part[blockIdx]; z0 = omega dinv r is the first Jacobi sweep
+// of the next V-cycle (skipped when z0 is null).
+__global__ void __launch_bounds__(256) k_cg_xr_fused(int64_t n, const double* __restrict__ rz,
+                                                     const double* __restrict__ pq_part, int nb,
+                                                     double* __restrict__ pq,
+                                                     double* __restrict__ x,
+                                                     double* __restrict__ r,
+                                                     const double* __restrict__ p,
+                                                     const double* __restrict__ q,
+                                                     double* __restrict__ rr_part,
+                                                     const double* __restrict__ dinv, double omega,
+                                                     double* __restrict__ z0) {
+  __shared__ double sh[5];
+  const double pqv = finish_partials(pq_part, nb, sh);
+  if (blockIdx.x == 0 && threadIdx.x == 0) *pq = pqv;
+  const double alpha = *rz / pqv;
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) {
+    x[i] = fma(alpha, p[i], x[i]);
+    const double ri = fma(-alpha, q[i], r[i]);
+    r[i] = ri;
+    acc = fma(ri, ri, acc);
+    if (z0) z0[i] = omega * dinv[i] * ri;
+  }
+  acc = block_sum(acc, sh);
+  if (threadIdx.x == 0) rr_part[blockIdx.x] = acc;
+}
+
+// beta = rz_new / *rz_old with rz_new finished from the nb partials of
+// k_multidot (block 0 stores it in *rz_new); p = z + beta p.
+__global__ void __launch_bounds__(256) k_cg_p_fused(int64_t n, const double* __restrict__ rz_part,
+                                                    int nb, double* __restrict__ rz_new,
+                                                    const double* __restrict__ rz_old,
+                                                    const double* __restrict__ z,
+                                                    double* __restrict__ p) {
+  __shared__ double sh[5];
+  const double rzv = finish_partials(rz_part, nb, sh);
+  if (blockIdx.x == 0 && threadIdx.x == 0) *rz_new = rzv;
+  const double beta = rzv / *rz_old;
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride)
+    p[i] = fma(beta, p[i], z[i]);
+}
+
 __global__ void k_copy_masked(int64_t nn, int ncomp, const double* __restrict__ src,
                               const uint8_t* __restrict__ mask, double* __restrict__ dst) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -274,6 +335,34 @@ void multidot_t(const DotSetT<T>& d, const RedScratch& rs, hipStream_t s) {
 
 void launch_multidot(const DotSet& d, const RedScratch& rs, hipStream_t s) {
   multidot_t<double>(d, rs, s);
+}
+
+int dot_blocks(int64_t n) {
+  const int64_t want = (n + 255) / 256;
+  return (int)(want < kRedBlocks ? (want < 1 ? 1 : want) : kRedBlocks);
+}
+
+void launch_dot_partials(int64_t n, const double* a, const double* b, double* part,
+                         hipStream_t s) {
+  DotSet d{};
+  d.k = 1;
+  d.n = n;
+  d.a[0] = a;
+  d.b[0] = b;
+  k_multidot<double><<<dot_blocks(n), 256, 0, s>>>(d, part);
+}
+
+void launch_cg_xr_fused(int64_t n, const double* rz, const double* pq_part, double* pq, double* x,
+                        double* r, const double* p, const double* q, double* rr_part,
+                        const double* dinv, double omega, double* z0, hipStream_t s) {
+  const int nb = dot_blocks(n);
+  k_cg_xr_fused<<<nb, 256, 0, s>>>(n, rz, pq_part, nb, pq, x, r, p, q, rr_part, dinv, omega, z0);
+}
+
+void launch_cg_p_fused(int64_t n, const double* rz_part, double* rz_new, const double* rz_old,
+                       const double* z, double* p, hipStream_t s) {
+  const int nb = dot_blocks(n);
+  k_cg_p_fused<<<nb, 256, 0, s>>>(n, rz_part, nb, rz_new, rz_old, z, p);
 }
 
 void launch_multidot_f32(const DotSetT<float>& d, const RedScratch& rs, hipStream_t s) {
