@@ -298,7 +298,8 @@ int aarmr_oc_update(aarmr_mesh* m, const double* x, const double* dc, const doub
  * runs 14 x 15-node tiles of the x-y plane, each marching over a chunk of
  * node planes; times the residency-sized default chunk length and candidate
  * lengths 4..n_z+1 on this mesh's grid (scratch operands: the solver state is
- * untouched), 3 launches each after a warm-up, and keeps the fastest for the
+ * untouched), the best of 3 rounds of 5 launches each after a warm-up, and
+ * keeps the fastest for the
  * mesh's later products (FP64 and, in the refinement form, FP32).
  * tz_out: host [2] or NULL, receives the chosen lengths (0 = the default).
  * The result of every product is the same for every chunk length.  On the

@@ -602,7 +602,9 @@ int apply(aarmr_mesh* m, int l, const double* v, double* y, hipStream_t s,
 // into neighbouring kernels: the restriction forms the coarse level's first
 // sweep, and below the finest level the last post-smoothing sweep is the
 // epilogue of its operator product.  On levels >= 2 that product writes into
-// L.t and the level's x and t buffers swap roles, so there x must be L.x.
+// L.t and the level's x and t buffers swap roles, so there x must be L.x; on
+// the finest level this is done only for the solver's own z (m->z, which
+// swaps with t0), a caller's buffer gets the separate sweep.
 int vcycle(aarmr_mesh* m, int l, const double* b, double* x, hipStream_t s,
            bool x_init = false) {
   if (l == m->nlev - 1) {
@@ -643,6 +645,15 @@ int vcycle(aarmr_mesh* m, int l, const double* b, double* x, hipStream_t s,
   launch_prolong_add(G, C.x, mask, x, s, m->dim);    // line 4
   KCHECK();
   for (int it = 0; it < m->p.nu_post; ++it) {        // line 5
+    if (fuse && l == 0 && x == m->z && it == m->p.nu_post - 1) {
+      // the solver's own z: the sweep writes into t0 and the two swap roles
+      launch_ebe_jacobi(G, m->wk, m->E, m->mask, x, b, L.dinv, om, m->t0, s, m->tz64);
+      ++m->sweeps;
+      KCHECK();
+      std::swap(m->z, m->t0);
+      L.t = m->t0;
+      continue;
+    }
     if (fuse && l >= 1 && it == m->p.nu_post - 1) {
       if (l == 1) {
         TRY(flagged_count(m, s));
@@ -1009,8 +1020,8 @@ int pcg64(aarmr_mesh* m, double* x, int* iters, double* relres, int maxit_in, bo
       launch_cg_xr_fused(n3, sc + SC_RZ + it, part_pq, sc + SC_PQ + it, x, m->r, m->pv, m->q,
                          part_rr, m->lv[0].dinv, m->p.omega, z0 ? m->z : nullptr, s);
       KCHECK();
-      HIP_TRY(hipMemcpyAsync(m->hpin + 1, sc + SC_PQ + it, sizeof(double), hipMemcpyDeviceToHost, s));
-      HIP_TRY(hipMemcpyAsync(hrr, part_rr, nb * sizeof(double), hipMemcpyDeviceToHost, s));
+      // r^T r partials and the finished p^T q (stored after them) in one copy
+      HIP_TRY(hipMemcpyAsync(hrr, part_rr, (nb + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
       HIP_TRY(hipEventRecord(m->ev_cg, s));
       if (it + 1 < maxit) {
         TRY(vcycle(m, 0, m->r, m->z, s, z0));
@@ -1023,7 +1034,7 @@ int pcg64(aarmr_mesh* m, double* x, int* iters, double* relres, int maxit_in, bo
       for (int b = 0; b < nb; ++b) rr += hrr[b];
       *iters = it + 1;
       *relres = std::sqrt(rr / ff);
-      if (!(m->hpin[1] > 0.0)) return fail(AARMR_E_SINGULAR, "CG: p^T A p <= 0");
+      if (!(hrr[nb] > 0.0)) return fail(AARMR_E_SINGULAR, "CG: p^T A p <= 0");
       if (rr <= tol2) return AARMR_OK;
     }
     return fail(AARMR_E_NOT_CONVERGED, "CG reached cg_maxit before cg_rtol");
@@ -1655,15 +1666,19 @@ int aarmr_autotune(aarmr_mesh* m, int32_t* tz_out, void* stream) {
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
-  auto time_one = [&](auto launch) -> float {
+  auto time_one = [&](auto launch) -> float {  // best of 3 rounds of 5 launches
     launch();  // warm-up
-    (void)hipEventRecord(e0, s);
-    for (int r = 0; r < 3; ++r) launch();
-    (void)hipEventRecord(e1, s);
-    (void)hipEventSynchronize(e1);
-    float ms = 0.f;
-    (void)hipEventElapsedTime(&ms, e0, e1);
-    return ms;
+    float best_ms = 1e30f;
+    for (int round = 0; round < 3; ++round) {
+      (void)hipEventRecord(e0, s);
+      for (int r = 0; r < 5; ++r) launch();
+      (void)hipEventRecord(e1, s);
+      (void)hipEventSynchronize(e1);
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      best_ms = std::min(best_ms, ms);
+    }
+    return best_ms;
   };
   // scratch operands: moduli 1, input 1 (the timing does not depend on values)
   launch_fill(g.ne, 1.0, m->ework, s);

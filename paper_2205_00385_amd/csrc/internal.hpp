@@ -62,6 +62,11 @@ void launch_ebe(const Grid& g, const WalshConsts& K, const double* E, const uint
                 const double* v, double* y, int mode, hipStream_t s, int tz = 0);
 void launch_ebe_f32(const Grid& g, const WalshConsts& K, const float* E, const uint8_t* mask,
                     const float* v, float* y, int mode, hipStream_t s, int tz = 0);
+// The mode-2 product feeding a damped-Jacobi sweep: out = v + omega dinv
+// (b - A v), out distinct from v.
+void launch_ebe_jacobi(const Grid& g, const WalshConsts& K, const double* E, const uint8_t* mask,
+                       const double* v, const double* b, const double* dinv, double omega,
+                       double* out, hipStream_t s, int tz = 0);
 void launch_energy_walsh(const Grid& g, const WalshConsts& K, const uint8_t* mask,
                          const double* u, double* energy, hipStream_t s);
 void launch_simp(int64_t ne, const double* rho, double E0, double Emin, double p, double* E,
@@ -175,8 +180,9 @@ void launch_cg_p(int64_t n, const double* rz_new, const double* rz_old, const do
 int dot_blocks(int64_t n);
 void launch_dot_partials(int64_t n, const double* a, const double* b, double* part,
                          hipStream_t s);
-// pq finished from pq_part (stored to *pq); x += alpha p, r -= alpha q with
-// alpha = *rz / pq; rr_part[0..dot_blocks(n)) = partials of r^T r;
+// pq finished from pq_part (stored to *pq and rr_part[dot_blocks(n)]);
+// x += alpha p, r -= alpha q with alpha = *rz / pq;
+// rr_part[0..dot_blocks(n)) = partials of r^T r;
 // z0 = omega dinv r unless z0 is null.
 void launch_cg_xr_fused(int64_t n, const double* rz, const double* pq_part, double* pq, double* x,
                         double* r, const double* p, const double* q, double* rr_part,

@@ -112,12 +112,19 @@ struct PlaneRaw {
 // y = Df K Df v (zero on fixed DOFs).  MASK_IN: zero the fixed DOFs of v on
 // load; without it the caller guarantees that v is already zero there (true
 // of every vector inside the solvers), which saves the loads and selects.
-// PF: prefetch distance in node planes (1 or 2).
-template <typename T, bool MASK_IN, int PF>
-__global__ void __launch_bounds__(kThreads) k_ebe_z(int nx, int ny, int nz, int gx, int gy, int TZ,
+// PF: prefetch distance in node planes (1 or 2).  JAC: the product feeds a
+// damped-Jacobi sweep, y = v + omega jd (jb - A v) (y distinct from v); the
+// node's own v, jb and jd are fetched one plane ahead like the moduli.
+#ifndef AARMR_EBE_MINB
+#define AARMR_EBE_MINB 1  // workgroups per CU the register budget is sized for
+#endif
+template <typename T, bool MASK_IN, int PF, bool JAC>
+__global__ void __launch_bounds__(kThreads, AARMR_EBE_MINB) k_ebe_z(int nx, int ny, int nz, int gx, int gy, int TZ,
                                                     WalshConsts K, const T* __restrict__ E,
                                                     const uint8_t* __restrict__ mask,
-                                                    const T* __restrict__ v, T* __restrict__ y) {
+                                                    const T* __restrict__ v, T* __restrict__ y,
+                                                    const T* __restrict__ jb,
+                                                    const T* __restrict__ jd, T omega) {
   __shared__ T xs[2][3][kRows][kLanes];
   const int tx = threadIdx.x & (kLanes - 1), ty = threadIdx.x / kLanes;
   // XCD-aware tile order: workgroups are dispatched round-robin over the 8
@@ -146,6 +153,8 @@ __global__ void __launch_bounds__(kThreads) k_ebe_z(int nx, int ny, int nz, int 
   const auto ry = make_rsrc(y, 3u * nn * TS);
   const auto rE = make_rsrc(E, (uint32_t)eplane * nz * TS);
   const auto rm = make_rsrc(mask, (uint32_t)nn);
+  const auto rjb = make_rsrc(jb, JAC ? 3u * nn * TS : 0u);
+  const auto rjd = make_rsrc(jd, JAC ? 3u * nn * TS : 0u);
   // the last lane of a row only supplies node values to its left neighbour:
   // it computes no element and owns no node
   const bool col_ok = tx < kLanes - 1 && i >= 0 && i < nx && j >= 0 && j < ny;
@@ -205,6 +214,7 @@ __global__ void __launch_bounds__(kThreads) k_ebe_z(int nx, int ny, int nz, int 
     WB = load_w(kz0);
   }
   uint32_t own_m = 7u;  // fixed-DOF mask of node (i, j) on the plane written next
+  T own_v[3] = {}, own_b[3] = {}, own_d[3] = {};  // JAC: that node's v, jb, jd
 #pragma unroll
   for (int q = 0; q < 4; ++q)
 #pragma unroll
@@ -218,6 +228,16 @@ __global__ void __launch_bounds__(kThreads) k_ebe_z(int nx, int ny, int nz, int 
     transform(R, Pt);
     const T w = W;
     const uint32_t m_next = R.m0;
+    T v_next[3], b_next[3], d_next[3];
+    if (JAC) {  // node (i, j) of plane k + 1, written by the next step
+      const uint32_t on = (own && k + 1 <= nz) ? (uint32_t)((k + 1) * plane + off00) * TS : kOutside;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        v_next[c] = R.q0[c];
+        b_next[c] = ld(rjb, on + (uint32_t)c * cstride, T());
+        d_next[c] = ld(rjd, on + (uint32_t)c * cstride, T());
+      }
+    }
     load_plane(k + 1 + PF <= kz1 ? k + 1 + PF : -2, R);
     W = load_w(k + PF < kz1 ? k + PF : -1);
     T h[8][3], z[8][3];
@@ -260,11 +280,20 @@ __global__ void __launch_bounds__(kThreads) k_ebe_z(int nx, int ny, int nz, int 
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       T out = X0[c] + xs[buf][c][ty > 0 ? ty - 1 : 0][tx];
+      if (JAC) out = own_v[c] + omega * own_d[c] * (own_b[c] - out);
       if ((own_m >> c) & 1u) out = (T)0;
       st(ry, oy + (uint32_t)c * cstride, out);
     }
     buf ^= 1;
     own_m = m_next;
+    if (JAC) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        own_v[c] = v_next[c];
+        own_b[c] = b_next[c];
+        own_d[c] = d_next[c];
+      }
+    }
   };
   for (int k = kz0 - 1; k < kz1; k += 2) {
     step(k, RA, WA, P0, P1);
@@ -345,16 +374,17 @@ __global__ void k_identity_rows(int64_t nn, const uint8_t* __restrict__ mask,
 #define AARMR_EBE_PF 1
 #endif
 
-template <typename T, bool MASK_IN>
+template <typename T, bool MASK_IN, bool JAC = false>
 static void launch_ebe_t(const Grid& g, const WalshConsts& K, const T* E, const uint8_t* mask,
-                         const T* v, T* y, int tz_req, hipStream_t s) {
+                         const T* v, T* y, int tz_req, hipStream_t s, const T* jb = nullptr,
+                         const T* jd = nullptr, T omega = 0) {
   // resident workgroups of this kernel on the device (thread-safe one-time init)
   static const int slots = [] {
     int dev = 0, cus = 0, per_cu = 0;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_ebe_z<T, MASK_IN, AARMR_EBE_PF>,
-                                                       kThreads, 0);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &per_cu, k_ebe_z<T, MASK_IN, AARMR_EBE_PF, JAC>, kThreads, 0);
     return (cus > 0 && per_cu > 0) ? cus * per_cu : 512;
   }();
   const int gx = (g.nx + 1 + kTileX - 1) / kTileX;
@@ -366,8 +396,8 @@ static void launch_ebe_t(const Grid& g, const WalshConsts& K, const T* E, const 
   if (tz_req > 0) tz = tz_req < planes ? tz_req : planes;  // tuned z-chunk length
   if (tz < 4) tz = 4;
   gz = (planes + tz - 1) / tz;
-  k_ebe_z<T, MASK_IN, AARMR_EBE_PF><<<(unsigned)(gx * gy * gz), kThreads, 0, s>>>(g.nx, g.ny, g.nz, gx, gy, tz, K,
-                                                                     E, mask, v, y);
+  k_ebe_z<T, MASK_IN, AARMR_EBE_PF, JAC><<<(unsigned)(gx * gy * gz), kThreads, 0, s>>>(
+      g.nx, g.ny, g.nz, gx, gy, tz, K, E, mask, v, y, jb, jd, omega);
 }
 
 void launch_ebe(const Grid& g, const WalshConsts& K, const double* E, const uint8_t* mask,
@@ -378,6 +408,12 @@ void launch_ebe(const Grid& g, const WalshConsts& K, const double* E, const uint
   }
   launch_ebe_t<double, true>(g, K, E, mask, v, y, tz, s);
   if (mode == 0) k_identity_rows<double><<<nblk(g.nn, 256), 256, 0, s>>>(g.nn, mask, v, y);
+}
+
+void launch_ebe_jacobi(const Grid& g, const WalshConsts& K, const double* E, const uint8_t* mask,
+                       const double* v, const double* b, const double* dinv, double omega,
+                       double* out, hipStream_t s, int tz) {
+  launch_ebe_t<double, false, true>(g, K, E, mask, v, out, tz, s, b, dinv, omega);
 }
 
 void launch_ebe_f32(const Grid& g, const WalshConsts& K, const float* E, const uint8_t* mask,

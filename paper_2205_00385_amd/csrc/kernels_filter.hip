@@ -152,31 +152,29 @@ __global__ void __launch_bounds__(256) k_oc_step3(int64_t ne, const double* __re
 // then up to three bisection steps along the path the decisions take; lam[2]
 // records the last multiplier evaluated, lam[3] = 1 once (l2-l1)/(l1+l2) <= 1e-3
 // or after the 200th step.
-__global__ void __launch_bounds__(256) k_oc_bisect3(double* lam, const double* __restrict__ partial,
+__global__ void __launch_bounds__(512) k_oc_bisect3(double* lam, const double* __restrict__ partial,
                                                     int nparts, double target) {
-  __shared__ double red[4];
   __shared__ double vol[7];
   if (lam[3] != 0.0) return;
-  for (int t = 0; t < 7; ++t) {
+  const int t = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (t < 7) {  // wave t sums trial t's partials
     double acc = 0.0;
-    for (int b = threadIdx.x; b < nparts; b += 256) acc += partial[t * kRedBlocks + b];
+    for (int b = lane; b < nparts; b += 64) acc += partial[t * kRedBlocks + b];
     for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
-    __syncthreads();
-    if (threadIdx.x == 0) vol[t] = (red[0] + red[1]) + (red[2] + red[3]);
-    __syncthreads();
+    if (lane == 0) vol[t] = acc;
   }
+  __syncthreads();
   if (threadIdx.x != 0) return;
-  int t = 0;
+  int h = 0;  // heap index of the multiplier evaluated next
   for (int level = 0; level < 3 && lam[3] == 0.0; ++level) {
     const double lmid = 0.5 * (lam[0] + lam[1]);
     lam[2] = lmid;
-    if (vol[t] > target) {
+    if (vol[h] > target) {
       lam[0] = lmid;
-      t = 2 * t + 2;
+      h = 2 * h + 2;
     } else {
       lam[1] = lmid;
-      t = 2 * t + 1;
+      h = 2 * h + 1;
     }
     lam[4] += 1.0;
     if ((lam[1] - lam[0]) / (lam[0] + lam[1]) <= 1e-3 || lam[4] >= 200.0) lam[3] = 1.0;
@@ -250,7 +248,7 @@ void launch_oc_step3(int64_t ne, const double* x, const double* dc, const double
 
 void launch_oc_bisect3(double* lam, const double* partial, int nparts, double target,
                        hipStream_t s) {
-  k_oc_bisect3<<<1, 256, 0, s>>>(lam, partial, nparts, target);
+  k_oc_bisect3<<<1, 512, 0, s>>>(lam, partial, nparts, target);
 }
 
 void launch_oc_final(int64_t ne, const double* x, const double* dc, const double* dv, double move,

@@ -914,8 +914,17 @@ __global__ void __launch_bounds__(256) k_gemv(int n, const double* __restrict__ 
   const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (row >= n) return;
   const double* a = A + (int64_t)row * n;
-  double acc = 0.0;
-  for (int j = lane; j < n; j += 64) acc = fma(a[j], (double)x[j], acc);
+  // four independent accumulators: eight loads in flight per lane
+  double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+  int j = lane;
+  for (; j + 192 < n; j += 256) {
+    acc0 = fma(a[j], (double)x[j], acc0);
+    acc1 = fma(a[j + 64], (double)x[j + 64], acc1);
+    acc2 = fma(a[j + 128], (double)x[j + 128], acc2);
+    acc3 = fma(a[j + 192], (double)x[j + 192], acc3);
+  }
+  for (; j < n; j += 64) acc0 = fma(a[j], (double)x[j], acc0);
+  double acc = (acc0 + acc1) + (acc2 + acc3);
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
   if (lane == 0) y[row] = (TY)acc;
 }

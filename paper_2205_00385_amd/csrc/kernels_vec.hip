@@ -81,10 +81,11 @@ __device__ inline double finish_partials(const double* __restrict__ part, int nb
 }
 
 // CG step with its reductions folded in (grid-stride, nb blocks): p^T q is
-// finished from the nb partials of k_multidot (block 0 stores it in *pq),
-// alpha = *rz / p^T q, x += alpha p, r -= alpha q; the block partials of
-// r^T r go to rr_part[blockIdx]; z0 = omega dinv r is the first Jacobi sweep
-// of the next V-cycle (skipped when z0 is null).
+// finished from the nb partials of k_multidot (block 0 stores it in *pq and
+// in rr_part[nb], so one copy brings it to the host with the r^T r
+// partials), alpha = *rz / p^T q, x += alpha p, r -= alpha q; the block
+// partials of r^T r go to rr_part[blockIdx]; z0 = omega dinv r is the first
+// Jacobi sweep of the next V-cycle (skipped when z0 is null).
 __global__ void __launch_bounds__(256) k_cg_xr_fused(int64_t n, const double* __restrict__ rz,
                                                      const double* __restrict__ pq_part, int nb,
                                                      double* __restrict__ pq,
@@ -97,7 +98,10 @@ __global__ void __launch_bounds__(256) k_cg_xr_fused(int64_t n, const double* __
                                                      double* __restrict__ z0) {
   __shared__ double sh[5];
   const double pqv = finish_partials(pq_part, nb, sh);
-  if (blockIdx.x == 0 && threadIdx.x == 0) *pq = pqv;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    *pq = pqv;
+    rr_part[nb] = pqv;
+  }
   const double alpha = *rz / pqv;
   const int64_t stride = (int64_t)gridDim.x * 256;
   double acc = 0.0;
