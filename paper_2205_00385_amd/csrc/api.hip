@@ -1010,8 +1010,8 @@ int pcg64(aarmr_mesh* m, double* x, int* iters, double* relres, int maxit_in, bo
     // simply unused.
     double* part_pq = m->partial;
     double* part_rz = m->partial + kRedBlocks;
-    double* part_rr = m->partial + 2 * kRedBlocks;
-    const int nb = dot_blocks(n3);
+    double* part_rr = m->partial + 2 * kRedBlocks;  // fused_blocks(n3) + 1 entries
+    const int nb = fused_blocks(n3);
     const bool z0 = m->p.nu_pre >= 1;
     double* hrr = m->hpin + 1024;
     for (int it = 0; it < maxit; ++it) {

@@ -16,6 +16,7 @@
 namespace aarmr {
 
 constexpr int kRedBlocks = 512;    // partial-sum blocks of one reduction
+constexpr int kFusedBlocks = 2048; // block limit of the CG updates with folded reductions
 constexpr int kRedSlots = 24;      // dot products one reduction launch can hold
 constexpr int kMaxIt = 4096;       // bound of cg_maxit (scalar history length)
 constexpr int kGJBlock = 64;       // block size of the coarsest inversion
@@ -175,14 +176,16 @@ void launch_cg_xr(int64_t n, const double* rz, const double* pq, double* x, doub
 void launch_cg_p(int64_t n, const double* rz_new, const double* rz_old, const double* z,
                  double* p, hipStream_t s);
 // CG with folded reductions.  dot_blocks(n): the block count of one dot's
-// partials (and of the fused updates that finish them); launch_dot_partials
-// writes a^T b's partials to part[0..dot_blocks(n)).
+// partials; fused_blocks(n): that of the fused updates (each finishes the
+// dot partials it needs); launch_dot_partials writes a^T b's partials to
+// part[0..dot_blocks(n)).
 int dot_blocks(int64_t n);
+int fused_blocks(int64_t n);
 void launch_dot_partials(int64_t n, const double* a, const double* b, double* part,
                          hipStream_t s);
-// pq finished from pq_part (stored to *pq and rr_part[dot_blocks(n)]);
+// pq finished from pq_part (stored to *pq and rr_part[fused_blocks(n)]);
 // x += alpha p, r -= alpha q with alpha = *rz / pq;
-// rr_part[0..dot_blocks(n)) = partials of r^T r;
+// rr_part[0..fused_blocks(n)) = partials of r^T r;
 // z0 = omega dinv r unless z0 is null.
 void launch_cg_xr_fused(int64_t n, const double* rz, const double* pq_part, double* pq, double* x,
                         double* r, const double* p, const double* q, double* rr_part,

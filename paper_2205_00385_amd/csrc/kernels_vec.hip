@@ -80,12 +80,12 @@ __device__ inline double finish_partials(const double* __restrict__ part, int nb
   return s;
 }
 
-// CG step with its reductions folded in (grid-stride, nb blocks): p^T q is
-// finished from the nb partials of k_multidot (block 0 stores it in *pq and
-// in rr_part[nb], so one copy brings it to the host with the r^T r
-// partials), alpha = *rz / p^T q, x += alpha p, r -= alpha q; the block
-// partials of r^T r go to rr_part[blockIdx]; z0 = omega dinv r is the first
-// Jacobi sweep of the next V-cycle (skipped when z0 is null).
+// CG step with its reductions folded in (grid-stride over gridDim.x blocks):
+// p^T q is finished from the nb partials of k_multidot (block 0 stores it in
+// *pq and in rr_part[gridDim.x], so one copy brings it to the host with the
+// r^T r partials), alpha = *rz / p^T q, x += alpha p, r -= alpha q; the
+// block partials of r^T r go to rr_part[blockIdx]; z0 = omega dinv r is the
+// first Jacobi sweep of the next V-cycle (skipped when z0 is null).
 __global__ void __launch_bounds__(256) k_cg_xr_fused(int64_t n, const double* __restrict__ rz,
                                                      const double* __restrict__ pq_part, int nb,
                                                      double* __restrict__ pq,
@@ -100,7 +100,7 @@ __global__ void __launch_bounds__(256) k_cg_xr_fused(int64_t n, const double* __
   const double pqv = finish_partials(pq_part, nb, sh);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     *pq = pqv;
-    rr_part[nb] = pqv;
+    rr_part[gridDim.x] = pqv;
   }
   const double alpha = *rz / pqv;
   const int64_t stride = (int64_t)gridDim.x * 256;
@@ -346,6 +346,11 @@ int dot_blocks(int64_t n) {
   return (int)(want < kRedBlocks ? (want < 1 ? 1 : want) : kRedBlocks);
 }
 
+int fused_blocks(int64_t n) {
+  const int64_t want = (n + 1023) / 1024;  // about four entries per thread
+  return (int)(want < kFusedBlocks ? (want < 1 ? 1 : want) : kFusedBlocks);
+}
+
 void launch_dot_partials(int64_t n, const double* a, const double* b, double* part,
                          hipStream_t s) {
   DotSet d{};
@@ -359,14 +364,13 @@ void launch_dot_partials(int64_t n, const double* a, const double* b, double* pa
 void launch_cg_xr_fused(int64_t n, const double* rz, const double* pq_part, double* pq, double* x,
                         double* r, const double* p, const double* q, double* rr_part,
                         const double* dinv, double omega, double* z0, hipStream_t s) {
-  const int nb = dot_blocks(n);
-  k_cg_xr_fused<<<nb, 256, 0, s>>>(n, rz, pq_part, nb, pq, x, r, p, q, rr_part, dinv, omega, z0);
+  k_cg_xr_fused<<<fused_blocks(n), 256, 0, s>>>(n, rz, pq_part, dot_blocks(n), pq, x, r, p, q,
+                                                rr_part, dinv, omega, z0);
 }
 
 void launch_cg_p_fused(int64_t n, const double* rz_part, double* rz_new, const double* rz_old,
                        const double* z, double* p, hipStream_t s) {
-  const int nb = dot_blocks(n);
-  k_cg_p_fused<<<nb, 256, 0, s>>>(n, rz_part, nb, rz_new, rz_old, z, p);
+  k_cg_p_fused<<<fused_blocks(n), 256, 0, s>>>(n, rz_part, dot_blocks(n), rz_new, rz_old, z, p);
 }
 
 void launch_multidot_f32(const DotSetT<float>& d, const RedScratch& rs, hipStream_t s) {
