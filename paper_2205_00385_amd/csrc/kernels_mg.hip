@@ -80,8 +80,9 @@ __global__ void k_parent_flags(int cnx, int cny, int cnz, const uint8_t* __restr
 __global__ void k_zero_int(int* p) { *p = 0; }
 
 // Galerkin matrix of one parent per block iteration: the 8 child matrices
-// are staged in LDS, T_c = K_c P_c is formed by a column pass and
-// sum_c P_c^T T_c by a row pass.  FROM_FINE: children are E_c Df KE Df with
+// are staged in LDS, then child by child T_c = K_c P_c is formed by a column
+// pass and P_c^T T_c added by a row pass (registers stay few, so several
+// workgroups share a CU).  FROM_FINE: children are E_c Df KE Df with
 // the fine fixed-DOF mask, for the parents listed by k_parent_flags (the
 // others are exact from the fast path); list entry w < cap is also written to
 // the compact copy Kcomp[entry][w].  Otherwise every parent, with the
@@ -97,6 +98,7 @@ __global__ void __launch_bounds__(256) k_galerkin_lds(int cnx, int cny, int cnz,
                                                       double* __restrict__ Kc,
                                                       double* __restrict__ Kcomp, int cap) {
   __shared__ double sK[8][24][25];
+  __shared__ double sT[24][25];
   __shared__ uint8_t sm[27];
   __shared__ double sw[8];
   const int64_t cne = (int64_t)cnx * cny * cnz;
@@ -104,7 +106,19 @@ __global__ void __launch_bounds__(256) k_galerkin_lds(int cnx, int cny, int cnz,
   const int64_t fne = cne * 8;
   const int tid = threadIdx.x;
   const int64_t nwork = FROM_FINE ? (int64_t)*count : cne;
-  for (int64_t w = blockIdx.x; w < nwork; w += gridDim.x) {
+  // XCD-aware order (every parent): workgroups are dispatched round-robin
+  // over the 8 XCDs, so XCD x takes a contiguous range of parents and its
+  // workgroups walk it together.  Neighbouring parents read their children
+  // from the same cache lines (the children of 8 parents along x share one
+  // 128-byte line of each packed entry), which then meet in one L2.
+  int64_t w0 = blockIdx.x, w1 = nwork, ws = gridDim.x;
+  if (!FROM_FINE && gridDim.x >= 8) {
+    const int x = blockIdx.x & 7, nbx = (int)(gridDim.x >> 3) + (x < (int)(gridDim.x & 7) ? 1 : 0);
+    w0 = nwork * x / 8 + (blockIdx.x >> 3);
+    w1 = nwork * (x + 1) / 8;
+    ws = nbx;
+  }
+  for (int64_t w = w0; w < w1; w += ws) {
   const int64_t eid = FROM_FINE ? (int64_t)list[w] : w;
   const int cx = (int)(eid % cnx);
   const int64_t rest = eid / cnx;
@@ -119,63 +133,80 @@ __global__ void __launch_bounds__(256) k_galerkin_lds(int cnx, int cny, int cnz,
                   (int64_t)fnx * ((2 * cy + ((tid >> 1) & 1)) + (int64_t)fny * (2 * cz + (tid >> 2)))];
     __syncthreads();
   }
-  for (int t = tid; t < 8 * 576; t += 256) {
+  // the 8 x 576 child entries, 18 per thread, all loads in flight before
+  // the first LDS store
+  double lv[18];
+#pragma unroll
+  for (int u = 0; u < 18; ++u) {
+    const int t = tid + 256 * u;
     const int c = t / 576, r = (t % 576) / 24, q = t % 24;
     const int dx = c & 1, dy = (c >> 1) & 1, dz = c >> 2;
-    double v;
     if (FROM_FINE) {
       const int br = r / 3, bq = q / 3;
       const int pr = (dx + (br & 1)) + 3 * (dy + ((br >> 1) & 1)) + 9 * (dz + (br >> 2));
       const int pq = (dx + (bq & 1)) + 3 * (dy + ((bq >> 1) & 1)) + 9 * (dz + (bq >> 2));
       const bool fx = ((sm[pr] >> (r % 3)) & 1) || ((sm[pq] >> (q % 3)) & 1);
-      v = fx ? 0.0 : sw[c] * KE[r * 24 + q];
+      lv[u] = fx ? 0.0 : sw[c] * KE[r * 24 + q];
     } else {
       const int64_t fe = (int64_t)(2 * cx + dx) + (int64_t)fnx * ((2 * cy + dy) + (int64_t)fny * (2 * cz + dz));
-      v = Kf[(int64_t)sidx(r, q) * fne + fe];
+      lv[u] = Kf[(int64_t)sidx(r, q) * fne + fe];
     }
-    sK[c][r][q] = v;
   }
-  __syncthreads();
-  // column pass: T_c[r][3B+j] = sum_b P_c[b][B] K_c[r][3b+j]
-  double tv[18];
 #pragma unroll
   for (int u = 0; u < 18; ++u) {
     const int t = tid + 256 * u;
-    const int c = t / 576, r = (t % 576) / 24, J = t % 24;
-    const int B = J / 3, j = J % 3;
-    const int dx = c & 1, dy = (c >> 1) & 1, dz = c >> 2;
-    double acc = 0.0;
-    for (int b = 0; b < 8; ++b) {
-      const double pb = phi1(dx + (b & 1), B & 1) * phi1(dy + ((b >> 1) & 1), (B >> 1) & 1) *
-                        phi1(dz + (b >> 2), B >> 2);
-      acc = fma(pb, sK[c][r][3 * b + j], acc);
-    }
-    tv[u] = acc;
+    sK[t / 576][(t % 576) / 24][t % 24] = lv[u];
   }
   __syncthreads();
+  // child by child: column pass T[r][3B+j] = sum_b P_c[b][B] K_c[r][3b+j]
+  // into sT, then the row pass adds sum_b P_c[b][A] T[3b+i][J] to the packed
+  // entries (I <= J) this thread owns (sx = tid and tid + 256)
+  int Iown[2], Jown[2];
 #pragma unroll
-  for (int u = 0; u < 18; ++u) {
-    const int t = tid + 256 * u;
-    sK[t / 576][(t % 576) / 24][t % 24] = tv[u];
-  }
-  __syncthreads();
-  // row pass over packed entries (I <= J): sum_c sum_b P_c[b][A] T_c[3b+i][J]
-  for (int sx = tid; sx < kSym; sx += 256) {
+  for (int h = 0; h < 2; ++h) {
+    const int sx = tid + 256 * h;
     int I = 0;
-    while (sidx(I, 23) < sx) ++I;  // row of packed entry sx
-    const int J = I + (sx - sidx(I, I));
-    const int A = I / 3, i = I % 3;
-    double acc = 0.0;
-    for (int c = 0; c < 8; ++c) {
-      const int dx = c & 1, dy = (c >> 1) & 1, dz = c >> 2;
+    if (sx < kSym)
+      while (sidx(I, 23) < sx) ++I;  // row of packed entry sx
+    Iown[h] = I;
+    Jown[h] = sx < kSym ? I + (sx - sidx(I, I)) : 0;
+  }
+  double racc[2] = {0.0, 0.0};
+  for (int c = 0; c < 8; ++c) {
+    const int dx = c & 1, dy = (c >> 1) & 1, dz = c >> 2;
+    for (int t = tid; t < 576; t += 256) {
+      const int r = t / 24, J = t % 24, B = J / 3, j = J % 3;
+      double acc = 0.0;
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {
+        const double pb = phi1(dx + (b & 1), B & 1) * phi1(dy + ((b >> 1) & 1), (B >> 1) & 1) *
+                          phi1(dz + (b >> 2), B >> 2);
+        acc = fma(pb, sK[c][r][3 * b + j], acc);
+      }
+      sT[r][J] = acc;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int A = Iown[h] / 3, i = Iown[h] % 3, J = Jown[h];
+      double acc = racc[h];
+#pragma unroll
       for (int b = 0; b < 8; ++b) {
         const double pa = phi1(dx + (b & 1), A & 1) * phi1(dy + ((b >> 1) & 1), (A >> 1) & 1) *
                           phi1(dz + (b >> 2), A >> 2);
-        acc = fma(pa, sK[c][3 * b + i][J], acc);
+        acc = fma(pa, sT[3 * b + i][J], acc);
       }
+      racc[h] = acc;
     }
-    Kc[(int64_t)sx * cne + eid] = acc;
-    if (FROM_FINE && w < cap) Kcomp[(int64_t)sx * cap + w] = acc;
+    __syncthreads();  // sT is rewritten for the next child
+  }
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int sx = tid + 256 * h;
+    if (sx < kSym) {
+      Kc[(int64_t)sx * cne + eid] = racc[h];
+      if (FROM_FINE && w < cap) Kcomp[(int64_t)sx * cap + w] = racc[h];
+    }
   }
   __syncthreads();  // sK, sm, sw are reused by the next parent
   }
