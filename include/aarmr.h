@@ -329,6 +329,8 @@ typedef struct aarmr_batch_item {
   int32_t flags;
   int32_t status;               /* out: the item's aarmr_solve return code */
   aarmr_stats stats;            /* out */
+  int32_t done;                 /* out: set to 1 (release store) once status,
+                                   stats and the item's outputs are final */
 } aarmr_batch_item;
 
 /* Solve every item (see above).  streams: host array of n_streams hipStream_t
@@ -339,6 +341,27 @@ typedef struct aarmr_batch_item {
  * n_streams; item errors as aarmr_solve. */
 int aarmr_batch_solve(aarmr_batch_item* items, int32_t n_items, void* const* streams,
                       int32_t n_streams);
+
+/* Asynchronous form of aarmr_batch_solve, for callers that keep submitting
+ * work while a batch runs (the serving loop).  aarmr_batch_submit validates
+ * the items like aarmr_batch_solve, clears every item's `done`, starts the
+ * worker threads and returns at once; *out receives a handle.  The items
+ * array, the streams array and all memory the items name must stay valid
+ * until aarmr_batch_wait returns.  Errors: as aarmr_batch_solve's argument
+ * errors (nothing is started then, *out is NULL). */
+typedef struct aarmr_batch aarmr_batch;
+int aarmr_batch_submit(aarmr_batch_item* items, int32_t n_items, void* const* streams,
+                       int32_t n_streams, aarmr_batch** out);
+
+/* Non-blocking progress: *n_done receives the number of items finished so
+ * far (those whose `done` is 1).  Returns AARMR_OK, or AARMR_E_INVALID for a
+ * null argument. */
+int aarmr_batch_poll(aarmr_batch* b, int32_t* n_done);
+
+/* Block until every item is finished, synchronise the streams and release
+ * the handle.  Returns AARMR_OK or the first non-OK item status in item
+ * order, like aarmr_batch_solve. */
+int aarmr_batch_wait(aarmr_batch* b);
 
 /* Thread-local description of the last error on this thread ("" if none). */
 const char* aarmr_last_error(void);

@@ -70,6 +70,7 @@ class BatchItem(ctypes.Structure):
         ("n_rhs", ctypes.c_int32), ("fixed_dofs", ctypes.c_void_p), ("n_fixed", ctypes.c_int64),
         ("u", ctypes.c_void_p), ("compliance", ctypes.c_void_p), ("dc", ctypes.c_void_p),
         ("flags", ctypes.c_int32), ("status", ctypes.c_int32), ("stats", Stats),
+        ("done", ctypes.c_int32),
     ]
 
 
@@ -77,7 +78,8 @@ EXPORTS = [
     "aarmr_default_params", "aarmr_mesh_create", "aarmr_mesh_destroy", "aarmr_workspace_bytes",
     "aarmr_bind_workspace", "aarmr_solve", "aarmr_ca_update", "aarmr_filter", "aarmr_setup",
     "aarmr_apply_operator", "aarmr_vcycle", "aarmr_element_energy", "aarmr_oc_update",
-    "aarmr_autotune", "aarmr_batch_solve", "aarmr_set_springs", "aarmr_last_error",
+    "aarmr_autotune", "aarmr_batch_solve", "aarmr_batch_submit", "aarmr_batch_poll",
+    "aarmr_batch_wait", "aarmr_set_springs", "aarmr_last_error",
 ]
 
 
@@ -106,6 +108,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.aarmr_element_energy.argtypes = [P, vp, vp, vp]
     lib.aarmr_oc_update.argtypes = [P, vp, vp, vp, dbl, dbl, vp, vp, vp]
     lib.aarmr_batch_solve.argtypes = [ctypes.POINTER(BatchItem), i32, ctypes.POINTER(P), i32]
+    lib.aarmr_batch_submit.argtypes = [ctypes.POINTER(BatchItem), i32, ctypes.POINTER(P), i32,
+                                       ctypes.POINTER(P)]
+    lib.aarmr_batch_poll.argtypes = [P, ctypes.POINTER(i32)]
+    lib.aarmr_batch_wait.argtypes = [P]
     lib.aarmr_autotune.argtypes = [P, ctypes.POINTER(i32), vp]
     lib.aarmr_set_springs.argtypes = [P, ctypes.POINTER(i64), ctypes.POINTER(dbl), i32]
     lib.aarmr_last_error.argtypes = []
@@ -267,12 +273,7 @@ class Mesh:
                                      float(move), _ptr(x_new), _ptr(rho_new), _stream()))
 
 
-def batch_solve(jobs, streams, check=True):
-    """Solve independent analyses concurrently (aarmr_batch_solve).
-
-    jobs: list of dicts with keys mesh, rho, f, fixed, u and optionally dc,
-    flags; tensors as for Mesh.solve.  streams: torch.cuda.Stream objects.
-    Returns (compliances per job, the BatchItem array, return code)."""
+def _batch_items(jobs):
     n = len(jobs)
     items = (BatchItem * n)()
     comp = []
@@ -297,12 +298,54 @@ def batch_solve(jobs, streams, check=True):
         dc = jb.get("dc")
         it.dc = dc.data_ptr() if dc is not None else None
         it.flags = jb.get("flags", 0)
+    return items, comp
+
+
+def batch_solve(jobs, streams, check=True):
+    """Solve independent analyses concurrently (aarmr_batch_solve).
+
+    jobs: list of dicts with keys mesh, rho, f, fixed, u and optionally dc,
+    flags; tensors as for Mesh.solve.  streams: torch.cuda.Stream objects.
+    Returns (compliances per job, the BatchItem array, return code)."""
+    n = len(jobs)
+    items, comp = _batch_items(jobs)
     hs = (ctypes.c_void_p * len(streams))(*[s.cuda_stream for s in streams])
     code = lib().aarmr_batch_solve(items, n, hs, len(streams))
     if check:
         _check(code, allow=(E_NOT_CONVERGED,))
     out = [[comp[i][l] for l in range(items[i].n_rhs)] for i in range(n)]
     return out, items, code
+
+
+class BatchRun:
+    """A batch started with aarmr_batch_submit: poll() reports progress
+    without blocking, wait() finishes it (returns compliances per job and
+    the return code).  The job tensors must stay alive until wait()."""
+
+    def __init__(self, jobs, streams):
+        self._jobs = jobs
+        self._items, self._comp = _batch_items(jobs)
+        self._hs = (ctypes.c_void_p * len(streams))(*[s.cuda_stream for s in streams])
+        self._h = ctypes.c_void_p()
+        _check(lib().aarmr_batch_submit(self._items, len(jobs), self._hs, len(streams),
+                                        ctypes.byref(self._h)))
+
+    @property
+    def items(self):
+        return self._items
+
+    def poll(self) -> int:
+        n = ctypes.c_int32()
+        _check(lib().aarmr_batch_poll(self._h, ctypes.byref(n)))
+        return n.value
+
+    def wait(self, check=True):
+        code = lib().aarmr_batch_wait(self._h)
+        self._h = None
+        if check:
+            _check(code, allow=(E_NOT_CONVERGED,))
+        n = len(self._jobs)
+        return [[self._comp[i][l] for l in range(self._items[i].n_rhs)] for i in range(n)], code
 
 
 def fixed_dofs_soa(prob, n_node: int) -> list:

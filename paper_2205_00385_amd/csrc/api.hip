@@ -5,6 +5,7 @@
 // (CG convergence, Gram-Schmidt rank decisions, the eq. (29) accept/reject
 // branch).  Every arithmetic step of the method runs on the GPU.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -139,6 +140,16 @@ struct aarmr_mesh {
   double* hpin = nullptr;  // pinned host staging
   hipEvent_t ev_cg = nullptr;  // marks a CG iteration's scalar read-back
   int64_t sweeps = 0;
+};
+
+// A running batch: worker threads, each with its stream and queue of items.
+struct aarmr_batch {
+  aarmr_batch_item* items = nullptr;
+  int n_items = 0;
+  std::vector<void*> streams;
+  std::vector<std::vector<int>> queue;
+  std::vector<std::thread> pool;
+  std::atomic<int> n_done{0};
 };
 
 namespace {
@@ -1719,11 +1730,12 @@ int aarmr_autotune(aarmr_mesh* m, int32_t* tz_out, void* stream) {
   return AARMR_OK;
 }
 
-int aarmr_batch_solve(aarmr_batch_item* items, int32_t n_items, void* const* streams,
-                      int32_t n_streams) {
+int aarmr_batch_submit(aarmr_batch_item* items, int32_t n_items, void* const* streams,
+                       int32_t n_streams, aarmr_batch** out) {
+  if (!out) return fail(AARMR_E_INVALID, "null handle pointer");
+  *out = nullptr;
   if (n_items < 0 || (n_items > 0 && !items)) return fail(AARMR_E_INVALID, "bad item array");
   if (!streams || n_streams < 1 || n_streams > 64) return fail(AARMR_E_INVALID, "bad stream array");
-  if (n_items == 0) return AARMR_OK;
   std::vector<int> order(n_items);
   for (int i = 0; i < n_items; ++i) {
     if (!items[i].mesh) return fail(AARMR_E_INVALID, "null mesh in batch");
@@ -1736,34 +1748,62 @@ int aarmr_batch_solve(aarmr_batch_item* items, int32_t n_items, void* const* str
     if (std::adjacent_find(seen.begin(), seen.end()) != seen.end())
       return fail(AARMR_E_INVALID, "a mesh appears twice in the batch");
   }
-  // largest first, then round-robin over the streams: a simple balance of
-  // the per-stream work (work ~ nodes x load cases)
-  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-    return items[a].mesh->lg[0].nn * items[a].n_rhs > items[b].mesh->lg[0].nn * items[b].n_rhs;
+  for (int i = 0; i < n_items; ++i) __atomic_store_n(&items[i].done, 0, __ATOMIC_RELAXED);
+  aarmr_batch* b = new aarmr_batch();
+  b->items = items;
+  b->n_items = n_items;
+  b->streams.assign(streams, streams + n_streams);
+  // largest first, then greedy: next item to the least-loaded worker (work ~
+  // nodes x load cases)
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+    return items[x].mesh->lg[0].nn * items[x].n_rhs > items[y].mesh->lg[0].nn * items[y].n_rhs;
   });
-  const int nw = std::min<int>(n_streams, n_items);
-  std::vector<std::vector<int>> queue(nw);
+  const int nw = std::max(1, std::min<int>(n_streams, n_items));
+  b->queue.assign(nw, {});
   std::vector<int64_t> load(nw, 0);
-  for (int i : order) {  // greedy: next item to the least-loaded worker
+  for (int i : order) {
     const int w = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-    queue[w].push_back(i);
+    b->queue[w].push_back(i);
     load[w] += items[i].mesh->lg[0].nn * std::max(1, items[i].n_rhs);
   }
-  auto work = [&](int w) {
-    for (int i : queue[w]) {
-      aarmr_batch_item& it = items[i];
-      it.status = aarmr_solve(it.mesh, it.rho, it.f, it.n_rhs, it.fixed_dofs, it.n_fixed, it.u,
-                              it.compliance, it.dc, it.flags, &it.stats, streams[w]);
-    }
-  };
-  std::vector<std::thread> pool;
-  for (int w = 1; w < nw; ++w) pool.emplace_back(work, w);
-  work(0);
-  for (auto& t : pool) t.join();
-  for (int w = 0; w < nw; ++w) HIP_TRY(hipStreamSynchronize(S(streams[w])));
-  for (int i = 0; i < n_items; ++i)
-    if (items[i].status != AARMR_OK) return fail(items[i].status, "a batch item failed (see its status)");
+  for (int w = 0; w < nw; ++w)
+    b->pool.emplace_back([b, w] {
+      for (int i : b->queue[w]) {
+        aarmr_batch_item& it = b->items[i];
+        it.status = aarmr_solve(it.mesh, it.rho, it.f, it.n_rhs, it.fixed_dofs, it.n_fixed, it.u,
+                                it.compliance, it.dc, it.flags, &it.stats, b->streams[w]);
+        __atomic_store_n(&it.done, 1, __ATOMIC_RELEASE);  // aarmr_solve synchronised the stream
+        b->n_done.fetch_add(1, std::memory_order_release);
+      }
+    });
+  *out = b;
   return AARMR_OK;
+}
+
+int aarmr_batch_poll(aarmr_batch* b, int32_t* n_done) {
+  if (!b || !n_done) return fail(AARMR_E_INVALID, "null argument");
+  *n_done = b->n_done.load(std::memory_order_acquire);
+  return AARMR_OK;
+}
+
+int aarmr_batch_wait(aarmr_batch* b) {
+  if (!b) return fail(AARMR_E_INVALID, "null handle");
+  for (auto& t : b->pool) t.join();
+  int rc = AARMR_OK;
+  for (void* st : b->streams)
+    if (hipStreamSynchronize(S(st)) != hipSuccess && rc == AARMR_OK) rc = AARMR_E_HIP;
+  for (int i = 0; i < b->n_items && rc == AARMR_OK; ++i)
+    if (b->items[i].status != AARMR_OK) rc = b->items[i].status;
+  delete b;
+  if (rc != AARMR_OK) return fail(rc, "a batch item failed (see its status)");
+  return AARMR_OK;
+}
+
+int aarmr_batch_solve(aarmr_batch_item* items, int32_t n_items, void* const* streams,
+                      int32_t n_streams) {
+  aarmr_batch* b = nullptr;
+  TRY(aarmr_batch_submit(items, n_items, streams, n_streams, &b));
+  return aarmr_batch_wait(b);
 }
 
 const char* aarmr_last_error(void) { return g_err.c_str(); }

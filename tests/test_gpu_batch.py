@@ -86,3 +86,36 @@ def test_batch_fp64_small_matches_alone_and_rejects_repeats():
         assert torch.equal(u2, jb["u"]) and C2 == comp[i]
     with pytest.raises(aarmr.AarmrError):
         aarmr.batch_solve([jobs[0], jobs[0]], streams)
+
+
+def test_batch_submit_poll_wait_matches_blocking_form():
+    """aarmr_batch_submit returns at once; polling reports progress until
+    every item is done (each item's done flag set); the results equal the
+    blocking aarmr_batch_solve on fresh meshes, bit for bit."""
+    import time
+
+    aarmr = _aarmr()
+    sizes = [(16, 16, 16), (24, 16, 16), (16, 24, 32), (32, 16, 16), (16, 16, 24)]
+    jobs = [_instance(i, sz, aarmr.FP64) for i, sz in enumerate(sizes)]
+    streams = [torch.cuda.Stream() for _ in range(3)]
+    run = aarmr.BatchRun(jobs, streams)
+    seen = []
+    t0 = time.perf_counter()
+    while True:
+        n = run.poll()
+        if not seen or seen[-1] != n:
+            seen.append(n)
+        if n == len(jobs) or time.perf_counter() - t0 > 60.0:
+            break
+        time.sleep(0.001)
+    comp, code = run.wait()
+    log(f"  progress seen: {seen}")
+    assert code == aarmr.OK and seen[-1] == len(jobs)
+    assert seen == sorted(seen)
+    assert all(run.items[i].done == 1 and run.items[i].status == aarmr.OK for i in range(len(jobs)))
+    ref = [_instance(i, sz, aarmr.FP64) for i, sz in enumerate(sizes)]
+    comp_ref, _, code_ref = aarmr.batch_solve(ref, streams)
+    assert code_ref == aarmr.OK
+    for a, b in zip(jobs, ref):
+        assert torch.equal(a["u"], b["u"])
+    assert comp == comp_ref
