@@ -933,23 +933,7 @@ int refine(aarmr_mesh* m, double* x, int* iters, double* relres, bool* fallback,
   return fail(AARMR_E_NOT_CONVERGED, "refinement reached cg_maxit before cg_rtol");
 }
 
-int pcg64(aarmr_mesh* m, double* x, int* iters, double* relres, int maxit_in, bool use32,
-          hipStream_t s);
-
-// z = M^-1 r: the FP64 V-cycle, or (use32) the FP32 V-cycle on r converted to
-// FP32 (scaled to unit norm; rr = ||r||^2 on the device).
-int precond(aarmr_mesh* m, const double* r, const double* rr, double* z, bool use32,
-            hipStream_t s) {
-  if (!use32) return vcycle(m, 0, r, z, s);
-  const int64_t n3 = ndof(m, 0);
-  launch_to_f32_scaled(n3, r, rr, m->r32, s);
-  KCHECK();
-  TRY(vcycle32(m, 0, m->r32, m->z32, s));
-  HIP_TRY(hipMemsetAsync(z, 0, n3 * sizeof(double), s));
-  launch_add_scaled_f32(n3, m->z32, rr, z, s);
-  KCHECK();
-  return AARMR_OK;
-}
+int pcg64(aarmr_mesh* m, double* x, int* iters, double* relres, int maxit_in, hipStream_t s);
 
 // Preconditioned CG on A x = fm (fm already masked), x in/out (masked).  In
 // the refinement form the FP32 refinement runs first; if it hands over, FP64
@@ -964,14 +948,13 @@ int pcg(aarmr_mesh* m, double* x, int* iters, double* relres, hipStream_t s) {
       return rc;
     }
   }
-  const int rc = pcg64(m, x, iters, relres, std::min(m->p.cg_maxit, kMaxIt) - it0, false, s);
+  const int rc = pcg64(m, x, iters, relres, std::min(m->p.cg_maxit, kMaxIt) - it0, s);
   *iters += it0;
   return rc;
 }
 
-// CG with the V-cycle preconditioner (precond) for at most maxit iterations.
-int pcg64(aarmr_mesh* m, double* x, int* iters, double* relres, int maxit_in, bool use32,
-          hipStream_t s) {
+// CG with the FP64 V-cycle preconditioner for at most maxit iterations.
+int pcg64(aarmr_mesh* m, double* x, int* iters, double* relres, int maxit_in, hipStream_t s) {
   const Grid& g = m->lg[0];
   const int64_t n3 = ndof(m, 0);
   double* sc = m->scal;
@@ -1007,11 +990,11 @@ int pcg64(aarmr_mesh* m, double* x, int* iters, double* relres, int maxit_in, bo
   }
   *relres = std::sqrt(rr / ff);
   if (rr <= tol2) return AARMR_OK;
-  TRY(precond(m, m->r, sc + SC_RR, m->z, use32, s));
+  TRY(vcycle(m, 0, m->r, m->z, s));
   TRY(dot1(m, m->r, m->z, sc + SC_RZ, n3, s));
   HIP_TRY(hipMemcpyAsync(m->pv, m->z, n3 * sizeof(double), hipMemcpyDeviceToDevice, s));
   const int maxit = std::max(0, maxit_in);
-  if (!use32) {
+  {
     // reductions folded into the updates: p^T q finished by the x/r update,
     // r^T r summed on the host from its block partials, r^T z finished by the
     // p update; the update also forms the V-cycle's first sweep.  While the
@@ -1048,25 +1031,6 @@ int pcg64(aarmr_mesh* m, double* x, int* iters, double* relres, int maxit_in, bo
       if (!(hrr[nb] > 0.0)) return fail(AARMR_E_SINGULAR, "CG: p^T A p <= 0");
       if (rr <= tol2) return AARMR_OK;
     }
-    return fail(AARMR_E_NOT_CONVERGED, "CG reached cg_maxit before cg_rtol");
-  }
-  for (int it = 0; it < maxit; ++it) {
-    TRY(apply(m, 0, m->pv, m->q, s));
-    TRY(dot1(m, m->pv, m->q, sc + SC_PQ + it, n3, s));
-    launch_cg_xr(n3, sc + SC_RZ + it, sc + SC_PQ + it, x, m->r, m->pv, m->q, s);
-    KCHECK();
-    TRY(dot1(m, m->r, m->r, sc + SC_RR + it + 1, n3, s));
-    const double* src[2] = {sc + SC_RR + it + 1, sc + SC_PQ + it};
-    TRY(read_scalars(m, src, 2, h, s));
-    *iters = it + 1;
-    rr = h[0];
-    *relres = std::sqrt(rr / ff);
-    if (!(h[1] > 0.0)) return fail(AARMR_E_SINGULAR, "CG: p^T A p <= 0");
-    if (rr <= tol2) return AARMR_OK;
-    TRY(precond(m, m->r, sc + SC_RR + it + 1, m->z, use32, s));
-    TRY(dot1(m, m->r, m->z, sc + SC_RZ + it + 1, n3, s));
-    launch_cg_p(n3, sc + SC_RZ + it + 1, sc + SC_RZ + it, m->z, m->pv, s);
-    KCHECK();
   }
   return fail(AARMR_E_NOT_CONVERGED, "CG reached cg_maxit before cg_rtol");
 }

@@ -171,10 +171,6 @@ void launch_copy_f32(int64_t n, const float* src, float* dst, hipStream_t s);
 void launch_copy_masked(const Grid& g, const double* src, const uint8_t* mask, double* dst,
                         hipStream_t s, int ncomp = 3);
 void launch_sub(int64_t n, const double* a, const double* b, double* out, hipStream_t s);
-void launch_cg_xr(int64_t n, const double* rz, const double* pq, double* x, double* r,
-                  const double* p, const double* q, hipStream_t s);
-void launch_cg_p(int64_t n, const double* rz_new, const double* rz_old, const double* z,
-                 double* p, hipStream_t s);
 // CG with folded reductions.  dot_blocks(n): the block count of one dot's
 // partials; fused_blocks(n): that of the fused updates (each finishes the
 // dot partials it needs); launch_dot_partials writes a^T b's partials to

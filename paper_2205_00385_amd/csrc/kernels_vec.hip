@@ -147,27 +147,6 @@ __global__ void k_sub(int64_t n, const double* __restrict__ a, const double* __r
   if (i < n) out[i] = a[i] - b[i];
 }
 
-// alpha = rz / pq; x += alpha p; r -= alpha q.
-__global__ void k_cg_xr(int64_t n, const double* __restrict__ rz, const double* __restrict__ pq,
-                        double* __restrict__ x, double* __restrict__ r,
-                        const double* __restrict__ p, const double* __restrict__ q) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const double alpha = *rz / *pq;
-  x[i] = fma(alpha, p[i], x[i]);
-  r[i] = fma(-alpha, q[i], r[i]);
-}
-
-// beta = rz_new / rz_old; p = z + beta p.
-__global__ void k_cg_p(int64_t n, const double* __restrict__ rz_new,
-                       const double* __restrict__ rz_old, const double* __restrict__ z,
-                       double* __restrict__ p) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const double beta = *rz_new / *rz_old;
-  p[i] = fma(beta, p[i], z[i]);
-}
-
 __global__ void k_scale_inv_sqrt(int64_t n, const double* __restrict__ src,
                                  const double* __restrict__ nrm2, double* __restrict__ dst) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -410,15 +389,6 @@ void launch_sub(int64_t n, const double* a, const double* b, double* out, hipStr
   k_sub<<<nblk(n, 256), 256, 0, s>>>(n, a, b, out);
 }
 
-void launch_cg_xr(int64_t n, const double* rz, const double* pq, double* x, double* r,
-                  const double* p, const double* q, hipStream_t s) {
-  k_cg_xr<<<nblk(n, 256), 256, 0, s>>>(n, rz, pq, x, r, p, q);
-}
-
-void launch_cg_p(int64_t n, const double* rz_new, const double* rz_old, const double* z,
-                 double* p, hipStream_t s) {
-  k_cg_p<<<nblk(n, 256), 256, 0, s>>>(n, rz_new, rz_old, z, p);
-}
 
 void launch_scale_by_inv_sqrt(int64_t n, const double* src, const double* nrm2, double* dst,
                               hipStream_t s) {
