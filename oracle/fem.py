@@ -97,6 +97,29 @@ def element_dofs(nx: int, ny: int, nz: int) -> np.ndarray:
     return edof
 
 
+def element_dofs_grid(nx: int, ny: int, nz: int) -> np.ndarray:
+    """element_dofs built with array operations (same numbering), for grids
+    too large for the element loop."""
+    k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    i, j, k = i.ravel(), j.ravel(), k.ravel()  # element order e = i + nx (j + ny k)
+    cols = []
+    for a in range(8):
+        di, dj, dk = local_corner(a)
+        n = node_id(nx, ny, i + di, j + dj, k + dk)
+        cols += [3 * n + c for c in range(3)]
+    return np.stack(cols, axis=1).astype(np.int64)
+
+
+def apply_ebe(nx: int, ny: int, nz: int, Ee: np.ndarray, KE: np.ndarray, v: np.ndarray,
+              edof: np.ndarray = None) -> np.ndarray:
+    """K v = sum_e E_e L_e^T KE L_e v element by element, without assembling
+    K (eq. 7's product for grids whose assembled K would not fit); AoS."""
+    if edof is None:
+        edof = element_dofs_grid(nx, ny, nz)
+    ye = (np.asarray(v)[edof] @ KE.T) * np.asarray(Ee, dtype=np.float64)[:, None]
+    return np.bincount(edof.ravel(), weights=ye.ravel(), minlength=3 * (nx + 1) * (ny + 1) * (nz + 1))
+
+
 def assemble(nx: int, ny: int, nz: int, Ee: np.ndarray, KE: np.ndarray) -> sp.csr_matrix:
     """Global stiffness K = sum_e E_e L_e^T KE L_e (no boundary conditions)."""
     edof = element_dofs(nx, ny, nz)

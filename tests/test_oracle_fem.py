@@ -188,3 +188,17 @@ def test_sensitivity_central_difference_two_cases():
     Cp = sum(sens.analyse(prob, rp, KE)[1])
     Cm = sum(sens.analyse(prob, rm, KE)[1])
     assert abs((Cp - Cm) / (2 * h) - dc[e]) < 1e-6 * abs(dc[e])
+
+
+def test_vectorised_element_dofs_and_product_match_assembly():
+    """The array-built element DOF table equals the loop-built one, and the
+    element-by-element product equals the assembled K times v."""
+    nx, ny, nz = 5, 3, 2
+    assert np.array_equal(fem.element_dofs_grid(nx, ny, nz), fem.element_dofs(nx, ny, nz))
+    rng = np.random.default_rng(19)
+    Ee = rng.uniform(0.1, 1.0, nx * ny * nz)
+    KE = fem.hex8_ke()
+    v = rng.standard_normal(3 * (nx + 1) * (ny + 1) * (nz + 1))
+    K = fem.assemble(nx, ny, nz, Ee, KE)
+    y = fem.apply_ebe(nx, ny, nz, Ee, KE, v)
+    assert np.abs(y - K @ v).max() <= 1e-14 * np.abs(K @ v).max()
