@@ -139,6 +139,12 @@ struct aarmr_mesh {
   bool mg_ready = false;
   double* hpin = nullptr;  // pinned host staging
   hipEvent_t ev_cg = nullptr;  // marks a CG iteration's scalar read-back
+  // speculative hierarchy build beside the reduced-model step
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fine = nullptr, ev_mg = nullptr;
+  bool mg_pending = false;     // a build on `side` not yet joined into the caller's stream
+  bool spec_mg = false;        // the last reduced-model attempt was rejected
+  int oc_pairs = 0;            // OC launch pairs the last update needed
   int64_t sweeps = 0;
 };
 
@@ -685,17 +691,11 @@ int vcycle(aarmr_mesh* m, int l, const double* b, double* x, hipStream_t s,
   return AARMR_OK;
 }
 
-// SIMP moduli, mask and the MG hierarchy for the density rho~.
-int setup(aarmr_mesh* m, const double* rho, const int64_t* fixed, int64_t nfixed, bool build_mg,
-          hipStream_t s) {
+// The MG hierarchy of the current moduli and mask (Algorithm 2's operators):
+// Jacobi diagonals, Galerkin operators of the coarse levels, the coarsest
+// dense inverse.  Reads E, mask and the element matrices only.
+int build_mg(aarmr_mesh* m, hipStream_t s) {
   const Grid& g = m->lg[0];
-  launch_build_mask(g.nn, fixed, nfixed, m->mask, m->flags, s, m->dim);
-  KCHECK();
-  launch_simp(g.ne, rho, m->p.E0, m->p.Emin, m->p.penal, m->E, m->fp32 ? m->E32 : nullptr,
-              m->flags, s);
-  KCHECK();
-  m->mg_ready = false;
-  if (!build_mg) return AARMR_OK;
   if (m->dim == 2) {
     launch_q4_diag(g, m->KEd, m->E, m->mask, m->lv[0].dinv, s);
     launch_springs_diag(m->springs, g, m->mask, m->lv[0].dinv, s);
@@ -744,6 +744,29 @@ int setup(aarmr_mesh* m, const double* rho, const int64_t* fixed, int64_t nfixed
   KCHECK();
   m->mg_ready = true;
   return AARMR_OK;
+}
+
+// Make stream s wait for a speculative hierarchy build, if one is in flight.
+int join_mg(aarmr_mesh* m, hipStream_t s) {
+  if (!m->mg_pending) return AARMR_OK;
+  m->mg_pending = false;
+  HIP_TRY(hipStreamWaitEvent(s, m->ev_mg, 0));
+  return AARMR_OK;
+}
+
+// Fixed-DOF mask and SIMP moduli of the density rho~; with_mg: also the hierarchy.
+int setup(aarmr_mesh* m, const double* rho, const int64_t* fixed, int64_t nfixed, bool with_mg,
+          hipStream_t s) {
+  TRY(join_mg(m, s));
+  const Grid& g = m->lg[0];
+  launch_build_mask(g.nn, fixed, nfixed, m->mask, m->flags, s, m->dim);
+  KCHECK();
+  launch_simp(g.ne, rho, m->p.E0, m->p.Emin, m->p.penal, m->E, m->fp32 ? m->E32 : nullptr,
+              m->flags, s);
+  KCHECK();
+  m->mg_ready = false;
+  if (!with_mg) return AARMR_OK;
+  return build_mg(m, s);
 }
 
 // ---- refinement form: FP32 inner solve ------------------------------------
@@ -1225,6 +1248,9 @@ void aarmr_mesh_destroy(aarmr_mesh* m) {
   if (!m) return;
   if (m->hpin) (void)hipHostFree(m->hpin);
   if (m->ev_cg) (void)hipEventDestroy(m->ev_cg);
+  if (m->ev_fine) (void)hipEventDestroy(m->ev_fine);
+  if (m->ev_mg) (void)hipEventDestroy(m->ev_mg);
+  if (m->side) (void)hipStreamDestroy(m->side);
   delete m;
 }
 
@@ -1233,6 +1259,8 @@ int64_t aarmr_workspace_bytes(const aarmr_mesh* m) {
   aarmr_mesh tmp = *m;
   tmp.hpin = nullptr;
   tmp.ev_cg = nullptr;
+  tmp.ev_fine = tmp.ev_mg = nullptr;
+  tmp.side = nullptr;
   return layout(&tmp, nullptr);
 }
 
@@ -1243,6 +1271,10 @@ int aarmr_bind_workspace(aarmr_mesh* m, void* dev_ptr, int64_t bytes, void* stre
   if (bytes < need) return fail(AARMR_E_NO_WORKSPACE, "workspace too small");
   if (!m->hpin) HIP_TRY(hipHostMalloc((void**)&m->hpin, 4096 * sizeof(double), hipHostMallocDefault));
   if (!m->ev_cg) HIP_TRY(hipEventCreateWithFlags(&m->ev_cg, hipEventDisableTiming));
+  if (!m->ev_fine) HIP_TRY(hipEventCreateWithFlags(&m->ev_fine, hipEventDisableTiming));
+  if (!m->ev_mg) HIP_TRY(hipEventCreateWithFlags(&m->ev_mg, hipEventDisableTiming));
+  // default priority; non-blocking so that it does not serialise with the null stream
+  if (!m->side) HIP_TRY(hipStreamCreateWithFlags(&m->side, hipStreamNonBlocking));
   m->ws = static_cast<char*>(dev_ptr);
   m->ws_bytes = bytes;
   layout(m, m->ws);
@@ -1408,6 +1440,23 @@ int aarmr_ca_update(aarmr_mesh* m, const double* rho, const double* f, int32_t n
   }
   TRY(setup(m, rho_phys, fixed_dofs, n_fixed, false, s));
   TRY(finish_flags(m, s));
+  // Algorithm 1 needs the MG hierarchy only when the reduced model is
+  // rejected.  After a rejection, the next attempt builds it on a second
+  // stream while the reduced model runs (both read the new moduli; neither
+  // writes what the other reads); the fallback and the return wait for it.
+  struct JoinOnExit {
+    aarmr_mesh* m;
+    hipStream_t s;
+    ~JoinOnExit() { (void)join_mg(m, s); }
+  } join_guard{m, s};
+  if (m->spec_mg) {
+    HIP_TRY(hipEventRecord(m->ev_fine, s));
+    HIP_TRY(hipStreamWaitEvent(m->side, m->ev_fine, 0));
+    TRY(build_mg(m, m->side));
+    HIP_TRY(hipEventRecord(m->ev_mg, m->side));
+    m->mg_pending = true;
+  }
+  bool any_rejected = false;
   launch_diff(g.ne, m->E, m->E_prev, m->dE, s);  // weights of dK = K - K0
   KCHECK();
   double* misc = m->scal + SC_MISC;
@@ -1542,8 +1591,10 @@ int aarmr_ca_update(aarmr_mesh* m, const double* rho, const double* f, int32_t n
     }
     if (!accept) {
       // Algorithm 1 lines 9-10: MGCG warm-started from u~, then PARM update
+      any_rejected = true;
       if (kept == 0) HIP_TRY(hipMemsetAsync(ul, 0, n3 * sizeof(double), s));
-      if (!m->mg_ready) TRY(setup(m, rho_phys, fixed_dofs, n_fixed, true, s));
+      TRY(join_mg(m, s));
+      if (!m->mg_ready) TRY(build_mg(m, s));
       int its = 0;
       double rel = 0.0;
       int rc = pcg(m, ul, &its, &rel, s);
@@ -1559,6 +1610,8 @@ int aarmr_ca_update(aarmr_mesh* m, const double* rho, const double* f, int32_t n
   }
   if (dc && mutual) TRY(mutual_dc(m, rho_phys, u, s));
   TRY(finish_dc(m, dc, flags, s));
+  TRY(join_mg(m, s));
+  m->spec_mg = any_rejected;
   HIP_TRY(hipMemcpyAsync(m->E_prev, m->E, g.ne * sizeof(double), hipMemcpyDeviceToDevice, s));
   HIP_TRY(hipStreamSynchronize(s));
   if (st) st->fine_sweeps = m->sweeps - sw0;
@@ -1605,16 +1658,21 @@ int aarmr_oc_update(aarmr_mesh* m, const double* x, const double* dc, const doub
   launch_oc_init(lam, s);
   KCHECK();
   // three bisection steps per launch pair, 200 at most (the kernels count
-  // them); the done flag is read every 12 steps
+  // them; pairs after the end return at once).  The done flag is first read
+  // after one pair more than the previous call needed, then every 4 pairs.
+  const int first = std::min(67, std::max(4, m->oc_pairs + 1));
   for (int it = 0; it < 67; ++it) {
     launch_oc_step3(g.ne, x, dc, dv, m->cw, move, m->p.oc_eta, lam, m->partial, nparts, s);
     launch_oc_bisect3(lam, m->partial, nparts, target, s);
     KCHECK();
-    if ((it & 3) == 3) {
-      double done;
-      const double* src = lam + 3;
-      TRY(read_scalars(m, &src, 1, &done, s));
-      if (done != 0.0) break;
+    if (it + 1 >= first && (it + 1 - first) % 4 == 0) {
+      double h[2];
+      const double* src[2] = {lam + 3, lam + 4};
+      TRY(read_scalars(m, src, 2, h, s));
+      if (h[0] != 0.0) {
+        m->oc_pairs = ((int)h[1] + 2) / 3;
+        break;
+      }
     }
   }
   launch_oc_final(g.ne, x, dc, dv, move, m->p.oc_eta, lam, x_new, s);
