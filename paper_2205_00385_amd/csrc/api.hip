@@ -131,6 +131,9 @@ struct aarmr_mesh {
   double* KR = nullptr;    // [Nm][3nn]
   double* scal = nullptr;
   double* partial = nullptr;
+  double *part_pq = nullptr, *part_rz = nullptr;  // per-workgroup partials of the fine products
+  bool want_rz = false;  // the V-cycle's last fine sweep also forms r^T z partials
+  int rz_nb = 0;         // how many it wrote (0: none)
   unsigned* flags = nullptr;
   // host state
   int phi_count[AARMR_MAX_RHS] = {};
@@ -440,6 +443,11 @@ int64_t layout(aarmr_mesh* m, char* base) {
   m->KR = (double*)take((int64_t)m->p.Nm * n3 * d8);
   m->scal = (double*)take(SC_TOTAL * d8);
   m->partial = (double*)take((int64_t)kRedSlots * kRedBlocks * d8);
+  if (m->dim == 3) {  // CG's p^T A p and r^T z partials from the fine-grid products
+    const int64_t cap = ebe_partials_max(m->lg[0]);
+    m->part_pq = (double*)take(cap * d8);
+    m->part_rz = (double*)take(cap * d8);
+  }
   m->flags = (unsigned*)take(64);
   return off;
 }
@@ -664,7 +672,11 @@ int vcycle(aarmr_mesh* m, int l, const double* b, double* x, hipStream_t s,
   for (int it = 0; it < m->p.nu_post; ++it) {        // line 5
     if (fuse && l == 0 && x == m->z && it == m->p.nu_post - 1) {
       // the solver's own z: the sweep writes into t0 and the two swap roles
-      launch_ebe_jacobi(G, m->wk, m->E, m->mask, x, b, L.dinv, om, m->t0, s, m->tz64);
+      if (m->want_rz)
+        m->rz_nb = launch_ebe_jacobi_dot(G, m->wk, m->E, m->mask, x, b, L.dinv, om, m->t0,
+                                         m->part_rz, s, m->tz64);
+      else
+        launch_ebe_jacobi(G, m->wk, m->E, m->mask, x, b, L.dinv, om, m->t0, s, m->tz64);
       ++m->sweeps;
       KCHECK();
       std::swap(m->z, m->t0);
@@ -1031,19 +1043,40 @@ int pcg64(aarmr_mesh* m, double* x, int* iters, double* relres, int maxit_in, hi
     const int nb = fused_blocks(n3);
     const bool z0 = m->p.nu_pre >= 1;
     double* hrr = m->hpin + 1024;
+    // 3D: p^T A p comes with the product and r^T z with the V-cycle's last
+    // fine sweep (workgroup partials of the EbE kernel)
+    const bool ebe_dots = m->dim == 3;
     for (int it = 0; it < maxit; ++it) {
-      TRY(apply(m, 0, m->pv, m->q, s));
-      launch_dot_partials(n3, m->pv, m->q, part_pq, s);
-      launch_cg_xr_fused(n3, sc + SC_RZ + it, part_pq, sc + SC_PQ + it, x, m->r, m->pv, m->q,
-                         part_rr, m->lv[0].dinv, m->p.omega, z0 ? m->z : nullptr, s);
+      int n_pq = 0;
+      if (ebe_dots) {
+        n_pq = launch_ebe_dot(g, m->wk, m->E, m->mask, m->pv, m->q, m->part_pq, s, m->tz64);
+        ++m->sweeps;
+        KCHECK();
+      } else {
+        TRY(apply(m, 0, m->pv, m->q, s));
+        launch_dot_partials(n3, m->pv, m->q, part_pq, s);
+      }
+      launch_cg_xr_fused(n3, sc + SC_RZ + it, ebe_dots ? m->part_pq : part_pq, n_pq,
+                         sc + SC_PQ + it, x, m->r, m->pv, m->q, part_rr, m->lv[0].dinv,
+                         m->p.omega, z0 ? m->z : nullptr, s);
       KCHECK();
       // r^T r partials and the finished p^T q (stored after them) in one copy
       HIP_TRY(hipMemcpyAsync(hrr, part_rr, (nb + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
       HIP_TRY(hipEventRecord(m->ev_cg, s));
       if (it + 1 < maxit) {
-        TRY(vcycle(m, 0, m->r, m->z, s, z0));
-        launch_dot_partials(n3, m->r, m->z, part_rz, s);
-        launch_cg_p_fused(n3, part_rz, sc + SC_RZ + it + 1, sc + SC_RZ + it, m->z, m->pv, s);
+        m->want_rz = ebe_dots;
+        m->rz_nb = 0;
+        const int rc = vcycle(m, 0, m->r, m->z, s, z0);
+        m->want_rz = false;
+        TRY(rc);
+        if (m->rz_nb > 0) {
+          launch_cg_p_fused(n3, m->part_rz, m->rz_nb, sc + SC_RZ + it + 1, sc + SC_RZ + it,
+                            m->z, m->pv, s);
+        } else {
+          launch_dot_partials(n3, m->r, m->z, part_rz, s);
+          launch_cg_p_fused(n3, part_rz, 0, sc + SC_RZ + it + 1, sc + SC_RZ + it, m->z, m->pv,
+                            s);
+        }
         KCHECK();
       }
       HIP_TRY(hipEventSynchronize(m->ev_cg));

@@ -68,6 +68,17 @@ void launch_ebe_f32(const Grid& g, const WalshConsts& K, const float* E, const u
 void launch_ebe_jacobi(const Grid& g, const WalshConsts& K, const double* E, const uint8_t* mask,
                        const double* v, const double* b, const double* dinv, double omega,
                        double* out, hipStream_t s, int tz = 0);
+// The same two products with CG's dot product folded in: each workgroup w
+// writes part[w], the sum over the nodes it owns of v . y (launch_ebe_dot,
+// mode 2: p^T A p) or b . out (launch_ebe_jacobi_dot: r^T z); the return
+// value is the number of partials.  part holds ebe_partials_max(g) entries.
+int ebe_partials_max(const Grid& g);
+int launch_ebe_dot(const Grid& g, const WalshConsts& K, const double* E, const uint8_t* mask,
+                   const double* v, double* y, double* part, hipStream_t s, int tz = 0);
+int launch_ebe_jacobi_dot(const Grid& g, const WalshConsts& K, const double* E,
+                          const uint8_t* mask, const double* v, const double* b,
+                          const double* dinv, double omega, double* out, double* part,
+                          hipStream_t s, int tz = 0);
 void launch_energy_walsh(const Grid& g, const WalshConsts& K, const uint8_t* mask,
                          const double* u, double* energy, hipStream_t s);
 void launch_simp(int64_t ne, const double* rho, double E0, double Emin, double p, double* E,
@@ -179,16 +190,18 @@ int dot_blocks(int64_t n);
 int fused_blocks(int64_t n);
 void launch_dot_partials(int64_t n, const double* a, const double* b, double* part,
                          hipStream_t s);
-// pq finished from pq_part (stored to *pq and rr_part[fused_blocks(n)]);
-// x += alpha p, r -= alpha q with alpha = *rz / pq;
-// rr_part[0..fused_blocks(n)) = partials of r^T r;
+// pq finished from the n_part entries of pq_part (n_part <= 0: dot_blocks(n)),
+// stored to *pq and rr_part[fused_blocks(n)]; x += alpha p, r -= alpha q with
+// alpha = *rz / pq; rr_part[0..fused_blocks(n)) = partials of r^T r;
 // z0 = omega dinv r unless z0 is null.
-void launch_cg_xr_fused(int64_t n, const double* rz, const double* pq_part, double* pq, double* x,
-                        double* r, const double* p, const double* q, double* rr_part,
-                        const double* dinv, double omega, double* z0, hipStream_t s);
-// rz_new finished from rz_part (stored to *rz_new); p = z + (rz_new / *rz_old) p.
-void launch_cg_p_fused(int64_t n, const double* rz_part, double* rz_new, const double* rz_old,
-                       const double* z, double* p, hipStream_t s);
+void launch_cg_xr_fused(int64_t n, const double* rz, const double* pq_part, int n_part,
+                        double* pq, double* x, double* r, const double* p, const double* q,
+                        double* rr_part, const double* dinv, double omega, double* z0,
+                        hipStream_t s);
+// rz_new finished from the n_part entries of rz_part (n_part <= 0:
+// dot_blocks(n)), stored to *rz_new; p = z + (rz_new / *rz_old) p.
+void launch_cg_p_fused(int64_t n, const double* rz_part, int n_part, double* rz_new,
+                       const double* rz_old, const double* z, double* p, hipStream_t s);
 void launch_scale_by_inv_sqrt(int64_t n, const double* src, const double* nrm2, double* dst,
                               hipStream_t s);
 // out = sum_j coef[j] * V_j (+ add) with coefficients read from device memory

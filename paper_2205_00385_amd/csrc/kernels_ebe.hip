@@ -115,16 +115,21 @@ struct PlaneRaw {
 // PF: prefetch distance in node planes (1 or 2).  JAC: the product feeds a
 // damped-Jacobi sweep, y = v + omega jd (jb - A v) (y distinct from v); the
 // node's own v, jb and jd are fetched one plane ahead like the moduli.
+// DOT: the workgroup also writes part[blockIdx.x], the sum over the nodes it
+// owns of d . y with d = jb (JAC) or d = v: the partials of CG's r^T z or
+// p^T A p, summed in a fixed order by the kernel that consumes them.
 #ifndef AARMR_EBE_MINB
 #define AARMR_EBE_MINB 1  // workgroups per CU the register budget is sized for
 #endif
-template <typename T, bool MASK_IN, int PF, bool JAC>
+template <typename T, bool MASK_IN, int PF, bool JAC, bool DOT>
 __global__ void __launch_bounds__(kThreads, AARMR_EBE_MINB) k_ebe_z(int nx, int ny, int nz, int gx, int gy, int TZ,
                                                     WalshConsts K, const T* __restrict__ E,
                                                     const uint8_t* __restrict__ mask,
                                                     const T* __restrict__ v, T* __restrict__ y,
                                                     const T* __restrict__ jb,
-                                                    const T* __restrict__ jd, T omega) {
+                                                    const T* __restrict__ jd, T omega,
+                                                    T* __restrict__ part) {
+  constexpr bool OWNV = JAC || DOT;  // keep the node's own v of the plane written next
   __shared__ T xs[2][3][kRows][kLanes];
   const int tx = threadIdx.x & (kLanes - 1), ty = threadIdx.x / kLanes;
   // XCD-aware tile order: workgroups are dispatched round-robin over the 8
@@ -215,6 +220,7 @@ __global__ void __launch_bounds__(kThreads, AARMR_EBE_MINB) k_ebe_z(int nx, int 
   }
   uint32_t own_m = 7u;  // fixed-DOF mask of node (i, j) on the plane written next
   T own_v[3] = {}, own_b[3] = {}, own_d[3] = {};  // JAC: that node's v, jb, jd
+  T dacc = (T)0;                                   // DOT: this thread's share
 #pragma unroll
   for (int q = 0; q < 4; ++q)
 #pragma unroll
@@ -229,11 +235,14 @@ __global__ void __launch_bounds__(kThreads, AARMR_EBE_MINB) k_ebe_z(int nx, int 
     const T w = W;
     const uint32_t m_next = R.m0;
     T v_next[3], b_next[3], d_next[3];
-    if (JAC) {  // node (i, j) of plane k + 1, written by the next step
+    if (OWNV) {  // node (i, j) of plane k + 1, written by the next step
+#pragma unroll
+      for (int c = 0; c < 3; ++c) v_next[c] = R.q0[c];
+    }
+    if (JAC) {
       const uint32_t on = (own && k + 1 <= nz) ? (uint32_t)((k + 1) * plane + off00) * TS : kOutside;
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        v_next[c] = R.q0[c];
         b_next[c] = ld(rjb, on + (uint32_t)c * cstride, T());
         d_next[c] = ld(rjd, on + (uint32_t)c * cstride, T());
       }
@@ -283,13 +292,17 @@ __global__ void __launch_bounds__(kThreads, AARMR_EBE_MINB) k_ebe_z(int nx, int 
       if (JAC) out = own_v[c] + omega * own_d[c] * (own_b[c] - out);
       if ((own_m >> c) & 1u) out = (T)0;
       st(ry, oy + (uint32_t)c * cstride, out);
+      if (DOT) dacc += wr ? (JAC ? own_b[c] : own_v[c]) * out : (T)0;
     }
     buf ^= 1;
     own_m = m_next;
+    if (OWNV) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) own_v[c] = v_next[c];
+    }
     if (JAC) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        own_v[c] = v_next[c];
         own_b[c] = b_next[c];
         own_d[c] = d_next[c];
       }
@@ -301,6 +314,14 @@ __global__ void __launch_bounds__(kThreads, AARMR_EBE_MINB) k_ebe_z(int nx, int 
       if (PF == 2) step(k + 1, RB, WB, P1, P0);
       else step(k + 1, RA, WA, P1, P0);
     }
+  }
+  if (DOT) {  // wavefront sums, then the four in wave order
+    __shared__ T wsum[kThreads / 64];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) dacc += __shfl_down(dacc, off, 64);
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = dacc;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = (wsum[0] + wsum[1]) + (wsum[2] + wsum[3]);
   }
 }
 
@@ -374,17 +395,17 @@ __global__ void k_identity_rows(int64_t nn, const uint8_t* __restrict__ mask,
 #define AARMR_EBE_PF 1
 #endif
 
-template <typename T, bool MASK_IN, bool JAC = false>
-static void launch_ebe_t(const Grid& g, const WalshConsts& K, const T* E, const uint8_t* mask,
-                         const T* v, T* y, int tz_req, hipStream_t s, const T* jb = nullptr,
-                         const T* jd = nullptr, T omega = 0) {
+template <typename T, bool MASK_IN, bool JAC = false, bool DOT = false>
+static int launch_ebe_t(const Grid& g, const WalshConsts& K, const T* E, const uint8_t* mask,
+                        const T* v, T* y, int tz_req, hipStream_t s, const T* jb = nullptr,
+                        const T* jd = nullptr, T omega = 0, T* part = nullptr) {
   // resident workgroups of this kernel on the device (thread-safe one-time init)
   static const int slots = [] {
     int dev = 0, cus = 0, per_cu = 0;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &per_cu, k_ebe_z<T, MASK_IN, AARMR_EBE_PF, JAC>, kThreads, 0);
+        &per_cu, k_ebe_z<T, MASK_IN, AARMR_EBE_PF, JAC, DOT>, kThreads, 0);
     return (cus > 0 && per_cu > 0) ? cus * per_cu : 512;
   }();
   const int gx = (g.nx + 1 + kTileX - 1) / kTileX;
@@ -396,8 +417,29 @@ static void launch_ebe_t(const Grid& g, const WalshConsts& K, const T* E, const 
   if (tz_req > 0) tz = tz_req < planes ? tz_req : planes;  // tuned z-chunk length
   if (tz < 4) tz = 4;
   gz = (planes + tz - 1) / tz;
-  k_ebe_z<T, MASK_IN, AARMR_EBE_PF, JAC><<<(unsigned)(gx * gy * gz), kThreads, 0, s>>>(
-      g.nx, g.ny, g.nz, gx, gy, tz, K, E, mask, v, y, jb, jd, omega);
+  k_ebe_z<T, MASK_IN, AARMR_EBE_PF, JAC, DOT><<<(unsigned)(gx * gy * gz), kThreads, 0, s>>>(
+      g.nx, g.ny, g.nz, gx, gy, tz, K, E, mask, v, y, jb, jd, omega, part);
+  return gx * gy * gz;
+}
+
+int ebe_partials_max(const Grid& g) {
+  const int gx = (g.nx + 1 + kTileX - 1) / kTileX;
+  const int gy = (g.ny + 1 + kTileY - 1) / kTileY;
+  return gx * gy * ((g.nz + 1 + 3) / 4);
+}
+
+int launch_ebe_dot(const Grid& g, const WalshConsts& K, const double* E, const uint8_t* mask,
+                   const double* v, double* y, double* part, hipStream_t s, int tz) {
+  return launch_ebe_t<double, false, false, true>(g, K, E, mask, v, y, tz, s, nullptr, nullptr,
+                                                  0.0, part);
+}
+
+int launch_ebe_jacobi_dot(const Grid& g, const WalshConsts& K, const double* E,
+                          const uint8_t* mask, const double* v, const double* b,
+                          const double* dinv, double omega, double* out, double* part,
+                          hipStream_t s, int tz) {
+  return launch_ebe_t<double, false, true, true>(g, K, E, mask, v, out, tz, s, b, dinv, omega,
+                                                 part);
 }
 
 void launch_ebe(const Grid& g, const WalshConsts& K, const double* E, const uint8_t* mask,

@@ -585,31 +585,47 @@ __global__ void k_jacobi_update(int64_t n3, const T* __restrict__ b, const T* __
 }
 
 // Dense coarsest operator in SoA DOF order (c * nn + node); thread per row.
-__global__ void k_assemble_dense(int nx, int ny, int nz, const double* __restrict__ Ke,
-                                 double* __restrict__ A) {
+// One wavefront per row, lanes over the columns (coalesced): an entry is the
+// sum, over the elements around the row's node in corner order a = 0..7, of
+// the element matrices' entries coupling the two nodes; zero for columns
+// outside the 27-node neighbourhood.  A row with zero diagonal (a coarse DOF
+// no free fine DOF interpolates from) becomes an identity row.
+__global__ void __launch_bounds__(256) k_assemble_dense(int nx, int ny, int nz,
+                                                        const double* __restrict__ Ke,
+                                                        double* __restrict__ A) {
   const int64_t nn = (int64_t)(nx + 1) * (ny + 1) * (nz + 1);
   const int64_t ne = (int64_t)nx * ny * nz;
   const int64_t nd = 3 * nn;
-  int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (row >= nd) return;
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= nd) return;  // wave-uniform
   const int c = (int)(row / nn);
   const int64_t n = row % nn;
-  double* Ar = A + row * nd;
-  for (int64_t t = 0; t < nd; ++t) Ar[t] = 0.0;
   const int i = (int)(n % (nx + 1));
-  const int64_t rest = n / (nx + 1);
-  const int j = (int)(rest % (ny + 1));
-  const int k = (int)(rest / (ny + 1));
-  for (int a = 0; a < 8; ++a) {
-    const int ex = i - (a & 1), ey = j - ((a >> 1) & 1), ez = k - (a >> 2);
-    if (ex < 0 || ex >= nx || ey < 0 || ey >= ny || ez < 0 || ez >= nz) continue;
-    const int64_t e = (int64_t)ex + (int64_t)nx * ((int64_t)ey + (int64_t)ny * ez);
-    for (int b = 0; b < 8; ++b) {
-      const int64_t nb = node_of(nx, ny, ex + (b & 1), ey + ((b >> 1) & 1), ez + (b >> 2));
-      for (int cc = 0; cc < 3; ++cc) Ar[cc * nn + nb] += Ke[(int64_t)sidx(3 * a + c, 3 * b + cc) * ne + e];
+  const int j = (int)((n / (nx + 1)) % (ny + 1));
+  const int k = (int)(n / ((int64_t)(nx + 1) * (ny + 1)));
+  double* Ar = A + row * nd;
+  for (int64_t t = lane; t < nd; t += 64) {
+    const int cc = (int)(t / nn);
+    const int64_t nb = t % nn;
+    const int bi = (int)(nb % (nx + 1));
+    const int bj = (int)((nb / (nx + 1)) % (ny + 1));
+    const int bk = (int)(nb / ((int64_t)(nx + 1) * (ny + 1)));
+    double acc = 0.0;
+    if (abs(bi - i) <= 1 && abs(bj - j) <= 1 && abs(bk - k) <= 1) {
+      for (int a = 0; a < 8; ++a) {
+        const int ex = i - (a & 1), ey = j - ((a >> 1) & 1), ez = k - (a >> 2);
+        if (ex < 0 || ex >= nx || ey < 0 || ey >= ny || ez < 0 || ez >= nz) continue;
+        const int dx = bi - ex, dy = bj - ey, dz = bk - ez;  // corner of nb in element e
+        if (dx < 0 || dx > 1 || dy < 0 || dy > 1 || dz < 0 || dz > 1) continue;
+        const int b = dx + 2 * dy + 4 * dz;
+        const int64_t e = (int64_t)ex + (int64_t)nx * ((int64_t)ey + (int64_t)ny * ez);
+        acc += Ke[(int64_t)sidx(3 * a + c, 3 * b + cc) * ne + e];
+      }
     }
+    if (t == row && acc == 0.0) acc = 1.0;  // dead coarse DOF: identity row
+    Ar[t] = acc;
   }
-  if (Ar[row] == 0.0) Ar[row] = 1.0;  // dead coarse DOF: identity row
 }
 
 // ---- blocked Gauss-Jordan inversion of an SPD matrix (sweep operator) -----
@@ -1097,7 +1113,7 @@ void launch_jacobi_update(int64_t n3, const double* b, const double* t, const do
 }
 
 void launch_assemble_dense(const Grid& g, const double* Ke, double* A, hipStream_t s) {
-  k_assemble_dense<<<nblk(3 * g.nn, 64), 64, 0, s>>>(g.nx, g.ny, g.nz, Ke, A);
+  k_assemble_dense<<<(unsigned)((3 * g.nn + 3) / 4), 256, 0, s>>>(g.nx, g.ny, g.nz, Ke, A);
 }
 
 void launch_gj_invert(int n, double* A, double* P, double* T, double* C, hipStream_t s) {

@@ -262,28 +262,39 @@ __global__ void k_springs_galerkin(SpringSet S, int cnx, int cny, const uint8_t*
   }
 }
 
-// Dense coarsest operator in SoA DOF order (c * nn + node); thread per row.
-__global__ void k_q4_assemble_dense(int nx, int ny, const double* __restrict__ Ke,
-                                    double* __restrict__ A) {
+// Dense coarsest operator in SoA DOF order (c * nn + node); one wavefront
+// per row, lanes over the columns: an entry sums, over the elements around
+// the row's node in corner order a = 0..3, the entries coupling the two nodes.
+__global__ void __launch_bounds__(256) k_q4_assemble_dense(int nx, int ny,
+                                                           const double* __restrict__ Ke,
+                                                           double* __restrict__ A) {
   const int64_t nn = (int64_t)(nx + 1) * (ny + 1);
   const int64_t ne = (int64_t)nx * ny;
-  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (row >= 2 * nn) return;
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= 2 * nn) return;  // wave-uniform
   const int c = (int)(row / nn);
   const int64_t n = row % nn;
   const int i = (int)(n % (nx + 1)), j = (int)(n / (nx + 1));
   double* Ar = A + row * 2 * nn;
-  for (int64_t q = 0; q < 2 * nn; ++q) Ar[q] = 0.0;
-  for (int a = 0; a < 4; ++a) {
-    const int ex = i - (a & 1), ey = j - (a >> 1);
-    if (ex < 0 || ex >= nx || ey < 0 || ey >= ny) continue;
-    const int64_t e = (int64_t)ex + (int64_t)nx * ey;
-    for (int b = 0; b < 4; ++b) {
-      const int64_t nb = (int64_t)(ex + (b & 1)) + (int64_t)(nx + 1) * (ey + (b >> 1));
-      for (int d = 0; d < 2; ++d) Ar[d * nn + nb] += Ke[(int64_t)s2(2 * a + c, 2 * b + d) * ne + e];
+  for (int64_t q = lane; q < 2 * nn; q += 64) {
+    const int d = (int)(q / nn);
+    const int64_t nb = q % nn;
+    const int bi = (int)(nb % (nx + 1)), bj = (int)(nb / (nx + 1));
+    double acc = 0.0;
+    if (abs(bi - i) <= 1 && abs(bj - j) <= 1) {
+      for (int a = 0; a < 4; ++a) {
+        const int ex = i - (a & 1), ey = j - (a >> 1);
+        if (ex < 0 || ex >= nx || ey < 0 || ey >= ny) continue;
+        const int dx = bi - ex, dy = bj - ey;
+        if (dx < 0 || dx > 1 || dy < 0 || dy > 1) continue;
+        const int64_t e = (int64_t)ex + (int64_t)nx * ey;
+        acc += Ke[(int64_t)s2(2 * a + c, 2 * (dx + 2 * dy) + d) * ne + e];
+      }
     }
+    if (q == row && acc == 0.0) acc = 1.0;  // dead coarse DOF: identity row
+    Ar[q] = acc;
   }
-  if (Ar[row] == 0.0) Ar[row] = 1.0;  // dead coarse DOF: identity row
 }
 
 }  // namespace
@@ -340,7 +351,7 @@ void launch_q4_diag_elemmat(const Grid& g, const double* Ke, double* dinv, hipSt
 }
 
 void launch_q4_assemble_dense(const Grid& g, const double* Ke, double* A, hipStream_t s) {
-  k_q4_assemble_dense<<<nblk(2 * g.nn, 64), 64, 0, s>>>(g.nx, g.ny, Ke, A);
+  k_q4_assemble_dense<<<(unsigned)((2 * g.nn + 3) / 4), 256, 0, s>>>(g.nx, g.ny, Ke, A);
 }
 
 }  // namespace aarmr

@@ -340,16 +340,18 @@ void launch_dot_partials(int64_t n, const double* a, const double* b, double* pa
   k_multidot<double><<<dot_blocks(n), 256, 0, s>>>(d, part);
 }
 
-void launch_cg_xr_fused(int64_t n, const double* rz, const double* pq_part, double* pq, double* x,
-                        double* r, const double* p, const double* q, double* rr_part,
-                        const double* dinv, double omega, double* z0, hipStream_t s) {
-  k_cg_xr_fused<<<fused_blocks(n), 256, 0, s>>>(n, rz, pq_part, dot_blocks(n), pq, x, r, p, q,
-                                                rr_part, dinv, omega, z0);
+void launch_cg_xr_fused(int64_t n, const double* rz, const double* pq_part, int n_part,
+                        double* pq, double* x, double* r, const double* p, const double* q,
+                        double* rr_part, const double* dinv, double omega, double* z0,
+                        hipStream_t s) {
+  k_cg_xr_fused<<<fused_blocks(n), 256, 0, s>>>(n, rz, pq_part, n_part > 0 ? n_part : dot_blocks(n),
+                                                pq, x, r, p, q, rr_part, dinv, omega, z0);
 }
 
-void launch_cg_p_fused(int64_t n, const double* rz_part, double* rz_new, const double* rz_old,
-                       const double* z, double* p, hipStream_t s) {
-  k_cg_p_fused<<<fused_blocks(n), 256, 0, s>>>(n, rz_part, dot_blocks(n), rz_new, rz_old, z, p);
+void launch_cg_p_fused(int64_t n, const double* rz_part, int n_part, double* rz_new,
+                       const double* rz_old, const double* z, double* p, hipStream_t s) {
+  k_cg_p_fused<<<fused_blocks(n), 256, 0, s>>>(n, rz_part, n_part > 0 ? n_part : dot_blocks(n),
+                                               rz_new, rz_old, z, p);
 }
 
 void launch_multidot_f32(const DotSetT<float>& d, const RedScratch& rs, hipStream_t s) {
