@@ -293,7 +293,7 @@ __device__ __forceinline__ void wht8(T* x, int s) {
 //   W Ke_e W / 64 = B'[kappa][lambda] * Ehat[mu(kappa) ^ mu(lambda)]
 // with B' = W M_0 W / 64 and Ehat the Walsh transform of the 8 child moduli:
 // y = W ((B' o Ehat) (W v)), about 256 FMA per thread.  Parents with eflag 1
-// are left to k_l1_masked, so no wave carries both paths.
+// are left to l1_masked_rows, so no wave carries both paths.
 template <typename T, int so>
 __device__ __forceinline__ void l1_elem(int nx, int ny, int nz, const double* __restrict__ Ke,
                                         const T* __restrict__ Bw, const T* __restrict__ Ef,
@@ -302,7 +302,7 @@ __device__ __forceinline__ void l1_elem(int nx, int ny, int nz, const double* __
   const int64_t nn = (int64_t)(nx + 1) * (ny + 1) * (nz + 1);
   const int64_t ne = (int64_t)nx * ny * nz;
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= ne || eflag[e]) return;  // flagged parents: k_l1_masked
+  if (e >= ne || eflag[e]) return;  // flagged parents: l1_masked_rows
   const int ex = (int)(e % nx);
   const int64_t rest = e / nx;
   const int ey = (int)(rest % ny), ez = (int)(rest / ny);
@@ -367,42 +367,60 @@ __device__ __forceinline__ void l1_elem(int nx, int ny, int nz, const double* __
 // stored Galerkin matrices: one thread per (listed parent, row r).
 // Rows come from the compact copy Kcomp[entry][w] (coalesced over list entries
 // w) while the list fits its capacity, else from Ke.  Thread (w, r): lanes run
-// over w, the row r is uniform per wave.
+// over w from chunk * 64 in steps of nchunk * 64; the row r is uniform per
+// wave.  Four corners' loads in flight at a time keep its registers within
+// those of the element path it shares a kernel with.
 template <typename T>
-__global__ void __launch_bounds__(256) k_l1_masked(int nx, int ny, int nz,
-                                                   const double* __restrict__ Ke,
-                                                   const double* __restrict__ Kcomp, int cap,
-                                                   const int* __restrict__ list, int cnt,
-                                                   const T* __restrict__ v, T* __restrict__ Y) {
+__device__ __forceinline__ void l1_masked_rows(int nx, int ny, int nz,
+                                               const double* __restrict__ Ke,
+                                               const double* __restrict__ Kcomp, int cap,
+                                               const int* __restrict__ list, int cnt,
+                                               const T* __restrict__ v, T* __restrict__ Y,
+                                               int chunk, int nchunk, int r) {
   const int64_t nn = (int64_t)(nx + 1) * (ny + 1) * (nz + 1);
   const int64_t ne = (int64_t)nx * ny * nz;
   const bool compact = cnt <= cap;
-  const int64_t stride = (int64_t)gridDim.x * 64;
-  const int r = blockIdx.y * 4 + (threadIdx.x >> 6);  // 6 x 4 waves: rows 0..23
-  for (int64_t w = (int64_t)blockIdx.x * 64 + (threadIdx.x & 63); w < cnt; w += stride) {
+  const int64_t stride = (int64_t)nchunk * 64;
+  for (int64_t w = (int64_t)chunk * 64 + (threadIdx.x & 63); w < cnt; w += stride) {
     const int64_t e = list[w];
     const int ex = (int)(e % nx);
     const int64_t rest = e / nx;
     const int ey = (int)(rest % ny), ez = (int)(rest / ny);
     T acc = 0;
-#pragma unroll
-    for (int q = 0; q < 24; ++q) {
-      const int b = q / 3, c = q % 3;
+#pragma unroll 4
+    for (int b = 0; b < 8; ++b) {  // corners in order, components within: q = 3b + c
       const int64_t nb = node_of(nx, ny, ex + (b & 1), ey + ((b >> 1) & 1), ez + (b >> 2));
-      const double k = compact ? Kcomp[(int64_t)sidx(r, q) * cap + w] : Ke[(int64_t)sidx(r, q) * ne + e];
-      acc = fma((T)k, v[c * nn + nb], acc);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const int q = 3 * b + c;
+        const double k =
+            compact ? Kcomp[(int64_t)sidx(r, q) * cap + w] : Ke[(int64_t)sidx(r, q) * ne + e];
+        acc = fma((T)k, v[c * nn + nb], acc);
+      }
     }
     Y[(int64_t)r * ne + e] = acc;
   }
 }
 
+// Pass 1 in one launch: workgroups x < nbe run the element path (grid.y:
+// output component); the rest run the flagged parents, two per grid.y, each
+// with four rows (one per wavefront) of a 64-entry chunk of the list.
 template <typename T>
 __global__ void __launch_bounds__(256) k_l1_elem(int nx, int ny, int nz,
                                                  const double* __restrict__ Ke,
                                                  const T* __restrict__ Bw,
                                                  const T* __restrict__ Ef,
                                                  const uint8_t* __restrict__ eflag,
-                                                 const T* __restrict__ v, T* __restrict__ Y) {
+                                                 const T* __restrict__ v, T* __restrict__ Y,
+                                                 int nbe, const double* __restrict__ Kcomp,
+                                                 int cap, const int* __restrict__ list, int cnt) {
+  if ((int)blockIdx.x >= nbe) {  // workgroup-uniform
+    const int mb = (int)blockIdx.x - nbe;
+    const int r = (int)(blockIdx.y * 2 + (mb & 1)) * 4 + (int)(threadIdx.x >> 6);
+    l1_masked_rows<T>(nx, ny, nz, Ke, Kcomp, cap, list, cnt, v, Y, mb >> 1,
+                      ((int)gridDim.x - nbe) >> 1, r);
+    return;
+  }
   switch (blockIdx.y) {  // output component
     case 0: l1_elem<T, 0>(nx, ny, nz, Ke, Bw, Ef, eflag, v, Y); break;
     case 1: l1_elem<T, 1>(nx, ny, nz, Ke, Bw, Ef, eflag, v, Y); break;
@@ -1019,11 +1037,11 @@ void l1_apply(const Grid& g, const double* Ke, const double* Kcomp, int cap, con
               const T* Ef, const uint8_t* eflag, const int* list, const int* count, int nflag,
               const T* v, T* Y, T* y, hipStream_t s, const T* jb = nullptr,
               const T* jd = nullptr, T omega = 0) {
-  k_l1_elem<T><<<dim3(nblk(g.ne, 256), 3), 256, 0, s>>>(g.nx, g.ny, g.nz, Ke, Bw, Ef, eflag, v, Y);
-  if (nflag > 0) {  // nflag: the flagged-parent count, known to the host after setup
-    const unsigned mb = (unsigned)std::min<int64_t>(nblk(nflag, 64), 256);
-    k_l1_masked<T><<<dim3(mb, 6), 256, 0, s>>>(g.nx, g.ny, g.nz, Ke, Kcomp, cap, list, nflag, v, Y);
-  }
+  // nflag: the flagged-parent count, known to the host after setup
+  const int nbe = (int)nblk(g.ne, 256);
+  const int nbm = nflag > 0 ? 2 * (int)std::min<int64_t>(nblk(nflag, 64), 256) : 0;
+  k_l1_elem<T><<<dim3(nbe + nbm, 3), 256, 0, s>>>(g.nx, g.ny, g.nz, Ke, Bw, Ef, eflag, v, Y, nbe,
+                                                  Kcomp, cap, list, nflag);
   k_l1_gather<T><<<nblk(g.nn, 256), 256, 0, s>>>(g.nx, g.ny, g.nz, Y, y, jb, jd, omega);
 }
 
