@@ -364,12 +364,12 @@ __device__ __forceinline__ void l1_elem(int nx, int ny, int nz, const double* __
 }
 
 // Level-1 element products of the flagged parents (list[0..cnt)) from their
-// stored Galerkin matrices: one thread per (listed parent, row r).
-// Rows come from the compact copy Kcomp[entry][w] (coalesced over list entries
-// w) while the list fits its capacity, else from Ke.  Thread (w, r): lanes run
-// over w from chunk * 64 in steps of nchunk * 64; the row r is uniform per
-// wave.  Four corners' loads in flight at a time keep its registers within
-// those of the element path it shares a kernel with.
+// stored Galerkin matrices.  Row r is uniform per wavefront; its lanes take
+// 16 list entries w (from chunk * 16 in steps of nchunk * 16), four lanes per
+// entry, each lane two corners (six columns q = 3b + c), so that all of a
+// lane's loads are in flight at once; the four sums are then added in a
+// fixed order.  Rows come from the compact copy Kcomp[entry][w] (coalesced
+// over w) while the list fits its capacity, else from Ke.
 template <typename T>
 __device__ __forceinline__ void l1_masked_rows(int nx, int ny, int nz,
                                                const double* __restrict__ Ke,
@@ -380,31 +380,40 @@ __device__ __forceinline__ void l1_masked_rows(int nx, int ny, int nz,
   const int64_t nn = (int64_t)(nx + 1) * (ny + 1) * (nz + 1);
   const int64_t ne = (int64_t)nx * ny * nz;
   const bool compact = cnt <= cap;
-  const int64_t stride = (int64_t)nchunk * 64;
-  for (int64_t w = (int64_t)chunk * 64 + (threadIdx.x & 63); w < cnt; w += stride) {
-    const int64_t e = list[w];
-    const int ex = (int)(e % nx);
-    const int64_t rest = e / nx;
-    const int ey = (int)(rest % ny), ez = (int)(rest / ny);
+  const int lane = threadIdx.x & 63, quarter = lane >> 4;
+  const int64_t stride = (int64_t)nchunk * 16;
+  // the loop bound is uniform per wavefront, so every lane reaches the shuffles
+  for (int64_t base = (int64_t)chunk * 16; base < cnt; base += stride) {
+    const int64_t w = base + (lane & 15);
     T acc = 0;
-#pragma unroll 4
-    for (int b = 0; b < 8; ++b) {  // corners in order, components within: q = 3b + c
-      const int64_t nb = node_of(nx, ny, ex + (b & 1), ey + ((b >> 1) & 1), ez + (b >> 2));
+    int64_t e = 0;
+    if (w < cnt) {
+      e = list[w];
+      const int ex = (int)(e % nx);
+      const int64_t rest = e / nx;
+      const int ey = (int)(rest % ny), ez = (int)(rest / ny);
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const int q = 3 * b + c;
-        const double k =
-            compact ? Kcomp[(int64_t)sidx(r, q) * cap + w] : Ke[(int64_t)sidx(r, q) * ne + e];
-        acc = fma((T)k, v[c * nn + nb], acc);
+      for (int h = 0; h < 2; ++h) {
+        const int b = 2 * quarter + h;
+        const int64_t nb = node_of(nx, ny, ex + (b & 1), ey + ((b >> 1) & 1), ez + (b >> 2));
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const int q = 3 * b + c;
+          const double k =
+              compact ? Kcomp[(int64_t)sidx(r, q) * cap + w] : Ke[(int64_t)sidx(r, q) * ne + e];
+          acc = fma((T)k, v[c * nn + nb], acc);
+        }
       }
     }
-    Y[(int64_t)r * ne + e] = acc;
+    acc += __shfl_down(acc, 32, 64);  // corners 0-3 + 4-7
+    acc += __shfl_down(acc, 16, 64);
+    if (quarter == 0 && w < cnt) Y[(int64_t)r * ne + e] = acc;
   }
 }
 
 // Pass 1 in one launch: workgroups x < nbe run the element path (grid.y:
 // output component); the rest run the flagged parents, two per grid.y, each
-// with four rows (one per wavefront) of a 64-entry chunk of the list.
+// with four rows (one per wavefront) of a 16-entry chunk of the list.
 template <typename T>
 __global__ void __launch_bounds__(256) k_l1_elem(int nx, int ny, int nz,
                                                  const double* __restrict__ Ke,
@@ -1039,7 +1048,7 @@ void l1_apply(const Grid& g, const double* Ke, const double* Kcomp, int cap, con
               const T* jd = nullptr, T omega = 0) {
   // nflag: the flagged-parent count, known to the host after setup
   const int nbe = (int)nblk(g.ne, 256);
-  const int nbm = nflag > 0 ? 2 * (int)std::min<int64_t>(nblk(nflag, 64), 256) : 0;
+  const int nbm = nflag > 0 ? 2 * (int)std::min<int64_t>(nblk(nflag, 16), 1024) : 0;
   k_l1_elem<T><<<dim3(nbe + nbm, 3), 256, 0, s>>>(g.nx, g.ny, g.nz, Ke, Bw, Ef, eflag, v, Y, nbe,
                                                   Kcomp, cap, list, nflag);
   k_l1_gather<T><<<nblk(g.nn, 256), 256, 0, s>>>(g.nx, g.ny, g.nz, Y, y, jb, jd, omega);
