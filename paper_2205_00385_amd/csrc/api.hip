@@ -435,7 +435,7 @@ int64_t layout(aarmr_mesh* m, char* base) {
     }
   }
   m->Ainv = (double*)take((int64_t)m->nc * m->nc * d8);
-  m->gjP = (double*)take(kGJBlock * kGJBlock * d8);
+  m->gjP = (double*)take(2 * kGJBlock * kGJBlock * d8);  // two pivot inverses
   m->gjT = (double*)take((int64_t)m->nc * kGJBlock * d8);
   m->gjC = (double*)take((int64_t)m->nc * kGJBlock * d8);
   m->Phi = (double*)take((int64_t)m->p.n_rhs_max * m->p.Ns * n3 * d8);

@@ -767,11 +767,23 @@ __device__ __forceinline__ void gj64_block(double (*sS)[kGJBlock + 1]) {
   }
 }
 
-// Pivot inverse of the first block: Pb = A_00^-1 (kb x kb).
+// Workgroup 0: pivot inverse of the first block, Pb = A_00^-1 (kb x kb).
+// The others copy the first step's panel Cb[p][i] = A[p][i] (p < kb: the
+// stored first block row), 2048 entries each.
 __global__ void __launch_bounds__(256) k_gj_pivot_first(int n, int kb,
                                                         const double* __restrict__ A,
-                                                        double* __restrict__ Pb) {
+                                                        double* __restrict__ Pb,
+                                                        double* __restrict__ Cb) {
   __shared__ double sS[kGJBlock][kGJBlock + 1];
+  if (blockIdx.x > 0) {
+    const int64_t base = (int64_t)(blockIdx.x - 1) * 2048, total = (int64_t)kb * n;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const int64_t x = base + threadIdx.x + 256 * r;
+      if (x < total) Cb[x] = A[x];
+    }
+    return;
+  }
   for (int x = threadIdx.x; x < kGJBlock * kGJBlock; x += 256) {
     const int r = x / 64, c = x % 64;
     sS[r][c] = (r < kb && c < kb) ? A[(int64_t)r * n + c] : (r == c ? 1.0 : 0.0);
@@ -788,165 +800,171 @@ __global__ void __launch_bounds__(256) k_gj_pivot_first(int n, int kb,
 // the 64 KB a workgroup may hold).
 __device__ __forceinline__ int swz(int p, int i) { return p * 64 + (i ^ ((p & 3) << 3)); }
 
-// One block per 64-row block I != K: c_I gathered from the stored upper
-// triangle, T_I = c_I P with P = Pb; writes Cb, Tb ([kb][n], index-fastest)
-// and the new cross entries of A.  Block K writes A_KK = P.  Every global
-// load of P and c_I is issued before the first LDS store, so the block
-// waits for memory once.
-__global__ void __launch_bounds__(256) k_gj_cross(int n, int k0, int kb,
-                                                  double* __restrict__ A,
-                                                  const double* __restrict__ Pb,
-                                                  double* __restrict__ Tb,
-                                                  double* __restrict__ Cb) {
+// One block step in one launch, one workgroup per upper tile (bi <= bj).
+// The step reads the pivot inverse Pc = A_KK^-1 and the panel Cc[p][i] =
+// c_i[p] (c_i = A_iK before the step, taken from the stored upper triangle)
+// and writes the next step's Pn and Cn, so no workgroup reads what another
+// writes:
+//   tile (K, K):        A_KK = Pc;
+//   tile in row/col K:  T_O = c_O Pc for the other block O, and the new cross
+//                       entries A_OK = -T_O (O < K) or A_KO = T_O (O > K);
+//   other tiles (I, J): T_I = c_I Pc, A_IJ -= s_J T_I c_J^T (s_J = -1 for
+//                       J < K, +1 beyond), all on FP64 MFMA.
+// Entries that become the next panel (block column K+1 above the diagonal,
+// block row K+1 right of it, and A_{K,K+1}) are also written to Cn.
+// Workgroup 0 takes tile (K+1, K+1) and inverts the updated tile into Pn.
+__global__ void __launch_bounds__(256) k_gj_step(int n, int k0, int kb, int nb,
+                                                 double* __restrict__ A,
+                                                 const double* __restrict__ Pc,
+                                                 double* __restrict__ Pn,
+                                                 const double* __restrict__ Cc,
+                                                 double* __restrict__ Cn) {
   __shared__ double sm[2 * kGJBlock * kGJBlock];
-  double* sP = sm;                      // P[p][q]
-  double* sX = sm + kGJBlock * kGJBlock;  // c as [p][r], later T as [q][r]
-  const int tid = threadIdx.x;
-  const int i0 = blockIdx.x * kGJBlock;
-  const int rows = (n - i0 < kGJBlock) ? (n - i0) : kGJBlock;
-  if (i0 == k0) {
+  double* sP = sm;                        // Pc [p][q], later c_J [p][j]
+  double* sX = sm + kGJBlock * kGJBlock;  // c_O [p][i], later T [q][i]
+  const int K = k0 / kGJBlock;
+  const bool has_next = K + 1 < nb;
+  int bi, bj;
+  {
+    int t = blockIdx.x;
+    if (has_next) {  // workgroup 0: (K+1, K+1); the rest row-major, skipping it
+      if (t == 0) {
+        t = (K + 1) * nb - ((K + 1) * K) / 2;
+      } else {
+        --t;
+        const int nxt = (K + 1) * nb - ((K + 1) * K) / 2;
+        if (t >= nxt) ++t;
+      }
+    }
+    bi = 0;
+    while (t >= nb - bi) { t -= nb - bi; ++bi; }
+    bj = bi + t;
+  }
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  const int li = lane & 15, lk = lane >> 4;
+  if (bi == K && bj == K) {
     for (int x = tid; x < kb * kb; x += 256)
-      A[(int64_t)(k0 + x / kb) * n + k0 + x % kb] = Pb[x];
+      A[(int64_t)(k0 + x / kb) * n + k0 + x % kb] = Pc[x];
     return;
   }
-  const bool below = i0 < k0;  // rows already pivoted
-  double pv[16], xv[16];
+  const bool cross = bi == K || bj == K;
+  const int O = cross ? (bi == K ? bj : bi) : bi;  // the block whose T is formed
+  const int O0 = O * kGJBlock, J0 = bj * kGJBlock, I0 = bi * kGJBlock;
+  const int orows = (n - O0 < kGJBlock) ? (n - O0) : kGJBlock;
+  // every global load in flight before the first LDS store
+  double pv[16], xv[16], cj[16];
+  f64x4 acc[4];
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     const int x = tid + 256 * r, a = x >> 6, b = x & 63;
-    pv[r] = (a < kb && b < kb) ? Pb[a * kb + b] : 0.0;
-    // c(row, p): below, A[i0 + row][k0 + p] (row = a, p = b); above,
-    // A[k0 + p][i0 + row] (p = a, row = b): coalesced either way
-    if (below)
-      xv[r] = (a < rows && b < kb) ? A[(int64_t)(i0 + a) * n + k0 + b] : 0.0;
-    else
-      xv[r] = (a < kb && b < rows) ? A[(int64_t)(k0 + a) * n + i0 + b] : 0.0;
+    pv[r] = (a < kb && b < kb) ? Pc[a * kb + b] : 0.0;
+    xv[r] = (a < kb && b < orows) ? Cc[(int64_t)a * n + O0 + b] : 0.0;
+    cj[r] = (!cross && a < kb && J0 + b < n) ? Cc[(int64_t)a * n + J0 + b] : 0.0;
   }
+#pragma unroll
+  for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = I0 + 16 * w + lk + 4 * v, j = J0 + 16 * jb + li;
+      acc[jb][v] = (!cross && i < n && j < n) ? A[(int64_t)i * n + j] : 0.0;
+    }
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     const int x = tid + 256 * r, a = x >> 6, b = x & 63;
     sP[swz(a, b)] = pv[r];
-    sX[below ? swz(b, a) : swz(a, b)] = xv[r];
+    sX[swz(a, b)] = xv[r];
   }
   __syncthreads();
-#pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    const int x = tid + 256 * r, p = x >> 6, row = x & 63;
-    if (p < kb && row < rows) Cb[(int64_t)p * n + i0 + row] = sX[swz(p, row)];
-  }
   // T[16w + i][16jb + j] = sum_p c[16w + i][p] P[p][16jb + j]
-  const int w = tid >> 6, l = tid & 63, li = l & 15, lk = l >> 4;
-  f64x4 acc[4];
+  f64x4 tacc[4];
 #pragma unroll
-  for (int jb = 0; jb < 4; ++jb) acc[jb] = f64x4{0.0, 0.0, 0.0, 0.0};
+  for (int jb = 0; jb < 4; ++jb) tacc[jb] = f64x4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int kk = 0; kk < 16; ++kk) {
     const int p = 4 * kk + lk;
     const double a = sX[swz(p, 16 * w + li)];
 #pragma unroll
     for (int jb = 0; jb < 4; ++jb)
-      acc[jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, sP[swz(p, 16 * jb + li)], acc[jb], 0, 0, 0);
+      tacc[jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, sP[swz(p, 16 * jb + li)], tacc[jb], 0, 0, 0);
   }
   __syncthreads();
-  // acc[jb][v] = T[16w + lk + 4v][16jb + li]; stage as [q][row]
+  // tacc[jb][v] = T[16w + lk + 4v][16jb + li]; stage T as [q][i]
 #pragma unroll
   for (int jb = 0; jb < 4; ++jb)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) sX[swz(16 * jb + li, 16 * w + lk + 4 * v)] = acc[jb][v];
-  __syncthreads();
+    for (int v = 0; v < 4; ++v) sX[swz(16 * jb + li, 16 * w + lk + 4 * v)] = tacc[jb][v];
+  if (cross) {
+    if (O < K) {  // A[O0 + i][k0 + q] = -T[i][q], coalesced along q
+#pragma unroll
+      for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = 16 * w + lk + 4 * v, q = 16 * jb + li;
+          if (i < orows && q < kb) A[(int64_t)(O0 + i) * n + k0 + q] = -tacc[jb][v];
+        }
+      return;
+    }
+    if (O == K + 1) {  // next panel, rows of K: Cn[i][k0 + q] = T[i][q]
+#pragma unroll
+      for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = 16 * w + lk + 4 * v, q = 16 * jb + li;
+          if (i < orows && q < kb) Cn[(int64_t)i * n + k0 + q] = tacc[jb][v];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {  // A[k0 + q][O0 + i] = T[i][q], coalesced along i
+      const int x = tid + 256 * r, q = x >> 6, i = x & 63;
+      if (q < kb && i < orows) A[(int64_t)(k0 + q) * n + O0 + i] = sX[swz(q, i)];
+    }
+    return;
+  }
+  // tile: c_J as [p][j] replaces P
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
-    const int x = tid + 256 * r, q = x >> 6, row = x & 63;
-    if (q < kb && row < rows) {
-      const double t = sX[swz(q, row)];
-      Tb[(int64_t)q * n + i0 + row] = t;
-      if (!below) A[(int64_t)(k0 + q) * n + i0 + row] = t;
-    }
-  }
-  if (below) {  // A[i0 + row][k0 + q] = -T[row][q], coalesced along q
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int x = tid + 256 * r, row = x >> 6, q = x & 63;
-      if (q < kb && row < rows) A[(int64_t)(i0 + row) * n + k0 + q] = -sX[swz(q, row)];
-    }
-  }
-}
-
-// Upper tiles (bi <= bj) outside K: A_IJ -= s_J T_I C_J^T on 64x64 tiles with
-// FP64 MFMA (wave w: rows 16w..16w+15, four 16x16 accumulators that start
-// from A_IJ).  T_I and C_J are staged in LDS with all loads in flight at
-// once.  Block 0 takes the next diagonal tile (K+1, K+1) and then inverts it
-// into Pb, the pivot of the next step.
-__global__ void __launch_bounds__(256) k_gj_update(int n, int k0, int kb, int nb,
-                                                   double* __restrict__ A,
-                                                   double* __restrict__ Pb,
-                                                   const double* __restrict__ Tb,
-                                                   const double* __restrict__ Cb) {
-  __shared__ double sm[2 * kGJBlock * kGJBlock];
-  double* sT = sm;
-  double* sC = sm + kGJBlock * kGJBlock;
-  const int kblk = k0 / kGJBlock;
-  const bool has_next = kblk + 1 < nb;
-  int bi, bj;
-  if (blockIdx.x == 0) {
-    if (!has_next) return;
-    bi = bj = kblk + 1;
-  } else {
-    // linear index over the upper triangle, row-major, skipping (K+1, K+1)
-    int t = blockIdx.x - 1;
-    if (has_next) {
-      const int nxt = (kblk + 1) * nb - ((kblk + 1) * kblk) / 2;  // index of (K+1, K+1)
-      if (t >= nxt) ++t;
-    }
-    bi = 0;
-    while (t >= nb - bi) { t -= nb - bi; ++bi; }
-    bj = bi + t;
-    if (bi == kblk || bj == kblk) return;
-  }
-  const int I0 = bi * kGJBlock, J0 = bj * kGJBlock;
-  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-  const int li = lane & 15, lk = lane >> 4;
-  double tv[16], cv[16];
-#pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    const int x = tid + 256 * r, p = x >> 6, i = x & 63;
-    tv[r] = (p < kb && I0 + i < n) ? Tb[(int64_t)p * n + I0 + i] : 0.0;
-    cv[r] = (p < kb && J0 + i < n) ? Cb[(int64_t)p * n + J0 + i] : 0.0;
-  }
-  // accumulator layout: lane l, element v -> row l/16 + 4v, column l%16 of
-  // the 16x16 block (operands: A[l%16][l/16], B[l/16][l%16])
-  f64x4 acc[4];
-#pragma unroll
-  for (int jb = 0; jb < 4; ++jb)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int i = I0 + 16 * w + lk + 4 * v, j = J0 + 16 * jb + li;
-      acc[jb][v] = (i < n && j < n) ? A[(int64_t)i * n + j] : 0.0;
-    }
-#pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    const int x = tid + 256 * r, p = x >> 6, i = x & 63;
-    sT[swz(p, i)] = tv[r];
-    sC[swz(p, i)] = cv[r];
+    const int x = tid + 256 * r, a = x >> 6, b = x & 63;
+    sP[swz(a, b)] = cj[r];
   }
   __syncthreads();
   const double ns = (J0 < k0) ? 1.0 : -1.0;  // -s_J
 #pragma unroll
   for (int kk = 0; kk < 16; ++kk) {
     const int p = 4 * kk + lk;
-    const double a = ns * sT[swz(p, 16 * w + li)];
+    const double a = ns * sX[swz(p, 16 * w + li)];
 #pragma unroll
     for (int jb = 0; jb < 4; ++jb)
-      acc[jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, sC[swz(p, 16 * jb + li)], acc[jb], 0, 0, 0);
+      acc[jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, sP[swz(p, 16 * jb + li)], acc[jb], 0, 0, 0);
   }
+  const bool next_col = bj == K + 1 && bi != K + 1, next_row = bi == K + 1 && bj != K + 1;
 #pragma unroll
   for (int jb = 0; jb < 4; ++jb)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int i = I0 + 16 * w + lk + 4 * v, j = J0 + 16 * jb + li;
-      if (i < n && j < n) A[(int64_t)i * n + j] = acc[jb][v];
+      if (i < n && j < n) {
+        A[(int64_t)i * n + j] = acc[jb][v];
+        // row K+1 of the next panel: Cn[p][j] = A[(K+1)0 + p][j]
+        if (next_row) Cn[(int64_t)(i - I0) * n + j] = acc[jb][v];
+      }
     }
-  if (blockIdx.x != 0) return;
+  if (next_col) {  // column K+1: Cn[p][i] = A[i][J0 + p], staged to be coalesced along i
+    __syncthreads();
+#pragma unroll
+    for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) sX[swz(16 * jb + li, 16 * w + lk + 4 * v)] = acc[jb][v];
+    __syncthreads();
+    const int ncol = (n - J0 < kGJBlock) ? (n - J0) : kGJBlock;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int x = tid + 256 * r, p = x >> 6, i = x & 63;
+      if (p < ncol && I0 + i < n) Cn[(int64_t)p * n + I0 + i] = sX[swz(p, i)];
+    }
+    return;
+  }
+  if (blockIdx.x != 0 || !has_next) return;
   // next pivot block: the tile just updated, identity beyond the matrix
   double (*sS)[kGJBlock + 1] = reinterpret_cast<double (*)[kGJBlock + 1]>(sm);
   const int kbn = (n - I0 < kGJBlock) ? (n - I0) : kGJBlock;
@@ -960,7 +978,7 @@ __global__ void __launch_bounds__(256) k_gj_update(int n, int k0, int kb, int nb
     }
   __syncthreads();
   gj64_block(sS);
-  for (int x = threadIdx.x; x < kbn * kbn; x += 256) Pb[x] = sS[x / kbn][x % kbn];
+  for (int x = threadIdx.x; x < kbn * kbn; x += 256) Pn[x] = sS[x / kbn][x % kbn];
 }
 
 // Lower tiles (bi > bj) <- transpose of the upper tiles.
@@ -1146,11 +1164,17 @@ void launch_assemble_dense(const Grid& g, const double* Ke, double* A, hipStream
 void launch_gj_invert(int n, double* A, double* P, double* T, double* C, hipStream_t s) {
   const int nb = (n + kGJBlock - 1) / kGJBlock;
   const unsigned n_upper = (unsigned)(nb * (nb + 1) / 2);
-  k_gj_pivot_first<<<1, 256, 0, s>>>(n, std::min(n, kGJBlock), A, P);
-  for (int k0 = 0; k0 < n; k0 += kGJBlock) {
+  // pivot inverses and panels alternate between two buffers each
+  double* Pb[2] = {P, P + kGJBlock * kGJBlock};
+  double* Cb[2] = {C, T};
+  const int kb0 = std::min(n, kGJBlock);
+  k_gj_pivot_first<<<(unsigned)(1 + ((int64_t)kb0 * n + 2047) / 2048), 256, 0, s>>>(n, kb0, A,
+                                                                                  Pb[0], Cb[0]);
+  int step = 0;
+  for (int k0 = 0; k0 < n; k0 += kGJBlock, ++step) {
     const int kb = std::min(kGJBlock, n - k0);
-    k_gj_cross<<<nb, 256, 0, s>>>(n, k0, kb, A, P, T, C);
-    k_gj_update<<<n_upper, 256, 0, s>>>(n, k0, kb, nb, A, P, T, C);
+    k_gj_step<<<n_upper, 256, 0, s>>>(n, k0, kb, nb, A, Pb[step & 1], Pb[(step + 1) & 1],
+                                      Cb[step & 1], Cb[(step + 1) & 1]);
   }
   k_gj_mirror<<<dim3(nb, nb), 256, 0, s>>>(n, A);
 }
