@@ -297,15 +297,25 @@ int aarmr_oc_update(aarmr_mesh* m, const double* x, const double* dc, const doub
 /* Autotuner of the fine-grid operator's launch shape: the z-marching kernel
  * runs 14 x 15-node tiles of the x-y plane, each marching over a chunk of
  * node planes; times the residency-sized default chunk length and candidate
- * lengths 4..n_z+1 on this mesh's grid (scratch operands: the solver state is
+ * lengths 2..n_z+1 on this mesh's grid (scratch operands: the solver state is
  * untouched), the best of 3 rounds of 5 launches each after a warm-up, and
  * keeps the fastest for the
  * mesh's later products (FP64 and, in the refinement form, FP32).
  * tz_out: host [2] or NULL, receives the chosen lengths (0 = the default).
- * The result of every product is the same for every chunk length.  On the
- * plane-stress grid there is nothing to tune: tz_out receives 0, 0.
- * Synchronises `stream`.  Errors: AARMR_E_NO_WORKSPACE, AARMR_E_HIP. */
+ * Every product gives the same bits for every chunk length; CG's dot products
+ * are summed per workgroup of that product, so a solve's last bits may
+ * change with it.  On the plane-stress grid there is nothing to tune: tz_out
+ * receives 0, 0.  Synchronises `stream`.  Errors: AARMR_E_NO_WORKSPACE,
+ * AARMR_E_HIP. */
 int aarmr_autotune(aarmr_mesh* m, int32_t* tz_out, void* stream);
+
+/* Set the fine-grid operator's z-chunk lengths without timing (for
+ * instance the values an earlier aarmr_autotune returned for the same grid):
+ * tz64 for FP64 products, tz32 for the refinement form's FP32 products; 0
+ * restores the default, lengths above n_z + 1 are clamped to it.  Host-only,
+ * takes effect at the next product.  Errors: AARMR_E_INVALID (null mesh, a
+ * length below 0 or equal to 1). */
+int aarmr_set_chunk(aarmr_mesh* m, int32_t tz64, int32_t tz32);
 
 /* ---- batched form ------------------------------------------------------
  * Many independent analyses (meshes of uneven size, each with its own load

@@ -78,7 +78,7 @@ EXPORTS = [
     "aarmr_default_params", "aarmr_mesh_create", "aarmr_mesh_destroy", "aarmr_workspace_bytes",
     "aarmr_bind_workspace", "aarmr_solve", "aarmr_ca_update", "aarmr_filter", "aarmr_setup",
     "aarmr_apply_operator", "aarmr_vcycle", "aarmr_element_energy", "aarmr_oc_update",
-    "aarmr_autotune", "aarmr_batch_solve", "aarmr_batch_submit", "aarmr_batch_poll",
+    "aarmr_autotune", "aarmr_set_chunk", "aarmr_batch_solve", "aarmr_batch_submit", "aarmr_batch_poll",
     "aarmr_batch_wait", "aarmr_set_springs", "aarmr_last_error",
 ]
 
@@ -113,6 +113,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.aarmr_batch_poll.argtypes = [P, ctypes.POINTER(i32)]
     lib.aarmr_batch_wait.argtypes = [P]
     lib.aarmr_autotune.argtypes = [P, ctypes.POINTER(i32), vp]
+    lib.aarmr_set_chunk.argtypes = [P, i32, i32]
     lib.aarmr_set_springs.argtypes = [P, ctypes.POINTER(i64), ctypes.POINTER(dbl), i32]
     lib.aarmr_last_error.argtypes = []
     lib.aarmr_last_error.restype = ctypes.c_char_p
@@ -260,6 +261,10 @@ class Mesh:
         out = (ctypes.c_int32 * 2)()
         _check(lib().aarmr_autotune(self._h, out, _stream()))
         return out[0], out[1]
+
+    def set_chunk(self, tz64, tz32=0):
+        """Set the fine-grid operator's z-chunk lengths (0: the default)."""
+        _check(lib().aarmr_set_chunk(self._h, int(tz64), int(tz32)))
 
     def set_springs(self, dofs, k):
         """Grounded springs (host sequences of SoA DOF ids and stiffnesses)."""

@@ -1715,6 +1715,15 @@ int aarmr_oc_update(aarmr_mesh* m, const double* x, const double* dc, const doub
   return AARMR_OK;
 }
 
+int aarmr_set_chunk(aarmr_mesh* m, int32_t tz64, int32_t tz32) {
+  if (!m) return fail(AARMR_E_INVALID, "null mesh");
+  if (tz64 < 0 || tz64 == 1 || tz32 < 0 || tz32 == 1)
+    return fail(AARMR_E_INVALID, "chunk lengths must be 0 (default) or at least 2");
+  m->tz64 = tz64;
+  m->tz32 = tz32;
+  return AARMR_OK;
+}
+
 int aarmr_autotune(aarmr_mesh* m, int32_t* tz_out, void* stream) {
   TRY(need_ws(m));
   if (m->dim == 2) {  // the plane-stress product has no tunable chunk
@@ -1726,7 +1735,7 @@ int aarmr_autotune(aarmr_mesh* m, int32_t* tz_out, void* stream) {
   const int planes = g.nz + 1;
   const int64_t n3 = ndof(m, 0);
   std::vector<int> cand{0};  // 0: the residency-sized default
-  for (int t : {4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512})
+  for (int t : {2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512})
     if (t <= planes) cand.push_back(t);
   if (planes > 4) cand.push_back(planes);
   hipEvent_t e0, e1;

@@ -390,7 +390,8 @@ __global__ void k_identity_rows(int64_t nn, const uint8_t* __restrict__ mask,
 // z-chunk of node planes per workgroup.  A chunk costs one extra element
 // layer (the carry is primed from the layer below it), so chunks are made
 // as long as possible while the grid still fills every resident workgroup
-// slot of the device in a single round; at least 4 planes per chunk.
+// slot of the device in a single round; at least 4 planes per chunk unless a
+// tuned length (2 or more) is given.
 #ifndef AARMR_EBE_PF
 #define AARMR_EBE_PF 1
 #endif
@@ -414,8 +415,9 @@ static int launch_ebe_t(const Grid& g, const WalshConsts& K, const T* E, const u
   int gz = slots / (gx * gy);
   gz = gz < 1 ? 1 : (gz > planes ? planes : gz);
   int tz = (planes + gz - 1) / gz;
-  if (tz_req > 0) tz = tz_req < planes ? tz_req : planes;  // tuned z-chunk length
   if (tz < 4) tz = 4;
+  if (tz_req > 0) tz = tz_req < planes ? tz_req : planes;  // tuned z-chunk length
+  if (tz < 2) tz = 2;
   gz = (planes + tz - 1) / tz;
   k_ebe_z<T, MASK_IN, AARMR_EBE_PF, JAC, DOT><<<(unsigned)(gx * gy * gz), kThreads, 0, s>>>(
       g.nx, g.ny, g.nz, gx, gy, tz, K, E, mask, v, y, jb, jd, omega, part);
@@ -425,7 +427,7 @@ static int launch_ebe_t(const Grid& g, const WalshConsts& K, const T* E, const u
 int ebe_partials_max(const Grid& g) {
   const int gx = (g.nx + 1 + kTileX - 1) / kTileX;
   const int gy = (g.ny + 1 + kTileY - 1) / kTileY;
-  return gx * gy * ((g.nz + 1 + 3) / 4);
+  return gx * gy * ((g.nz + 1 + 1) / 2);
 }
 
 int launch_ebe_dot(const Grid& g, const WalshConsts& K, const double* E, const uint8_t* mask,

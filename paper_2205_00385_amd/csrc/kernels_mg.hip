@@ -612,46 +612,44 @@ __global__ void k_jacobi_update(int64_t n3, const T* __restrict__ b, const T* __
 }
 
 // Dense coarsest operator in SoA DOF order (c * nn + node); thread per row.
-// One wavefront per row, lanes over the columns (coalesced): an entry is the
-// sum, over the elements around the row's node in corner order a = 0..7, of
-// the element matrices' entries coupling the two nodes; zero for columns
-// outside the 27-node neighbourhood.  A row with zero diagonal (a coarse DOF
-// no free fine DOF interpolates from) becomes an identity row.
+// One wavefront per row: the row is zeroed (coalesced stores), then lanes
+// take the 81 columns of the 27-node neighbourhood (3 components each); an
+// entry is the sum, over the elements around the row's node in corner order
+// a = 0..7, of the element matrices' entries coupling the two nodes.  A row
+// with zero diagonal (a coarse DOF no free fine DOF interpolates from)
+// becomes an identity row.  32-bit indices: the coarsest order is at most
+// 8192.
 __global__ void __launch_bounds__(256) k_assemble_dense(int nx, int ny, int nz,
                                                         const double* __restrict__ Ke,
                                                         double* __restrict__ A) {
-  const int64_t nn = (int64_t)(nx + 1) * (ny + 1) * (nz + 1);
-  const int64_t ne = (int64_t)nx * ny * nz;
-  const int64_t nd = 3 * nn;
-  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int nxp = nx + 1, nyp = ny + 1;
+  const int nn = nxp * nyp * (nz + 1), ne = nx * ny * nz, nd = 3 * nn;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  if (row >= nd) return;  // wave-uniform
-  const int c = (int)(row / nn);
-  const int64_t n = row % nn;
-  const int i = (int)(n % (nx + 1));
-  const int j = (int)((n / (nx + 1)) % (ny + 1));
-  const int k = (int)(n / ((int64_t)(nx + 1) * (ny + 1)));
-  double* Ar = A + row * nd;
-  for (int64_t t = lane; t < nd; t += 64) {
-    const int cc = (int)(t / nn);
-    const int64_t nb = t % nn;
-    const int bi = (int)(nb % (nx + 1));
-    const int bj = (int)((nb / (nx + 1)) % (ny + 1));
-    const int bk = (int)(nb / ((int64_t)(nx + 1) * (ny + 1)));
+  const bool active = row < nd;  // wave-uniform; every wave reaches the barrier
+  double* Ar = A + (int64_t)(active ? row : 0) * nd;
+  if (active)
+    for (int t = lane; t < nd; t += 64) Ar[t] = 0.0;
+  __syncthreads();  // the zeros are stored before the same addresses are rewritten
+  if (!active) return;
+  const int c = row / nn, n = row % nn;
+  const int i = n % nxp, j = (n / nxp) % nyp, k = n / (nxp * nyp);
+  for (int l = lane; l < 81; l += 64) {
+    const int cc = l / 27, d = l % 27;
+    const int bi = i + d % 3 - 1, bj = j + (d / 3) % 3 - 1, bk = k + d / 9 - 1;
+    if (bi < 0 || bi > nx || bj < 0 || bj > ny || bk < 0 || bk > nz) continue;
     double acc = 0.0;
-    if (abs(bi - i) <= 1 && abs(bj - j) <= 1 && abs(bk - k) <= 1) {
-      for (int a = 0; a < 8; ++a) {
-        const int ex = i - (a & 1), ey = j - ((a >> 1) & 1), ez = k - (a >> 2);
-        if (ex < 0 || ex >= nx || ey < 0 || ey >= ny || ez < 0 || ez >= nz) continue;
-        const int dx = bi - ex, dy = bj - ey, dz = bk - ez;  // corner of nb in element e
-        if (dx < 0 || dx > 1 || dy < 0 || dy > 1 || dz < 0 || dz > 1) continue;
-        const int b = dx + 2 * dy + 4 * dz;
-        const int64_t e = (int64_t)ex + (int64_t)nx * ((int64_t)ey + (int64_t)ny * ez);
-        acc += Ke[(int64_t)sidx(3 * a + c, 3 * b + cc) * ne + e];
-      }
+    for (int a = 0; a < 8; ++a) {
+      const int ex = i - (a & 1), ey = j - ((a >> 1) & 1), ez = k - (a >> 2);
+      if (ex < 0 || ex >= nx || ey < 0 || ey >= ny || ez < 0 || ez >= nz) continue;
+      const int dx = bi - ex, dy = bj - ey, dz = bk - ez;  // corner of the column node
+      if (dx < 0 || dx > 1 || dy < 0 || dy > 1 || dz < 0 || dz > 1) continue;
+      const int b = dx + 2 * dy + 4 * dz;
+      const int e = ex + nx * (ey + ny * ez);
+      acc += Ke[(int64_t)sidx(3 * a + c, 3 * b + cc) * ne + e];
     }
-    if (t == row && acc == 0.0) acc = 1.0;  // dead coarse DOF: identity row
-    Ar[t] = acc;
+    const int col = cc * nn + bi + nxp * (bj + nyp * bk);
+    Ar[col] = (col == row && acc == 0.0) ? 1.0 : acc;
   }
 }
 

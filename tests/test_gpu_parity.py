@@ -315,28 +315,49 @@ def test_level1_many_fixed_parents_strided_path():
 @pytest.mark.parametrize("dims", [(24, 12, 12), (36, 20, 40)])
 def test_autotune_keeps_products_bitwise(dims):
     """The autotuner only changes the z-chunk length of the fine-grid
-    operator; every chunk length gives the same bits."""
+    operator.  Every chunk length (the tuned one and 2, 3, 5, 7 and all
+    planes set explicitly) gives the same bits for the product and for a
+    V-cycle; a solve, whose CG dot products are summed per workgroup of the
+    product, agrees to rounding (1e-10)."""
     from paper_2205_00385_amd import aarmr
 
     prob = synth.cantilever(*dims)
     for prec in (aarmr.FP64, aarmr.FP32_REFINE):
         m = mesh_for(prob, mg_levels=3, precision=prec)
         fixed = fixed_tensor(prob, m)
-        m.setup(t64(_density(prob, 41)), fixed)
+        rho = t64(_density(prob, 41))
+        m.setup(rho, fixed)
         v = np.random.default_rng(42).standard_normal(3 * m.n_node)
         y0 = torch.empty(3 * m.n_node, dtype=torch.float64, device="cuda")
-        y1 = torch.empty_like(y0)
         m.apply(t64(v), y0)
+        z0 = torch.empty_like(y0)
+        r = t64(v * fem.aos_to_soa(fem.free_mask(3 * m.n_node, fem.fixed_dofs_aos(prob))
+                                   .astype(np.float64)).ravel())
+        m.vcycle(r, z0)
         f = loads_tensor(prob, m)
         u0 = torch.zeros_like(f)
-        m.solve(t64(_density(prob, 41)), f, fixed, u0)
-        tz = m.autotune()
-        log(f"  {dims} precision {prec}: chunk lengths {tz}")
-        m.apply(t64(v), y1)
-        assert torch.equal(y0, y1)
-        u1 = torch.zeros_like(f)
-        m.solve(t64(_density(prob, 41)), f, fixed, u1)
-        assert torch.equal(u0, u1)
+        C0, st0, _ = m.solve(rho, f, fixed, u0)
+        tuned = m.autotune()
+        log(f"  {dims} precision {prec}: tuned chunk lengths {tuned}")
+        for tz in (None, 2, 3, 5, 7, prob.nz + 1):
+            if tz is not None:
+                m.set_chunk(tz, tz)
+            y1 = torch.empty_like(y0)
+            m.apply(t64(v), y1)
+            assert torch.equal(y0, y1), f"product, chunk {tz}"
+            z1 = torch.empty_like(z0)
+            m.vcycle(r, z1)
+            assert torch.equal(z0, z1), f"V-cycle, chunk {tz}"
+            u1 = torch.zeros_like(f)
+            C1, st1, _ = m.solve(rho, f, fixed, u1)
+            assert rel(u1.cpu().numpy(), u0.cpu().numpy()) < 1e-10, f"solve, chunk {tz}"
+            assert abs(C1[0] - C0[0]) <= 1e-10 * abs(C0[0])
+            # the iteration count is not compared: on this slowly converging
+            # case (hundreds of iterations) rounding alone moves it
+            log(f"    chunk {tz}: {st1.iterations[0]} iterations (default {st0.iterations[0]})")
+        with pytest.raises(aarmr.AarmrError):
+            m.set_chunk(1, 0)
+        m.close()
 
 
 def test_ca_svd_and_gs_bases_give_same_reduced_solution():
