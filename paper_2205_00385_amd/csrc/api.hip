@@ -71,6 +71,9 @@ constexpr int M_Y = 168;       // reduced solution
 constexpr int M_KR = 180;      // reduced matrix (up to 10x10, slots 180..279)
 constexpr int M_SVC = 300;     // SVD basis coefficients (up to 10x10, slots 300..399)
 constexpr int M_SVK = 400;     // SVD: number of kept singular vectors
+constexpr int M_N0 = 410;      // GS: squared column norms before the projections (Nm)
+constexpr int M_N1 = 420;      // GS: and after them (Nm)
+constexpr int M_KEEP = 430;    // GS: 1 for a kept column, 0 for a dropped one (Nm)
 
 constexpr int64_t kAlign = 256;
 
@@ -1533,60 +1536,72 @@ int aarmr_ca_update(aarmr_mesh* m, const double* rho, const double* f, int32_t n
       launch_lincomb(n3, Ns, V.data(), misc + M_C2, -1.0, nullptr, m->R + i * n3, s);
       KCHECK();
     }
-    {
+    // Gram-Schmidt (two passes, classical) with rank drop, or the SVD of
+    // eq. 21.  Gram-Schmidt runs on the device: every column stays in its
+    // slot, a dropped one becomes zero (its projections onto later columns
+    // are then exact zeros) with keep flag 0.  One read-back then brings the
+    // keep flags and the flags word (bit 4: K_Phi not positive definite,
+    // which rejects the step), and the reduced system uses the kept slots.
+    std::vector<int> slot;  // kept columns, in order
+    if (m->p.orth == AARMR_ORTH_SVD) {
       unsigned fl = 0;
       TRY(read_flags(m, &fl, s));
       if (fl & 4u) ca_ok = false;  // K_Phi not positive definite: reject CA
-    }
-    // Gram-Schmidt (two passes, classical) with rank drop, or the SVD of eq. 21
-    int kept = 0;
-    if (ca_ok && m->p.orth == AARMR_ORTH_SVD) {
-      TRY(orth_svd(m, Nm, &kept, s));
-    } else if (ca_ok) {
+      int kept_svd = 0;
+      if (ca_ok) TRY(orth_svd(m, Nm, &kept_svd, s));
+      for (int j = 0; j < kept_svd; ++j) slot.push_back(j);
+    } else {
       for (int i = 0; i < Nm; ++i) {
         double* v = m->R + i * n3;
-        double n0;
-        double* nrm = misc + M_NRM;
-        TRY(dot1(m, v, v, nrm, n3, s));
-        TRY(read_scalars(m, (const double* const*)&nrm, 1, &n0, s));
-        if (!(n0 > 0.0)) continue;
-        for (int pass = 0; pass < 2 && kept > 0; ++pass) {
-          std::vector<const double*> a(kept), b(kept);
-          std::vector<double*> o(kept);
-          for (int j = 0; j < kept; ++j) {
+        TRY(dot1(m, v, v, misc + M_N0 + i, n3, s));
+        for (int pass = 0; pass < 2 && i > 0; ++pass) {
+          std::vector<const double*> a(i), b(i);
+          std::vector<double*> o(i);
+          for (int j = 0; j < i; ++j) {
             a[j] = m->R + j * n3;
             b[j] = v;
             o[j] = misc + M_H + j;
           }
-          TRY(dots(m, kept, a.data(), b.data(), o.data(), n3, s));
-          launch_lincomb(n3, kept, a.data(), misc + M_H, -1.0, v, v, s);
+          TRY(dots(m, i, a.data(), b.data(), o.data(), n3, s));
+          launch_lincomb(n3, i, a.data(), misc + M_H, -1.0, v, v, s);
           KCHECK();
         }
-        double n1;
-        TRY(dot1(m, v, v, nrm, n3, s));
-        TRY(read_scalars(m, (const double* const*)&nrm, 1, &n1, s));
-        if (!(std::sqrt(n1) > m->p.gs_tau * std::sqrt(n0))) continue;  // dependent column
-        launch_scale_by_inv_sqrt(n3, v, nrm, m->R + kept * n3, s);
+        TRY(dot1(m, v, v, misc + M_N1 + i, n3, s));
+        launch_gs_keep(n3, v, misc + M_N0 + i, misc + M_N1 + i, m->p.gs_tau, v,
+                       misc + M_KEEP + i, s);
         KCHECK();
-        ++kept;
       }
+      unsigned* hfl = reinterpret_cast<unsigned*>(m->hpin + 64);
+      HIP_TRY(hipMemcpyAsync(hfl, m->flags, sizeof(unsigned), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipMemsetAsync(m->flags, 0, sizeof(unsigned), s));
+      std::vector<const double*> src(Nm);
+      std::vector<double> keep(Nm);
+      for (int i = 0; i < Nm; ++i) src[i] = misc + M_KEEP + i;
+      TRY(read_scalars(m, src.data(), Nm, keep.data(), s));
+      if (*hfl & 4u) ca_ok = false;  // K_Phi not positive definite: reject CA
+      for (int i = 0; ca_ok && i < Nm; ++i)
+        if (keep[i] != 0.0) slot.push_back(i);
     }
+    const int kept = (int)slot.size();
     double eps = 1.0;
     if (kept > 0) {
       // eqs. (22)-(25): K_R~ = R~^T K R~, f_R~ = R~^T f, y, u~ = R~ y
+      std::vector<const double*> Q(kept), KQ(kept);
       for (int j = 0; j < kept; ++j) {
-        TRY(fine_product(m, m->E, m->R + j * n3, m->KR + j * n3, s));
+        Q[j] = m->R + slot[j] * n3;
+        KQ[j] = m->KR + slot[j] * n3;
+        TRY(fine_product(m, m->E, Q[j], m->KR + slot[j] * n3, s));
       }
       std::vector<const double*> a, b;
       std::vector<double*> o;
       for (int i = 0; i < kept; ++i)
         for (int j = 0; j < kept; ++j) {
-          a.push_back(m->R + i * n3);
-          b.push_back(m->KR + j * n3);
+          a.push_back(Q[i]);
+          b.push_back(KQ[j]);
           o.push_back(misc + M_KR + i * kept + j);
         }
       for (int i = 0; i < kept; ++i) {
-        a.push_back(m->R + i * n3);
+        a.push_back(Q[i]);
         b.push_back(m->fm);
         o.push_back(misc + M_FR + i);
       }
@@ -1596,23 +1611,20 @@ int aarmr_ca_update(aarmr_mesh* m, const double* rho, const double* f, int32_t n
       TRY(dots(m, (int)a.size(), a.data(), b.data(), o.data(), n3, s));
       launch_small_spd_solve(kept, kept, misc + M_KR, misc + M_FR, misc + M_Y, m->flags, s);
       KCHECK();
-      std::vector<const double*> Q(kept), KQ(kept);
-      for (int j = 0; j < kept; ++j) {
-        Q[j] = m->R + j * n3;
-        KQ[j] = m->KR + j * n3;
-      }
       launch_lincomb(n3, kept, Q.data(), misc + M_Y, 1.0, nullptr, ul, s);
       KCHECK();
       // eq. (29) from the stored K R~ columns: f - sum_j y_j K r~_j
       launch_lincomb(n3, kept, KQ.data(), misc + M_Y, -1.0, m->fm, m->t0, s);
       KCHECK();
       TRY(dot1(m, m->t0, m->t0, misc + M_EPS, n3, s));
+      // one read-back: eps^2, f^T f and the flags (bit 4: K_R~ not positive definite)
+      unsigned* hfl = reinterpret_cast<unsigned*>(m->hpin + 64);
+      HIP_TRY(hipMemcpyAsync(hfl, m->flags, sizeof(unsigned), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipMemsetAsync(m->flags, 0, sizeof(unsigned), s));
       double h[2];
       const double* src[2] = {misc + M_EPS, misc + M_FF};
       TRY(read_scalars(m, src, 2, h, s));
-      unsigned fl = 0;
-      TRY(read_flags(m, &fl, s));
-      eps = (h[1] > 0.0 && !(fl & 4u)) ? std::sqrt(h[0] / h[1]) : 1.0;
+      eps = (h[1] > 0.0 && !(*hfl & 4u)) ? std::sqrt(h[0] / h[1]) : 1.0;
       if (h[1] == 0.0) eps = 0.0;
     }
     const bool accept = kept > 0 && eps < m->p.ca_tol;

@@ -209,8 +209,15 @@ void launch_scale_by_inv_sqrt(int64_t n, const double* src, const double* nrm2, 
 // out = sum_j coef[j] * V_j (+ add) with coefficients read from device memory
 void launch_lincomb(int64_t n, int k, const double* const* V, const double* coef, double sign,
                     const double* add, double* out, hipStream_t s);
+// Cholesky solve of A x = b (n x n, row stride lda, entries averaged with
+// their transpose); not positive definite: bit 4 of *bad and x = 0.
 void launch_small_spd_solve(int n, int lda, const double* A, const double* b, double* x,
                             unsigned* bad, hipStream_t s);
+// Gram-Schmidt keep test on a projected column (n0, n1: squared norms before
+// and after the projections): dst = src / sqrt(n1) and *keep = 1 when
+// sqrt(n1) > tau sqrt(n0), else dst = 0 and *keep = 0.
+void launch_gs_keep(int64_t n, const double* src, const double* n0, const double* n1, double tau,
+                    double* dst, double* keep, hipStream_t s);
 // Thin SVD of the small n x n matrix T (row-major): left singular vectors of
 // sigma > tau sigma_1, decreasing, column by column into coef[j * n + i];
 // their count (as a double) into *kept.

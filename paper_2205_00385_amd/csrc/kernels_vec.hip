@@ -272,6 +272,9 @@ __global__ void k_lincomb(int64_t n, int k, VecList V, const double* __restrict_
 
 // Solve A x = b for a small SPD matrix (row-major, leading dimension lda) by
 // Cholesky in one thread; flags a non-positive pivot.
+// Cholesky solve of the small SPD system A x = b (entries averaged with
+// their transpose); one that is not positive definite sets bit 4 of *bad
+// and gives x = 0.  One thread.
 __global__ void k_small_spd_solve(int n, int lda, const double* __restrict__ A,
                                   const double* __restrict__ b, double* __restrict__ x,
                                   unsigned* bad) {
@@ -304,6 +307,20 @@ __global__ void k_small_spd_solve(int n, int lda, const double* __restrict__ A,
     for (int k = i + 1; k < n; ++k) s -= L[k][i] * x[k];
     x[i] = s / L[i][i];
   }
+}
+
+// Gram-Schmidt keep test: with n0 = ||v||^2 before and n1 after the
+// projections, a column with sqrt(n1) > tau sqrt(n0) is scaled to unit norm
+// (dst = src / sqrt(n1)) and *keep = 1; any other becomes zero, *keep = 0.
+__global__ void k_gs_keep(int64_t n, const double* __restrict__ src,
+                          const double* __restrict__ n0, const double* __restrict__ n1,
+                          double tau, double* __restrict__ dst, double* __restrict__ keep) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const double a = *n0, b = *n1;
+  const bool k = sqrt(b) > tau * sqrt(a);
+  const double sc = 1.0 / sqrt(b);
+  if (i < n) dst[i] = k ? src[i] * sc : 0.0;  // exact zeros, also for a non-finite column
+  if (i == 0) *keep = k ? 1.0 : 0.0;
 }
 
 }  // namespace
@@ -412,6 +429,11 @@ void launch_small_svd(int n, const double* T, double tau, double* coef, double* 
 void launch_small_spd_solve(int n, int lda, const double* A, const double* b, double* x,
                             unsigned* bad, hipStream_t s) {
   k_small_spd_solve<<<1, 64, 0, s>>>(n, lda, A, b, x, bad);
+}
+
+void launch_gs_keep(int64_t n, const double* src, const double* n0, const double* n1, double tau,
+                    double* dst, double* keep, hipStream_t s) {
+  k_gs_keep<<<nblk(n, 256), 256, 0, s>>>(n, src, n0, n1, tau, dst, keep);
 }
 
 }  // namespace aarmr
