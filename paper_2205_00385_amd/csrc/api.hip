@@ -144,6 +144,10 @@ struct aarmr_mesh {
   bool have_prev = false;
   bool mg_ready = false;
   double* hpin = nullptr;  // pinned host staging
+  // CG's r^T r partials: coherent host memory the x/r update stores into
+  // directly (host and device addresses), read by the host after an event
+  double* hrr = nullptr;
+  double* hrr_dev = nullptr;
   hipEvent_t ev_cg = nullptr;  // marks a CG iteration's scalar read-back
   // speculative hierarchy build beside the reduced-model step
   hipStream_t side = nullptr;
@@ -1042,10 +1046,10 @@ int pcg64(aarmr_mesh* m, double* x, int* iters, double* relres, int maxit_in, hi
     // simply unused.
     double* part_pq = m->partial;
     double* part_rz = m->partial + kRedBlocks;
-    double* part_rr = m->partial + 2 * kRedBlocks;  // fused_blocks(n3) + 1 entries
+    double* part_rr = m->hrr_dev;  // fused_blocks(n3) + 1 entries, in host memory
     const int nb = fused_blocks(n3);
     const bool z0 = m->p.nu_pre >= 1;
-    double* hrr = m->hpin + 1024;
+    const double* hrr = m->hrr;
     // 3D: p^T A p comes with the product and r^T z with the V-cycle's last
     // fine sweep (workgroup partials of the EbE kernel)
     const bool ebe_dots = m->dim == 3;
@@ -1063,8 +1067,8 @@ int pcg64(aarmr_mesh* m, double* x, int* iters, double* relres, int maxit_in, hi
                          sc + SC_PQ + it, x, m->r, m->pv, m->q, part_rr, m->lv[0].dinv,
                          m->p.omega, z0 ? m->z : nullptr, s);
       KCHECK();
-      // r^T r partials and the finished p^T q (stored after them) in one copy
-      HIP_TRY(hipMemcpyAsync(hrr, part_rr, (nb + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
+      // the update stored the r^T r partials and the finished p^T q (after
+      // them) into host memory: the event marks them complete
       HIP_TRY(hipEventRecord(m->ev_cg, s));
       if (it + 1 < maxit) {
         m->want_rz = ebe_dots;
@@ -1283,6 +1287,7 @@ int aarmr_mesh_create(const aarmr_params* p, aarmr_mesh** out) {
 void aarmr_mesh_destroy(aarmr_mesh* m) {
   if (!m) return;
   if (m->hpin) (void)hipHostFree(m->hpin);
+  if (m->hrr) (void)hipHostFree(m->hrr);
   if (m->ev_cg) (void)hipEventDestroy(m->ev_cg);
   if (m->ev_fine) (void)hipEventDestroy(m->ev_fine);
   if (m->ev_mg) (void)hipEventDestroy(m->ev_mg);
@@ -1294,6 +1299,7 @@ int64_t aarmr_workspace_bytes(const aarmr_mesh* m) {
   if (!m) return -1;
   aarmr_mesh tmp = *m;
   tmp.hpin = nullptr;
+  tmp.hrr = tmp.hrr_dev = nullptr;
   tmp.ev_cg = nullptr;
   tmp.ev_fine = tmp.ev_mg = nullptr;
   tmp.side = nullptr;
@@ -1306,6 +1312,11 @@ int aarmr_bind_workspace(aarmr_mesh* m, void* dev_ptr, int64_t bytes, void* stre
   const int64_t need = layout(m, nullptr);
   if (bytes < need) return fail(AARMR_E_NO_WORKSPACE, "workspace too small");
   if (!m->hpin) HIP_TRY(hipHostMalloc((void**)&m->hpin, 4096 * sizeof(double), hipHostMallocDefault));
+  if (!m->hrr) {
+    HIP_TRY(hipHostMalloc((void**)&m->hrr, (kFusedBlocks + 8) * sizeof(double),
+                          hipHostMallocMapped | hipHostMallocCoherent));
+    HIP_TRY(hipHostGetDevicePointer((void**)&m->hrr_dev, m->hrr, 0));
+  }
   if (!m->ev_cg) HIP_TRY(hipEventCreateWithFlags(&m->ev_cg, hipEventDisableTiming));
   if (!m->ev_fine) HIP_TRY(hipEventCreateWithFlags(&m->ev_fine, hipEventDisableTiming));
   if (!m->ev_mg) HIP_TRY(hipEventCreateWithFlags(&m->ev_mg, hipEventDisableTiming));
