@@ -128,7 +128,7 @@ struct aarmr_mesh {
   double *r = nullptr, *z = nullptr, *pv = nullptr, *q = nullptr, *t0 = nullptr, *fm = nullptr;
   LevelBuf lv[AARMR_MAX_LEVELS];
   double* Ainv = nullptr;
-  double *gjP = nullptr, *gjT = nullptr, *gjC = nullptr;
+  double *gjP = nullptr, *gjT = nullptr, *gjC = nullptr, *gjTb = nullptr;
   double* Phi = nullptr;   // [n_rhs_max][Ns][3nn]
   double* R = nullptr;     // [Nm][3nn]
   double* KR = nullptr;    // [Nm][3nn]
@@ -445,6 +445,7 @@ int64_t layout(aarmr_mesh* m, char* base) {
   m->gjP = (double*)take(2 * kGJBlock * kGJBlock * d8);  // two pivot inverses
   m->gjT = (double*)take((int64_t)m->nc * kGJBlock * d8);
   m->gjC = (double*)take((int64_t)m->nc * kGJBlock * d8);
+  m->gjTb = (double*)take((int64_t)m->nc * kGJBlock * d8);
   m->Phi = (double*)take((int64_t)m->p.n_rhs_max * m->p.Ns * n3 * d8);
   m->R = (double*)take((int64_t)m->p.Nm * n3 * d8);
   m->KR = (double*)take((int64_t)m->p.Nm * n3 * d8);
@@ -733,7 +734,7 @@ int build_mg(aarmr_mesh* m, hipStream_t s) {
     }
     launch_q4_assemble_dense(m->lg[m->nlev - 1], m->lv[m->nlev - 1].Ke, m->Ainv, s);
     KCHECK();
-    launch_gj_invert(m->nc, m->Ainv, m->gjP, m->gjT, m->gjC, s);
+    launch_gj_invert(m->nc, m->Ainv, m->gjP, m->gjT, m->gjC, m->gjTb, s);
     KCHECK();
     m->mg_ready = true;
     return AARMR_OK;
@@ -759,7 +760,7 @@ int build_mg(aarmr_mesh* m, hipStream_t s) {
   }
   launch_assemble_dense(m->lg[m->nlev - 1], m->lv[m->nlev - 1].Ke, m->Ainv, s);
   KCHECK();
-  launch_gj_invert(m->nc, m->Ainv, m->gjP, m->gjT, m->gjC, s);
+  launch_gj_invert(m->nc, m->Ainv, m->gjP, m->gjT, m->gjC, m->gjTb, s);
   KCHECK();
   m->mg_ready = true;
   return AARMR_OK;

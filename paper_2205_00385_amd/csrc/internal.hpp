@@ -149,8 +149,10 @@ void launch_jacobi_update(int64_t n3, const double* b, const double* t, const do
                           double omega, double* x, hipStream_t s);
 void launch_assemble_dense(const Grid& g, const double* Ke, double* A, hipStream_t s);
 // In-place inverse of the SPD n x n matrix A (blocked symmetric Gauss-Jordan).
-// Scratch: P holds two 64 x 64 pivot inverses, T and C one 64 x n panel each.
-void launch_gj_invert(int n, double* A, double* P, double* T, double* C, hipStream_t s);
+// Scratch: P holds two 64 x 64 pivot inverses, T, C and Tb one 64 x n panel
+// each.
+void launch_gj_invert(int n, double* A, double* P, double* T, double* C, double* Tb,
+                      hipStream_t s);
 void launch_gemv(int n, const double* A, const double* x, double* y, hipStream_t s);
 // FP32 V-cycle pieces (vectors FP32; element matrices and the coarsest
 // inverse stay FP64 and are applied with FP32 vectors).

@@ -798,6 +798,87 @@ __global__ void __launch_bounds__(256) k_gj_pivot_first(int n, int kb,
 // the 64 KB a workgroup may hold).
 __device__ __forceinline__ int swz(int p, int i) { return p * 64 + (i ^ ((p & 3) << 3)); }
 
+// The cross part of a block step for large orders, one workgroup per block
+// row O: A_KK = Pc for O = K; otherwise T_O = c_O Pc into Tb[q][O0 + i], the
+// new cross entries A_OK = -T_O (O < K) or A_KO = T_O (O > K), and for
+// O = K+1 the next panel's rows of K.  k_gj_step<true> then forms the tiles.
+__global__ void __launch_bounds__(256) k_gj_cross(int n, int k0, int kb, double* __restrict__ A,
+                                                  const double* __restrict__ Pc,
+                                                  const double* __restrict__ Cc,
+                                                  double* __restrict__ Cn,
+                                                  double* __restrict__ Tb) {
+  __shared__ double sm[2 * kGJBlock * kGJBlock];
+  double* sP = sm;
+  double* sX = sm + kGJBlock * kGJBlock;
+  const int K = k0 / kGJBlock, O = blockIdx.x;
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  const int li = lane & 15, lk = lane >> 4;
+  if (O == K) {
+    for (int x = tid; x < kb * kb; x += 256)
+      A[(int64_t)(k0 + x / kb) * n + k0 + x % kb] = Pc[x];
+    return;
+  }
+  const int O0 = O * kGJBlock;
+  const int orows = (n - O0 < kGJBlock) ? (n - O0) : kGJBlock;
+  double pv[16], xv[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int x = tid + 256 * r, a = x >> 6, b = x & 63;
+    pv[r] = (a < kb && b < kb) ? Pc[a * kb + b] : 0.0;
+    xv[r] = (a < kb && b < orows) ? Cc[(int64_t)a * n + O0 + b] : 0.0;
+  }
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int x = tid + 256 * r, a = x >> 6, b = x & 63;
+    sP[swz(a, b)] = pv[r];
+    sX[swz(a, b)] = xv[r];
+  }
+  __syncthreads();
+  f64x4 tacc[4];
+#pragma unroll
+  for (int jb = 0; jb < 4; ++jb) tacc[jb] = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int kk = 0; kk < 16; ++kk) {
+    const int p = 4 * kk + lk;
+    const double a = sX[swz(p, 16 * w + li)];
+#pragma unroll
+    for (int jb = 0; jb < 4; ++jb)
+      tacc[jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, sP[swz(p, 16 * jb + li)], tacc[jb], 0, 0, 0);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) sX[swz(16 * jb + li, 16 * w + lk + 4 * v)] = tacc[jb][v];
+  if (O < K) {
+#pragma unroll
+    for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = 16 * w + lk + 4 * v, q = 16 * jb + li;
+        if (i < orows && q < kb) A[(int64_t)(O0 + i) * n + k0 + q] = -tacc[jb][v];
+      }
+  } else if (O == K + 1) {
+#pragma unroll
+    for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = 16 * w + lk + 4 * v, q = 16 * jb + li;
+        if (i < orows && q < kb) Cn[(int64_t)i * n + k0 + q] = tacc[jb][v];
+      }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {  // Tb[q][O0 + i] and, beyond K, A[k0 + q][O0 + i]
+    const int x = tid + 256 * r, q = x >> 6, i = x & 63;
+    if (q < kb && i < orows) {
+      const double t = sX[swz(q, i)];
+      Tb[(int64_t)q * n + O0 + i] = t;
+      if (O > K) A[(int64_t)(k0 + q) * n + O0 + i] = t;
+    }
+  }
+}
+
 // One block step in one launch, one workgroup per upper tile (bi <= bj).
 // The step reads the pivot inverse Pc = A_KK^-1 and the panel Cc[p][i] =
 // c_i[p] (c_i = A_iK before the step, taken from the stored upper triangle)
@@ -811,12 +892,18 @@ __device__ __forceinline__ int swz(int p, int i) { return p * 64 + (i ^ ((p & 3)
 // Entries that become the next panel (block column K+1 above the diagonal,
 // block row K+1 right of it, and A_{K,K+1}) are also written to Cn.
 // Workgroup 0 takes tile (K+1, K+1) and inverts the updated tile into Pn.
+// PRE_T: k_gj_cross has already formed T_O (into Tb[q][i]) and the row/col K
+// entries for this step; the tiles read T_I instead of forming it, and the
+// row/col K workgroups have nothing to do (large orders, where the repeated
+// T products cost more than the second launch).
+template <bool PRE_T>
 __global__ void __launch_bounds__(256) k_gj_step(int n, int k0, int kb, int nb,
                                                  double* __restrict__ A,
                                                  const double* __restrict__ Pc,
                                                  double* __restrict__ Pn,
                                                  const double* __restrict__ Cc,
-                                                 double* __restrict__ Cn) {
+                                                 double* __restrict__ Cn,
+                                                 const double* __restrict__ Tb) {
   __shared__ double sm[2 * kGJBlock * kGJBlock];
   double* sP = sm;                        // Pc [p][q], later c_J [p][j]
   double* sX = sm + kGJBlock * kGJBlock;  // c_O [p][i], later T [q][i]
@@ -840,12 +927,13 @@ __global__ void __launch_bounds__(256) k_gj_step(int n, int k0, int kb, int nb,
   }
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   const int li = lane & 15, lk = lane >> 4;
+  const bool cross = bi == K || bj == K;
+  if (PRE_T && cross) return;
   if (bi == K && bj == K) {
     for (int x = tid; x < kb * kb; x += 256)
       A[(int64_t)(k0 + x / kb) * n + k0 + x % kb] = Pc[x];
     return;
   }
-  const bool cross = bi == K || bj == K;
   const int O = cross ? (bi == K ? bj : bi) : bi;  // the block whose T is formed
   const int O0 = O * kGJBlock, J0 = bj * kGJBlock, I0 = bi * kGJBlock;
   const int orows = (n - O0 < kGJBlock) ? (n - O0) : kGJBlock;
@@ -855,8 +943,9 @@ __global__ void __launch_bounds__(256) k_gj_step(int n, int k0, int kb, int nb,
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     const int x = tid + 256 * r, a = x >> 6, b = x & 63;
-    pv[r] = (a < kb && b < kb) ? Pc[a * kb + b] : 0.0;
-    xv[r] = (a < kb && b < orows) ? Cc[(int64_t)a * n + O0 + b] : 0.0;
+    // PRE_T: xv holds T_I as [q][i] instead of c_O as [p][i]
+    pv[r] = (!PRE_T && a < kb && b < kb) ? Pc[a * kb + b] : 0.0;
+    xv[r] = (a < kb && b < orows) ? (PRE_T ? Tb : Cc)[(int64_t)a * n + O0 + b] : 0.0;
     cj[r] = (!cross && a < kb && J0 + b < n) ? Cc[(int64_t)a * n + J0 + b] : 0.0;
   }
 #pragma unroll
@@ -869,9 +958,10 @@ __global__ void __launch_bounds__(256) k_gj_step(int n, int k0, int kb, int nb,
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     const int x = tid + 256 * r, a = x >> 6, b = x & 63;
-    sP[swz(a, b)] = pv[r];
+    if (!PRE_T) sP[swz(a, b)] = pv[r];
     sX[swz(a, b)] = xv[r];
   }
+  if (!PRE_T) {
   __syncthreads();
   // T[16w + i][16jb + j] = sum_p c[16w + i][p] P[p][16jb + j]
   f64x4 tacc[4];
@@ -891,7 +981,7 @@ __global__ void __launch_bounds__(256) k_gj_step(int n, int k0, int kb, int nb,
   for (int jb = 0; jb < 4; ++jb)
 #pragma unroll
     for (int v = 0; v < 4; ++v) sX[swz(16 * jb + li, 16 * w + lk + 4 * v)] = tacc[jb][v];
-  if (cross) {
+  if (cross) {  // only without PRE_T
     if (O < K) {  // A[O0 + i][k0 + q] = -T[i][q], coalesced along q
 #pragma unroll
       for (int jb = 0; jb < 4; ++jb)
@@ -919,6 +1009,7 @@ __global__ void __launch_bounds__(256) k_gj_step(int n, int k0, int kb, int nb,
     }
     return;
   }
+  }  // !PRE_T: T formed and staged as [q][i] in sX
   // tile: c_J as [p][j] replaces P
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
@@ -1159,20 +1250,34 @@ void launch_assemble_dense(const Grid& g, const double* Ke, double* A, hipStream
   k_assemble_dense<<<(unsigned)((3 * g.nn + 3) / 4), 256, 0, s>>>(g.nx, g.ny, g.nz, Ke, A);
 }
 
-void launch_gj_invert(int n, double* A, double* P, double* T, double* C, hipStream_t s) {
+void launch_gj_invert(int n, double* A, double* P, double* T, double* C, double* Tb,
+                      hipStream_t s) {
   const int nb = (n + kGJBlock - 1) / kGJBlock;
   const unsigned n_upper = (unsigned)(nb * (nb + 1) / 2);
   // pivot inverses and panels alternate between two buffers each
   double* Pb[2] = {P, P + kGJBlock * kGJBlock};
   double* Cb[2] = {C, T};
+  // beyond 40 block rows the repeated T products of the one-launch step cost
+  // more than a separate cross launch (measured: 32 us per step at 30 block
+  // rows in one launch; 73 vs 61 us per step at 65)
+  const bool split = nb > 40;
   const int kb0 = std::min(n, kGJBlock);
   k_gj_pivot_first<<<(unsigned)(1 + ((int64_t)kb0 * n + 2047) / 2048), 256, 0, s>>>(n, kb0, A,
                                                                                   Pb[0], Cb[0]);
   int step = 0;
   for (int k0 = 0; k0 < n; k0 += kGJBlock, ++step) {
     const int kb = std::min(kGJBlock, n - k0);
-    k_gj_step<<<n_upper, 256, 0, s>>>(n, k0, kb, nb, A, Pb[step & 1], Pb[(step + 1) & 1],
-                                      Cb[step & 1], Cb[(step + 1) & 1]);
+    if (split) {
+      k_gj_cross<<<nb, 256, 0, s>>>(n, k0, kb, A, Pb[step & 1], Cb[step & 1],
+                                    Cb[(step + 1) & 1], Tb);
+      k_gj_step<true><<<n_upper, 256, 0, s>>>(n, k0, kb, nb, A, Pb[step & 1],
+                                              Pb[(step + 1) & 1], Cb[step & 1],
+                                              Cb[(step + 1) & 1], Tb);
+    } else {
+      k_gj_step<false><<<n_upper, 256, 0, s>>>(n, k0, kb, nb, A, Pb[step & 1],
+                                               Pb[(step + 1) & 1], Cb[step & 1],
+                                               Cb[(step + 1) & 1], nullptr);
+    }
   }
   k_gj_mirror<<<dim3(nb, nb), 256, 0, s>>>(n, A);
 }
