@@ -806,9 +806,11 @@ int apply32(aarmr_mesh* m, int l, const float* v, float* y, hipStream_t s) {
   return AARMR_OK;
 }
 
-// The V-cycle of vcycle() with FP32 vectors and smoothing; the coarsest
-// inverse is the FP64 one.
-int vcycle32(aarmr_mesh* m, int l, const float* b, float* x, hipStream_t s) {
+// The V-cycle of vcycle() with FP32 vectors and smoothing, and the same
+// fused sweeps; the coarsest inverse is the FP64 one.  x_init: x already
+// holds the level's first Jacobi sweep.
+int vcycle32(aarmr_mesh* m, int l, const float* b, float* x, hipStream_t s,
+             bool x_init = false) {
   if (l == m->nlev - 1) {
     launch_gemv_f32(m->nc, m->Ainv, b, x, s);
     KCHECK();
@@ -820,25 +822,56 @@ int vcycle32(aarmr_mesh* m, int l, const float* b, float* x, hipStream_t s) {
   LevelBuf& C = m->lv[l + 1];
   const uint8_t* mask = (l == 0) ? m->mask : nullptr;
   const float om = (float)m->p.omega;
+  const bool child_first = m->p.nu_pre >= 1 && l + 1 < m->nlev - 1;
   if (m->p.nu_pre >= 1) {
-    launch_jacobi_first_f32(n3, b, L.dinv32, om, x, s);
-    KCHECK();
+    if (!x_init) {
+      launch_jacobi_first_f32(n3, b, L.dinv32, om, x, s);
+      KCHECK();
+    }
     for (int it = 1; it < m->p.nu_pre; ++it) {
       TRY(apply32(m, l, x, L.t32, s));
       launch_jacobi_update_f32(n3, b, L.t32, L.dinv32, om, x, s);
       KCHECK();
     }
     TRY(apply32(m, l, x, L.t32, s));
-    launch_restrict_f32(m->lg[l + 1], b, L.t32, mask, C.b32, s);
+    if (child_first)
+      launch_restrict_jacobi_f32(m->lg[l + 1], b, L.t32, mask, C.b32, C.dinv32, om, C.x32, s);
+    else
+      launch_restrict_f32(m->lg[l + 1], b, L.t32, mask, C.b32, s);
   } else {
     HIP_TRY(hipMemsetAsync(x, 0, n3 * sizeof(float), s));
     launch_restrict_f32(m->lg[l + 1], b, nullptr, mask, C.b32, s);
   }
   KCHECK();
-  TRY(vcycle32(m, l + 1, C.b32, C.x32, s));
+  TRY(vcycle32(m, l + 1, C.b32, C.x32, s, child_first));
   launch_prolong_add_f32(G, C.x32, mask, x, s);
   KCHECK();
   for (int it = 0; it < m->p.nu_post; ++it) {
+    const bool last = it == m->p.nu_post - 1;
+    if (l == 0 && x == m->z32 && last) {
+      // the solver's own z: the sweep (with r^T z partials) writes into t32,
+      // and the two swap roles
+      m->rz_nb = launch_ebe_jacobi_f32_dot(G, m->wk, m->E32, m->mask, x, b, L.dinv32, om, L.t32,
+                                           m->part_rz, s, m->tz32);
+      ++m->sweeps;
+      KCHECK();
+      std::swap(m->z32, L.t32);
+      continue;
+    }
+    if (l >= 1 && last) {
+      if (l == 1) {
+        TRY(flagged_count(m, s));
+        launch_apply_l1_jacobi_f32(m->lg[1], L.Ke, m->Kcomp1, m->cap1, m->Bw32d, m->E32,
+                                   m->eflag1, m->list1, m->count1, m->nflag1, x, m->Y1f, b,
+                                   L.dinv32, om, s);
+      } else {
+        if (x != L.x32) return fail(AARMR_E_STATE, "V-cycle iterate is not the level's buffer");
+        launch_apply_elemmat_jacobi_f32(G, L.Ke, x, b, L.dinv32, om, L.t32, s);
+        std::swap(L.x32, L.t32);
+      }
+      KCHECK();
+      continue;
+    }
     TRY(apply32(m, l, x, L.t32, s));
     launch_jacobi_update_f32(n3, b, L.t32, L.dinv32, om, x, s);
     KCHECK();
@@ -872,30 +905,48 @@ int pcg32(aarmr_mesh* m, double rtol, int maxit, int* iters, double* relres, boo
   *relres = 1.0;
   *stalled = false;
   const double tol2 = rtol * rtol;
+  m->rz_nb = 0;
   TRY(vcycle32(m, 0, m->r32, m->z32, s));
   TRY(dot32(m, m->r32, m->z32, sc + SC_RZ, n3, s));
   launch_copy_f32(n3, m->z32, m->p32, s);
   KCHECK();
-  double h[3];
+  // as pcg64: p^T A p from the product's workgroups, r^T z from the V-cycle's
+  // last fine sweep, the x/r update storing the r^T r partials, p^T q and r^T z
+  // into host memory, and the next V-cycle and direction update queued before
+  // the host waits for them
+  const int nb = fused_blocks(n3);
+  const double* hrr = m->hrr;
+  const float om = (float)m->p.omega;
   for (int it = 0; it < maxit; ++it) {
-    TRY(apply32(m, 0, m->p32, m->q32, s));
-    TRY(dot32(m, m->p32, m->q32, sc + SC_PQ + it, n3, s));
-    launch_cg_xr_f32(n3, sc + SC_RZ + it, sc + SC_PQ + it, m->d32, m->r32, m->p32, m->q32, s);
+    const int n_pq = launch_ebe_f32_dot(g, m->wk, m->E32, m->mask, m->p32, m->q32, m->part_pq,
+                                        s, m->tz32);
+    ++m->sweeps;
+    launch_cg_xr_fused_f32(n3, sc + SC_RZ + it, m->part_pq, n_pq, sc + SC_PQ + it, m->d32,
+                           m->r32, m->p32, m->q32, m->hrr_dev, m->lv[0].dinv32, om, m->z32, s);
     KCHECK();
-    TRY(dot32(m, m->r32, m->r32, sc + SC_RR + it + 1, n3, s));
-    const double* src[3] = {sc + SC_RR + it + 1, sc + SC_PQ + it, sc + SC_RZ + it};
-    TRY(read_scalars(m, src, 3, h, s));
+    HIP_TRY(hipEventRecord(m->ev_cg, s));
+    if (it + 1 < maxit) {
+      m->rz_nb = 0;
+      TRY(vcycle32(m, 0, m->r32, m->z32, s, m->p.nu_pre >= 1));
+      if (m->rz_nb > 0) {
+        launch_cg_p_fused_f32(n3, m->part_rz, m->rz_nb, sc + SC_RZ + it + 1, sc + SC_RZ + it,
+                              m->z32, m->p32, s);
+      } else {
+        TRY(dot32(m, m->r32, m->z32, sc + SC_RZ + it + 1, n3, s));
+        launch_cg_p_f32(n3, sc + SC_RZ + it + 1, sc + SC_RZ + it, m->z32, m->p32, s);
+      }
+      KCHECK();
+    }
+    HIP_TRY(hipEventSynchronize(m->ev_cg));
+    double rr = 0.0;
+    for (int b = 0; b < nb; ++b) rr += hrr[b];
     *iters = it + 1;
-    *relres = std::sqrt(h[0]);
-    if (!(h[1] > 0.0) || !(h[2] > 0.0)) {
+    *relres = std::sqrt(rr);
+    if (!(hrr[nb] > 0.0) || !(hrr[nb + 1] > 0.0)) {
       *stalled = true;
       return AARMR_OK;
     }
-    if (h[0] <= tol2) return AARMR_OK;
-    TRY(vcycle32(m, 0, m->r32, m->z32, s));
-    TRY(dot32(m, m->r32, m->z32, sc + SC_RZ + it + 1, n3, s));
-    launch_cg_p_f32(n3, sc + SC_RZ + it + 1, sc + SC_RZ + it, m->z32, m->p32, s);
-    KCHECK();
+    if (rr <= tol2) return AARMR_OK;
   }
   return AARMR_OK;
 }

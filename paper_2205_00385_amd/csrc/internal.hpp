@@ -79,6 +79,13 @@ int launch_ebe_jacobi_dot(const Grid& g, const WalshConsts& K, const double* E,
                           const uint8_t* mask, const double* v, const double* b,
                           const double* dinv, double omega, double* out, double* part,
                           hipStream_t s, int tz = 0);
+// FP32 forms of the two (vectors FP32, partials summed in FP64).
+int launch_ebe_f32_dot(const Grid& g, const WalshConsts& K, const float* E, const uint8_t* mask,
+                       const float* v, float* y, double* part, hipStream_t s, int tz = 0);
+int launch_ebe_jacobi_f32_dot(const Grid& g, const WalshConsts& K, const float* E,
+                              const uint8_t* mask, const float* v, const float* b,
+                              const float* dinv, float omega, float* out, double* part,
+                              hipStream_t s, int tz = 0);
 void launch_energy_walsh(const Grid& g, const WalshConsts& K, const uint8_t* mask,
                          const double* u, double* energy, hipStream_t s);
 void launch_simp(int64_t ne, const double* rho, double E0, double Emin, double p, double* E,
@@ -119,6 +126,17 @@ void launch_apply_l1(const Grid& g, const double* Ke, const double* Kcomp, int c
                      const double* Bw, const double* Ef, const uint8_t* eflag, const int* list,
                      const int* count, int nflag, const double* v, double* Y, double* y,
                      hipStream_t s);
+// FP32 forms of the Jacobi-fused products and restriction (as the FP64 ones).
+void launch_apply_l1_jacobi_f32(const Grid& g, const double* Ke, const double* Kcomp, int cap,
+                                const float* Bw, const float* Ef, const uint8_t* eflag,
+                                const int* list, const int* count, int nflag, float* x, float* Y,
+                                const float* b, const float* dinv, float omega, hipStream_t s);
+void launch_apply_elemmat_jacobi_f32(const Grid& g, const double* Ke, const float* v,
+                                     const float* b, const float* dinv, float omega, float* out,
+                                     hipStream_t s);
+void launch_restrict_jacobi_f32(const Grid& coarse, const float* bf, const float* tf,
+                                const uint8_t* mask, float* bc, const float* dinv_c, float omega,
+                                float* xc, hipStream_t s);
 void launch_apply_l1_f32(const Grid& g, const double* Ke, const double* Kcomp, int cap,
                          const float* Bw, const float* Ef, const uint8_t* eflag, const int* list,
                          const int* count, int nflag, const float* v, float* Y, float* y,
@@ -206,6 +224,14 @@ void launch_cg_xr_fused(int64_t n, const double* rz, const double* pq_part, int 
 // dot_blocks(n)), stored to *rz_new; p = z + (rz_new / *rz_old) p.
 void launch_cg_p_fused(int64_t n, const double* rz_part, int n_part, double* rz_new,
                        const double* rz_old, const double* z, double* p, hipStream_t s);
+// The FP32 forms (FP32 vectors, FP64 scalars and partials); the x/r update
+// also stores *rz at rr_part[fused_blocks(n) + 1] and always writes z0.
+void launch_cg_xr_fused_f32(int64_t n, const double* rz, const double* pq_part, int n_part,
+                            double* pq, float* x, float* r, const float* p, const float* q,
+                            double* rr_part, const float* dinv, float omega, float* z0,
+                            hipStream_t s);
+void launch_cg_p_fused_f32(int64_t n, const double* rz_part, int n_part, double* rz_new,
+                           const double* rz_old, const float* z, float* p, hipStream_t s);
 void launch_scale_by_inv_sqrt(int64_t n, const double* src, const double* nrm2, double* dst,
                               hipStream_t s);
 // out = sum_j coef[j] * V_j (+ add) with coefficients read from device memory

@@ -128,7 +128,7 @@ __global__ void __launch_bounds__(kThreads, AARMR_EBE_MINB) k_ebe_z(int nx, int 
                                                     const T* __restrict__ v, T* __restrict__ y,
                                                     const T* __restrict__ jb,
                                                     const T* __restrict__ jd, T omega,
-                                                    T* __restrict__ part) {
+                                                    double* __restrict__ part) {
   constexpr bool OWNV = JAC || DOT;  // keep the node's own v of the plane written next
   __shared__ T xs[2][3][kRows][kLanes];
   const int tx = threadIdx.x & (kLanes - 1), ty = threadIdx.x / kLanes;
@@ -220,7 +220,7 @@ __global__ void __launch_bounds__(kThreads, AARMR_EBE_MINB) k_ebe_z(int nx, int 
   }
   uint32_t own_m = 7u;  // fixed-DOF mask of node (i, j) on the plane written next
   T own_v[3] = {}, own_b[3] = {}, own_d[3] = {};  // JAC: that node's v, jb, jd
-  T dacc = (T)0;                                   // DOT: this thread's share
+  double dacc = 0.0;                               // DOT: this thread's share, FP64
 #pragma unroll
   for (int q = 0; q < 4; ++q)
 #pragma unroll
@@ -292,7 +292,7 @@ __global__ void __launch_bounds__(kThreads, AARMR_EBE_MINB) k_ebe_z(int nx, int 
       if (JAC) out = own_v[c] + omega * own_d[c] * (own_b[c] - out);
       if ((own_m >> c) & 1u) out = (T)0;
       st(ry, oy + (uint32_t)c * cstride, out);
-      if (DOT) dacc += wr ? (JAC ? own_b[c] : own_v[c]) * out : (T)0;
+      if (DOT) dacc += wr ? (double)(JAC ? own_b[c] : own_v[c]) * (double)out : 0.0;
     }
     buf ^= 1;
     own_m = m_next;
@@ -316,7 +316,7 @@ __global__ void __launch_bounds__(kThreads, AARMR_EBE_MINB) k_ebe_z(int nx, int 
     }
   }
   if (DOT) {  // wavefront sums, then the four in wave order
-    __shared__ T wsum[kThreads / 64];
+    __shared__ double wsum[kThreads / 64];
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) dacc += __shfl_down(dacc, off, 64);
     if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = dacc;
@@ -399,7 +399,7 @@ __global__ void k_identity_rows(int64_t nn, const uint8_t* __restrict__ mask,
 template <typename T, bool MASK_IN, bool JAC = false, bool DOT = false>
 static int launch_ebe_t(const Grid& g, const WalshConsts& K, const T* E, const uint8_t* mask,
                         const T* v, T* y, int tz_req, hipStream_t s, const T* jb = nullptr,
-                        const T* jd = nullptr, T omega = 0, T* part = nullptr) {
+                        const T* jd = nullptr, T omega = 0, double* part = nullptr) {
   // resident workgroups of this kernel on the device (thread-safe one-time init)
   static const int slots = [] {
     int dev = 0, cus = 0, per_cu = 0;
@@ -442,6 +442,20 @@ int launch_ebe_jacobi_dot(const Grid& g, const WalshConsts& K, const double* E,
                           hipStream_t s, int tz) {
   return launch_ebe_t<double, false, true, true>(g, K, E, mask, v, out, tz, s, b, dinv, omega,
                                                  part);
+}
+
+int launch_ebe_f32_dot(const Grid& g, const WalshConsts& K, const float* E, const uint8_t* mask,
+                       const float* v, float* y, double* part, hipStream_t s, int tz) {
+  return launch_ebe_t<float, false, false, true>(g, K, E, mask, v, y, tz, s, nullptr, nullptr,
+                                                 0.0f, part);
+}
+
+int launch_ebe_jacobi_f32_dot(const Grid& g, const WalshConsts& K, const float* E,
+                              const uint8_t* mask, const float* v, const float* b,
+                              const float* dinv, float omega, float* out, double* part,
+                              hipStream_t s, int tz) {
+  return launch_ebe_t<float, false, true, true>(g, K, E, mask, v, out, tz, s, b, dinv, omega,
+                                                part);
 }
 
 void launch_ebe(const Grid& g, const WalshConsts& K, const double* E, const uint8_t* mask,

@@ -1176,11 +1176,34 @@ void launch_apply_l1(const Grid& g, const double* Ke, const double* Kcomp, int c
   l1_apply<double>(g, Ke, Kcomp, cap, Bw, Ef, eflag, list, count, nflag, v, Y, y, s);
 }
 
+void launch_apply_l1_jacobi_f32(const Grid& g, const double* Ke, const double* Kcomp, int cap,
+                                const float* Bw, const float* Ef, const uint8_t* eflag,
+                                const int* list, const int* count, int nflag, float* x, float* Y,
+                                const float* b, const float* dinv, float omega, hipStream_t s) {
+  l1_apply<float>(g, Ke, Kcomp, cap, Bw, Ef, eflag, list, count, nflag, x, Y, x, s, b, dinv,
+                  omega);
+}
+
 void launch_apply_l1_f32(const Grid& g, const double* Ke, const double* Kcomp, int cap,
                          const float* Bw, const float* Ef, const uint8_t* eflag, const int* list,
                          const int* count, int nflag, const float* v, float* Y, float* y,
                          hipStream_t s) {
   l1_apply<float>(g, Ke, Kcomp, cap, Bw, Ef, eflag, list, count, nflag, v, Y, y, s);
+}
+
+void launch_apply_elemmat_jacobi_f32(const Grid& g, const double* Ke, const float* v,
+                                     const float* b, const float* dinv, float omega, float* out,
+                                     hipStream_t s) {
+  k_apply_elemmat<float><<<nblk(g.nn, 64), 512, 0, s>>>(g.nx, g.ny, g.nz, Ke, v, out, b, dinv,
+                                                        omega);
+}
+
+void launch_restrict_jacobi_f32(const Grid& coarse, const float* bf, const float* tf,
+                                const uint8_t* mask, float* bc, const float* dinv_c, float omega,
+                                float* xc, hipStream_t s) {
+  k_restrict<float><<<dim3(nblk(coarse.nn, 64), 3), 192, 0, s>>>(coarse.nx, coarse.ny, coarse.nz,
+                                                                 bf, tf, mask, bc, dinv_c, omega,
+                                                                 xc);
 }
 
 void launch_restrict_f32(const Grid& coarse, const float* bf, const float* tf,

@@ -132,6 +132,58 @@ __global__ void __launch_bounds__(256) k_cg_p_fused(int64_t n, const double* __r
     p[i] = fma(beta, p[i], z[i]);
 }
 
+// The FP32 CG step with its reductions folded in, as k_cg_xr_fused: FP32
+// vectors, FP64 scalars and partials.  Block 0 also stores *rz beside p^T q
+// (rr_part[gridDim.x + 1]) so that the host sees both signs the stall test
+// needs.  z0 = omega dinv r in FP32, the V-cycle's first sweep.
+__global__ void __launch_bounds__(256) k_cg_xr_fused_f32(int64_t n, const double* __restrict__ rz,
+                                                         const double* __restrict__ pq_part,
+                                                         int nb, double* __restrict__ pq,
+                                                         float* __restrict__ x,
+                                                         float* __restrict__ r,
+                                                         const float* __restrict__ p,
+                                                         const float* __restrict__ q,
+                                                         double* __restrict__ rr_part,
+                                                         const float* __restrict__ dinv,
+                                                         float omega, float* __restrict__ z0) {
+  __shared__ double sh[5];
+  const double pqv = finish_partials(pq_part, nb, sh);
+  const double rzv = *rz;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    *pq = pqv;
+    rr_part[gridDim.x] = pqv;
+    rr_part[gridDim.x + 1] = rzv;
+  }
+  const double alpha = rzv / pqv;
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) {
+    x[i] = (float)fma(alpha, (double)p[i], (double)x[i]);
+    const float ri = (float)fma(-alpha, (double)q[i], (double)r[i]);
+    r[i] = ri;
+    acc = fma((double)ri, (double)ri, acc);
+    z0[i] = omega * dinv[i] * ri;
+  }
+  acc = block_sum(acc, sh);
+  if (threadIdx.x == 0) rr_part[blockIdx.x] = acc;
+}
+
+// beta = rz_new / *rz_old, rz_new finished from nb FP64 partials (block 0
+// stores it); p = z + beta p in FP32 vectors.
+__global__ void __launch_bounds__(256) k_cg_p_fused_f32(int64_t n, const double* __restrict__ rz_part,
+                                                        int nb, double* __restrict__ rz_new,
+                                                        const double* __restrict__ rz_old,
+                                                        const float* __restrict__ z,
+                                                        float* __restrict__ p) {
+  __shared__ double sh[5];
+  const double rzv = finish_partials(rz_part, nb, sh);
+  if (blockIdx.x == 0 && threadIdx.x == 0) *rz_new = rzv;
+  const double beta = rzv / *rz_old;
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride)
+    p[i] = (float)fma(beta, (double)p[i], (double)z[i]);
+}
+
 __global__ void k_copy_masked(int64_t nn, int ncomp, const double* __restrict__ src,
                               const uint8_t* __restrict__ mask, double* __restrict__ dst) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -378,6 +430,19 @@ void launch_multidot_f32(const DotSetT<float>& d, const RedScratch& rs, hipStrea
 void launch_cg_xr_f32(int64_t n, const double* rz, const double* pq, float* x, float* r,
                       const float* p, const float* q, hipStream_t s) {
   k_cg_xr_f32<<<nblk(n, 256), 256, 0, s>>>(n, rz, pq, x, r, p, q);
+}
+
+void launch_cg_xr_fused_f32(int64_t n, const double* rz, const double* pq_part, int n_part,
+                            double* pq, float* x, float* r, const float* p, const float* q,
+                            double* rr_part, const float* dinv, float omega, float* z0,
+                            hipStream_t s) {
+  k_cg_xr_fused_f32<<<fused_blocks(n), 256, 0, s>>>(n, rz, pq_part, n_part, pq, x, r, p, q,
+                                                    rr_part, dinv, omega, z0);
+}
+
+void launch_cg_p_fused_f32(int64_t n, const double* rz_part, int n_part, double* rz_new,
+                           const double* rz_old, const float* z, float* p, hipStream_t s) {
+  k_cg_p_fused_f32<<<fused_blocks(n), 256, 0, s>>>(n, rz_part, n_part, rz_new, rz_old, z, p);
 }
 
 void launch_cg_p_f32(int64_t n, const double* rz_new, const double* rz_old, const float* z,
