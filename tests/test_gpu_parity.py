@@ -363,6 +363,54 @@ def test_autotune_keeps_products_bitwise(dims):
         m.close()
 
 
+def test_rejected_reduced_model_runs_beside_speculative_hierarchy():
+    """Three reduced-model steps in a row that are all rejected (ca_tol
+    1e-12): from the second on, the MG hierarchy of the new design is built on
+    a second stream while the reduced model runs.  Every fallback solution,
+    compliance and sensitivity must still be the direct solve's, and the
+    reported rank and eps must agree (1e-6) with a fresh mesh taken through
+    the same history, whose reduced-model step is its first and so builds
+    the hierarchy only after the rejection."""
+    from paper_2205_00385_amd import aarmr
+
+    prob = synth.cantilever(16, 8, 8)
+    Ns, Nm = 2, 3
+    kw = dict(mg_levels=3, cg_rtol=1e-11, Ns=Ns, Nm=Nm, ca_tol=1e-12)
+    m = mesh_for(prob, **kw)
+    fixed = fixed_tensor(prob, m)
+    f = loads_tensor(prob, m)
+    base = synth.smoothed_field(16, 8, 8, 2.0, 0.2, 1.0, seed=60).ravel()
+    d = synth.smoothed_field(16, 8, 8, 3.0, -1.0, 1.0, seed=61).ravel()
+    designs = [np.clip(base + 0.03 * k * d, 0.05, 1.0) for k in range(6)]
+    edof = fem.element_dofs(16, 8, 8)
+    u = torch.zeros_like(f)
+    dc = torch.zeros(m.n_elem, dtype=torch.float64, device="cuda")
+    for k in range(Ns):
+        m.solve(t64(designs[k]), f, fixed, u, flags=aarmr.RECORD_PARM | (aarmr.WARM_START if k else 0))
+    for k in range(Ns, 6):
+        rho = designs[k]
+        # reference: a fresh mesh taken through the same history, its step not speculative
+        # (PARM = the last Ns solutions, reference design k - 1, u_last = m's u)
+        m2 = mesh_for(prob, **kw)
+        u2 = torch.zeros_like(f)
+        for j in range(k):
+            m2.solve(t64(designs[j]), f, fixed, u2,
+                     flags=aarmr.WARM_START | (aarmr.RECORD_PARM if j >= k - Ns else 0))
+        u2.copy_(u)
+        C2, st2, _ = m2.ca_update(t64(rho), f, fixed, u2)
+        m2.close()
+        C, st, code = m.ca_update(t64(rho), f, fixed, u, dc=dc)
+        assert code == aarmr.OK and st.accepted[0] == 0
+        log(f"  step {k}: eps {st.eps[0]:.3e} rank {st.rank[0]}, fallback {st.mgcg_iterations[0]} it")
+        (u_ref,), (C_ref,), dc_ref = sens.analyse(prob, rho)
+        assert rel(u.cpu().numpy(), soa(u_ref)) < 1e-8
+        assert abs(C[0] - C_ref) <= 1e-8 * abs(C_ref)
+        assert rel(dc.cpu().numpy(), dc_ref) < 1e-7
+        assert st.rank[0] == st2.rank[0]
+        assert abs(st.eps[0] - st2.eps[0]) <= 1e-6 * st2.eps[0]
+    m.close()
+
+
 def test_ca_svd_and_gs_bases_give_same_reduced_solution():
     """Nm > Ns + 1 (dependent CARM columns): the SVD and the Gram-Schmidt
     bases span the same space, so the reduced solution and eps agree."""
