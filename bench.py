@@ -519,6 +519,7 @@ def batched_form(torch, aarmr, synth, stream_counts=(1, 4), reps=2):
                        "cases each, refinement form, 4 levels, rel. residual 1e-8",
            "elements": int(sum(a * b * c for a, b, c in sizes)), "solves_per_batch": n_solves,
            "autotune_s": round(t_tune, 3)}
+    comp_refine = None
     for ns in stream_counts:
         streams = [torch.cuda.Stream() for _ in range(ns)]
         times = []
@@ -527,7 +528,7 @@ def batched_form(torch, aarmr, synth, stream_counts=(1, 4), reps=2):
                 jb["u"].zero_()
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            _, items, code = aarmr.batch_solve(jobs, streams)
+            comp_refine, items, code = aarmr.batch_solve(jobs, streams)
             dt = time.perf_counter() - t0
             if r > 0:
                 times.append(dt)
@@ -539,6 +540,52 @@ def batched_form(torch, aarmr, synth, stream_counts=(1, 4), reps=2):
         print(f"[bench] batch {ns} streams: {T * 1e3:.1f} ms", file=sys.stderr, flush=True)
     for jb in jobs:
         jb["mesh"].close()
+    # the same 64 analyses in plain FP64, one after another on one stream
+    plain = []
+    for jb in jobs:
+        m = jb["mesh"]
+        p = aarmr.default_params(nx=m.nx, ny=m.ny, nz=m.nz, mg_levels=4, cg_rtol=1e-8,
+                                 cg_maxit=2000, n_rhs_max=4, precision=aarmr.FP64)
+        m64 = aarmr.Mesh(p)
+        m64.autotune()
+        plain.append(m64)
+    times, comp_plain = [], []
+    for r in range(reps + 1):
+        for jb in jobs:
+            jb["u"].zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        comp_plain = [m64.solve(jb["rho"], jb["f"], jb["fixed"], jb["u"])[0]
+                      for m64, jb in zip(plain, jobs)]
+        dt = time.perf_counter() - t0
+        if r > 0:
+            times.append(dt)
+    T = float(np.median(times))
+    worst = max(abs(a - b) / abs(b) for ca, cb in zip(comp_refine, comp_plain)
+                for a, b in zip(ca, cb))
+    out["plain_fp64_one_at_a_time"] = {"ms_per_batch": round(T * 1e3, 2),
+                                       "solves_s": round(n_solves / T, 2)}
+    # and the FP64 meshes through the batch call on 4 streams: how much of the
+    # gain is the concurrency and how much the precision
+    jobs64 = [dict(jb, mesh=m64) for m64, jb in zip(plain, jobs)]
+    streams = [torch.cuda.Stream() for _ in range(4)]
+    times = []
+    for r in range(reps + 1):
+        for jb in jobs64:
+            jb["u"].zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        aarmr.batch_solve(jobs64, streams)
+        dt = time.perf_counter() - t0
+        if r > 0:
+            times.append(dt)
+    T = float(np.median(times))
+    out["fp64_streams_4"] = {"ms_per_batch": round(T * 1e3, 2), "solves_s": round(n_solves / T, 2)}
+    out["compliance_max_rel_diff_vs_plain"] = worst
+    out["within_1e-6"] = bool(worst <= 1e-6)
+    print(f"[bench] batch plain FP64: {T * 1e3:.1f} ms", file=sys.stderr, flush=True)
+    for m64 in plain:
+        m64.close()
     return out
 
 
