@@ -705,27 +705,50 @@ __device__ __forceinline__ void st16(double* C, int ldc, f64x4 x, double sgn) {
   for (int v = 0; v < 4; ++v) C[(lk + 4 * v) * ldc + li] = sgn * x[v];
 }
 
+// Lane (16 r + k)'s value of v for every lane of the 16-lane row r (DPP
+// row_newbcast).
+template <int K>
+__device__ __forceinline__ double row_bcast(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x150 + K, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x150 + K, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+// One pivot step k of gj16_wave.  The pivot S[k][k] is wave-uniform (lane
+// reads), the pivot column S[4 r4 + q][k] comes from lane k of the lane's own
+// 16-lane row (row_newbcast), and the pivot row S[k][c] from lane 16 (k/4) + c.
+template <int K>
+struct Gj16Step {
+  static __device__ __forceinline__ void run(double (&x)[4], int c, int r4) {
+    constexpr int kq = K & 3, kr = K >> 2;
+    const double rk = __shfl(x[kq], kr * 16 + c, 64);  // S[k][c]
+    const int plo = __builtin_amdgcn_readlane(__double2loint(x[kq]), kr * 16 + K);
+    const int phi = __builtin_amdgcn_readlane(__double2hiint(x[kq]), kr * 16 + K);
+    const double piv = recip(__hiloint2double(phi, plo));
+    const bool pc = (c == K);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const double ck = row_bcast<K>(x[q]);  // S[4 r4 + q][k]
+      const double upd = pc ? -ck * piv : fma(-ck * piv, rk, x[q]);
+      x[q] = (4 * r4 + q == K) ? (pc ? piv : rk * piv) : upd;
+    }
+    Gj16Step<K + 1>::run(x, c, r4);
+  }
+};
+template <>
+struct Gj16Step<16> {
+  static __device__ __forceinline__ void run(double (&)[4], int, int) {}
+};
+
 // In-place Gauss-Jordan inversion of a 16x16 block of LDS (row stride ld) by
 // one wavefront in registers: lane l holds rows 4(l/16)..4(l/16)+3 of column
-// l%16; pivot row and column are exchanged with lane shuffles.
+// l%16.
 __device__ __forceinline__ void gj16_wave(double* S, int ld) {
   const int l = threadIdx.x & 63, c = l & 15, r4 = l >> 4;
   double x[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) x[q] = S[(4 * r4 + q) * ld + c];
-#pragma unroll
-  for (int k = 0; k < 16; ++k) {
-    const int kq = k & 3, kr = k >> 2;
-    const double rk = __shfl(x[kq], kr * 16 + c, 64);   // S[k][c]
-    const double piv = recip(__shfl(x[kq], kr * 16 + k, 64));
-    const bool pc = (c == k);
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const double ck = __shfl(x[q], r4 * 16 + k, 64);  // S[4 r4 + q][k]
-      const double upd = pc ? -ck * piv : fma(-ck * piv, rk, x[q]);
-      x[q] = (4 * r4 + q == k) ? (pc ? piv : rk * piv) : upd;
-    }
-  }
+  Gj16Step<0>::run(x, c, r4);
 #pragma unroll
   for (int q = 0; q < 4; ++q) S[(4 * r4 + q) * ld + c] = x[q];
 }
