@@ -771,9 +771,9 @@ __device__ __forceinline__ void gj64_block(double (*sS)[kGJBlock + 1]) {
     if (w < 3) {
       T = mma16(&sS[ob][J0], ld, &sS[J0][J0], ld, zero, 1.0);
       R = mma16(&sS[J0][J0], ld, &sS[J0][ob], ld, zero, 1.0);
+      // no barrier before this store: S_J,ob is read only by this wave
+      st16(&sS[J0][ob], ld, R, 1.0);
     }
-    __syncthreads();
-    if (w < 3) st16(&sS[J0][ob], ld, R, 1.0);
     __syncthreads();
     for (int t = w; t < 9; t += 4) {
       const int q1 = t / 3, q2 = t % 3;
