@@ -229,7 +229,11 @@ int aarmr_solve(aarmr_mesh* m, const double* rho, const double* f, int32_t n_rhs
  * and its normalised solution enters the PARM (Algorithm 1 lines 9-10).
  * Arguments as for aarmr_solve; `u` must hold each case's last solution on
  * entry.  Compliance and dc use the returned u (eq. 34 when accepted).
- * Records the new reference design.  Synchronises `stream`.
+ * Records the new reference design.  When the previous call on this mesh
+ * rejected the reduced model, the MG hierarchy of the new design is built on
+ * a second stream the mesh owns (default priority, non-blocking) while the
+ * reduced model runs on `stream`; it is joined into `stream` before the
+ * fallback and before the call returns.  Synchronises `stream`.
  * Errors: as aarmr_solve, plus AARMR_E_STATE if a case holds fewer than Ns
  * PARM vectors or no reference design exists. */
 int aarmr_ca_update(aarmr_mesh* m, const double* rho, const double* f, int32_t n_rhs,
