@@ -494,8 +494,13 @@ int dot1(aarmr_mesh* m, const double* a, const double* b, double* out, int64_t n
 
 // Copy `cnt` device scalars to the pinned staging buffer and synchronise.
 int read_scalars(aarmr_mesh* m, const double* const* src, int cnt, double* dst, hipStream_t s) {
-  for (int i = 0; i < cnt; ++i)
-    HIP_TRY(hipMemcpyAsync(m->hpin + i, src[i], sizeof(double), hipMemcpyDeviceToHost, s));
+  bool contiguous = true;  // then one copy brings them all
+  for (int i = 1; i < cnt; ++i) contiguous = contiguous && src[i] == src[0] + i;
+  if (contiguous && cnt > 1)
+    HIP_TRY(hipMemcpyAsync(m->hpin, src[0], cnt * sizeof(double), hipMemcpyDeviceToHost, s));
+  else
+    for (int i = 0; i < cnt; ++i)
+      HIP_TRY(hipMemcpyAsync(m->hpin + i, src[i], sizeof(double), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   for (int i = 0; i < cnt; ++i) dst[i] = m->hpin[i];
   return AARMR_OK;
