@@ -59,9 +59,10 @@ def test_operator_apply_is_deterministic():
 
 
 # (32, 16, 16, 2): a 4131-DOF coarsest level, 65 Gauss-Jordan block rows,
-# which the inverse runs as separate cross and tile launches
+# which the inverse runs as separate cross and tile launches; (40, 20, 20, 2):
+# 7623 DOFs, near the 8192-DOF limit of the dense coarsest inverse
 @pytest.mark.parametrize("nx,ny,nz,lev", [(8, 4, 4, 3), (24, 12, 12, 3), (16, 8, 8, 4), (48, 24, 24, 3),
-                                          (32, 16, 16, 2)])
+                                          (32, 16, 16, 2), (40, 20, 20, 2)])
 def test_coarse_operators_and_vcycle(nx, ny, nz, lev):
     log(f"coarse ops / vcycle {nx}x{ny}x{nz} levels={lev}")
     prob = synth.cantilever(nx, ny, nz)
