@@ -32,20 +32,21 @@ namespace {
 inline unsigned nblk(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
 // Lane i of a wavefront takes the value of lane i+1 (wave_shl:1) or lane
-// i-1 (wave_shr:1) through DPP; the end lanes keep their own value.  Across
-// the boundary of two 16-lane x-rows this moves a value between the last
-// lane of a row (which only supplies node values) and the first lane of
-// the next (a halo lane that owns nothing), so both results are unused.
+// i-1 (wave_shr:1) through DPP; the end lanes read 0 (bound_ctrl), so the
+// destination needs no copy of the source first.  Across the boundary of
+// two 16-lane x-rows this moves a value between the last lane of a row
+// (which only supplies node values) and the first lane of the next (a halo
+// lane that owns nothing); lanes 0 and 63 are such lanes too, so none of
+// these results is used.
 template <int CTRL>
 __device__ inline double dpp(double x) {
-  const int lo = __builtin_amdgcn_update_dpp(__double2loint(x), __double2loint(x), CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(__double2hiint(x), __double2hiint(x), CTRL, 0xF, 0xF, false);
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), CTRL, 0xF, 0xF, true);
   return __hiloint2double(hi, lo);
 }
 template <int CTRL>
 __device__ inline float dpp(float x) {
-  const int v = __float_as_int(x);
-  return __int_as_float(__builtin_amdgcn_update_dpp(v, v, CTRL, 0xF, 0xF, false));
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), CTRL, 0xF, 0xF, true));
 }
 constexpr int kWaveShl1 = 0x130;  // lane i <- lane i+1 across the wavefront
 constexpr int kWaveShr1 = 0x138;  // lane i <- lane i-1
@@ -184,16 +185,19 @@ __global__ void __launch_bounds__(kThreads, AARMR_EBE_MINB) k_ebe_z(int nx, int 
     load_node(kin && xi_ok && yj1_ok, base + nxp, R.q2, R.m2, MASK_IN);
   };
   auto masked = [](T x, uint32_t m, int c) { return (MASK_IN && ((m >> c) & 1u)) ? (T)0 : x; };
+  // x-y Walsh transform of the element's four plane corners: the y
+  // butterfly of the lane's own two nodes first, then the x butterfly with
+  // the next lane's (6 additions and 2 lane moves per component)
   auto transform = [&](const PlaneRaw<T>& R, T (&P)[4][3]) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      T a0 = masked(R.q0[c], R.m0, c), a2 = masked(R.q2[c], R.m2, c);
-      T a1 = from_next_lane(a0), a3 = from_next_lane(a2);
-      walsh4(a0, a1, a2, a3);
-      P[0][c] = a0;
-      P[1][c] = a1;
-      P[2][c] = a2;
-      P[3][c] = a3;
+      const T a0 = masked(R.q0[c], R.m0, c), a2 = masked(R.q2[c], R.m2, c);
+      const T ye = a0 + a2, yo = a0 - a2;
+      const T ye1 = from_next_lane(ye), yo1 = from_next_lane(yo);
+      P[0][c] = ye + ye1;
+      P[1][c] = ye - ye1;
+      P[2][c] = yo + yo1;
+      P[3][c] = yo - yo1;
     }
   };
   auto load_w = [&](int k) -> T {
@@ -258,30 +262,28 @@ __global__ void __launch_bounds__(kThreads, AARMR_EBE_MINB) k_ebe_z(int nx, int 
         h[q + 4][c] = Pb[q][c] - Pt[q][c];
       }
     walsh_blocks<T>(K, w, h, z);
-    // plane k: carry (dz=1 of layer k-1) + dz=0 of layer k, back to corners;
-    // the carry is then replaced by the dz=1 part of layer k
-    T cor[4][3];
+    // plane k: carry (dz=1 of layer k-1) + dz=0 of layer k, then back to
+    // corners and summed with the previous lane's element.  With the x
+    // butterfly s = a0 + a1, d = a0 - a1 (y index 0) and t = a2 + a3,
+    // e = a2 - a3 (y index 1), node (i, j) of row j is s + t + prev(d + e)
+    // and node (i, j+1) is s - t + prev(d - e), so u = s + prev(d) and
+    // w = t + prev(e) give both as u + w and u - w.  The carry is then
+    // replaced by the dz=1 part of layer k.
+    T X0[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      T a0 = carry[0][c] + (z[0][c] + z[4][c]);
-      T a1 = carry[1][c] + (z[1][c] + z[5][c]);
-      T a2 = carry[2][c] + (z[2][c] + z[6][c]);
-      T a3 = carry[3][c] + (z[3][c] + z[7][c]);
+      const T a0 = carry[0][c] + (z[0][c] + z[4][c]);
+      const T a1 = carry[1][c] + (z[1][c] + z[5][c]);
+      const T a2 = carry[2][c] + (z[2][c] + z[6][c]);
+      const T a3 = carry[3][c] + (z[3][c] + z[7][c]);
       carry[0][c] = z[0][c] - z[4][c];
       carry[1][c] = z[1][c] - z[5][c];
       carry[2][c] = z[2][c] - z[6][c];
       carry[3][c] = z[3][c] - z[7][c];
-      walsh4(a0, a1, a2, a3);
-      cor[0][c] = a0;
-      cor[1][c] = a1;
-      cor[2][c] = a2;
-      cor[3][c] = a3;
-    }
-    T X0[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      X0[c] = cor[0][c] + from_prev_lane(cor[1][c]);                 // node (i, j), row j
-      xs[buf][c][ty][tx] = cor[2][c] + from_prev_lane(cor[3][c]);  // node (i, j+1), row j
+      const T u = (a0 + a1) + from_prev_lane(a0 - a1);
+      const T w = (a2 + a3) + from_prev_lane(a2 - a3);
+      X0[c] = u + w;                 // node (i, j), row j
+      xs[buf][c][ty][tx] = u - w;    // node (i, j+1), row j
     }
     __syncthreads();
     const bool wr = own && k >= kz0;
