@@ -963,6 +963,9 @@ int pcg32(aarmr_mesh* m, double rtol, int maxit, int* iters, double* relres, boo
 // progress (a non-positive p^T A p or r^T z in the inner CG, or an outer step
 // that reduces the FP64 residual less than 5x) *fallback is set and x holds the latest
 // iterate: the caller continues from it with FP64 CG and the FP64 V-cycle.
+#ifndef AARMR_INNER_FLOOR
+#define AARMR_INNER_FLOOR 5e-6
+#endif
 int refine(aarmr_mesh* m, double* x, int* iters, double* relres, bool* fallback,
            hipStream_t s) {
   const Grid& g = m->lg[0];
@@ -970,7 +973,7 @@ int refine(aarmr_mesh* m, double* x, int* iters, double* relres, bool* fallback,
   double* misc = m->scal + SC_MISC;
   const double rtol = m->p.cg_rtol;
   const int budget = std::min(m->p.cg_maxit, kMaxIt);
-  constexpr double kInnerFloor = 2e-5;  // attainable FP32 reduction per step
+  constexpr double kInnerFloor = AARMR_INNER_FLOOR;  // attainable FP32 reduction per step
   *iters = 0;
   *fallback = false;
   double ff = -1.0, prev_rel = 0.0;
