@@ -212,6 +212,135 @@ __global__ void __launch_bounds__(256) k_galerkin_lds(int cnx, int cny, int cnz,
   }
 }
 
+// Row and column of packed entry s (upper triangle, row-major, 24 x 24).
+__device__ inline void sym_unpack(int s, int& r, int& q) {
+  int a = (int)((49.0f - sqrtf((float)(2401 - 8 * s))) * 0.5f);
+  if (a < 23 && sidx(a + 1, a + 1) <= s) ++a;
+  if (sidx(a, a) > s) --a;
+  r = a;
+  q = a + (s - sidx(a, a));
+}
+
+// Levels >= 2: Kc = sum_c P_c^T Kf_c P_c from the stored matrices of the
+// level below, for 8 parents along x per workgroup.  The children of 8
+// consecutive parents at one child position lie at every other element of a
+// 16-element x-run of the level below, so one load instruction takes 8 whole
+// entries from 8 cache lines (a parent alone used 16 bytes of each of its
+// 1200 lines).  Per child position: the 8 children are unpacked into LDS,
+// then column passes T = K_c P_c for 4 parents at a time and row passes
+// add P_c^T T to the packed entries each thread owns (as k_galerkin_lds);
+// 5 barriers per child position and 8 parents.
+__global__ void __launch_bounds__(256) k_galerkin_row8(int cnx, int cny, int cnz,
+                                                       const double* __restrict__ Kf,
+                                                       double* __restrict__ Kc) {
+  __shared__ double sK[8][24][25];
+  __shared__ double sT[4][24][25];
+  const int64_t cne = (int64_t)cnx * cny * cnz;
+  const int fnx = 2 * cnx, fny = 2 * cny;
+  const int64_t fne = cne * 8;
+  const int gxr = (cnx + 7) / 8;
+  const int64_t nwork = (int64_t)gxr * cny * cnz;
+  const int tid = threadIdx.x;
+  // XCD-aware order, as in k_galerkin_lds: each XCD walks a contiguous range
+  // of groups, so y/z-neighbouring groups are close in time on one L2
+  int64_t w0 = blockIdx.x, w1 = nwork, ws = gridDim.x;
+  if (gridDim.x >= 8) {
+    const int x = blockIdx.x & 7, nbx = (int)(gridDim.x >> 3) + (x < (int)(gridDim.x & 7) ? 1 : 0);
+    w0 = nwork * x / 8 + (blockIdx.x >> 3);
+    w1 = nwork * (x + 1) / 8;
+    ws = nbx;
+  }
+  int Iown[2], Jown[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int sx = tid + 256 * h;
+    int I = 0;
+    if (sx < kSym)
+      while (sidx(I, 23) < sx) ++I;
+    Iown[h] = I;
+    Jown[h] = sx < kSym ? I + (sx - sidx(I, I)) : 0;
+  }
+  for (int64_t w = w0; w < w1; w += ws) {
+    const int gx = (int)(w % gxr);
+    const int64_t rest = w / gxr;
+    const int cy = (int)(rest % cny), cz = (int)(rest / cny);
+    const int cx0 = 8 * gx;
+    const int np = min(8, cnx - cx0);
+    double racc[8][2];
+#pragma unroll
+    for (int p = 0; p < 8; ++p) racc[p][0] = racc[p][1] = 0.0;
+    for (int c = 0; c < 8; ++c) {
+      const int dx = c & 1, dy = (c >> 1) & 1, dz = c >> 2;
+      const int64_t fe0 = (int64_t)(2 * cx0 + dx) + (int64_t)fnx * ((2 * cy + dy) + (int64_t)fny * (2 * cz + dz));
+      // lane t: entry t / 8 of parent t % 8; all loads in flight first
+      double lv[10];
+#pragma unroll
+      for (int u = 0; u < 10; ++u) {
+        const int t = tid + 256 * u;
+        const int p = t & 7;
+        lv[u] = (t < 8 * kSym && p < np) ? Kf[(int64_t)(t >> 3) * fne + fe0 + 2 * p] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 10; ++u) {
+        const int t = tid + 256 * u;
+        if (t < 8 * kSym) {
+          int r, q;
+          sym_unpack(t >> 3, r, q);
+          sK[t & 7][r][q] = lv[u];
+          sK[t & 7][q][r] = lv[u];
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int pg = 0; pg < 8; pg += 4) {
+        for (int t = tid; t < 4 * 576; t += 256) {
+          const int pp = t / 576, r = (t % 576) / 24, J = t % 24, B = J / 3, j = J % 3;
+          double acc = 0.0;
+#pragma unroll
+          for (int b = 0; b < 8; ++b) {
+            const double pb = phi1(dx + (b & 1), B & 1) * phi1(dy + ((b >> 1) & 1), (B >> 1) & 1) *
+                              phi1(dz + (b >> 2), B >> 2);
+            acc = fma(pb, sK[pg + pp][r][3 * b + j], acc);
+          }
+          sT[pp][r][J] = acc;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int pp = 0; pp < 4; ++pp)
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const int A = Iown[h] / 3, i = Iown[h] % 3, J = Jown[h];
+            double acc = racc[pg + pp][h];
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+              const double pa = phi1(dx + (b & 1), A & 1) * phi1(dy + ((b >> 1) & 1), (A >> 1) & 1) *
+                                phi1(dz + (b >> 2), A >> 2);
+              acc = fma(pa, sT[pp][3 * b + i][J], acc);
+            }
+            racc[pg + pp][h] = acc;
+          }
+        __syncthreads();  // sT (next round) and sK (next child) are rewritten
+      }
+    }
+    // outputs through LDS, then 8 consecutive parents per entry in one run
+    double* sO = &sK[0][0][0];  // [entry][parent], 2400 doubles
+#pragma unroll
+    for (int p = 0; p < 8; ++p)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int sx = tid + 256 * h;
+        if (sx < kSym) sO[sx * 8 + p] = racc[p][h];
+      }
+    __syncthreads();
+    const int64_t e0 = (int64_t)cx0 + (int64_t)cnx * (cy + (int64_t)cny * cz);
+    for (int t = tid; t < 8 * kSym; t += 256) {
+      const int p = t & 7;
+      if (p < np) Kc[(int64_t)(t >> 3) * cne + e0 + p] = sO[t];
+    }
+    __syncthreads();  // sK is reused by the next group
+  }
+}
+
 // y = sum_e L_e^T Ke_e L_e v on a coarse level (levels >= 2) from the stored
 // packed element matrices.  Block: 64 consecutive nodes x 8 waves; wave a
 // takes each node as local corner a of the element e = node - offset(a) and
@@ -1148,6 +1277,14 @@ void launch_galerkin_from_fine(const Grid& coarse, const double* KE, const doubl
 }
 
 void launch_galerkin_from_coarse(const Grid& coarse, const double* Kf, double* Kc, hipStream_t s) {
+  const int64_t groups = (int64_t)((coarse.nx + 7) / 8) * coarse.ny * coarse.nz;
+  if (groups >= 256) {
+    // 57.6 KB of LDS per workgroup: two per CU, 512 resident
+    const unsigned grid = (unsigned)std::min<int64_t>(groups, 512);
+    k_galerkin_row8<<<grid, 256, 0, s>>>(coarse.nx, coarse.ny, coarse.nz, Kf, Kc);
+    return;
+  }
+  // fewer groups than CUs: one parent per workgroup keeps more of the chip busy
   const unsigned grid = (unsigned)std::min<int64_t>(coarse.ne, 4096);
   k_galerkin_lds<false><<<grid, 256, 0, s>>>(coarse.nx, coarse.ny, coarse.nz, nullptr, nullptr,
                                              nullptr, nullptr, nullptr, Kf, Kc, nullptr, 0);

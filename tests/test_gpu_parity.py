@@ -87,6 +87,33 @@ def test_coarse_operators_and_vcycle(nx, ny, nz, lev):
     assert rel(z.cpu().numpy(), want) < 1e-9
 
 
+def test_coarse_galerkin_eight_parent_groups():
+    """Levels >= 2 with at least 256 groups of 8 parents along x are built 8
+    parents per workgroup.  At 48x64x64 with 4 levels, level 2 (12x16x16) has
+    512 such groups, half of them partial (12 = 8 + 4 parents per row), while
+    level 3 (6x8x8) is built one parent per workgroup.  Each is checked against
+    the Galerkin identity A_l v = P^T A_{l-1} P v of Algorithm 2's coarse
+    operators, with P the oracle's trilinear prolongation and A_{l-1} the
+    library's operator one level down (itself checked against the oracle at
+    small sizes above)."""
+    nx, ny, nz = 48, 64, 64
+    log(f"coarse galerkin groups {nx}x{ny}x{nz} levels=4")
+    prob = synth.cantilever(nx, ny, nz)
+    m = mesh_for(prob, mg_levels=4)
+    m.setup(t64(_density(prob, 23)), fixed_tensor(prob, m))
+    rng = np.random.default_rng(24)
+    for l in (2, 3):
+        cx, cy, cz = nx >> l, ny >> l, nz >> l
+        P = mg.prolongation(cx, cy, cz)
+        v = rng.standard_normal(P.shape[1])
+        y = torch.zeros(P.shape[1], dtype=torch.float64, device="cuda")
+        m.apply(t64(soa(v)), y, level=l)
+        yf = torch.zeros(P.shape[0], dtype=torch.float64, device="cuda")
+        m.apply(t64(soa(P @ v)), yf, level=l - 1)
+        want = P.T @ aos(yf.cpu().numpy())
+        assert rel(aos(y.cpu().numpy()), want) < 1e-12, f"level {l}"
+
+
 def test_energy_matches_oracle():
     prob = synth.cantilever(18, 10, 6)
     m = mesh_for(prob, mg_levels=2)
