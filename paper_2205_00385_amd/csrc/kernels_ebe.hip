@@ -10,9 +10,9 @@
 // mesh is created).  So KE v = W^T B (W v) / 8 costs two 8-point Walsh
 // transforms per component plus ~40 multiply-adds instead of 576.
 //
-// Data flow.  A workgroup of 16 x 16 threads (four 16-lane x-rows per
-// wavefront) owns 14 x 15 node columns; thread (tx, ty) handles the element
-// column (i, j) = (14 bx - 1 + tx, 15 by - 1 + ty) (the last lane of a row
+// Data flow.  A workgroup of 32 x 8 threads (two 32-lane x-rows per
+// wavefront) owns 30 x 7 node columns; thread (tx, ty) handles the element
+// column (i, j) = (30 bx - 1 + tx, 7 by - 1 + ty) (the last lane of a row
 // only supplies node values) and marches along z over a chunk of node planes.  The x-y
 // Walsh transform of a node plane is computed once and reused by the two
 // element layers that share the plane; the dz = 1 outputs of layer k-1 stay
@@ -34,7 +34,7 @@ inline unsigned nblk(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); 
 // Lane i of a wavefront takes the value of lane i+1 (wave_shl:1) or lane
 // i-1 (wave_shr:1) through DPP; the end lanes read 0 (bound_ctrl), so the
 // destination needs no copy of the source first.  Across the boundary of
-// two 16-lane x-rows this moves a value between the last lane of a row
+// two 32-lane x-rows this moves a value between the last lane of a row
 // (which only supplies node values) and the first lane of the next (a halo
 // lane that owns nothing); lanes 0 and 63 are such lanes too, so none of
 // these results is used.
@@ -73,8 +73,10 @@ __device__ inline void walsh4(T& q0, T& q1, T& q2, T& q3) {
 // compiler can count outstanding memory operations statically and never has
 // to drain the prefetched plane.
 constexpr uint32_t kOutside = 0x80000000u;
-constexpr int kLanes = 16;           // element columns per x-row
-constexpr int kRows = 16;            // x-rows per workgroup (4 per wavefront)
+// 32-lane rows: a row segment of y is 30 nodes, so per owned node half as
+// many cache lines are shared with the neighbouring tile as with 16 lanes
+constexpr int kLanes = 32;           // element columns per x-row
+constexpr int kRows = 8;             // x-rows per workgroup (2 per wavefront)
 constexpr int kTileX = kLanes - 2;   // node columns owned per row
 constexpr int kTileY = kRows - 1;    // node rows owned per workgroup
 constexpr int kThreads = kLanes * kRows;
