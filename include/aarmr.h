@@ -173,7 +173,10 @@ void aarmr_default_params(aarmr_params* p);
  * Errors: AARMR_E_INVALID for non-positive sizes, sizes not divisible by
  * 2^(mg_levels-1), mg_levels outside [2, AARMR_MAX_LEVELS], Ns or Nm outside
  * [1, AARMR_MAX_BASIS], n_rhs_max outside [1, AARMR_MAX_RHS], nu outside
- * (-1, 0.5), a coarsest grid above 8192 DOFs, the DOF count >= 2^31, or
+ * (-1, 0.5), a coarsest grid above 8192 DOFs, the DOF count >= 2^31, a
+ * 3D grid whose FP64 DOF vector (3 * n_node * 8 bytes) or modulus array
+ * (n_elem * 8 bytes) reaches 2^31 bytes (the fine-grid product addresses
+ * them with 32-bit offsets; 446^3 elements is the largest cube), or
  * AARMR_FP32_REFINE with nz = 0. */
 int aarmr_mesh_create(const aarmr_params* p, aarmr_mesh** out);
 

@@ -1307,6 +1307,16 @@ int aarmr_mesh_create(const aarmr_params* p, aarmr_mesh** out) {
     return fail(AARMR_E_INVALID, "bad smoother parameters");
   if (dim * (int64_t)(p->nx + 1) * (p->ny + 1) * (p->nz + 1) >= (int64_t(1) << 31))
     return fail(AARMR_E_INVALID, "grid too large: DOF count must stay below 2^31");
+  // The fine-grid hex8 product addresses its vectors and moduli with 32-bit
+  // byte offsets and parks idle lanes at offset 2^31, so every FP64 array it
+  // reads or writes must stay below 2^31 bytes.
+  if (dim == 3) {
+    const int64_t nn3 = (int64_t)(p->nx + 1) * (p->ny + 1) * (p->nz + 1);
+    const int64_t ne3 = (int64_t)p->nx * p->ny * p->nz;
+    if (3 * nn3 * 8 >= (int64_t(1) << 31) || ne3 * 8 >= (int64_t(1) << 31))
+      return fail(AARMR_E_INVALID,
+                  "grid too large: 3 * n_node * 8 and n_elem * 8 bytes must stay below 2^31");
+  }
   aarmr_mesh* m = new aarmr_mesh();
   m->p = *p;
   m->dim = dim;

@@ -63,6 +63,8 @@ def _create(lib, **kw):
     dict(Ns=0), dict(Nm=11), dict(n_rhs_max=9), dict(nu=0.5), dict(Emin=0.0),
     dict(cg_maxit=0), dict(precision=7), dict(omega=0.0),
     dict(nx=256, ny=256, nz=256, mg_levels=2),  # coarsest dense too large
+    # 449^3 nodes: 3 * n_node * 8 bytes exceed the fine product's 2^31 offsets
+    dict(nx=448, ny=448, nz=448, mg_levels=7),
 ])
 def test_mesh_create_rejects(lib, kw):
     from paper_2205_00385_amd import aarmr
