@@ -301,6 +301,26 @@ int aarmr_oc_update(aarmr_mesh* m, const double* x, const double* dc, const doub
                     double volfrac, double move, double* x_new, double* rho_phys_new,
                     void* stream);
 
+/* The same OC update for callers that cannot allocate device memory or
+ * synchronise (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): it calls no hipMalloc, hipFree or allocating
+ * library routine and reads nothing back, so the whole update is
+ * stream-ordered.  Its scratch (bisection state and the volume partials of
+ * the trial multipliers, 28,736 bytes) lives in a static device array that
+ * each GPU holds until the process ends; the call clears what must start at
+ * zero.  Every call on one GPU shares that array, so calls that overlap on
+ * one GPU (other streams, other threads) race: serialise them.  The
+ * partials are per reduction block, not per element, so every grid fits.
+ * It issues all 67 launch pairs of the at most 200 bisection steps (pairs
+ * after convergence return at once) instead of stopping at the first one
+ * after convergence.  Needs the mesh's bound workspace for the filter
+ * tables, as aarmr_oc_update does.  Outputs are bitwise those of
+ * aarmr_oc_update.  Errors: AARMR_E_NO_WORKSPACE, AARMR_E_INVALID (null
+ * argument, rmin <= 0), AARMR_E_HIP (symbol lookup or launch). */
+int aarmr_oc_update_noalloc(aarmr_mesh* m, const double* x, const double* dc, const double* dv,
+                            double volfrac, double move, double* x_new, double* rho_phys_new,
+                            void* stream);
+
 /* Autotuner of the fine-grid operator's launch shape: the z-marching kernel
  * runs 14 x 15-node tiles of the x-y plane, each marching over a chunk of
  * node planes; times the residency-sized default chunk length and candidate

@@ -78,6 +78,7 @@ EXPORTS = [
     "aarmr_default_params", "aarmr_mesh_create", "aarmr_mesh_destroy", "aarmr_workspace_bytes",
     "aarmr_bind_workspace", "aarmr_solve", "aarmr_ca_update", "aarmr_filter", "aarmr_setup",
     "aarmr_apply_operator", "aarmr_vcycle", "aarmr_element_energy", "aarmr_oc_update",
+    "aarmr_oc_update_noalloc",
     "aarmr_autotune", "aarmr_set_chunk", "aarmr_batch_solve", "aarmr_batch_submit", "aarmr_batch_poll",
     "aarmr_batch_wait", "aarmr_set_springs", "aarmr_last_error",
 ]
@@ -107,6 +108,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.aarmr_vcycle.argtypes = [P, vp, vp, vp]
     lib.aarmr_element_energy.argtypes = [P, vp, vp, vp]
     lib.aarmr_oc_update.argtypes = [P, vp, vp, vp, dbl, dbl, vp, vp, vp]
+    lib.aarmr_oc_update_noalloc.argtypes = [P, vp, vp, vp, dbl, dbl, vp, vp, vp]
     lib.aarmr_batch_solve.argtypes = [ctypes.POINTER(BatchItem), i32, ctypes.POINTER(P), i32]
     lib.aarmr_batch_submit.argtypes = [ctypes.POINTER(BatchItem), i32, ctypes.POINTER(P), i32,
                                        ctypes.POINTER(P)]
@@ -276,6 +278,11 @@ class Mesh:
     def oc_update(self, x, dc, dv, volfrac, move, x_new, rho_new):
         _check(lib().aarmr_oc_update(self._h, _ptr(x), _ptr(dc), _ptr(dv), float(volfrac),
                                      float(move), _ptr(x_new), _ptr(rho_new), _stream()))
+
+    def oc_update_noalloc(self, x, dc, dv, volfrac, move, x_new, rho_new):
+        _check(lib().aarmr_oc_update_noalloc(self._h, _ptr(x), _ptr(dc), _ptr(dv),
+                                             float(volfrac), float(move), _ptr(x_new),
+                                             _ptr(rho_new), _stream()))
 
 
 def _batch_items(jobs):

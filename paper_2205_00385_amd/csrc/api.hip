@@ -9,6 +9,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <vector>
@@ -24,6 +25,37 @@ thread_local std::string g_err;
 int fail(int code, const std::string& msg) {
   g_err = msg;
   return code;
+}
+
+// Static scratch of the allocation-free OC update: the bisection state
+// (5 doubles, padded to 8) and the volume partials of the seven trial
+// multipliers, [7][kRedBlocks].  Each GPU holds its own copy until the
+// process ends; host code must use the address hipGetSymbolAddress returns
+// for the current device, never the array's name.
+constexpr int kOcScratchLam = 8;
+constexpr int kOcScratchDoubles = kOcScratchLam + 7 * kRedBlocks;
+static __device__ __align__(256) double oc_scratch[kOcScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_dev[kMaxDevices] = {};
+
+int oc_scratch_ptr(double** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(AARMR_E_HIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+  if (dev < 0 || dev >= kMaxDevices) return fail(AARMR_E_INVALID, "device index above 63");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(oc_scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(AARMR_E_HIP, std::string("hipGetSymbolAddress(oc_scratch): ") +
+                                   hipGetErrorString(e));
+    g_scratch_dev[dev] = static_cast<double*>(ptr);
+  }
+  *out = g_scratch_dev[dev];
+  return AARMR_OK;
 }
 
 #define HIP_TRY(x)                                                               \
@@ -1800,6 +1832,41 @@ int aarmr_oc_update(aarmr_mesh* m, const double* x, const double* dc, const doub
         break;
       }
     }
+  }
+  launch_oc_final(g.ne, x, dc, dv, move, m->p.oc_eta, lam, x_new, s);
+  KCHECK();
+  launch_filter(m->fg, m->p.rmin, m->Wf, 0, m->Hs, x_new, rho_phys_new, s);
+  KCHECK();
+  return AARMR_OK;
+}
+
+int aarmr_oc_update_noalloc(aarmr_mesh* m, const double* x, const double* dc, const double* dv,
+                            double volfrac, double move, double* x_new, double* rho_phys_new,
+                            void* stream) {
+  TRY(need_ws(m));
+  if (!x || !dc || !dv || !x_new || !rho_phys_new) return fail(AARMR_E_INVALID, "null argument");
+  if (!(m->p.rmin > 0.0)) return fail(AARMR_E_INVALID, "OC needs the filter (rmin > 0)");
+  const Grid& g = m->lg[0];
+  // the partials are per reduction block, not per element: any grid fits
+  const int nparts = kRedBlocks;
+  if (kOcScratchLam + 7 * nparts > kOcScratchDoubles)
+    return fail(AARMR_E_INVALID, "OC scratch above its static maximum");
+  double* base = nullptr;
+  TRY(oc_scratch_ptr(&base));
+  hipStream_t s = S(stream);
+  double* lam = base;
+  double* partial = base + kOcScratchLam;
+  const double target = volfrac * (double)g.ne;
+  // the bisection state starts from the kernel's fill, never from what the
+  // array held after an earlier call
+  launch_oc_init(lam, s);
+  KCHECK();
+  // no read-back: every pair is issued (at most 200 bisection steps in 67
+  // pairs; pairs after convergence return at once)
+  for (int it = 0; it < 67; ++it) {
+    launch_oc_step3(g.ne, x, dc, dv, m->cw, move, m->p.oc_eta, lam, partial, nparts, s);
+    launch_oc_bisect3(lam, partial, nparts, target, s);
+    KCHECK();
   }
   launch_oc_final(g.ne, x, dc, dv, move, m->p.oc_eta, lam, x_new, s);
   KCHECK();
