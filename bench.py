@@ -1,21 +1,22 @@
 #!/usr/bin/env python3
 """Benchmark of the AARMR analysis step on one MI355X.
 
-Workload (one "step"): the complete 50-cycle topology-optimisation run of the
-96x48x48 hex8 cantilever (clamped x=0 face, unit load spread over the bottom
-edge of the x=96 face), volume fraction 0.3, SIMP p=3, density filter r=2,
-OC update, starting from a uniform design of 0.3.  Analyses follow
-Algorithm 1: MGCG (4 grid levels, damped Jacobi, rel. residual 1e-8) for
-cycles 1..20 while the last Ns=2 solutions build the PARM, then the
-combined-approximation reduced model (Nm=6) with the eq. (29) criterion
-eps < 1e-3 and the MGCG fallback.  Every step starts from the same state, so
-steps are identical work.
+Headline workload (one "step"): 50 applications of the fine-grid FP64
+element-by-element stiffness product y = K(rho~) v (eq. 7's operator with
+the Dirichlet identity rows) on the 256x128x128 hex8 cantilever
+(4,194,304 elements, 12,830,211 DOFs), whose density is a Gaussian-smoothed
+random field (correlation length 8 voxels) mapped to [1e-3, 1].  Two
+independent meshes (seeds 3 and 4: moduli, mask, v and y each) alternate,
+so the ~490 MB working set exceeds the 256 MB Infinity Cache and the
+traffic is HBM traffic.  ``value`` is GDOF/s: 3 n_node x products / s.
 
-Printed: one JSON line.  ``value`` is analyses (design-cycle equilibrium
-solves with compliance and sensitivities) per second over the timed steps.
-``roofline`` is the fine-grid element-by-element K.v kernel, timed with HIP
-events on the library's stream; ``cpu_baseline`` is the CPU FP64 oracle on a
-bounded sample of the workload.
+``roofline`` is that kernel (HIP events on the library's stream over the
+timed region); ``cpu_baseline`` is the CPU FP64 oracle's element-by-element
+product on the same grid in the same unit.  Further keys: whole analyses of
+the same grid in FP64 and in the FP32-refinement form (solves/s at rel.
+residual 1e-8, compliance error against FP64), the 50-cycle AARMR
+optimisation loop of the 96x48x48 cantilever, the 64-instance batch and
+the served request stream.
 """
 
 from __future__ import annotations
@@ -32,6 +33,8 @@ sys.path.insert(0, ROOT)
 METRIC = "EbE K·v GDOF/s; solves/s at 1e-6 rel. compliance; p50/p99 latency vs plain"
 HBM_PEAK_GBS = 8000.0
 
+KV_GRID = (256, 128, 128)
+KV_PER_STEP = 50  # products per timed step (25 per mesh)
 NX, NY, NZ = 96, 48, 48
 CYCLES, N_ON, NS, NM = 50, 20, 2, 6
 VOLFRAC, RMIN, MOVE, CA_TOL = 0.3, 2.0, 0.2, 1e-3
@@ -40,10 +43,11 @@ VOLFRAC, RMIN, MOVE, CA_TOL = 0.3, 2.0, 0.2, 1e-3
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--loop-steps", type=int, default=3,
+                    help="timed runs of the 96x48x48 optimisation loop (extra key)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-large", action="store_true", help="skip the 256x128x128 K.v roofline")
     ap.add_argument("--no-plain", action="store_true",
                     help="skip the comparison run with plain MGCG every cycle")
     ap.add_argument("--kv-launches", type=int, default=200)
@@ -55,7 +59,7 @@ def parse():
     ap.add_argument("--batch-only", action="store_true", help="only the 64-instance batch")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving workload")
     ap.add_argument("--serve-only", action="store_true", help="only the serving workload")
-    ap.add_argument("--study", choices=["nsnm", "bridge", "nsnm2d", "halfwheel", "inverter"],
+    ap.add_argument("--study", choices=["nsnm", "bridge", "inverter"],
                     help="run a parameter study instead of the benchmark")
     ap.add_argument("--kv-only", action="store_true",
                     help="only the 256x128x128 K.v timing (for hardware-counter runs)")
@@ -208,66 +212,6 @@ def study_bridge(torch, aarmr, synth):
     return {"cycles": 80, "Ns": 2, "Nm": 2, "N_on": 20, "rows": out}
 
 
-def study_ns_nm_2d(torch, aarmr, synth, values=(1, 2, 3, 4, 6, 8, 10), cycles=100):
-    """Section 4.1.1: the plane-stress cantilever (left side clamped, unit
-    load at the middle of the right end), volfrac 0.5, r = 2.5, MGCG to rel.
-    residual 1e-6 with at most 200 iterations, eps_tol = 0.1, N_on = 20, Ns
-    and Nm over the paper's 49 combinations (SVD basis, eq. 21), against
-    MGCG every cycle.  The paper's 300x180 grid with 3 levels would leave a
-    6992-DOF dense coarsest inverse in every MG setup; the grid here is
-    320x192 (the same 5:3 aspect) with 5 levels (546 coarsest DOFs)."""
-    prob = synth.cantilever2d(320, 192)
-    kw = dict(cycles=cycles, volfrac=0.5, rmin=2.5, levels=5, cg_rtol=1e-6, cg_maxit=200)
-    ref = run_opt(torch, aarmr, synth, prob, plain=True, **kw)
-    c_ref = ref["compliance"][-1]
-    rows = []
-    for ns in values:
-        for nm in values:
-            r = run_opt(torch, aarmr, synth, prob, ns=ns, nm=nm, ca_tol=0.1, orth=1, **kw)
-            rows.append({"Ns": ns, "Nm": nm, "analysis_ms": round(r["analysis_ms"], 1),
-                         "speedup": round(ref["analysis_ms"] / r["analysis_ms"], 3),
-                         "mgcg_calls": sum(p != "ca" for p in r["paths"]),
-                         "ca_accepted": r["paths"].count("ca"),
-                         "end_compliance": r["compliance"][-1],
-                         "end_rel_diff": (r["compliance"][-1] - c_ref) / c_ref})
-            print(f"[study] Ns={ns} Nm={nm}: {rows[-1]}", file=sys.stderr, flush=True)
-    return {"grid": "320x192 plane-stress cantilever", "cycles": cycles, "eps_tol": 0.1,
-            "mgcg_every_cycle": {"analysis_ms": round(ref["analysis_ms"], 1),
-                                 "cg_iterations": ref["cg_iterations"], "end_compliance": c_ref},
-            "cases": rows}
-
-
-def study_half_wheel(torch, aarmr, synth, cycles=100):
-    """Section 4.2.1: the plane-stress half-wheel (lower-left corner clamped,
-    vertical DOF of the lower-right corner fixed, unit load at the bottom
-    centre) on the paper's grids, volfrac 0.5, r = 2.5, N_on = 20,
-    Ns = Nm = 2, MGCG to rel. residual 1e-6 with at most 200 iterations;
-    AARMR with eps_tol 0.5%, 1% and 5% against MGCG every cycle.  Grid
-    levels: the fewest that bring the dense coarsest operator to 2500 DOFs
-    or less (the paper's 3 would leave 6642 to 58322, whose dense inverse
-    would dominate every MG setup); 840x420 is run as 832x416, the nearest
-    grid that coarsens that far."""
-    out = []
-    for dims, lev in (((320, 160), 4), ((640, 320), 5), ((832, 416), 6), ((960, 480), 6)):
-        prob = synth.half_wheel(*dims)
-        kw = dict(cycles=cycles, volfrac=0.5, rmin=2.5, levels=lev, cg_rtol=1e-6, cg_maxit=200)
-        ref = run_opt(torch, aarmr, synth, prob, plain=True, **kw)
-        row = {"grid": "x".join(map(str, dims)), "levels": lev,
-               "mgcg_ms": round(ref["analysis_ms"], 1), "mgcg_cg_iterations": ref["cg_iterations"],
-               "mgcg_end_compliance": ref["compliance"][-1]}
-        for tol in (0.005, 0.01, 0.05):
-            r = run_opt(torch, aarmr, synth, prob, ns=2, nm=2, ca_tol=tol, **kw)
-            row[f"eps_{tol}"] = {"analysis_ms": round(r["analysis_ms"], 1),
-                                 "speedup": round(ref["analysis_ms"] / r["analysis_ms"], 3),
-                                 "mgcg_calls": sum(p != "ca" for p in r["paths"]),
-                                 "cg_iterations": r["cg_iterations"],
-                                 "end_rel_diff": (r["compliance"][-1] - ref["compliance"][-1])
-                                 / ref["compliance"][-1]}
-        print(f"[study] half-wheel {row}", file=sys.stderr, flush=True)
-        out.append(row)
-    return {"cycles": cycles, "Ns": 2, "Nm": 2, "N_on": 20, "rows": out}
-
-
 def run_mechanism(torch, aarmr, synth, prob, cycles, levels, plain, ca_tol=1e-3, volfrac=0.3,
                   rmin=2.5, move=0.05, n_on=20, ns=2, nm=2):
     """A full displacement-inverter optimisation (Section 4.3): load cases
@@ -402,14 +346,15 @@ def ebe_bytes(nx, ny, nz):
     return 49 * nn + 8 * ne, nn
 
 
-def large_kv(torch, aarmr, synth, n_launch):
-    """FP64 K.v on the 256x128x128 cantilever grid (smoothed random field in
-    [1e-3, 1]), two independent meshes alternating so that the working set
-    (~490 MB) exceeds the 256 MB Infinity Cache."""
+def kv_sets(torch, aarmr, synth):
+    """Two independent 256x128x128 cantilever meshes (smoothed random fields,
+    seeds 3 and 4, in [1e-3, 1]) with their moduli and masks set up and a
+    random v (zero on fixed DOFs) and an output y each: ~490 MB together,
+    more than the 256 MB Infinity Cache."""
     dev = torch.device("cuda")
-    L = (256, 128, 128)
+    L = KV_GRID
     prob = synth.cantilever(*L)
-    big = []
+    sets = []
     for seed in (3, 4):
         p = aarmr.default_params(nx=L[0], ny=L[1], nz=L[2], mg_levels=6)
         m = aarmr.Mesh(p)
@@ -417,18 +362,25 @@ def large_kv(torch, aarmr, synth, n_launch):
         fx = torch.tensor(aarmr.fixed_dofs_soa(prob, m.n_node), dtype=torch.int64, device=dev)
         m.setup(torch.tensor(rho, dtype=torch.float64, device=dev), fx)
         nb = 3 * m.n_node
-        vb = torch.randn(nb, dtype=torch.float64, device=dev)
+        g = torch.Generator(device=dev)
+        g.manual_seed(seed)
+        vb = torch.randn(nb, dtype=torch.float64, device=dev, generator=g)
         vb[fx] = 0.0
-        big.append((m, vb, torch.empty(nb, dtype=torch.float64, device=dev)))
-    ms_big = kv_event_timing(torch, aarmr, n_launch, big)
-    bb, nnb = ebe_bytes(*L)
-    gb = bb / (ms_big * 1e-3) / 1e9
-    return {"bound": "hbm", "achieved": round(gb, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(gb / HBM_PEAK_GBS, 4), "traffic": pmc_traffic("256x128x128"),
-            "ms_per_launch": round(ms_big, 5), "bytes_per_launch": bb,
-            "gdof_s": round(3 * nnb / (ms_big * 1e-3) / 1e9, 2),
-            "note": "two independent meshes (v, y, E, mask) alternate so the working set "
-                    "exceeds the 256 MB Infinity Cache"}
+        sets.append((m, vb, torch.empty(nb, dtype=torch.float64, device=dev)))
+    return sets
+
+
+def kv_roofline(ms, grid, extra=None):
+    bb, nnb = ebe_bytes(*grid)
+    gb = bb / (ms * 1e-3) / 1e9
+    out = {"bound": "hbm", "achieved": round(gb, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(gb / HBM_PEAK_GBS, 4), "traffic": pmc_traffic("x".join(map(str, grid))),
+           "kernel": "k_ebe_z (fine-grid K.v, FP64)", "grid": "x".join(map(str, grid)),
+           "ms_per_launch": round(ms, 5), "bytes_per_launch": bb,
+           "gdof_s": round(3 * nnb / (ms * 1e-3) / 1e9, 2)}
+    if extra:
+        out.update(extra)
+    return out
 
 
 def precision_form(torch, aarmr, synth, reps=3):
@@ -636,36 +588,121 @@ def served_form(torch, aarmr, synth, n_requests=40):
     return out
 
 
-def cpu_baseline():
-    """The oracle's analysis (assembly, banded Cholesky, compliance,
-    sensitivities, filter and its adjoint) on the 48x24x24 sub-grid of the
-    workload: the full 96x48x48 direct solve needs ~41 GB and ~3.7e13 flop."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(sets=None, torch=None, aarmr=None, synth=None, reps=8):
+    """The oracle's FP64 element-by-element product (oracle.fem.apply_ebe:
+    gather, dense 24x24 element products through BLAS, scatter by bincount)
+    on the headline grid, in the headline's unit (GDOF/s): `reps` products on
+    the full 256x128x128 grid after one untimed product, with the same
+    moduli as the first GPU mesh.  The DOF table is built once, outside the
+    timed region, as the GPU mesh builds its own once."""
     import numpy as np
 
-    import synth
-    from oracle import filt, sens
+    import synth as _synth
+    from oracle import fem
 
-    nx, ny, nz = NX // 2, NY // 2, NZ // 2
-    prob = synth.cantilever(nx, ny, nz)
-    reps = 3
+    L = KV_GRID
+    nn = (L[0] + 1) * (L[1] + 1) * (L[2] + 1)
+    rho = _synth.smoothed_field(*L, 8.0, 1e-3, 1.0, seed=3).ravel()
+    E = fem.simp(rho)
+    KE = fem.hex8_ke()
+    edof = fem.element_dofs_grid(*L)
+    v = np.random.default_rng(3).standard_normal(3 * nn)
+    fem.apply_ebe(*L, E, KE, v, edof)
     t0 = time.perf_counter()
-    for r in range(reps):
-        x = np.full(prob.n_elem, VOLFRAC) + 0.01 * r
-        H, Hs = filt.filter_matrix(nx, ny, nz, RMIN)
-        xp = filt.forward(H, Hs, x)
-        _, Cs, dcp = sens.analyse(prob, xp)
-        filt.adjoint(H, Hs, dcp)
+    for _ in range(reps):
+        fem.apply_ebe(*L, E, KE, v, edof)
     dt = time.perf_counter() - t0
     cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
-    return {"value": round(reps / dt, 4), "unit": "solves/s", "cores": cores, "kind": "oracle",
-            "sample": f"{reps} analyses of the {nx}x{ny}x{nz} sub-grid (1/8 of the elements): "
-                      f"filter, assembly, banded Cholesky, C, dC/drho; {dt:.1f} s total"}
+    return {"value": round(3 * nn * reps / dt / 1e9, 5), "unit": "GDOF/s", "cores": cores,
+            "kind": "oracle", "cpu_model": cpu_model(),
+            "sample": f"{reps} FP64 element-by-element products on the full "
+                      f"{L[0]}x{L[1]}x{L[2]} grid (oracle.fem.apply_ebe; BLAS on all cores, "
+                      f"scatter single-threaded): {dt:.1f} s, {dt / reps * 1e3:.0f} ms per product"}
+
+
+def loop_form(torch, aarmr, synth, steps, warmup, plain=True):
+    """The 50-cycle AARMR optimisation loop of the 96x48x48 cantilever
+    (Algorithm 1: MGCG for cycles 1..20, then the reduced model with the
+    MGCG fallback), `steps` timed runs after `warmup`; optionally the same
+    loop with MGCG every cycle (the "plain" comparison of eq. 35)."""
+    import numpy as np
+
+    mesh, fixed, f, dv = make_loop_state(torch, aarmr, synth)
+    for w in range(warmup):
+        run_loop(torch, aarmr, mesh, fixed, f, dv)
+    torch.cuda.synchronize()
+    lat_all, paths_all, comp_last, record = [], [], None, []
+    t0 = time.perf_counter()
+    for k in range(steps):
+        lat, paths, comp = run_loop(torch, aarmr, mesh, fixed, f, dv,
+                                    record=record if k == 0 else None)
+        lat_all += lat
+        paths_all += paths
+        comp_last = comp
+    torch.cuda.synchronize()
+    T = time.perf_counter() - t0
+    lat_solve = np.array([a for a, _ in lat_all])
+    lat_cycle = np.array([b for _, b in lat_all])
+    out = {"workload": "AARMR topology-optimisation loop, 96x48x48 hex8 cantilever, 50 cycles "
+                       "(N_on=20, Ns=2, Nm=6, eps_tol=1e-3), MGCG 4 levels rtol 1e-8, filter "
+                       "r=2, OC volfrac 0.3",
+           "runs": steps, "solves_s": round(CYCLES * steps / T, 3),
+           "ms_per_run": round(T * 1e3 / steps, 3),
+           "latency_ms": {"analysis_p50": round(float(np.percentile(lat_solve, 50)), 3),
+                          "analysis_p99": round(float(np.percentile(lat_solve, 99)), 3),
+                          "cycle_p50": round(float(np.percentile(lat_cycle, 50)), 3),
+                          "cycle_p99": round(float(np.percentile(lat_cycle, 99)), 3)},
+           "paths": {p: paths_all.count(p) // steps for p in ("mgcg", "ca", "fallback")},
+           "final_compliance": comp_last[-1]}
+    if os.environ.get("AARMR_BENCH_TRACE"):
+        out["trace_first_run"] = record
+    if plain:
+        tp = time.perf_counter()
+        latp, _, compp = run_loop(torch, aarmr, mesh, fixed, f, dv, plain=True)
+        Tp = time.perf_counter() - tp
+        out["plain_mgcg"] = {"solves_s": round(CYCLES / Tp, 3),
+                             "analysis_p50_ms": round(float(np.median([a for a, _ in latp])), 3),
+                             "analysis_p99_ms": round(float(np.percentile([a for a, _ in latp], 99)), 3),
+                             "final_compliance": compp[-1],
+                             "aarmr_speedup_eq35": round(
+                                 sum(a for a, _ in latp) / (sum(a for a, _ in lat_all) / steps), 3)}
+    mesh.close()
+    return out
+
+
+def kv_steps(torch, aarmr, sets, n_steps):
+    """n_steps steps of KV_PER_STEP products alternating over `sets`, in the
+    form the solvers launch them (input zero on fixed DOFs); returns the
+    elapsed ms from HIP events recorded on the stream the library launches
+    on (torch's current stream)."""
+    s = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    fl = aarmr.INPUT_MASKED
+    e0.record(s)
+    for i in range(n_steps * KV_PER_STEP):
+        m, v, y = sets[i % len(sets)]
+        m.apply(v, y, flags=fl)
+    e1.record(s)
+    e1.synchronize()
+    return e0.elapsed_time(e1)
 
 
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
+                                   "(no multi-GPU path is built)"}))
         sys.exit(2)
     import numpy as np
     import torch
@@ -677,28 +714,8 @@ def main():
         print(json.dumps({"error": "no GPU visible"}))
         sys.exit(2)
     torch.cuda.set_device(0)
-    if args.kv_only:
-        # a plain copy of known size (1 GiB read + 1 GiB written, four times the
-        # Infinity Cache) first, to calibrate the FETCH_SIZE / WRITE_SIZE
-        # counters of a counter run
-        a = torch.ones(2 ** 27, dtype=torch.float64, device="cuda")
-        b = torch.empty_like(a)
-        b.copy_(a)
-        torch.cuda.synchronize()
-        del a, b
-        mesh, fixed, _, _ = make_loop_state(torch, aarmr, synth)
-        mesh.setup(torch.full((NX * NY * NZ,), VOLFRAC, dtype=torch.float64, device="cuda"), fixed)
-        n3 = 3 * mesh.n_node
-        vr = torch.randn(n3, dtype=torch.float64, device="cuda")
-        vr[fixed] = 0.0
-        ms_loop = kv_event_timing(torch, aarmr, args.kv_launches,
-                                  [(mesh, vr, torch.empty_like(vr))])
-        print(json.dumps({"kv_96x48x48_ms": ms_loop,
-                          "roofline_kv_256x128x128": large_kv(torch, aarmr, synth, args.kv_launches)}))
-        return
     if args.study:
-        fn = {"nsnm": study_ns_nm, "bridge": study_bridge, "nsnm2d": study_ns_nm_2d,
-              "halfwheel": study_half_wheel, "inverter": study_inverter}[args.study]
+        fn = {"nsnm": study_ns_nm, "bridge": study_bridge, "inverter": study_inverter}[args.study]
         print(json.dumps({f"study_{args.study}": fn(torch, aarmr, synth)}))
         return
     if args.serve_only:
@@ -708,106 +725,95 @@ def main():
         print(json.dumps({"batched_form_64": batched_form(torch, aarmr, synth)}))
         return
     if args.precision_only:
-        print(json.dumps({"precision_form_256x128x128": precision_form(torch, aarmr, synth)}))
+        print(json.dumps({"analysis_256x128x128": precision_form(torch, aarmr, synth)}))
         return
-    mesh, fixed, f, dv = make_loop_state(torch, aarmr, synth)
-    print(f"[bench] mesh {NX}x{NY}x{NZ}, workspace {mesh.workspace_bytes / 2**20:.0f} MiB",
+    if args.kv_only:
+        # a plain copy of known size (1 GiB read + 1 GiB written, four times the
+        # Infinity Cache) first, to calibrate the FETCH_SIZE / WRITE_SIZE
+        # counters of a counter run
+        a = torch.ones(2 ** 27, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    # ---- headline: FP64 K.v on 256x128x128, two meshes alternating ----
+    sets = kv_sets(torch, aarmr, synth)
+    nn = sets[0][0].n_node
+    print(f"[bench] K.v grid {'x'.join(map(str, KV_GRID))}: {3 * nn} DOFs, two meshes",
           file=sys.stderr, flush=True)
-    for w in range(args.warmup):
-        run_loop(torch, aarmr, mesh, fixed, f, dv)
-        print(f"[bench] warmup step {w + 1} done", file=sys.stderr, flush=True)
+    for (m, v, y) in sets:
+        m.apply(v, y, flags=aarmr.INPUT_MASKED)
+    if args.warmup:
+        kv_steps(torch, aarmr, sets, args.warmup)
     torch.cuda.synchronize()
-    lat_all, paths_all, comp_last = [], [], None
-    record = []
     t0 = time.perf_counter()
-    for k in range(args.steps):
-        lat, paths, comp = run_loop(torch, aarmr, mesh, fixed, f, dv,
-                                    record=record if k == 0 else None)
-        lat_all += lat
-        paths_all += paths
-        comp_last = comp
-        print(f"[bench] step {k + 1}/{args.steps} done", file=sys.stderr, flush=True)
+    ms_ev = kv_steps(torch, aarmr, sets, args.steps)
     torch.cuda.synchronize()
     T = time.perf_counter() - t0
-    n_analyses = CYCLES * args.steps
-    ms_per_step = T * 1e3 / args.steps
-
-    # K.v roofline at the loop size (design of the last cycle is set up)
-    dev = torch.device("cuda")
-    n3 = 3 * mesh.n_node
-    sets = []
-    for _ in range(3):
-        vr = torch.randn(n3, dtype=torch.float64, device=dev)
-        vr[fixed] = 0.0
-        sets.append((mesh, vr, torch.empty(n3, dtype=torch.float64, device=dev)))
-    ms_kv = kv_event_timing(torch, aarmr, args.kv_launches, sets)
-    bytes_kv, nn = ebe_bytes(NX, NY, NZ)
-    gbs = bytes_kv / (ms_kv * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": pmc_traffic(f"{NX}x{NY}x{NZ}"),
-                "kernel": "k_ebe (fine-grid K.v, FP64)", "grid": f"{NX}x{NY}x{NZ}",
-                "ms_per_launch": round(ms_kv, 5), "bytes_per_launch": bytes_kv,
-                "gdof_s": round(3 * nn / (ms_kv * 1e-3) / 1e9, 2)}
+    n_prod = args.steps * KV_PER_STEP
+    ms_launch = ms_ev / n_prod
+    print(f"[bench] {n_prod} products: {ms_launch * 1e3:.2f} us each", file=sys.stderr, flush=True)
+    roofline = kv_roofline(ms_launch, KV_GRID, {
+        "note": "two independent meshes (v, y, moduli, mask) alternate so the working set "
+                "exceeds the 256 MB Infinity Cache; achieved = algorithmic bytes (49 B per node "
+                "+ 8 B per element) / HIP-event time per launch"})
+    out = {
+        "metric": METRIC,
+        "value": round(3 * nn * n_prod / T / 1e9, 2),
+        "unit": "GDOF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(T * 1e3 / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "FP64 element-by-element K.v (eq. 7 operator, Dirichlet rows), "
+                               "256x128x128 hex8 cantilever, smoothed random density "
+                               "[1e-3, 1], two meshes alternating, 50 products per step",
+                   "elements": KV_GRID[0] * KV_GRID[1] * KV_GRID[2], "dofs": 3 * nn,
+                   "parallelism": "single GPU"},
+        "roofline": roofline,
+    }
+    if args.kv_only:
+        print(json.dumps(out), flush=True)
+        return
+    for (m, _, _) in sets:
+        m.close()
+    del sets
+    torch.cuda.empty_cache()
     extra = {}
-    if not args.no_large:
-        extra["roofline_kv_256x128x128"] = large_kv(torch, aarmr, synth, args.kv_launches)
-        torch.cuda.empty_cache()
     if not args.no_precision:
-        extra["precision_form_256x128x128"] = precision_form(torch, aarmr, synth)
+        extra["analysis_256x128x128"] = precision_form(torch, aarmr, synth)
         torch.cuda.empty_cache()
+    extra["loop_96x48x48"] = loop_form(torch, aarmr, synth, args.loop_steps, 1,
+                                       plain=not args.no_plain)
+    # the same K.v on the loop grid (cache-resident working set: GDOF/s only)
+    mesh, fixed, _, _ = make_loop_state(torch, aarmr, synth)
+    mesh.setup(torch.full((NX * NY * NZ,), VOLFRAC, dtype=torch.float64, device="cuda"), fixed)
+    vr = torch.randn(3 * mesh.n_node, dtype=torch.float64, device="cuda")
+    vr[fixed] = 0.0
+    ms96 = kv_event_timing(torch, aarmr, args.kv_launches, [(mesh, vr, torch.empty_like(vr))])
+    extra["loop_96x48x48"]["kv"] = {"ms_per_launch": round(ms96, 5),
+                                    "gdof_s": round(3 * mesh.n_node / (ms96 * 1e-3) / 1e9, 2),
+                                    "note": "13 MB working set, resident in the Infinity Cache"}
+    mesh.close()
+    torch.cuda.empty_cache()
     if not args.no_batch:
         extra["batched_form_64"] = batched_form(torch, aarmr, synth)
         torch.cuda.empty_cache()
     if not args.no_serve:
         extra["served_form"] = served_form(torch, aarmr, synth)
         torch.cuda.empty_cache()
-
-    lat_solve = np.array([a for a, _ in lat_all])
-    lat_cycle = np.array([b for _, b in lat_all])
-    out = {
-        "metric": METRIC,
-        "value": round(n_analyses / T, 3),
-        "unit": "solves/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 3),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": "AARMR topology-optimisation loop, 96x48x48 hex8 cantilever, "
-                               "50 cycles (N_on=20, Ns=2, Nm=6, eps_tol=1e-3), MGCG 4 levels "
-                               "rtol 1e-8, filter r=2, OC volfrac 0.3",
-                   "elements": NX * NY * NZ, "dofs": 3 * mesh.n_node,
-                   "parallelism": "single GPU"},
-        "latency_ms": {"analysis_p50": round(float(np.percentile(lat_solve, 50)), 3),
-                       "analysis_p99": round(float(np.percentile(lat_solve, 99)), 3),
-                       "cycle_p50": round(float(np.percentile(lat_cycle, 50)), 3),
-                       "cycle_p99": round(float(np.percentile(lat_cycle, 99)), 3)},
-        "paths": {p: paths_all.count(p) // args.steps for p in ("mgcg", "ca", "fallback")},
-        "final_compliance": comp_last[-1],
-        "roofline": roofline,
-    }
     out.update(extra)
-    if not args.no_plain:
-        # the same loop with MGCG every cycle (no reduced model): the "vs plain" comparison
-        tp = time.perf_counter()
-        latp, _, compp = run_loop(torch, aarmr, mesh, fixed, f, dv, plain=True)
-        Tp = time.perf_counter() - tp
-        out["plain_mgcg"] = {"solves_s": round(CYCLES / Tp, 3),
-                             "analysis_p50_ms": round(float(np.median([a for a, _ in latp])), 3),
-                             "analysis_p99_ms": round(float(np.percentile([a for a, _ in latp], 99)), 3),
-                             "final_compliance": compp[-1],
-                             "aarmr_speedup_eq35": round(
-                                 sum(a for a, _ in latp) /
-                                 (sum(a for a, _ in lat_all) / args.steps), 3)}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
+        gpu = out["value"]
+        out["cpu_baseline"]["gpu_over_cpu"] = round(gpu / out["cpu_baseline"]["value"], 1)
     print(json.dumps(out), flush=True)
-    if os.environ.get("AARMR_BENCH_TRACE"):
-        print(json.dumps({"trace_first_step": record}), file=sys.stderr)
 
 
 if __name__ == "__main__":
