@@ -55,6 +55,9 @@ def parse():
                     help="skip the 256x128x128 FP64 vs refinement-form solve")
     ap.add_argument("--precision-only", action="store_true",
                     help="only the 256x128x128 FP64 vs refinement-form solve")
+    ap.add_argument("--no-ca-study", action="store_true",
+                    help="skip the bridge loop and the eps / compliance-error relation")
+    ap.add_argument("--ca-study-only", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-instance batch")
     ap.add_argument("--batch-only", action="store_true", help="only the 64-instance batch")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving workload")
@@ -81,7 +84,7 @@ def make_loop_state(torch, aarmr, synth):
     return mesh, fixed, f, dv
 
 
-def run_loop(torch, aarmr, mesh, fixed, f, dv, plain=False, record=None):
+def run_loop(torch, aarmr, mesh, fixed, f, dv, plain=False, record=None, reuse=False):
     """One full optimisation run; returns per-cycle wall times (ms) and paths."""
     dev = f.device
     x = torch.full((mesh.n_elem,), VOLFRAC, dtype=torch.float64, device=dev)
@@ -90,7 +93,8 @@ def run_loop(torch, aarmr, mesh, fixed, f, dv, plain=False, record=None):
     u = torch.zeros_like(f)
     dc = torch.empty_like(x)
     lat, paths, comp = [], [], []
-    fl = aarmr.FILTER_INPUT
+    fl = aarmr.FILTER_INPUT | (aarmr.REUSE_COARSEST if reuse else 0)
+    inv = 0
     for loop in range(1, CYCLES + 1):
         t0 = time.perf_counter()
         if plain or loop <= N_ON:
@@ -100,12 +104,14 @@ def run_loop(torch, aarmr, mesh, fixed, f, dv, plain=False, record=None):
             C, st, code = mesh.solve(x, f, fixed, u, dc=dc, flags=flags)
             paths.append("mgcg")
             if record is not None:
-                record.append(("mgcg", st.iterations[0], st.fine_sweeps))
+                record.append(("mgcg", st.iterations[0], st.fine_sweeps, st.coarsest_inversions))
         else:
             C, st, code = mesh.ca_update(x, f, fixed, u, dc=dc, flags=fl)
             paths.append("ca" if st.accepted[0] else "fallback")
             if record is not None:
-                record.append((paths[-1], st.mgcg_iterations[0], st.fine_sweeps, st.eps[0]))
+                record.append((paths[-1], st.mgcg_iterations[0], st.fine_sweeps, st.eps[0],
+                               st.coarsest_inversions))
+        inv += st.coarsest_inversions
         t1 = time.perf_counter()
         mesh.oc_update(x, dc, dv, VOLFRAC, MOVE, xn, rp)
         x, xn = xn, x
@@ -113,6 +119,8 @@ def run_loop(torch, aarmr, mesh, fixed, f, dv, plain=False, record=None):
         t2 = time.perf_counter()
         lat.append(((t1 - t0) * 1e3, (t2 - t0) * 1e3))
         comp.append(C[0])
+    if record is not None:
+        record.append(("coarsest_inversions", inv))
     return lat, paths, comp
 
 
@@ -630,6 +638,128 @@ def cpu_baseline(sets=None, torch=None, aarmr=None, synth=None, reps=8):
                       f"scatter single-threaded): {dt:.1f} s, {dt / reps * 1e3:.0f} ms per product"}
 
 
+def reuse_form(torch, aarmr, synth, reps=2):
+    """A repeat analysis of the 256x128x128 cantilever (FP64, 5 levels, rel.
+    residual 1e-8) after a smooth 5% density perturbation of the smoothed
+    random field, with a new coarsest inverse (plain) and with the previous
+    design's inverse kept (AARMR_REUSE_COARSEST).  Each timing is the repeat
+    solve alone, after a solve of the unperturbed design, warm-started from
+    its solution; median of `reps`."""
+    import numpy as np
+
+    dev = torch.device("cuda")
+    L = (256, 128, 128)
+    prob = synth.cantilever(*L)
+    r0 = synth.smoothed_field(*L, 8.0, 1e-3, 1.0, seed=3)
+    r1 = synth.smooth_perturb(r0, 0.05, seed=33, sigma=4.0)
+    rho0 = torch.tensor(r0.ravel(), dtype=torch.float64, device=dev)
+    rho1 = torch.tensor(r1.ravel(), dtype=torch.float64, device=dev)
+    m = aarmr.Mesh(aarmr.default_params(nx=L[0], ny=L[1], nz=L[2], mg_levels=5, cg_rtol=1e-8,
+                                        cg_maxit=2000))
+    fixed = torch.tensor(aarmr.fixed_dofs_soa(prob, m.n_node), dtype=torch.int64, device=dev)
+    f = torch.tensor(np.asarray(aarmr.loads_soa(prob, m.n_node)[0]), dtype=torch.float64,
+                     device=dev)
+    u = torch.zeros_like(f)
+    out = {}
+    for name, fl in (("new_inverse", 0), ("kept_inverse", aarmr.REUSE_COARSEST)):
+        times, its, inv, Cs = [], [], [], []
+        for r in range(reps + 1):
+            u.zero_()
+            m.solve(rho0, f, fixed, u, flags=aarmr.REUSE_COARSEST)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            C, st, code = m.solve(rho1, f, fixed, u, flags=fl | aarmr.WARM_START)
+            dt = time.perf_counter() - t0
+            if r > 0:
+                times.append(dt)
+                its.append(int(st.iterations[0]))
+                inv.append(int(st.coarsest_inversions))
+                Cs.append(C[0])
+        out[name] = {"ms": round(float(np.median(times)) * 1e3, 3), "iterations": its,
+                     "coarsest_inversions": inv, "compliance": Cs[-1]}
+    m.close()
+    a, b = out["new_inverse"], out["kept_inverse"]
+    out["speedup"] = round(a["ms"] / b["ms"], 3)
+    out["compliance_rel_diff"] = abs(a["compliance"] - b["compliance"]) / abs(a["compliance"])
+    out["workload"] = ("256x128x128 cantilever, FP64, 5 levels, rel. residual 1e-8: repeat "
+                       "solve after a smooth 5% density perturbation")
+    return out
+
+
+def ca_fidelity(torch, aarmr, synth):
+    """How the eq. (29) residual eps of a reduced-model solution relates to
+    its compliance and displacement errors: the 96x48x48 loop (N_on = 20,
+    Ns = 2, Nm = 6) with every reduced-model solution accepted (eps_tol = 1),
+    each compared with an FP64 MGCG solve to rel. residual 1e-10 of the same
+    design on a second mesh."""
+    import numpy as np
+
+    dev = torch.device("cuda")
+    prob = synth.cantilever(NX, NY, NZ)
+    mk = lambda tol, rtol: aarmr.Mesh(aarmr.default_params(
+        nx=NX, ny=NY, nz=NZ, rmin=RMIN, mg_levels=4, cg_rtol=rtol, cg_maxit=2000, Ns=NS, Nm=NM,
+        ca_tol=tol))
+    mesh, ref = mk(1.0, 1e-8), mk(1.0, 1e-10)
+    fixed = torch.tensor(aarmr.fixed_dofs_soa(prob, mesh.n_node), dtype=torch.int64, device=dev)
+    f = torch.tensor(aarmr.loads_soa(prob, mesh.n_node)[0], dtype=torch.float64, device=dev)
+    ones = torch.ones(mesh.n_elem, dtype=torch.float64, device=dev)
+    dv = torch.empty_like(ones)
+    mesh.filter(ones, dv, mode=1)
+    x = torch.full((mesh.n_elem,), VOLFRAC, dtype=torch.float64, device=dev)
+    xn, rp = torch.empty_like(x), torch.empty_like(x)
+    u, ue = torch.zeros_like(f), torch.zeros_like(f)
+    dc = torch.empty_like(x)
+    rows = []
+    for loop in range(1, CYCLES + 1):
+        if loop <= N_ON:
+            flags = aarmr.FILTER_INPUT | aarmr.WARM_START | (aarmr.RECORD_PARM if loop > N_ON - NS else 0)
+            C, st, _ = mesh.solve(x, f, fixed, u, dc=dc, flags=flags)
+        else:
+            C, st, _ = mesh.ca_update(x, f, fixed, u, dc=dc, flags=aarmr.FILTER_INPUT)
+            Ce, _, _ = ref.solve(x, f, fixed, ue, flags=aarmr.FILTER_INPUT | aarmr.WARM_START)
+            rows.append((loop, float(st.eps[0]), abs(C[0] - Ce[0]) / abs(Ce[0]),
+                         float(torch.linalg.norm(u - ue) / torch.linalg.norm(ue))))
+        mesh.oc_update(x, dc, dv, VOLFRAC, MOVE, xn, rp)
+        x, xn = xn, x
+    torch.cuda.synchronize()
+    mesh.close()
+    ref.close()
+    eps = np.array([r[1] for r in rows])
+    cerr = np.array([r[2] for r in rows])
+    ok = eps[cerr <= 1e-6]
+    bad = eps[cerr > 1e-6]
+    # the largest eps below which every observed step met the 1e-6 compliance bar
+    safe = float(min(bad.min(), ok.max() if ok.size else 0.0)) if bad.size else float(eps.max())
+    return {"workload": "96x48x48 cantilever loop, cycles 21-50 all accepted (eps_tol = 1), "
+                        "each against FP64 MGCG at 1e-10",
+            "steps": [{"cycle": r[0], "eps": r[1], "compliance_rel_err": r[2], "u_rel_err": r[3]}
+                      for r in rows],
+            "eps_range": [float(eps.min()), float(eps.max())],
+            "compliance_rel_err_range": [float(cerr.min()), float(cerr.max())],
+            "max_compliance_err_over_eps2": float((cerr / eps ** 2).max()),
+            "eps_meeting_1e-6_compliance": safe}
+
+
+def bridge_loop(torch, aarmr, synth):
+    """Section 4.2.2's simply supported beam on its smallest grid (72x24x48,
+    four bottom corners fixed, unit load at the bottom centre), volfrac 0.2,
+    80 cycles, r = 2, MGCG to rel. residual 1e-6 with at most 50 iterations
+    (the paper's settings), 4 levels; AARMR with N_on = 20, Ns = Nm = 2 and
+    eps_tol = 1% against MGCG every cycle (eq. 35's speedup)."""
+    prob = synth.bridge(72, 24, 48)
+    kw = dict(cycles=80, volfrac=0.2, rmin=2.0, levels=4, cg_rtol=1e-6, cg_maxit=50)
+    ref = run_opt(torch, aarmr, synth, prob, plain=True, **kw)
+    r = run_opt(torch, aarmr, synth, prob, ns=2, nm=2, ca_tol=0.01, **kw)
+    return {"workload": "72x24x48 simply supported beam, 80 cycles, eps_tol 1%, Ns = Nm = 2, "
+                        "N_on = 20, MGCG rtol 1e-6 / 50 its, 4 levels",
+            "paths": {p: r["paths"].count(p) for p in ("mgcg", "ca", "fallback")},
+            "mgcg_analysis_ms": round(ref["analysis_ms"], 1),
+            "aarmr_analysis_ms": round(r["analysis_ms"], 1),
+            "speedup_eq35": round(ref["analysis_ms"] / r["analysis_ms"], 3),
+            "end_compliance_rel_diff": (r["compliance"][-1] - ref["compliance"][-1])
+            / ref["compliance"][-1]}
+
+
 def loop_form(torch, aarmr, synth, steps, warmup, plain=True):
     """The 50-cycle AARMR optimisation loop of the 96x48x48 cantilever
     (Algorithm 1: MGCG for cycles 1..20, then the reduced model with the
@@ -664,6 +794,8 @@ def loop_form(torch, aarmr, synth, steps, warmup, plain=True):
                           "cycle_p99": round(float(np.percentile(lat_cycle, 99)), 3)},
            "paths": {p: paths_all.count(p) // steps for p in ("mgcg", "ca", "fallback")},
            "final_compliance": comp_last[-1]}
+    out["coarsest_inversions_per_run"] = record[-1][1] if record else None
+    out["cg_iterations_per_run"] = sum(r[1] for r in record[:-1]) if record else None
     if os.environ.get("AARMR_BENCH_TRACE"):
         out["trace_first_run"] = record
     if plain:
@@ -717,6 +849,10 @@ def main():
     if args.study:
         fn = {"nsnm": study_ns_nm, "bridge": study_bridge, "inverter": study_inverter}[args.study]
         print(json.dumps({f"study_{args.study}": fn(torch, aarmr, synth)}))
+        return
+    if args.ca_study_only:
+        print(json.dumps({"bridge_72x24x48_eps1pct": bridge_loop(torch, aarmr, synth),
+                          "ca_fidelity_96x48x48": ca_fidelity(torch, aarmr, synth)}))
         return
     if args.serve_only:
         print(json.dumps({"served_form": served_form(torch, aarmr, synth)}))
@@ -789,8 +925,14 @@ def main():
     if not args.no_precision:
         extra["analysis_256x128x128"] = precision_form(torch, aarmr, synth)
         torch.cuda.empty_cache()
+        extra["repeat_analysis_256x128x128"] = reuse_form(torch, aarmr, synth)
+        torch.cuda.empty_cache()
     extra["loop_96x48x48"] = loop_form(torch, aarmr, synth, args.loop_steps, 1,
                                        plain=not args.no_plain)
+    if not args.no_ca_study:
+        extra["bridge_72x24x48_eps1pct"] = bridge_loop(torch, aarmr, synth)
+        extra["ca_fidelity_96x48x48"] = ca_fidelity(torch, aarmr, synth)
+        torch.cuda.empty_cache()
     # the same K.v on the loop grid (cache-resident working set: GDOF/s only)
     mesh, fixed, _, _ = make_loop_state(torch, aarmr, synth)
     mesh.setup(torch.full((NX * NY * NZ,), VOLFRAC, dtype=torch.float64, device="cuda"), fixed)

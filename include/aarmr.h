@@ -110,6 +110,20 @@ extern "C" {
                                   model when accepted: the approximate
                                   sensitivity of eq. (34)'s form.  Plane-stress
                                   grid only. */
+#define AARMR_REUSE_COARSEST 32  /* Algorithm 2's coarsest solve may keep the
+                                  dense inverse of an earlier design's
+                                  coarsest operator (same fixed DOFs) instead
+                                  of inverting the current one: it stays
+                                  symmetric positive definite, so CG still
+                                  converges to this design's solution, in a
+                                  few more iterations.  The inverse is
+                                  rebuilt when a solve with it needed
+                                  max(3, n0/8) or more iterations beyond the
+                                  n0 of the first solve after the inversion;
+                                  a solve that has not converged after
+                                  2 n0 + 20 iterations inverts the current
+                                  operator and continues from its iterate.
+                                  aarmr_setup always inverts. */
 
 /* ---- parameters -------------------------------------------------------- */
 typedef struct aarmr_params {
@@ -145,6 +159,9 @@ typedef struct aarmr_stats {
   double rel_residual[AARMR_MAX_RHS];  /* final ||f - A u|| / ||f|| */
   int64_t fine_sweeps;                 /* fine-grid operator applications */
   double setup_ms, solve_ms;           /* host wall time of the phases */
+  int32_t coarsest_inversions;         /* dense inversions of the coarsest
+                                          operator this call made (0 when an
+                                          earlier inverse was kept) */
 } aarmr_stats;
 
 /* Statistics of one aarmr_ca_update call. */
@@ -155,6 +172,7 @@ typedef struct aarmr_ca_stats {
   int32_t mgcg_iterations[AARMR_MAX_RHS]; /* fallback CG iterations (0 if accepted) */
   double rel_residual[AARMR_MAX_RHS];  /* final residual of the returned u */
   int64_t fine_sweeps;
+  int32_t coarsest_inversions;         /* as in aarmr_stats */
 } aarmr_ca_stats;
 
 typedef struct aarmr_mesh aarmr_mesh;
@@ -321,27 +339,32 @@ int aarmr_oc_update_noalloc(aarmr_mesh* m, const double* x, const double* dc, co
                             double volfrac, double move, double* x_new, double* rho_phys_new,
                             void* stream);
 
-/* Autotuner of the fine-grid operator's launch shape: the z-marching kernel
- * runs 14 x 15-node tiles of the x-y plane, each marching over a chunk of
- * node planes; times the residency-sized default chunk length and candidate
- * lengths 2..n_z+1 on this mesh's grid (scratch operands: the solver state is
- * untouched), the best of 3 rounds of 5 launches each after a warm-up, and
- * keeps the fastest for the
+/* Autotuner of the fine-grid operator's launch shape.  The z-marching
+ * kernel runs tiles of 30 node columns by ROWS - 1 node rows of the x-y
+ * plane (ROWS in {8, 12, 16}; 16 by default), each marching over a
+ * chunk of node planes.
+ * The autotuner times every tile height (16 being the default) with the
+ * residency-sized default chunk length and candidate lengths 2..n_z+1 on this
+ * mesh's grid (scratch operands: the solver state is untouched), the best of
+ * 3 rounds of 5 launches each after a warm-up, and keeps the fastest for the
  * mesh's later products (FP64 and, in the refinement form, FP32).
- * tz_out: host [2] or NULL, receives the chosen lengths (0 = the default).
- * Every product gives the same bits for every chunk length; CG's dot products
- * are summed per workgroup of that product, so a solve's last bits may
- * change with it.  On the plane-stress grid there is nothing to tune: tz_out
- * receives 0, 0.  Synchronises `stream`.  Errors: AARMR_E_NO_WORKSPACE,
- * AARMR_E_HIP. */
+ * tz_out: host [2] or NULL, receives the chosen shape words (chunk length in
+ * the low 16 bits, 0 = the default; tile rows above them, 0 = the
+ * default).  Every product gives the same bits for every shape; CG's dot
+ * products are summed per workgroup of that product, so a solve's last bits
+ * may change with it.  On the plane-stress grid there is nothing to tune:
+ * tz_out receives 0, 0.  Synchronises `stream`.  Errors:
+ * AARMR_E_NO_WORKSPACE, AARMR_E_HIP. */
 int aarmr_autotune(aarmr_mesh* m, int32_t* tz_out, void* stream);
 
-/* Set the fine-grid operator's z-chunk lengths without timing (for
- * instance the values an earlier aarmr_autotune returned for the same grid):
- * tz64 for FP64 products, tz32 for the refinement form's FP32 products; 0
- * restores the default, lengths above n_z + 1 are clamped to it.  Host-only,
- * takes effect at the next product.  Errors: AARMR_E_INVALID (null mesh, a
- * length below 0 or equal to 1). */
+/* Set the fine-grid operator's launch shapes without timing (for instance
+ * the words an earlier aarmr_autotune returned for the same grid): tz64 for
+ * FP64 products, tz32 for the refinement form's FP32 products.  A shape word
+ * is chunk_length | (tile_rows << 16): chunk length 0 (default) or >= 2
+ * (lengths above n_z + 1 are clamped to it), tile rows 0 (default, 16),
+ * 8, 12 or 16.  0 restores both defaults.  Host-only, takes effect at the
+ * next product.  Errors: AARMR_E_INVALID (null mesh, a negative word, a
+ * chunk length of 1, other tile rows). */
 int aarmr_set_chunk(aarmr_mesh* m, int32_t tz64, int32_t tz32);
 
 /* ---- batched form ------------------------------------------------------

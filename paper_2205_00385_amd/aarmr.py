@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(_PKG, "libaarmr.so")
 OK, E_INVALID, E_HIP, E_NOT_CONVERGED, E_SINGULAR, E_NO_WORKSPACE, E_STATE = range(7)
 MAX_RHS, MAX_LEVELS, MAX_BASIS, MAX_SPRINGS = 8, 8, 10, 8
 FP64, FP32_REFINE = 0, 1
-FILTER_INPUT, RECORD_PARM, WARM_START, INPUT_MASKED, MUTUAL_SENS = 1, 2, 4, 8, 16
+FILTER_INPUT, RECORD_PARM, WARM_START, INPUT_MASKED, MUTUAL_SENS, REUSE_COARSEST = 1, 2, 4, 8, 16, 32
 ORTH_GS, ORTH_SVD = 0, 1
 
 
@@ -50,6 +50,7 @@ class Stats(ctypes.Structure):
         ("rel_residual", ctypes.c_double * MAX_RHS),
         ("fine_sweeps", ctypes.c_int64),
         ("setup_ms", ctypes.c_double), ("solve_ms", ctypes.c_double),
+        ("coarsest_inversions", ctypes.c_int32),
     ]
 
 
@@ -61,6 +62,7 @@ class CAStats(ctypes.Structure):
         ("mgcg_iterations", ctypes.c_int32 * MAX_RHS),
         ("rel_residual", ctypes.c_double * MAX_RHS),
         ("fine_sweeps", ctypes.c_int64),
+        ("coarsest_inversions", ctypes.c_int32),
     ]
 
 

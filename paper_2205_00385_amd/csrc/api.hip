@@ -188,6 +188,19 @@ struct aarmr_mesh {
   bool spec_mg = false;        // the last reduced-model attempt was rejected
   int oc_pairs = 0;            // OC launch pairs the last update needed
   int64_t sweeps = 0;
+  // Reuse of the coarsest inverse across designs (AARMR_REUSE_COARSEST):
+  // Ainv may stay the inverse of an earlier design's coarsest operator for
+  // the same fixed DOFs while solves with it need few more iterations than
+  // the first solve after the inversion did.
+  uint8_t* mask_prev = nullptr;  // the mask Ainv was built for
+  bool reuse_req = false;        // the running call allows reuse
+  bool mask_changed = true;      // the last setup's mask differs from mask_prev
+  bool ainv_valid = false;       // Ainv inverts some design's operator for mask_prev
+  bool ainv_stale = false;       // the current hierarchy uses such an older inverse
+  bool ainv_fresh = false;       // inverted for the current design; no solve yet
+  bool ainv_rebuild = false;     // invert again at the next hierarchy build
+  int ainv_base_its = 0;         // iterations of the first solve after the inversion
+  int ainv_builds = 0, ainv_reuses = 0;
 };
 
 // A running batch: worker threads, each with its stream and queue of items.
@@ -433,6 +446,7 @@ int64_t layout(aarmr_mesh* m, char* base) {
   m->Wf = (double*)take((m->p.rmin > 0.0 ? filter_taps(m->p.rmin) : 1) * d8);
   m->cw = (double*)take(g.ne * d8);
   m->mask = (uint8_t*)take((g.nn + 3) / 4 * 4);
+  m->mask_prev = (uint8_t*)take((g.nn + 3) / 4 * 4);
   m->r = (double*)take(n3 * d8);
   m->z = (double*)take(n3 * d8);
   m->pv = (double*)take(n3 * d8);
@@ -748,6 +762,44 @@ int vcycle(aarmr_mesh* m, int l, const double* b, double* x, hipStream_t s,
   return AARMR_OK;
 }
 
+// Algorithm 2's coarsest solve: the dense inverse of the coarsest Galerkin
+// operator, by Gauss-Jordan.
+int invert_coarsest(aarmr_mesh* m, hipStream_t s) {
+  const Grid& G = m->lg[m->nlev - 1];
+  if (m->dim == 2)
+    launch_q4_assemble_dense(G, m->lv[m->nlev - 1].Ke, m->Ainv, s);
+  else
+    launch_assemble_dense(G, m->lv[m->nlev - 1].Ke, m->Ainv, s);
+  KCHECK();
+  launch_gj_invert(m->nc, m->Ainv, m->gjP, m->gjT, m->gjC, m->gjTb, s);
+  KCHECK();
+  HIP_TRY(hipMemcpyAsync(m->mask_prev, m->mask, (m->lg[0].nn + 3) / 4 * 4,
+                         hipMemcpyDeviceToDevice, s));
+  m->ainv_valid = true;
+  m->ainv_stale = false;
+  m->ainv_fresh = true;
+  m->ainv_rebuild = false;
+  ++m->ainv_builds;
+  return AARMR_OK;
+}
+
+// The coarsest solve of a new hierarchy: keep the inverse of an earlier
+// design when the call allows it, the fixed DOFs are the same and the last
+// solve with it did not need markedly more iterations than the first;
+// otherwise invert the current coarsest operator.  An older inverse is still
+// symmetric positive definite, so the V-cycle stays a symmetric positive
+// definite preconditioner and CG still converges to the current design's
+// solution; only the iteration count changes.
+int coarsest_inverse(aarmr_mesh* m, hipStream_t s) {
+  if (m->reuse_req && m->ainv_valid && !m->mask_changed && !m->ainv_rebuild) {
+    m->ainv_stale = true;
+    m->ainv_fresh = false;
+    ++m->ainv_reuses;
+    return AARMR_OK;
+  }
+  return invert_coarsest(m, s);
+}
+
 // The MG hierarchy of the current moduli and mask (Algorithm 2's operators):
 // Jacobi diagonals, Galerkin operators of the coarse levels, the coarsest
 // dense inverse.  Reads E, mask and the element matrices only.
@@ -769,10 +821,7 @@ int build_mg(aarmr_mesh* m, hipStream_t s) {
         KCHECK();
       }
     }
-    launch_q4_assemble_dense(m->lg[m->nlev - 1], m->lv[m->nlev - 1].Ke, m->Ainv, s);
-    KCHECK();
-    launch_gj_invert(m->nc, m->Ainv, m->gjP, m->gjT, m->gjC, m->gjTb, s);
-    KCHECK();
+    TRY(coarsest_inverse(m, s));
     m->mg_ready = true;
     return AARMR_OK;
   }
@@ -795,10 +844,7 @@ int build_mg(aarmr_mesh* m, hipStream_t s) {
       KCHECK();
     }
   }
-  launch_assemble_dense(m->lg[m->nlev - 1], m->lv[m->nlev - 1].Ke, m->Ainv, s);
-  KCHECK();
-  launch_gj_invert(m->nc, m->Ainv, m->gjP, m->gjT, m->gjC, m->gjTb, s);
-  KCHECK();
+  TRY(coarsest_inverse(m, s));
   m->mg_ready = true;
   return AARMR_OK;
 }
@@ -818,6 +864,10 @@ int setup(aarmr_mesh* m, const double* rho, const int64_t* fixed, int64_t nfixed
   const Grid& g = m->lg[0];
   launch_build_mask(g.nn, fixed, nfixed, m->mask, m->flags, s, m->dim);
   KCHECK();
+  if (m->reuse_req && m->ainv_valid) {
+    launch_mask_diff(g.nn, m->mask, m->mask_prev, m->flags, s);
+    KCHECK();
+  }
   launch_simp(g.ne, rho, m->p.E0, m->p.Emin, m->p.penal, m->E, m->fp32 ? m->E32 : nullptr,
               m->flags, s);
   KCHECK();
@@ -1087,6 +1137,42 @@ int pcg(aarmr_mesh* m, double* x, int* iters, double* relres, hipStream_t s) {
   return rc;
 }
 
+// pcg() with the bookkeeping of a reused coarsest inverse.  A solve with an
+// older inverse gets at most 2 n0 + 20 iterations (n0: the first solve after
+// the inversion); if it has not converged by then the current coarsest
+// operator is inverted and CG continues from its iterate.  A solve that
+// needs max(3, n0 / 8) or more iterations beyond n0 asks for a new inversion
+// at the next hierarchy build.
+int pcg_reuse(aarmr_mesh* m, double* x, int* iters, double* relres, hipStream_t s) {
+  if (!m->ainv_stale) {
+    const int rc = pcg(m, x, iters, relres, s);
+    if (m->ainv_fresh && rc == AARMR_OK) {
+      m->ainv_base_its = *iters;
+      m->ainv_fresh = false;
+    }
+    return rc;
+  }
+  const int maxit = m->p.cg_maxit;
+  const int cap = std::min(maxit, 2 * m->ainv_base_its + 20);
+  m->p.cg_maxit = cap;
+  int rc = pcg(m, x, iters, relres, s);
+  m->p.cg_maxit = maxit;
+  if (rc == AARMR_OK) {
+    if (*iters >= m->ainv_base_its + std::max(3, m->ainv_base_its / 8)) m->ainv_rebuild = true;
+    return rc;
+  }
+  if (rc != AARMR_E_NOT_CONVERGED || cap >= maxit) return rc;
+  TRY(invert_coarsest(m, s));
+  int more = 0;
+  m->p.cg_maxit = maxit - *iters;
+  rc = pcg(m, x, &more, relres, s);
+  m->p.cg_maxit = maxit;
+  *iters += more;
+  m->ainv_fresh = false;
+  m->ainv_base_its = more;
+  return rc;
+}
+
 // CG with the FP64 V-cycle preconditioner for at most maxit iterations.
 int pcg64(aarmr_mesh* m, double* x, int* iters, double* relres, int maxit_in, hipStream_t s) {
   const Grid& g = m->lg[0];
@@ -1216,6 +1302,7 @@ int check_common(aarmr_mesh* m, const double* rho, const double* f, int32_t n_rh
 int finish_flags(aarmr_mesh* m, hipStream_t s) {
   unsigned fl = 0;
   TRY(read_flags(m, &fl, s));
+  m->mask_changed = (fl & 4u) != 0 || !m->ainv_valid;
   if (fl & 1u) return fail(AARMR_E_INVALID, "density outside [0, 1]");
   if (fl & 2u) return fail(AARMR_E_INVALID, "fixed DOF id out of range");
   return AARMR_OK;
@@ -1413,6 +1500,7 @@ int aarmr_bind_workspace(aarmr_mesh* m, void* dev_ptr, int64_t bytes, void* stre
   if (reinterpret_cast<uintptr_t>(dev_ptr) % kAlign) return fail(AARMR_E_INVALID, "workspace not 256-byte aligned");
   const int64_t need = layout(m, nullptr);
   if (bytes < need) return fail(AARMR_E_NO_WORKSPACE, "workspace too small");
+  m->ainv_valid = false;  // a new workspace holds no inverse
   if (!m->hpin) HIP_TRY(hipHostMalloc((void**)&m->hpin, 4096 * sizeof(double), hipHostMallocDefault));
   if (!m->hrr) {
     HIP_TRY(hipHostMalloc((void**)&m->hrr, (kFusedBlocks + 8) * sizeof(double),
@@ -1462,6 +1550,7 @@ int aarmr_setup(aarmr_mesh* m, const double* rho_phys, const int64_t* fixed_dofs
   TRY(need_ws(m));
   if (!rho_phys) return fail(AARMR_E_INVALID, "null rho");
   if (n_fixed < 0 || (n_fixed > 0 && !fixed_dofs)) return fail(AARMR_E_INVALID, "bad fixed DOF list");
+  m->reuse_req = false;
   return setup(m, rho_phys, fixed_dofs, n_fixed, true, S(stream));
 }
 
@@ -1521,8 +1610,11 @@ int aarmr_solve(aarmr_mesh* m, const double* rho, const double* f, int32_t n_rhs
     KCHECK();
     rho_phys = m->rho_f;
   }
-  TRY(setup(m, rho_phys, fixed_dofs, n_fixed, true, s));
-  TRY(finish_flags(m, s));
+  m->reuse_req = (flags & AARMR_REUSE_COARSEST) != 0;
+  const int inv0 = m->ainv_builds;
+  TRY(setup(m, rho_phys, fixed_dofs, n_fixed, false, s));
+  TRY(finish_flags(m, s));  // also tells whether the fixed DOFs changed
+  TRY(build_mg(m, s));
   if (st) {
     std::memset(st, 0, sizeof(*st));
     st->setup_ms = ms_since(t0);
@@ -1541,7 +1633,7 @@ int aarmr_solve(aarmr_mesh* m, const double* rho, const double* f, int32_t n_rhs
     }
     int its = 0;
     double rel = 0.0;
-    int rc = pcg(m, ul, &its, &rel, s);
+    int rc = pcg_reuse(m, ul, &its, &rel, s);
     if (rc != AARMR_OK && rc != AARMR_E_NOT_CONVERGED) return rc;
     if (rc == AARMR_E_NOT_CONVERGED) status = rc;
     if (st) {
@@ -1559,6 +1651,7 @@ int aarmr_solve(aarmr_mesh* m, const double* rho, const double* f, int32_t n_rhs
   if (st) {
     st->solve_ms = ms_since(t1);
     st->fine_sweeps = m->sweeps - sw0;
+    st->coarsest_inversions = m->ainv_builds - inv0;
   }
   if (status != AARMR_OK) return fail(status, "CG reached cg_maxit before cg_rtol");
   return AARMR_OK;
@@ -1587,6 +1680,8 @@ int aarmr_ca_update(aarmr_mesh* m, const double* rho, const double* f, int32_t n
     KCHECK();
     rho_phys = m->rho_f;
   }
+  m->reuse_req = (flags & AARMR_REUSE_COARSEST) != 0;
+  const int inv0 = m->ainv_builds;
   TRY(setup(m, rho_phys, fixed_dofs, n_fixed, false, s));
   TRY(finish_flags(m, s));
   // Algorithm 1 needs the MG hierarchy only when the reduced model is
@@ -1755,7 +1850,7 @@ int aarmr_ca_update(aarmr_mesh* m, const double* rho, const double* f, int32_t n
       if (!m->mg_ready) TRY(build_mg(m, s));
       int its = 0;
       double rel = 0.0;
-      int rc = pcg(m, ul, &its, &rel, s);
+      int rc = pcg_reuse(m, ul, &its, &rel, s);
       if (rc != AARMR_OK && rc != AARMR_E_NOT_CONVERGED) return rc;
       if (rc == AARMR_E_NOT_CONVERGED) status = rc;
       if (st) {
@@ -1772,7 +1867,10 @@ int aarmr_ca_update(aarmr_mesh* m, const double* rho, const double* f, int32_t n
   m->spec_mg = any_rejected;
   HIP_TRY(hipMemcpyAsync(m->E_prev, m->E, g.ne * sizeof(double), hipMemcpyDeviceToDevice, s));
   HIP_TRY(hipStreamSynchronize(s));
-  if (st) st->fine_sweeps = m->sweeps - sw0;
+  if (st) {
+    st->fine_sweeps = m->sweeps - sw0;
+    st->coarsest_inversions = m->ainv_builds - inv0;
+  }
   if (status != AARMR_OK) return fail(status, "fallback CG reached cg_maxit before cg_rtol");
   return AARMR_OK;
 }
@@ -1797,6 +1895,7 @@ int aarmr_set_springs(aarmr_mesh* m, const int64_t* dofs, const double* k, int32
   }
   m->springs = S;
   m->mg_ready = false;
+  m->ainv_valid = false;
   return AARMR_OK;
 }
 
@@ -1877,8 +1976,12 @@ int aarmr_oc_update_noalloc(aarmr_mesh* m, const double* x, const double* dc, co
 
 int aarmr_set_chunk(aarmr_mesh* m, int32_t tz64, int32_t tz32) {
   if (!m) return fail(AARMR_E_INVALID, "null mesh");
-  if (tz64 < 0 || tz64 == 1 || tz32 < 0 || tz32 == 1)
-    return fail(AARMR_E_INVALID, "chunk lengths must be 0 (default) or at least 2");
+  for (int sh : {tz64, tz32}) {
+    const int tz = sh & 0xFFFF, rows = sh >> 16;
+    if (sh < 0 || tz == 1 || (rows != 0 && rows != 8 && rows != 12 && rows != 16))
+      return fail(AARMR_E_INVALID,
+                  "launch shape: chunk length 0 (default) or >= 2, tile rows 0, 8, 12 or 16");
+  }
   m->tz64 = tz64;
   m->tz32 = tz32;
   return AARMR_OK;
@@ -1919,13 +2022,17 @@ int aarmr_autotune(aarmr_mesh* m, int32_t* tz_out, void* stream) {
   launch_fill(g.ne, 1.0, m->ework, s);
   launch_fill(n3, 1.0, m->q, s);
   KCHECK();
+  // launch shapes: tile rows (0 = the per-grid choice, 8, 12, 16) x chunk length
+  std::vector<int> shapes;
+  for (int rows : {0, 8, 12})
+    for (int tz : cand) shapes.push_back(tz | (rows << 16));
   float best = 1e30f;
   int best_tz = 0;
-  for (int tz : cand) {
+  for (int sh : shapes) {
     const float ms = time_one([&] {
-      launch_ebe(g, m->wk, m->ework, m->mask, m->q, m->t0, 2, s, tz);
+      launch_ebe(g, m->wk, m->ework, m->mask, m->q, m->t0, 2, s, sh);
     });
-    if (ms < best) { best = ms; best_tz = tz; }
+    if (ms < best) { best = ms; best_tz = sh; }
   }
   m->tz64 = best_tz;
   if (m->fp32) {
@@ -1935,11 +2042,11 @@ int aarmr_autotune(aarmr_mesh* m, int32_t* tz_out, void* stream) {
     KCHECK();
     best = 1e30f;
     best_tz = 0;
-    for (int tz : cand) {
+    for (int sh : shapes) {
       const float ms = time_one([&] {
-        launch_ebe_f32(g, m->wk, m->d32, m->mask, m->q32, m->p32, 2, s, tz);
+        launch_ebe_f32(g, m->wk, m->d32, m->mask, m->q32, m->p32, 2, s, sh);
       });
-      if (ms < best) { best = ms; best_tz = tz; }
+      if (ms < best) { best = ms; best_tz = sh; }
     }
     m->tz32 = best_tz;
   }

@@ -94,6 +94,8 @@ void launch_diff(int64_t n, const double* a, const double* b, double* out, hipSt
 // ncomp: DOFs per node (3, or 2 on the plane-stress grid)
 void launch_build_mask(int64_t nn, const int64_t* fixed, int64_t nfixed, uint8_t* mask,
                        unsigned* bad, hipStream_t s, int ncomp = 3);
+void launch_mask_diff(int64_t nn, const uint8_t* a, const uint8_t* b, unsigned* flags,
+                      hipStream_t s);
 void launch_diag_fine(const Grid& g, const double* KE, const double* E, const uint8_t* mask,
                       double* dinv, float* dinv32, hipStream_t s);
 void launch_dc_accum(int64_t ne, const double* rho, const double* energy, double E0, double Emin,

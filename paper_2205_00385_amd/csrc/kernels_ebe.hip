@@ -10,10 +10,12 @@
 // mesh is created).  So KE v = W^T B (W v) / 8 costs two 8-point Walsh
 // transforms per component plus ~40 multiply-adds instead of 576.
 //
-// Data flow.  A workgroup of 32 x 8 threads (two 32-lane x-rows per
-// wavefront) owns 30 x 7 node columns; thread (tx, ty) handles the element
-// column (i, j) = (30 bx - 1 + tx, 7 by - 1 + ty) (the last lane of a row
-// only supplies node values) and marches along z over a chunk of node planes.  The x-y
+// Data flow.  A workgroup of 32 x ROWS threads (two 32-lane x-rows per
+// wavefront; ROWS = 16 unless a tuned shape says otherwise) owns
+// 30 x (ROWS - 1) node columns; thread (tx, ty) handles the element column
+// (i, j) = (30 bx - 1 + tx, (ROWS - 1) by - 1 + ty) (the last lane of a row
+// only supplies node values) and marches along z over a chunk of node
+// planes.  The x-y
 // Walsh transform of a node plane is computed once and reused by the two
 // element layers that share the plane; the dz = 1 outputs of layer k-1 stay
 // in registers and are added to the dz = 0 outputs of layer k.  The four
@@ -74,12 +76,11 @@ __device__ inline void walsh4(T& q0, T& q1, T& q2, T& q3) {
 // to drain the prefetched plane.
 constexpr uint32_t kOutside = 0x80000000u;
 // 32-lane rows: a row segment of y is 30 nodes, so per owned node half as
-// many cache lines are shared with the neighbouring tile as with 16 lanes
+// many cache lines are shared with the neighbouring tile as with 16 lanes.
+// A workgroup has ROWS x-rows (2 per wavefront) and owns ROWS - 1 node rows;
+// ROWS is one of {8, 12, 16} (ebe_rows below).
 constexpr int kLanes = 32;           // element columns per x-row
-constexpr int kRows = 8;             // x-rows per workgroup (2 per wavefront)
 constexpr int kTileX = kLanes - 2;   // node columns owned per row
-constexpr int kTileY = kRows - 1;    // node rows owned per workgroup
-constexpr int kThreads = kLanes * kRows;
 constexpr int kBufferWord3 = 0x00020000;  // raw buffer, 32-bit dwords (gfx9)
 
 __device__ inline __amdgpu_buffer_rsrc_t make_rsrc(const void* p, uint32_t bytes) {
@@ -124,8 +125,8 @@ struct PlaneRaw {
 #ifndef AARMR_EBE_MINB
 #define AARMR_EBE_MINB 1  // workgroups per CU the register budget is sized for
 #endif
-template <typename T, bool MASK_IN, int PF, bool JAC, bool DOT>
-__global__ void __launch_bounds__(kThreads, AARMR_EBE_MINB) k_ebe_z(int nx, int ny, int nz, int gx, int gy, int TZ,
+template <typename T, int ROWS, bool MASK_IN, int PF, bool JAC, bool DOT>
+__global__ void __launch_bounds__(kLanes * ROWS, AARMR_EBE_MINB) k_ebe_z(int nx, int ny, int nz, int gx, int gy, int TZ,
                                                     WalshConsts K, const T* __restrict__ E,
                                                     const uint8_t* __restrict__ mask,
                                                     const T* __restrict__ v, T* __restrict__ y,
@@ -133,7 +134,8 @@ __global__ void __launch_bounds__(kThreads, AARMR_EBE_MINB) k_ebe_z(int nx, int 
                                                     const T* __restrict__ jd, T omega,
                                                     double* __restrict__ part) {
   constexpr bool OWNV = JAC || DOT;  // keep the node's own v of the plane written next
-  __shared__ T xs[2][3][kRows][kLanes];
+  constexpr int kTileY = ROWS - 1;   // node rows owned per workgroup
+  __shared__ T xs[2][3][ROWS][kLanes];
   const int tx = threadIdx.x & (kLanes - 1), ty = threadIdx.x / kLanes;
   // XCD-aware tile order: workgroups are dispatched round-robin over the 8
   // XCDs, so workgroup w is given tile (w % 8) * (count / 8) + w / 8 and
@@ -320,12 +322,17 @@ __global__ void __launch_bounds__(kThreads, AARMR_EBE_MINB) k_ebe_z(int nx, int 
     }
   }
   if (DOT) {  // wavefront sums, then the four in wave order
-    __shared__ double wsum[kThreads / 64];
+    __shared__ double wsum[ROWS / 2];
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) dacc += __shfl_down(dacc, off, 64);
     if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = dacc;
     __syncthreads();
-    if (threadIdx.x == 0) part[blockIdx.x] = (wsum[0] + wsum[1]) + (wsum[2] + wsum[3]);
+    if (threadIdx.x == 0) {
+      double t = (wsum[0] + wsum[1]) + (wsum[2] + wsum[3]);
+#pragma unroll
+      for (int q = 4; q < ROWS / 2; q += 2) t += wsum[q] + wsum[q + 1];
+      part[blockIdx.x] = t;
+    }
   }
 }
 
@@ -400,17 +407,35 @@ __global__ void k_identity_rows(int64_t nn, const uint8_t* __restrict__ mask,
 #define AARMR_EBE_PF 1
 #endif
 
-template <typename T, bool MASK_IN, bool JAC = false, bool DOT = false>
-static int launch_ebe_t(const Grid& g, const WalshConsts& K, const T* E, const uint8_t* mask,
-                        const T* v, T* y, int tz_req, hipStream_t s, const T* jb = nullptr,
-                        const T* jd = nullptr, T omega = 0, double* part = nullptr) {
+// Tile rows.  The launch shape word `shape` carries a tuned z-chunk length
+// in its low 16 bits (0: residency-sized) and a tuned ROWS in the bits above
+// (0: the default, 16 rows).  Sixteen rows measured fastest on both the
+// 96x48x48 and the 256x128x128 grid: 8.8 and 66.7 us against 9.2 and 76 us
+// with 8 rows and 14 and 83 us with 12, although a 512-thread workgroup of
+// this kernel leaves a third of the wavefront slots of a compute unit empty.
+#ifndef AARMR_EBE_ROWS
+#define AARMR_EBE_ROWS 16
+#endif
+
+int ebe_rows(int shape) {
+  const int tuned = shape >> 16;
+  if (tuned == 8 || tuned == 12 || tuned == 16) return tuned;
+  return AARMR_EBE_ROWS;
+}
+
+template <typename T, int ROWS, bool MASK_IN, bool JAC, bool DOT>
+static int launch_ebe_r(const Grid& g, const WalshConsts& K, const T* E, const uint8_t* mask,
+                        const T* v, T* y, int tz_req, hipStream_t s, const T* jb, const T* jd,
+                        T omega, double* part) {
+  constexpr int kThreads = kLanes * ROWS;
+  constexpr int kTileY = ROWS - 1;
   // resident workgroups of this kernel on the device (thread-safe one-time init)
   static const int slots = [] {
     int dev = 0, cus = 0, per_cu = 0;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &per_cu, k_ebe_z<T, MASK_IN, AARMR_EBE_PF, JAC, DOT>, kThreads, 0);
+        &per_cu, k_ebe_z<T, ROWS, MASK_IN, AARMR_EBE_PF, JAC, DOT>, kThreads, 0);
     return (cus > 0 && per_cu > 0) ? cus * per_cu : 512;
   }();
   const int gx = (g.nx + 1 + kTileX - 1) / kTileX;
@@ -423,14 +448,30 @@ static int launch_ebe_t(const Grid& g, const WalshConsts& K, const T* E, const u
   if (tz_req > 0) tz = tz_req < planes ? tz_req : planes;  // tuned z-chunk length
   if (tz < 2) tz = 2;
   gz = (planes + tz - 1) / tz;
-  k_ebe_z<T, MASK_IN, AARMR_EBE_PF, JAC, DOT><<<(unsigned)(gx * gy * gz), kThreads, 0, s>>>(
+  k_ebe_z<T, ROWS, MASK_IN, AARMR_EBE_PF, JAC, DOT><<<(unsigned)(gx * gy * gz), kThreads, 0, s>>>(
       g.nx, g.ny, g.nz, gx, gy, tz, K, E, mask, v, y, jb, jd, omega, part);
   return gx * gy * gz;
 }
 
+template <typename T, bool MASK_IN, bool JAC = false, bool DOT = false>
+static int launch_ebe_t(const Grid& g, const WalshConsts& K, const T* E, const uint8_t* mask,
+                        const T* v, T* y, int shape, hipStream_t s, const T* jb = nullptr,
+                        const T* jd = nullptr, T omega = 0, double* part = nullptr) {
+  const int tz = shape & 0xFFFF;
+  switch (ebe_rows(shape)) {
+    case 8:
+      return launch_ebe_r<T, 8, MASK_IN, JAC, DOT>(g, K, E, mask, v, y, tz, s, jb, jd, omega, part);
+    case 12:
+      return launch_ebe_r<T, 12, MASK_IN, JAC, DOT>(g, K, E, mask, v, y, tz, s, jb, jd, omega, part);
+    default:
+      return launch_ebe_r<T, 16, MASK_IN, JAC, DOT>(g, K, E, mask, v, y, tz, s, jb, jd, omega, part);
+  }
+}
+
 int ebe_partials_max(const Grid& g) {
+  // the most workgroups of any tile height (8 rows) and chunk length (2)
   const int gx = (g.nx + 1 + kTileX - 1) / kTileX;
-  const int gy = (g.ny + 1 + kTileY - 1) / kTileY;
+  const int gy = (g.ny + 1 + 7 - 1) / 7;
   return gx * gy * ((g.nz + 1 + 1) / 2);
 }
 

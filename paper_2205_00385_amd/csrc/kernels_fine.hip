@@ -54,6 +54,14 @@ __global__ void k_mask_set(int64_t nn, int ncomp, const int64_t* __restrict__ fi
   atomicOr(&mask_words[node >> 2], bit);
 }
 
+// flags |= 4 if the two masks differ in any word (padding bytes are zero in
+// both: the mask is cleared word-wise before its bits are set).
+__global__ void k_mask_diff(int64_t nw, const uint32_t* __restrict__ a,
+                            const uint32_t* __restrict__ b, unsigned* flags) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < nw && a[t] != b[t]) atomicOr(flags, 4u);
+}
+
 // Jacobi diagonal of A: sum over adjacent elements of E_e * KE_(aa) per
 // component; identity on fixed DOFs.  Stores the inverse.
 __global__ void k_diag_fine(int nx, int ny, int nz, const double* __restrict__ KE,
@@ -116,6 +124,13 @@ void launch_build_mask(int64_t nn, const int64_t* fixed, int64_t nfixed, uint8_t
   uint32_t* w = reinterpret_cast<uint32_t*>(mask);
   k_mask_clear<<<nblk((nn + 3) / 4, 256), 256, 0, s>>>(nn, w);
   if (nfixed > 0) k_mask_set<<<nblk(nfixed, 256), 256, 0, s>>>(nn, ncomp, fixed, nfixed, w, bad);
+}
+
+void launch_mask_diff(int64_t nn, const uint8_t* a, const uint8_t* b, unsigned* flags,
+                      hipStream_t s) {
+  const int64_t nw = (nn + 3) / 4;
+  k_mask_diff<<<nblk(nw, 256), 256, 0, s>>>(nw, reinterpret_cast<const uint32_t*>(a),
+                                            reinterpret_cast<const uint32_t*>(b), flags);
 }
 
 void launch_diag_fine(const Grid& g, const double* KE, const double* E, const uint8_t* mask,

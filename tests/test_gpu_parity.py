@@ -370,7 +370,9 @@ def test_autotune_keeps_products_bitwise(dims):
         C0, st0, _ = m.solve(rho, f, fixed, u0)
         tuned = m.autotune()
         log(f"  {dims} precision {prec}: tuned chunk lengths {tuned}")
-        for tz in (None, 2, 3, 5, 7, prob.nz + 1):
+        # chunk lengths, then tile heights (shape word: rows << 16 | chunk)
+        for tz in (None, 2, 3, 5, 7, prob.nz + 1, 8 << 16, 12 << 16, (16 << 16) | 3,
+                   (12 << 16) | 2):
             if tz is not None:
                 m.set_chunk(tz, tz)
             y1 = torch.empty_like(y0)
@@ -388,6 +390,8 @@ def test_autotune_keeps_products_bitwise(dims):
             log(f"    chunk {tz}: {st1.iterations[0]} iterations (default {st0.iterations[0]})")
         with pytest.raises(aarmr.AarmrError):
             m.set_chunk(1, 0)
+        with pytest.raises(aarmr.AarmrError):
+            m.set_chunk(10 << 16, 0)
         m.close()
 
 
@@ -463,3 +467,52 @@ def test_ca_svd_and_gs_bases_give_same_reduced_solution():
     assert rg == rs
     assert rel(us, ug) <= 1e-9
     assert abs(es - eg) <= 1e-9 * max(eg, 1e-12) + 1e-12
+
+
+def test_ca_nm6_accepted_branch_48x24x24():
+    """Algorithm 1 with the benchmark loop's basis size (Nm = 6, Ns = 2) on a
+    48x24x24 cantilever: the GPU's reduced-model steps against the oracle's
+    (eq. 21's SVD basis, exact solves for the PARM and the fallback).  Small
+    smooth design steps first, so the accepted branch (eps < 1%, the paper's
+    3D range) is taken, then larger ones until a fallback occurs."""
+    from paper_2205_00385_amd import aarmr
+
+    dims = (48, 24, 24)
+    prob = synth.cantilever(*dims)
+    Ns, Nm, N_on, tol = 2, 6, 2, 1e-2
+    alg = oca.AARMR(prob, Ns=Ns, Nm=Nm, N_on=N_on, eps_tol=tol)
+    m = mesh_for(prob, mg_levels=4, cg_rtol=1e-11, Ns=Ns, Nm=Nm, ca_tol=tol)
+    fixed = fixed_tensor(prob, m)
+    f = loads_tensor(prob, m)
+    u = torch.zeros_like(f)
+    dc = torch.zeros(m.n_elem, dtype=torch.float64, device="cuda")
+    base = synth.smoothed_field(*dims, 3.0, 0.2, 1.0, seed=70).ravel()
+    d = synth.smoothed_field(*dims, 4.0, -1.0, 1.0, seed=71).ravel()
+    edof = fem.element_dofs(*dims)
+    KE = fem.hex8_ke()
+    steps = [0.0, 0.002, 0.004, 0.006, 0.008, 0.03, 0.15]
+    paths = []
+    for loop, amp in enumerate(steps, start=1):
+        rho = np.clip(base + amp * d, 0.05, 1.0)
+        log(f"  Nm=6 loop {loop} ({dims}, step {amp})")
+        (u_ref, path, eps_ref, rank_ref), = alg.cycle(loop, rho)
+        if loop <= N_on:
+            flags = aarmr.WARM_START | (aarmr.RECORD_PARM if loop > N_on - Ns else 0)
+            C, st, _ = m.solve(t64(rho), f, fixed, u, dc=dc, flags=flags)
+            gpath = "mgcg"
+        else:
+            C, st, _ = m.ca_update(t64(rho), f, fixed, u, dc=dc)
+            gpath = "ca" if st.accepted[0] else "fallback"
+            log(f"    eps gpu={st.eps[0]:.6e} oracle={eps_ref:.6e} rank {st.rank[0]}/{rank_ref}")
+            if abs(st.eps[0] - tol) > 1e-6 * tol:
+                assert gpath == path
+            assert abs(st.eps[0] - eps_ref) <= 1e-6 * max(eps_ref, 1e-12) + 1e-9
+        paths.append(gpath)
+        assert rel(u.cpu().numpy(), soa(u_ref)) <= 1e-6
+        Cref = float(alg.f[0] @ u_ref)
+        assert abs(C[0] - Cref) <= 1e-6 * abs(Cref)
+        dref = sens.dc_drho_phys(rho, sens.element_energy(u_ref, edof, KE))
+        assert rel(dc.cpu().numpy(), dref) <= 1e-6
+    log(f"  paths {paths}")
+    assert paths.count("ca") >= 2 and "fallback" in paths
+    m.close()
