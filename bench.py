@@ -58,6 +58,8 @@ def parse():
     ap.add_argument("--no-ca-study", action="store_true",
                     help="skip the bridge loop and the eps / compliance-error relation")
     ap.add_argument("--ca-study-only", action="store_true")
+    ap.add_argument("--loop-only", action="store_true",
+                    help="only the 96x48x48 optimisation loop (for kernel traces)")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-instance batch")
     ap.add_argument("--batch-only", action="store_true", help="only the 64-instance batch")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving workload")
@@ -688,18 +690,20 @@ def reuse_form(torch, aarmr, synth, reps=2):
 
 def ca_fidelity(torch, aarmr, synth):
     """How the eq. (29) residual eps of a reduced-model solution relates to
-    its compliance and displacement errors: the 96x48x48 loop (N_on = 20,
-    Ns = 2, Nm = 6) with every reduced-model solution accepted (eps_tol = 1),
-    each compared with an FP64 MGCG solve to rel. residual 1e-10 of the same
-    design on a second mesh."""
+    its compliance and displacement errors.  The 96x48x48 loop runs its 20
+    MGCG cycles (the last two build the PARM, Ns = 2); from that design,
+    smooth design perturbations of mean size 1e-4 ... 1e-1 are each analysed
+    by one reduced-model step (Nm = 6, accepted whatever eps: eps_tol = 1)
+    from the unperturbed design's exact solution, and compared with an FP64
+    MGCG solve to rel. residual 1e-10 of the perturbed design."""
     import numpy as np
 
     dev = torch.device("cuda")
     prob = synth.cantilever(NX, NY, NZ)
-    mk = lambda tol, rtol: aarmr.Mesh(aarmr.default_params(
+    mk = lambda rtol: aarmr.Mesh(aarmr.default_params(
         nx=NX, ny=NY, nz=NZ, rmin=RMIN, mg_levels=4, cg_rtol=rtol, cg_maxit=2000, Ns=NS, Nm=NM,
-        ca_tol=tol))
-    mesh, ref = mk(1.0, 1e-8), mk(1.0, 1e-10)
+        ca_tol=1.0))
+    mesh, ref = mk(1e-10), mk(1e-10)
     fixed = torch.tensor(aarmr.fixed_dofs_soa(prob, mesh.n_node), dtype=torch.int64, device=dev)
     f = torch.tensor(aarmr.loads_soa(prob, mesh.n_node)[0], dtype=torch.float64, device=dev)
     ones = torch.ones(mesh.n_elem, dtype=torch.float64, device=dev)
@@ -709,33 +713,39 @@ def ca_fidelity(torch, aarmr, synth):
     xn, rp = torch.empty_like(x), torch.empty_like(x)
     u, ue = torch.zeros_like(f), torch.zeros_like(f)
     dc = torch.empty_like(x)
+    FI = aarmr.FILTER_INPUT
+    for loop in range(1, N_ON + 1):
+        flags = FI | aarmr.WARM_START | (aarmr.RECORD_PARM if loop > N_ON - NS else 0)
+        mesh.solve(x, f, fixed, u, dc=dc, flags=flags)
+        if loop < N_ON:
+            mesh.oc_update(x, dc, dv, VOLFRAC, MOVE, xn, rp)
+            x, xn = xn, x
+    x0 = x.cpu().numpy().reshape(NZ, NY, NX)
     rows = []
-    for loop in range(1, CYCLES + 1):
-        if loop <= N_ON:
-            flags = aarmr.FILTER_INPUT | aarmr.WARM_START | (aarmr.RECORD_PARM if loop > N_ON - NS else 0)
-            C, st, _ = mesh.solve(x, f, fixed, u, dc=dc, flags=flags)
-        else:
-            C, st, _ = mesh.ca_update(x, f, fixed, u, dc=dc, flags=aarmr.FILTER_INPUT)
-            Ce, _, _ = ref.solve(x, f, fixed, ue, flags=aarmr.FILTER_INPUT | aarmr.WARM_START)
-            rows.append((loop, float(st.eps[0]), abs(C[0] - Ce[0]) / abs(Ce[0]),
-                         float(torch.linalg.norm(u - ue) / torch.linalg.norm(ue))))
-        mesh.oc_update(x, dc, dv, VOLFRAC, MOVE, xn, rp)
-        x, xn = xn, x
+    for k, amp in enumerate((1e-4, 3e-4, 1e-3, 3e-3, 1e-2, 3e-2, 1e-1)):
+        xp = torch.tensor(synth.smooth_perturb(x0, amp, seed=500 + k, sigma=2.0, lo=0.0).ravel(),
+                          dtype=torch.float64, device=dev)
+        mesh.solve(x, f, fixed, u, flags=FI | aarmr.WARM_START)  # reference state: x0, u(x0)
+        C, st, _ = mesh.ca_update(xp, f, fixed, u, flags=FI)
+        Ce, _, _ = ref.solve(xp, f, fixed, ue, flags=FI | aarmr.WARM_START)
+        rows.append({"perturbation": amp, "eps": float(st.eps[0]),
+                     "compliance_rel_err": abs(C[0] - Ce[0]) / abs(Ce[0]),
+                     "u_rel_err": float(torch.linalg.norm(u - ue) / torch.linalg.norm(ue)),
+                     "rank": int(st.rank[0])})
     torch.cuda.synchronize()
     mesh.close()
     ref.close()
-    eps = np.array([r[1] for r in rows])
-    cerr = np.array([r[2] for r in rows])
-    ok = eps[cerr <= 1e-6]
-    bad = eps[cerr > 1e-6]
-    # the largest eps below which every observed step met the 1e-6 compliance bar
-    safe = float(min(bad.min(), ok.max() if ok.size else 0.0)) if bad.size else float(eps.max())
-    return {"workload": "96x48x48 cantilever loop, cycles 21-50 all accepted (eps_tol = 1), "
-                        "each against FP64 MGCG at 1e-10",
-            "steps": [{"cycle": r[0], "eps": r[1], "compliance_rel_err": r[2], "u_rel_err": r[3]}
-                      for r in rows],
-            "eps_range": [float(eps.min()), float(eps.max())],
-            "compliance_rel_err_range": [float(cerr.min()), float(cerr.max())],
+    eps = np.array([r["eps"] for r in rows])
+    cerr = np.array([r["compliance_rel_err"] for r in rows])
+    order = np.argsort(eps)
+    safe = 0.0  # largest eps below which every observed step met the 1e-6 compliance bar
+    for i in order:
+        if cerr[i] > 1e-6:
+            break
+        safe = float(eps[i])
+    return {"workload": "96x48x48 cantilever: design after 20 MGCG cycles, smooth perturbations, "
+                        "one reduced-model step each (Nm = 6, Ns = 2) against FP64 MGCG at 1e-10",
+            "steps": rows,
             "max_compliance_err_over_eps2": float((cerr / eps ** 2).max()),
             "eps_meeting_1e-6_compliance": safe}
 
@@ -849,6 +859,10 @@ def main():
     if args.study:
         fn = {"nsnm": study_ns_nm, "bridge": study_bridge, "inverter": study_inverter}[args.study]
         print(json.dumps({f"study_{args.study}": fn(torch, aarmr, synth)}))
+        return
+    if args.loop_only:
+        print(json.dumps({"loop_96x48x48": loop_form(torch, aarmr, synth, args.loop_steps, 1,
+                                                     plain=False)}))
         return
     if args.ca_study_only:
         print(json.dumps({"bridge_72x24x48_eps1pct": bridge_loop(torch, aarmr, synth),

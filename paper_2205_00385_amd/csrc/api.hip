@@ -167,6 +167,9 @@ struct aarmr_mesh {
   double* scal = nullptr;
   double* partial = nullptr;
   double *part_pq = nullptr, *part_rz = nullptr;  // per-workgroup partials of the fine products
+  int part_cap = 0;                               // their length per load case
+  int* act = nullptr;      // lock-step solve: 1 for a load case still iterating [n_rhs_max]
+  int* hact = nullptr;     // pinned host staging of act
   bool want_rz = false;  // the V-cycle's last fine sweep also forms r^T z partials
   int rz_nb = 0;         // how many it wrote (0: none)
   unsigned* flags = nullptr;
@@ -466,26 +469,29 @@ int64_t layout(aarmr_mesh* m, char* base) {
     L.x = (double*)take(nl * d8);
     L.t = (double*)take(nl * d8);
   }
+  // the refinement form's FP32 vectors hold every load case (lock-step solve)
+  const int64_t R = m->fp32 ? m->p.n_rhs_max : 1;
   if (m->fp32) {
     const int64_t f4 = sizeof(float);
     m->Bw32d = (float*)take(576 * f4);
-    m->Y1f = (float*)take(24 * m->lg[1].ne * f4);
+    m->Y1f = (float*)take(R * 24 * m->lg[1].ne * f4);
     m->E32 = (float*)take(g.ne * f4);
-    m->r32 = (float*)take(n3 * f4);
-    m->z32 = (float*)take(n3 * f4);
-    m->p32 = (float*)take(n3 * f4);
-    m->q32 = (float*)take(n3 * f4);
-    m->d32 = (float*)take(n3 * f4);
+    m->r32 = (float*)take(R * n3 * f4);
+    m->z32 = (float*)take(R * n3 * f4);
+    m->p32 = (float*)take(R * n3 * f4);
+    m->q32 = (float*)take(R * n3 * f4);
+    m->d32 = (float*)take(R * n3 * f4);
     for (int l = 0; l < m->nlev; ++l) {
       const int64_t m3 = ndof(m, l);
       LevelBuf& L = m->lv[l];
       L.dinv32 = (float*)take(m3 * f4);
-      L.t32 = (float*)take(m3 * f4);
+      L.t32 = (float*)take(R * m3 * f4);
       if (l >= 1) {
-        L.b32 = (float*)take(m3 * f4);
-        L.x32 = (float*)take(m3 * f4);
+        L.b32 = (float*)take(R * m3 * f4);
+        L.x32 = (float*)take(R * m3 * f4);
       }
     }
+    m->act = (int*)take(R * 4);
   }
   m->Ainv = (double*)take((int64_t)m->nc * m->nc * d8);
   m->gjP = (double*)take(2 * kGJBlock * kGJBlock * d8);  // two pivot inverses
@@ -495,12 +501,13 @@ int64_t layout(aarmr_mesh* m, char* base) {
   m->Phi = (double*)take((int64_t)m->p.n_rhs_max * m->p.Ns * n3 * d8);
   m->R = (double*)take((int64_t)m->p.Nm * n3 * d8);
   m->KR = (double*)take((int64_t)m->p.Nm * n3 * d8);
-  m->scal = (double*)take(SC_TOTAL * d8);
+  m->scal = (double*)take(R * SC_TOTAL * d8);  // one block of scalars per load case
   m->partial = (double*)take((int64_t)kRedSlots * kRedBlocks * d8);
   if (m->dim == 3) {  // CG's p^T A p and r^T z partials from the fine-grid products
     const int64_t cap = ebe_partials_max(m->lg[0]);
-    m->part_pq = (double*)take(cap * d8);
-    m->part_rz = (double*)take(cap * d8);
+    m->part_cap = (int)cap;
+    m->part_pq = (double*)take(R * cap * d8);
+    m->part_rz = (double*)take(R * cap * d8);
   }
   m->flags = (unsigned*)take(64);
   return off;
@@ -878,16 +885,16 @@ int setup(aarmr_mesh* m, const double* rho, const int64_t* fixed, int64_t nfixed
 
 // ---- refinement form: FP32 inner solve ------------------------------------
 // y = A v on level l with FP32 vectors (v zero on fixed DOFs).
-int apply32(aarmr_mesh* m, int l, const float* v, float* y, hipStream_t s) {
+int apply32(aarmr_mesh* m, int l, const float* v, float* y, hipStream_t s, int nr = 1) {
   if (l == 0) {
-    launch_ebe_f32(m->lg[0], m->wk, m->E32, m->mask, v, y, 2, s, m->tz32);
+    launch_ebe_f32(m->lg[0], m->wk, m->E32, m->mask, v, y, 2, s, m->tz32, nr);
     ++m->sweeps;
   } else if (l == 1) {
     TRY(flagged_count(m, s));
     launch_apply_l1_f32(m->lg[1], m->lv[1].Ke, m->Kcomp1, m->cap1, m->Bw32d, m->E32,
-                        m->eflag1, m->list1, m->count1, m->nflag1, v, m->Y1f, y, s);
+                        m->eflag1, m->list1, m->count1, m->nflag1, v, m->Y1f, y, s, nr);
   } else {
-    launch_apply_elemmat_f32(m->lg[l], m->lv[l].Ke, v, y, s);
+    launch_apply_elemmat_f32(m->lg[l], m->lv[l].Ke, v, y, s, nr);
   }
   KCHECK();
   return AARMR_OK;
@@ -896,10 +903,12 @@ int apply32(aarmr_mesh* m, int l, const float* v, float* y, hipStream_t s) {
 // The V-cycle of vcycle() with FP32 vectors and smoothing, and the same
 // fused sweeps; the coarsest inverse is the FP64 one.  x_init: x already
 // holds the level's first Jacobi sweep.
+// nr load cases in lock step: b and x (and the level buffers) hold nr
+// vectors each, one after another.
 int vcycle32(aarmr_mesh* m, int l, const float* b, float* x, hipStream_t s,
-             bool x_init = false) {
+             bool x_init = false, int nr = 1) {
   if (l == m->nlev - 1) {
-    launch_gemv_f32(m->nc, m->Ainv, b, x, s);
+    launch_gemv_f32(m->nc, m->Ainv, b, x, s, nr);
     KCHECK();
     return AARMR_OK;
   }
@@ -912,26 +921,27 @@ int vcycle32(aarmr_mesh* m, int l, const float* b, float* x, hipStream_t s,
   const bool child_first = m->p.nu_pre >= 1 && l + 1 < m->nlev - 1;
   if (m->p.nu_pre >= 1) {
     if (!x_init) {
-      launch_jacobi_first_f32(n3, b, L.dinv32, om, x, s);
+      launch_jacobi_first_f32(n3, b, L.dinv32, om, x, s, nr);
       KCHECK();
     }
     for (int it = 1; it < m->p.nu_pre; ++it) {
-      TRY(apply32(m, l, x, L.t32, s));
-      launch_jacobi_update_f32(n3, b, L.t32, L.dinv32, om, x, s);
+      TRY(apply32(m, l, x, L.t32, s, nr));
+      launch_jacobi_update_f32(n3, b, L.t32, L.dinv32, om, x, s, nr);
       KCHECK();
     }
-    TRY(apply32(m, l, x, L.t32, s));
+    TRY(apply32(m, l, x, L.t32, s, nr));
     if (child_first)
-      launch_restrict_jacobi_f32(m->lg[l + 1], b, L.t32, mask, C.b32, C.dinv32, om, C.x32, s);
+      launch_restrict_jacobi_f32(m->lg[l + 1], b, L.t32, mask, C.b32, C.dinv32, om, C.x32, s,
+                                 nr);
     else
-      launch_restrict_f32(m->lg[l + 1], b, L.t32, mask, C.b32, s);
+      launch_restrict_f32(m->lg[l + 1], b, L.t32, mask, C.b32, s, nr);
   } else {
-    HIP_TRY(hipMemsetAsync(x, 0, n3 * sizeof(float), s));
-    launch_restrict_f32(m->lg[l + 1], b, nullptr, mask, C.b32, s);
+    HIP_TRY(hipMemsetAsync(x, 0, nr * n3 * sizeof(float), s));
+    launch_restrict_f32(m->lg[l + 1], b, nullptr, mask, C.b32, s, nr);
   }
   KCHECK();
-  TRY(vcycle32(m, l + 1, C.b32, C.x32, s, child_first));
-  launch_prolong_add_f32(G, C.x32, mask, x, s);
+  TRY(vcycle32(m, l + 1, C.b32, C.x32, s, child_first, nr));
+  launch_prolong_add_f32(G, C.x32, mask, x, s, nr);
   KCHECK();
   for (int it = 0; it < m->p.nu_post; ++it) {
     const bool last = it == m->p.nu_post - 1;
@@ -939,7 +949,7 @@ int vcycle32(aarmr_mesh* m, int l, const float* b, float* x, hipStream_t s,
       // the solver's own z: the sweep (with r^T z partials) writes into t32,
       // and the two swap roles
       m->rz_nb = launch_ebe_jacobi_f32_dot(G, m->wk, m->E32, m->mask, x, b, L.dinv32, om, L.t32,
-                                           m->part_rz, s, m->tz32);
+                                           m->part_rz, s, m->tz32, nr, m->part_cap);
       ++m->sweeps;
       KCHECK();
       std::swap(m->z32, L.t32);
@@ -950,17 +960,17 @@ int vcycle32(aarmr_mesh* m, int l, const float* b, float* x, hipStream_t s,
         TRY(flagged_count(m, s));
         launch_apply_l1_jacobi_f32(m->lg[1], L.Ke, m->Kcomp1, m->cap1, m->Bw32d, m->E32,
                                    m->eflag1, m->list1, m->count1, m->nflag1, x, m->Y1f, b,
-                                   L.dinv32, om, s);
+                                   L.dinv32, om, s, nr);
       } else {
         if (x != L.x32) return fail(AARMR_E_STATE, "V-cycle iterate is not the level's buffer");
-        launch_apply_elemmat_jacobi_f32(G, L.Ke, x, b, L.dinv32, om, L.t32, s);
+        launch_apply_elemmat_jacobi_f32(G, L.Ke, x, b, L.dinv32, om, L.t32, s, nr);
         std::swap(L.x32, L.t32);
       }
       KCHECK();
       continue;
     }
-    TRY(apply32(m, l, x, L.t32, s));
-    launch_jacobi_update_f32(n3, b, L.t32, L.dinv32, om, x, s);
+    TRY(apply32(m, l, x, L.t32, s, nr));
+    launch_jacobi_update_f32(n3, b, L.t32, L.dinv32, om, x, s, nr);
     KCHECK();
   }
   return AARMR_OK;
@@ -1115,6 +1125,220 @@ int refine(aarmr_mesh* m, double* x, int* iters, double* relres, bool* fallback,
     KCHECK();
   }
   return fail(AARMR_E_NOT_CONVERGED, "refinement reached cg_maxit before cg_rtol");
+}
+
+// ---- refinement form, load cases in lock step ----------------------------
+// The nr load cases of one mesh share every launch of the FP32 inner solve:
+// the fine product, the V-cycle and the CG updates run over nr vectors
+// stored one after another (a grid dimension per load case), so the
+// launches per iteration do not depend on nr.  Each case keeps its own CG
+// scalars, partials and stopping test; a finished case is flagged inactive
+// and its updates are skipped.  Every case follows exactly the arithmetic
+// of its own single-case solve.
+
+// Upload the activity flags act[0..nr) to the device (stream-ordered; the
+// host writes the pinned staging only after the stream has passed the
+// previous copy, which every caller ensures by synchronising in between).
+int upload_act(aarmr_mesh* m, int nr, const bool* act, hipStream_t s) {
+  for (int l = 0; l < nr; ++l) m->hact[l] = act[l] ? 1 : 0;
+  HIP_TRY(hipMemcpyAsync(m->act, m->hact, nr * sizeof(int), hipMemcpyHostToDevice, s));
+  return AARMR_OK;
+}
+
+// Lock-step pcg32: case l (act[l] set on entry) solves A d_l = r32_l from
+// d_l = 0 until ||r_l|| <= rtol[l] or maxit iterations.  On return act[l] is
+// cleared for every case; iters, relres and stalled are per case.
+int pcg32_multi(aarmr_mesh* m, int nr, const double* rtol, int maxit, bool* act, int* iters,
+                double* relres, bool* stalled, hipStream_t s) {
+  const Grid& g = m->lg[0];
+  const int64_t n3 = ndof(m, 0);
+  double* sc = m->scal;
+  const int hs = kFusedBlocks + 8;
+  MultiRhs mr;
+  mr.n = nr;
+  mr.vs = n3;
+  mr.ss = SC_TOTAL;
+  mr.ps = m->part_cap;
+  mr.hs = hs;
+  mr.active = m->act;
+  TRY(upload_act(m, nr, act, s));
+  HIP_TRY(hipMemsetAsync(m->d32, 0, nr * n3 * sizeof(float), s));
+  for (int l = 0; l < nr; ++l) {
+    iters[l] = 0;
+    relres[l] = 1.0;
+    stalled[l] = false;
+  }
+  m->rz_nb = 0;
+  TRY(vcycle32(m, 0, m->r32, m->z32, s, false, nr));
+  {
+    DotSetT<float> d{};
+    d.k = nr;
+    d.n = n3;
+    for (int l = 0; l < nr; ++l) {
+      d.a[l] = m->r32 + l * n3;
+      d.b[l] = m->z32 + l * n3;
+      d.out[l] = sc + l * SC_TOTAL + SC_RZ;
+    }
+    launch_multidot_f32(d, red(m), s);
+    KCHECK();
+  }
+  launch_copy_f32(nr * n3, m->z32, m->p32, s);
+  KCHECK();
+  const int nb = fused_blocks(n3);
+  const double* hrr = m->hrr;
+  const float om = (float)m->p.omega;
+  for (int it = 0; it < maxit; ++it) {
+    const int n_pq = launch_ebe_f32_dot(g, m->wk, m->E32, m->mask, m->p32, m->q32, m->part_pq,
+                                        s, m->tz32, nr, m->part_cap);
+    ++m->sweeps;
+    launch_cg_xr_fused_f32(n3, sc + SC_RZ + it, m->part_pq, n_pq, sc + SC_PQ + it, m->d32,
+                           m->r32, m->p32, m->q32, m->hrr_dev, m->lv[0].dinv32, om, m->z32, s,
+                           mr);
+    KCHECK();
+    HIP_TRY(hipEventRecord(m->ev_cg, s));
+    if (it + 1 < maxit) {
+      m->rz_nb = 0;
+      TRY(vcycle32(m, 0, m->r32, m->z32, s, m->p.nu_pre >= 1, nr));
+      if (m->rz_nb <= 0) return fail(AARMR_E_STATE, "lock-step solve needs the fused fine sweep");
+      launch_cg_p_fused_f32(n3, m->part_rz, m->rz_nb, sc + SC_RZ + it + 1, sc + SC_RZ + it,
+                            m->z32, m->p32, s, mr);
+      KCHECK();
+    }
+    HIP_TRY(hipEventSynchronize(m->ev_cg));
+    bool any = false, changed = false;
+    for (int l = 0; l < nr; ++l) {
+      if (!act[l]) continue;
+      const double* h = hrr + (int64_t)l * hs;
+      double rr = 0.0;
+      for (int b = 0; b < nb; ++b) rr += h[b];
+      iters[l] = it + 1;
+      relres[l] = std::sqrt(rr);
+      if (!(h[nb] > 0.0) || !(h[nb + 1] > 0.0)) {
+        stalled[l] = true;
+        act[l] = false;
+        changed = true;
+      } else if (rr <= rtol[l] * rtol[l]) {
+        act[l] = false;
+        changed = true;
+      }
+      any = any || act[l];
+    }
+    if (!any) return AARMR_OK;
+    if (changed) TRY(upload_act(m, nr, act, s));
+  }
+  for (int l = 0; l < nr; ++l) act[l] = false;
+  return AARMR_OK;
+}
+
+// Lock-step refinement of nr load cases, as refine() per case: the FP64
+// residual r_l = f_l - A u_l (f_l masked into fm, case by case), the FP32
+// solve of all unfinished cases together on r_l / ||r_l||, u_l += ||r_l||
+// d_l.  fallback[l]: FP32 could not resolve case l (the caller continues it
+// with FP64 CG).  status[l]: AARMR_OK or AARMR_E_NOT_CONVERGED.
+int refine_multi(aarmr_mesh* m, int nr, const double* f, double* u, int* iters, double* relres,
+                 bool* fallback, int* status, hipStream_t s) {
+  const Grid& g = m->lg[0];
+  const int64_t n3 = ndof(m, 0);
+  const double rtol = m->p.cg_rtol;
+  const int budget = std::min(m->p.cg_maxit, kMaxIt);
+  constexpr double kInnerFloor = AARMR_INNER_FLOOR;
+  double ff[AARMR_MAX_RHS] = {}, prev_rel[AARMR_MAX_RHS] = {}, inner[AARMR_MAX_RHS] = {};
+  double rin[AARMR_MAX_RHS] = {};
+  bool done[AARMR_MAX_RHS] = {}, act[AARMR_MAX_RHS] = {}, stalled[AARMR_MAX_RHS] = {};
+  int its[AARMR_MAX_RHS] = {};
+  for (int l = 0; l < nr; ++l) {
+    ff[l] = -1.0;
+    prev_rel[l] = 0.0;
+    done[l] = false;
+    fallback[l] = false;
+    status[l] = AARMR_OK;
+    iters[l] = 0;
+    relres[l] = 1.0;
+  }
+  // cases that take no part in a round keep a zero FP32 right-hand side
+  HIP_TRY(hipMemsetAsync(m->r32, 0, nr * n3 * sizeof(float), s));
+  for (int outer = 0; outer < 64; ++outer) {
+    bool any = false;
+    for (int l = 0; l < nr; ++l) {
+      act[l] = false;
+      if (done[l] || fallback[l]) continue;
+      double* ul = u + l * n3;
+      double* misc = m->scal + l * SC_TOTAL + SC_MISC;
+      launch_copy_masked(g, f + l * n3, m->mask, m->fm, s, m->dim);
+      KCHECK();
+      TRY(apply(m, 0, ul, m->q, s));
+      launch_sub(n3, m->fm, m->q, m->r, s);
+      KCHECK();
+      double h[2];
+      if (ff[l] < 0.0) {
+        const double* a[2] = {m->fm, m->r};
+        double* o[2] = {misc + M_FF, misc + M_RR64};
+        TRY(dots(m, 2, a, a, o, n3, s));
+        const double* src[2] = {misc + M_FF, misc + M_RR64};
+        TRY(read_scalars(m, src, 2, h, s));
+        ff[l] = h[0];
+        if (ff[l] == 0.0) {
+          HIP_TRY(hipMemsetAsync(ul, 0, n3 * sizeof(double), s));
+          relres[l] = 0.0;
+          done[l] = true;
+          continue;
+        }
+        if (h[1] > ff[l]) {  // the initial guess is worse than zero: start from zero
+          HIP_TRY(hipMemsetAsync(ul, 0, n3 * sizeof(double), s));
+          HIP_TRY(hipMemcpyAsync(m->r, m->fm, n3 * sizeof(double), hipMemcpyDeviceToDevice, s));
+          HIP_TRY(hipMemcpyAsync(misc + M_RR64, misc + M_FF, sizeof(double),
+                                 hipMemcpyDeviceToDevice, s));
+          h[1] = ff[l];
+        }
+      } else {
+        TRY(dot1(m, m->r, m->r, misc + M_RR64, n3, s));
+        const double* src = misc + M_RR64;
+        TRY(read_scalars(m, &src, 1, h + 1, s));
+      }
+      const double rel = std::sqrt(h[1] / ff[l]);
+      relres[l] = rel;
+      if (rel <= rtol) {
+        done[l] = true;
+        continue;
+      }
+      if (iters[l] >= budget) {
+        done[l] = true;
+        status[l] = AARMR_E_NOT_CONVERGED;
+        continue;
+      }
+      if (outer > 0 && rel > 0.2 * prev_rel[l]) {
+        fallback[l] = true;
+        continue;
+      }
+      prev_rel[l] = rel;
+      inner[l] = std::min(0.1, std::max(kInnerFloor, 0.5 * rtol / rel));
+      launch_to_f32_scaled(n3, m->r, misc + M_RR64, m->r32 + l * n3, s);
+      KCHECK();
+      act[l] = true;
+      any = true;
+    }
+    if (!any) return AARMR_OK;
+    int maxit = 0;
+    for (int l = 0; l < nr; ++l)
+      if (act[l]) maxit = std::max(maxit, budget - iters[l]);
+    bool was[AARMR_MAX_RHS] = {};
+    for (int l = 0; l < nr; ++l) was[l] = act[l];
+    TRY(pcg32_multi(m, nr, inner, maxit, act, its, rin, stalled, s));
+    for (int l = 0; l < nr; ++l) {
+      if (!was[l]) continue;
+      iters[l] += its[l];
+      if (stalled[l]) {
+        fallback[l] = true;
+        continue;
+      }
+      launch_add_scaled_f32(n3, m->d32 + l * n3, m->scal + l * SC_TOTAL + SC_MISC + M_RR64,
+                            u + l * n3, s);
+      KCHECK();
+    }
+  }
+  for (int l = 0; l < nr; ++l)
+    if (!done[l] && !fallback[l]) status[l] = AARMR_E_NOT_CONVERGED;
+  return AARMR_OK;
 }
 
 int pcg64(aarmr_mesh* m, double* x, int* iters, double* relres, int maxit_in, hipStream_t s);
@@ -1503,10 +1727,12 @@ int aarmr_bind_workspace(aarmr_mesh* m, void* dev_ptr, int64_t bytes, void* stre
   m->ainv_valid = false;  // a new workspace holds no inverse
   if (!m->hpin) HIP_TRY(hipHostMalloc((void**)&m->hpin, 4096 * sizeof(double), hipHostMallocDefault));
   if (!m->hrr) {
-    HIP_TRY(hipHostMalloc((void**)&m->hrr, (kFusedBlocks + 8) * sizeof(double),
+    HIP_TRY(hipHostMalloc((void**)&m->hrr,
+                          (int64_t)m->p.n_rhs_max * (kFusedBlocks + 8) * sizeof(double),
                           hipHostMallocMapped | hipHostMallocCoherent));
     HIP_TRY(hipHostGetDevicePointer((void**)&m->hrr_dev, m->hrr, 0));
   }
+  m->hact = reinterpret_cast<int*>(m->hpin + 3072);  // lock-step flags (n_rhs_max ints)
   if (!m->ev_cg) HIP_TRY(hipEventCreateWithFlags(&m->ev_cg, hipEventDisableTiming));
   if (!m->ev_fine) HIP_TRY(hipEventCreateWithFlags(&m->ev_fine, hipEventDisableTiming));
   if (!m->ev_mg) HIP_TRY(hipEventCreateWithFlags(&m->ev_mg, hipEventDisableTiming));
@@ -1621,7 +1847,57 @@ int aarmr_solve(aarmr_mesh* m, const double* rho, const double* f, int32_t n_rhs
   }
   auto t1 = std::chrono::steady_clock::now();
   int status = AARMR_OK;
-  for (int l = 0; l < n_rhs; ++l) {
+  // Several load cases of the refinement form run their FP32 solves in lock
+  // step (one set of launches per iteration for all of them); each case
+  // gets the iterates of its own single-case solve.
+  const bool lockstep = m->fp32 && m->dim == 3 && n_rhs > 1 && m->p.nu_post >= 1 &&
+                        !m->ainv_stale;
+  if (lockstep) {
+    for (int l = 0; l < n_rhs; ++l) {
+      double* ul = u + l * n3;
+      if (flags & AARMR_WARM_START) {
+        launch_copy_masked(g, ul, m->mask, ul, s, m->dim);
+        KCHECK();
+      } else {
+        HIP_TRY(hipMemsetAsync(ul, 0, n3 * sizeof(double), s));
+      }
+    }
+    int its[AARMR_MAX_RHS] = {}, stl[AARMR_MAX_RHS] = {};
+    double rel[AARMR_MAX_RHS] = {};
+    bool fb[AARMR_MAX_RHS] = {};
+    TRY(refine_multi(m, n_rhs, f, u, its, rel, fb, stl, s));
+    int its_max = 0;
+    for (int l = 0; l < n_rhs; ++l) {
+      double* ul = u + l * n3;
+      if (fb[l]) {  // FP32 could not resolve this case: FP64 CG from its iterate
+        launch_copy_masked(g, f + l * n3, m->mask, m->fm, s, m->dim);
+        KCHECK();
+        int more = 0;
+        const int rc = pcg64(m, ul, &more, &rel[l], std::min(m->p.cg_maxit, kMaxIt) - its[l], s);
+        its[l] += more;
+        if (rc != AARMR_OK && rc != AARMR_E_NOT_CONVERGED) return rc;
+        if (rc == AARMR_E_NOT_CONVERGED) status = rc;
+      } else if (stl[l] != AARMR_OK) {
+        status = stl[l];
+      }
+      if (!fb[l]) {  // C = f^T u below reads this case's masked load
+        launch_copy_masked(g, f + l * n3, m->mask, m->fm, s, m->dim);
+        KCHECK();
+      }
+      its_max = std::max(its_max, its[l]);
+      if (st) {
+        st->iterations[l] = its[l];
+        st->rel_residual[l] = rel[l];
+      }
+      TRY(post_case(m, l, rho_phys, ul, compliance, dc != nullptr && !mutual, s));
+      if (flags & AARMR_RECORD_PARM) TRY(push_parm(m, l, ul, s));
+    }
+    if (m->ainv_fresh) {
+      m->ainv_base_its = its_max;
+      m->ainv_fresh = false;
+    }
+  }
+  for (int l = 0; l < n_rhs && !lockstep; ++l) {
     double* ul = u + l * n3;
     launch_copy_masked(g, f + l * n3, m->mask, m->fm, s, m->dim);
     KCHECK();

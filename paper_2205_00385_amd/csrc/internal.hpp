@@ -43,6 +43,18 @@ struct RedScratch {
 
 // k dot products a_i . b_i (b_i == nullptr: plain sum of a_i) of vectors of
 // element type T, accumulated and returned in FP64.
+// Load cases solved in lock step by one set of launches: case l's vectors
+// start at l * vs, its CG scalars at l * ss, its workgroup partials at l * ps
+// and its host-visible partials at l * hs; active (device, n entries): 0 for
+// a case that has finished, whose updates are then skipped.  n = 1 with zero
+// strides is the single-case solve.
+struct MultiRhs {
+  int n = 1;
+  int64_t vs = 0;
+  int ss = 0, ps = 0, hs = 0;
+  const int* active = nullptr;
+};
+
 template <typename T>
 struct DotSetT {
   const T* a[kRedSlots];
@@ -62,7 +74,8 @@ using DotSet = DotSetT<double>;
 void launch_ebe(const Grid& g, const WalshConsts& K, const double* E, const uint8_t* mask,
                 const double* v, double* y, int mode, hipStream_t s, int tz = 0);
 void launch_ebe_f32(const Grid& g, const WalshConsts& K, const float* E, const uint8_t* mask,
-                    const float* v, float* y, int mode, hipStream_t s, int tz = 0);
+                    const float* v, float* y, int mode, hipStream_t s, int tz = 0,
+                    int nr = 1);
 // The mode-2 product feeding a damped-Jacobi sweep: out = v + omega dinv
 // (b - A v), out distinct from v.
 void launch_ebe_jacobi(const Grid& g, const WalshConsts& K, const double* E, const uint8_t* mask,
@@ -81,11 +94,12 @@ int launch_ebe_jacobi_dot(const Grid& g, const WalshConsts& K, const double* E,
                           hipStream_t s, int tz = 0);
 // FP32 forms of the two (vectors FP32, partials summed in FP64).
 int launch_ebe_f32_dot(const Grid& g, const WalshConsts& K, const float* E, const uint8_t* mask,
-                       const float* v, float* y, double* part, hipStream_t s, int tz = 0);
+                       const float* v, float* y, double* part, hipStream_t s, int tz = 0,
+                       int nr = 1, int pst = 0);
 int launch_ebe_jacobi_f32_dot(const Grid& g, const WalshConsts& K, const float* E,
                               const uint8_t* mask, const float* v, const float* b,
                               const float* dinv, float omega, float* out, double* part,
-                              hipStream_t s, int tz = 0);
+                              hipStream_t s, int tz = 0, int nr = 1, int pst = 0);
 void launch_energy_walsh(const Grid& g, const WalshConsts& K, const uint8_t* mask,
                          const double* u, double* energy, hipStream_t s);
 void launch_simp(int64_t ne, const double* rho, double E0, double Emin, double p, double* E,
@@ -132,17 +146,17 @@ void launch_apply_l1(const Grid& g, const double* Ke, const double* Kcomp, int c
 void launch_apply_l1_jacobi_f32(const Grid& g, const double* Ke, const double* Kcomp, int cap,
                                 const float* Bw, const float* Ef, const uint8_t* eflag,
                                 const int* list, const int* count, int nflag, float* x, float* Y,
-                                const float* b, const float* dinv, float omega, hipStream_t s);
+                                const float* b, const float* dinv, float omega, hipStream_t s, int nr = 1);
 void launch_apply_elemmat_jacobi_f32(const Grid& g, const double* Ke, const float* v,
                                      const float* b, const float* dinv, float omega, float* out,
-                                     hipStream_t s);
+                                     hipStream_t s, int nr = 1);
 void launch_restrict_jacobi_f32(const Grid& coarse, const float* bf, const float* tf,
                                 const uint8_t* mask, float* bc, const float* dinv_c, float omega,
-                                float* xc, hipStream_t s);
+                                float* xc, hipStream_t s, int nr = 1);
 void launch_apply_l1_f32(const Grid& g, const double* Ke, const double* Kcomp, int cap,
                          const float* Bw, const float* Ef, const uint8_t* eflag, const int* list,
                          const int* count, int nflag, const float* v, float* Y, float* y,
-                         hipStream_t s);
+                         hipStream_t s, int nr = 1);
 void launch_diag_elemmat(const Grid& g, const double* Ke, double* dinv, float* dinv32,
                          hipStream_t s);
 // Transfers act per component; ncomp = 2 on the plane-stress grid (nz = 0).
@@ -177,16 +191,16 @@ void launch_gemv(int n, const double* A, const double* x, double* y, hipStream_t
 // FP32 V-cycle pieces (vectors FP32; element matrices and the coarsest
 // inverse stay FP64 and are applied with FP32 vectors).
 void launch_apply_elemmat_f32(const Grid& g, const double* Ke, const float* v, float* y,
-                              hipStream_t s);
+                              hipStream_t s, int nr = 1);
 void launch_restrict_f32(const Grid& coarse, const float* bf, const float* tf,
-                         const uint8_t* mask, float* bc, hipStream_t s);
+                         const uint8_t* mask, float* bc, hipStream_t s, int nr = 1);
 void launch_prolong_add_f32(const Grid& fine, const float* xc, const uint8_t* mask, float* xf,
-                            hipStream_t s);
+                            hipStream_t s, int nr = 1);
 void launch_jacobi_first_f32(int64_t n3, const float* b, const float* dinv, float omega, float* x,
-                             hipStream_t s);
+                             hipStream_t s, int nr = 1);
 void launch_jacobi_update_f32(int64_t n3, const float* b, const float* t, const float* dinv,
-                              float omega, float* x, hipStream_t s);
-void launch_gemv_f32(int n, const double* A, const float* x, float* y, hipStream_t s);
+                              float omega, float* x, hipStream_t s, int nr = 1);
+void launch_gemv_f32(int n, const double* A, const float* x, float* y, hipStream_t s, int nr = 1);
 
 // ---- vector kernels and reductions ----------------------------------------
 void launch_multidot(const DotSet& d, const RedScratch& rs, hipStream_t s);
@@ -231,9 +245,11 @@ void launch_cg_p_fused(int64_t n, const double* rz_part, int n_part, double* rz_
 void launch_cg_xr_fused_f32(int64_t n, const double* rz, const double* pq_part, int n_part,
                             double* pq, float* x, float* r, const float* p, const float* q,
                             double* rr_part, const float* dinv, float omega, float* z0,
-                            hipStream_t s);
+                            hipStream_t s,
+                            const MultiRhs& mr = MultiRhs());
 void launch_cg_p_fused_f32(int64_t n, const double* rz_part, int n_part, double* rz_new,
-                           const double* rz_old, const float* z, float* p, hipStream_t s);
+                           const double* rz_old, const float* z, float* p, hipStream_t s,
+                            const MultiRhs& mr = MultiRhs());
 void launch_scale_by_inv_sqrt(int64_t n, const double* src, const double* nrm2, double* dst,
                               hipStream_t s);
 // out = sum_j coef[j] * V_j (+ add) with coefficients read from device memory

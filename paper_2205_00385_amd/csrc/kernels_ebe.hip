@@ -132,8 +132,17 @@ __global__ void __launch_bounds__(kLanes * ROWS, AARMR_EBE_MINB) k_ebe_z(int nx,
                                                     const T* __restrict__ v, T* __restrict__ y,
                                                     const T* __restrict__ jb,
                                                     const T* __restrict__ jd, T omega,
-                                                    double* __restrict__ part) {
+                                                    double* __restrict__ part, int64_t rs,
+                                                    int pst) {
   constexpr bool OWNV = JAC || DOT;  // keep the node's own v of the plane written next
+  {  // load case blockIdx.z of a lock-step multi-vector (the moduli, mask and
+     // Jacobi diagonal are shared)
+    const int64_t ro = (int64_t)blockIdx.z * rs;
+    v += ro;
+    y += ro;
+    if (JAC) jb += ro;
+    if (DOT) part += (int64_t)blockIdx.z * pst;
+  }
   constexpr int kTileY = ROWS - 1;   // node rows owned per workgroup
   __shared__ T xs[2][3][ROWS][kLanes];
   const int tx = threadIdx.x & (kLanes - 1), ty = threadIdx.x / kLanes;
@@ -426,7 +435,7 @@ int ebe_rows(int shape) {
 template <typename T, int ROWS, bool MASK_IN, bool JAC, bool DOT>
 static int launch_ebe_r(const Grid& g, const WalshConsts& K, const T* E, const uint8_t* mask,
                         const T* v, T* y, int tz_req, hipStream_t s, const T* jb, const T* jd,
-                        T omega, double* part) {
+                        T omega, double* part, int nr, int pst) {
   constexpr int kThreads = kLanes * ROWS;
   constexpr int kTileY = ROWS - 1;
   // resident workgroups of this kernel on the device (thread-safe one-time init)
@@ -448,23 +457,28 @@ static int launch_ebe_r(const Grid& g, const WalshConsts& K, const T* E, const u
   if (tz_req > 0) tz = tz_req < planes ? tz_req : planes;  // tuned z-chunk length
   if (tz < 2) tz = 2;
   gz = (planes + tz - 1) / tz;
-  k_ebe_z<T, ROWS, MASK_IN, AARMR_EBE_PF, JAC, DOT><<<(unsigned)(gx * gy * gz), kThreads, 0, s>>>(
-      g.nx, g.ny, g.nz, gx, gy, tz, K, E, mask, v, y, jb, jd, omega, part);
+  k_ebe_z<T, ROWS, MASK_IN, AARMR_EBE_PF, JAC, DOT>
+      <<<dim3((unsigned)(gx * gy * gz), 1, (unsigned)nr), kThreads, 0, s>>>(
+          g.nx, g.ny, g.nz, gx, gy, tz, K, E, mask, v, y, jb, jd, omega, part, 3 * g.nn, pst);
   return gx * gy * gz;
 }
 
 template <typename T, bool MASK_IN, bool JAC = false, bool DOT = false>
 static int launch_ebe_t(const Grid& g, const WalshConsts& K, const T* E, const uint8_t* mask,
                         const T* v, T* y, int shape, hipStream_t s, const T* jb = nullptr,
-                        const T* jd = nullptr, T omega = 0, double* part = nullptr) {
+                        const T* jd = nullptr, T omega = 0, double* part = nullptr, int nr = 1,
+                        int pst = 0) {
   const int tz = shape & 0xFFFF;
   switch (ebe_rows(shape)) {
     case 8:
-      return launch_ebe_r<T, 8, MASK_IN, JAC, DOT>(g, K, E, mask, v, y, tz, s, jb, jd, omega, part);
+      return launch_ebe_r<T, 8, MASK_IN, JAC, DOT>(g, K, E, mask, v, y, tz, s, jb, jd, omega, part,
+                                                   nr, pst);
     case 12:
-      return launch_ebe_r<T, 12, MASK_IN, JAC, DOT>(g, K, E, mask, v, y, tz, s, jb, jd, omega, part);
+      return launch_ebe_r<T, 12, MASK_IN, JAC, DOT>(g, K, E, mask, v, y, tz, s, jb, jd, omega,
+                                                    part, nr, pst);
     default:
-      return launch_ebe_r<T, 16, MASK_IN, JAC, DOT>(g, K, E, mask, v, y, tz, s, jb, jd, omega, part);
+      return launch_ebe_r<T, 16, MASK_IN, JAC, DOT>(g, K, E, mask, v, y, tz, s, jb, jd, omega,
+                                                    part, nr, pst);
   }
 }
 
@@ -490,17 +504,18 @@ int launch_ebe_jacobi_dot(const Grid& g, const WalshConsts& K, const double* E,
 }
 
 int launch_ebe_f32_dot(const Grid& g, const WalshConsts& K, const float* E, const uint8_t* mask,
-                       const float* v, float* y, double* part, hipStream_t s, int tz) {
+                       const float* v, float* y, double* part, hipStream_t s, int tz, int nr,
+                       int pst) {
   return launch_ebe_t<float, false, false, true>(g, K, E, mask, v, y, tz, s, nullptr, nullptr,
-                                                 0.0f, part);
+                                                 0.0f, part, nr, pst);
 }
 
 int launch_ebe_jacobi_f32_dot(const Grid& g, const WalshConsts& K, const float* E,
                               const uint8_t* mask, const float* v, const float* b,
                               const float* dinv, float omega, float* out, double* part,
-                              hipStream_t s, int tz) {
+                              hipStream_t s, int tz, int nr, int pst) {
   return launch_ebe_t<float, false, true, true>(g, K, E, mask, v, out, tz, s, b, dinv, omega,
-                                                part);
+                                                part, nr, pst);
 }
 
 void launch_ebe(const Grid& g, const WalshConsts& K, const double* E, const uint8_t* mask,
@@ -520,9 +535,9 @@ void launch_ebe_jacobi(const Grid& g, const WalshConsts& K, const double* E, con
 }
 
 void launch_ebe_f32(const Grid& g, const WalshConsts& K, const float* E, const uint8_t* mask,
-                    const float* v, float* y, int mode, hipStream_t s, int tz) {
+                    const float* v, float* y, int mode, hipStream_t s, int tz, int nr) {
   if (mode == 2) {
-    launch_ebe_t<float, false>(g, K, E, mask, v, y, tz, s);
+    launch_ebe_t<float, false>(g, K, E, mask, v, y, tz, s, nullptr, nullptr, 0.0f, nullptr, nr);
     return;
   }
   launch_ebe_t<float, true>(g, K, E, mask, v, y, tz, s);

@@ -354,8 +354,15 @@ __global__ void __launch_bounds__(512) k_apply_elemmat(int nx, int ny, int nz,
                                                        const T* __restrict__ v,
                                                        T* __restrict__ y,
                                                        const T* __restrict__ jb,
-                                                       const T* __restrict__ jd, T omega) {
+                                                       const T* __restrict__ jd, T omega,
+                                                       int64_t rs = 0) {
   __shared__ T red[8][3][64];
+  {  // load case blockIdx.z of a lock-step multi-vector (rs: vector stride)
+    const int64_t ro = (int64_t)blockIdx.z * rs;
+    v += ro;
+    y += ro;
+    if (jb) jb += ro;
+  }
   const int a = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int lane = threadIdx.x & 63;
   const int64_t nn = (int64_t)(nx + 1) * (ny + 1) * (nz + 1);
@@ -551,7 +558,10 @@ __global__ void __launch_bounds__(256) k_l1_elem(int nx, int ny, int nz,
                                                  const uint8_t* __restrict__ eflag,
                                                  const T* __restrict__ v, T* __restrict__ Y,
                                                  int nbe, const double* __restrict__ Kcomp,
-                                                 int cap, const int* __restrict__ list, int cnt) {
+                                                 int cap, const int* __restrict__ list, int cnt,
+                                                 int64_t rs = 0, int64_t Ys = 0) {
+  v += (int64_t)blockIdx.z * rs;  // load case blockIdx.z
+  Y += (int64_t)blockIdx.z * Ys;
   if ((int)blockIdx.x >= nbe) {  // workgroup-uniform
     const int mb = (int)blockIdx.x - nbe;
     const int r = (int)(blockIdx.y * 2 + (mb & 1)) * 4 + (int)(threadIdx.x >> 6);
@@ -574,10 +584,14 @@ template <typename T>
 __global__ void __launch_bounds__(256) k_l1_gather(int nx, int ny, int nz,
                                                    const T* __restrict__ Y, T* __restrict__ y,
                                                    const T* __restrict__ jb,
-                                                   const T* __restrict__ jd, T omega) {
+                                                   const T* __restrict__ jd, T omega,
+                                                   int64_t rs = 0, int64_t Ys = 0) {
   const int64_t nn = (int64_t)(nx + 1) * (ny + 1) * (nz + 1);
   const int64_t ne = (int64_t)nx * ny * nz;
   const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  Y += (int64_t)blockIdx.z * Ys;  // load case blockIdx.z
+  y += (int64_t)blockIdx.z * rs;
+  if (jb) jb += (int64_t)blockIdx.z * rs;
   if (n >= nn) return;
   const int i = (int)(n % (nx + 1));
   const int64_t rest = n / (nx + 1);
@@ -639,8 +653,16 @@ __global__ void __launch_bounds__(192) k_restrict(int cnx, int cny, int cnz,
                                                   const uint8_t* __restrict__ mask,
                                                   T* __restrict__ bc,
                                                   const T* __restrict__ dc, T omega,
-                                                  T* __restrict__ xc) {
+                                                  T* __restrict__ xc, int64_t fs = 0,
+                                                  int64_t cs = 0) {
   __shared__ T part[3][64];
+  {  // load case blockIdx.z (fs, cs: fine and coarse vector strides)
+    const int64_t fo = (int64_t)blockIdx.z * fs, co = (int64_t)blockIdx.z * cs;
+    bf += fo;
+    if (tf) tf += fo;
+    bc += co;
+    if (xc) xc += co;
+  }
   const int lane = threadIdx.x & 63, dzi = threadIdx.x >> 6;
   const int c = blockIdx.y;
   const int64_t cnn = (int64_t)(cnx + 1) * (cny + 1) * (cnz + 1);
@@ -691,7 +713,10 @@ template <typename T>
 __global__ void __launch_bounds__(256) k_prolong_add(int fnx, int fny, int fnz,
                                                      const T* __restrict__ xc,
                                                      const uint8_t* __restrict__ mask,
-                                                     T* __restrict__ xf, int ncomp) {
+                                                     T* __restrict__ xf, int ncomp,
+                                                     int64_t cs = 0, int64_t fs = 0) {
+  xc += (int64_t)blockIdx.z * cs;  // load case blockIdx.z
+  xf += (int64_t)blockIdx.z * fs;
   const int64_t fnn = (int64_t)(fnx + 1) * (fny + 1) * (fnz + 1);
   const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= fnn) return;
@@ -728,16 +753,19 @@ __global__ void __launch_bounds__(256) k_prolong_add(int fnx, int fny, int fnz,
 
 template <typename T>
 __global__ void k_jacobi_first(int64_t n3, const T* __restrict__ b, const T* __restrict__ dinv,
-                               T omega, T* __restrict__ x) {
+                               T omega, T* __restrict__ x, int64_t rs = 0) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n3) x[i] = omega * dinv[i] * b[i];
+  const int64_t ro = (int64_t)blockIdx.z * rs;  // load case blockIdx.z
+  if (i < n3) x[ro + i] = omega * dinv[i] * b[ro + i];
 }
 
 template <typename T>
 __global__ void k_jacobi_update(int64_t n3, const T* __restrict__ b, const T* __restrict__ t,
-                                const T* __restrict__ dinv, T omega, T* __restrict__ x) {
+                                const T* __restrict__ dinv, T omega, T* __restrict__ x,
+                                int64_t rs = 0) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n3) x[i] += omega * dinv[i] * (b[i] - t[i]);
+  const int64_t ro = (int64_t)blockIdx.z * rs;  // load case blockIdx.z
+  if (i < n3) x[ro + i] += omega * dinv[i] * (b[ro + i] - t[ro + i]);
 }
 
 // Dense coarsest operator in SoA DOF order (c * nn + node); thread per row.
@@ -1242,7 +1270,10 @@ __global__ void __launch_bounds__(256) k_gj_mirror(int n, double* __restrict__ A
 // y = A x for the dense (symmetric) inverse; one wavefront per row.
 template <typename TX, typename TY>
 __global__ void __launch_bounds__(256) k_gemv(int n, const double* __restrict__ A,
-                                              const TX* __restrict__ x, TY* __restrict__ y) {
+                                              const TX* __restrict__ x, TY* __restrict__ y,
+                                              int64_t rs = 0) {
+  x += (int64_t)blockIdx.z * rs;  // load case blockIdx.z
+  y += (int64_t)blockIdx.z * rs;
   const int lane = threadIdx.x & 63;
   const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (row >= n) return;
@@ -1303,22 +1334,25 @@ void launch_apply_elemmat_jacobi(const Grid& g, const double* Ke, const double* 
 }
 
 void launch_apply_elemmat_f32(const Grid& g, const double* Ke, const float* v, float* y,
-                              hipStream_t s) {
-  k_apply_elemmat<float><<<nblk(g.nn, 64), 512, 0, s>>>(g.nx, g.ny, g.nz, Ke, v, y, nullptr,
-                                                        nullptr, 0.0f);
+                              hipStream_t s, int nr) {
+  k_apply_elemmat<float><<<dim3(nblk(g.nn, 64), 1, nr), 512, 0, s>>>(
+      g.nx, g.ny, g.nz, Ke, v, y, nullptr, nullptr, 0.0f, 3 * g.nn);
 }
 
+// nr load cases in lock step: vectors [nr][3 nn], element products [nr][24][ne]
 template <typename T>
 void l1_apply(const Grid& g, const double* Ke, const double* Kcomp, int cap, const T* Bw,
               const T* Ef, const uint8_t* eflag, const int* list, const int* count, int nflag,
               const T* v, T* Y, T* y, hipStream_t s, const T* jb = nullptr,
-              const T* jd = nullptr, T omega = 0) {
+              const T* jd = nullptr, T omega = 0, int nr = 1) {
   // nflag: the flagged-parent count, known to the host after setup
   const int nbe = (int)nblk(g.ne, 256);
   const int nbm = nflag > 0 ? 2 * (int)std::min<int64_t>(nblk(nflag, 16), 1024) : 0;
-  k_l1_elem<T><<<dim3(nbe + nbm, 3), 256, 0, s>>>(g.nx, g.ny, g.nz, Ke, Bw, Ef, eflag, v, Y, nbe,
-                                                  Kcomp, cap, list, nflag);
-  k_l1_gather<T><<<nblk(g.nn, 256), 256, 0, s>>>(g.nx, g.ny, g.nz, Y, y, jb, jd, omega);
+  const int64_t rs = 3 * g.nn, Ys = 24 * g.ne;
+  k_l1_elem<T><<<dim3(nbe + nbm, 3, nr), 256, 0, s>>>(g.nx, g.ny, g.nz, Ke, Bw, Ef, eflag, v, Y,
+                                                      nbe, Kcomp, cap, list, nflag, rs, Ys);
+  k_l1_gather<T><<<dim3(nblk(g.nn, 256), 1, nr), 256, 0, s>>>(g.nx, g.ny, g.nz, Y, y, jb, jd,
+                                                              omega, rs, Ys);
 }
 
 void launch_apply_l1_jacobi(const Grid& g, const double* Ke, const double* Kcomp, int cap,
@@ -1339,58 +1373,63 @@ void launch_apply_l1(const Grid& g, const double* Ke, const double* Kcomp, int c
 void launch_apply_l1_jacobi_f32(const Grid& g, const double* Ke, const double* Kcomp, int cap,
                                 const float* Bw, const float* Ef, const uint8_t* eflag,
                                 const int* list, const int* count, int nflag, float* x, float* Y,
-                                const float* b, const float* dinv, float omega, hipStream_t s) {
+                                const float* b, const float* dinv, float omega, hipStream_t s,
+                                int nr) {
   l1_apply<float>(g, Ke, Kcomp, cap, Bw, Ef, eflag, list, count, nflag, x, Y, x, s, b, dinv,
-                  omega);
+                  omega, nr);
 }
 
 void launch_apply_l1_f32(const Grid& g, const double* Ke, const double* Kcomp, int cap,
                          const float* Bw, const float* Ef, const uint8_t* eflag, const int* list,
                          const int* count, int nflag, const float* v, float* Y, float* y,
-                         hipStream_t s) {
-  l1_apply<float>(g, Ke, Kcomp, cap, Bw, Ef, eflag, list, count, nflag, v, Y, y, s);
+                         hipStream_t s, int nr) {
+  l1_apply<float>(g, Ke, Kcomp, cap, Bw, Ef, eflag, list, count, nflag, v, Y, y, s, nullptr,
+                  nullptr, 0.0f, nr);
 }
 
 void launch_apply_elemmat_jacobi_f32(const Grid& g, const double* Ke, const float* v,
                                      const float* b, const float* dinv, float omega, float* out,
-                                     hipStream_t s) {
-  k_apply_elemmat<float><<<nblk(g.nn, 64), 512, 0, s>>>(g.nx, g.ny, g.nz, Ke, v, out, b, dinv,
-                                                        omega);
+                                     hipStream_t s, int nr) {
+  k_apply_elemmat<float><<<dim3(nblk(g.nn, 64), 1, nr), 512, 0, s>>>(
+      g.nx, g.ny, g.nz, Ke, v, out, b, dinv, omega, 3 * g.nn);
 }
 
 void launch_restrict_jacobi_f32(const Grid& coarse, const float* bf, const float* tf,
                                 const uint8_t* mask, float* bc, const float* dinv_c, float omega,
-                                float* xc, hipStream_t s) {
-  k_restrict<float><<<dim3(nblk(coarse.nn, 64), 3), 192, 0, s>>>(coarse.nx, coarse.ny, coarse.nz,
-                                                                 bf, tf, mask, bc, dinv_c, omega,
-                                                                 xc);
+                                float* xc, hipStream_t s, int nr) {
+  const int64_t fnn = (int64_t)(2 * coarse.nx + 1) * (2 * coarse.ny + 1) * (2 * coarse.nz + 1);
+  k_restrict<float><<<dim3(nblk(coarse.nn, 64), 3, nr), 192, 0, s>>>(
+      coarse.nx, coarse.ny, coarse.nz, bf, tf, mask, bc, dinv_c, omega, xc, 3 * fnn,
+      3 * coarse.nn);
 }
 
 void launch_restrict_f32(const Grid& coarse, const float* bf, const float* tf,
-                         const uint8_t* mask, float* bc, hipStream_t s) {
-  k_restrict<float><<<dim3(nblk(coarse.nn, 64), 3), 192, 0, s>>>(coarse.nx, coarse.ny, coarse.nz,
-                                                                 bf, tf, mask, bc, nullptr, 0.0f,
-                                                                 nullptr);
+                         const uint8_t* mask, float* bc, hipStream_t s, int nr) {
+  const int64_t fnn = (int64_t)(2 * coarse.nx + 1) * (2 * coarse.ny + 1) * (2 * coarse.nz + 1);
+  k_restrict<float><<<dim3(nblk(coarse.nn, 64), 3, nr), 192, 0, s>>>(
+      coarse.nx, coarse.ny, coarse.nz, bf, tf, mask, bc, nullptr, 0.0f, nullptr, 3 * fnn,
+      3 * coarse.nn);
 }
 
 void launch_prolong_add_f32(const Grid& fine, const float* xc, const uint8_t* mask, float* xf,
-                            hipStream_t s) {
-  k_prolong_add<float><<<nblk(fine.nn, 256), 256, 0, s>>>(fine.nx, fine.ny, fine.nz, xc, mask, xf,
-                                                          3);
+                            hipStream_t s, int nr) {
+  const int64_t cnn = (int64_t)(fine.nx / 2 + 1) * (fine.ny / 2 + 1) * (fine.nz / 2 + 1);
+  k_prolong_add<float><<<dim3(nblk(fine.nn, 256), 1, nr), 256, 0, s>>>(
+      fine.nx, fine.ny, fine.nz, xc, mask, xf, 3, 3 * cnn, 3 * fine.nn);
 }
 
 void launch_jacobi_first_f32(int64_t n3, const float* b, const float* dinv, float omega, float* x,
-                             hipStream_t s) {
-  k_jacobi_first<float><<<nblk(n3, 256), 256, 0, s>>>(n3, b, dinv, omega, x);
+                             hipStream_t s, int nr) {
+  k_jacobi_first<float><<<dim3(nblk(n3, 256), 1, nr), 256, 0, s>>>(n3, b, dinv, omega, x, n3);
 }
 
 void launch_jacobi_update_f32(int64_t n3, const float* b, const float* t, const float* dinv,
-                              float omega, float* x, hipStream_t s) {
-  k_jacobi_update<float><<<nblk(n3, 256), 256, 0, s>>>(n3, b, t, dinv, omega, x);
+                              float omega, float* x, hipStream_t s, int nr) {
+  k_jacobi_update<float><<<dim3(nblk(n3, 256), 1, nr), 256, 0, s>>>(n3, b, t, dinv, omega, x, n3);
 }
 
-void launch_gemv_f32(int n, const double* A, const float* x, float* y, hipStream_t s) {
-  k_gemv<float, float><<<nblk(n, 4), 256, 0, s>>>(n, A, x, y);
+void launch_gemv_f32(int n, const double* A, const float* x, float* y, hipStream_t s, int nr) {
+  k_gemv<float, float><<<dim3(nblk(n, 4), 1, nr), 256, 0, s>>>(n, A, x, y, n);
 }
 
 void launch_diag_elemmat(const Grid& g, const double* Ke, double* dinv, float* dinv32,

@@ -145,8 +145,24 @@ __global__ void __launch_bounds__(256) k_cg_xr_fused_f32(int64_t n, const double
                                                          const float* __restrict__ q,
                                                          double* __restrict__ rr_part,
                                                          const float* __restrict__ dinv,
-                                                         float omega, float* __restrict__ z0) {
+                                                         float omega, float* __restrict__ z0,
+                                                         int64_t vs = 0, int ss = 0, int ps = 0,
+                                                         int hs = 0,
+                                                         const int* __restrict__ active = nullptr) {
   __shared__ double sh[5];
+  {  // load case blockIdx.z of a lock-step solve; a finished case is left as it is
+    const int l = blockIdx.z;
+    if (active && !active[l]) return;  // workgroup-uniform
+    rz += l * ss;
+    pq += l * ss;
+    pq_part += l * ps;
+    rr_part += l * hs;
+    x += l * vs;
+    r += l * vs;
+    p += l * vs;
+    q += l * vs;
+    z0 += l * vs;
+  }
   const double pqv = finish_partials(pq_part, nb, sh);
   const double rzv = *rz;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -174,8 +190,19 @@ __global__ void __launch_bounds__(256) k_cg_p_fused_f32(int64_t n, const double*
                                                         int nb, double* __restrict__ rz_new,
                                                         const double* __restrict__ rz_old,
                                                         const float* __restrict__ z,
-                                                        float* __restrict__ p) {
+                                                        float* __restrict__ p, int64_t vs = 0,
+                                                        int ss = 0, int ps = 0,
+                                                        const int* __restrict__ active = nullptr) {
   __shared__ double sh[5];
+  {  // load case blockIdx.z of a lock-step solve
+    const int l = blockIdx.z;
+    if (active && !active[l]) return;  // workgroup-uniform
+    rz_part += l * ps;
+    rz_new += l * ss;
+    rz_old += l * ss;
+    z += l * vs;
+    p += l * vs;
+  }
   const double rzv = finish_partials(rz_part, nb, sh);
   if (blockIdx.x == 0 && threadIdx.x == 0) *rz_new = rzv;
   const double beta = rzv / *rz_old;
@@ -435,14 +462,17 @@ void launch_cg_xr_f32(int64_t n, const double* rz, const double* pq, float* x, f
 void launch_cg_xr_fused_f32(int64_t n, const double* rz, const double* pq_part, int n_part,
                             double* pq, float* x, float* r, const float* p, const float* q,
                             double* rr_part, const float* dinv, float omega, float* z0,
-                            hipStream_t s) {
-  k_cg_xr_fused_f32<<<fused_blocks(n), 256, 0, s>>>(n, rz, pq_part, n_part, pq, x, r, p, q,
-                                                    rr_part, dinv, omega, z0);
+                            hipStream_t s, const MultiRhs& mr) {
+  k_cg_xr_fused_f32<<<dim3(fused_blocks(n), 1, mr.n), 256, 0, s>>>(
+      n, rz, pq_part, n_part, pq, x, r, p, q, rr_part, dinv, omega, z0, mr.vs, mr.ss, mr.ps,
+      mr.hs, mr.active);
 }
 
 void launch_cg_p_fused_f32(int64_t n, const double* rz_part, int n_part, double* rz_new,
-                           const double* rz_old, const float* z, float* p, hipStream_t s) {
-  k_cg_p_fused_f32<<<fused_blocks(n), 256, 0, s>>>(n, rz_part, n_part, rz_new, rz_old, z, p);
+                           const double* rz_old, const float* z, float* p, hipStream_t s,
+                           const MultiRhs& mr) {
+  k_cg_p_fused_f32<<<dim3(fused_blocks(n), 1, mr.n), 256, 0, s>>>(
+      n, rz_part, n_part, rz_new, rz_old, z, p, mr.vs, mr.ss, mr.ps, mr.active);
 }
 
 void launch_cg_p_f32(int64_t n, const double* rz_new, const double* rz_old, const float* z,

@@ -20,6 +20,9 @@ Scheduling:
   its memory admitted) as soon as it is free, so requests that arrive while
   others are on the GPU start as slots free up, and their kernels overlap on
   the device.  The library calls release the GIL.
+- A repeat design also keeps the family's coarsest multigrid inverse
+  (AARMR_REUSE_COARSEST): it is rebuilt only when the solves it serves need
+  markedly more iterations than right after it was built.
 - The requests of one family run one at a time in arrival order, so each
   result depends only on its family's request sequence, not on the other
   requests in flight: with no eviction in between, it is bit for bit the
@@ -100,10 +103,14 @@ class AnalysisServer:
     """Continuous-batching analysis server (see the module docstring).
 
     hbm_budget: bytes of workspace the resident families may hold.
-    precision: aarmr.FP64 or aarmr.FP32_REFINE for every solve."""
+    precision: aarmr.FP64 or aarmr.FP32_REFINE for every solve.
+    ca_tol: eq. (29)'s acceptance bound.  Measured on the 96x48x48
+    cantilever, a reduced-model step's compliance error grows as about
+    0.07 eps^2 (3.3e-8 at eps = 7.5e-4, 3.1e-7 at 2.2e-3, 3.2e-6 at 7e-3),
+    so eps < 2e-3 keeps accepted steps within the 1e-6 compliance bar."""
 
     def __init__(self, hbm_budget: int, n_workers: int = 4, precision: int = aarmr.FP32_REFINE,
-                 ca_tol: float = 1e-4, Ns: int = 2, Nm: int = 4, cg_rtol: float = 1e-8,
+                 ca_tol: float = 2e-3, Ns: int = 2, Nm: int = 4, cg_rtol: float = 1e-8,
                  keep_u: bool = False):
         self.budget = int(hbm_budget)
         self.n_workers = n_workers
@@ -192,14 +199,16 @@ class AnalysisServer:
             fam.u = torch.zeros_like(fam.f)
         rho = torch.tensor(np.asarray(req["rho"], dtype=np.float64).ravel(), device=dev)
         m = fam.mesh
+        # a repeat design keeps the family's coarsest inverse while it serves
+        reuse = aarmr.REUSE_COARSEST if fam.records > 0 else 0
         if fam.records >= self.Ns:
-            C, st, code = m.ca_update(rho, fam.f, fam.fixed, fam.u)
+            C, st, code = m.ca_update(rho, fam.f, fam.fixed, fam.u, flags=reuse)
             acc = [st.accepted[l] for l in range(req["n_case"])]
             path = "ca" if all(acc) else "fallback"
             its = sum(st.mgcg_iterations[l] for l in range(req["n_case"]))
             res = max(st.rel_residual[l] for l in range(req["n_case"]))
         else:
-            flags = aarmr.RECORD_PARM | (aarmr.WARM_START if fam.records > 0 else 0)
+            flags = aarmr.RECORD_PARM | (aarmr.WARM_START if fam.records > 0 else 0) | reuse
             C, st, code = m.solve(rho, fam.f, fam.fixed, fam.u, flags=flags)
             fam.records += 1
             path = "mgcg"
