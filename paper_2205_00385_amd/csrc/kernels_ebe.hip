@@ -232,8 +232,8 @@ __global__ void __launch_bounds__(kLanes * ROWS, AARMR_EBE_MINB) k_ebe_z(int nx,
   load_plane(kz0, RA);
   T WA = load_w(kz0 - 1), WB = (T)0;
   if (PF == 2) {
-    load_plane(kz0 + 1, RB);
-    WB = load_w(kz0);
+    load_plane(kz0 + 1 <= kz1 ? kz0 + 1 : -2, RB);
+    WB = load_w(kz0 < kz1 ? kz0 : -1);
   }
   uint32_t own_m = 7u;  // fixed-DOF mask of node (i, j) on the plane written next
   T own_v[3] = {}, own_b[3] = {}, own_d[3] = {};  // JAC: that node's v, jb, jd
@@ -412,8 +412,12 @@ __global__ void k_identity_rows(int64_t nn, const uint8_t* __restrict__ mask,
 // as long as possible while the grid still fills every resident workgroup
 // slot of the device in a single round; at least 4 planes per chunk unless a
 // tuned length (2 or more) is given.
+// Prefetch distance: two node planes in flight for the 16-row tile (a
+// 512-thread workgroup leaves registers to spare at its occupancy of two
+// wavefronts per SIMD; 256x128x128: 70 -> 67 us), one for the smaller tiles,
+// whose occupancy the extra registers would cut.
 #ifndef AARMR_EBE_PF
-#define AARMR_EBE_PF 1
+#define AARMR_EBE_PF(ROWS) ((ROWS) == 16 ? 2 : 1)
 #endif
 
 // Tile rows.  The launch shape word `shape` carries a tuned z-chunk length
@@ -444,7 +448,7 @@ static int launch_ebe_r(const Grid& g, const WalshConsts& K, const T* E, const u
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &per_cu, k_ebe_z<T, ROWS, MASK_IN, AARMR_EBE_PF, JAC, DOT>, kThreads, 0);
+        &per_cu, k_ebe_z<T, ROWS, MASK_IN, AARMR_EBE_PF(ROWS), JAC, DOT>, kThreads, 0);
     return (cus > 0 && per_cu > 0) ? cus * per_cu : 512;
   }();
   const int gx = (g.nx + 1 + kTileX - 1) / kTileX;
@@ -457,7 +461,7 @@ static int launch_ebe_r(const Grid& g, const WalshConsts& K, const T* E, const u
   if (tz_req > 0) tz = tz_req < planes ? tz_req : planes;  // tuned z-chunk length
   if (tz < 2) tz = 2;
   gz = (planes + tz - 1) / tz;
-  k_ebe_z<T, ROWS, MASK_IN, AARMR_EBE_PF, JAC, DOT>
+  k_ebe_z<T, ROWS, MASK_IN, AARMR_EBE_PF(ROWS), JAC, DOT>
       <<<dim3((unsigned)(gx * gy * gz), 1, (unsigned)nr), kThreads, 0, s>>>(
           g.nx, g.ny, g.nz, gx, gy, tz, K, E, mask, v, y, jb, jd, omega, part, 3 * g.nn, pst);
   return gx * gy * gz;
