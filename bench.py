@@ -236,7 +236,7 @@ def run_mechanism(torch, aarmr, synth, prob, cycles, levels, plain, ca_tol=1e-3,
     mesh = aarmr.Mesh(p)
     mesh.set_springs(*aarmr.springs_soa(prob, mesh.n_node))
     fixed = torch.tensor(aarmr.fixed_dofs_soa(prob, mesh.n_node), dtype=torch.int64, device=dev)
-    f = torch.tensor([v for c in aarmr.loads_soa(prob, mesh.n_node) for v in c],
+    f = torch.tensor(np.concatenate(aarmr.loads_soa(prob, mesh.n_node)),
                      dtype=torch.float64, device=dev)
     ones = torch.ones(mesh.n_elem, dtype=torch.float64, device=dev)
     dv = torch.empty_like(ones)

@@ -362,14 +362,21 @@ class BatchRun:
         return [[self._comp[i][l] for l in range(self._items[i].n_rhs)] for i in range(n)], code
 
 
-def fixed_dofs_soa(prob, n_node: int) -> list:
+def fixed_dofs_soa(prob, n_node: int):
     """Flatten a problem's fixed (i, j, k, c) list, or (i, j, c) for a
-    plane-stress problem, into SoA DOF ids c*n_node + n."""
+    plane-stress problem, into sorted unique SoA DOF ids c*n_node + n
+    (numpy int64)."""
+    import numpy as np
+
     nx, ny = prob.nx, prob.ny
+    if not prob.fixed:
+        return np.zeros(0, dtype=np.int64)
+    f = np.asarray(prob.fixed, dtype=np.int64)
     if not hasattr(prob, "nz"):
-        return sorted({c * n_node + i + (nx + 1) * j for (i, j, c) in prob.fixed})
-    ids = sorted({c * n_node + i + (nx + 1) * (j + (ny + 1) * k) for (i, j, k, c) in prob.fixed})
-    return ids
+        ids = f[:, 2] * n_node + f[:, 0] + (nx + 1) * f[:, 1]
+    else:
+        ids = f[:, 3] * n_node + f[:, 0] + (nx + 1) * (f[:, 1] + (ny + 1) * f[:, 2])
+    return np.unique(ids)
 
 
 def springs_soa(prob, n_node: int):
@@ -379,21 +386,53 @@ def springs_soa(prob, n_node: int):
     return [c * n_node + i + (nx + 1) * j for (i, j, c, _) in sp], [k for (*_, k) in sp]
 
 
+def loads_device(prob, n_node: int, device, cases: Optional[Sequence[int]] = None):
+    """The SoA load vectors of loads_soa, concatenated over the cases, built
+    directly in device memory (zeros plus the few point loads), for grids
+    whose host vectors would cost more to build and copy than the solve."""
+    import numpy as np
+
+    nx, ny = prob.nx, prob.ny
+    plane = not hasattr(prob, "nz")
+    n = (2 if plane else 3) * n_node
+    cases = list(range(prob.n_case) if cases is None else cases)
+    f = torch.zeros(len(cases) * n, dtype=torch.float64, device=device)
+    idx, val = [], []
+    for slot, l in enumerate(cases):
+        for ld in prob.loads[l]:
+            if plane:
+                i, j, c, w = ld
+                idx.append(slot * n + c * n_node + i + (nx + 1) * j)
+            else:
+                i, j, k, c, w = ld
+                idx.append(slot * n + c * n_node + i + (nx + 1) * (j + (ny + 1) * k))
+            val.append(float(w))
+    if idx:
+        f.index_put_((torch.tensor(idx, dtype=torch.int64, device=device),),
+                     torch.tensor(val, dtype=torch.float64, device=device), accumulate=True)
+    return f
+
+
 def loads_soa(prob, n_node: int, cases: Optional[Sequence[int]] = None) -> list:
     """Flatten a problem's point loads into SoA vectors [case][dim * n_node]
-    (dim = 2 for a plane-stress problem, whose loads are (i, j, c, value))."""
+    (dim = 2 for a plane-stress problem, whose loads are (i, j, c, value));
+    numpy float64 arrays, repeated points summed."""
+    import numpy as np
+
     nx, ny = prob.nx, prob.ny
     plane = not hasattr(prob, "nz")
     cases = range(prob.n_case) if cases is None else cases
     out = []
     for l in cases:
-        v = [0.0] * ((2 if plane else 3) * n_node)
-        for ld in prob.loads[l]:
+        v = np.zeros((2 if plane else 3) * n_node)
+        lds = prob.loads[l]
+        if lds:
+            a = np.asarray(lds, dtype=np.float64)
+            ii = a[:, :-1].astype(np.int64)
             if plane:
-                i, j, c, val = ld
-                v[c * n_node + i + (nx + 1) * j] += val
+                idx = ii[:, 2] * n_node + ii[:, 0] + (nx + 1) * ii[:, 1]
             else:
-                i, j, k, c, val = ld
-                v[c * n_node + i + (nx + 1) * (j + (ny + 1) * k)] += val
+                idx = ii[:, 3] * n_node + ii[:, 0] + (nx + 1) * (ii[:, 1] + (ny + 1) * ii[:, 2])
+            np.add.at(v, idx, a[:, -1])
         out.append(v)
     return out

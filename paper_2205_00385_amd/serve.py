@@ -193,8 +193,7 @@ class AnalysisServer:
             prob = family_problem(req)
             fam.mesh = aarmr.Mesh(self.params(req))
             n_node = fam.mesh.n_node
-            fam.f = torch.tensor(np.concatenate([np.asarray(v) for v in aarmr.loads_soa(prob, n_node)]),
-                                 dtype=torch.float64, device=dev)
+            fam.f = aarmr.loads_device(prob, n_node, dev)
             fam.fixed = torch.tensor(aarmr.fixed_dofs_soa(prob, n_node), dtype=torch.int64, device=dev)
             fam.u = torch.zeros_like(fam.f)
         rho = torch.tensor(np.asarray(req["rho"], dtype=np.float64).ravel(), device=dev)

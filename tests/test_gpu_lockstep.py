@@ -85,3 +85,14 @@ def test_lockstep_with_a_zero_load_case():
     assert st.iterations[1] == 0
     assert st.rel_residual[0] <= 1e-8 and st.rel_residual[2] <= 1e-8
     m.close()
+
+
+def test_loads_built_on_the_device_equal_host_loads():
+    aarmr = _aarmr()
+    for prob, nn in ((synth.point_loads_on_face(12, 8, 8, n_case=5, seed=85), 13 * 9 * 9),
+                     (synth.inverter2d(16, 8), 17 * 9)):
+        host = np.concatenate(aarmr.loads_soa(prob, nn))
+        dev = aarmr.loads_device(prob, nn, "cuda")
+        assert torch.equal(dev.cpu(), torch.tensor(host))
+        sub = aarmr.loads_device(prob, nn, "cuda", cases=[1, 0])
+        assert torch.equal(sub.cpu(), torch.tensor(np.concatenate(aarmr.loads_soa(prob, nn, [1, 0]))))
