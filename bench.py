@@ -34,6 +34,10 @@ METRIC = "EbE K·v GDOF/s; solves/s at 1e-6 rel. compliance; p50/p99 latency vs 
 HBM_PEAK_GBS = 8000.0
 
 KV_GRID = (256, 128, 128)
+# grid levels of the 256x128x128 analyses: 6 (coarsest 8x4x4, 675 DOFs) measured
+# fastest, 23.8 / 19.8 ms (FP64 / refinement) against 25.2 / 22.7 ms with 5
+# levels (a 4131-DOF coarsest inverse) and 26.2 / 21.5 ms with 7
+LEVELS_256 = 6
 KV_PER_STEP = 50  # products per timed step (25 per mesh)
 NX, NY, NZ = 96, 48, 48
 CYCLES, N_ON, NS, NM = 50, 20, 2, 6
@@ -396,7 +400,7 @@ def kv_roofline(ms, grid, extra=None):
 def precision_form(torch, aarmr, synth, reps=3):
     """One analysis (setup + MGCG to rel. residual 1e-8, compliance) of the
     256x128x128 cantilever on a smoothed random field (correlation length 8
-    voxels, seed 3, mapped to [1e-3, 1]), 5 grid levels, in FP64 and in the
+    voxels, seed 3, mapped to [1e-3, 1]), 6 grid levels (coarsest 8x4x4), in FP64 and in the
     refinement form (FP32 operator sweeps, V-cycle and inner CG; FP64
     residuals, dot accumulation and updates of u).  Median of `reps` timed
     solves after one warm-up solve, each from u = 0."""
@@ -409,7 +413,7 @@ def precision_form(torch, aarmr, synth, reps=3):
                        dtype=torch.float64, device=dev)
     res = {}
     for prec in (aarmr.FP64, aarmr.FP32_REFINE):
-        p = aarmr.default_params(nx=L[0], ny=L[1], nz=L[2], mg_levels=5, cg_rtol=1e-8,
+        p = aarmr.default_params(nx=L[0], ny=L[1], nz=L[2], mg_levels=LEVELS_256, cg_rtol=1e-8,
                                  cg_maxit=2000, precision=prec)
         m = aarmr.Mesh(p)
         fixed = torch.tensor(aarmr.fixed_dofs_soa(prob, m.n_node), dtype=torch.int64, device=dev)
@@ -435,7 +439,7 @@ def precision_form(torch, aarmr, synth, reps=3):
     a, b = res[aarmr.FP64], res[aarmr.FP32_REFINE]
     du = float(torch.linalg.norm(b["u"] - a["u"]) / torch.linalg.norm(a["u"]))
     return {"workload": "256x128x128 hex8 cantilever, smoothed random field [1e-3, 1], "
-                        "5 levels, rel. residual 1e-8, one load case",
+                        f"{LEVELS_256} levels, rel. residual 1e-8, one load case",
             "dofs": 3 * (L[0] + 1) * (L[1] + 1) * (L[2] + 1),
             "fp64": {"ms_per_solve": round(a["ms"], 3), "solves_s": round(1e3 / a["ms"], 3),
                      "iterations": a["its"], "rel_residual": a["rel"]},
@@ -640,13 +644,15 @@ def cpu_baseline(sets=None, torch=None, aarmr=None, synth=None, reps=8):
                       f"scatter single-threaded): {dt:.1f} s, {dt / reps * 1e3:.0f} ms per product"}
 
 
-def reuse_form(torch, aarmr, synth, reps=2):
-    """A repeat analysis of the 256x128x128 cantilever (FP64, 5 levels, rel.
-    residual 1e-8) after a smooth 5% density perturbation of the smoothed
-    random field, with a new coarsest inverse (plain) and with the previous
-    design's inverse kept (AARMR_REUSE_COARSEST).  Each timing is the repeat
-    solve alone, after a solve of the unperturbed design, warm-started from
-    its solution; median of `reps`."""
+def reuse_form(torch, aarmr, synth, reps=2, levels=(5, LEVELS_256)):
+    """A repeat analysis of the 256x128x128 cantilever (FP64, rel. residual
+    1e-8) after a smooth 5% density perturbation of the smoothed random
+    field, with a new coarsest inverse (plain) and with the previous design's
+    inverse kept (AARMR_REUSE_COARSEST), at each grid depth in `levels`:
+    5 levels leave a 4131-DOF coarsest system, 6 levels a 675-DOF one whose
+    inversion is cheap.  Each timing is the repeat solve alone, after a solve
+    of the unperturbed design, warm-started from its solution; median of
+    `reps`."""
     import numpy as np
 
     dev = torch.device("cuda")
@@ -656,36 +662,43 @@ def reuse_form(torch, aarmr, synth, reps=2):
     r1 = synth.smooth_perturb(r0, 0.05, seed=33, sigma=4.0)
     rho0 = torch.tensor(r0.ravel(), dtype=torch.float64, device=dev)
     rho1 = torch.tensor(r1.ravel(), dtype=torch.float64, device=dev)
-    m = aarmr.Mesh(aarmr.default_params(nx=L[0], ny=L[1], nz=L[2], mg_levels=5, cg_rtol=1e-8,
-                                        cg_maxit=2000))
-    fixed = torch.tensor(aarmr.fixed_dofs_soa(prob, m.n_node), dtype=torch.int64, device=dev)
-    f = torch.tensor(np.asarray(aarmr.loads_soa(prob, m.n_node)[0]), dtype=torch.float64,
-                     device=dev)
-    u = torch.zeros_like(f)
-    out = {}
-    for name, fl in (("new_inverse", 0), ("kept_inverse", aarmr.REUSE_COARSEST)):
-        times, its, inv, Cs = [], [], [], []
-        for r in range(reps + 1):
-            u.zero_()
-            m.solve(rho0, f, fixed, u, flags=aarmr.REUSE_COARSEST)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            C, st, code = m.solve(rho1, f, fixed, u, flags=fl | aarmr.WARM_START)
-            dt = time.perf_counter() - t0
-            if r > 0:
-                times.append(dt)
-                its.append(int(st.iterations[0]))
-                inv.append(int(st.coarsest_inversions))
-                Cs.append(C[0])
-        out[name] = {"ms": round(float(np.median(times)) * 1e3, 3), "iterations": its,
-                     "coarsest_inversions": inv, "compliance": Cs[-1]}
-    m.close()
-    a, b = out["new_inverse"], out["kept_inverse"]
-    out["speedup"] = round(a["ms"] / b["ms"], 3)
-    out["compliance_rel_diff"] = abs(a["compliance"] - b["compliance"]) / abs(a["compliance"])
-    out["workload"] = ("256x128x128 cantilever, FP64, 5 levels, rel. residual 1e-8: repeat "
-                       "solve after a smooth 5% density perturbation")
-    return out
+    res = {"workload": "256x128x128 cantilever, FP64, rel. residual 1e-8: repeat solve "
+                       "after a smooth 5% density perturbation"}
+    for lev in levels:
+        m = aarmr.Mesh(aarmr.default_params(nx=L[0], ny=L[1], nz=L[2], mg_levels=lev,
+                                            cg_rtol=1e-8, cg_maxit=2000))
+        fixed = torch.tensor(aarmr.fixed_dofs_soa(prob, m.n_node), dtype=torch.int64,
+                             device=dev)
+        f = torch.tensor(np.asarray(aarmr.loads_soa(prob, m.n_node)[0]), dtype=torch.float64,
+                         device=dev)
+        u = torch.zeros_like(f)
+        out = {}
+        for name, fl in (("new_inverse", 0), ("kept_inverse", aarmr.REUSE_COARSEST)):
+            times, its, inv, Cs = [], [], [], []
+            for r in range(reps + 1):
+                u.zero_()
+                m.solve(rho0, f, fixed, u, flags=aarmr.REUSE_COARSEST)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                C, st, code = m.solve(rho1, f, fixed, u, flags=fl | aarmr.WARM_START)
+                dt = time.perf_counter() - t0
+                if r > 0:
+                    times.append(dt)
+                    its.append(int(st.iterations[0]))
+                    inv.append(int(st.coarsest_inversions))
+                    Cs.append(C[0])
+            out[name] = {"ms": round(float(np.median(times)) * 1e3, 3), "iterations": its,
+                         "coarsest_inversions": inv, "compliance": Cs[-1]}
+        m.close()
+        a, b = out["new_inverse"], out["kept_inverse"]
+        out["speedup"] = round(a["ms"] / b["ms"], 3)
+        out["compliance_rel_diff"] = (abs(a["compliance"] - b["compliance"])
+                                      / abs(a["compliance"]))
+        print(f"[bench] repeat solve, {lev} levels: {a['ms']:.2f} / {b['ms']:.2f} ms",
+              file=sys.stderr, flush=True)
+        res[f"levels_{lev}"] = out
+        del m, u
+    return res
 
 
 def ca_fidelity(torch, aarmr, synth):
