@@ -87,19 +87,25 @@ __device__ inline __amdgpu_buffer_rsrc_t make_rsrc(const void* p, uint32_t bytes
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes,
                                            kBufferWord3);
 }
-__device__ inline double ld(__amdgpu_buffer_rsrc_t r, uint32_t off, double) {
-  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+// `soff` is a wave-uniform byte offset carried in the scalar operand (the
+// component stride), so it costs no vector instruction.  An out-of-range
+// lane stays out of range with it: kOutside + soff is below 2^32 and above
+// every buffer size.
+__device__ inline double ld(__amdgpu_buffer_rsrc_t r, uint32_t off, double, uint32_t soff = 0) {
+  return __builtin_bit_cast(double,
+                            __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, (int)soff, 0));
 }
-__device__ inline float ld(__amdgpu_buffer_rsrc_t r, uint32_t off, float) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
+__device__ inline float ld(__amdgpu_buffer_rsrc_t r, uint32_t off, float, uint32_t soff = 0) {
+  return __builtin_bit_cast(float,
+                            __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, (int)soff, 0));
 }
-__device__ inline void st(__amdgpu_buffer_rsrc_t r, uint32_t off, double x) {
+__device__ inline void st(__amdgpu_buffer_rsrc_t r, uint32_t off, double x, uint32_t soff = 0) {
   __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(decltype(
-      __builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0)), x), r, (int)off, 0, 0);
+      __builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0)), x), r, (int)off, (int)soff, 0);
 }
-__device__ inline void st(__amdgpu_buffer_rsrc_t r, uint32_t off, float x) {
+__device__ inline void st(__amdgpu_buffer_rsrc_t r, uint32_t off, float x, uint32_t soff = 0) {
   __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(decltype(
-      __builtin_amdgcn_raw_buffer_load_b32(r, 0, 0, 0)), x), r, (int)off, 0, 0);
+      __builtin_amdgcn_raw_buffer_load_b32(r, 0, 0, 0)), x), r, (int)off, (int)soff, 0);
 }
 __device__ inline uint32_t ld_u8(__amdgpu_buffer_rsrc_t r, uint32_t off) {
   return (uint32_t)__builtin_amdgcn_raw_buffer_load_b8(r, (int)off, 0, 0);
@@ -189,7 +195,7 @@ __global__ void __launch_bounds__(kLanes * ROWS, AARMR_EBE_MINB) k_ebe_z(int nx,
     const uint32_t o = ok ? (uint32_t)node * TS : kOutside;
     m = want_mask ? ld_u8(rm, ok ? (uint32_t)node : kOutside) : 0u;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) q[c] = ld(rv, o + (uint32_t)c * cstride, T());
+    for (int c = 0; c < 3; ++c) q[c] = ld(rv, o, T(), (uint32_t)c * cstride);
   };
   auto load_plane = [&](int k, PlaneRaw<T>& R) {
     const bool kin = k >= 0 && k <= nz;
@@ -260,8 +266,8 @@ __global__ void __launch_bounds__(kLanes * ROWS, AARMR_EBE_MINB) k_ebe_z(int nx,
       const uint32_t on = (own && k + 1 <= nz) ? (uint32_t)((k + 1) * plane + off00) * TS : kOutside;
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        b_next[c] = ld(rjb, on + (uint32_t)c * cstride, T());
-        d_next[c] = ld(rjd, on + (uint32_t)c * cstride, T());
+        b_next[c] = ld(rjb, on, T(), (uint32_t)c * cstride);
+        d_next[c] = ld(rjd, on, T(), (uint32_t)c * cstride);
       }
     }
     load_plane(k + 1 + PF <= kz1 ? k + 1 + PF : -2, R);
@@ -306,7 +312,7 @@ __global__ void __launch_bounds__(kLanes * ROWS, AARMR_EBE_MINB) k_ebe_z(int nx,
       T out = X0[c] + xs[buf][c][ty > 0 ? ty - 1 : 0][tx];
       if (JAC) out = own_v[c] + omega * own_d[c] * (own_b[c] - out);
       if ((own_m >> c) & 1u) out = (T)0;
-      st(ry, oy + (uint32_t)c * cstride, out);
+      st(ry, oy, out, (uint32_t)c * cstride);
       if (DOT) dacc += wr ? (double)(JAC ? own_b[c] : own_v[c]) * (double)out : 0.0;
     }
     buf ^= 1;
