@@ -705,6 +705,109 @@ __global__ void __launch_bounds__(192) k_restrict(int cnx, int cny, int cnz,
   }
 }
 
+// Lane i of a wavefront takes lane i-1's (wave_shr:1) or lane i+1's
+// (wave_shl:1) value through DPP; the end lanes read 0.
+template <int CTRL>
+__device__ inline double wave_shift(double x) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), CTRL, 0xF, 0xF, true);
+  return __hiloint2double(hi, lo);
+}
+template <int CTRL>
+__device__ inline float wave_shift(float x) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), CTRL, 0xF, 0xF, true));
+}
+
+// The same restriction on 3D grids, separably: a workgroup forms one coarse
+// plane K of a tile of kRsCI x kRsCJ coarse nodes.  It loads the tile's rows
+// of fine planes 2K-1, 2K and 2K+1 at once (one fine node per lane, 63
+// nodes of a row on lanes 0..62, whole rows, coalesced; the 2 kRsCJ + 1
+// rows spread over the four wavefronts), restricts along x in registers
+// (DPP neighbours), along y through LDS and along z in registers.  Per
+// coarse node the sum is formed as m + (l + r) / 2 along x, then y, then z:
+// a fixed order, so results are deterministic, and equal to the per-node
+// sum of the other kernel up to rounding.  blockIdx.x: (tile, K) with K
+// fastest, in XCD-contiguous order, so the fine plane 2K+1 that planes K
+// and K+1 share is read twice through one L2; blockIdx.y: component;
+// blockIdx.z: load case.
+constexpr int kRsCI = 31;
+constexpr int kRsCJ = 8;
+constexpr int kRsRows = 2 * kRsCJ + 1;
+constexpr int kRsRowsPerWave = (kRsRows + 3) / 4;
+template <typename T>
+__global__ void __launch_bounds__(256) k_restrict_z(int cnx, int cny, int cnz, int gx,
+                                                    const T* __restrict__ bf,
+                                                    const T* __restrict__ tf,
+                                                    const uint8_t* __restrict__ mask,
+                                                    T* __restrict__ bc, const T* __restrict__ dc,
+                                                    T omega, T* __restrict__ xc, int64_t fs,
+                                                    int64_t cs) {
+  __shared__ T xr[3][kRsRows][32];
+  {  // load case blockIdx.z
+    const int64_t fo = (int64_t)blockIdx.z * fs, co = (int64_t)blockIdx.z * cs;
+    bf += fo;
+    if (tf) tf += fo;
+    bc += co;
+    if (xc) xc += co;
+  }
+  const int c = blockIdx.y;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int bx, by, K;
+  {
+    const int total = gridDim.x, wg = blockIdx.x;
+    const int xcd = wg & 7, pos = wg >> 3, q = total >> 3, r = total & 7;
+    const int t = (xcd < r) ? xcd * (q + 1) + pos : r * (q + 1) + (xcd - r) * q + pos;
+    K = t % (cnz + 1);
+    const int tile = t / (cnz + 1);
+    bx = tile % gx;
+    by = tile / gx;
+  }
+  const int I0 = bx * kRsCI, J0 = by * kRsCJ;
+  const int fnx = 2 * cnx, fny = 2 * cny, fnz = 2 * cnz;
+  const int64_t fnn = (int64_t)(fnx + 1) * (fny + 1) * (fnz + 1);
+  const int64_t cnn = (int64_t)(cnx + 1) * (cny + 1) * (cnz + 1);
+  const int64_t fplane = (int64_t)(fnx + 1) * (fny + 1);
+  const int fx = 2 * I0 - 1 + lane;
+  const bool xok = lane < 2 * kRsCI + 1 && fx >= 0 && fx <= fnx;
+  const T* b = bf + c * fnn;
+  const T* tt = tf ? tf + c * fnn : nullptr;
+  // Df (b - t) at this lane's node of rows w + 4q of fine planes 2K-1+dz; 0 outside
+  T v[3][kRsRowsPerWave];
+#pragma unroll
+  for (int dz = 0; dz < 3; ++dz)
+#pragma unroll
+    for (int q = 0; q < kRsRowsPerWave; ++q) {
+      const int r = w + 4 * q, fy = 2 * J0 - 1 + r, fz = 2 * K - 1 + dz;
+      const bool ok = r < kRsRows && xok && fy >= 0 && fy <= fny && fz >= 0 && fz <= fnz;
+      const int64_t f = (int64_t)fz * fplane + (int64_t)fy * (fnx + 1) + fx;
+      T val = ok ? b[f] : T(0);
+      if (tt) val -= ok ? tt[f] : T(0);
+      if (mask && ok && ((mask[f] >> c) & 1)) val = T(0);
+      v[dz][q] = val;
+    }
+  // along x: odd lanes 2i+1 hold coarse column i
+#pragma unroll
+  for (int dz = 0; dz < 3; ++dz)
+#pragma unroll
+    for (int q = 0; q < kRsRowsPerWave; ++q) {
+      const int r = w + 4 * q;
+      const T l = wave_shift<0x138>(v[dz][q]), rr = wave_shift<0x130>(v[dz][q]);
+      const T sx = v[dz][q] + T(0.5) * (l + rr);
+      if (r < kRsRows && (lane & 1) && lane < 2 * kRsCI) xr[dz][r][lane >> 1] = sx;
+    }
+  __syncthreads();
+  const int ci = threadIdx.x & 31, cj = threadIdx.x >> 5;  // this thread's coarse node
+  if (ci >= kRsCI || I0 + ci > cnx || J0 + cj > cny) return;
+  T sy[3];
+#pragma unroll
+  for (int dz = 0; dz < 3; ++dz)
+    sy[dz] = xr[dz][2 * cj + 1][ci] + T(0.5) * (xr[dz][2 * cj][ci] + xr[dz][2 * cj + 2][ci]);
+  const T acc = sy[1] + T(0.5) * (sy[0] + sy[2]);
+  const int64_t n = (int64_t)K * (cnx + 1) * (cny + 1) + (int64_t)(J0 + cj) * (cnx + 1) + I0 + ci;
+  bc[c * cnn + n] = acc;
+  if (xc) xc[c * cnn + n] = omega * dc[c * cnn + n] * acc;
+}
+
 // xf += Df P xc: thread per fine node, branch-free over the (up to) 8
 // parent nodes: along an axis an even fine index takes its parent with
 // weight 1, an odd one both neighbours with weight 1/2.  On the plane grid
@@ -1379,6 +1482,22 @@ void launch_apply_l1_jacobi_f32(const Grid& g, const double* Ke, const double* K
                   omega, nr);
 }
 
+// 3D restriction launch: one workgroup per (tile, coarse plane, component,
+// case).  Used from kRsMinNodes coarse nodes up; on smaller grids, where a
+// launch is a few microseconds either way, the per-node kernel measured
+// faster (256x128x128, FP32: fine level 90 -> 68 us and second level 13.1 ->
+// 11.0 us with this kernel; third to fifth level 6.1/5.2/4.7 -> 8.2/6.9/5.2).
+constexpr int64_t kRsMinNodes = 100000;
+template <typename T>
+static void restrict_z(const Grid& coarse, const T* bf, const T* tf, const uint8_t* mask, T* bc,
+                       const T* dc, T omega, T* xc, hipStream_t s, int nr, int64_t fs,
+                       int64_t cs) {
+  const int gx = (coarse.nx + 1 + kRsCI - 1) / kRsCI;
+  const int gy = (coarse.ny + 1 + kRsCJ - 1) / kRsCJ;
+  k_restrict_z<T><<<dim3((unsigned)(gx * gy * (coarse.nz + 1)), 3, (unsigned)nr), 256, 0, s>>>(
+      coarse.nx, coarse.ny, coarse.nz, gx, bf, tf, mask, bc, dc, omega, xc, fs, cs);
+}
+
 void launch_apply_l1_f32(const Grid& g, const double* Ke, const double* Kcomp, int cap,
                          const float* Bw, const float* Ef, const uint8_t* eflag, const int* list,
                          const int* count, int nflag, const float* v, float* Y, float* y,
@@ -1398,6 +1517,10 @@ void launch_restrict_jacobi_f32(const Grid& coarse, const float* bf, const float
                                 const uint8_t* mask, float* bc, const float* dinv_c, float omega,
                                 float* xc, hipStream_t s, int nr) {
   const int64_t fnn = (int64_t)(2 * coarse.nx + 1) * (2 * coarse.ny + 1) * (2 * coarse.nz + 1);
+  if (coarse.nz > 0 && coarse.nn >= kRsMinNodes) {
+    restrict_z<float>(coarse, bf, tf, mask, bc, dinv_c, omega, xc, s, nr, 3 * fnn, 3 * coarse.nn);
+    return;
+  }
   k_restrict<float><<<dim3(nblk(coarse.nn, 64), 3, nr), 192, 0, s>>>(
       coarse.nx, coarse.ny, coarse.nz, bf, tf, mask, bc, dinv_c, omega, xc, 3 * fnn,
       3 * coarse.nn);
@@ -1406,6 +1529,11 @@ void launch_restrict_jacobi_f32(const Grid& coarse, const float* bf, const float
 void launch_restrict_f32(const Grid& coarse, const float* bf, const float* tf,
                          const uint8_t* mask, float* bc, hipStream_t s, int nr) {
   const int64_t fnn = (int64_t)(2 * coarse.nx + 1) * (2 * coarse.ny + 1) * (2 * coarse.nz + 1);
+  if (coarse.nz > 0 && coarse.nn >= kRsMinNodes) {
+    restrict_z<float>(coarse, bf, tf, mask, bc, nullptr, 0.0f, nullptr, s, nr, 3 * fnn,
+                      3 * coarse.nn);
+    return;
+  }
   k_restrict<float><<<dim3(nblk(coarse.nn, 64), 3, nr), 192, 0, s>>>(
       coarse.nx, coarse.ny, coarse.nz, bf, tf, mask, bc, nullptr, 0.0f, nullptr, 3 * fnn,
       3 * coarse.nn);
@@ -1439,6 +1567,10 @@ void launch_diag_elemmat(const Grid& g, const double* Ke, double* dinv, float* d
 
 void launch_restrict(const Grid& coarse, const double* bf, const double* tf, const uint8_t* mask,
                      double* bc, hipStream_t s, int ncomp) {
+  if (coarse.nz > 0 && ncomp == 3 && coarse.nn >= kRsMinNodes) {
+    restrict_z<double>(coarse, bf, tf, mask, bc, nullptr, 0.0, nullptr, s, 1, 0, 0);
+    return;
+  }
   k_restrict<double><<<dim3(nblk(coarse.nn, 64), ncomp), 192, 0, s>>>(coarse.nx, coarse.ny, coarse.nz,
                                                                   bf, tf, mask, bc, nullptr, 0.0,
                                                                   nullptr);
@@ -1447,6 +1579,10 @@ void launch_restrict(const Grid& coarse, const double* bf, const double* tf, con
 void launch_restrict_jacobi(const Grid& coarse, const double* bf, const double* tf,
                             const uint8_t* mask, double* bc, const double* dinv_c, double omega,
                             double* xc, hipStream_t s) {
+  if (coarse.nz > 0 && coarse.nn >= kRsMinNodes) {
+    restrict_z<double>(coarse, bf, tf, mask, bc, dinv_c, omega, xc, s, 1, 0, 0);
+    return;
+  }
   k_restrict<double><<<dim3(nblk(coarse.nn, 64), 3), 192, 0, s>>>(coarse.nx, coarse.ny, coarse.nz,
                                                                   bf, tf, mask, bc, dinv_c, omega,
                                                                   xc);
