@@ -82,6 +82,7 @@ struct LevelBuf {
   float* b32 = nullptr;
   float* x32 = nullptr;
   float* t32 = nullptr;
+  float* Ke32 = nullptr;  // 3D levels >= 2: FP32 copy of Ke for the FP32 V-cycle
 };
 
 // Scalar history in device memory (indices into m->scal).
@@ -490,6 +491,7 @@ int64_t layout(aarmr_mesh* m, char* base) {
         L.b32 = (float*)take(R * m3 * f4);
         L.x32 = (float*)take(R * m3 * f4);
       }
+      if (solid && l >= 2 && l < m->nlev - 1) L.Ke32 = (float*)take(m->lg[l].ne * nsym * f4);
     }
     m->act = (int*)take(R * 4);
   }
@@ -843,8 +845,11 @@ int build_mg(aarmr_mesh* m, hipStream_t s) {
       // stall, read at the first level-1 product (nflag1 < 0 until then)
       HIP_TRY(hipMemcpyAsync(m->hpin + 72, m->count1, sizeof(int), hipMemcpyDeviceToHost, s));
       m->nflag1 = -1;
-    } else
+    } else {
       launch_galerkin_from_coarse(m->lg[l], m->lv[l - 1].Ke, m->lv[l].Ke, s);
+      if (m->fp32 && l < m->nlev - 1)  // the FP32 V-cycle's copy (the coarsest uses its inverse)
+        launch_to_f32(m->lg[l].ne * kSymEntries, m->lv[l].Ke, m->lv[l].Ke32, s);
+    }
     KCHECK();
     if (l < m->nlev - 1) {
       launch_diag_elemmat(m->lg[l], m->lv[l].Ke, m->lv[l].dinv, m->lv[l].dinv32, s);
@@ -894,7 +899,7 @@ int apply32(aarmr_mesh* m, int l, const float* v, float* y, hipStream_t s, int n
     launch_apply_l1_f32(m->lg[1], m->lv[1].Ke, m->Kcomp1, m->cap1, m->Bw32d, m->E32,
                         m->eflag1, m->list1, m->count1, m->nflag1, v, m->Y1f, y, s, nr);
   } else {
-    launch_apply_elemmat_f32(m->lg[l], m->lv[l].Ke, v, y, s, nr);
+    launch_apply_elemmat_f32(m->lg[l], m->lv[l].Ke32, v, y, s, nr);
   }
   KCHECK();
   return AARMR_OK;
@@ -963,7 +968,7 @@ int vcycle32(aarmr_mesh* m, int l, const float* b, float* x, hipStream_t s,
                                    L.dinv32, om, s, nr);
       } else {
         if (x != L.x32) return fail(AARMR_E_STATE, "V-cycle iterate is not the level's buffer");
-        launch_apply_elemmat_jacobi_f32(G, L.Ke, x, b, L.dinv32, om, L.t32, s, nr);
+        launch_apply_elemmat_jacobi_f32(G, L.Ke32, x, b, L.dinv32, om, L.t32, s, nr);
         std::swap(L.x32, L.t32);
       }
       KCHECK();

@@ -147,7 +147,7 @@ void launch_apply_l1_jacobi_f32(const Grid& g, const double* Ke, const double* K
                                 const float* Bw, const float* Ef, const uint8_t* eflag,
                                 const int* list, const int* count, int nflag, float* x, float* Y,
                                 const float* b, const float* dinv, float omega, hipStream_t s, int nr = 1);
-void launch_apply_elemmat_jacobi_f32(const Grid& g, const double* Ke, const float* v,
+void launch_apply_elemmat_jacobi_f32(const Grid& g, const float* Ke, const float* v,
                                      const float* b, const float* dinv, float omega, float* out,
                                      hipStream_t s, int nr = 1);
 void launch_restrict_jacobi_f32(const Grid& coarse, const float* bf, const float* tf,
@@ -190,7 +190,7 @@ void launch_gj_invert(int n, double* A, double* P, double* T, double* C, double*
 void launch_gemv(int n, const double* A, const double* x, double* y, hipStream_t s);
 // FP32 V-cycle pieces (vectors FP32; element matrices and the coarsest
 // inverse stay FP64 and are applied with FP32 vectors).
-void launch_apply_elemmat_f32(const Grid& g, const double* Ke, const float* v, float* y,
+void launch_apply_elemmat_f32(const Grid& g, const float* Ke, const float* v, float* y,
                               hipStream_t s, int nr = 1);
 void launch_restrict_f32(const Grid& coarse, const float* bf, const float* tf,
                          const uint8_t* mask, float* bc, hipStream_t s, int nr = 1);
@@ -212,6 +212,8 @@ void launch_cg_xr_f32(int64_t n, const double* rz, const double* pq, float* x, f
 void launch_cg_p_f32(int64_t n, const double* rz_new, const double* rz_old, const float* z,
                      float* p, hipStream_t s);
 // Refinement transfers: dst32 = src64 / sqrt(*nrm2);  x64 += sqrt(*nrm2) d32.
+// dst = (float)src, elementwise.
+void launch_to_f32(int64_t n, const double* src, float* dst, hipStream_t s);
 void launch_to_f32_scaled(int64_t n, const double* src, const double* nrm2, float* dst,
                           hipStream_t s);
 void launch_add_scaled_f32(int64_t n, const float* d, const double* nrm2, double* x,

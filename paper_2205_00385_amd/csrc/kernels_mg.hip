@@ -345,12 +345,14 @@ __global__ void __launch_bounds__(256) k_galerkin_row8(int cnx, int cny, int cnz
 // packed element matrices.  Block: 64 consecutive nodes x 8 waves; wave a
 // takes each node as local corner a of the element e = node - offset(a) and
 // forms rows 3a..3a+2 of Ke_e v_e; the 8 partial rows are summed in LDS in a
-// fixed order.  Vectors of type T, matrices FP64.
+// fixed order.  Vectors of type T, matrices of type KT (FP64, or the FP32
+// copy the refinement form keeps, which holds the values the FP32 product
+// would round them to anyway).
 // With jb non-null the product feeds a damped-Jacobi sweep instead:
 // y = v + omega jd (jb - A v) (y distinct from v).
-template <typename T>
+template <typename T, typename KT = double>
 __global__ void __launch_bounds__(512) k_apply_elemmat(int nx, int ny, int nz,
-                                                       const double* __restrict__ Ke,
+                                                       const KT* __restrict__ Ke,
                                                        const T* __restrict__ v,
                                                        T* __restrict__ y,
                                                        const T* __restrict__ jb,
@@ -1436,9 +1438,9 @@ void launch_apply_elemmat_jacobi(const Grid& g, const double* Ke, const double* 
                                                          omega);
 }
 
-void launch_apply_elemmat_f32(const Grid& g, const double* Ke, const float* v, float* y,
+void launch_apply_elemmat_f32(const Grid& g, const float* Ke, const float* v, float* y,
                               hipStream_t s, int nr) {
-  k_apply_elemmat<float><<<dim3(nblk(g.nn, 64), 1, nr), 512, 0, s>>>(
+  k_apply_elemmat<float, float><<<dim3(nblk(g.nn, 64), 1, nr), 512, 0, s>>>(
       g.nx, g.ny, g.nz, Ke, v, y, nullptr, nullptr, 0.0f, 3 * g.nn);
 }
 
@@ -1506,10 +1508,10 @@ void launch_apply_l1_f32(const Grid& g, const double* Ke, const double* Kcomp, i
                   nullptr, 0.0f, nr);
 }
 
-void launch_apply_elemmat_jacobi_f32(const Grid& g, const double* Ke, const float* v,
+void launch_apply_elemmat_jacobi_f32(const Grid& g, const float* Ke, const float* v,
                                      const float* b, const float* dinv, float omega, float* out,
                                      hipStream_t s, int nr) {
-  k_apply_elemmat<float><<<dim3(nblk(g.nn, 64), 1, nr), 512, 0, s>>>(
+  k_apply_elemmat<float, float><<<dim3(nblk(g.nn, 64), 1, nr), 512, 0, s>>>(
       g.nx, g.ny, g.nz, Ke, v, out, b, dinv, omega, 3 * g.nn);
 }
 

@@ -254,6 +254,11 @@ __global__ void k_cg_p_f32(int64_t n, const double* __restrict__ rz_new,
   p[i] = (float)fma(beta, (double)p[i], (double)z[i]);
 }
 
+__global__ void k_to_f32(int64_t n, const double* __restrict__ src, float* __restrict__ dst) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = (float)src[i];
+}
+
 __global__ void k_to_f32_scaled(int64_t n, const double* __restrict__ src,
                                 const double* __restrict__ nrm2, float* __restrict__ dst) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -478,6 +483,10 @@ void launch_cg_p_fused_f32(int64_t n, const double* rz_part, int n_part, double*
 void launch_cg_p_f32(int64_t n, const double* rz_new, const double* rz_old, const float* z,
                      float* p, hipStream_t s) {
   k_cg_p_f32<<<nblk(n, 256), 256, 0, s>>>(n, rz_new, rz_old, z, p);
+}
+
+void launch_to_f32(int64_t n, const double* src, float* dst, hipStream_t s) {
+  k_to_f32<<<nblk(n, 256), 256, 0, s>>>(n, src, dst);
 }
 
 void launch_to_f32_scaled(int64_t n, const double* src, const double* nrm2, float* dst,
