@@ -124,6 +124,7 @@ struct aarmr_mesh {
   double KE[576];             // 24x24 (3D) or 8x8 (2D) row-major
   WalshConsts wk;             // reflection-blocked form of KE (3D)
   double Mc[8 * kSymEntries]; // P_c^T KE P_c per child position, packed
+  std::vector<double> N2;     // [300][64]: P_c1^T M_c0 P_c1 per fine descendant d = 8 c1 + c0 of a level-2 parent
   double Bw[576];             // W M_0 W / 64 in the Walsh x component basis
   float Bw32[576];
   bool fp32 = false;          // precision == AARMR_FP32_REFINE
@@ -134,6 +135,9 @@ struct aarmr_mesh {
   int64_t ws_bytes = 0;
   double* KEd = nullptr;
   double* Mcd = nullptr;      // P_c^T KE P_c of the 8 children, packed
+  double* N2d = nullptr;      // N2 on the device
+  int* list2 = nullptr;       // level-2 parents with a flagged level-1 child
+  int* count2 = nullptr;
   double* Bwd = nullptr;      // Bw on the device
   float* Bw32d = nullptr;
   double* Y1 = nullptr;       // level-1 element products [24][ne1]
@@ -348,6 +352,33 @@ void child_galerkin(const double* KE, double* Mc) {
   }
 }
 
+// Nt[entry][8 c1 + c0] = (P_c1^T M_c0 P_c1)[entry]: the contribution of fine
+// descendant c0 of level-1 child c1 to a level-2 parent's Galerkin matrix,
+// per unit modulus (packed entries, stored transposed).  So a parent whose level-1 children touch no fixed DOF has the
+// matrix sum_d E_d N_d over its 64 fine descendants.
+void grandchild_galerkin(const double* Mc, double* N) {
+  auto phi = [](int pos, int A) { return pos == 1 ? 0.5 : ((pos >> 1) == A ? 1.0 : 0.0); };
+  for (int c1 = 0; c1 < 8; ++c1) {
+    const int dx = c1 & 1, dy = (c1 >> 1) & 1, dz = c1 >> 2;
+    double P[8][8];  // P[b][A]: child corner b from parent corner A
+    for (int b = 0; b < 8; ++b)
+      for (int A = 0; A < 8; ++A)
+        P[b][A] = phi(dx + (b & 1), A & 1) * phi(dy + ((b >> 1) & 1), (A >> 1) & 1) *
+                  phi(dz + (b >> 2), A >> 2);
+    for (int c0 = 0; c0 < 8; ++c0) {
+      const double* M = Mc + c0 * kSymEntries;
+      for (int I = 0; I < 24; ++I)
+        for (int J = I; J < 24; ++J) {
+          double acc = 0.0;
+          for (int b = 0; b < 8; ++b)
+            for (int b2 = 0; b2 < 8; ++b2)
+              acc += P[b][I / 3] * M[sym_index(3 * b + I % 3, 3 * b2 + J % 3)] * P[b2][J / 3];
+          N[(int64_t)sym_index(I, J) * 64 + 8 * c1 + c0] = acc;
+        }
+    }
+  }
+}
+
 // Check M_c = R_c M_0 R_c for every child c, where R_c mirrors the parent in
 // the axes set in c: (R_c v)[3b + s] = (-1)^(bit s of c) v[3(b ^ c) + s].
 bool mirror_children(const double* Mc) {
@@ -431,6 +462,11 @@ int64_t layout(aarmr_mesh* m, char* base) {
   m->KEd = (double*)take(576 * d8);
   if (solid) {  // level-1 Walsh product (3D only)
     m->Mcd = (double*)take(8 * kSymEntries * d8);
+    m->N2d = (double*)take(64 * kSymEntries * d8);
+    if (m->nlev > 2) {
+      m->list2 = (int*)take(m->lg[2].ne * 4);
+      m->count2 = (int*)take(4);
+    }
     m->eflag1 = (uint8_t*)take(m->lg[1].ne);
     m->list1 = (int*)take(m->lg[1].ne * 4);
     m->count1 = (int*)take(4);
@@ -836,23 +872,36 @@ int build_mg(aarmr_mesh* m, hipStream_t s) {
   }
   launch_diag_fine(g, m->KEd, m->E, m->mask, m->lv[0].dinv, m->lv[0].dinv32, s);
   KCHECK();
+  // Below a coarser level, the level-1 matrices of parents without a fixed
+  // fine DOF are never stored: the level-1 product forms them from the moduli,
+  // the level-1 diagonal and the level-2 Galerkin matrices come from the
+  // moduli too.  Only as the coarsest level are they assembled.
+  const bool l1_all = m->nlev == 2;
   for (int l = 1; l < m->nlev; ++l) {
     if (l == 1) {
       launch_galerkin_from_fine(m->lg[1], m->KEd, m->Mcd, m->E, m->mask, m->eflag1, m->list1,
-                                m->count1, m->lv[1].Ke, m->Kcomp1, m->cap1, s);
+                                m->count1, m->lv[1].Ke, m->Kcomp1, m->cap1, s, l1_all);
       KCHECK();
       // the flagged count sizes the level-1 launches: fetched without a
       // stall, read at the first level-1 product (nflag1 < 0 until then)
       HIP_TRY(hipMemcpyAsync(m->hpin + 72, m->count1, sizeof(int), hipMemcpyDeviceToHost, s));
       m->nflag1 = -1;
     } else {
-      launch_galerkin_from_coarse(m->lg[l], m->lv[l - 1].Ke, m->lv[l].Ke, s);
+      if (l == 2)
+        launch_galerkin_l2_from_fine(m->lg[2], m->N2d, m->Mcd, m->E, m->eflag1, m->list2,
+                                     m->count2, m->lv[1].Ke, m->lv[2].Ke, s);
+      else
+        launch_galerkin_from_coarse(m->lg[l], m->lv[l - 1].Ke, m->lv[l].Ke, s);
       if (m->fp32 && l < m->nlev - 1)  // the FP32 V-cycle's copy (the coarsest uses its inverse)
         launch_to_f32(m->lg[l].ne * kSymEntries, m->lv[l].Ke, m->lv[l].Ke32, s);
     }
     KCHECK();
     if (l < m->nlev - 1) {
-      launch_diag_elemmat(m->lg[l], m->lv[l].Ke, m->lv[l].dinv, m->lv[l].dinv32, s);
+      if (l == 1)
+        launch_diag_l1(m->lg[1], m->lv[1].Ke, m->Mcd, m->E, m->eflag1, m->lv[1].dinv,
+                       m->lv[1].dinv32, s);
+      else
+        launch_diag_elemmat(m->lg[l], m->lv[l].Ke, m->lv[l].dinv, m->lv[l].dinv32, s);
       KCHECK();
     }
   }
@@ -1683,6 +1732,8 @@ int aarmr_mesh_create(const aarmr_params* p, aarmr_mesh** out) {
   }
   hex8_stiffness(p->nu, m->KE);  // unit modulus; E0 enters through SIMP
   child_galerkin(m->KE, m->Mc);
+  m->N2.resize(64 * kSymEntries);
+  grandchild_galerkin(m->Mc, m->N2.data());
   walsh_child(m->Mc, m->Bw);
   for (int x = 0; x < 576; ++x) m->Bw32[x] = (float)m->Bw[x];
   if (!walsh_parent_check(m->Mc, m->Bw)) {
@@ -1750,6 +1801,8 @@ int aarmr_bind_workspace(aarmr_mesh* m, void* dev_ptr, int64_t bytes, void* stre
   HIP_TRY(hipMemcpyAsync(m->KEd, m->KE, 576 * sizeof(double), hipMemcpyHostToDevice, s));
   if (m->dim == 3) {
     HIP_TRY(hipMemcpyAsync(m->Mcd, m->Mc, 8 * kSymEntries * sizeof(double), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(m->N2d, m->N2.data(), 64 * kSymEntries * sizeof(double),
+                           hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(m->Bwd, m->Bw, 576 * sizeof(double), hipMemcpyHostToDevice, s));
   }
   if (m->fp32) {

@@ -128,9 +128,22 @@ __host__ __device__ constexpr int sym_index(int r, int c) {
 // masked product for the parents flagged in eflag (1 = touches a fixed DOF),
 // whose indices are listed in list[0..*count); list entries w < cap are also
 // stored compactly, Kcomp[entry][w].
+// all: also the fast-path matrices of the unflagged parents (needed only when
+// level 1 is the coarsest; otherwise nothing reads them).
 void launch_galerkin_from_fine(const Grid& coarse, const double* KE, const double* Mc,
                                const double* E, const uint8_t* mask, uint8_t* eflag, int* list,
-                               int* count, double* Kc, double* Kcomp, int cap, hipStream_t s);
+                               int* count, double* Kc, double* Kcomp, int cap, hipStream_t s,
+                               bool all);
+// Level-2 Galerkin matrices from the fine moduli (N2: [64][300] descendant
+// matrices) for parents without a flagged level-1 child; the others from the
+// stored flagged level-1 matrices K1 and the moduli.  list2/count2: scratch.
+void launch_galerkin_l2_from_fine(const Grid& l2, const double* N2, const double* Mc,
+                                  const double* E, const uint8_t* eflag1, int* list2, int* count2,
+                                  const double* K1, double* K2, hipStream_t s);
+// Level-1 inverse Jacobi diagonal from the moduli (unflagged parents) and the
+// stored matrices (flagged ones).
+void launch_diag_l1(const Grid& g, const double* Ke, const double* Mc, const double* E,
+                    const uint8_t* eflag, double* dinv, float* dinv32, hipStream_t s);
 void launch_galerkin_from_coarse(const Grid& coarse, const double* Kf, double* Kc, hipStream_t s);
 void launch_apply_elemmat(const Grid& g, const double* Ke, const double* v, double* y,
                           hipStream_t s);

@@ -24,6 +24,7 @@ __device__ inline double phi1(int pos, int A) {
 }
 
 constexpr int kSym = kSymEntries;
+typedef double f64x4 __attribute__((ext_vector_type(4)));
 __host__ __device__ constexpr int sidx(int r, int c) { return sym_index(r, c); }
 
 // Level-1 Galerkin matrices, fast path: Kc = sum_c E_c M_c with
@@ -79,15 +80,140 @@ __global__ void k_parent_flags(int cnx, int cny, int cnz, const uint8_t* __restr
 
 __global__ void k_zero_int(int* p) { *p = 0; }
 
+// Level-2 parents with a level-1 child flagged in eflag1: indices appended to
+// list (in no particular order).  *count must be zero on entry.
+__global__ void k_parent_flags2(int cnx, int cny, int cnz, const uint8_t* __restrict__ eflag1,
+                                int* __restrict__ list, int* __restrict__ count) {
+  const int64_t cne = (int64_t)cnx * cny * cnz;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= cne) return;
+  const int cx = (int)(e % cnx);
+  const int64_t rest = e / cnx;
+  const int cy = (int)(rest % cny), cz = (int)(rest / cny);
+  const int nx1 = 2 * cnx, ny1 = 2 * cny;
+  unsigned any = 0;
+#pragma unroll
+  for (int c = 0; c < 8; ++c)
+    any |= eflag1[(int64_t)(2 * cx + (c & 1)) +
+                  (int64_t)nx1 * ((2 * cy + ((c >> 1) & 1)) + (int64_t)ny1 * (2 * cz + (c >> 2)))];
+  if (any) list[atomicAdd(count, 1)] = (int)e;
+}
+
+// Level-2 Galerkin matrices from the fine moduli: Kc = sum_d E_d N_d over the
+// 64 fine descendants d = 8 c1 + c0 (level-1 child c1, its fine child c0),
+// N_d = P_c1^T M_c0 P_c1 precomputed and stored transposed, Nt[entry][d].
+// Exact for parents whose level-1 children touch no fixed DOF (the level-1
+// matrix of such a child is sum_c0 E M_c0); k_galerkin_lds<2> then
+// overwrites the others.  The level-1 matrices are never formed for it.
+// As a product [300 x 64] x [64 x parents] on FP64 MFMA: each wavefront
+// takes 16 parents (their 64 moduli as the B operand, in registers) and
+// walks the 19 tiles of 16 entries, 16 MFMA steps of k = 4 each; a lane
+// holds result rows g + 4v (g = lane / 16) of column lane % 16, so each
+// store writes 16 consecutive parents of one entry.
+__global__ void __launch_bounds__(256) k_galerkin_fast2(int cnx, int cny, int cnz,
+                                                        const double* __restrict__ Nt,
+                                                        const double* __restrict__ E,
+                                                        double* __restrict__ Kc) {
+  const int64_t cne = (int64_t)cnx * cny * cnz;
+  const int lane = threadIdx.x & 63, g = lane >> 4, j = lane & 15;
+  const int64_t p0 = (int64_t)blockIdx.x * 64 + 16 * (threadIdx.x >> 6);
+  const int64_t par = p0 + j;
+  const bool live = par < cne;
+  double bop[16];  // B[k = g][col = j] of step s: modulus of descendant 4 s + g of parent par
+  {
+    const int64_t e = live ? par : 0;
+    const int cx = (int)(e % cnx);
+    const int64_t rest = e / cnx;
+    const int cy = (int)(rest % cny), cz = (int)(rest / cny);
+    const int fnx = 4 * cnx, fny = 4 * cny;
+#pragma unroll
+    for (int st = 0; st < 16; ++st) {
+      const int d = 4 * st + g, c1 = d >> 3, c0 = d & 7;
+      const int gx = 4 * cx + 2 * (c1 & 1) + (c0 & 1);
+      const int gy = 4 * cy + 2 * ((c1 >> 1) & 1) + ((c0 >> 1) & 1);
+      const int gz = 4 * cz + 2 * (c1 >> 2) + (c0 >> 2);
+      bop[st] = live ? E[(int64_t)gx + (int64_t)fnx * (gy + (int64_t)fny * gz)] : 0.0;
+    }
+  }
+  if (p0 >= cne) return;  // a whole wavefront past the end (no LDS, no barriers)
+  for (int e0 = 0; e0 < kSym; e0 += 16) {
+    const int ea = e0 + j;  // A[row = j][k = g] = Nt[e0 + j][4 s + g]
+    double aop[16];
+#pragma unroll
+    for (int st = 0; st < 16; ++st) aop[st] = ea < kSym ? Nt[(int64_t)ea * 64 + 4 * st + g] : 0.0;
+    f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int st = 0; st < 16; ++st)
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(aop[st], bop[st], acc, 0, 0, 0);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int ent = e0 + g + 4 * v;
+      if (live && ent < kSym) Kc[(int64_t)ent * cne + par] = acc[v];
+    }
+  }
+}
+
+// Level-1 inverse Jacobi diagonal without the stored matrices of unflagged
+// parents: their diagonal entries are sum_c0 E_c0 M_c0, formed in the order
+// of the level-1 fast path, so the result is the one k_diag_elemmat gives on
+// fully stored matrices.
+__global__ void k_diag_l1(int nx, int ny, int nz, const double* __restrict__ Ke,
+                          const double* __restrict__ Mc, const double* __restrict__ E,
+                          const uint8_t* __restrict__ eflag, double* __restrict__ dinv,
+                          float* __restrict__ dinv32) {
+  const int64_t nn = (int64_t)(nx + 1) * (ny + 1) * (nz + 1);
+  const int64_t ne = (int64_t)nx * ny * nz;
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= nn) return;
+  const int i = (int)(n % (nx + 1));
+  const int64_t rest = n / (nx + 1);
+  const int j = (int)(rest % (ny + 1));
+  const int k = (int)(rest / (ny + 1));
+  const int fnx = 2 * nx, fny = 2 * ny;
+  double d[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int a = 0; a < 8; ++a) {
+    const int ex = i - (a & 1), ey = j - ((a >> 1) & 1), ez = k - (a >> 2);
+    if (ex < 0 || ex >= nx || ey < 0 || ey >= ny || ez < 0 || ez >= nz) continue;
+    const int64_t e = (int64_t)ex + (int64_t)nx * ((int64_t)ey + (int64_t)ny * ez);
+    if (eflag[e]) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) d[c] += Ke[(int64_t)sidx(3 * a + c, 3 * a + c) * ne + e];
+    } else {
+      double w[8];
+#pragma unroll
+      for (int c0 = 0; c0 < 8; ++c0)
+        w[c0] = E[(int64_t)(2 * ex + (c0 & 1)) +
+                  (int64_t)fnx * ((2 * ey + ((c0 >> 1) & 1)) + (int64_t)fny * (2 * ez + (c0 >> 2)))];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        double acc = 0.0;
+#pragma unroll
+        for (int c0 = 0; c0 < 8; ++c0) acc = fma(w[c0], Mc[c0 * kSym + sidx(3 * a + c, 3 * a + c)], acc);
+        d[c] += acc;
+      }
+    }
+  }
+  for (int c = 0; c < 3; ++c) {
+    const double di = d[c] == 0.0 ? 1.0 : 1.0 / d[c];  // dead coarse DOF: identity row
+    dinv[c * nn + n] = di;
+    if (dinv32) dinv32[c * nn + n] = (float)di;
+  }
+}
+
 // Galerkin matrix of one parent per block iteration: the 8 child matrices
 // are staged in LDS, then child by child T_c = K_c P_c is formed by a column
 // pass and P_c^T T_c added by a row pass (registers stay few, so several
-// workgroups share a CU).  FROM_FINE: children are E_c Df KE Df with
-// the fine fixed-DOF mask, for the parents listed by k_parent_flags (the
-// others are exact from the fast path); list entry w < cap is also written to
-// the compact copy Kcomp[entry][w].  Otherwise every parent, with the
-// previous level's packed matrices as children.
-template <bool FROM_FINE>
+// workgroups share a CU).  MODE 1 (from the fine grid): children are
+// E_c Df KE Df with the fine fixed-DOF mask, for the parents listed by
+// k_parent_flags (the others are exact from the fast path); list entry
+// w < cap is also written to the compact copy Kcomp[entry][w].  MODE 0: every
+// parent, with the previous level's packed matrices as children.  MODE 2
+// (level 2): the parents listed by k_parent_flags2; a child flagged in
+// `mask` (the level-1 flags) is read from Kf, the others are formed from
+// their fine moduli as sum_c0 E_c0 M_c0 (KE holds the 8 M_c0), the value
+// the level-1 fast path would have stored.
+template <int MODE>
 __global__ void __launch_bounds__(256) k_galerkin_lds(int cnx, int cny, int cnz,
                                                       const double* __restrict__ KE,
                                                       const double* __restrict__ E,
@@ -100,26 +226,27 @@ __global__ void __launch_bounds__(256) k_galerkin_lds(int cnx, int cny, int cnz,
   __shared__ double sK[8][24][25];
   __shared__ double sT[24][25];
   __shared__ uint8_t sm[27];
-  __shared__ double sw[8];
+  __shared__ double sw[64];
+  constexpr bool FROM_FINE = MODE == 1;
   const int64_t cne = (int64_t)cnx * cny * cnz;
   const int fnx = 2 * cnx, fny = 2 * cny;
   const int64_t fne = cne * 8;
   const int tid = threadIdx.x;
-  const int64_t nwork = FROM_FINE ? (int64_t)*count : cne;
+  const int64_t nwork = MODE != 0 ? (int64_t)*count : cne;
   // XCD-aware order (every parent): workgroups are dispatched round-robin
   // over the 8 XCDs, so XCD x takes a contiguous range of parents and its
   // workgroups walk it together.  Neighbouring parents read their children
   // from the same cache lines (the children of 8 parents along x share one
   // 128-byte line of each packed entry), which then meet in one L2.
   int64_t w0 = blockIdx.x, w1 = nwork, ws = gridDim.x;
-  if (!FROM_FINE && gridDim.x >= 8) {
+  if (MODE == 0 && gridDim.x >= 8) {
     const int x = blockIdx.x & 7, nbx = (int)(gridDim.x >> 3) + (x < (int)(gridDim.x & 7) ? 1 : 0);
     w0 = nwork * x / 8 + (blockIdx.x >> 3);
     w1 = nwork * (x + 1) / 8;
     ws = nbx;
   }
   for (int64_t w = w0; w < w1; w += ws) {
-  const int64_t eid = FROM_FINE ? (int64_t)list[w] : w;
+  const int64_t eid = MODE != 0 ? (int64_t)list[w] : w;
   const int cx = (int)(eid % cnx);
   const int64_t rest = eid / cnx;
   const int cy = (int)(rest % cny), cz = (int)(rest / cny);
@@ -131,6 +258,21 @@ __global__ void __launch_bounds__(256) k_galerkin_lds(int cnx, int cny, int cnz,
     if (tid < 8)
       sw[tid] = E[(int64_t)(2 * cx + (tid & 1)) +
                   (int64_t)fnx * ((2 * cy + ((tid >> 1) & 1)) + (int64_t)fny * (2 * cz + (tid >> 2)))];
+    __syncthreads();
+  }
+  if (MODE == 2) {  // child flags, and the moduli of the 64 fine descendants
+    if (tid < 8) {
+      const int64_t ce = (int64_t)(2 * cx + (tid & 1)) +
+                         (int64_t)fnx * ((2 * cy + ((tid >> 1) & 1)) + (int64_t)fny * (2 * cz + (tid >> 2)));
+      sm[tid] = mask[ce];
+    }
+    if (tid < 64) {
+      const int c1 = tid >> 3, c0 = tid & 7;
+      const int gx = 4 * cx + 2 * (c1 & 1) + (c0 & 1);
+      const int gy = 4 * cy + 2 * ((c1 >> 1) & 1) + ((c0 >> 1) & 1);
+      const int gz = 4 * cz + 2 * (c1 >> 2) + (c0 >> 2);
+      sw[tid] = E[(int64_t)gx + (int64_t)(2 * fnx) * (gy + (int64_t)(2 * fny) * gz)];
+    }
     __syncthreads();
   }
   // the 8 x 576 child entries, 18 per thread, all loads in flight before
@@ -147,6 +289,11 @@ __global__ void __launch_bounds__(256) k_galerkin_lds(int cnx, int cny, int cnz,
       const int pq = (dx + (bq & 1)) + 3 * (dy + ((bq >> 1) & 1)) + 9 * (dz + (bq >> 2));
       const bool fx = ((sm[pr] >> (r % 3)) & 1) || ((sm[pq] >> (q % 3)) & 1);
       lv[u] = fx ? 0.0 : sw[c] * KE[r * 24 + q];
+    } else if (MODE == 2 && !sm[c]) {
+      double acc = 0.0;  // the level-1 fast path's sum, in its order
+#pragma unroll
+      for (int c0 = 0; c0 < 8; ++c0) acc = fma(sw[8 * c + c0], KE[c0 * kSym + sidx(r, q)], acc);
+      lv[u] = acc;
     } else {
       const int64_t fe = (int64_t)(2 * cx + dx) + (int64_t)fnx * ((2 * cy + dy) + (int64_t)fny * (2 * cz + dz));
       lv[u] = Kf[(int64_t)sidx(r, q) * fne + fe];
@@ -929,8 +1076,6 @@ __global__ void __launch_bounds__(256) k_assemble_dense(int nx, int ny, int nz,
 // After the last block the stored upper triangle is A^-1 and the lower
 // triangle is filled by transposition.
 
-typedef double f64x4 __attribute__((ext_vector_type(4)));
-
 // 1/x from the hardware reciprocal estimate and two Newton steps.
 __device__ __forceinline__ double recip(double x) {
   double r = __builtin_amdgcn_rcp(x);
@@ -1402,14 +1547,33 @@ __global__ void __launch_bounds__(256) k_gemv(int n, const double* __restrict__ 
 
 void launch_galerkin_from_fine(const Grid& coarse, const double* KE, const double* Mc,
                                const double* E, const uint8_t* mask, uint8_t* eflag, int* list,
-                               int* count, double* Kc, double* Kcomp, int cap, hipStream_t s) {
-  k_galerkin_fast<<<nblk(coarse.ne, 64), 256, 0, s>>>(coarse.nx, coarse.ny, coarse.nz, Mc, E, Kc);
+                               int* count, double* Kc, double* Kcomp, int cap, hipStream_t s,
+                               bool all) {
+  if (all)
+    k_galerkin_fast<<<nblk(coarse.ne, 64), 256, 0, s>>>(coarse.nx, coarse.ny, coarse.nz, Mc, E,
+                                                        Kc);
   k_zero_int<<<1, 1, 0, s>>>(count);
   k_parent_flags<<<nblk(coarse.ne, 256), 256, 0, s>>>(coarse.nx, coarse.ny, coarse.nz, mask, eflag,
                                                        list, count);
   const unsigned grid = (unsigned)std::min<int64_t>(coarse.ne, 2048);
-  k_galerkin_lds<true><<<grid, 256, 0, s>>>(coarse.nx, coarse.ny, coarse.nz, KE, E, mask, list,
+  k_galerkin_lds<1><<<grid, 256, 0, s>>>(coarse.nx, coarse.ny, coarse.nz, KE, E, mask, list,
                                             count, nullptr, Kc, Kcomp, cap);
+}
+
+void launch_galerkin_l2_from_fine(const Grid& l2, const double* N2, const double* Mc,
+                                  const double* E, const uint8_t* eflag1, int* list2, int* count2,
+                                  const double* K1, double* K2, hipStream_t s) {
+  k_galerkin_fast2<<<nblk(l2.ne, 64), 256, 0, s>>>(l2.nx, l2.ny, l2.nz, N2, E, K2);
+  k_zero_int<<<1, 1, 0, s>>>(count2);
+  k_parent_flags2<<<nblk(l2.ne, 256), 256, 0, s>>>(l2.nx, l2.ny, l2.nz, eflag1, list2, count2);
+  const unsigned grid = (unsigned)std::min<int64_t>(l2.ne, 2048);
+  k_galerkin_lds<2><<<grid, 256, 0, s>>>(l2.nx, l2.ny, l2.nz, Mc, E, eflag1, list2, count2, K1,
+                                         K2, nullptr, 0);
+}
+
+void launch_diag_l1(const Grid& g, const double* Ke, const double* Mc, const double* E,
+                    const uint8_t* eflag, double* dinv, float* dinv32, hipStream_t s) {
+  k_diag_l1<<<nblk(g.nn, 256), 256, 0, s>>>(g.nx, g.ny, g.nz, Ke, Mc, E, eflag, dinv, dinv32);
 }
 
 void launch_galerkin_from_coarse(const Grid& coarse, const double* Kf, double* Kc, hipStream_t s) {
@@ -1422,7 +1586,7 @@ void launch_galerkin_from_coarse(const Grid& coarse, const double* Kf, double* K
   }
   // fewer groups than CUs: one parent per workgroup keeps more of the chip busy
   const unsigned grid = (unsigned)std::min<int64_t>(coarse.ne, 4096);
-  k_galerkin_lds<false><<<grid, 256, 0, s>>>(coarse.nx, coarse.ny, coarse.nz, nullptr, nullptr,
+  k_galerkin_lds<0><<<grid, 256, 0, s>>>(coarse.nx, coarse.ny, coarse.nz, nullptr, nullptr,
                                              nullptr, nullptr, nullptr, Kf, Kc, nullptr, 0);
 }
 
