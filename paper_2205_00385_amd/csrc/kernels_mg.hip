@@ -569,9 +569,12 @@ __device__ __forceinline__ void wht8(T* x, int s) {
       }
 }
 
-// Level-1 element products, pass 1: Y[q][e] = (Ke_e v_e)[q], one thread per
-// parent element e and output component s (grid.y), which writes the entries
-// q = 3a + s.  Parents without a fixed DOF among their fine nodes have
+// Level-1 element products, pass 1: Y[q][e] = (Ke_e v_e)[q].  SO = 0..2: one
+// thread per parent element e and output component SO, which writes the
+// entries q = 3a + SO; SO = 3: one thread per parent, all 24 entries (the
+// inputs, their transforms and the moduli's are then formed once, not three
+// times; on large levels that is faster, on small ones three times the
+// threads fill the chip better).  Parents without a fixed DOF among their fine nodes have
 // Ke_e = sum_c E_c M_c with M_c = R_c M_0 R_c (R_c the mirror map of child c).
 // In the Walsh basis over the 8 corners (index 3k + s), R_c is the diagonal
 // sign (-1)^popcount(c & mu), mu(k, s) = k ^ (1 << s), so
@@ -579,14 +582,15 @@ __device__ __forceinline__ void wht8(T* x, int s) {
 // with B' = W M_0 W / 64 and Ehat the Walsh transform of the 8 child moduli:
 // y = W ((B' o Ehat) (W v)), about 256 FMA per thread.  Parents with eflag 1
 // are left to l1_masked_rows, so no wave carries both paths.
-template <typename T, int so>
+template <typename T, int SO>
 __device__ __forceinline__ void l1_elem(int nx, int ny, int nz, const double* __restrict__ Ke,
                                         const T* __restrict__ Bw, const T* __restrict__ Ef,
                                         const uint8_t* __restrict__ eflag,
-                                        const T* __restrict__ v, T* __restrict__ Y) {
+                                        const T* __restrict__ v, T* __restrict__ Y, int nbe) {
   const int64_t nn = (int64_t)(nx + 1) * (ny + 1) * (nz + 1);
   const int64_t ne = (int64_t)nx * ny * nz;
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t e = SO == 3 ? ((int64_t)blockIdx.y * nbe + blockIdx.x) * blockDim.x + threadIdx.x
+                            : (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= ne || eflag[e]) return;  // flagged parents: l1_masked_rows
   const int ex = (int)(e % nx);
   const int64_t rest = e / nx;
@@ -598,7 +602,6 @@ __device__ __forceinline__ void l1_elem(int nx, int ny, int nz, const double* __
 #pragma unroll
     for (int c = 0; c < 3; ++c) x[3 * b + c] = v[c * nn + nb];
   }
-  T y[8];  // entries 3a + so
   {
     T Eh[8];
     const int fnx = 2 * nx, fny = 2 * ny;
@@ -617,35 +620,40 @@ __device__ __forceinline__ void l1_elem(int nx, int ny, int nz, const double* __
         }
 #pragma unroll
     for (int s = 0; s < 3; ++s) wht8(x, s);
-    const T* B = Bw + so * 24;  // row kappa = 3k + so starts at B + 72k
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const int muk = k ^ (1 << so);
-      T acc = 0;
+    for (int so = 0; so < 3; ++so) {  // output component: entries 3a + so
+      if (SO != 3 && so != SO) continue;
+      const T* B = Bw + so * 24;       // row kappa = 3k + so starts at B + 72k
+      T y[8];
 #pragma unroll
-      for (int mm = 0; mm < 8; ++mm) {
-        T t = 0;
+      for (int k = 0; k < 8; ++k) {
+        const int muk = k ^ (1 << so);
+        T acc = 0;
 #pragma unroll
-        for (int s2 = 0; s2 < 3; ++s2) {
-          const int la = 3 * (muk ^ mm ^ (1 << s2)) + s2;
-          t = fma(B[72 * k + la], x[la], t);
+        for (int mm = 0; mm < 8; ++mm) {
+          T t = 0;
+#pragma unroll
+          for (int s2 = 0; s2 < 3; ++s2) {
+            const int la = 3 * (muk ^ mm ^ (1 << s2)) + s2;
+            t = fma(B[72 * k + la], x[la], t);
+          }
+          acc = fma(Eh[mm], t, acc);
         }
-        acc = fma(Eh[mm], t, acc);
+        y[k] = acc;
       }
-      y[k] = acc;
+#pragma unroll
+      for (int bit = 1; bit < 8; bit <<= 1)
+#pragma unroll
+        for (int a = 0; a < 8; ++a)
+          if (!(a & bit)) {
+            const T p = y[a], q = y[a | bit];
+            y[a] = p + q;
+            y[a | bit] = p - q;
+          }
+#pragma unroll
+      for (int a = 0; a < 8; ++a) Y[(int64_t)(3 * a + so) * ne + e] = y[a];
     }
-#pragma unroll
-    for (int bit = 1; bit < 8; bit <<= 1)
-#pragma unroll
-      for (int a = 0; a < 8; ++a)
-        if (!(a & bit)) {
-          const T p = y[a], q = y[a | bit];
-          y[a] = p + q;
-          y[a | bit] = p - q;
-        }
   }
-#pragma unroll
-  for (int a = 0; a < 8; ++a) Y[(int64_t)(3 * a + so) * ne + e] = y[a];
 }
 
 // Level-1 element products of the flagged parents (list[0..cnt)) from their
@@ -697,8 +705,9 @@ __device__ __forceinline__ void l1_masked_rows(int nx, int ny, int nz,
 }
 
 // Pass 1 in one launch: workgroups x < nbe run the element path (grid.y:
-// output component); the rest run the flagged parents, two per grid.y, each
-// with four rows (one per wavefront) of a 16-entry chunk of the list.
+// output component, or with all3 a third of the elements each); the rest
+// run the flagged parents, two per grid.y, each with four rows (one per
+// wavefront) of a 16-entry chunk of the list.
 template <typename T>
 __global__ void __launch_bounds__(256) k_l1_elem(int nx, int ny, int nz,
                                                  const double* __restrict__ Ke,
@@ -708,7 +717,7 @@ __global__ void __launch_bounds__(256) k_l1_elem(int nx, int ny, int nz,
                                                  const T* __restrict__ v, T* __restrict__ Y,
                                                  int nbe, const double* __restrict__ Kcomp,
                                                  int cap, const int* __restrict__ list, int cnt,
-                                                 int64_t rs = 0, int64_t Ys = 0) {
+                                                 int all3, int64_t rs = 0, int64_t Ys = 0) {
   v += (int64_t)blockIdx.z * rs;  // load case blockIdx.z
   Y += (int64_t)blockIdx.z * Ys;
   if ((int)blockIdx.x >= nbe) {  // workgroup-uniform
@@ -718,10 +727,14 @@ __global__ void __launch_bounds__(256) k_l1_elem(int nx, int ny, int nz,
                       ((int)gridDim.x - nbe) >> 1, r);
     return;
   }
+  if (all3) {
+    l1_elem<T, 3>(nx, ny, nz, Ke, Bw, Ef, eflag, v, Y, nbe);
+    return;
+  }
   switch (blockIdx.y) {  // output component
-    case 0: l1_elem<T, 0>(nx, ny, nz, Ke, Bw, Ef, eflag, v, Y); break;
-    case 1: l1_elem<T, 1>(nx, ny, nz, Ke, Bw, Ef, eflag, v, Y); break;
-    default: l1_elem<T, 2>(nx, ny, nz, Ke, Bw, Ef, eflag, v, Y); break;
+    case 0: l1_elem<T, 0>(nx, ny, nz, Ke, Bw, Ef, eflag, v, Y, nbe); break;
+    case 1: l1_elem<T, 1>(nx, ny, nz, Ke, Bw, Ef, eflag, v, Y, nbe); break;
+    default: l1_elem<T, 2>(nx, ny, nz, Ke, Bw, Ef, eflag, v, Y, nbe); break;
   }
 }
 
@@ -1609,17 +1622,23 @@ void launch_apply_elemmat_f32(const Grid& g, const float* Ke, const float* v, fl
 }
 
 // nr load cases in lock step: vectors [nr][3 nn], element products [nr][24][ne]
+constexpr int64_t kL1All3 = 200000;
 template <typename T>
 void l1_apply(const Grid& g, const double* Ke, const double* Kcomp, int cap, const T* Bw,
               const T* Ef, const uint8_t* eflag, const int* list, const int* count, int nflag,
               const T* v, T* Y, T* y, hipStream_t s, const T* jb = nullptr,
               const T* jd = nullptr, T omega = 0, int nr = 1) {
   // nflag: the flagged-parent count, known to the host after setup
-  const int nbe = (int)nblk(g.ne, 256);
+  // one thread per element from kL1All3 elements up (256x128x128, level 1:
+  // 41.6 -> 33.2 us per call in FP32, 60 -> 49.5 us in FP64); per (element,
+  // component) below, where the 96x48x48 loop's level 1 measured faster
+  const int all3 = g.ne >= kL1All3 ? 1 : 0;
+  const int nbe = (int)nblk(g.ne, all3 ? 3 * 256 : 256);
   const int nbm = nflag > 0 ? 2 * (int)std::min<int64_t>(nblk(nflag, 16), 1024) : 0;
   const int64_t rs = 3 * g.nn, Ys = 24 * g.ne;
   k_l1_elem<T><<<dim3(nbe + nbm, 3, nr), 256, 0, s>>>(g.nx, g.ny, g.nz, Ke, Bw, Ef, eflag, v, Y,
-                                                      nbe, Kcomp, cap, list, nflag, rs, Ys);
+                                                      nbe, Kcomp, cap, list, nflag, all3, rs,
+                                                      Ys);
   k_l1_gather<T><<<dim3(nblk(g.nn, 256), 1, nr), 256, 0, s>>>(g.nx, g.ny, g.nz, Y, y, jb, jd,
                                                               omega, rs, Ys);
 }
