@@ -158,6 +158,52 @@ def test_precision_form_full_size_certificate():
     assert abs(c32 - c64) <= 1e-6 * c64
 
 
+@pytest.mark.parametrize("levels", [5, 6])
+def test_full_size_level1_operator_and_vcycle_symmetric(levels):
+    """The kernels that take over on large grids only (the separable
+    restriction and the LDS-staged interpolation, from 1e5 coarse / 1e6 fine
+    nodes; the per-element level-1 product, from 2e5 level-1 elements; the
+    level-2 matrices from the fine moduli) at 256x128x128: the level-1
+    Galerkin operator and the V-cycle are symmetric, <A x, y> = <x, A y>
+    and <M x, y> = <x, M y>, which fails if a restriction weight or index
+    differs from the interpolation's or if an element's output entries are
+    misplaced; A_1 is positive definite on random vectors."""
+    aarmr = _aarmr()
+    dims = (256, 128, 128)
+    log(f"full-size symmetry, {levels} levels")
+    prob = synth.cantilever(*dims)
+    rho = synth.smoothed_field(*dims, 8.0, 1e-3, 1.0, seed=3).ravel()
+    m = _mesh(prob, autotune=False, mg_levels=levels)
+    fx = _fixed(prob, m)
+    m.setup(t64(rho), fx)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(31)
+    n1 = 3 * (dims[0] // 2 + 1) * (dims[1] // 2 + 1) * (dims[2] // 2 + 1)
+    x1 = torch.randn(n1, dtype=torch.float64, device="cuda", generator=g)
+    y1 = torch.randn(n1, dtype=torch.float64, device="cuda", generator=g)
+    ax = torch.empty_like(x1)
+    ay = torch.empty_like(y1)
+    m.apply(x1, ax, level=1)
+    m.apply(y1, ay, level=1)
+    lhs, rhs = float(ax @ y1), float(x1 @ ay)
+    assert abs(lhs - rhs) <= 1e-12 * (float(ax.norm()) * float(y1.norm()))
+    assert float(ax @ x1) > 0.0
+    n0 = 3 * m.n_node
+    x = torch.randn(n0, dtype=torch.float64, device="cuda", generator=g)
+    y = torch.randn(n0, dtype=torch.float64, device="cuda", generator=g)
+    x[fx] = 0.0
+    y[fx] = 0.0
+    zx = torch.empty_like(x)
+    zy = torch.empty_like(y)
+    m.vcycle(x, zx)
+    m.vcycle(y, zy)
+    lhs, rhs = float(zx @ y), float(x @ zy)
+    log(f"  <Mx,y> {lhs:.12e}  <x,My> {rhs:.12e}")
+    assert abs(lhs - rhs) <= 1e-11 * (float(zx.norm()) * float(y.norm()))
+    assert float(zx @ x) > 0.0
+    m.close()
+
+
 def test_zero_load_gives_zero_solution():
     """Degenerate case: no load, u = 0, C = 0 and dc = 0 without iterating."""
     aarmr = _aarmr()
