@@ -888,10 +888,10 @@ __device__ inline float wave_shift(float x) {
 // (DPP neighbours), along y through LDS and along z in registers.  Per
 // coarse node the sum is formed as m + (l + r) / 2 along x, then y, then z:
 // a fixed order, so results are deterministic, and equal to the per-node
-// sum of the other kernel up to rounding.  blockIdx.x: (tile, K) with K
+// sum of the other kernel up to rounding.  All three components in one
+// workgroup (one mask load per fine node).  blockIdx.x: (tile, K) with K
 // fastest, in XCD-contiguous order, so the fine plane 2K+1 that planes K
-// and K+1 share is read twice through one L2; blockIdx.y: component;
-// blockIdx.z: load case.
+// and K+1 share is read twice through one L2; blockIdx.z: load case.
 constexpr int kRsCI = 31;
 constexpr int kRsCJ = 8;
 constexpr int kRsRows = 2 * kRsCJ + 1;
@@ -904,7 +904,7 @@ __global__ void __launch_bounds__(256) k_restrict_z(int cnx, int cny, int cnz, i
                                                     T* __restrict__ bc, const T* __restrict__ dc,
                                                     T omega, T* __restrict__ xc, int64_t fs,
                                                     int64_t cs) {
-  __shared__ T xr[3][kRsRows][32];
+  __shared__ T xr[3][3][kRsRows][32];  // [component][plane][row][coarse column]
   {  // load case blockIdx.z
     const int64_t fo = (int64_t)blockIdx.z * fs, co = (int64_t)blockIdx.z * cs;
     bf += fo;
@@ -912,7 +912,6 @@ __global__ void __launch_bounds__(256) k_restrict_z(int cnx, int cny, int cnz, i
     bc += co;
     if (xc) xc += co;
   }
-  const int c = blockIdx.y;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   int bx, by, K;
   {
@@ -931,10 +930,9 @@ __global__ void __launch_bounds__(256) k_restrict_z(int cnx, int cny, int cnz, i
   const int64_t fplane = (int64_t)(fnx + 1) * (fny + 1);
   const int fx = 2 * I0 - 1 + lane;
   const bool xok = lane < 2 * kRsCI + 1 && fx >= 0 && fx <= fnx;
-  const T* b = bf + c * fnn;
-  const T* tt = tf ? tf + c * fnn : nullptr;
-  // Df (b - t) at this lane's node of rows w + 4q of fine planes 2K-1+dz; 0 outside
-  T v[3][kRsRowsPerWave];
+  // Df (b - t) at this lane's node of rows w + 4q of fine planes 2K-1+dz, all
+  // three components (one mask load per node); 0 outside
+  T v[3][3][kRsRowsPerWave];
 #pragma unroll
   for (int dz = 0; dz < 3; ++dz)
 #pragma unroll
@@ -942,32 +940,41 @@ __global__ void __launch_bounds__(256) k_restrict_z(int cnx, int cny, int cnz, i
       const int r = w + 4 * q, fy = 2 * J0 - 1 + r, fz = 2 * K - 1 + dz;
       const bool ok = r < kRsRows && xok && fy >= 0 && fy <= fny && fz >= 0 && fz <= fnz;
       const int64_t f = (int64_t)fz * fplane + (int64_t)fy * (fnx + 1) + fx;
-      T val = ok ? b[f] : T(0);
-      if (tt) val -= ok ? tt[f] : T(0);
-      if (mask && ok && ((mask[f] >> c) & 1)) val = T(0);
-      v[dz][q] = val;
+      const uint32_t mk = (mask && ok) ? mask[f] : 0u;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        T val = ok ? bf[c * fnn + f] : T(0);
+        if (tf) val -= ok ? tf[c * fnn + f] : T(0);
+        v[c][dz][q] = ((mk >> c) & 1u) ? T(0) : val;
+      }
     }
   // along x: odd lanes 2i+1 hold coarse column i
 #pragma unroll
-  for (int dz = 0; dz < 3; ++dz)
+  for (int c = 0; c < 3; ++c)
 #pragma unroll
-    for (int q = 0; q < kRsRowsPerWave; ++q) {
-      const int r = w + 4 * q;
-      const T l = wave_shift<0x138>(v[dz][q]), rr = wave_shift<0x130>(v[dz][q]);
-      const T sx = v[dz][q] + T(0.5) * (l + rr);
-      if (r < kRsRows && (lane & 1) && lane < 2 * kRsCI) xr[dz][r][lane >> 1] = sx;
-    }
+    for (int dz = 0; dz < 3; ++dz)
+#pragma unroll
+      for (int q = 0; q < kRsRowsPerWave; ++q) {
+        const int r = w + 4 * q;
+        const T l = wave_shift<0x138>(v[c][dz][q]), rr = wave_shift<0x130>(v[c][dz][q]);
+        const T sx = v[c][dz][q] + T(0.5) * (l + rr);
+        if (r < kRsRows && (lane & 1) && lane < 2 * kRsCI) xr[c][dz][r][lane >> 1] = sx;
+      }
   __syncthreads();
   const int ci = threadIdx.x & 31, cj = threadIdx.x >> 5;  // this thread's coarse node
   if (ci >= kRsCI || I0 + ci > cnx || J0 + cj > cny) return;
-  T sy[3];
-#pragma unroll
-  for (int dz = 0; dz < 3; ++dz)
-    sy[dz] = xr[dz][2 * cj + 1][ci] + T(0.5) * (xr[dz][2 * cj][ci] + xr[dz][2 * cj + 2][ci]);
-  const T acc = sy[1] + T(0.5) * (sy[0] + sy[2]);
   const int64_t n = (int64_t)K * (cnx + 1) * (cny + 1) + (int64_t)(J0 + cj) * (cnx + 1) + I0 + ci;
-  bc[c * cnn + n] = acc;
-  if (xc) xc[c * cnn + n] = omega * dc[c * cnn + n] * acc;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    T sy[3];
+#pragma unroll
+    for (int dz = 0; dz < 3; ++dz)
+      sy[dz] = xr[c][dz][2 * cj + 1][ci] +
+               T(0.5) * (xr[c][dz][2 * cj][ci] + xr[c][dz][2 * cj + 2][ci]);
+    const T acc = sy[1] + T(0.5) * (sy[0] + sy[2]);
+    bc[c * cnn + n] = acc;
+    if (xc) xc[c * cnn + n] = omega * dc[c * cnn + n] * acc;
+  }
 }
 
 // xf += Df P xc: thread per fine node, branch-free over the (up to) 8
@@ -1755,8 +1762,7 @@ void launch_apply_l1_jacobi_f32(const Grid& g, const double* Ke, const double* K
                   omega, nr);
 }
 
-// 3D restriction launch: one workgroup per (tile, coarse plane, component,
-// case).  Used from kRsMinNodes coarse nodes up; on smaller grids, where a
+// 3D restriction launch: one workgroup per (tile, coarse plane, case).  Used from kRsMinNodes coarse nodes up; on smaller grids, where a
 // launch is a few microseconds either way, the per-node kernel measured
 // faster (256x128x128, FP32: fine level 90 -> 68 us and second level 13.1 ->
 // 11.0 us with this kernel; third to fifth level 6.1/5.2/4.7 -> 8.2/6.9/5.2).
@@ -1767,7 +1773,7 @@ static void restrict_z(const Grid& coarse, const T* bf, const T* tf, const uint8
                        int64_t cs) {
   const int gx = (coarse.nx + 1 + kRsCI - 1) / kRsCI;
   const int gy = (coarse.ny + 1 + kRsCJ - 1) / kRsCJ;
-  k_restrict_z<T><<<dim3((unsigned)(gx * gy * (coarse.nz + 1)), 3, (unsigned)nr), 256, 0, s>>>(
+  k_restrict_z<T><<<dim3((unsigned)(gx * gy * (coarse.nz + 1)), 1, (unsigned)nr), 256, 0, s>>>(
       coarse.nx, coarse.ny, coarse.nz, gx, bf, tf, mask, bc, dc, omega, xc, fs, cs);
 }
 
