@@ -69,6 +69,50 @@ def test_lockstep_cases_equal_single_case_solves(dims, n_case, levels):
     single.close()
 
 
+def test_lockstep_large_grid_kernels():
+    """Lock step on a grid where the large-grid kernels take over (the
+    separable restriction from 1e5 coarse nodes, the LDS-staged interpolation
+    from 1e6 fine nodes, the per-element level-1 product from 2e5 level-1
+    elements), whose load-case strides only the lock-step solve exercises:
+    160x112x112, 3 cases, 5 levels.  Every case gets the bits of its own
+    single-case solve, and the oracle's FP64 residual of each meets 1e-8."""
+    aarmr = _aarmr()
+    dims = (160, 112, 112)
+    log(f"lock-step large grid {dims}")
+    prob = synth.point_loads_on_face(*dims, n_case=3, seed=85)
+    rho = synth.smoothed_field(*dims, 6.0, 1e-3, 1.0, seed=86).ravel()
+    multi = mesh_for(prob, mg_levels=5, n_rhs_max=3, precision=aarmr.FP32_REFINE)
+    single = mesh_for(prob, mg_levels=5, n_rhs_max=1, precision=aarmr.FP32_REFINE)
+    fixed = fixed_tensor(prob, multi)
+    fl = _loads(prob, multi, None)
+    f = t64(np.concatenate(fl))
+    u = torch.zeros_like(f)
+    C, st, code = multi.solve(t64(rho), f, fixed, u)
+    assert code == 0
+    n3 = 3 * multi.n_node
+    fx = fem.fixed_dofs_aos(prob)
+    edof = fem.element_dofs_grid(*dims)
+    Ee = fem.simp(rho)
+    for l in range(3):
+        u1 = torch.zeros(n3, dtype=torch.float64, device="cuda")
+        C1, st1, code1 = single.solve(t64(rho), t64(fl[l]), fixed, u1)
+        assert code1 == 0
+        log(f"  case {l}: lock-step {st.iterations[l]} its, alone {st1.iterations[0]} its")
+        assert torch.equal(u[l * n3:(l + 1) * n3], u1), f"case {l} differs from its own solve"
+        assert C[l] == C1[0]
+        ua = fem.soa_to_aos(u1.cpu().numpy())
+        fa = fem.dof_vector_aos(prob, l)
+        fa[fx] = 0.0
+        um = ua.copy()
+        um[fx] = 0.0
+        Au = fem.apply_ebe(*dims, Ee, fem.hex8_ke(), um, edof)
+        Au[fx] = ua[fx]
+        res = np.linalg.norm(fa - Au) / np.linalg.norm(fa)
+        assert res <= 1.05e-8, f"case {l}: oracle residual {res:.3e}"
+    multi.close()
+    single.close()
+
+
 def test_lockstep_with_a_zero_load_case():
     aarmr = _aarmr()
     dims = (16, 8, 8)
