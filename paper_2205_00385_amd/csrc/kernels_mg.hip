@@ -27,6 +27,16 @@ constexpr int kSym = kSymEntries;
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 __host__ __device__ constexpr int sidx(int r, int c) { return sym_index(r, c); }
 
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own
+// L2.  Workgroup w of `total` is given slot (w % 8) * (total / 8) + w / 8
+// (the remainder spread over the first XCDs), so every XCD walks one
+// contiguous range of slots and data shared by neighbouring slots meets in
+// one L2.
+__device__ __forceinline__ int xcd_slot(int w, int total) {
+  const int xcd = w & 7, pos = w >> 3, q = total >> 3, r = total & 7;
+  return (xcd < r) ? xcd * (q + 1) + pos : r * (q + 1) + (xcd - r) * q + pos;
+}
+
 // Level-1 Galerkin matrices, fast path: Kc = sum_c E_c M_c with
 // M_c = P_c^T KE P_c precomputed (P_c the trilinear map from the parent's
 // corners to child c's corners).  Exact for parents whose 27 fine nodes are
@@ -494,7 +504,9 @@ __global__ void __launch_bounds__(256) k_galerkin_row8(int cnx, int cny, int cnz
 // forms rows 3a..3a+2 of Ke_e v_e; the 8 partial rows are summed in LDS in a
 // fixed order.  Vectors of type T, matrices of type KT (FP64, or the FP32
 // copy the refinement form keeps, which holds the values the FP32 product
-// would round them to anyway).
+// would round them to anyway).  Blocks in XCD-contiguous order: the two
+// copies of a symmetric entry are read by the waves of two corners, for
+// nodes up to a plane apart, and are then fetched into one L2 only.
 // With jb non-null the product feeds a damped-Jacobi sweep instead:
 // y = v + omega jd (jb - A v) (y distinct from v).
 template <typename T, typename KT = double>
@@ -516,7 +528,7 @@ __global__ void __launch_bounds__(512) k_apply_elemmat(int nx, int ny, int nz,
   const int lane = threadIdx.x & 63;
   const int64_t nn = (int64_t)(nx + 1) * (ny + 1) * (nz + 1);
   const int64_t ne = (int64_t)nx * ny * nz;
-  const int64_t n = (int64_t)blockIdx.x * 64 + lane;
+  const int64_t n = (int64_t)xcd_slot(blockIdx.x, gridDim.x) * 64 + lane;
   T acc0 = 0, acc1 = 0, acc2 = 0;
   if (n < nn) {
     const int i = (int)(n % (nx + 1));
