@@ -67,6 +67,17 @@ def test_prolongation_reproduces_linear_fields():
     assert np.allclose(P.sum(axis=0).A.ravel().max(), 8.0)
 
 
+def test_prolongation_kron_equals_node_loop():
+    """The Kronecker-built interpolation is the node-loop one, entry for
+    entry, on grids with unequal and odd/even extents."""
+    for dims in ((1, 1, 1), (3, 2, 2), (2, 5, 3), (4, 1, 6)):
+        A = mg.prolongation(*dims)
+        B = mg.prolongation_kron(*dims)
+        assert A.shape == B.shape
+        assert abs(A - B).max() == 0.0
+        assert A.nnz == B.nnz
+
+
 def _setup(dims, levels, seed=0):
     prob = synth.cantilever(*dims)
     rho = np.random.default_rng(seed).uniform(0.3, 1.0, prob.n_elem)
