@@ -218,10 +218,8 @@ void launch_gemv_f32(int n, const double* A, const float* x, float* y, hipStream
 // ---- vector kernels and reductions ----------------------------------------
 void launch_multidot(const DotSet& d, const RedScratch& rs, hipStream_t s);
 void launch_multidot_f32(const DotSetT<float>& d, const RedScratch& rs, hipStream_t s);
-// FP32 CG updates; the scalars stay FP64 in device memory and the updates are
-// formed in FP64 before rounding to FP32.
-void launch_cg_xr_f32(int64_t n, const double* rz, const double* pq, float* x, float* r,
-                      const float* p, const float* q, hipStream_t s);
+// FP32 direction update after a separate r^T z; the scalars stay FP64 in
+// device memory and the update is formed in FP64 before rounding to FP32.
 void launch_cg_p_f32(int64_t n, const double* rz_new, const double* rz_old, const float* z,
                      float* p, hipStream_t s);
 // Refinement transfers: dst32 = src64 / sqrt(*nrm2);  x64 += sqrt(*nrm2) d32.

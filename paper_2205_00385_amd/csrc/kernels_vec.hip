@@ -234,17 +234,6 @@ __global__ void k_scale_inv_sqrt(int64_t n, const double* __restrict__ src,
   dst[i] = src[i] * s;
 }
 
-__global__ void k_cg_xr_f32(int64_t n, const double* __restrict__ rz,
-                            const double* __restrict__ pq, float* __restrict__ x,
-                            float* __restrict__ r, const float* __restrict__ p,
-                            const float* __restrict__ q) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const double alpha = *rz / *pq;
-  x[i] = (float)fma(alpha, (double)p[i], (double)x[i]);
-  r[i] = (float)fma(-alpha, (double)q[i], (double)r[i]);
-}
-
 __global__ void k_cg_p_f32(int64_t n, const double* __restrict__ rz_new,
                            const double* __restrict__ rz_old, const float* __restrict__ z,
                            float* __restrict__ p) {
@@ -457,11 +446,6 @@ void launch_cg_p_fused(int64_t n, const double* rz_part, int n_part, double* rz_
 
 void launch_multidot_f32(const DotSetT<float>& d, const RedScratch& rs, hipStream_t s) {
   multidot_t<float>(d, rs, s);
-}
-
-void launch_cg_xr_f32(int64_t n, const double* rz, const double* pq, float* x, float* r,
-                      const float* p, const float* q, hipStream_t s) {
-  k_cg_xr_f32<<<nblk(n, 256), 256, 0, s>>>(n, rz, pq, x, r, p, q);
 }
 
 void launch_cg_xr_fused_f32(int64_t n, const double* rz, const double* pq_part, int n_part,
