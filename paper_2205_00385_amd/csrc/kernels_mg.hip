@@ -892,31 +892,38 @@ __device__ inline float wave_shift(float x) {
   return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), CTRL, 0xF, 0xF, true));
 }
 
-// The same restriction on 3D grids, separably: a workgroup forms one coarse
-// plane K of a tile of kRsCI x kRsCJ coarse nodes.  It loads the tile's rows
-// of fine planes 2K-1, 2K and 2K+1 at once (one fine node per lane, 63
-// nodes of a row on lanes 0..62, whole rows, coalesced; the 2 kRsCJ + 1
-// rows spread over the four wavefronts), restricts along x in registers
-// (DPP neighbours), along y through LDS and along z in registers.  Per
-// coarse node the sum is formed as m + (l + r) / 2 along x, then y, then z:
-// a fixed order, so results are deterministic, and equal to the per-node
-// sum of the other kernel up to rounding.  All three components in one
-// workgroup (one mask load per fine node).  blockIdx.x: (tile, K) with K
-// fastest, in XCD-contiguous order, so the fine plane 2K+1 that planes K
-// and K+1 share is read twice through one L2; blockIdx.z: load case.
+// The same restriction on large 3D grids, separably and as a z-march: a
+// workgroup takes a tile of kRsCI x kRsCJ coarse columns and a chunk of
+// coarse planes [K0, K1), and reads each fine plane of the chunk once (the
+// tile's 2 kRsCJ + 1 fine rows, one fine node per lane, 63 nodes of a row on
+// lanes 0..62: whole rows, coalesced).  A fine plane is restricted along x in
+// registers (DPP neighbours) and along y through LDS; every coarse node
+// keeps the xy sum of the last odd fine plane and forms plane K along z as
+// sy(2K) + (sy(2K-1) + sy(2K+1)) / 2.  Per coarse node the sum is thus
+// m + (l + r) / 2 along x, then y, then z: a fixed order, so results are
+// deterministic, and equal to the per-node sum of the small-grid kernel up
+// to rounding.  All three components in one workgroup (one mask load per
+// fine node).  Eight wavefronts take three of the 17 fine rows each.  Two
+// raw-plane buffers: a buffer is reloaded with the plane two ahead as soon
+// as its values are read, so each plane's loads have two planes of work to
+// arrive in.  blockIdx.x: (tile, chunk) with tiles fastest, in XCD-contiguous
+// order; blockIdx.z: load case.
 constexpr int kRsCI = 31;
 constexpr int kRsCJ = 8;
 constexpr int kRsRows = 2 * kRsCJ + 1;
-constexpr int kRsRowsPerWave = (kRsRows + 3) / 4;
+constexpr int kRmWaves = 8;
+constexpr int kRmRowsPerWave = (kRsRows + kRmWaves - 1) / kRmWaves;
 template <typename T>
-__global__ void __launch_bounds__(256) k_restrict_z(int cnx, int cny, int cnz, int gx,
-                                                    const T* __restrict__ bf,
-                                                    const T* __restrict__ tf,
-                                                    const uint8_t* __restrict__ mask,
-                                                    T* __restrict__ bc, const T* __restrict__ dc,
-                                                    T omega, T* __restrict__ xc, int64_t fs,
-                                                    int64_t cs) {
-  __shared__ T xr[3][3][kRsRows][32];  // [component][plane][row][coarse column]
+struct RmRaw {
+  T b[3][kRmRowsPerWave], t[3][kRmRowsPerWave];
+  uint32_t m[kRmRowsPerWave];
+};
+template <typename T>
+__global__ void __launch_bounds__(64 * kRmWaves) k_restrict_zm(
+    int cnx, int cny, int cnz, int gx, int gy, int TK, const T* __restrict__ bf,
+    const T* __restrict__ tf, const uint8_t* __restrict__ mask, T* __restrict__ bc,
+    const T* __restrict__ dc, T omega, T* __restrict__ xc, int64_t fs, int64_t cs) {
+  __shared__ T xr[2][3][kRsRows][32];  // [buffer][component][row][coarse column]
   {  // load case blockIdx.z
     const int64_t fo = (int64_t)blockIdx.z * fs, co = (int64_t)blockIdx.z * cs;
     bf += fo;
@@ -925,16 +932,14 @@ __global__ void __launch_bounds__(256) k_restrict_z(int cnx, int cny, int cnz, i
     if (xc) xc += co;
   }
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  int bx, by, K;
+  int bx, by, K0;
   {
-    const int total = gridDim.x, wg = blockIdx.x;
-    const int xcd = wg & 7, pos = wg >> 3, q = total >> 3, r = total & 7;
-    const int t = (xcd < r) ? xcd * (q + 1) + pos : r * (q + 1) + (xcd - r) * q + pos;
-    K = t % (cnz + 1);
-    const int tile = t / (cnz + 1);
-    bx = tile % gx;
-    by = tile / gx;
+    const int t = xcd_slot(blockIdx.x, gridDim.x);
+    bx = t % gx;
+    by = (t / gx) % gy;
+    K0 = (t / (gx * gy)) * TK;
   }
+  const int K1 = min(K0 + TK, cnz + 1);
   const int I0 = bx * kRsCI, J0 = by * kRsCJ;
   const int fnx = 2 * cnx, fny = 2 * cny, fnz = 2 * cnz;
   const int64_t fnn = (int64_t)(fnx + 1) * (fny + 1) * (fnz + 1);
@@ -942,50 +947,85 @@ __global__ void __launch_bounds__(256) k_restrict_z(int cnx, int cny, int cnz, i
   const int64_t fplane = (int64_t)(fnx + 1) * (fny + 1);
   const int fx = 2 * I0 - 1 + lane;
   const bool xok = lane < 2 * kRsCI + 1 && fx >= 0 && fx <= fnx;
-  // Df (b - t) at this lane's node of rows w + 4q of fine planes 2K-1+dz, all
-  // three components (one mask load per node); 0 outside
-  T v[3][3][kRsRowsPerWave];
+  // raw values of this lane's nodes of rows w + 8 q of fine plane fz; 0 outside
+  auto load = [&](int fz, RmRaw<T>& R) {
 #pragma unroll
-  for (int dz = 0; dz < 3; ++dz)
-#pragma unroll
-    for (int q = 0; q < kRsRowsPerWave; ++q) {
-      const int r = w + 4 * q, fy = 2 * J0 - 1 + r, fz = 2 * K - 1 + dz;
+    for (int q = 0; q < kRmRowsPerWave; ++q) {
+      const int r = w + kRmWaves * q, fy = 2 * J0 - 1 + r;
       const bool ok = r < kRsRows && xok && fy >= 0 && fy <= fny && fz >= 0 && fz <= fnz;
       const int64_t f = (int64_t)fz * fplane + (int64_t)fy * (fnx + 1) + fx;
-      const uint32_t mk = (mask && ok) ? mask[f] : 0u;
+      R.m[q] = (mask && ok) ? mask[f] : 0u;
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        T val = ok ? bf[c * fnn + f] : T(0);
-        if (tf) val -= ok ? tf[c * fnn + f] : T(0);
-        v[c][dz][q] = ((mk >> c) & 1u) ? T(0) : val;
+        R.b[c][q] = ok ? bf[c * fnn + f] : T(0);
+        R.t[c][q] = (tf && ok) ? tf[c * fnn + f] : T(0);
       }
     }
-  // along x: odd lanes 2i+1 hold coarse column i
+  };
+  const int ci = threadIdx.x & 31, cj = threadIdx.x >> 5;  // output thread's coarse node
+  const bool out = threadIdx.x < 32 * kRsCJ && ci < kRsCI && I0 + ci <= cnx && J0 + cj <= cny;
+  int buf = 0;
+  // Df (b - t) of a loaded plane, then its x sums into LDS; after the
+  // barrier the output threads form the y sums sy
+  auto values = [&](const RmRaw<T>& R, T (&v)[3][kRmRowsPerWave]) {
 #pragma unroll
-  for (int c = 0; c < 3; ++c)
+    for (int q = 0; q < kRmRowsPerWave; ++q)
 #pragma unroll
-    for (int dz = 0; dz < 3; ++dz)
-#pragma unroll
-      for (int q = 0; q < kRsRowsPerWave; ++q) {
-        const int r = w + 4 * q;
-        const T l = wave_shift<0x138>(v[c][dz][q]), rr = wave_shift<0x130>(v[c][dz][q]);
-        const T sx = v[c][dz][q] + T(0.5) * (l + rr);
-        if (r < kRsRows && (lane & 1) && lane < 2 * kRsCI) xr[c][dz][r][lane >> 1] = sx;
+      for (int c = 0; c < 3; ++c) {
+        T val = R.b[c][q];
+        if (tf) val -= R.t[c][q];
+        v[c][q] = ((R.m[q] >> c) & 1u) ? T(0) : val;
       }
-  __syncthreads();
-  const int ci = threadIdx.x & 31, cj = threadIdx.x >> 5;  // this thread's coarse node
-  if (ci >= kRsCI || I0 + ci > cnx || J0 + cj > cny) return;
-  const int64_t n = (int64_t)K * (cnx + 1) * (cny + 1) + (int64_t)(J0 + cj) * (cnx + 1) + I0 + ci;
+  };
+  auto xy = [&](const T (&v)[3][kRmRowsPerWave], T (&sy)[3]) {
 #pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    T sy[3];
+    for (int c = 0; c < 3; ++c)
 #pragma unroll
-    for (int dz = 0; dz < 3; ++dz)
-      sy[dz] = xr[c][dz][2 * cj + 1][ci] +
-               T(0.5) * (xr[c][dz][2 * cj][ci] + xr[c][dz][2 * cj + 2][ci]);
-    const T acc = sy[1] + T(0.5) * (sy[0] + sy[2]);
-    bc[c * cnn + n] = acc;
-    if (xc) xc[c * cnn + n] = omega * dc[c * cnn + n] * acc;
+      for (int q = 0; q < kRmRowsPerWave; ++q) {
+        const int r = w + kRmWaves * q;
+        const T l = wave_shift<0x138>(v[c][q]), rr = wave_shift<0x130>(v[c][q]);
+        const T sx = v[c][q] + T(0.5) * (l + rr);
+        if (r < kRsRows && (lane & 1) && lane < 2 * kRsCI) xr[buf][c][r][lane >> 1] = sx;
+      }
+    __syncthreads();
+    if (out) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+        sy[c] = xr[buf][c][2 * cj + 1][ci] +
+                T(0.5) * (xr[buf][c][2 * cj][ci] + xr[buf][c][2 * cj + 2][ci]);
+    }
+    buf ^= 1;
+  };
+  RmRaw<T> RA, RB;
+  T carry[3] = {T(0), T(0), T(0)}, s0[3] = {T(0), T(0), T(0)}, s1[3] = {T(0), T(0), T(0)};
+  {
+    RmRaw<T> R0;
+    load(2 * K0 - 1, R0);
+    load(2 * K0, RA);
+    load(2 * K0 + 1, RB);
+    T v[3][kRmRowsPerWave];
+    values(R0, v);
+    xy(v, carry);
+  }
+  for (int K = K0; K < K1; ++K) {
+    T v[3][kRmRowsPerWave];
+    values(RA, v);
+    load(K + 1 < K1 ? 2 * K + 2 : -1, RA);
+    xy(v, s0);
+    values(RB, v);
+    load(K + 1 < K1 ? 2 * K + 3 : -1, RB);
+    xy(v, s1);
+    if (out) {
+      const int64_t n =
+          (int64_t)K * (cnx + 1) * (cny + 1) + (int64_t)(J0 + cj) * (cnx + 1) + I0 + ci;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const T acc = s0[c] + T(0.5) * (carry[c] + s1[c]);
+        bc[c * cnn + n] = acc;
+        if (xc) xc[c * cnn + n] = omega * dc[c * cnn + n] * acc;
+        carry[c] = s1[c];
+      }
+    }
   }
 }
 
@@ -1774,10 +1814,13 @@ void launch_apply_l1_jacobi_f32(const Grid& g, const double* Ke, const double* K
                   omega, nr);
 }
 
-// 3D restriction launch: one workgroup per (tile, coarse plane, case).  Used from kRsMinNodes coarse nodes up; on smaller grids, where a
+// 3D restriction launch: one workgroup per (tile, chunk of coarse planes,
+// case).  Used from kRsMinNodes coarse nodes up; on smaller grids, where a
 // launch is a few microseconds either way, the per-node kernel measured
-// faster (256x128x128, FP32: fine level 90 -> 68 us and second level 13.1 ->
-// 11.0 us with this kernel; third to fifth level 6.1/5.2/4.7 -> 8.2/6.9/5.2).
+// faster than the separable form (256x128x128, FP32, as one workgroup per
+// coarse plane: fine level 90 -> 68 us, second level 13.1 -> 11.0 us, third
+// to fifth level 6.1/5.2/4.7 -> 8.2/6.9/5.2).  As a z-march the fine level
+// takes 79.5 us (FP64) and 39.1 us (FP32).
 constexpr int64_t kRsMinNodes = 100000;
 template <typename T>
 static void restrict_z(const Grid& coarse, const T* bf, const T* tf, const uint8_t* mask, T* bc,
@@ -1785,8 +1828,24 @@ static void restrict_z(const Grid& coarse, const T* bf, const T* tf, const uint8
                        int64_t cs) {
   const int gx = (coarse.nx + 1 + kRsCI - 1) / kRsCI;
   const int gy = (coarse.ny + 1 + kRsCJ - 1) / kRsCJ;
-  k_restrict_z<T><<<dim3((unsigned)(gx * gy * (coarse.nz + 1)), 1, (unsigned)nr), 256, 0, s>>>(
-      coarse.nx, coarse.ny, coarse.nz, gx, bf, tf, mask, bc, dc, omega, xc, fs, cs);
+  // z-march in chunks, as many workgroups as the device holds at once (each
+  // chunk re-reads one fine plane): one per CU in FP64, two in FP32
+  // (256x128x128 fine level: 79.5 and 39.1 us; three per CU in FP32 46.3 us)
+  static const int slots = [] {
+    int dev = 0, n = 0, per_cu = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_restrict_zm<T>,
+                                                        64 * kRmWaves, 0);
+    return (n > 0 && per_cu > 0) ? n * per_cu : 256;
+  }();
+  const int planes = coarse.nz + 1, tiles = gx * gy;
+  int gz = slots / tiles;
+  gz = gz < 1 ? 1 : (gz > planes ? planes : gz);
+  const int tk = (planes + gz - 1) / gz;
+  gz = (planes + tk - 1) / tk;
+  k_restrict_zm<T><<<dim3((unsigned)(tiles * gz), 1, (unsigned)nr), 64 * kRmWaves, 0, s>>>(
+      coarse.nx, coarse.ny, coarse.nz, gx, gy, tk, bf, tf, mask, bc, dc, omega, xc, fs, cs);
 }
 
 void launch_apply_l1_f32(const Grid& g, const double* Ke, const double* Kcomp, int cap,
