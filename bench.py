@@ -856,7 +856,7 @@ def kv_steps(torch, aarmr, sets, n_steps):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
+        print(json.dumps({"error": "the AARMR library runs on one GPU only; --gpus must be 1 "
                                    "(no multi-GPU path is built)"}))
         sys.exit(2)
     import numpy as np
