@@ -612,7 +612,7 @@ def cpu_model():
     return "unknown"
 
 
-def cpu_baseline(sets=None, torch=None, aarmr=None, synth=None, reps=8):
+def cpu_baseline(sets=None, torch=None, aarmr=None, synth=None, reps=32):
     """The oracle's FP64 element-by-element product (oracle.fem.apply_ebe:
     gather, dense 24x24 element products through BLAS, scatter by bincount)
     on the headline grid, in the headline's unit (GDOF/s): `reps` products on
