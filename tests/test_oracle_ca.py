@@ -151,3 +151,23 @@ def test_oc_volume_and_bounds():
     assert np.all(xn >= np.maximum(0, x - 0.2) - 1e-15)
     assert np.all(xn <= np.minimum(1, x + 0.2) + 1e-15)
     assert abs(xp.sum() / n - 0.3) < 1e-2
+
+
+def test_reduced_solve_and_force_residual_by_hand():
+    """eqs. 22-25 and 29 on a 3x3 case solved by hand: K = diag(1, 2, 4),
+    f = (1, 1, 1).  With the basis e1: K_R = 1, y = 1, u~ = (1, 0, 0), the
+    force residual K u~ - f = (0, -1, -1) and eps = sqrt(2) / sqrt(3).  With
+    the basis (1, 1, 0)/sqrt(2): K_R = 3/2, f_R = sqrt(2), u~ = (2/3, 2/3, 0),
+    K u~ - f = (-1/3, 1/3, -1) and eps = sqrt(11/9) / sqrt(3).  eps is relative
+    to the load, not to the displacement."""
+    K = np.diag([1.0, 2.0, 4.0])
+    f = np.ones(3)
+    u, y, KR = ca.reduced_solve(K, np.array([[1.0], [0.0], [0.0]]), f)
+    assert np.allclose(u, [1.0, 0.0, 0.0], atol=1e-15) and np.allclose(y, [1.0])
+    assert abs(ca.force_residual(K, u, f) - np.sqrt(2.0 / 3.0)) < 1e-15
+    Rt = np.array([[1.0], [1.0], [0.0]]) / np.sqrt(2.0)
+    u, y, KR = ca.reduced_solve(K, Rt, f)
+    assert np.allclose(y, [np.sqrt(2.0) / 1.5], rtol=1e-15)
+    assert np.allclose(u, [2.0 / 3.0, 2.0 / 3.0, 0.0], atol=1e-15)
+    assert np.allclose(KR[:, 0], K @ Rt[:, 0], atol=1e-15)
+    assert abs(ca.force_residual(K, u, f) - np.sqrt(11.0 / 27.0)) < 1e-15
