@@ -171,3 +171,58 @@ def test_reduced_solve_and_force_residual_by_hand():
     assert np.allclose(u, [2.0 / 3.0, 2.0 / 3.0, 0.0], atol=1e-15)
     assert np.allclose(KR[:, 0], K @ Rt[:, 0], atol=1e-15)
     assert abs(ca.force_residual(K, u, f) - np.sqrt(11.0 / 27.0)) < 1e-15
+
+
+def test_svd_cutoff_is_relative_to_largest_singular_value():
+    """eq. 21 truncation, read as sigma_i / sigma_1 > tau on column-normalised
+    R.  Two columns 3 e1 and 5 (e1 + d e2) normalise to unit vectors with
+    cosine c = 1 / sqrt(1 + d^2); their Gram matrix [[1, c], [c, 1]] gives
+    sigma_1 = sqrt(1 + c) and sigma_2 = sqrt(1 - c), the leading singular
+    vector along the sum of the two unit columns.  A tau between sigma_2 and
+    sigma_2 / sigma_1 separates the relative cut-off (rank 1) from an absolute
+    one (rank 2)."""
+    d = 1e-3
+    R = np.zeros((4, 2))
+    R[0, 0] = 3.0
+    R[0, 1], R[1, 1] = 5.0, 5.0 * d
+    s = np.sqrt(1.0 + d * d)
+    one_minus_c = d * d / (s * (1.0 + s))
+    s1, s2 = np.sqrt(2.0 - one_minus_c), np.sqrt(one_minus_c)
+    assert s2 / s1 < s2 / 1.2 < s2
+    Rt = ca.orthogonalise_svd(R, tau=s2 / 1.2)
+    assert Rt.shape == (4, 1)
+    lead = np.array([1.0, 0.0, 0.0, 0.0]) + np.array([1.0, d, 0.0, 0.0]) / s
+    lead /= np.linalg.norm(lead)
+    assert abs(abs(Rt[:, 0] @ lead) - 1.0) < 1e-14
+    Rt2 = ca.orthogonalise_svd(R, tau=s2 / s1 / 1.2)
+    assert Rt2.shape == (4, 2)
+    assert np.allclose(Rt2.T @ Rt2, np.eye(2), atol=1e-12)
+    assert ca.orthogonalise_svd(R, tau=s2 / s1 * 1.2).shape == (4, 1)
+
+
+def test_oc_volume_constraint_is_on_the_filtered_density():
+    """eq. 3 constrains the volume of the filtered density rho~ = H x / Hs, not
+    of x.  The volume of the filtered trial design is non-increasing in the
+    multiplier, so the bisection's final multiplier must bracket the target
+    within its stopping gap (a relative width of 1e-3, hence a factor
+    1 +- 3e-3 on the multiplier).  The sensitivities favour boundary elements,
+    whose filter column sums differ from one, so the unfiltered volume misses
+    the target by far more than the gap."""
+    nx, ny, nz = 6, 4, 4
+    n = nx * ny * nz
+    H, Hs = filt.filter_matrix(nx, ny, nz, 2.0)
+    cw = filt.adjoint(H, Hs, np.ones(n))
+    rng = np.random.default_rng(3)
+    x = np.full(n, 0.4)
+    dc = -np.where(cw > 1.0, 10.0, 0.1) * rng.uniform(0.9, 1.1, n)
+    xn, xp, lam = oc.oc_update(x, dc, cw, H, Hs, 0.4)
+
+    def filtered_volume(l):
+        B = np.maximum(0.0, -dc) / cw
+        t = np.clip(x * np.sqrt(B / l), np.maximum(0.0, x - 0.2), np.minimum(1.0, x + 0.2))
+        return (H @ t / Hs).sum()
+
+    target = 0.4 * n
+    assert filtered_volume(lam * (1 - 3e-3)) >= target >= filtered_volume(lam * (1 + 3e-3))
+    assert np.allclose(xp, (H @ xn) / Hs, rtol=1e-15)
+    assert abs(xn.sum() - target) > 0.02 * target
