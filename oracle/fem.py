@@ -120,6 +120,32 @@ def apply_ebe(nx: int, ny: int, nz: int, Ee: np.ndarray, KE: np.ndarray, v: np.n
     return np.bincount(edof.ravel(), weights=ye.ravel(), minlength=3 * (nx + 1) * (ny + 1) * (nz + 1))
 
 
+def apply_ebe_at_nodes(nx: int, ny: int, nz: int, Ee: np.ndarray, KE: np.ndarray,
+                       dof_value, nodes) -> np.ndarray:
+    """(K v) at the listed nodes only, (len(nodes), 3): for each node, the sum
+    over the up to eight elements that contain it of E_e times the node's three
+    rows of KE applied to the element's 24 values (eq. 7's product, row by
+    row).  ``dof_value(ids)`` returns v at AoS DOF ids, so v may live in any
+    layout; meant for sampled checks on grids too large for apply_ebe."""
+    out = np.zeros((len(nodes), 3))
+    for t, n in enumerate(nodes):
+        n = int(n)
+        i, j, k = n % (nx + 1), (n // (nx + 1)) % (ny + 1), n // ((nx + 1) * (ny + 1))
+        for a in range(8):  # the node is local corner a of element (i, j, k) - corner(a)
+            di, dj, dk = local_corner(a)
+            ei, ej, ek = i - di, j - dj, k - dk
+            if not (0 <= ei < nx and 0 <= ej < ny and 0 <= ek < nz):
+                continue
+            ids = []
+            for b in range(8):
+                bi, bj, bk = local_corner(b)
+                nb = node_id(nx, ny, ei + bi, ej + bj, ek + bk)
+                ids += [3 * nb, 3 * nb + 1, 3 * nb + 2]
+            ve = np.asarray(dof_value(np.array(ids, dtype=np.int64)), dtype=np.float64)
+            out[t] += float(Ee[ei + nx * (ej + ny * ek)]) * (KE[3 * a:3 * a + 3, :] @ ve)
+    return out
+
+
 def assemble(nx: int, ny: int, nz: int, Ee: np.ndarray, KE: np.ndarray) -> sp.csr_matrix:
     """Global stiffness K = sum_e E_e L_e^T KE L_e (no boundary conditions)."""
     edof = element_dofs(nx, ny, nz)

@@ -250,3 +250,68 @@ def test_zero_load_gives_zero_solution():
                           flags=aarmr.WARM_START)
     assert code == aarmr.OK and C[0] == 0.0 and st.iterations[0] == 0
     assert float(u.abs().max()) == 0.0 and float(dc.abs().max()) == 0.0
+
+
+def test_fine_operator_at_largest_accepted_mesh():
+    """The largest grid the mesh check accepts for this shape: 704x384x320
+    (86.5 M elements, 261 M DOFs, 7 levels), where the fine product's FP64
+    vectors take 0.974 of its 2^31-byte offset range.  The oracle's row-by-row
+    product checks sampled outputs: the grid's corners, nodes on both sides of
+    the 30-node x and 15-row y tile seams, the last nodes of the grid (the
+    largest offsets) and 3000 random nodes, in the general form and in the
+    solver form (input zero on fixed DOFs)."""
+    aarmr = _aarmr()
+    dims = (704, 384, 320)
+    nx, ny, nz = dims
+    nxp, nyp = nx + 1, ny + 1
+    log(f"largest mesh K.v {dims}")
+    prob = synth.cantilever(*dims)
+    m = _mesh(prob, autotune=False, mg_levels=7)
+    nn = m.n_node
+    assert 3 * nn * 8 < 2 ** 31 and 3 * nn * 8 > 0.97 * 2 ** 31
+    rho = synth.uniform_iid(nx, ny, nz, 1e-3, 1.0, seed=11).ravel()
+    fx = _fixed(prob, m)
+    m.setup(t64(rho), fx)
+    rng = np.random.default_rng(111)
+    v = rng.standard_normal((3, nn))
+    fixed = np.zeros((3, nn), dtype=bool)
+    fixed.ravel()[fx.cpu().numpy()] = True
+
+    def nid(i, j, k):
+        return i + nxp * (j + nyp * k)
+
+    sample = [nid(i, j, k) for i in (0, nx) for j in (0, ny) for k in (0, nz)]
+    sample += [nid(i, j, k) for i in (0, 1, 29, 30, 31, 59, 60, 61, nx - 1)
+               for j in (14, 15, 16, 29, 30, ny - 1) for k in (1, nz // 2, nz - 1)]
+    sample += [nn - 1, nn - 2, nn - nxp, nn - nxp * nyp]
+    sample = np.unique(np.concatenate([np.array(sample), rng.integers(0, nn, 3000)]))
+    vm = np.where(fixed, 0.0, v)
+    rows = fem.apply_ebe_at_nodes(nx, ny, nz, fem.simp(rho), fem.hex8_ke(),
+                                  lambda ids: vm[ids % 3, ids // 3], sample)
+    want = np.where(fixed[:, sample].T, v[:, sample].T, rows)  # identity rows on fixed DOFs
+    scale = np.abs(want).max()
+    idx = torch.tensor(sample, dtype=torch.int64, device="cuda")
+    vt = t64(v.ravel())
+    y = torch.empty(3 * nn, dtype=torch.float64, device="cuda")
+    m.apply(vt, y)
+    got = y.view(3, nn)[:, idx].T.cpu().numpy()
+    err = np.abs(got - want).max() / scale
+    log(f"  general form, {len(sample)} nodes: max rel err {err:.2e}")
+    assert err < 1e-13
+    del vt
+    vmt = t64(vm.ravel())
+    m.apply(vmt, y, flags=aarmr.INPUT_MASKED)
+    got = y.view(3, nn)[:, idx].T.cpu().numpy()
+    want_m = np.where(fixed[:, sample].T, 0.0, rows)  # the masked input's identity rows
+    err = np.abs(got - want_m).max() / scale
+    log(f"  solver form: max rel err {err:.2e}")
+    assert err < 1e-13
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(5):
+        m.apply(vmt, y, flags=aarmr.INPUT_MASKED)
+    t1.record()
+    t1.synchronize()
+    ms = t0.elapsed_time(t1) / 5
+    log(f"  solver-form product {ms:.3f} ms, {3 * nn / ms / 1e6:.1f} GDOF/s")
+    m.close()
