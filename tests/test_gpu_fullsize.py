@@ -206,12 +206,12 @@ def test_full_size_level1_operator_and_vcycle_symmetric(levels):
 
 def test_level1_galerkin_identity_per_element_path():
     """The per-element level-1 product (one thread per parent for all 24
-    outputs, used from 2e5 level-1 elements) against the Galerkin identity of Algorithm 2's first coarse
-    operator, A_1 v = (Df P)^T A_0 (Df P) v, with P the oracle's trilinear
-    interpolation and A_0 the library's fine operator (checked against the
-    oracle's element-by-element product above).  At 160x112x112 level 1 has
-    80x56x56 = 250880 parents, and the clamped face's flagged parents take
-    the stored-matrix rows of the same launch."""
+    outputs, used from 2e5 level-1 elements) against Algorithm 2's first
+    coarse operator composed on the oracle's side, A_1 v = (Df P)^T K (Df P) v,
+    with P the oracle's trilinear interpolation and K its element-by-element
+    product.  At 160x112x112 level 1 has 80x56x56 = 250880 parents, and the
+    clamped face's flagged parents take the stored-matrix rows of the same
+    launch."""
     from oracle import mg
 
     dims = (160, 112, 112)
@@ -225,12 +225,9 @@ def test_level1_galerkin_identity_per_element_path():
     v = np.random.default_rng(41).standard_normal(P.shape[1])
     y1 = torch.zeros(P.shape[1], dtype=torch.float64, device="cuda")
     m.apply(t64(fem.aos_to_soa(v).ravel()), y1, level=1)
-    pv = t64(fem.aos_to_soa(P @ v).ravel())
-    pv[fx] = 0.0
-    y0 = torch.zeros_like(pv)
-    m.apply(pv, y0, level=0)
-    y0[fx] = 0.0
-    want = P.T @ fem.soa_to_aos(y0.cpu().numpy())
+    free = fem.free_mask(3 * m.n_node, fem.fixed_dofs_aos(prob)).astype(np.float64)
+    y0 = free * fem.apply_ebe(*dims, fem.simp(rho), fem.hex8_ke(), free * (P @ v))
+    want = P.T @ y0
     got = fem.soa_to_aos(y1.cpu().numpy())
     err = float(np.linalg.norm(got - want) / np.linalg.norm(want))
     log(f"  rel {err:.3e}")

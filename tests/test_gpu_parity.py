@@ -92,26 +92,33 @@ def test_coarse_galerkin_eight_parent_groups():
     parents per workgroup.  At 48x64x64 with 4 levels, level 2 (12x16x16) has
     512 such groups, half of them partial (12 = 8 + 4 parents per row), while
     level 3 (6x8x8) is built one parent per workgroup.  Each is checked against
-    the Galerkin identity A_l v = P^T A_{l-1} P v of Algorithm 2's coarse
-    operators, with P the oracle's trilinear prolongation and A_{l-1} the
-    library's operator one level down (itself checked against the oracle at
-    small sizes above)."""
+    Algorithm 2's coarse operators composed on the oracle's side alone:
+    A_l = Q^T Df K Df Q with Q = P_1 ... P_l the oracle's trilinear
+    interpolations and K the oracle's element-by-element product."""
     nx, ny, nz = 48, 64, 64
     log(f"coarse galerkin groups {nx}x{ny}x{nz} levels=4")
     prob = synth.cantilever(nx, ny, nz)
     m = mesh_for(prob, mg_levels=4)
-    m.setup(t64(_density(prob, 23)), fixed_tensor(prob, m))
+    rho = _density(prob, 23)
+    m.setup(t64(rho), fixed_tensor(prob, m))
+    free = fem.free_mask(3 * m.n_node, fem.fixed_dofs_aos(prob)).astype(np.float64)
+    Ee, KE = fem.simp(rho), fem.hex8_ke()
+    edof = fem.element_dofs_grid(nx, ny, nz)
     rng = np.random.default_rng(24)
     for l in (2, 3):
-        cx, cy, cz = nx >> l, ny >> l, nz >> l
-        P = mg.prolongation(cx, cy, cz)
-        v = rng.standard_normal(P.shape[1])
-        y = torch.zeros(P.shape[1], dtype=torch.float64, device="cuda")
-        m.apply(t64(soa(v)), y, level=l)
-        yf = torch.zeros(P.shape[0], dtype=torch.float64, device="cuda")
-        m.apply(t64(soa(P @ v)), yf, level=l - 1)
-        want = P.T @ aos(yf.cpu().numpy())
-        assert rel(aos(y.cpu().numpy()), want) < 1e-12, f"level {l}"
+        Ps = [mg.prolongation_kron(nx >> k, ny >> k, nz >> k) for k in range(1, l + 1)]
+        v = rng.standard_normal(Ps[-1].shape[1])
+        x = v
+        for P in reversed(Ps):  # Q v = P_1 (P_2 ( ... P_l v))
+            x = P @ x
+        y = free * fem.apply_ebe(nx, ny, nz, Ee, KE, free * x, edof)
+        for P in Ps:  # Q^T y
+            y = P.T @ y
+        got = torch.zeros(Ps[-1].shape[1], dtype=torch.float64, device="cuda")
+        m.apply(t64(soa(v)), got, level=l)
+        err = rel(aos(got.cpu().numpy()), y)
+        log(f"  level {l}: rel {err:.2e}")
+        assert err < 1e-12, f"level {l}"
 
 
 def test_energy_matches_oracle():
