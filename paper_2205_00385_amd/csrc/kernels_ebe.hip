@@ -414,10 +414,10 @@ __global__ void k_identity_rows(int64_t nn, const uint8_t* __restrict__ mask,
 }
 
 // z-chunk of node planes per workgroup.  A chunk costs one extra element
-// layer (the carry is primed from the layer below it), so chunks are made
-// as long as possible while the grid still fills every resident workgroup
-// slot of the device in a single round; at least 4 planes per chunk unless a
-// tuned length (2 or more) is given.
+// layer (the carry is primed from the layer below it); the length is chosen
+// by the number of rounds over the device's resident workgroup slots times
+// the plane steps per chunk (see launch_ebe_r), at least 4 planes per chunk
+// unless a tuned length (2 or more) is given.
 // Prefetch distance: two node planes in flight for the 16-row tile (a
 // 512-thread workgroup leaves registers to spare at its occupancy of two
 // wavefronts per SIMD; 256x128x128: 70 -> 67 us), one for the smaller tiles,
@@ -460,13 +460,30 @@ static int launch_ebe_r(const Grid& g, const WalshConsts& K, const T* E, const u
   const int gx = (g.nx + 1 + kTileX - 1) / kTileX;
   const int gy = (g.ny + 1 + kTileY - 1) / kTileY;
   const int planes = g.nz + 1;
-  int gz = slots / (gx * gy);
-  gz = gz < 1 ? 1 : (gz > planes ? planes : gz);
-  int tz = (planes + gz - 1) / gz;
-  if (tz < 4) tz = 4;
-  if (tz_req > 0) tz = tz_req < planes ? tz_req : planes;  // tuned z-chunk length
+  int tz = planes;
+  if (tz_req > 0) {
+    tz = tz_req < planes ? tz_req : planes;  // tuned z-chunk length
+  } else {
+    // Chunks of t planes take about ceil(workgroups / slots) rounds of t + 1
+    // plane steps (a chunk also primes its carry with one layer), so take
+    // the length with the fewest steps, at least 4 planes a chunk.  Grids
+    // with fewer tiles than slots get one round of the shortest chunks that
+    // fit; larger ones get a split whose last round is well filled.
+    const int64_t tiles = (int64_t)gx * gy;
+    int64_t best = -1;
+    for (int n = 1; n <= planes; ++n) {
+      const int t = (planes + n - 1) / n;
+      if (t < 4 && n > 1) break;
+      const int64_t chunks = (planes + t - 1) / t;
+      const int64_t cost = (tiles * chunks + slots - 1) / slots * (t + 1);
+      if (best < 0 || cost < best) {
+        best = cost;
+        tz = t;
+      }
+    }
+  }
   if (tz < 2) tz = 2;
-  gz = (planes + tz - 1) / tz;
+  const int gz = (planes + tz - 1) / tz;
   k_ebe_z<T, ROWS, MASK_IN, AARMR_EBE_PF(ROWS), JAC, DOT>
       <<<dim3((unsigned)(gx * gy * gz), 1, (unsigned)nr), kThreads, 0, s>>>(
           g.nx, g.ny, g.nz, gx, gy, tz, K, E, mask, v, y, jb, jd, omega, part, 3 * g.nn, pst);
