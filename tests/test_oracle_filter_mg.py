@@ -127,3 +127,31 @@ def test_mgcg_matches_direct():
     assert rel <= 1e-10
     assert np.linalg.norm(u - u_d) <= 1e-8 * np.linalg.norm(u_d)
     assert it < 100
+
+
+def test_coarse_operators_are_the_energy_of_the_interpolated_field():
+    """Algorithm 2's coarse operators, read physically: for a coarse vector v
+    on level l, v^T A_l v is the strain energy sum_e E_e u_e^T KE u_e of the
+    fine displacement u interpolated from v through every level and held at
+    zero on the supports.  Checked on levels 1 and 2 of a 3-level hierarchy
+    with element-by-element energies, not the matrix chain, so a coarse
+    operator formed from the wrong level or an interpolation that ignores
+    the supports fails it."""
+    dims = (8, 4, 4)
+    prob, K, fixed = _setup(dims, 3, seed=6)
+    H = mg.Hierarchy(K, fixed, dims, 3)
+    rng = np.random.default_rng(6)
+    rho = np.random.default_rng(6).uniform(0.3, 1.0, prob.n_elem)
+    Ee = fem.simp(rho)
+    edof = fem.element_dofs(*dims)
+    KE = fem.hex8_ke()
+    free = fem.free_mask(K.shape[0], fixed)
+    for level in (1, 2):
+        Ps = [mg.prolongation(dims[0] >> k, dims[1] >> k, dims[2] >> k) for k in range(1, level + 1)]
+        v = rng.standard_normal(Ps[-1].shape[1])
+        u = v
+        for P in reversed(Ps):
+            u = P @ u
+        u = np.where(free, u, 0.0)
+        energy = float((Ee * np.einsum("ei,ij,ej->e", u[edof], KE, u[edof])).sum())
+        assert abs(v @ (H.A[level] @ v) - energy) <= 1e-12 * energy, f"level {level}"
