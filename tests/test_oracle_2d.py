@@ -164,3 +164,25 @@ def test_mutual_sensitivity_reduces_to_compliance():
     _, Cs, dc = fem2d.analyse2(synth.Problem2D(6, 4, base.fixed, [base.loads[0]], "c", base.springs), rho)
     assert abs(uout - Cs[0]) <= 1e-13 * Cs[0]
     assert np.abs(dout - dc).max() <= 1e-12 * np.abs(dc).max()
+
+
+def test_springs_and_loads_on_one_dof_add_up():
+    """Linearity of the boundary data: two springs (or two point loads) listed
+    on the same DOF act as one with the summed stiffness (or force), so a
+    problem split that way has the same operator, solution and compliance."""
+    import dataclasses
+
+    prob = synth.inverter2d(8, 4)
+    i, j, c, k = prob.springs[0]
+    split = dataclasses.replace(prob, springs=[(i, j, c, 0.25 * k), (i, j, c, 0.75 * k)]
+                                + list(prob.springs[1:]))
+    assert abs(fem2d.spring_matrix2(split) - fem2d.spring_matrix2(prob)).max() == 0.0
+    (li, lj, lc, lv) = prob.loads[0][0]
+    loads = [list(case) for case in prob.loads]
+    loads[0] = [(li, lj, lc, 0.5 * lv), (li, lj, lc, 0.5 * lv)] + list(prob.loads[0][1:])
+    split2 = dataclasses.replace(prob, loads=loads)
+    assert np.array_equal(fem2d.dof_vector_aos2(split2, 0), fem2d.dof_vector_aos2(prob, 0))
+    rho = np.full(prob.n_elem, 0.5)
+    _, C1, _ = fem2d.analyse2(split2, rho)
+    _, C0, _ = fem2d.analyse2(prob, rho)
+    assert abs(C1[0] - C0[0]) <= 1e-12 * abs(C0[0])

@@ -220,3 +220,14 @@ def test_product_at_sampled_nodes_matches_assembly():
     got = fem.apply_ebe_at_nodes(nx, ny, nz, Ee, KE, lambda ids: v_soa[ids % 3, ids // 3],
                                  np.arange(nn))
     assert np.abs(got - want).max() <= 1e-14 * np.abs(want).max()
+
+
+def test_point_loads_on_one_dof_add_up():
+    """Two point loads listed on the same DOF act as one with the summed force."""
+    import dataclasses
+
+    prob = synth.cantilever(4, 2, 2)
+    (i, j, k, c, v) = prob.loads[0][0]
+    split = dataclasses.replace(prob, loads=[[(i, j, k, c, 0.3 * v), (i, j, k, c, 0.7 * v)]
+                                             + list(prob.loads[0][1:])])
+    assert np.allclose(fem.dof_vector_aos(split), fem.dof_vector_aos(prob), rtol=1e-15, atol=0)
