@@ -315,39 +315,47 @@ def test_fine_operator_at_largest_accepted_mesh():
 
 
 def test_analysis_at_largest_accepted_mesh():
-    """One FP64 analysis on the largest accepted grid (704x384x320, 261 M
-    DOFs, 7 levels, rel. residual 1e-8, iid density in [0.3, 1]): the residual
-    ||f - A u|| / ||f|| from the library's product (itself checked against the
-    oracle at sampled nodes on this grid) meets the tolerance, the compliance
-    equals f^T u and the energy u^T A u.  Element-wise iid moduli raise
-    lambda_max(D^-1 A) to about 3.9 (3.09 for a uniform design), so the
+    """One analysis on the largest accepted grid (704x384x320, 261 M DOFs, 7
+    levels, rel. residual 1e-8, iid density in [0.3, 1]) in FP64 and in the
+    refinement form: the residual ||f - A u|| / ||f|| from the library's FP64
+    product (itself checked against the oracle at sampled nodes on this grid)
+    meets the tolerance, the compliance equals f^T u and the energy u^T A u,
+    and the two forms' compliances agree to 1e-6.  Element-wise iid moduli
+    raise lambda_max(D^-1 A) to about 3.9 (3.09 for a uniform design), so the
     damped-Jacobi weight is 0.5: the sweep must keep omega lambda_max < 2 for
     the V-cycle to stay positive definite."""
     aarmr = _aarmr()
     dims = (704, 384, 320)
-    log(f"largest mesh analysis {dims}")
     prob = synth.cantilever(*dims)
-    m = _mesh(prob, autotune=False, mg_levels=7, cg_rtol=1e-8, cg_maxit=500, omega=0.5)
-    rho = synth.uniform_iid(*dims, 0.3, 1.0, seed=12).ravel()
-    fx = _fixed(prob, m)
-    f = t64(np.asarray(aarmr.loads_soa(prob, m.n_node)[0]))
-    u = torch.zeros_like(f)
-    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    t0.record()
-    C, st, code = m.solve(t64(rho), f, fx, u)
-    t1.record()
-    t1.synchronize()
-    assert code == aarmr.OK
-    fm = f.clone()
-    fm[fx] = 0.0
-    Au = torch.empty_like(u)
-    m.apply(u, Au)
-    Au[fx] = 0.0
-    res = float(torch.linalg.vector_norm(fm - Au) / torch.linalg.vector_norm(fm))
-    ftu, uau = float(fm @ u), float(u @ Au)
-    log(f"  {st.iterations[0]} iterations, {t0.elapsed_time(t1):.0f} ms, residual {res:.3e}, "
-        f"C {C[0]:.10g}")
-    assert res <= 1.05e-8
-    assert abs(C[0] - ftu) <= 1e-12 * abs(C[0])
-    assert abs(uau - C[0]) <= 1e-8 * abs(C[0])
-    m.close()
+    rho = t64(synth.uniform_iid(*dims, 0.3, 1.0, seed=12).ravel())
+    comp = {}
+    for prec in (aarmr.FP64, aarmr.FP32_REFINE):
+        log(f"largest mesh analysis {dims} precision {prec}")
+        m = _mesh(prob, autotune=False, mg_levels=7, cg_rtol=1e-8, cg_maxit=500, omega=0.5,
+                  precision=prec)
+        fx = _fixed(prob, m)
+        f = t64(np.asarray(aarmr.loads_soa(prob, m.n_node)[0]))
+        u = torch.zeros_like(f)
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0.record()
+        C, st, code = m.solve(rho, f, fx, u)
+        t1.record()
+        t1.synchronize()
+        assert code == aarmr.OK
+        fm = f.clone()
+        fm[fx] = 0.0
+        Au = torch.empty_like(u)
+        m.apply(u, Au)
+        Au[fx] = 0.0
+        res = float(torch.linalg.vector_norm(fm - Au) / torch.linalg.vector_norm(fm))
+        ftu, uau = float(fm @ u), float(u @ Au)
+        log(f"  {st.iterations[0]} iterations, {t0.elapsed_time(t1):.0f} ms, residual {res:.3e}, "
+            f"C {C[0]:.10g}")
+        assert res <= 1.05e-8
+        assert abs(C[0] - ftu) <= 1e-12 * abs(C[0])
+        assert abs(uau - C[0]) <= 1e-8 * abs(C[0])
+        comp[prec] = C[0]
+        m.close()
+        del m, f, u, fm, Au
+        torch.cuda.empty_cache()
+    assert abs(comp[aarmr.FP32_REFINE] - comp[aarmr.FP64]) <= 1e-6 * comp[aarmr.FP64]
