@@ -1828,9 +1828,12 @@ static void restrict_z(const Grid& coarse, const T* bf, const T* tf, const uint8
                        int64_t cs) {
   const int gx = (coarse.nx + 1 + kRsCI - 1) / kRsCI;
   const int gy = (coarse.ny + 1 + kRsCJ - 1) / kRsCJ;
-  // z-march in chunks, as many workgroups as the device holds at once (each
-  // chunk re-reads one fine plane): one per CU in FP64, two in FP32
-  // (256x128x128 fine level: 79.5 and 39.1 us; three per CU in FP32 46.3 us)
+  // z-march in chunks sized by the device's resident workgroups (one per CU
+  // in FP64, two in FP32; 256x128x128 fine level: 79.5 and 39.1 us, three
+  // per CU in FP32 46.3 us).  A chunk of t coarse planes reads 2 t + 1 fine
+  // planes, and the launch takes about ceil(workgroups / slots) rounds of
+  // them: the chunk length with the fewest fine-plane reads in sequence is
+  // taken (one round where the tiles fit; results do not depend on it)
   static const int slots = [] {
     int dev = 0, n = 0, per_cu = 0;
     (void)hipGetDevice(&dev);
@@ -1840,10 +1843,18 @@ static void restrict_z(const Grid& coarse, const T* bf, const T* tf, const uint8
     return (n > 0 && per_cu > 0) ? n * per_cu : 256;
   }();
   const int planes = coarse.nz + 1, tiles = gx * gy;
-  int gz = slots / tiles;
-  gz = gz < 1 ? 1 : (gz > planes ? planes : gz);
-  const int tk = (planes + gz - 1) / gz;
-  gz = (planes + tk - 1) / tk;
+  int tk = planes;
+  int64_t best = -1;
+  for (int n = 1; n <= planes; ++n) {
+    const int t = (planes + n - 1) / n;
+    const int64_t chunks = (planes + t - 1) / t;
+    const int64_t cost = ((int64_t)tiles * chunks + slots - 1) / slots * (2 * t + 1);
+    if (best < 0 || cost < best) {
+      best = cost;
+      tk = t;
+    }
+  }
+  const int gz = (planes + tk - 1) / tk;
   k_restrict_zm<T><<<dim3((unsigned)(tiles * gz), 1, (unsigned)nr), 64 * kRmWaves, 0, s>>>(
       coarse.nx, coarse.ny, coarse.nz, gx, gy, tk, bf, tf, mask, bc, dc, omega, xc, fs, cs);
 }
