@@ -245,20 +245,23 @@ def test_not_converged_reports_and_writes():
     assert torch.isfinite(u).all() and float(u.abs().max()) > 0
 
 
-@pytest.mark.parametrize("orth", ["gs", "svd"])
-def test_ca_sequence_matches_oracle_algorithm1(orth):
+@pytest.mark.parametrize("orth,form", [("gs", "fp64"), ("svd", "fp64"), ("gs", "refine")])
+def test_ca_sequence_matches_oracle_algorithm1(orth, form):
     """Algorithm 1 on both sides over the same density sequence: N_on exact
     (oracle) / converged MGCG (GPU) cycles build the PARM, then CA cycles.
     The accept/reject path, u, C and dc must agree.  The oracle
     orthogonalises by eq. 21's SVD; the GPU by Gram-Schmidt or by the same
-    SVD (rank of the kept basis compared too)."""
+    SVD (rank of the kept basis compared too).  In the refinement form the
+    MGCG solves that fill the PARM and the fallbacks run in FP32 inside FP64
+    refinement, while the reduced model itself stays FP64."""
     from paper_2205_00385_amd import aarmr
 
     prob = synth.cantilever(16, 8, 8)
     Ns, Nm, N_on, tol = 2, 3, 3, 0.05
     alg = oca.AARMR(prob, Ns=Ns, Nm=Nm, N_on=N_on, eps_tol=tol)
     m = mesh_for(prob, mg_levels=3, cg_rtol=1e-11, Ns=Ns, Nm=Nm, ca_tol=tol,
-                 orth=aarmr.ORTH_SVD if orth == "svd" else aarmr.ORTH_GS)
+                 orth=aarmr.ORTH_SVD if orth == "svd" else aarmr.ORTH_GS,
+                 precision=aarmr.FP32_REFINE if form == "refine" else aarmr.FP64)
     fixed = fixed_tensor(prob, m)
     f = loads_tensor(prob, m)
     u = torch.zeros_like(f)
@@ -476,19 +479,23 @@ def test_ca_svd_and_gs_bases_give_same_reduced_solution():
     assert abs(es - eg) <= 1e-9 * max(eg, 1e-12) + 1e-12
 
 
-def test_ca_nm6_accepted_branch_48x24x24():
+@pytest.mark.parametrize("form", ["fp64", "refine"])
+def test_ca_nm6_accepted_branch_48x24x24(form):
     """Algorithm 1 with the benchmark loop's basis size (Nm = 6, Ns = 2) on a
     48x24x24 cantilever: the GPU's reduced-model steps against the oracle's
     (eq. 21's SVD basis, exact solves for the PARM and the fallback).  Small
     smooth design steps first, so the accepted branch (eps < 1%, the paper's
-    3D range) is taken, then larger ones until a fallback occurs."""
+    3D range) is taken, then larger ones until a fallback occurs.  Also in the
+    refinement form (the PARM's and the fallback's solves in FP32 inside FP64
+    refinement)."""
     from paper_2205_00385_amd import aarmr
 
     dims = (48, 24, 24)
     prob = synth.cantilever(*dims)
     Ns, Nm, N_on, tol = 2, 6, 2, 1e-2
     alg = oca.AARMR(prob, Ns=Ns, Nm=Nm, N_on=N_on, eps_tol=tol)
-    m = mesh_for(prob, mg_levels=4, cg_rtol=1e-11, Ns=Ns, Nm=Nm, ca_tol=tol)
+    m = mesh_for(prob, mg_levels=4, cg_rtol=1e-11, Ns=Ns, Nm=Nm, ca_tol=tol,
+                 precision=aarmr.FP32_REFINE if form == "refine" else aarmr.FP64)
     fixed = fixed_tensor(prob, m)
     f = loads_tensor(prob, m)
     u = torch.zeros_like(f)
