@@ -235,6 +235,46 @@ def test_level1_galerkin_identity_per_element_path():
     m.close()
 
 
+def test_filter_and_oc_on_the_loop_mesh():
+    """The optimisation loop's support steps at its own size (96x48x48, filter
+    radius 2): every output of the density filter and its adjoint (eqs. 31-33)
+    against the oracle's explicit filter matrix, and one OC update from a
+    loop-like state (smoothed design, sensitivities of a smoothed field)
+    against the oracle's bisection."""
+    from oracle import filt, oc
+
+    aarmr = _aarmr()
+    dims = (96, 48, 48)
+    log("filter and OC on the loop mesh 96x48x48, r = 2")
+    prob = synth.cantilever(*dims)
+    m = _mesh(prob, autotune=False, **LOOP)
+    H, Hs = filt.filter_matrix(*dims, 2.0)
+    x = synth.smoothed_field(*dims, 3.0, 0.05, 1.0, seed=21).ravel()
+    out = torch.zeros(m.n_elem, dtype=torch.float64, device="cuda")
+    m.filter(t64(x), out, mode=0)
+    want = filt.forward(H, Hs, x)
+    err = np.abs(out.cpu().numpy() - want).max() / np.abs(want).max()
+    log(f"  forward max rel err {err:.2e}")
+    assert err < 1e-14
+    g = -synth.smoothed_field(*dims, 2.0, 0.01, 3.0, seed=22).ravel()
+    m.filter(t64(g), out, mode=1)
+    want = filt.adjoint(H, Hs, g)
+    err = np.abs(out.cpu().numpy() - want).max() / np.abs(want).max()
+    log(f"  adjoint max rel err {err:.2e}")
+    assert err < 1e-14
+    dv = filt.adjoint(H, Hs, np.ones(m.n_elem))
+    dc = filt.adjoint(H, Hs, g)
+    xn, xp, lam = oc.oc_update(x, dc, dv, H, Hs, 0.3)
+    gx = torch.zeros(m.n_elem, dtype=torch.float64, device="cuda")
+    gp = torch.zeros_like(gx)
+    m.oc_update(t64(x), t64(dc), t64(dv), 0.3, 0.2, gx, gp)
+    ex = float(np.linalg.norm(gx.cpu().numpy() - xn) / np.linalg.norm(xn))
+    ep = float(np.linalg.norm(gp.cpu().numpy() - xp) / np.linalg.norm(xp))
+    log(f"  OC: x rel {ex:.2e}, filtered rel {ep:.2e}, volume {gp.sum().item() / m.n_elem:.6f}")
+    assert ex < 1e-9 and ep < 1e-9
+    m.close()
+
+
 def test_zero_load_gives_zero_solution():
     """Degenerate case: no load, u = 0, C = 0 and dc = 0 without iterating."""
     aarmr = _aarmr()
