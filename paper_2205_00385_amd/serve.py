@@ -229,7 +229,12 @@ class AnalysisServer:
                     while job is None:
                         if self._error is not None:
                             return
-                        job = self._pick()
+                        try:
+                            job = self._pick()
+                        except BaseException as exc:  # e.g. a request above the budget
+                            self._error = exc
+                            self._cv.notify_all()
+                            return
                         if job is None:
                             if self._closed and not self._queue:
                                 return
