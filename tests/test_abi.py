@@ -101,3 +101,12 @@ def test_workspace_grows_with_parm_and_cases(lib):
         sizes.append(lib.aarmr_workspace_bytes(h))
         lib.aarmr_mesh_destroy(h)
     assert sizes[0] < sizes[1] < sizes[2]
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    """Without the built HIP library the binding raises at load time: there is
+    no CPU fallback for any entry point."""
+    from paper_2205_00385_amd import aarmr
+
+    with pytest.raises(ImportError, match="no CPU fallback"):
+        aarmr.load_library(str(tmp_path / "libaarmr.so"))
