@@ -52,7 +52,9 @@ extern "C" {
 #define AARMR_OK               0
 #define AARMR_E_INVALID        1  /* bad argument: null pointer, size, range */
 #define AARMR_E_HIP            2  /* a HIP runtime call or kernel launch failed */
-#define AARMR_E_NOT_CONVERGED  3  /* CG hit cg_maxit; outputs are written anyway */
+#define AARMR_E_NOT_CONVERGED  3  /* CG hit cg_maxit; outputs are written anyway
+                                     (aarmr_last_error names the smoother's omega
+                                     condition, a common cause of a stall) */
 #define AARMR_E_SINGULAR       4  /* non-positive pivot or p^T A p <= 0 */
 #define AARMR_E_NO_WORKSPACE   5  /* no (or too small a) workspace bound */
 #define AARMR_E_STATE          6  /* CA called before its PARM is complete */

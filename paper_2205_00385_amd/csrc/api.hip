@@ -937,6 +937,14 @@ int setup(aarmr_mesh* m, const double* rho, const int64_t* fixed, int64_t nfixed
   return build_mg(m, s);
 }
 
+// Appended to the non-convergence messages: a V-cycle whose damped-Jacobi
+// sweep is no contraction (omega lambda_max(D^-1 A) >= 2, e.g. on moduli that
+// vary from element to element without a filter) is indefinite, and CG then
+// stalls instead of failing outright.
+#define AARMR_OMEGA_HINT \
+  " (if it stalls, the moduli may be too rough for omega: the damped-Jacobi sweep needs " \
+  "omega * lambda_max(D^-1 A) < 2, about 0.5 for unfiltered element-wise moduli)"
+
 // ---- refinement form: FP32 inner solve ------------------------------------
 // y = A v on level l with FP32 vectors (v zero on fixed DOFs).
 int apply32(aarmr_mesh* m, int l, const float* v, float* y, hipStream_t s, int nr = 1) {
@@ -1178,7 +1186,7 @@ int refine(aarmr_mesh* m, double* x, int* iters, double* relres, bool* fallback,
     launch_add_scaled_f32(n3, m->d32, misc + M_RR64, x, s);
     KCHECK();
   }
-  return fail(AARMR_E_NOT_CONVERGED, "refinement reached cg_maxit before cg_rtol");
+  return fail(AARMR_E_NOT_CONVERGED, "refinement reached cg_maxit before cg_rtol" AARMR_OMEGA_HINT);
 }
 
 // ---- refinement form, load cases in lock step ----------------------------
@@ -1551,7 +1559,7 @@ int pcg64(aarmr_mesh* m, double* x, int* iters, double* relres, int maxit_in, hi
       if (rr <= tol2) return AARMR_OK;
     }
   }
-  return fail(AARMR_E_NOT_CONVERGED, "CG reached cg_maxit before cg_rtol");
+  return fail(AARMR_E_NOT_CONVERGED, "CG reached cg_maxit before cg_rtol" AARMR_OMEGA_HINT);
 }
 
 // phi = u / ||u|| into case l's PARM ring (eqs. 27-28, oldest dropped).
@@ -1987,7 +1995,7 @@ int aarmr_solve(aarmr_mesh* m, const double* rho, const double* f, int32_t n_rhs
     st->fine_sweeps = m->sweeps - sw0;
     st->coarsest_inversions = m->ainv_builds - inv0;
   }
-  if (status != AARMR_OK) return fail(status, "CG reached cg_maxit before cg_rtol");
+  if (status != AARMR_OK) return fail(status, "CG reached cg_maxit before cg_rtol" AARMR_OMEGA_HINT);
   return AARMR_OK;
 }
 
@@ -2205,7 +2213,8 @@ int aarmr_ca_update(aarmr_mesh* m, const double* rho, const double* f, int32_t n
     st->fine_sweeps = m->sweeps - sw0;
     st->coarsest_inversions = m->ainv_builds - inv0;
   }
-  if (status != AARMR_OK) return fail(status, "fallback CG reached cg_maxit before cg_rtol");
+  if (status != AARMR_OK)
+    return fail(status, "fallback CG reached cg_maxit before cg_rtol" AARMR_OMEGA_HINT);
   return AARMR_OK;
 }
 

@@ -243,6 +243,8 @@ def test_not_converged_reports_and_writes():
     assert code == aarmr.E_NOT_CONVERGED
     assert st.iterations[0] == 2 and st.rel_residual[0] > 1e-8
     assert torch.isfinite(u).all() and float(u.abs().max()) > 0
+    # the message names the smoother condition a stalled solve may be breaking
+    assert "omega" in aarmr.lib().aarmr_last_error().decode()
 
 
 @pytest.mark.parametrize("orth,form", [("gs", "fp64"), ("svd", "fp64"), ("gs", "refine")])
