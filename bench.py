@@ -72,6 +72,8 @@ def parse():
                     help="run a parameter study instead of the benchmark")
     ap.add_argument("--kv-only", action="store_true",
                     help="only the 256x128x128 K.v timing (for hardware-counter runs)")
+    ap.add_argument("--kv-sizes", action="store_true",
+                    help="only the K.v rate by grid size, 64x32x32 to 704x384x320")
     return ap.parse_args()
 
 
@@ -327,6 +329,55 @@ def kv_event_timing(torch, aarmr, n_launch, sets):
     e1.record(s)
     e1.synchronize()
     return e0.elapsed_time(e1) / n_launch  # ms per launch
+
+
+KV_SIZES = [(64, 32, 32), (96, 48, 48), (128, 64, 64), (192, 96, 96), (256, 128, 128),
+            (384, 192, 192), (512, 256, 256), (704, 384, 320)]
+
+
+def kv_by_size(torch, aarmr, synth, n_launch=100):
+    """The fine-grid K.v by grid size, from the launch floor up to the largest
+    grid the mesh check accepts: for each size two meshes (i.i.d. density in
+    [1e-3, 1], seeds 3 and 4; each with the most levels whose coarsest grid
+    stays under 8000 DOFs), `n_launch` products alternating between them in
+    the solver form, HIP events.  Returns one row per size."""
+    rows = []
+    for dims in KV_SIZES:
+        lev = None
+        for L in range(2, 9):
+            sc = 2 ** (L - 1)
+            if any(d % sc for d in dims):
+                break
+            c = [d // sc for d in dims]
+            if 3 * (c[0] + 1) * (c[1] + 1) * (c[2] + 1) <= 8000:
+                lev = L
+                break
+        sets = []
+        for seed in (3, 4):
+            prob = synth.cantilever(*dims)
+            m = aarmr.Mesh(aarmr.default_params(nx=dims[0], ny=dims[1], nz=dims[2], mg_levels=lev))
+            rho = torch.tensor(synth.uniform_iid(*dims, 1e-3, 1.0, seed=seed).ravel(),
+                               dtype=torch.float64, device="cuda")
+            fx = torch.tensor(aarmr.fixed_dofs_soa(prob, m.n_node), dtype=torch.int64,
+                              device="cuda")
+            m.setup(rho, fx)
+            g = torch.Generator(device="cuda").manual_seed(seed)
+            v = torch.randn(3 * m.n_node, dtype=torch.float64, device="cuda", generator=g)
+            v[fx] = 0.0
+            sets.append((m, v, torch.empty_like(v)))
+        ms = kv_event_timing(torch, aarmr, n_launch, sets)
+        byts, nn = ebe_bytes(*dims)
+        rows.append({"grid": "x".join(map(str, dims)), "levels": lev, "us": round(ms * 1e3, 2),
+                     "gdof_s": round(3 * nn / ms / 1e6, 1),
+                     "alg_GB_s": round(byts / ms / 1e6, 1),
+                     "hbm_frac": round(byts / ms / 1e6 / HBM_PEAK_GBS, 3),
+                     "working_set_MB": round(2 * byts / 1e6, 1)})
+        print(f"[bench] kv {rows[-1]}", file=sys.stderr, flush=True)
+        for m, v, y in sets:
+            m.close()
+        del sets
+        torch.cuda.empty_cache()
+    return rows
 
 
 def pmc_traffic(grid):
@@ -886,6 +937,9 @@ def main():
         return
     if args.batch_only:
         print(json.dumps({"batched_form_64": batched_form(torch, aarmr, synth)}))
+        return
+    if args.kv_sizes:
+        print(json.dumps({"kv_by_grid_size": kv_by_size(torch, aarmr, synth)}))
         return
     if args.precision_only:
         print(json.dumps({"analysis_256x128x128": precision_form(torch, aarmr, synth)}))
