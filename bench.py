@@ -338,7 +338,7 @@ KV_SIZES = [(64, 32, 32), (96, 48, 48), (128, 64, 64), (192, 96, 96), (256, 128,
 def kv_by_size(torch, aarmr, synth, n_launch=100):
     """The fine-grid K.v by grid size, from the launch floor up to the largest
     grid the mesh check accepts: for each size two meshes (i.i.d. density in
-    [1e-3, 1], seeds 3 and 4; each with the most levels whose coarsest grid
+    [1e-3, 1], seeds 3 and 4; each with the fewest levels whose coarsest grid
     stays under 8000 DOFs), `n_launch` products alternating between them in
     the solver form, HIP events.  Returns one row per size."""
     rows = []
